@@ -1,0 +1,184 @@
+/*
+ * c3x.h -- C ABI of the MI355X positional cross-match library (libc3x.so).
+ *
+ * The library implements the "Sky" functional case of the C^3 cross-match
+ * (Riccio et al., ADASS XXVI, arXiv:1611.08494, Section 2.1): for every
+ * source of catalogue A it finds the catalogue-B sources inside a region
+ * centred on that source -- a circle of fixed radius, or an ellipse whose
+ * semi-axes and position angle come from per-source catalogue parameters --
+ * with the "all" and "best" match selections of Section 2.2, on equatorial or
+ * galactic coordinates (Section 2). The sky partitioning of Section 2.3
+ * (catalogue B assigned to cells, each A source tested only against the
+ * cells around it) is restated for the sphere as declination zones split
+ * into RA cells.
+ *
+ * Semantics (the exact pair set). Inputs are IEEE doubles taken as exact
+ * reals and theta(i, j) is the exact great-circle angle.
+ *   circle : j matches i  <=>  theta(i, j) <= r.
+ *   ellipse: j matches i  <=>  (u/a_i)^2 + (v/b_i)^2 <= 1, where
+ *            (u, v) = theta * (cos(phi - T_i), sin(phi - T_i)), phi is the
+ *            bearing of j seen from i from local north (+Dec, or +b for
+ *            galactic input) towards local east (+RA / +l), and
+ *            T_i = pa_zero_deg + pa_sense * pa_deg[i] is the direction of
+ *            the semi-major axis (Section 2.1: the PA has a zero-point and a
+ *            direction of rotation). a = b gives theta <= a.
+ *   Boundaries are inclusive. best(i) is the match with the smallest exact
+ *   theta; an exact tie goes to the lower B row.
+ * Every decision is certified: the GPU decides in FP32 (MIXED) or FP64 with
+ * proven error margins, re-decides band cases with a relative-accuracy FP64
+ * formula, and resolves what is still undecided on the host in binary128.
+ * Pairs whose exact value lies within 2^-96 (relative) of the threshold are
+ * treated as on the boundary, so inside.
+ *
+ * Memory and ownership. Catalogue and area arrays are caller-owned, C-
+ * contiguous float64 DEVICE pointers on the current HIP device; they only
+ * need to stay valid for the duration of the call. An index owns copies of
+ * what it needs and is immutable: several c3x_match calls may share it
+ * concurrently on different streams. Results own their device buffers until
+ * c3x_result_free. All work is ordered on opts->stream (NULL: the null
+ * stream); c3x_match synchronises that stream to size its outputs.
+ *
+ * Errors. Every call returns a status; on error *out is NULL and nothing
+ * leaks. c3x_last_error() gives a thread-local message (for bad input rows it
+ * names the first offending row). The library never throws or aborts.
+ *
+ * Input domain: RA (or l) in [0, 360), Dec (or b) in [-90, 90], finite;
+ * radius 0 or in [1e-6", 324000"]; ellipse 1e-6" <= b <= a <= 324000",
+ * a <= 1000 b, PA finite; pa_sense +1 or -1; row counts <= 2^31 - 1.
+ */
+#ifndef C3X_H
+#define C3X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define C3X_ABI_VERSION 1
+
+typedef enum {
+    C3X_OK = 0,
+    C3X_EINVAL = 1,   /* bad argument or out-of-domain input value */
+    C3X_ERANGE = 2,   /* a row count above 2^31 - 1 */
+    C3X_ENOMEM = 3,   /* device or host allocation failed */
+    C3X_EDEVICE = 4,  /* HIP runtime error (message holds the HIP string) */
+    C3X_EFRAME = 5    /* index and match frames differ */
+} c3x_status;
+
+/* Coordinate frame of both catalogues (Section 2: equatorial and galactic).
+ * It fixes what "north" means for the position angle; both catalogues of one
+ * match must share it. */
+typedef enum { C3X_EQUATORIAL = 0, C3X_GALACTIC = 1 } c3x_frame;
+
+/* Region shape (Section 2.1: the circle as a special ellipse). */
+typedef enum { C3X_CIRCLE = 0, C3X_ELLIPSE = 1 } c3x_shape;
+
+/* Match selection (Section 2.2). OR-able. ALL writes every pair; BEST fills
+ * the per-A best arrays; BEST alone writes one pair per matched A row. */
+enum { C3X_ALL = 1u, C3X_BEST = 2u };
+
+/* Arithmetic of the GPU filter. Both give the same pair set. */
+typedef enum { C3X_FP64 = 0, C3X_MIXED = 1 } c3x_precision;
+
+/* The matching area centred on each A source (Section 2.1). */
+typedef struct {
+    c3x_shape shape;
+    double radius_arcsec;            /* CIRCLE: fixed radius */
+    const double *semi_major_arcsec; /* ELLIPSE: device, nA entries */
+    const double *semi_minor_arcsec; /* ELLIPSE: device, nA entries */
+    const double *pa_deg;            /* ELLIPSE: device, nA entries */
+    double pa_zero_deg;              /* T = pa_zero_deg + pa_sense * PA */
+    int pa_sense;                    /* +1 or -1 */
+} c3x_area;
+
+/* Options. Zero-initialised fields mean "choose automatically".
+ * cell_arcsec: side of the sky cells (the partition resolution the paper
+ *   lets users tune, Section 4); 0 lets the planner pick it. It never
+ *   changes the answer.
+ * tile: A sources per workgroup in the match kernels (64 or 256; 0 = auto).
+ * stream: hipStream_t to order all work on (NULL = null stream). */
+typedef struct {
+    c3x_precision precision;
+    double cell_arcsec;
+    int tile;
+    void *stream;
+} c3x_opts;
+
+typedef struct c3x_index c3x_index;
+typedef struct c3x_result c3x_result;
+typedef struct c3x_batch c3x_batch;
+
+/* Counters and phase times of one call (milliseconds from HIP events). */
+typedef struct {
+    int64_t n_a, n_b;
+    int64_t n_pairs;          /* pairs written (ALL) or matched A rows (BEST only) */
+    int64_t n_tests;          /* candidate (A, B) pairs examined by the match kernel */
+    int64_t n_band;           /* candidates re-decided by the FP64 haversine form */
+    int64_t n_ambiguous;      /* pairs resolved on the host in binary128 */
+    int64_t n_best_ties;      /* best matches re-ranked on the host */
+    int64_t n_cells;          /* cells of the sky grid */
+    double cell_arcsec;       /* cell side used */
+    double ms_index;          /* build_index phases (index stats only) */
+    double ms_a_prep;         /* A keys, sort, records */
+    double ms_count;          /* count pass */
+    double ms_scan;
+    double ms_write;          /* write pass + best */
+    double ms_sort_pairs;     /* per-A segment ordering */
+    double ms_total;
+    int32_t precision;
+    int32_t tile;
+} c3x_stats;
+
+/* Builds the sky index over catalogue B: validates the rows, assigns each to
+ * a zone/RA cell (Section 2.3, "the objects of the second catalogue are
+ * assigned to one of the cells"), sorts B by cell with an LDS radix sort,
+ * and builds the cell directory. ra_deg/dec_deg: device float64[nB].
+ * reach_hint_arcsec: the largest radius or semi-major axis expected (sizes
+ * the cells; any reach still works). opts may be NULL.
+ * Errors: C3X_EINVAL (bad row: message names it; bad frame or options),
+ * C3X_ERANGE (nB > 2^31 - 1), C3X_ENOMEM, C3X_EDEVICE. */
+c3x_status c3x_build_index(const double *ra_deg, const double *dec_deg, int64_t nB,
+                           c3x_frame frame, double reach_hint_arcsec, const c3x_opts *opts,
+                           c3x_index **out);
+
+/* Cross-matches catalogue A against an index (Section 2.1 region test,
+ * Section 2.2 selection). ra_deg/dec_deg: device float64[nA]; area as
+ * above; mode: C3X_ALL, C3X_BEST or both. opts->precision must be the one
+ * the index was built with (opts NULL: the index's).
+ * Output (via c3x_result_copy): pairs in canonical (idxA, idxB) ascending
+ * order, 0-based rows of the caller's arrays; sep in arcsec (float64, within
+ * 1e-6" of exact); best_idxB[nA] (-1 if unmatched), best_sep[nA] (NaN).
+ * Errors: C3X_EINVAL, C3X_ERANGE, C3X_EFRAME, C3X_ENOMEM, C3X_EDEVICE. */
+c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const double *dec_deg,
+                     int64_t nA, c3x_frame frame, const c3x_area *area, unsigned mode,
+                     const c3x_opts *opts, c3x_result **out);
+
+/* Sizes of a result: number of pairs and of A rows. */
+c3x_status c3x_result_sizes(const c3x_result *r, int64_t *n_pairs, int64_t *nA);
+
+/* Copies result arrays into caller buffers (device or host pointers; any may
+ * be NULL to skip it). idxA/idxB/sep_arcsec take n_pairs entries,
+ * best_idxB/best_sep_arcsec nA entries. Ordered on `stream`, synchronous
+ * with respect to the host when any destination is host memory. */
+c3x_status c3x_result_copy(const c3x_result *r, int32_t *idxA, int32_t *idxB,
+                           double *sep_arcsec, int32_t *best_idxB, double *best_sep_arcsec,
+                           void *stream);
+
+/* Counters and timings of the call that produced r (or of an index). */
+c3x_status c3x_result_stats(const c3x_result *r, c3x_stats *s);
+c3x_status c3x_index_stats(const c3x_index *ix, c3x_stats *s);
+
+void c3x_result_free(c3x_result *r);
+void c3x_index_free(c3x_index *ix);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *c3x_last_error(void);
+const char *c3x_version(void);
+int c3x_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* C3X_H */

@@ -1,0 +1,25 @@
+"""MI355X positional cross-match (the "Sky" case of the C^3 tool, arXiv:1611.08494).
+
+Python face of libc3x.so: ``build_index`` over catalogue B and ``match`` of
+catalogue A against it, circle or per-source ellipse areas, "all" and "best"
+selections, equatorial or galactic frames. All computation happens in the
+HIP library; torch tensors only carry device memory and streams.
+"""
+from ._binding import (  # noqa: F401
+    ALL,
+    BEST,
+    CIRCLE,
+    ELLIPSE,
+    EQUATORIAL,
+    FP64,
+    GALACTIC,
+    LIB_PATH,
+    MIXED,
+    C3XError,
+    Index,
+    MatchResult,
+    build_index,
+    lib,
+    match,
+    version,
+)

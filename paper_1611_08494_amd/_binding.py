@@ -1,0 +1,241 @@
+"""ctypes binding of libc3x.so (declared in include/c3x.h).
+
+Argument marshalling only: every step of the cross-match runs in the HIP
+library. torch supplies device memory (float64 CUDA tensors on the current
+device) and the stream the library orders its work on. If the library is not
+built the import fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libc3x.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EFRAME = range(6)
+EQUATORIAL, GALACTIC = 0, 1
+CIRCLE, ELLIPSE = 0, 1
+ALL, BEST = 1, 2
+FP64, MIXED = 0, 1
+_STATUS = {0: "C3X_OK", 1: "C3X_EINVAL", 2: "C3X_ERANGE", 3: "C3X_ENOMEM", 4: "C3X_EDEVICE",
+           5: "C3X_EFRAME"}
+
+
+class C3XError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Area(ctypes.Structure):
+    _fields_ = [
+        ("shape", ctypes.c_int),
+        ("radius_arcsec", ctypes.c_double),
+        ("semi_major_arcsec", ctypes.c_void_p),
+        ("semi_minor_arcsec", ctypes.c_void_p),
+        ("pa_deg", ctypes.c_void_p),
+        ("pa_zero_deg", ctypes.c_double),
+        ("pa_sense", ctypes.c_int),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("cell_arcsec", ctypes.c_double),
+        ("tile", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_a", ctypes.c_int64), ("n_b", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+        ("n_tests", ctypes.c_int64), ("n_band", ctypes.c_int64),
+        ("n_ambiguous", ctypes.c_int64), ("n_best_ties", ctypes.c_int64),
+        ("n_cells", ctypes.c_int64), ("cell_arcsec", ctypes.c_double),
+        ("ms_index", ctypes.c_double), ("ms_a_prep", ctypes.c_double),
+        ("ms_count", ctypes.c_double), ("ms_scan", ctypes.c_double),
+        ("ms_write", ctypes.c_double), ("ms_sort_pairs", ctypes.c_double),
+        ("ms_total", ctypes.c_double), ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Loads libc3x.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc for gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.c3x_build_index.argtypes = [vp, vp, i64, ctypes.c_int, dbl, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(vp)]
+    L.c3x_build_index.restype = ctypes.c_int
+    L.c3x_match.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.POINTER(Area), ctypes.c_uint,
+                            ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.c3x_match.restype = ctypes.c_int
+    L.c3x_result_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.c3x_result_sizes.restype = ctypes.c_int
+    L.c3x_result_copy.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.c3x_result_copy.restype = ctypes.c_int
+    L.c3x_result_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.c3x_result_stats.restype = ctypes.c_int
+    L.c3x_index_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.c3x_index_stats.restype = ctypes.c_int
+    L.c3x_result_free.argtypes = [vp]
+    L.c3x_result_free.restype = None
+    L.c3x_index_free.argtypes = [vp]
+    L.c3x_index_free.restype = None
+    L.c3x_last_error.restype = ctypes.c_char_p
+    L.c3x_version.restype = ctypes.c_char_p
+    L.c3x_abi_version.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != OK:
+        raise C3XError(status, lib().c3x_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f64(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 1:
+        raise TypeError(f"{name} must be a contiguous 1-D float64 tensor")
+    return t
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Index:
+    """Immutable sky index over catalogue B (owns its device buffers)."""
+
+    def __init__(self, handle, n, frame, precision):
+        self._h = handle
+        self.n = n
+        self.frame = frame
+        self.precision = precision
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("index was freed")
+        return self._h
+
+    def stats(self) -> dict:
+        s = Stats()
+        check(lib().c3x_index_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def free(self):
+        if self._h is not None:
+            lib().c3x_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class MatchResult:
+    def __init__(self, idxA, idxB, sep, best_idx, best_sep, stats):
+        self.idxA = idxA
+        self.idxB = idxB
+        self.sep = sep
+        self.best_idx = best_idx
+        self.best_sep = best_sep
+        self.stats = stats
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.idxA.shape[0])
+
+
+def build_index(ra, dec, frame: int = EQUATORIAL, reach_hint_arcsec: float = 0.0,
+                precision: int = FP64, cell_arcsec: float = 0.0, stream=None) -> Index:
+    ra = _dev_f64(ra, "ra")
+    dec = _dev_f64(dec, "dec")
+    if ra.shape != dec.shape:
+        raise ValueError("ra and dec differ in length")
+    o = Opts(precision=int(precision), cell_arcsec=float(cell_arcsec), tile=0,
+             stream=_stream_ptr(stream))
+    h = ctypes.c_void_p()
+    check(lib().c3x_build_index(ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(frame),
+                                float(reach_hint_arcsec), ctypes.byref(o), ctypes.byref(h)))
+    return Index(h, ra.shape[0], frame, precision)
+
+
+def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
+          radius_arcsec: float = 1.0, a=None, b=None, pa=None, pa_zero_deg: float = 0.0,
+          pa_sense: int = 1, mode: int = ALL | BEST, stream=None,
+          raw: bool = False) -> MatchResult:
+    """Cross-matches catalogue A (ra, dec) against ``index``. Returns device
+    tensors: idxA, idxB (int32), sep (float64 arcsec) in canonical order and
+    best_idx (int32, -1 if unmatched), best_sep (float64, NaN) per A row."""
+    torch = _torch()
+    ra = _dev_f64(ra, "ra")
+    dec = _dev_f64(dec, "dec")
+    if ra.shape != dec.shape:
+        raise ValueError("ra and dec differ in length")
+    ar = Area(shape=int(shape), radius_arcsec=float(radius_arcsec), pa_zero_deg=float(pa_zero_deg),
+              pa_sense=int(pa_sense))
+    if shape == ELLIPSE:
+        for nm, v in (("a", a), ("b", b), ("pa", pa)):
+            v = _dev_f64(v, nm)
+            if v.shape != ra.shape:
+                raise ValueError(f"{nm} must have one entry per A row")
+        ar.semi_major_arcsec = a.data_ptr()
+        ar.semi_minor_arcsec = b.data_ptr()
+        ar.pa_deg = pa.data_ptr()
+    sp = _stream_ptr(stream)
+    o = Opts(precision=int(index.precision), cell_arcsec=0.0, tile=0, stream=sp)
+    h = ctypes.c_void_p()
+    check(lib().c3x_match(index.handle, ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(frame),
+                          ctypes.byref(ar), int(mode), ctypes.byref(o), ctypes.byref(h)))
+    try:
+        npairs = ctypes.c_int64()
+        na = ctypes.c_int64()
+        check(lib().c3x_result_sizes(h, ctypes.byref(npairs), ctypes.byref(na)))
+        dev = ra.device
+        P = npairs.value
+        ia = torch.empty(P, dtype=torch.int32, device=dev)
+        ib = torch.empty(P, dtype=torch.int32, device=dev)
+        sep = torch.empty(P, dtype=torch.float64, device=dev)
+        bi = torch.empty(na.value, dtype=torch.int32, device=dev)
+        bs = torch.empty(na.value, dtype=torch.float64, device=dev)
+        check(lib().c3x_result_copy(h, ia.data_ptr(), ib.data_ptr(), sep.data_ptr(), bi.data_ptr(),
+                                    bs.data_ptr(), sp))
+        st = Stats()
+        check(lib().c3x_result_stats(h, ctypes.byref(st)))
+    finally:
+        lib().c3x_result_free(h)
+    return MatchResult(ia, ib, sep, bi, bs, st.as_dict())
+
+
+def version() -> str:
+    return lib().c3x_version().decode()

@@ -1,0 +1,139 @@
+// c3x_host.h -- host-side objects of the library: index, result, device
+// memory cache, error reporting and phase timers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "c3x_internal.h"
+
+namespace c3x {
+
+// Thread-local error message; returns the status for convenience.
+c3x_status fail(c3x_status st, const char *fmt, ...);
+c3x_status fail_hip(hipError_t e, const char *what);
+void clear_error();
+
+// Device memory cache. Blocks are returned to the cache, not to HIP, and
+// reused by size class; every API call synchronises its stream before it
+// returns, so a block is never handed out while a kernel may still use it.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+
+// RAII owner of device blocks allocated during one call.
+// With a stream set, the destructor first waits for that stream, so blocks
+// freed on an early error return are never reused while a kernel runs.
+struct Arena {
+    std::vector<void *> blocks;
+    hipStream_t sync_stream = nullptr;
+    bool sync_on_release = false;
+    Arena() = default;
+    explicit Arena(hipStream_t s) : sync_stream(s), sync_on_release(true) {}
+    void *get(size_t bytes)
+    {
+        void *p = dev_alloc(bytes ? bytes : 16);
+        if (p) blocks.push_back(p);
+        return p;
+    }
+    template <typename T>
+    T *get_n(int64_t n)
+    {
+        return (T *)get((size_t)(n > 0 ? n : 1) * sizeof(T));
+    }
+    void release_all()
+    {
+        if (sync_on_release && !blocks.empty()) (void)hipStreamSynchronize(sync_stream);
+        for (void *p : blocks) dev_free(p);
+        blocks.clear();
+    }
+    // Hand a block over to a longer-lived owner.
+    void detach(void *p)
+    {
+        for (auto &b : blocks)
+            if (b == p) {
+                b = blocks.back();
+                blocks.pop_back();
+                return;
+            }
+    }
+    ~Arena() { release_all(); }
+};
+
+// HIP events around phases of one call.
+struct Timer {
+    hipEvent_t ev[16];
+    int n = 0;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st)
+    {
+        for (auto &e : ev) e = nullptr;
+    }
+    void mark()
+    {
+        if (n < 16) {
+            if (!ev[n]) (void)hipEventCreate(&ev[n]);
+            (void)hipEventRecord(ev[n], s);
+            n++;
+        }
+    }
+    double ms(int a, int b)
+    {
+        float t = 0.f;
+        if (a < n && b < n) (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+        return (double)t;
+    }
+    ~Timer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+struct GridPlan {
+    double cell_arcsec;
+    double h_deg;
+    int32_t nz;
+    uint64_t ncells;
+    int32_t dshift;
+    uint32_t dsize;
+    int key_bits;
+    double L_rad;                 // bound on |p - cell reference| (radians, chord)
+    std::vector<uint32_t> zbase;  // nz + 1
+    std::vector<uint32_t> zn;
+    std::vector<double> zf;
+    std::vector<double> zref;     // 2 per zone
+};
+
+}  // namespace c3x
+
+struct c3x_index {
+    int device;
+    c3x_frame frame;
+    c3x_precision precision;
+    int64_t nB;
+    double reach_hint_arcsec;
+    c3x::GridPlan plan;
+    c3x::Grid grid;               // device pointers
+    c3x::Arena mem;               // owns everything below
+    uint32_t *keys = nullptr;
+    c3x::Pay64 *pay64 = nullptr;
+    c3x::Pay32 *pay32 = nullptr;
+    double2 *radec = nullptr;
+    c3x_stats stats;
+};
+
+struct c3x_result {
+    int device;
+    int64_t n_pairs;
+    int64_t nA;
+    unsigned mode;
+    c3x::Arena mem;
+    int32_t *idxA = nullptr, *idxB = nullptr;
+    double *sep = nullptr;
+    int32_t *best_idx = nullptr;
+    double *best_sep = nullptr;
+    c3x_stats stats;
+};

@@ -1,0 +1,340 @@
+// c3x_index.hip -- sky index over catalogue B (paper Section 2.3: "the
+// objects of the second catalogue are assigned to one of the cells defined
+// by the partitioning procedure, according to their coordinates").
+//
+// The flat grid of the paper becomes declination zones of height h, each cut
+// into n_z RA cells of true width >= h at the zone's edge nearest the
+// equator; key = zbase[zone] + cell is zone-major, so the cells an A source
+// needs in one zone are one contiguous key range. Phases (one stream):
+//   k_prep_b    validate rows, key + row index          16 B in, 8 B out
+//   radix sort  (key, row) by key, ceil(bits/8) passes   16 B per pass
+//   k_gather_b  payload in sorted order                   16 B in, 36/52 B out
+//   k_dir       coarse directory over key >> dshift
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "c3x_host.h"
+#include "c3x_sort.h"
+
+namespace c3x {
+
+constexpr double kSkyArcsec2 = 4.0 * kPi * (180.0 / kPi * 3600.0) * (180.0 / kPi * 3600.0);
+constexpr double kMinCellArcsec = 16.0;  // keeps the key space below 2^31 cells
+
+static void build_zones(GridPlan &p, double cell_arcsec)
+{
+    p.cell_arcsec = cell_arcsec;
+    p.h_deg = cell_arcsec / 3600.0;
+    p.nz = (int32_t)std::max(1.0, ceil(180.0 / p.h_deg));
+    p.zbase.assign(p.nz + 1, 0);
+    p.zn.assign(p.nz, 1);
+    p.zf.assign(p.nz, 0.0);
+    p.zref.assign(2 * (size_t)p.nz, 0.0);
+    uint64_t tot = 0;
+    double L = 0.0;
+    for (int z = 0; z < p.nz; ++z) {
+        double lo = -90.0 + z * p.h_deg;
+        double hi = std::min(90.0, lo + p.h_deg);
+        if (z == p.nz - 1) hi = 90.0;
+        double deq = (lo <= 0.0 && hi >= 0.0) ? 0.0 : (fabs(lo) < fabs(hi) ? lo : hi);
+        double ceq = cos(deq * kDeg);
+        double nzf = floor(360.0 * ceq / p.h_deg);
+        uint32_t n = (uint32_t)std::max(1.0, std::min(nzf, 4.0e9));
+        p.zn[z] = n;
+        p.zbase[z] = (uint32_t)std::min<uint64_t>(tot, 0xffffffffull);
+        tot += n;
+        p.zf[z] = (double)n / 360.0;
+        double dc = std::max(-90.0, std::min(90.0, 0.5 * (lo + hi)));
+        p.zref[2 * z] = cos(dc * kDeg);
+        p.zref[2 * z + 1] = sin(dc * kDeg);
+        // largest distance from a point of a cell to the cell's reference
+        double ddec = std::max(hi - dc, dc - lo);
+        double dra = (180.0 / n + 180.0 / (1 << kRefBits)) * ceq;
+        double ang = sqrt(ddec * ddec + dra * dra) * kDeg;
+        L = std::max(L, ang);
+    }
+    p.zbase[p.nz] = (uint32_t)std::min<uint64_t>(tot, 0xffffffffull);
+    p.ncells = tot;
+    p.L_rad = L * 1.01 + 1e-12;
+}
+
+// Chooses the cell side and the directory resolution. The cell is the
+// reach (the paper sizes cells by the largest matching region), floored so
+// that the key space stays below 2^31 cells.
+c3x_status plan_grid(GridPlan &p, int64_t nB, double reach_arcsec, double cell_req)
+{
+    double cell = cell_req > 0.0 ? cell_req : std::max(reach_arcsec, kMinCellArcsec);
+    cell = std::max(cell, 1e-3);
+    cell = std::min(cell, 180.0 * 3600.0);
+    for (int it = 0; it < 64; ++it) {
+        build_zones(p, cell);
+        if (p.ncells < (1ull << 31)) break;
+        cell *= 1.25;
+    }
+    if (p.ncells >= (1ull << 31)) return fail(C3X_EINVAL, "grid plan failed");
+    uint64_t maxkey = p.ncells - 1;
+    int bits = 0;
+    while (bits < 32 && (maxkey >> bits)) ++bits;
+    p.key_bits = bits;
+    // directory: about one entry per four B rows
+    uint64_t want = std::max<uint64_t>(1, (uint64_t)(nB / 4));
+    int sh = 0;
+    while (sh < 31 && (maxkey >> sh) + 1 > want) ++sh;
+    p.dshift = sh;
+    p.dsize = (uint32_t)((maxkey >> sh) + 2);
+    return C3X_OK;
+}
+
+// ---------------------------------------------------------------------------- kernels
+
+__global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict__ dec, int64_t n,
+                         Grid g, uint32_t *__restrict__ keys, uint32_t *__restrict__ rows,
+                         uint32_t *__restrict__ bad)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double a = ra[j], d = dec[j];
+    bool ok = isfinite(a) && isfinite(d) && a >= 0.0 && a < 360.0 && fabs(d) <= 90.0;
+    if (!ok) {
+        atomicMin(bad, (uint32_t)j);
+        a = 0.0;
+        d = 0.0;
+    }
+    int z = zone_of(d, g);
+    keys[j] = g.zbase[z] + cell_of(z, a, g);
+    rows[j] = (uint32_t)j;
+}
+
+template <int PREC>
+__global__ void k_gather_b(const uint32_t *__restrict__ rows, const double *__restrict__ ra,
+                           const double *__restrict__ dec, int64_t n, Grid g,
+                           Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
+                           double2 *__restrict__ radec)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    uint32_t row = rows[s];
+    if (row >= (uint64_t)n) row = 0;  // unreachable for a permutation; keeps reads in bounds
+    double a = ra[row], d = dec[row];
+    radec[s] = make_double2(a, d);
+    double x, y, z;
+    unit_vec(a, d, x, y, z);
+    if (PREC == C3X_FP64) {
+        Pay64 q;
+        q.x = x;
+        q.y = y;
+        q.z = z;
+        q.idx = row;
+        q.pad = 0;
+        p64[s] = q;
+    } else {
+        int zz = zone_of(d, g);
+        uint32_t c = cell_of(zz, a, g);
+        double rx, ry, rz;
+        cell_ref(zz, c, g, rx, ry, rz);
+        Pay32 q;
+        q.x = (float)(x - rx);
+        q.y = (float)(y - ry);
+        q.z = (float)(z - rz);
+        q.idx = row;
+        p32[s] = q;
+    }
+}
+
+// dir[t] = number of keys with (key >> dshift) < t.
+__global__ void k_dir(const uint32_t *__restrict__ keys, int64_t n, int dshift, uint32_t dsize,
+                      uint32_t *__restrict__ dir)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= dsize) return;
+    uint64_t k = (uint64_t)t << dshift;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t m = (lo + hi) >> 1;
+        if ((uint64_t)keys[m] < k) lo = m + 1;
+        else hi = m;
+    }
+    dir[t] = (uint32_t)lo;
+}
+
+__global__ void k_ref_table(double2 *__restrict__ t)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (1 << kRefBits)) return;
+    double s, c;
+    sincospi((double)i / (double)(1 << (kRefBits - 1)), &s, &c);
+    t[i] = make_double2(c, s);
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Uploads the zone tables and the RA reference grid; fills ix->grid.
+c3x_status upload_grid(c3x_index *ix, hipStream_t s)
+{
+    GridPlan &p = ix->plan;
+    Grid &g = ix->grid;
+    uint32_t *zbase = ix->mem.get_n<uint32_t>(p.nz + 1);
+    uint32_t *zn = ix->mem.get_n<uint32_t>(p.nz);
+    double *zf = ix->mem.get_n<double>(p.nz);
+    double2 *zref = ix->mem.get_n<double2>(p.nz);
+    double2 *rref = ix->mem.get_n<double2>(1 << kRefBits);
+    if (!zbase || !zn || !zf || !zref || !rref) return fail(C3X_ENOMEM, "index tables");
+    hipError_t e = hipMemcpyAsync(zbase, p.zbase.data(), (p.nz + 1) * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(zn, p.zn.data(), p.nz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(zf, p.zf.data(), p.nz * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(zref, p.zref.data(), p.nz * sizeof(double2), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_hip(e, "index tables");
+    hipLaunchKernelGGL(k_ref_table, dim3(nblk(1 << kRefBits, 256)), dim3(256), 0, s, rref);
+    g.h_deg = p.h_deg;
+    g.inv_h = 1.0 / p.h_deg;
+    g.nz = p.nz;
+    g.ncells = (uint32_t)p.ncells;
+    g.zbase = zbase;
+    g.zf = zf;
+    g.zn = zn;
+    g.zref = zref;
+    g.rref = rref;
+    g.dshift = p.dshift;
+    g.dsize = p.dsize;
+    return C3X_OK;
+}
+
+}  // namespace c3x
+
+using namespace c3x;
+
+extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_deg, int64_t nB,
+                                      c3x_frame frame, double reach_hint_arcsec,
+                                      const c3x_opts *opts, c3x_index **out)
+{
+    clear_error();
+    if (!out) return fail(C3X_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nB < 0) return fail(C3X_EINVAL, "nB < 0");
+    if (nB > 2147483647LL) return fail(C3X_ERANGE, "nB above 2^31 - 1");
+    if (nB > 0 && (!ra_deg || !dec_deg)) return fail(C3X_EINVAL, "NULL coordinate array");
+    if (frame != C3X_EQUATORIAL && frame != C3X_GALACTIC) return fail(C3X_EINVAL, "bad frame");
+    if (!(reach_hint_arcsec >= 0.0) || !isfinite(reach_hint_arcsec))
+        return fail(C3X_EINVAL, "reach_hint_arcsec must be finite and >= 0");
+    c3x_opts o{};
+    if (opts) o = *opts;
+    if (o.precision != C3X_FP64 && o.precision != C3X_MIXED)
+        return fail(C3X_EINVAL, "bad precision");
+    if (!(o.cell_arcsec >= 0.0) || !isfinite(o.cell_arcsec))
+        return fail(C3X_EINVAL, "cell_arcsec must be finite and >= 0");
+    hipStream_t s = (hipStream_t)o.stream;
+
+    c3x_index *ix = new (std::nothrow) c3x_index();
+    if (!ix) return fail(C3X_ENOMEM, "host allocation");
+    (void)hipGetDevice(&ix->device);
+    ix->frame = frame;
+    ix->precision = o.precision;
+    ix->nB = nB;
+    ix->reach_hint_arcsec = reach_hint_arcsec;
+    memset(&ix->stats, 0, sizeof(ix->stats));
+    c3x_status st = plan_grid(ix->plan, nB, reach_hint_arcsec, o.cell_arcsec);
+    if (st != C3X_OK) {
+        delete ix;
+        return st;
+    }
+    Timer tm(s);
+    tm.mark();
+    st = upload_grid(ix, s);
+    if (st != C3X_OK) {
+        (void)hipStreamSynchronize(s);
+        delete ix;
+        return st;
+    }
+    Arena tmp(s);
+    int64_t n = nB;
+    uint32_t *keys = ix->mem.get_n<uint32_t>(n);
+    uint32_t *rows = tmp.get_n<uint32_t>(n);
+    uint32_t *ktmp = tmp.get_n<uint32_t>(n);
+    uint32_t *rtmp = tmp.get_n<uint32_t>(n);
+    void *ws = tmp.get(radix_ws_bytes(n));
+    uint32_t *bad = tmp.get_n<uint32_t>(1);
+    double2 *radec = ix->mem.get_n<double2>(n);
+    Pay64 *p64 = nullptr;
+    Pay32 *p32 = nullptr;
+    if (o.precision == C3X_FP64) p64 = ix->mem.get_n<Pay64>(n);
+    else p32 = ix->mem.get_n<Pay32>(n);
+    uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !radec || !dir || (!p64 && !p32)) {
+        (void)hipStreamSynchronize(s);
+        delete ix;
+        return fail(C3X_ENOMEM, "index buffers");
+    }
+    hipError_t e = hipMemsetAsync(bad, 0xff, sizeof(uint32_t), s);
+    Grid g = ix->grid;
+    g.nB = (int32_t)n;
+    if (n > 0)
+        hipLaunchKernelGGL(k_prep_b, dim3(nblk(n, 256)), dim3(256), 0, s, ra_deg, dec_deg, n, g,
+                           keys, rows, bad);
+    int in_tmp = 0;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess)
+        e = radix_sort_pairs(keys, rows, ktmp, rtmp, n, ix->plan.key_bits, ws, s, &in_tmp);
+    if (e == hipSuccess && in_tmp) {
+        e = hipMemcpyAsync(keys, ktmp, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        rows = rtmp;
+    }
+    if (e == hipSuccess && n > 0) {
+        if (o.precision == C3X_FP64)
+            hipLaunchKernelGGL(k_gather_b<C3X_FP64>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
+                               ra_deg, dec_deg, n, g, p64, p32, radec);
+        else
+            hipLaunchKernelGGL(k_gather_b<C3X_MIXED>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
+                               ra_deg, dec_deg, n, g, p64, p32, radec);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        hipLaunchKernelGGL(k_dir, dim3(nblk(ix->plan.dsize, 256)), dim3(256), 0, s, keys, n,
+                           ix->plan.dshift, ix->plan.dsize, dir);
+    tm.mark();
+    uint32_t bad_h = 0xffffffffu;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad_h, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        delete ix;
+        return fail_hip(e, "c3x_build_index");
+    }
+    if (bad_h != 0xffffffffu) {
+        delete ix;
+        return fail(C3X_EINVAL, "catalogue B row %u: coordinate outside RA [0,360), |Dec| <= 90 "
+                                "or not finite", bad_h);
+    }
+    ix->keys = keys;
+    ix->pay64 = p64;
+    ix->pay32 = p32;
+    ix->radec = radec;
+    ix->grid.keys = keys;
+    ix->grid.dir = dir;
+    ix->grid.nB = (int32_t)n;
+    c3x_stats &S = ix->stats;
+    S.n_b = n;
+    S.n_cells = (int64_t)ix->plan.ncells;
+    S.cell_arcsec = ix->plan.cell_arcsec;
+    S.ms_index = tm.ms(0, 1);
+    S.ms_total = S.ms_index;
+    S.precision = (int32_t)o.precision;
+    *out = ix;
+    return C3X_OK;
+}
+
+extern "C" void c3x_index_free(c3x_index *ix) { delete ix; }
+
+extern "C" c3x_status c3x_index_stats(const c3x_index *ix, c3x_stats *s)
+{
+    if (!ix || !s) return fail(C3X_EINVAL, "NULL argument");
+    *s = ix->stats;
+    return C3X_OK;
+}

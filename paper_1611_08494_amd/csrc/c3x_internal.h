@@ -1,0 +1,364 @@
+// c3x_internal.h -- shared declarations of the MI355X cross-match library.
+//
+// Data layout in HBM (all device arrays, catalogue B sorted by cell key):
+//   keys[nB]   u32   cell key = zbase[zone] + RA cell (zone-major)
+//   pay64[nB]  {f64 x, y, z; u32 idx; u32 pad}   FP64 unit vector (32 B)
+//   pay32[nB]  {f32 dx, dy, dz; u32 idx}          FP32 offset from the cell's
+//                                                 reference vector (16 B)
+//   radec[nB]  {f64 ra, dec}                      original coordinates
+//   dir[Q+1]   u32   dir[q] = #keys with (key >> dshift) < q
+// Catalogue A is keyed on the same grid and sorted, so a wavefront of
+// threads covers neighbouring sky and reads neighbouring cells of B.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/c3x.h"
+
+namespace c3x {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kDeg = kPi / 180.0;     // degrees -> radians
+constexpr double kHalfDeg = kPi / 360.0; // half of it (haversines)
+constexpr double kU = 1.1102230246251565e-16;   // 2^-53
+constexpr double kU32 = 5.9604644775390625e-08; // 2^-24
+constexpr double kE40 = 9.094947017729282e-13;  // 2^-40
+constexpr double kE38 = 3.637978807091713e-12;  // 2^-38
+constexpr int kRefBits = 16;                     // RA reference grid, 2^16 points
+
+enum Decision : int { OUT = 0, IN = 1, AMBIG = 2 };
+
+// Grid of declination zones split into RA cells (the paper's cells,
+// restated for the sphere). Passed by value to kernels.
+struct Grid {
+    double h_deg;          // zone height (degrees)
+    double inv_h;          // 1 / h_deg
+    int32_t nz;            // number of zones
+    uint32_t ncells;       // total cells
+    const uint32_t *zbase; // [nz + 1] first key of each zone
+    const double *zf;      // [nz] n_z / 360 (cells per degree of RA)
+    const uint32_t *zn;    // [nz] n_z, cells in the zone
+    const double2 *zref;   // [nz] cos, sin of the zone's reference Dec
+    const double2 *rref;   // [2^kRefBits] cos, sin of the RA reference grid
+    const uint32_t *keys;  // [nB] sorted keys of B
+    const uint32_t *dir;   // [dsize] coarse directory over key >> dshift
+    int32_t dshift;
+    uint32_t dsize;        // Q + 1
+    int32_t nB;
+};
+
+struct alignas(32) Pay64 {
+    double x, y, z;
+    uint32_t idx, pad;
+};
+struct alignas(16) Pay32 {
+    float x, y, z;
+    uint32_t idx;
+};
+
+// Sorted A record (FP64): position, unit vector (z = sin Dec), cos Dec with
+// small relative error near the poles, reach of the area in degrees.
+struct alignas(64) ARec {
+    double ra, dec, x, y, z, cosd, reach_deg;
+    uint32_t idx, pad;
+};
+
+// Per-A ellipse parameters (sorted order).
+struct alignas(64) AEll {
+    double ux, uy, uz;     // major-axis direction in the tangent plane
+    double vx, vy, vz;     // minor-axis direction
+    double ia, ib;         // 1/a, 1/b in radians^-1
+};
+struct AEllR {             // what the FP64 recheck needs
+    double a_arcsec, b_arcsec, ct, st;
+    double m64;            // FP64 filter margin on Q
+    float m32;             // FP32 filter margin on Q (0: FP32 filter unusable)
+    float pad;
+};
+
+// Everything a match kernel needs; passed by value.
+struct MatchArgs {
+    Grid g;
+    const Pay64 *pay64;
+    const Pay32 *pay32;
+    const double2 *radecB;
+    const ARec *arec;
+    const AEll *aell;
+    const AEllR *aellr;
+    int32_t nA;
+    // circle thresholds on the squared chord
+    double cr2;            // 4 sin^2(r/2)
+    double t64_in, t64_out;
+    float t32_in, t32_out;
+    double h_r;            // sin^2(r/2) for the haversine recheck
+    int32_t r_zero;        // radius exactly 0
+    double reach_pad_deg;  // extra reach pad
+    // count pass
+    uint32_t *cnt;         // [nA] in idxA order
+    // ambiguous list (count pass)
+    uint32_t *amb_n;       // counter
+    uint2 *amb;            // (sorted A pos, sorted B pos)
+    uint32_t amb_cap;
+    // verdicts (write pass): sorted keys (i << 32 | j) with verdict bit
+    const unsigned long long *ver_key;
+    const uint8_t *ver_in;
+    uint32_t n_ver;
+    // write pass
+    const int64_t *off;    // [nA + 1] in idxA order
+    int32_t *out_a, *out_b;
+    double *out_sep;
+    int32_t write_pairs;
+    int32_t *best_idx;     // [nA] idxA order
+    double *best_sep;
+    uint32_t *tie_n;       // best near-tie list
+    uint2 *tie;            // (sorted A pos, 0)
+    uint32_t tie_cap;
+    // collect pass (tie resolution): sorted A positions and separation limits
+    const uint32_t *col_pos;
+    const double *col_lim;
+    uint32_t n_col;
+    uint32_t *col_n;
+    uint4 *col;            // (col entry, idxB, sep hi, sep lo)
+    uint32_t col_cap;
+    // counters
+    unsigned long long *n_tests;
+    unsigned long long *n_band;
+    uint32_t *err_flag;    // bit 0: write overflow, bit 1: count mismatch
+};
+
+// ----------------------------------------------------------------------------
+// device geometry
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ int zone_of(double dec, const Grid &g)
+{
+    double t = floor((dec + 90.0) * g.inv_h);
+    if (!(t >= 0.0)) return 0;
+    if (t >= (double)g.nz) return g.nz - 1;
+    return (int)t;
+}
+
+__device__ __forceinline__ uint32_t cell_of(int z, double ra, const Grid &g)
+{
+    double t = floor(ra * g.zf[z]);
+    uint32_t n = g.zn[z];
+    if (!(t >= 0.0)) return 0;
+    if (t >= (double)n) return n - 1;
+    return (uint32_t)t;
+}
+
+// Reference vector of cell (z, c): zone reference Dec and the RA grid point
+// nearest the cell centre, both from tables, so every kernel gets identical
+// bits (products only, no additions to contract).
+__device__ __forceinline__ void cell_ref(int z, uint32_t c, const Grid &g, double &rx,
+                                         double &ry, double &rz)
+{
+    uint64_t n = g.zn[z];
+    uint64_t gidx = (((uint64_t)(2 * c + 1) << kRefBits) + n) / (2 * n);
+    gidx &= (1u << kRefBits) - 1;
+    double2 zr = g.zref[z];
+    double2 ar = g.rref[gidx];
+    rx = zr.x * ar.x;
+    ry = zr.x * ar.y;
+    rz = zr.y;
+}
+
+__device__ __forceinline__ void unit_vec(double ra, double dec, double &x, double &y, double &z)
+{
+    double sa, ca, sd, cd;
+    sincos(ra * kDeg, &sa, &ca);
+    sincos(dec * kDeg, &sd, &cd);
+    x = cd * ca;
+    y = cd * sa;
+    z = sd;
+}
+
+// cos(dec) with small relative error also near the poles.
+__device__ __forceinline__ double cos_dec_acc(double dec)
+{
+    double ad = fabs(dec);
+    if (ad > 45.0) return sin(kDeg * (90.0 - ad));
+    return cos(kDeg * dec);
+}
+
+// ra2 - ra1 reduced to (-180, 180] keeping relative accuracy (360 - ra is
+// exact for ra > 180).
+__device__ __forceinline__ double wrap_dra(double ra1, double ra2)
+{
+    double d = ra2 - ra1;
+    if (d > 180.0) return -((360.0 - ra2) + ra1);
+    if (d < -180.0) return (360.0 - ra1) + ra2;
+    return d;
+}
+
+__device__ __forceinline__ double haversine(double ra1, double dec1, double cd1, double ra2,
+                                            double dec2, double cd2)
+{
+    double s1 = sin(kHalfDeg * (dec2 - dec1));
+    double s2 = sin(kHalfDeg * wrap_dra(ra1, ra2));
+    return s1 * s1 + (cd1 * cd2) * (s2 * s2);
+}
+
+// Tangent-plane components (north, east) of point 2 seen from point 1.
+__device__ __forceinline__ void tangent_ne(double ra1, double dec1, double sd1, double ra2,
+                                           double dec2, double cd2, double &tn, double &te)
+{
+    double da = wrap_dra(ra1, ra2);
+    double s2 = sin(kHalfDeg * da);
+    tn = sin(kDeg * (dec2 - dec1)) + 2.0 * sd1 * cd2 * (s2 * s2);
+    te = cd2 * sin(kDeg * da);
+}
+
+// Separation in arcsec, accurate to a few ulps at every angle.
+__device__ __forceinline__ double sep_arcsec(const ARec &a, double ra2, double dec2)
+{
+    double cd2 = cos_dec_acc(dec2);
+    double tn, te;
+    tangent_ne(a.ra, a.dec, a.z, ra2, dec2, cd2, tn, te);
+    double h = haversine(a.ra, a.dec, a.cosd, ra2, dec2, cd2);
+    double th = atan2(sqrt(tn * tn + te * te), 1.0 - 2.0 * h);
+    return th * (180.0 / kPi * 3600.0);
+}
+
+// FP64 relative-accuracy recheck of the circle (error <= ~90 u against a
+// 2^-40 margin: see the library design notes).
+__device__ __forceinline__ int recheck_circle(const ARec &a, double2 rb, double h_r)
+{
+    double cd2 = cos_dec_acc(rb.y);
+    double h = haversine(a.ra, a.dec, a.cosd, rb.x, rb.y, cd2);
+    if (h <= h_r * (1.0 - kE40)) return IN;
+    if (h > h_r * (1.0 + kE40)) return OUT;
+    return AMBIG;
+}
+
+__device__ __forceinline__ int recheck_ellipse(const ARec &a, const AEllR &e, double2 rb)
+{
+    double cd2 = cos_dec_acc(rb.y);
+    double h = haversine(a.ra, a.dec, a.cosd, rb.x, rb.y, cd2);
+    if (h == 0.0) return IN;
+    double sa = sin(kHalfDeg * (e.a_arcsec / 3600.0));
+    if (h > (sa * sa) * (1.0 + kE40)) return OUT;
+    double tn, te;
+    tangent_ne(a.ra, a.dec, a.z, rb.x, rb.y, cd2, tn, te);
+    double th = 2.0 * asin(sqrt(h));
+    double sth = 2.0 * sqrt(h) * sqrt(1.0 - h);
+    double f = th / sth;
+    double su = tn * e.ct + te * e.st;
+    double sv = te * e.ct - tn * e.st;
+    double x = su / (kDeg * (e.a_arcsec / 3600.0));
+    double y = sv / (kDeg * (e.b_arcsec / 3600.0));
+    double q = (f * f) * (x * x + y * y);
+    double m = kE38 * (1.0 + e.a_arcsec / e.b_arcsec);
+    if (q <= 1.0 - m) return IN;
+    if (q > 1.0 + m) return OUT;
+    return AMBIG;
+}
+
+__device__ __forceinline__ bool same_point(const ARec &a, double2 rb)
+{
+    return a.dec == rb.y && (a.ra == rb.x || fabs(a.dec) == 90.0);
+}
+
+// First sorted position whose key is >= k (keys ascending).
+__device__ __forceinline__ uint32_t key_lower_bound(const Grid &g, uint32_t k)
+{
+    uint32_t q = k >> g.dshift;
+    if (q + 1 >= g.dsize) return (uint32_t)g.nB;
+    uint32_t lo = g.dir[q], hi = min(g.dir[q + 1], (uint32_t)g.nB);
+    while (lo < hi) {
+        uint32_t m = lo + ((hi - lo) >> 1);
+        if (g.keys[m] < k) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+// Calls f(zone, j0, j1) for every contiguous range of sorted B positions whose
+// cells can hold a source within reach_deg of (ra, dec). Exact superset:
+// zones cover [dec - R, dec + R] and each zone the RA interval
+// [ra - dRA, ra + dRA], dRA = asin(sin R / cos dec) (the widest RA extent of
+// a cap), split at RA = 0/360; a cap holding a pole, or a window of 180 deg
+// or more, takes the whole zone. The pads absorb every rounding of the
+// window arithmetic, and zone_of / cell_of are monotone.
+template <typename F>
+__device__ __forceinline__ void for_each_range(const Grid &g, double ra, double dec, double cosd,
+                                               double reach_deg, F &&f)
+{
+    double rp = reach_deg * (1.0 + 1e-9) + 1e-12;
+    int zlo = zone_of(dec - rp, g);
+    int zhi = zone_of(dec + rp, g);
+    bool full = false;
+    double dra = 0.0;
+    if (fabs(dec) + rp >= 90.0) {
+        full = true;
+    } else {
+        double x = sin(kDeg * rp) / cosd;
+        if (x >= 0.9999) {
+            full = true;
+        } else {
+            dra = asin(x) / kDeg * (1.0 + 1e-9) + 1e-12;
+            if (dra >= 180.0) full = true;
+        }
+    }
+    for (int z = zlo; z <= zhi; ++z) {
+        uint32_t base = g.zbase[z];
+        uint32_t n = g.zn[z];
+        uint32_t c0[2], c1[2];
+        int nr = 0;
+        bool zfull = full;
+        if (!zfull) {
+            double lo = ra - dra, hi = ra + dra;
+            if (lo < 0.0) {
+                uint32_t a0 = cell_of(z, lo + 360.0, g), b1 = cell_of(z, hi, g);
+                if (a0 <= b1) zfull = true;
+                else {
+                    c0[0] = 0; c1[0] = b1;
+                    c0[1] = a0; c1[1] = n - 1;
+                    nr = 2;
+                }
+            } else if (hi >= 360.0) {
+                uint32_t a0 = cell_of(z, lo, g), b1 = cell_of(z, hi - 360.0, g);
+                if (a0 <= b1) zfull = true;
+                else {
+                    c0[0] = 0; c1[0] = b1;
+                    c0[1] = a0; c1[1] = n - 1;
+                    nr = 2;
+                }
+            } else {
+                c0[0] = cell_of(z, lo, g);
+                c1[0] = cell_of(z, hi, g);
+                nr = 1;
+            }
+        }
+        if (zfull) {
+            c0[0] = 0;
+            c1[0] = n - 1;
+            nr = 1;
+        }
+        for (int k = 0; k < nr; ++k) {
+            uint32_t j0 = key_lower_bound(g, base + c0[k]);
+            uint32_t j1 = key_lower_bound(g, base + c1[k] + 1);
+            if (j0 < j1) f(z, j0, j1);
+        }
+    }
+}
+
+}  // namespace c3x
+
+// ----------------------------------------------------------------------------
+// host-side pieces shared between translation units
+// ----------------------------------------------------------------------------
+namespace c3x {
+
+void set_error(const char *fmt, ...);
+
+// binary128 fallback (exact128.cpp, compiled without HIP)
+extern "C" int c3x_q_circle(double ra1, double dec1, double ra2, double dec2, double r_arcsec);
+extern "C" int c3x_q_ellipse(double ra1, double dec1, double ra2, double dec2, double a_arcsec,
+                             double b_arcsec, double pa_deg, double pa_zero_deg, int pa_sense);
+extern "C" int c3x_q_best(double ra1, double dec1, int n, const double *ra2, const double *dec2,
+                          const int32_t *idx);
+extern "C" void c3x_q_thresholds(double r_arcsec, double *h_r, double *cr2);
+
+}  // namespace c3x

@@ -1,0 +1,23 @@
+// c3x_sort.h -- radix sort and scan entry points (device buffers, stream-ordered).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace c3x {
+
+// Workspace for radix_sort_pairs over n elements.
+size_t radix_ws_bytes(int64_t n);
+// Stable LSD sort of (keys, vals) on the low nbits bits. The sorted data end
+// up in (keys, vals) if *in_tmp == 0 on return, else in (ktmp, vtmp).
+hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
+                            int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp);
+
+size_t scan_ws_bytes(int64_t n);
+// Exclusive scans; *total (device, may be NULL) receives the sum.
+hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total, void *ws,
+                           hipStream_t s);
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *ws,
+                    hipStream_t s);
+
+}  // namespace c3x

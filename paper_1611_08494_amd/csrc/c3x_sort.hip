@@ -1,0 +1,295 @@
+// c3x_sort.hip -- LSD radix sort of (u32 key, u32 value) pairs and prefix
+// scans, written for 64-wide CDNA wavefronts.
+//
+// Sort: 8-bit digits, only as many passes as the key range needs. Each pass
+// is a digit histogram per 4096-element tile (LDS atomics), a scan of the
+// digit-major histogram table, and a stable scatter: every round of 256
+// elements is ranked per wavefront with ballots (eight ballots match the
+// lanes that share a digit; mbcnt gives the rank among them), wave counts go
+// through LDS so later waves land after earlier ones, and the round's keys
+// are staged in LDS in digit order so that the global writes of a digit run
+// are contiguous.
+#include "c3x_internal.h"
+#include "c3x_sort.h"
+
+namespace c3x {
+
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 4096
+constexpr int kWaves = kSortBlock / 64;
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    unsigned lane = __lane_id();
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+__device__ __forceinline__ unsigned rank_in_mask(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_digit_hist(const uint32_t *__restrict__ keys,
+                                                           int64_t n, int shift,
+                                                           uint32_t *__restrict__ hist,
+                                                           int nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; ++r) {
+        int64_t e = base + r * kSortBlock + threadIdx.x;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ offs, int nblocks)
+{
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t rstart[256];   // start of each digit inside the round
+    __shared__ uint32_t skey[kSortBlock], sval[kSortBlock];
+    __shared__ uint32_t sdig[kSortBlock];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    base[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        int64_t e = tbase + r * kSortBlock + tid;
+        bool valid = e < n;
+        uint32_t k = valid ? kin[e] : 0u;
+        uint32_t v = valid ? vin[e] : 0u;
+        uint32_t d = (k >> shift) & 255u;
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        unsigned rank = rank_in_mask(peers & lanemask_lt());
+        bool leader = valid && rank == 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        // exclusive scan of the round's digit counts -> rstart (one digit per thread)
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) tot += wcnt[w][tid];
+        // block exclusive scan of tot over 256 threads
+        uint32_t x = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o);
+            if ((tid & 63) >= o) x += y;
+        }
+        __shared__ uint32_t wsum[kWaves];
+        if ((tid & 63) == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (int w = 0; w < wave; ++w) pre += wsum[w];
+        rstart[tid] = pre + x - tot;
+        __syncthreads();
+        if (valid) {
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+            uint32_t slot = rstart[d] + before + rank;   // position in digit order
+            skey[slot] = k;
+            sval[slot] = v;
+            sdig[slot] = d;
+        }
+        __syncthreads();
+        int nvalid = (int)min<int64_t>(kSortBlock, max<int64_t>(0, n - (tbase + r * kSortBlock)));
+        if (tid < nvalid) {
+            uint32_t dd = sdig[tid];
+            uint32_t dst = base[dd] + (tid - rstart[dd]);
+            if (dst < (uint64_t)n) {
+                kout[dst] = skey[tid];
+                vout[dst] = sval[tid];
+            }
+        }
+        __syncthreads();
+        base[tid] += tot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------- scans
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T &total)
+{
+    __shared__ T ws[kScanBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    T inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    T pre = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kScanBlock / 64; ++w) {
+        if (w < wave) pre += ws[w];
+        total += ws[w];
+    }
+    __syncthreads();
+    return pre + inc - x;
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const Ti *__restrict__ in, int64_t n,
+                                                            To *__restrict__ part)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    To s = 0;
+    for (int r = 0; r < kScanItems; ++r) {
+        int64_t e = base + r * kScanBlock + threadIdx.x;
+        if (e < n) s += (To)in[e];
+    }
+    To tot;
+    block_excl_scan<To>(s, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <typename To>
+__global__ __launch_bounds__(kScanBlock) void k_scan_partials(To *part, int64_t np, To *total)
+{
+    To carry = 0;
+    for (int64_t b = 0; b < np; b += kScanBlock) {
+        int64_t e = b + threadIdx.x;
+        To x = e < np ? part[e] : (To)0;
+        To tot;
+        To ex = block_excl_scan<To>(x, tot);
+        if (e < np) part[e] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kScanBlock) void k_scan_final(const Ti *__restrict__ in, int64_t n,
+                                                           const To *__restrict__ part,
+                                                           To *__restrict__ out)
+{
+    __shared__ To tile[kScanTile];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int r = 0; r < kScanItems; ++r) {
+        int i = r * kScanBlock + threadIdx.x;
+        int64_t e = base + i;
+        tile[i] = e < n ? (To)in[e] : (To)0;
+    }
+    __syncthreads();
+    To v[kScanItems];
+    To s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        v[r] = tile[threadIdx.x * kScanItems + r];
+        s += v[r];
+    }
+    To tot;
+    To run = block_excl_scan<To>(s, tot) + part[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        tile[threadIdx.x * kScanItems + r] = run;
+        run += v[r];
+    }
+    __syncthreads();
+    for (int r = 0; r < kScanItems; ++r) {
+        int i = r * kScanBlock + threadIdx.x;
+        int64_t e = base + i;
+        if (e < n) out[e] = tile[i];
+    }
+}
+
+size_t scan_ws_bytes(int64_t n)
+{
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(nb + 1) * sizeof(int64_t);
+}
+
+template <typename Ti, typename To>
+static hipError_t scan_impl(const Ti *in, To *out, int64_t n, To *total, void *ws, hipStream_t s)
+{
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    To *part = (To *)ws;
+    if (n == 0) {
+        if (total) return hipMemsetAsync(total, 0, sizeof(To), s);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL((k_scan_reduce<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
+                       part);
+    hipLaunchKernelGGL((k_scan_partials<To>), dim3(1), dim3(kScanBlock), 0, s, part, nb, total);
+    hipLaunchKernelGGL((k_scan_final<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
+                       part, out);
+    return hipGetLastError();
+}
+
+hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total, void *ws,
+                           hipStream_t s)
+{
+    return scan_impl<uint32_t, int64_t>(in, out, n, total, ws, s);
+}
+
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *ws,
+                    hipStream_t s)
+{
+    return scan_impl<uint32_t, uint32_t>(in, out, n, total, ws, s);
+}
+
+size_t radix_ws_bytes(int64_t n)
+{
+    int64_t nb = (n + kSortTile - 1) / kSortTile;
+    size_t hist = (size_t)256 * (size_t)(nb > 0 ? nb : 1) * sizeof(uint32_t);
+    return 2 * hist + scan_ws_bytes(256 * (nb > 0 ? nb : 1)) + 256;
+}
+
+hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
+                            int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp)
+{
+    *in_tmp = 0;
+    if (n <= 1 || nbits <= 0) return hipSuccess;
+    int64_t nb = (n + kSortTile - 1) / kSortTile;
+    uint32_t *hist = (uint32_t *)ws;
+    uint32_t *offs = hist + 256 * nb;
+    void *sws = (void *)(offs + 256 * nb);
+    uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, n, shift,
+                           hist, (int)nb);
+        hipError_t e = scan_u32(hist, offs, 256 * nb, nullptr, sws, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, va, kb,
+                           vb, n, shift, offs, (int)nb);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint32_t *t = ka;
+        ka = kb;
+        kb = t;
+        t = va;
+        va = vb;
+        vb = t;
+        *in_tmp ^= 1;
+    }
+    return hipSuccess;
+}
+
+}  // namespace c3x

@@ -1,0 +1,120 @@
+// exact128.cpp -- host binary128 decisions for the few cases the GPU's
+// certified FP64 arithmetic leaves undecided.
+//
+// The predicates are those of the "Sky" case (paper Section 2.1): theta <= r
+// for the circle, the azimuthal-equidistant ellipse form Q <= 1 for the
+// ellipse (PA from north through east, T = pa_zero + pa_sense * PA), and the
+// exact argmin of (theta, index) for the best match (Section 2.2).
+// binary128 carries 113 bits; every value below is computed to a relative
+// error of about 2^-106, so a difference from the threshold under 2^-96
+// (relative) is taken as an exact tie, which the inclusive boundary puts
+// inside and the best-match rule breaks by the lower index.
+#include <quadmath.h>
+#include <stdint.h>
+
+typedef __float128 q128;
+
+static const q128 kTie = 1.2621774483536188886587657044524579674771e-29Q;  // 2^-96
+
+static inline q128 qdeg() { return M_PIq / 180; }
+
+struct QPts {
+    q128 d1, d2, dd, da;
+};
+
+static inline QPts pieces(double ra1, double dec1, double ra2, double dec2)
+{
+    QPts p;
+    q128 k = qdeg();
+    p.d1 = (q128)dec1 * k;
+    p.d2 = (q128)dec2 * k;
+    p.dd = ((q128)dec2 - (q128)dec1) * k;
+    p.da = ((q128)ra2 - (q128)ra1) * k;
+    return p;
+}
+
+static inline q128 qhav(const QPts &p)
+{
+    q128 s1 = sinq(p.dd / 2), s2 = sinq(p.da / 2);
+    return s1 * s1 + cosq(p.d1) * cosq(p.d2) * s2 * s2;
+}
+
+static inline q128 qtheta(double ra1, double dec1, double ra2, double dec2)
+{
+    QPts p = pieces(ra1, dec1, ra2, dec2);
+    q128 h = qhav(p);
+    if (h < 0) h = 0;
+    if (h > 1) h = 1;
+    return 2 * asinq(sqrtq(h));
+}
+
+static inline bool same_point(double ra1, double dec1, double ra2, double dec2)
+{
+    return dec1 == dec2 && (ra1 == ra2 || dec1 == 90.0 || dec1 == -90.0);
+}
+
+extern "C" int c3x_q_circle(double ra1, double dec1, double ra2, double dec2, double r_arcsec)
+{
+    if (r_arcsec == 0.0) return same_point(ra1, dec1, ra2, dec2) ? 1 : 0;
+    q128 th = qtheta(ra1, dec1, ra2, dec2);
+    q128 R = (q128)r_arcsec / 3600 * qdeg();
+    q128 d = th - R;
+    if (fabsq(d) <= kTie * R) return 1;
+    return d < 0 ? 1 : 0;
+}
+
+extern "C" int c3x_q_ellipse(double ra1, double dec1, double ra2, double dec2, double a_arcsec,
+                             double b_arcsec, double pa_deg, double pa_zero_deg, int pa_sense)
+{
+    QPts p = pieces(ra1, dec1, ra2, dec2);
+    q128 h = qhav(p);
+    if (h <= 0) return 1;
+    q128 th = 2 * asinq(sqrtq(h));
+    q128 s2 = sinq(p.da / 2);
+    q128 tn = sinq(p.dd) + 2 * sinq(p.d1) * cosq(p.d2) * s2 * s2;
+    q128 te = cosq(p.d2) * sinq(p.da);
+    q128 T = ((q128)pa_zero_deg + (q128)pa_sense * (q128)pa_deg) * qdeg();
+    q128 ct = cosq(T), st = sinq(T);
+    q128 su = tn * ct + te * st;
+    q128 sv = te * ct - tn * st;
+    q128 A = (q128)a_arcsec / 3600 * qdeg();
+    q128 B = (q128)b_arcsec / 3600 * qdeg();
+    q128 f = th / sinq(th);
+    q128 x = su / A, y = sv / B;
+    q128 Q = f * f * (x * x + y * y);
+    q128 d = Q - 1;
+    if (fabsq(d) <= kTie) return 1;
+    return d < 0 ? 1 : 0;
+}
+
+// Index (into the candidate list) of the exact argmin of (theta, idx).
+extern "C" int c3x_q_best(double ra1, double dec1, int n, const double *ra2, const double *dec2,
+                          const int32_t *idx)
+{
+    int best = -1;
+    q128 bt = 0;
+    for (int k = 0; k < n; ++k) {
+        q128 t = qtheta(ra1, dec1, ra2[k], dec2[k]);
+        if (best < 0) {
+            best = k;
+            bt = t;
+            continue;
+        }
+        q128 scale = bt > t ? bt : t;
+        bool tie = fabsq(t - bt) <= kTie * scale;
+        if (tie ? idx[k] < idx[best] : t < bt) {
+            best = k;
+            bt = tie ? (bt < t ? bt : t) : t;
+        }
+    }
+    return best;
+}
+
+// sin^2(r/2) and the squared chord 4 sin^2(r/2), r in arcsec, each rounded
+// to the nearest double.
+extern "C" void c3x_q_thresholds(double r_arcsec, double *h_r, double *cr2)
+{
+    q128 s = sinq((q128)r_arcsec / 7200 * qdeg());
+    *h_r = (double)(s * s);
+    *cr2 = (double)(4 * s * s);
+}

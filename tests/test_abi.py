@@ -1,0 +1,110 @@
+"""Host-side checks of libc3x.so that need no GPU: the library loads, exports
+every function include/c3x.h declares, rejects bad arguments before touching
+the device, and its binary128 fallback decides the closed-form cases right."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "c3x.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(c3x_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1611_08494_amd as c3x
+    return c3x.lib()
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for f in ("c3x_build_index", "c3x_match", "c3x_result_sizes", "c3x_result_copy",
+              "c3x_result_stats", "c3x_result_free", "c3x_index_free", "c3x_last_error",
+              "c3x_version", "c3x_abi_version", "c3x_index_stats"):
+        assert f in fns
+
+
+def test_every_declared_symbol_is_exported(L):
+    for f in header_functions():
+        assert hasattr(L, f), f
+
+
+def test_version(L):
+    assert L.c3x_abi_version() == 1
+    assert b"gfx950" in L.c3x_version()
+
+
+def test_argument_errors_need_no_device(L):
+    from paper_1611_08494_amd import _binding as b
+    h = ctypes.c_void_p()
+    assert L.c3x_build_index(None, None, -1, 0, 1.0, None, ctypes.byref(h)) == b.EINVAL
+    assert h.value is None
+    assert b"nB < 0" in L.c3x_last_error()
+    assert L.c3x_build_index(None, None, 1 << 31, 0, 1.0, None, ctypes.byref(h)) == b.ERANGE
+    assert L.c3x_build_index(None, None, 5, 0, 1.0, None, ctypes.byref(h)) == b.EINVAL
+    assert L.c3x_build_index(None, None, 0, 7, 1.0, None, ctypes.byref(h)) == b.EINVAL
+    assert L.c3x_build_index(None, None, 0, 0, -1.0, None, ctypes.byref(h)) == b.EINVAL
+    area = b.Area(shape=0, radius_arcsec=1.0, pa_sense=1)
+    assert L.c3x_match(None, None, None, 0, 0, ctypes.byref(area), 3, None,
+                       ctypes.byref(h)) == b.EINVAL
+    assert L.c3x_result_sizes(None, None, None) == b.EINVAL
+
+
+def _q(L):
+    L.c3x_q_circle.argtypes = [ctypes.c_double] * 5
+    L.c3x_q_circle.restype = ctypes.c_int
+    L.c3x_q_ellipse.argtypes = [ctypes.c_double] * 8 + [ctypes.c_int]
+    L.c3x_q_ellipse.restype = ctypes.c_int
+    return L
+
+
+def test_binary128_fallback_closed_forms(L):
+    """The host fallback alone (no FP64 ladder in front) gets every
+    closed-form case of tests/golden right."""
+    from test_oracle_pins import CLOSED
+    Q = _q(L)
+    bad = []
+    for r in CLOSED:
+        if r["shape"] == 0:
+            got = Q.c3x_q_circle(r["raA"], r["decA"], r["raB"], r["decB"], r["r"])
+        else:
+            got = Q.c3x_q_ellipse(r["raA"], r["decA"], r["raB"], r["decB"], r["a"], r["b"],
+                                  r["pa"], r["pz"], r["sense"])
+        if bool(got) != r["inside"]:
+            bad.append(r)
+    assert not bad, bad[:3]
+
+
+def test_binary128_thresholds(L):
+    L.c3x_q_thresholds.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
+    h = ctypes.c_double()
+    c = ctypes.c_double()
+    for r in (1e-6, 0.5, 1.0, 2.0, 60.0, 3600.0, 324000.0):
+        L.c3x_q_thresholds(r, ctypes.byref(h), ctypes.byref(c))
+        s = math.sin(r / 7200.0 * math.pi / 180.0)
+        assert h.value == pytest.approx(s * s, rel=1e-14)
+        assert c.value == pytest.approx(4 * s * s, rel=1e-14)
+
+
+def test_binary128_against_200bit_on_near_boundary_pairs(L):
+    """Random pairs placed within 2^-45 of the circle: binary128 and the
+    oracle's 200-bit decider agree on every one."""
+    import synth
+    from oracle import exact
+    Q = _q(L)
+    c = synth.adversarial_circle(radius_arcsec=2.0, n_centres=16)
+    n = c.nA
+    for k in range(c.nB):
+        i = k % n
+        want = exact.decide_circle(c.raA[i], c.decA[i], c.raB[k], c.decB[k], 2.0)
+        assert bool(Q.c3x_q_circle(c.raA[i], c.decA[i], c.raB[k], c.decB[k], 2.0)) == want
