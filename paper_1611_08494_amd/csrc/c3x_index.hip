@@ -9,12 +9,14 @@
 //   k_prep_b    validate rows, key + row index          16 B in, 8 B out
 //   radix sort  (key, row) by key, ceil(bits/8) passes   16 B per pass
 //   k_gather_b  payload in sorted order                   16 B in, 36/52 B out
-//   k_dir       coarse directory over key >> dshift
+//   k_dir_hist  bucket histogram of key >> dshift, then an exclusive scan:
+//               dir[q] = number of keys in buckets below q
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "c3x_host.h"
 #include "c3x_sort.h"
@@ -52,7 +54,9 @@ static void build_zones(GridPlan &p, double cell_arcsec)
         p.zref[2 * z + 1] = sin(dc * kDeg);
         // largest distance from a point of a cell to the cell's reference
         double ddec = std::max(hi - dc, dc - lo);
-        double dra = (180.0 / n + 180.0 / (1 << kRefBits)) * ceq;
+        // RA half-cell + half a reference-grid step (+1e-6 rad of slack for
+        // the FP32 sine/cosine of the grid point)
+        double dra = (180.0 / n + 180.0 / (1 << kRefBits)) * ceq + 1e-6 / kDeg;
         double ang = sqrt(ddec * ddec + dra * dra) * kDeg;
         L = std::max(L, ang);
     }
@@ -79,8 +83,9 @@ c3x_status plan_grid(GridPlan &p, int64_t nB, double reach_arcsec, double cell_r
     int bits = 0;
     while (bits < 32 && (maxkey >> bits)) ++bits;
     p.key_bits = bits;
-    // directory: about one entry per four B rows
-    uint64_t want = std::max<uint64_t>(1, (uint64_t)(nB / 4));
+    // directory: about two entries per B row, so that a bucket of the
+    // uniform sky holds about one key and a lookup is one or two loads
+    uint64_t want = std::max<uint64_t>(1024, (uint64_t)nB * 2);
     int sh = 0;
     while (sh < 31 && (maxkey >> sh) + 1 > want) ++sh;
     p.dshift = sh;
@@ -104,7 +109,8 @@ __global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict
         d = 0.0;
     }
     int z = zone_of(d, g);
-    keys[j] = g.zbase[z] + cell_of(z, a, g);
+    const ZoneInfo zi = g.zinfo[z];
+    keys[j] = zi.base + cell_in(zi, a);
     rows[j] = (uint32_t)j;
 }
 
@@ -144,29 +150,24 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double *__re
     }
 }
 
-// dir[t] = number of keys with (key >> dshift) < t.
-__global__ void k_dir(const uint32_t *__restrict__ keys, int64_t n, int dshift, uint32_t dsize,
-                      uint32_t *__restrict__ dir)
+// Bucket histogram over the sorted keys: lanes holding the same bucket are
+// adjacent, so each run is added once by its first lane.
+__global__ void k_dir_hist(const uint32_t *__restrict__ keys, int64_t n, int dshift,
+                           uint32_t *__restrict__ cnt)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= dsize) return;
-    uint64_t k = (uint64_t)t << dshift;
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        int64_t m = (lo + hi) >> 1;
-        if ((uint64_t)keys[m] < k) lo = m + 1;
-        else hi = m;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = s < n;
+    uint32_t q = valid ? keys[s] >> dshift : 0xffffffffu;
+    uint32_t prev = __shfl_up(q, 1);
+    unsigned lane = __lane_id();
+    bool lead = valid && (lane == 0 || prev != q);
+    uint64_t L = __ballot(lead);
+    uint64_t V = __ballot(valid);
+    if (lead) {
+        uint64_t after = lane == 63 ? 0ull : (L >> (lane + 1)) << (lane + 1);
+        unsigned end = after ? (unsigned)__ffsll((long long)after) - 1 : (unsigned)(64 - __clzll((long long)V));
+        atomicAdd(&cnt[q], end - lane);
     }
-    dir[t] = (uint32_t)lo;
-}
-
-__global__ void k_ref_table(double2 *__restrict__ t)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (1 << kRefBits)) return;
-    double s, c;
-    sincospi((double)i / (double)(1 << (kRefBits - 1)), &s, &c);
-    t[i] = make_double2(c, s);
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -176,31 +177,26 @@ c3x_status upload_grid(c3x_index *ix, hipStream_t s)
 {
     GridPlan &p = ix->plan;
     Grid &g = ix->grid;
-    uint32_t *zbase = ix->mem.get_n<uint32_t>(p.nz + 1);
-    uint32_t *zn = ix->mem.get_n<uint32_t>(p.nz);
-    double *zf = ix->mem.get_n<double>(p.nz);
+    ZoneInfo *zinfo = ix->mem.get_n<ZoneInfo>(p.nz);
     double2 *zref = ix->mem.get_n<double2>(p.nz);
-    double2 *rref = ix->mem.get_n<double2>(1 << kRefBits);
-    if (!zbase || !zn || !zf || !zref || !rref) return fail(C3X_ENOMEM, "index tables");
-    hipError_t e = hipMemcpyAsync(zbase, p.zbase.data(), (p.nz + 1) * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(zn, p.zn.data(), p.nz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(zf, p.zf.data(), p.nz * sizeof(double), hipMemcpyHostToDevice, s);
+    if (!zinfo || !zref) return fail(C3X_ENOMEM, "index tables");
+    std::vector<ZoneInfo> zh(p.nz);
+    for (int z = 0; z < p.nz; ++z) {
+        zh[z].base = p.zbase[z];
+        zh[z].n = p.zn[z];
+        zh[z].f = p.zf[z];
+    }
+    hipError_t e = hipMemcpyAsync(zinfo, zh.data(), p.nz * sizeof(ZoneInfo), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(zref, p.zref.data(), p.nz * sizeof(double2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables go out of scope
     if (e != hipSuccess) return fail_hip(e, "index tables");
-    hipLaunchKernelGGL(k_ref_table, dim3(nblk(1 << kRefBits, 256)), dim3(256), 0, s, rref);
     g.h_deg = p.h_deg;
     g.inv_h = 1.0 / p.h_deg;
     g.nz = p.nz;
     g.ncells = (uint32_t)p.ncells;
-    g.zbase = zbase;
-    g.zf = zf;
-    g.zn = zn;
+    g.zinfo = zinfo;
     g.zref = zref;
-    g.rref = rref;
     g.dshift = p.dshift;
     g.dsize = p.dsize;
     return C3X_OK;
@@ -266,7 +262,10 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     if (o.precision == C3X_FP64) p64 = ix->mem.get_n<Pay64>(n);
     else p32 = ix->mem.get_n<Pay32>(n);
     uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
-    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !radec || !dir || (!p64 && !p32)) {
+    uint32_t *dcnt = tmp.get_n<uint32_t>(ix->plan.dsize);
+    void *dws = tmp.get(scan_ws_bytes(ix->plan.dsize));
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !radec || !dir || !dcnt || !dws ||
+        (!p64 && !p32)) {
         (void)hipStreamSynchronize(s);
         delete ix;
         return fail(C3X_ENOMEM, "index buffers");
@@ -294,9 +293,11 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
                                ra_deg, dec_deg, n, g, p64, p32, radec);
         e = hipGetLastError();
     }
-    if (e == hipSuccess)
-        hipLaunchKernelGGL(k_dir, dim3(nblk(ix->plan.dsize, 256)), dim3(256), 0, s, keys, n,
-                           ix->plan.dshift, ix->plan.dsize, dir);
+    if (e == hipSuccess) e = hipMemsetAsync(dcnt, 0, (size_t)ix->plan.dsize * 4, s);
+    if (e == hipSuccess && n > 0)
+        hipLaunchKernelGGL(k_dir_hist, dim3(nblk(n, 256)), dim3(256), 0, s, keys, n,
+                           ix->plan.dshift, dcnt);
+    if (e == hipSuccess) e = scan_u32(dcnt, dir, ix->plan.dsize, nullptr, dws, s);
     tm.mark();
     uint32_t bad_h = 0xffffffffu;
     if (e == hipSuccess) e = hipGetLastError();

@@ -29,6 +29,12 @@ constexpr int kRefBits = 16;                     // RA reference grid, 2^16 poin
 
 enum Decision : int { OUT = 0, IN = 1, AMBIG = 2 };
 
+// One zone of the grid: first key, number of RA cells, cells per degree.
+struct alignas(16) ZoneInfo {
+    uint32_t base, n;
+    double f;              // n / 360
+};
+
 // Grid of declination zones split into RA cells (the paper's cells,
 // restated for the sphere). Passed by value to kernels.
 struct Grid {
@@ -36,11 +42,8 @@ struct Grid {
     double inv_h;          // 1 / h_deg
     int32_t nz;            // number of zones
     uint32_t ncells;       // total cells
-    const uint32_t *zbase; // [nz + 1] first key of each zone
-    const double *zf;      // [nz] n_z / 360 (cells per degree of RA)
-    const uint32_t *zn;    // [nz] n_z, cells in the zone
+    const ZoneInfo *zinfo; // [nz]
     const double2 *zref;   // [nz] cos, sin of the zone's reference Dec
-    const double2 *rref;   // [2^kRefBits] cos, sin of the RA reference grid
     const uint32_t *keys;  // [nB] sorted keys of B
     const uint32_t *dir;   // [dsize] coarse directory over key >> dshift
     int32_t dshift;
@@ -57,9 +60,10 @@ struct alignas(16) Pay32 {
     uint32_t idx;
 };
 
-// Sorted A record (FP64): position, unit vector (z = sin Dec), cos Dec with
-// small relative error near the poles, reach of the area in degrees.
-struct alignas(64) ARec {
+// One A source as a match lane sees it: position, unit vector (z = sin Dec),
+// cos Dec with small relative error near the poles, reach of its area.
+// Rebuilt from (ra, dec) inside each kernel, so every pass gets the same bits.
+struct ARec {
     double ra, dec, x, y, z, cosd, reach_deg;
     uint32_t idx, pad;
 };
@@ -77,54 +81,58 @@ struct AEllR {             // what the FP64 recheck needs
     float pad;
 };
 
+// Per-A counters of the count pass (idxA order).
+struct AStat {
+    uint32_t cnt;          // matches
+    uint32_t best_j;       // sorted B position of the best match
+};
+
 // Everything a match kernel needs; passed by value.
 struct MatchArgs {
     Grid g;
     const Pay64 *pay64;
     const Pay32 *pay32;
     const double2 *radecB;
-    const ARec *arec;
+    const double2 *arad;   // sorted A coordinates
+    const uint32_t *aidx;  // sorted A rows
     const AEll *aell;
     const AEllR *aellr;
     int32_t nA;
+    double reach_deg;      // circle reach
     // circle thresholds on the squared chord
     double cr2;            // 4 sin^2(r/2)
     double t64_in, t64_out;
     float t32_in, t32_out;
     double h_r;            // sin^2(r/2) for the haversine recheck
     int32_t r_zero;        // radius exactly 0
-    double reach_pad_deg;  // extra reach pad
+    double L_rad;          // bound on |p - cell reference| (FP32 error model)
     // count pass
-    uint32_t *cnt;         // [nA] in idxA order
-    // ambiguous list (count pass)
-    uint32_t *amb_n;       // counter
-    uint2 *amb;            // (sorted A pos, sorted B pos)
+    AStat *astat;          // [nA] idxA order
+    int32_t *best_idx;     // [nA] idxA order
+    uint32_t *amb_n;       // band candidates: (sorted A pos, sorted B pos)
+    uint2 *amb;
     uint32_t amb_cap;
-    // verdicts (write pass): sorted keys (i << 32 | j) with verdict bit
+    uint32_t *tie_n;       // near-tie best matches: (sorted A pos, row)
+    uint2 *tie;
+    uint32_t tie_cap;
+    // verdicts of the band candidates: sorted keys (i << 32 | j)
     const unsigned long long *ver_key;
     const uint8_t *ver_in;
     uint32_t n_ver;
     // write pass
-    const int64_t *off;    // [nA + 1] in idxA order
-    int32_t *out_a, *out_b;
-    double *out_sep;
-    int32_t write_pairs;
-    int32_t *best_idx;     // [nA] idxA order
-    double *best_sep;
-    uint32_t *tie_n;       // best near-tie list
-    uint2 *tie;            // (sorted A pos, 0)
-    uint32_t tie_cap;
-    // collect pass (tie resolution): sorted A positions and separation limits
+    const int64_t *off;    // [nA + 1] idxA order
+    int32_t *out_a;        // final idxA of each pair
+    uint2 *tmp;            // (idxB, sorted B pos) in enumeration order
+    // collect pass: sorted A positions; every match of each is listed
     const uint32_t *col_pos;
-    const double *col_lim;
     uint32_t n_col;
     uint32_t *col_n;
-    uint4 *col;            // (col entry, idxB, sep hi, sep lo)
+    void *col;
     uint32_t col_cap;
     // counters
     unsigned long long *n_tests;
     unsigned long long *n_band;
-    uint32_t *err_flag;    // bit 0: write overflow, bit 1: count mismatch
+    uint32_t *err_flag;    // 1: write overflow, 2: count mismatch, 4: missing verdict
 };
 
 // ----------------------------------------------------------------------------
@@ -139,28 +147,35 @@ __device__ __forceinline__ int zone_of(double dec, const Grid &g)
     return (int)t;
 }
 
-__device__ __forceinline__ uint32_t cell_of(int z, double ra, const Grid &g)
+__device__ __forceinline__ uint32_t cell_in(const ZoneInfo &zi, double ra)
 {
-    double t = floor(ra * g.zf[z]);
-    uint32_t n = g.zn[z];
+    double t = floor(ra * zi.f);
     if (!(t >= 0.0)) return 0;
-    if (t >= (double)n) return n - 1;
+    if (t >= (double)zi.n) return zi.n - 1;
     return (uint32_t)t;
 }
 
-// Reference vector of cell (z, c): zone reference Dec and the RA grid point
-// nearest the cell centre, both from tables, so every kernel gets identical
-// bits (products only, no additions to contract).
+__device__ __forceinline__ uint32_t cell_of(int z, double ra, const Grid &g)
+{
+    return cell_in(g.zinfo[z], ra);
+}
+
+// Reference vector of cell (z, c): the zone's reference Dec (table) and the
+// point of a 2^16-step RA grid nearest the cell centre (integer arithmetic,
+// then an FP32 sincospi of the exact dyadic angle). It is only a fixed point
+// near the cell shared by every kernel: its accuracy does not matter, only
+// that all kernels get the same bits and that |p - ref| stays below L.
 __device__ __forceinline__ void cell_ref(int z, uint32_t c, const Grid &g, double &rx,
                                          double &ry, double &rz)
 {
-    uint64_t n = g.zn[z];
+    uint64_t n = g.zinfo[z].n;
     uint64_t gidx = (((uint64_t)(2 * c + 1) << kRefBits) + n) / (2 * n);
     gidx &= (1u << kRefBits) - 1;
     double2 zr = g.zref[z];
-    double2 ar = g.rref[gidx];
-    rx = zr.x * ar.x;
-    ry = zr.x * ar.y;
+    float sa, ca;
+    sincospif((float)gidx * (1.0f / (float)(1 << (kRefBits - 1))), &sa, &ca);
+    rx = zr.x * (double)ca;
+    ry = zr.x * (double)sa;
     rz = zr.y;
 }
 
@@ -210,15 +225,39 @@ __device__ __forceinline__ void tangent_ne(double ra1, double dec1, double sd1, 
     te = cd2 * sin(kDeg * da);
 }
 
-// Separation in arcsec, accurate to a few ulps at every angle.
-__device__ __forceinline__ double sep_arcsec(const ARec &a, double ra2, double dec2)
+// Separation in arcsec between two positions given in degrees, accurate to
+// a few ulps at every angle.
+__device__ __forceinline__ double sep_arcsec_rd(double ra1, double dec1, double ra2, double dec2)
 {
-    double cd2 = cos_dec_acc(dec2);
+    double cd1 = cos_dec_acc(dec1), cd2 = cos_dec_acc(dec2);
+    double sd1 = sin(kDeg * dec1);
     double tn, te;
-    tangent_ne(a.ra, a.dec, a.z, ra2, dec2, cd2, tn, te);
-    double h = haversine(a.ra, a.dec, a.cosd, ra2, dec2, cd2);
+    tangent_ne(ra1, dec1, sd1, ra2, dec2, cd2, tn, te);
+    double h = haversine(ra1, dec1, cd1, ra2, dec2, cd2);
     double th = atan2(sqrt(tn * tn + te * te), 1.0 - 2.0 * h);
     return th * (180.0 / kPi * 3600.0);
+}
+
+// ---------------------------------------------------------------------------- wavefront helpers
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+// Orders the LDS writes of a wavefront before its later LDS reads.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // FP64 relative-accuracy recheck of the circle (error <= ~90 u against a
@@ -260,6 +299,24 @@ __device__ __forceinline__ bool same_point(const ARec &a, double2 rb)
     return a.dec == rb.y && (a.ra == rb.x || fabs(a.dec) == 90.0);
 }
 
+// Bound of a staged key range: a start (end = false) or an exclusive end
+// (end = true) at most as tight as lower_bound(k). When k's directory bucket
+// holds at most 8 keys the bucket's own bound is returned (no search); the
+// lanes find their exact cells inside the staged range anyway.
+__device__ __forceinline__ uint32_t key_bound(const Grid &g, uint32_t k, bool end)
+{
+    uint32_t q = k >> g.dshift;
+    if (q + 1 >= g.dsize) return (uint32_t)g.nB;
+    uint32_t lo = g.dir[q], hi = min(g.dir[q + 1], (uint32_t)g.nB);
+    if (hi - lo <= 8u || lo >= hi) return end ? hi : lo;
+    while (lo < hi) {
+        uint32_t m = lo + ((hi - lo) >> 1);
+        if (g.keys[m] < k) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
 // First sorted position whose key is >= k (keys ascending).
 __device__ __forceinline__ uint32_t key_lower_bound(const Grid &g, uint32_t k)
 {
@@ -274,68 +331,89 @@ __device__ __forceinline__ uint32_t key_lower_bound(const Grid &g, uint32_t k)
     return lo;
 }
 
-// Calls f(zone, j0, j1) for every contiguous range of sorted B positions whose
-// cells can hold a source within reach_deg of (ra, dec). Exact superset:
-// zones cover [dec - R, dec + R] and each zone the RA interval
-// [ra - dRA, ra + dRA], dRA = asin(sin R / cos dec) (the widest RA extent of
-// a cap), split at RA = 0/360; a cap holding a pole, or a window of 180 deg
-// or more, takes the whole zone. The pads absorb every rounding of the
-// window arithmetic, and zone_of / cell_of are monotone.
+// Window of one source: the zones within reach in Dec and, unless the
+// whole zone is needed (a cap holding a pole, or an RA half-width of 180 deg
+// or more), the RA half-width dRA = asin(sin R / cos dec), the widest RA
+// extent of a cap. The pads absorb every rounding of this arithmetic, and
+// zone_of / cell_of are monotone, so the cells found are an exact superset.
+struct Window {
+    int zlo, zhi;
+    bool full;
+    double dra;
+};
+
+__device__ __forceinline__ Window window_of(const Grid &g, double dec, double cosd,
+                                            double reach_deg)
+{
+    Window w;
+    double rp = reach_deg * (1.0 + 1e-9) + 1e-12;
+    w.zlo = zone_of(dec - rp, g);
+    w.zhi = zone_of(dec + rp, g);
+    w.full = false;
+    w.dra = 0.0;
+    if (fabs(dec) + rp >= 90.0) {
+        w.full = true;
+    } else {
+        double x = sin(kDeg * rp) / cosd;
+        if (x >= 0.9999) {
+            w.full = true;
+        } else {
+            w.dra = asin(x) / kDeg * (1.0 + 1e-9) + 1e-12;
+            if (w.dra >= 180.0) w.full = true;
+        }
+    }
+    return w;
+}
+
+// Cell ranges [c0[k], c1[k]] of zone z covering [ra - dRA, ra + dRA], split
+// at RA = 0/360 (at most two, disjoint). Returns how many.
+__device__ __forceinline__ int zone_ranges(const ZoneInfo &zi, const Window &w, double ra,
+                                           uint32_t c0[2], uint32_t c1[2])
+{
+    const uint32_t n = zi.n;
+    if (!w.full) {
+        double lo = ra - w.dra, hi = ra + w.dra;
+        if (lo < 0.0) {
+            uint32_t a0 = cell_in(zi, lo + 360.0), b1 = cell_in(zi, hi);
+            if (a0 > b1) {
+                c0[0] = 0;
+                c1[0] = b1;
+                c0[1] = a0;
+                c1[1] = n - 1;
+                return 2;
+            }
+        } else if (hi >= 360.0) {
+            uint32_t a0 = cell_in(zi, lo), b1 = cell_in(zi, hi - 360.0);
+            if (a0 > b1) {
+                c0[0] = 0;
+                c1[0] = b1;
+                c0[1] = a0;
+                c1[1] = n - 1;
+                return 2;
+            }
+        } else {
+            c0[0] = cell_in(zi, lo);
+            c1[0] = cell_in(zi, hi);
+            return 1;
+        }
+    }
+    c0[0] = 0;
+    c1[0] = n - 1;
+    return 1;
+}
+
+// Calls f(zone, j0, j1) for every contiguous range of sorted B positions
+// whose cells can hold a source within reach_deg of (ra, dec).
 template <typename F>
 __device__ __forceinline__ void for_each_range(const Grid &g, double ra, double dec, double cosd,
                                                double reach_deg, F &&f)
 {
-    double rp = reach_deg * (1.0 + 1e-9) + 1e-12;
-    int zlo = zone_of(dec - rp, g);
-    int zhi = zone_of(dec + rp, g);
-    bool full = false;
-    double dra = 0.0;
-    if (fabs(dec) + rp >= 90.0) {
-        full = true;
-    } else {
-        double x = sin(kDeg * rp) / cosd;
-        if (x >= 0.9999) {
-            full = true;
-        } else {
-            dra = asin(x) / kDeg * (1.0 + 1e-9) + 1e-12;
-            if (dra >= 180.0) full = true;
-        }
-    }
-    for (int z = zlo; z <= zhi; ++z) {
-        uint32_t base = g.zbase[z];
-        uint32_t n = g.zn[z];
+    Window w = window_of(g, dec, cosd, reach_deg);
+    for (int z = w.zlo; z <= w.zhi; ++z) {
+        const ZoneInfo zi = g.zinfo[z];
+        const uint32_t base = zi.base;
         uint32_t c0[2], c1[2];
-        int nr = 0;
-        bool zfull = full;
-        if (!zfull) {
-            double lo = ra - dra, hi = ra + dra;
-            if (lo < 0.0) {
-                uint32_t a0 = cell_of(z, lo + 360.0, g), b1 = cell_of(z, hi, g);
-                if (a0 <= b1) zfull = true;
-                else {
-                    c0[0] = 0; c1[0] = b1;
-                    c0[1] = a0; c1[1] = n - 1;
-                    nr = 2;
-                }
-            } else if (hi >= 360.0) {
-                uint32_t a0 = cell_of(z, lo, g), b1 = cell_of(z, hi - 360.0, g);
-                if (a0 <= b1) zfull = true;
-                else {
-                    c0[0] = 0; c1[0] = b1;
-                    c0[1] = a0; c1[1] = n - 1;
-                    nr = 2;
-                }
-            } else {
-                c0[0] = cell_of(z, lo, g);
-                c1[0] = cell_of(z, hi, g);
-                nr = 1;
-            }
-        }
-        if (zfull) {
-            c0[0] = 0;
-            c1[0] = n - 1;
-            nr = 1;
-        }
+        int nr = zone_ranges(zi, w, ra, c0, c1);
         for (int k = 0; k < nr; ++k) {
             uint32_t j0 = key_lower_bound(g, base + c0[k]);
             uint32_t j1 = key_lower_bound(g, base + c1[k] + 1);

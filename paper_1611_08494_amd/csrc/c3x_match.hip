@@ -1,26 +1,37 @@
 // c3x_match.hip -- cross-match of catalogue A against a sky index.
 //
 // Paper Section 2.1 ("Sky" case): a region is centred on each A source and
-// the B sources inside it are found "by comparing their distance from the
-// central object and the limits of the area"; Section 2.2: the matches are
+// the B sources inside it are found by comparing their distance from the
+// central object with the limits of the area; Section 2.2: the matches are
 // kept as rows, all of them or only the best; Section 2.3: each source is
 // tested only against the cells around it. Phases on one stream:
-//   A prep      validate, key, sort A by cell, sorted A records
-//   count       per A: enumerate cells in reach, decide every candidate
-//               (fast filter -> FP64 haversine recheck -> ambiguous list)
-//   [host]      ambiguous pairs decided in binary128, verdict table uploaded
-//   scan        per-A counts -> int64 offsets in idxA order
-//   write       same enumeration and decisions; writes (idxA, idxB, sep) and
-//               the best match (min separation, lower idxB on equal values);
-//               near-tie best matches are listed for the host
-//   order       each A's segment sorted by idxB (canonical order)
-// The decisions of the count and write passes come from the same device
+//   A prep     validate, key, sort A by cell (LDS radix sort), sorted
+//              coordinates (+ ellipse frames)
+//   count      wavefront tiles of 64 consecutive sorted A sources: per zone,
+//              the union of the lanes' cell windows is one key range of B,
+//              found with two directory lookups and staged through LDS; each
+//              lane binary-searches its own cells in LDS and decides its
+//              candidates with the certified filter; candidates inside the
+//              filter's error band are listed. Counts and the best match go
+//              to idxA order.
+//   recheck    one thread per listed candidate: FP64 relative-accuracy form;
+//              what it cannot certify is decided on the host in binary128
+//   [host]     verdict table; near-tie best matches re-ranked in binary128
+//              from a collect pass
+//   scan       counts -> int64 offsets (idxA order)
+//   write      same tiles and decisions; each lane writes (idxB, B position)
+//              into its own idxA segment
+//   finalize   one thread per pair: rank inside its segment by idxB
+//              (canonical order), separation in FP64, final write
+//   best       one thread per A: separation of the best match
+// Decisions of the count, write and collect passes come from one device
 // function compiled with -ffp-contract=off, so they agree bit for bit.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "c3x_host.h"
@@ -29,20 +40,23 @@
 namespace c3x {
 
 constexpr int kMatchBlock = 256;
-constexpr double kTieRel = kE40;  // best matches closer than this (relative) go to the host
+constexpr int kWavesPerBlock = kMatchBlock / 64;
+constexpr int kRankMax = 64;    // segments up to this long are ordered by the finalize kernel
+constexpr int kSegLds = 2048;   // segments up to this long are sorted in LDS
+constexpr int kTileZones = 5;   // zones a cooperative tile may span; wider tiles go per lane
+static_assert(6 * kTileZones <= 64, "one lane per hull end");
 
 struct alignas(16) ColEnt {
     uint32_t t, idxB, j, pad;
-    double sep, ra, dec;
+    double ra, dec;
 };
 struct AmbInfo {
     double raA, decA, raB, decB, a, b, pa;
     uint32_t i, j, idxA, idxB;
 };
-struct alignas(16) TieEnt {
-    uint32_t i, idxA;
-    double s1;
-};
+
+template <int PREC>
+using PayOf = typename std::conditional<PREC == C3X_FP64, Pay64, Pay32>::type;
 
 // ---------------------------------------------------------------------------- A preparation
 
@@ -67,7 +81,8 @@ __global__ void k_prep_a(const double *__restrict__ ra, const double *__restrict
         d = 0.0;
     }
     int z = zone_of(d, g);
-    keys[i] = g.zbase[z] + cell_of(z, a, g);
+    const ZoneInfo zi = g.zinfo[z];
+    keys[i] = zi.base + cell_in(zi, a);
     rows[i] = (uint32_t)i;
 }
 
@@ -87,37 +102,49 @@ __device__ __forceinline__ double ell_margin(double ar, double br, double kappa,
     return m > 0.25 ? 1e30 : m;
 }
 
+// Invalid rows (already reported through k_prep_a's flag) are given the
+// position (0, 0) and, for ellipses, a 1" circle, so every later loop stays
+// bounded even before the host sees the error.
 template <int SHAPE>
 __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double *__restrict__ ra,
-                           const double *__restrict__ dec, int64_t n, double radius_arcsec,
+                           const double *__restrict__ dec, int64_t n,
                            const double *__restrict__ sa, const double *__restrict__ sb,
                            const double *__restrict__ pa, double pa_zero, int pa_sense,
-                           double L_rad, ARec *__restrict__ arec, AEll *__restrict__ aell,
-                           AEllR *__restrict__ aellr)
+                           double L_rad, double2 *__restrict__ arad, uint32_t *__restrict__ aidx,
+                           AEll *__restrict__ aell, AEllR *__restrict__ aellr)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t row = rows[i];
     if (row >= (uint64_t)n) row = 0;  // unreachable for a permutation; keeps reads in bounds
-    ARec r;
-    r.ra = ra[row];
-    r.dec = dec[row];
-    unit_vec(r.ra, r.dec, r.x, r.y, r.z);
-    r.cosd = cos_dec_acc(r.dec);
-    r.idx = row;
-    double reach_as = SHAPE == C3X_ELLIPSE ? sa[row] : radius_arcsec;
-    r.reach_deg = reach_as / 3600.0;
-    arec[i] = r;
+    double r = ra[row], d = dec[row];
+    bool ok = isfinite(r) && isfinite(d) && r >= 0.0 && r < 360.0 && fabs(d) <= 90.0;
+    double A = 1.0, B = 1.0, P = 0.0;
     if (SHAPE == C3X_ELLIPSE) {
-        double A = sa[row], B = sb[row];
-        double T = pa_zero + (double)pa_sense * pa[row];
+        A = sa[row];
+        B = sb[row];
+        P = pa[row];
+        ok = ok && isfinite(A) && isfinite(B) && isfinite(P) && B >= 1e-6 && B <= A &&
+             A <= 324000.0 && A <= 1000.0 * B;
+    }
+    if (!ok) {
+        r = 0.0;
+        d = 0.0;
+        A = 1.0;
+        B = 1.0;
+        P = 0.0;
+    }
+    arad[i] = make_double2(r, d);
+    aidx[i] = row;
+    if (SHAPE == C3X_ELLIPSE) {
+        double T = pa_zero + (double)pa_sense * P;
         double st, ct;
         sincos(T * kDeg, &st, &ct);
-        double sdd = r.z;           // sin dec
-        double sra, cra;
-        sincos(r.ra * kDeg, &sra, &cra);
+        double sdd, cdd, sra, cra;
+        sincos(d * kDeg, &sdd, &cdd);
+        sincos(r * kDeg, &sra, &cra);
         // local north and east at A
-        double nx = -sdd * cra, ny = -sdd * sra, nz = r.cosd;
+        double nx = -sdd * cra, ny = -sdd * sra, nz = cos_dec_acc(d);
         double ex = -sra, ey = cra;
         AEll e;
         e.ux = nx * ct + ex * st;
@@ -150,7 +177,84 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double *__re
     }
 }
 
-// ---------------------------------------------------------------------------- match
+// ---------------------------------------------------------------------------- decisions
+
+__device__ __forceinline__ ARec load_a(const MatchArgs &m, uint32_t i, double reach_deg)
+{
+    ARec a;
+    double2 rd = m.arad[i];
+    a.ra = rd.x;
+    a.dec = rd.y;
+    unit_vec(a.ra, a.dec, a.x, a.y, a.z);
+    a.cosd = cos_dec_acc(a.dec);
+    a.reach_deg = reach_deg;
+    a.idx = m.aidx[i];
+    a.pad = 0;
+    return a;
+}
+
+struct LaneF32 {            // FP32 copies of the ellipse frame
+    float ux, uy, uz, vx, vy, vz, ia, ib;
+};
+
+struct CellCache {          // A's offset from the reference of the current B cell
+    uint32_t key;
+    float ax, ay, az;
+};
+
+// Fast certified filter of one candidate: IN, OUT, or AMBIG when the pair
+// lies inside the filter's error band (then the FP64 relative-accuracy
+// recheck decides it, in k_recheck). Also returns the filter's squared chord.
+// Radius 0 is decided structurally here (same point), without a band.
+template <int SHAPE, int PREC>
+__device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const AEll &e,
+                                      const AEllR &er, const LaneF32 &f, CellCache &cc, int z,
+                                      uint32_t key, const PayOf<PREC> &b, uint32_t j, double &c2o)
+{
+    int d;
+    if constexpr (PREC == C3X_FP64) {
+        double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+        double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        c2o = c2;
+        if constexpr (SHAPE == C3X_CIRCLE) {
+            d = c2 <= m.t64_in ? IN : (c2 > m.t64_out ? OUT : AMBIG);
+        } else {
+            double su = fma(dx, e.ux, fma(dy, e.uy, dz * e.uz));
+            double sv = fma(dx, e.vx, fma(dy, e.vy, dz * e.vz));
+            double xu = su * e.ia, xv = sv * e.ib;
+            double q = fma(xu, xu, xv * xv);
+            double qf = q * fma(c2, 1.0 / 3.0, 1.0);
+            d = qf <= 1.0 - er.m64 ? IN : (qf > 1.0 + er.m64 ? OUT : AMBIG);
+        }
+    } else {
+        if (key != cc.key) {
+            cc.key = key;
+            double rx, ry, rz;
+            cell_ref(z, key - m.g.zinfo[z].base, m.g, rx, ry, rz);
+            cc.ax = (float)(a.x - rx);
+            cc.ay = (float)(a.y - ry);
+            cc.az = (float)(a.z - rz);
+        }
+        float dx = b.x - cc.ax, dy = b.y - cc.ay, dz = b.z - cc.az;
+        float c2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        c2o = (double)c2;
+        if constexpr (SHAPE == C3X_CIRCLE) {
+            d = c2 <= m.t32_in ? IN : (c2 > m.t32_out ? OUT : AMBIG);
+        } else {
+            float su = fmaf(dx, f.ux, fmaf(dy, f.uy, dz * f.uz));
+            float sv = fmaf(dx, f.vx, fmaf(dy, f.vy, dz * f.vz));
+            float xu = su * f.ia, xv = sv * f.ib;
+            float q = fmaf(xu, xu, xv * xv);
+            float qf = q * fmaf(c2, 1.0f / 3.0f, 1.0f);
+            float mm = er.m32;
+            d = mm == 0.0f ? AMBIG : (qf <= 1.0f - mm ? IN : (qf > 1.0f + mm ? OUT : AMBIG));
+        }
+    }
+    if constexpr (SHAPE == C3X_CIRCLE) {
+        if (m.r_zero) d = same_point(a, m.radecB[j]) ? IN : OUT;
+    }
+    return d;
+}
 
 __device__ __forceinline__ int verdict(const MatchArgs &m, uint32_t i, uint32_t j)
 {
@@ -166,168 +270,284 @@ __device__ __forceinline__ int verdict(const MatchArgs &m, uint32_t i, uint32_t 
     return OUT;
 }
 
-// MODE 0: count, 1: write, 2: collect near-best candidates.
+// Error bound of the filter's squared chord at chord c (see circle_thresholds).
+template <int PREC>
+__device__ __forceinline__ double c2_err(double c, double L)
+{
+    const double s3 = 1.7320508075688772;
+    if constexpr (PREC == C3X_FP64) {
+        double eta = s3 * (64.0 * kU + kU * c);
+        return 2.0 * c * eta + eta * eta + 3.0 * kU * (c + eta) * (c + eta);
+    } else {
+        const double e32 = kU32 * 1.0001;
+        double eta = s3 * e32 * (2.0 * L + 2.0 * c) + 2.0 * s3 * 32.0 * kU;
+        return 2.0 * c * eta + eta * eta + 3.0 * e32 * (c + eta) * (c + eta);
+    }
+}
+
+__device__ __forceinline__ uint32_t lds_lower_bound(const uint32_t *k, uint32_t n, uint32_t v)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (k[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------- count / write
+
+// MODE 0: count + best; MODE 1: write.
 template <int SHAPE, int PREC, int MODE>
 __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 {
+    using PayT = PayOf<PREC>;
+    constexpr int kStage = PREC == C3X_FP64 ? 192 : 256;  // B staged per wavefront
+    __shared__ uint32_t s_key[kWavesPerBlock][kStage];
+    __shared__ PayT s_pay[kWavesPerBlock][kStage];
     __shared__ unsigned long long s_tests, s_band;
     if (threadIdx.x == 0) {
         s_tests = 0;
         s_band = 0;
     }
     __syncthreads();
-    uint32_t t = blockIdx.x * kMatchBlock + threadIdx.x;
-    uint32_t nwork = MODE == 2 ? m.n_col : (uint32_t)m.nA;
-    unsigned long long tests = 0, band = 0;
-    if (t < nwork) {
-        uint32_t i = MODE == 2 ? m.col_pos[t] : t;
-        const ARec a = m.arec[i];
-        AEll e{};
-        AEllR er{};
-        if (SHAPE == C3X_ELLIPSE) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const PayT *pay;
+    if constexpr (PREC == C3X_FP64) pay = m.pay64;
+    else pay = m.pay32;
+    uint32_t *sk = s_key[wave];
+    PayT *sp = s_pay[wave];
+
+    const uint32_t i = blockIdx.x * kMatchBlock + threadIdx.x;
+    const bool active = i < (uint32_t)m.nA;
+    ARec a{};
+    AEll e{};
+    AEllR er{};
+    LaneF32 f{};
+    Window w{0, -1, false, 0.0};
+    if (active) {
+        double reach = m.reach_deg;
+        if constexpr (SHAPE == C3X_ELLIPSE) {
             e = m.aell[i];
             er = m.aellr[i];
+            reach = er.a_arcsec / 3600.0;
+            f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
+                        (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
         }
-        float ux = (float)e.ux, uy = (float)e.uy, uz = (float)e.uz;
-        float vx = (float)e.vx, vy = (float)e.vy, vz = (float)e.vz;
-        float ia32 = (float)e.ia, ib32 = (float)e.ib;
-        double lim = MODE == 2 ? m.col_lim[t] : 0.0;
-        uint32_t cnt = 0;
-        int64_t o = 0, oe = 0;
-        if (MODE == 1) {
-            o = m.off[a.idx];
-            oe = m.off[a.idx + 1];
+        a = load_a(m, i, reach);
+        w = window_of(m.g, a.dec, a.cosd, a.reach_deg);
+    }
+    uint32_t zlo_all = wave_min_u32(active ? (uint32_t)w.zlo : 0xffffffffu);
+    uint32_t zhi_all = wave_max_u32(active ? (uint32_t)w.zhi : 0u);
+
+    uint32_t cnt = 0;
+    double b1 = INFINITY, b2 = INFINITY;
+    uint32_t bidx = 0xffffffffu, bj = 0;
+    int64_t o = 0, oe = 0;
+    if (MODE == 1 && active) {
+        o = m.off[a.idx];
+        oe = m.off[a.idx + 1];
+    }
+    unsigned long long tests = 0, band = 0;
+    CellCache cc{0xffffffffu, 0.f, 0.f, 0.f};
+
+    // One candidate: decide it, then count / rank it (MODE 0) or write it.
+    auto visit = [&](int z, uint32_t key, const PayT &b, uint32_t j) {
+        ++tests;
+        double c2;
+        int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, key, b, j, c2);
+        if (d == AMBIG) {
+            if (MODE == 0) {
+                ++band;
+                uint32_t slot = atomicAdd(m.amb_n, 1u);
+                if (slot < m.amb_cap) m.amb[slot] = make_uint2(i, j);
+                d = OUT;
+            } else {
+                d = verdict(m, i, j);
+            }
         }
-        double s1 = INFINITY, s2 = INFINITY;
-        int32_t bidx = -1;
-        for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
-            uint32_t curkey = 0xffffffffu;
-            float ax = 0.f, ay = 0.f, az = 0.f;
-            for (uint32_t j = j0; j < j1; ++j) {
-                ++tests;
-                int d;
-                uint32_t idxB;
-                if (PREC == C3X_FP64) {
-                    const Pay64 b = m.pay64[j];
-                    idxB = b.idx;
-                    double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                    double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    if (SHAPE == C3X_CIRCLE) {
-                        d = c2 <= m.t64_in ? IN : (c2 > m.t64_out ? OUT : AMBIG);
-                    } else {
-                        double su = fma(dx, e.ux, fma(dy, e.uy, dz * e.uz));
-                        double sv = fma(dx, e.vx, fma(dy, e.vy, dz * e.vz));
-                        double xu = su * e.ia, xv = sv * e.ib;
-                        double q = fma(xu, xu, xv * xv);
-                        double qf = q * fma(c2, 1.0 / 3.0, 1.0);
-                        d = qf <= 1.0 - er.m64 ? IN : (qf > 1.0 + er.m64 ? OUT : AMBIG);
-                    }
-                } else {
-                    uint32_t key = m.g.keys[j];
-                    if (key != curkey) {
-                        curkey = key;
-                        double rx, ry, rz;
-                        cell_ref(z, key - m.g.zbase[z], m.g, rx, ry, rz);
-                        ax = (float)(a.x - rx);
-                        ay = (float)(a.y - ry);
-                        az = (float)(a.z - rz);
-                    }
-                    const Pay32 b = m.pay32[j];
-                    idxB = b.idx;
-                    float dx = b.x - ax, dy = b.y - ay, dz = b.z - az;
-                    float c2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    if (SHAPE == C3X_CIRCLE) {
-                        d = c2 <= m.t32_in ? IN : (c2 > m.t32_out ? OUT : AMBIG);
-                    } else {
-                        float su = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
-                        float sv = fmaf(dx, vx, fmaf(dy, vy, dz * vz));
-                        float xu = su * ia32, xv = sv * ib32;
-                        float q = fmaf(xu, xu, xv * xv);
-                        float qf = q * fmaf(c2, 1.0f / 3.0f, 1.0f);
-                        float mm = er.m32;
-                        d = mm == 0.0f ? AMBIG
-                                       : (qf <= 1.0f - mm ? IN : (qf > 1.0f + mm ? OUT : AMBIG));
-                    }
+        if (d != IN) return;
+        if (MODE == 0) {
+            ++cnt;
+            if (c2 < b1 || (c2 == b1 && b.idx < bidx)) {
+                b2 = b1;
+                b1 = c2;
+                bidx = b.idx;
+                bj = j;
+            } else if (c2 < b2) {
+                b2 = c2;
+            }
+        } else {
+            int64_t p = o + cnt;
+            if (p < oe) {
+                m.out_a[p] = (int32_t)a.idx;
+                m.tmp[p] = make_uint2(b.idx, j);
+            } else {
+                atomicOr(m.err_flag, 1u);
+            }
+            ++cnt;
+        }
+    };
+
+    if (zhi_all >= zlo_all && zhi_all - zlo_all >= (uint32_t)kTileZones) {
+        // A tile spread over many zones (sparse sky near the poles): each
+        // lane walks its own few zones with direct loads.
+        if (active)
+            for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
+                cc.key = 0xffffffffu;
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const PayT b = pay[j];
+                    visit(z, m.g.keys[j], b, j);
                 }
-                double2 rb;
-                bool have_rb = false;
-                if (d == AMBIG) {
-                    ++band;
-                    rb = m.radecB[j];
-                    have_rb = true;
-                    if (SHAPE == C3X_CIRCLE)
-                        d = m.r_zero ? (same_point(a, rb) ? IN : OUT) : recheck_circle(a, rb, m.h_r);
-                    else
-                        d = recheck_ellipse(a, er, rb);
-                    if (d == AMBIG) {
-                        if (MODE == 0) {
-                            uint32_t slot = atomicAdd(m.amb_n, 1u);
-                            if (slot < m.amb_cap) m.amb[slot] = make_uint2(i, j);
-                            d = OUT;
-                        } else {
-                            d = verdict(m, i, j);
-                        }
-                    }
+            });
+    } else if (zhi_all >= zlo_all) {
+        // Cooperative tile. In each of the tile's zones the lanes' cell
+        // windows are gathered into up to three hulls -- plain windows, the
+        // [0, b] pieces and the [a, n-1] pieces of windows split at RA 0/360
+        // (so a tile near RA 0 does not stage its whole zone) -- each one key
+        // range of B. All range ends are looked up at once (lane 6q+2h and
+        // 6q+2h+1 for hull h of zone q), every range is staged in LDS behind
+        // one wave barrier, and each lane binary-searches its own cells in
+        // the segment of the matching hull. Lane windows are recomputed per
+        // zone rather than kept in registers.
+        const uint32_t zb = (uint32_t)__builtin_amdgcn_readfirstlane((int)zlo_all);
+        const int nzt = __builtin_amdgcn_readfirstlane((int)(zhi_all - zlo_all)) + 1;
+        uint32_t lkey = 0;
+        bool lvalid = false, lend = false;
+        for (int q = 0; q < nzt; ++q) {
+            const int z = (int)zb + q;
+            const ZoneInfo zi = m.g.zinfo[z];
+            uint32_t c0[2], c1[2];
+            int nr = 0;
+            if (active && z >= w.zlo && z <= w.zhi) nr = zone_ranges(zi, w, a.ra, c0, c1);
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+                uint32_t lo = 0xffffffffu, hi = 0;
+                if (h == 0 && nr == 1) {
+                    lo = c0[0];
+                    hi = c1[0];
+                } else if (h > 0 && nr == 2) {
+                    lo = c0[h - 1];
+                    hi = c1[h - 1];
                 }
-                if (d != IN) continue;
-                if (MODE == 0) {
-                    ++cnt;
-                    continue;
-                }
-                if (!have_rb) rb = m.radecB[j];
-                double sp = sep_arcsec(a, rb.x, rb.y);
-                if (MODE == 2) {
-                    if (sp <= lim) {
-                        uint32_t slot = atomicAdd(m.col_n, 1u);
-                        if (slot < m.col_cap) {
-                            ColEnt c;
-                            c.t = t;
-                            c.idxB = idxB;
-                            c.j = j;
-                            c.pad = 0;
-                            c.sep = sp;
-                            c.ra = rb.x;
-                            c.dec = rb.y;
-                            ((ColEnt *)m.col)[slot] = c;
-                        }
-                    }
-                    continue;
-                }
-                if (m.write_pairs) {
-                    int64_t p = o + cnt;
-                    if (p < oe) {
-                        m.out_a[p] = (int32_t)a.idx;
-                        m.out_b[p] = (int32_t)idxB;
-                        m.out_sep[p] = sp;
-                    } else {
-                        atomicOr(m.err_flag, 1u);
-                    }
-                }
-                ++cnt;
-                if (sp < s1 || (sp == s1 && (int32_t)idxB < bidx)) {
-                    s2 = s1;
-                    s1 = sp;
-                    bidx = (int32_t)idxB;
-                } else if (sp < s2) {
-                    s2 = sp;
+                lo = wave_min_u32(lo);
+                hi = wave_max_u32(hi);
+                if (lane >> 1 == 3 * q + h && lo <= hi) {
+                    lvalid = true;
+                    lend = lane & 1;
+                    lkey = lend ? zi.base + hi + 1 : zi.base + lo;
                 }
             }
-        });
-        if (MODE == 0) m.cnt[a.idx] = cnt;
-        if (MODE == 1) {
-            if (m.write_pairs && o + cnt != oe) atomicOr(m.err_flag, 2u);
-            m.best_idx[a.idx] = cnt ? bidx : -1;
-            m.best_sep[a.idx] = cnt ? s1 : NAN;
-            if (cnt >= 2 && s2 <= s1 * (1.0 + kTieRel) + 1e-300) {
+        }
+        const uint32_t lres = lvalid ? key_bound(m.g, lkey, lend) : 0u;
+        // ends of hull h of zone q (wave-uniform)
+        auto ends = [&](int q, int h, uint32_t &j0, uint32_t &j1) {
+            j0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)lres, 2 * (3 * q + h)));
+            j1 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)lres, 2 * (3 * q + h) + 1));
+            if (j1 < j0) j1 = j0;
+        };
+        uint32_t T = 0;
+        for (int q = 0; q < nzt; ++q)
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+                uint32_t j0, j1;
+                ends(q, h, j0, j1);
+                T += j1 - j0;
+            }
+        if (T <= (uint32_t)kStage) {
+            uint32_t seg = 0;
+            for (int q = 0; q < nzt; ++q)
+#pragma unroll
+                for (int h = 0; h < 3; ++h) {
+                    uint32_t j0, j1;
+                    ends(q, h, j0, j1);
+                    for (uint32_t s = lane; s < j1 - j0; s += 64) {
+                        sk[seg + s] = m.g.keys[j0 + s];
+                        sp[seg + s] = pay[j0 + s];
+                    }
+                    seg += j1 - j0;
+                }
+            wave_sync();
+            seg = 0;
+            for (int q = 0; q < nzt; ++q) {
+                const int z = (int)zb + q;
+                const ZoneInfo zi = m.g.zinfo[z];
+                uint32_t c0[2], c1[2];
+                int nr = 0;
+                if (active && z >= w.zlo && z <= w.zhi) nr = zone_ranges(zi, w, a.ra, c0, c1);
+                cc.key = 0xffffffffu;
+#pragma unroll
+                for (int h = 0; h < 3; ++h) {
+                    uint32_t j0, j1;
+                    ends(q, h, j0, j1);
+                    const uint32_t segn = j1 - j0;
+                    int k = -1;
+                    if (h == 0 && nr == 1) k = 0;
+                    else if (h > 0 && nr == 2) k = h - 1;
+                    if (segn > 0 && k >= 0) {
+                        const uint32_t ka = k ? c0[1] : c0[0], kb = k ? c1[1] : c1[0];
+                        uint32_t s0 = seg + lds_lower_bound(sk + seg, segn, zi.base + ka);
+                        uint32_t s1 = seg + lds_lower_bound(sk + seg, segn, zi.base + kb + 1);
+                        for (uint32_t s = s0; s < s1; ++s) {
+                            const PayT b = sp[s];
+                            visit(z, sk[s], b, j0 + (s - seg));
+                        }
+                    }
+                    seg += segn;
+                }
+            }
+        } else {
+            // more than fits in LDS at once: hull by hull, in chunks
+            for (int q = 0; q < nzt; ++q) {
+                const int z = (int)zb + q;
+                const ZoneInfo zi = m.g.zinfo[z];
+                uint32_t c0[2], c1[2];
+                int nr = 0;
+                if (active && z >= w.zlo && z <= w.zhi) nr = zone_ranges(zi, w, a.ra, c0, c1);
+#pragma unroll
+                for (int h = 0; h < 3; ++h) {
+                    uint32_t j0, j1;
+                    ends(q, h, j0, j1);
+                    int k = -1;
+                    if (h == 0 && nr == 1) k = 0;
+                    else if (h > 0 && nr == 2) k = h - 1;
+                    const uint32_t ka = k == 1 ? c0[1] : c0[0], kb = k == 1 ? c1[1] : c1[0];
+                    cc.key = 0xffffffffu;
+                    for (uint32_t c = j0; c < j1; c += kStage) {
+                        const uint32_t nst = min((uint32_t)kStage, j1 - c);
+                        wave_sync();
+                        for (uint32_t s = lane; s < nst; s += 64) {
+                            sk[s] = m.g.keys[c + s];
+                            sp[s] = pay[c + s];
+                        }
+                        wave_sync();
+                        if (k >= 0) {
+                            uint32_t s0 = lds_lower_bound(sk, nst, zi.base + ka);
+                            uint32_t s1 = lds_lower_bound(sk, nst, zi.base + kb + 1);
+                            for (uint32_t s = s0; s < s1; ++s) {
+                                const PayT b = sp[s];
+                                visit(z, sk[s], b, c + s);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (active) {
+        if (MODE == 0) {
+            AStat st;
+            st.cnt = cnt;
+            st.best_j = bj;
+            m.astat[a.idx] = st;
+            m.best_idx[a.idx] = cnt ? (int32_t)bidx : -1;
+            if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), m.L_rad)) {
                 uint32_t slot = atomicAdd(m.tie_n, 1u);
-                if (slot < m.tie_cap) {
-                    TieEnt te;
-                    te.i = i;
-                    te.idxA = a.idx;
-                    te.s1 = s1;
-                    ((TieEnt *)m.tie)[slot] = te;
-                }
+                if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
             }
+        } else {
+            if (o + cnt != oe) atomicOr(m.err_flag, 2u);
         }
     }
     if (tests) atomicAdd(&s_tests, tests);
@@ -339,133 +559,242 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     }
 }
 
-__global__ void k_amb_info(const uint2 *__restrict__ amb, uint32_t n, const ARec *__restrict__ arec,
-                           const double2 *__restrict__ radecB, const Pay64 *__restrict__ p64,
-                           const Pay32 *__restrict__ p32, const double *__restrict__ sa,
-                           const double *__restrict__ sb, const double *__restrict__ pa,
-                           AmbInfo *__restrict__ out)
+// Every match of the listed sorted A positions (best-match re-ranking).
+template <int SHAPE, int PREC>
+__global__ void k_collect(MatchArgs m)
+{
+    using PayT = PayOf<PREC>;
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n_col) return;
+    const PayT *pay;
+    if constexpr (PREC == C3X_FP64) pay = m.pay64;
+    else pay = m.pay32;
+    uint32_t i = m.col_pos[t];
+    AEll e{};
+    AEllR er{};
+    LaneF32 f{};
+    double reach = m.reach_deg;
+    if constexpr (SHAPE == C3X_ELLIPSE) {
+        e = m.aell[i];
+        er = m.aellr[i];
+        reach = er.a_arcsec / 3600.0;
+        f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
+                    (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
+    }
+    ARec a = load_a(m, i, reach);
+    CellCache cc{0xffffffffu, 0.f, 0.f, 0.f};
+    for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
+        cc.key = 0xffffffffu;
+        for (uint32_t j = j0; j < j1; ++j) {
+            const PayT b = pay[j];
+            double c2;
+            int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, m.g.keys[j], b, j, c2);
+            if (d == AMBIG) d = verdict(m, i, j);
+            if (d != IN) continue;
+            uint32_t slot = atomicAdd(m.col_n, 1u);
+            if (slot < m.col_cap) {
+                double2 rb = m.radecB[j];
+                ColEnt ce;
+                ce.t = t;
+                ce.idxB = b.idx;
+                ce.j = j;
+                ce.pad = 0;
+                ce.ra = rb.x;
+                ce.dec = rb.y;
+                ((ColEnt *)m.col)[slot] = ce;
+            }
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------- small kernels
+
+// One thread per band candidate: the FP64 relative-accuracy recheck (error
+// <= ~90 u against a 2^-40 margin). Writes 0 (out), 1 (in) or 2 (still
+// undecided: the host decides it in binary128), with what the host needs.
+template <int SHAPE>
+__global__ void k_recheck(const uint2 *__restrict__ band, uint32_t n, const double2 *__restrict__ arad,
+                          const uint32_t *__restrict__ aidx, const AEllR *__restrict__ aellr,
+                          const double2 *__restrict__ radecB, const Pay64 *__restrict__ p64,
+                          const Pay32 *__restrict__ p32, double h_r, const double *__restrict__ sa,
+                          const double *__restrict__ sb, const double *__restrict__ pa,
+                          AmbInfo *__restrict__ out, uint8_t *__restrict__ v)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    uint2 q = amb[t];
-    ARec a = arec[q.x];
-    double2 b = radecB[q.y];
+    uint2 q = band[t];
+    double2 ad = arad[q.x];
+    uint32_t row = aidx[q.x];
+    double2 rb = radecB[q.y];
+    ARec a;
+    a.ra = ad.x;
+    a.dec = ad.y;
+    unit_vec(a.ra, a.dec, a.x, a.y, a.z);
+    a.cosd = cos_dec_acc(a.dec);
+    a.reach_deg = 0.0;
+    a.idx = row;
+    a.pad = 0;
+    int d;
+    if (SHAPE == C3X_CIRCLE) d = recheck_circle(a, rb, h_r);
+    else d = recheck_ellipse(a, aellr[q.x], rb);
+    v[t] = (uint8_t)d;
     AmbInfo r;
-    r.raA = a.ra;
-    r.decA = a.dec;
-    r.raB = b.x;
-    r.decB = b.y;
-    r.a = sa ? sa[a.idx] : 0.0;
-    r.b = sb ? sb[a.idx] : 0.0;
-    r.pa = pa ? pa[a.idx] : 0.0;
+    r.raA = ad.x;
+    r.decA = ad.y;
+    r.raB = rb.x;
+    r.decB = rb.y;
+    r.a = sa ? sa[row] : 0.0;
+    r.b = sb ? sb[row] : 0.0;
+    r.pa = pa ? pa[row] : 0.0;
     r.i = q.x;
     r.j = q.y;
-    r.idxA = a.idx;
+    r.idxA = row;
     r.idxB = p64 ? p64[q.y].idx : p32[q.y].idx;
     out[t] = r;
 }
 
-__global__ void k_add_counts(const uint32_t *__restrict__ rows, uint32_t n, uint32_t *cnt)
+__global__ void k_gather_pos(const uint32_t *__restrict__ pos, uint32_t n,
+                             const double2 *__restrict__ arad, const uint32_t *__restrict__ aidx,
+                             double2 *__restrict__ oad, uint32_t *__restrict__ orow)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) atomicAdd(&cnt[rows[t]], 1u);
+    if (t >= n) return;
+    oad[t] = arad[pos[t]];
+    orow[t] = aidx[pos[t]];
 }
 
-__global__ void k_nonzero(const uint32_t *__restrict__ cnt, int64_t n, uint32_t *__restrict__ f)
+__global__ void k_add_counts(const uint32_t *__restrict__ rows, uint32_t n, AStat *st)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) f[t] = cnt[t] ? 1u : 0u;
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) atomicAdd(&st[rows[t]].cnt, 1u);
 }
 
-__global__ void k_best_pairs(int64_t n, int64_t P, const int64_t *__restrict__ off,
-                             const int32_t *__restrict__ bidx, const double *__restrict__ bsep,
-                             int32_t *__restrict__ oa, int32_t *__restrict__ ob,
-                             double *__restrict__ os, uint32_t *__restrict__ err)
+__global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
+                             const uint32_t *__restrict__ bj, uint32_t n, int32_t *best_idx,
+                             AStat *st)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n || bidx[t] < 0) return;
-    int64_t p = off[t];
-    if (p >= P || off[t + 1] != p + 1) {
-        atomicOr(err, 8u);
-        return;
-    }
-    oa[p] = (int32_t)t;
-    ob[p] = bidx[t];
-    os[p] = bsep[t];
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    best_idx[rows[t]] = bi[t];
+    st[rows[t]].best_j = bj[t];
 }
 
-// ---------------------------------------------------------------------------- canonical order
-
-constexpr int kSegSmall = 32;
-constexpr int kSegLds = 2048;
-
-__global__ void k_seg_small(const int64_t *__restrict__ off, int64_t n, int32_t *__restrict__ ob,
-                            double *__restrict__ os, uint32_t *__restrict__ big_n,
-                            uint32_t *__restrict__ big, uint32_t big_cap)
+__global__ void k_counts(const AStat *__restrict__ st, int64_t n, int nonzero,
+                         uint32_t *__restrict__ out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    int64_t o = off[t];
-    int64_t len = off[t + 1] - o;
-    if (len < 2) return;
-    if (len > kSegSmall) {
-        uint32_t s = atomicAdd(big_n, 1u);
-        if (s < big_cap) big[s] = (uint32_t)t;
+    uint32_t c = st[t].cnt;
+    out[t] = nonzero ? (c ? 1u : 0u) : c;
+}
+
+// One thread per pair: canonical position inside the A segment (rank by
+// idxB; longer segments were sorted beforehand) and the FP64 separation.
+__global__ void k_finalize(int64_t P, int64_t nA, int64_t nB, const int64_t *__restrict__ off,
+                           const int32_t *__restrict__ ia, const uint2 *__restrict__ tmp,
+                           const double *__restrict__ raA, const double *__restrict__ decA,
+                           const double2 *__restrict__ radecB, int32_t *__restrict__ ob,
+                           double *__restrict__ os, uint32_t *__restrict__ err)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int32_t a = ia[p];
+    uint2 my = tmp[p];
+    if (a < 0 || a >= nA || my.y >= (uint64_t)nB) {  // only after a write-pass fault
+        atomicOr(err, 16u);
         return;
     }
-    int32_t kb[kSegSmall];
-    double ks[kSegSmall];
-    for (int k = 0; k < len; ++k) {
-        kb[k] = ob[o + k];
-        ks[k] = os[o + k];
+    int64_t o = off[a], e = off[a + 1];
+    if (p < o || p >= e || e > P) {
+        atomicOr(err, 16u);
+        return;
     }
-    bool sorted = true;
-    for (int k = 1; k < len; ++k) sorted &= kb[k - 1] < kb[k];
-    if (sorted) return;
-    for (int k = 1; k < len; ++k) {
-        int32_t b = kb[k];
-        double s = ks[k];
-        int q = k - 1;
-        while (q >= 0 && kb[q] > b) {
-            kb[q + 1] = kb[q];
-            ks[q + 1] = ks[q];
-            --q;
+    int64_t r = p - o;
+    if (e - o <= kRankMax) {
+        r = 0;
+        for (int64_t q = o; q < e; ++q) r += tmp[q].x < my.x;
+    }
+    double2 rb = radecB[my.y];
+    double s = sep_arcsec_rd(raA[a], decA[a], rb.x, rb.y);
+    ob[o + r] = (int32_t)my.x;
+    os[o + r] = s;
+}
+
+// One thread per A row: separation of the best match; in BEST-only mode also
+// the compacted (idxA, idxB, sep) pair.
+__global__ void k_best_sep(int64_t n, int64_t nB, const int32_t *__restrict__ bidx,
+                           const AStat *__restrict__ st, const double *__restrict__ raA,
+                           const double *__restrict__ decA, const double2 *__restrict__ radecB,
+                           double *__restrict__ bsep, const int64_t *__restrict__ off, int64_t P,
+                           int32_t *__restrict__ oa, int32_t *__restrict__ ob,
+                           double *__restrict__ os, uint32_t *__restrict__ err)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int32_t b = bidx[t];
+    if (b < 0) {
+        bsep[t] = NAN;
+        return;
+    }
+    uint32_t bj = st[t].best_j;
+    if (bj >= (uint64_t)nB) {
+        atomicOr(err, 16u);
+        return;
+    }
+    double2 rb = radecB[bj];
+    double s = sep_arcsec_rd(raA[t], decA[t], rb.x, rb.y);
+    bsep[t] = s;
+    if (off) {
+        int64_t p = off[t];
+        if (p < P && off[t + 1] == p + 1) {
+            oa[p] = (int32_t)t;
+            ob[p] = b;
+            os[p] = s;
+        } else {
+            atomicOr(err, 8u);
         }
-        kb[q + 1] = b;
-        ks[q + 1] = s;
-    }
-    for (int k = 0; k < len; ++k) {
-        ob[o + k] = kb[k];
-        os[o + k] = ks[k];
     }
 }
 
-// One workgroup per segment of up to kSegLds pairs: bitonic sort in LDS.
-__global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off,
-                                                 const uint32_t *__restrict__ big, uint32_t nbig,
-                                                 int32_t *__restrict__ ob, double *__restrict__ os,
-                                                 uint32_t *__restrict__ huge_n,
-                                                 uint32_t *__restrict__ huge, uint32_t huge_cap)
+// ---------------------------------------------------------------------------- long segments
+
+__global__ void k_seg_list(const int64_t *__restrict__ off, int64_t n, uint32_t *__restrict__ cnt,
+                           uint32_t *__restrict__ list, uint32_t cap)
 {
-    __shared__ uint32_t key[kSegLds];
-    __shared__ uint32_t pos[kSegLds];
-    __shared__ double sep[kSegLds];
-    uint32_t a = big[blockIdx.x];
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    if (off[t + 1] - off[t] > kRankMax) {
+        uint32_t s = atomicAdd(cnt, 1u);
+        if (s < cap) list[s] = (uint32_t)t;
+    }
+}
+
+// One workgroup per segment of up to kSegLds pairs: bitonic sort by idxB.
+__global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off,
+                                                 const uint32_t *__restrict__ list,
+                                                 uint2 *__restrict__ tmp, uint32_t *__restrict__ huge_n,
+                                                 uint32_t *__restrict__ huge, uint32_t cap)
+{
+    __shared__ unsigned long long v[kSegLds];
+    uint32_t a = list[blockIdx.x];
     int64_t o = off[a];
     int len = (int)(off[a + 1] - o);
     if (len > kSegLds) {
         if (threadIdx.x == 0) {
             uint32_t s = atomicAdd(huge_n, 1u);
-            if (s < huge_cap) huge[s] = a;
+            if (s < cap) huge[s] = a;
         }
         return;
     }
     int p2 = 1;
     while (p2 < len) p2 <<= 1;
     for (int k = threadIdx.x; k < p2; k += blockDim.x) {
-        key[k] = k < len ? (uint32_t)ob[o + k] : 0xffffffffu;
-        pos[k] = (uint32_t)k;
-        if (k < len) sep[k] = os[o + k];
+        if (k < len) {
+            uint2 x = tmp[o + k];
+            v[k] = ((unsigned long long)x.x << 32) | x.y;
+        } else {
+            v[k] = ~0ull;
+        }
     }
     __syncthreads();
     for (int size = 2; size <= p2; size <<= 1) {
@@ -474,103 +803,89 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                 int l = k ^ stride;
                 if (l > k) {
                     bool up = (k & size) == 0;
-                    uint32_t x = key[k], y = key[l];
+                    unsigned long long x = v[k], y = v[l];
                     if ((x > y) == up) {
-                        key[k] = y;
-                        key[l] = x;
-                        uint32_t t = pos[k];
-                        pos[k] = pos[l];
-                        pos[l] = t;
+                        v[k] = y;
+                        v[l] = x;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    for (int k = threadIdx.x; k < len; k += blockDim.x) {
-        ob[o + k] = (int32_t)key[k];
-        os[o + k] = sep[pos[k]];
-    }
+    for (int k = threadIdx.x; k < len; k += blockDim.x)
+        tmp[o + k] = make_uint2((uint32_t)(v[k] >> 32), (uint32_t)v[k]);
 }
 
-__global__ void k_iota(uint32_t *v, int64_t n)
+__global__ void k_split(const uint2 *__restrict__ t, int64_t n, uint32_t *__restrict__ k,
+                        uint32_t *__restrict__ v)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) v[t] = (uint32_t)t;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint2 x = t[p];
+    k[p] = x.x;
+    v[p] = x.y;
 }
 
-__global__ void k_permute_seg(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ pos,
-                              const double *__restrict__ sin_, int64_t n, int32_t *__restrict__ ob,
-                              double *__restrict__ os)
+__global__ void k_merge(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t n,
+                        uint2 *__restrict__ t)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    ob[t] = (int32_t)keys[t];
-    os[t] = sin_[pos[t]];
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) t[p] = make_uint2(k[p], v[p]);
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// Sorts every A segment of (ob, os) by idxB.
-static c3x_status order_segments(const int64_t *off, int64_t nA, int32_t *ob, double *os,
-                                 hipStream_t s, double &ms)
+// Sorts, by idxB, the (idxB, j) segments longer than the finalize kernel ranks.
+static c3x_status order_long_segments(const int64_t *off, int64_t nA, uint2 *tmp, hipStream_t s)
 {
     if (nA == 0) return C3X_OK;
-    Arena tmp(s);
+    Arena t(s);
     uint32_t cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(nA, 1), 1 << 22);
-    uint32_t *cnt = tmp.get_n<uint32_t>(2);
-    uint32_t *big = tmp.get_n<uint32_t>(cap);
-    uint32_t *huge = tmp.get_n<uint32_t>(cap);
-    if (!cnt || !big || !huge) return fail(C3X_ENOMEM, "segment order buffers");
+    uint32_t *cnt = t.get_n<uint32_t>(2);
+    uint32_t *list = t.get_n<uint32_t>(cap);
+    uint32_t *huge = t.get_n<uint32_t>(cap);
+    if (!cnt || !list || !huge) return fail(C3X_ENOMEM, "segment order buffers");
     hipError_t e = hipMemsetAsync(cnt, 0, 2 * sizeof(uint32_t), s);
-    hipLaunchKernelGGL(k_seg_small, dim3(nblk(nA, 256)), dim3(256), 0, s, off, nA, ob, os, cnt,
-                       big, cap);
+    hipLaunchKernelGGL(k_seg_list, dim3(nblk(nA, 256)), dim3(256), 0, s, off, nA, cnt, list, cap);
     uint32_t h[2] = {0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_hip(e, "segment order");
     if (h[0] > cap) return fail(C3X_ENOMEM, "too many long segments");
-    if (h[0]) {
-        hipLaunchKernelGGL(k_seg_lds, dim3(h[0]), dim3(256), 0, s, off, big, h[0], ob, os, cnt + 1,
-                           huge, cap);
-        e = hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (h[0] == 0) return C3X_OK;
+    hipLaunchKernelGGL(k_seg_lds, dim3(h[0]), dim3(256), 0, s, off, list, tmp, cnt + 1, huge, cap);
+    e = hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "segment order");
+    if (h[1] == 0) return C3X_OK;
+    std::vector<uint32_t> hv(h[1]);
+    e = hipMemcpy(hv.data(), huge, h[1] * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    for (uint32_t k = 0; k < h[1] && e == hipSuccess; ++k) {
+        int64_t ob[2];
+        e = hipMemcpy(ob, off + hv[k], 2 * sizeof(int64_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) break;
+        int64_t o = ob[0], len = ob[1] - ob[0];
+        Arena t2(s);
+        uint32_t *k1 = t2.get_n<uint32_t>(len), *v1 = t2.get_n<uint32_t>(len);
+        uint32_t *k2 = t2.get_n<uint32_t>(len), *v2 = t2.get_n<uint32_t>(len);
+        void *ws = t2.get(radix_ws_bytes(len));
+        if (!k1 || !v1 || !k2 || !v2 || !ws) return fail(C3X_ENOMEM, "segment sort");
+        hipLaunchKernelGGL(k_split, dim3(nblk(len, 256)), dim3(256), 0, s, tmp + o, len, k1, v1);
+        int in_tmp = 0;
+        e = radix_sort_pairs(k1, v1, k2, v2, len, 31, ws, s, &in_tmp);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(k_merge, dim3(nblk(len, 256)), dim3(256), 0, s, in_tmp ? k2 : k1,
+                               in_tmp ? v2 : v1, len, tmp + o);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return fail_hip(e, "segment order");
     }
-    if (h[1]) {
-        std::vector<uint32_t> hv(h[1]);
-        e = hipMemcpy(hv.data(), huge, h[1] * sizeof(uint32_t), hipMemcpyDeviceToHost);
-        std::vector<int64_t> offs(2);
-        for (uint32_t k = 0; k < h[1] && e == hipSuccess; ++k) {
-            e = hipMemcpy(offs.data(), off + hv[k], 2 * sizeof(int64_t), hipMemcpyDeviceToHost);
-            if (e != hipSuccess) break;
-            int64_t o = offs[0], len = offs[1] - offs[0];
-            Arena t2(s);
-            uint32_t *k1 = t2.get_n<uint32_t>(len), *v1 = t2.get_n<uint32_t>(len);
-            uint32_t *k2 = t2.get_n<uint32_t>(len), *v2 = t2.get_n<uint32_t>(len);
-            double *sv = t2.get_n<double>(len);
-            void *ws = t2.get(radix_ws_bytes(len));
-            if (!k1 || !v1 || !k2 || !v2 || !sv || !ws) return fail(C3X_ENOMEM, "segment sort");
-            e = hipMemcpyAsync(k1, ob + o, len * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(sv, os + o, len * sizeof(double), hipMemcpyDeviceToDevice, s);
-            hipLaunchKernelGGL(k_iota, dim3(nblk(len, 256)), dim3(256), 0, s, v1, len);
-            int in_tmp = 0;
-            if (e == hipSuccess) e = radix_sort_pairs(k1, v1, k2, v2, len, 31, ws, s, &in_tmp);
-            if (e == hipSuccess)
-                hipLaunchKernelGGL(k_permute_seg, dim3(nblk(len, 256)), dim3(256), 0, s,
-                                   in_tmp ? k2 : k1, in_tmp ? v2 : v1, sv, len, ob + o, os + o);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-        }
-        if (e != hipSuccess) return fail_hip(e, "segment order");
-    }
-    (void)ms;
+    if (e != hipSuccess) return fail_hip(e, "segment order");
     return C3X_OK;
 }
 
-// Margins of the circle filters on the squared chord (see the library notes):
-// FP64 unit vectors carry <= 32 u per component; FP32 offsets from a cell
-// reference carry 2^-24 of their size (<= L + c). Factor 4 of safety.
+// Margins of the circle filters on the squared chord: FP64 unit vectors
+// carry <= 32 u per component; FP32 offsets from a cell reference carry
+// 2^-24 of their size (<= L + c). Factor 4 of safety on the error at 1.5 r.
 struct CircleThresholds {
     double cr2, h_r, t64_in, t64_out;
     float t32_in, t32_out;
@@ -614,20 +929,32 @@ template <int MODE>
 static void launch_match(const MatchArgs &m, int shape, int prec, unsigned grid, hipStream_t s)
 {
     if (grid == 0) return;
+#define C3X_LAUNCH(SH, PR) \
+    hipLaunchKernelGGL((k_match<SH, PR, MODE>), dim3(grid), dim3(kMatchBlock), 0, s, m)
+    if (shape == C3X_CIRCLE) {
+        if (prec == C3X_FP64) C3X_LAUNCH(C3X_CIRCLE, C3X_FP64);
+        else C3X_LAUNCH(C3X_CIRCLE, C3X_MIXED);
+    } else {
+        if (prec == C3X_FP64) C3X_LAUNCH(C3X_ELLIPSE, C3X_FP64);
+        else C3X_LAUNCH(C3X_ELLIPSE, C3X_MIXED);
+    }
+#undef C3X_LAUNCH
+}
+
+static void launch_collect(const MatchArgs &m, int shape, int prec, hipStream_t s)
+{
+    unsigned grid = nblk(m.n_col, 256);
+    if (grid == 0) return;
     if (shape == C3X_CIRCLE) {
         if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_match<C3X_CIRCLE, C3X_FP64, MODE>), dim3(grid), dim3(kMatchBlock), 0,
-                               s, m);
+            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_FP64>), dim3(grid), dim3(256), 0, s, m);
         else
-            hipLaunchKernelGGL((k_match<C3X_CIRCLE, C3X_MIXED, MODE>), dim3(grid),
-                               dim3(kMatchBlock), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_MIXED>), dim3(grid), dim3(256), 0, s, m);
     } else {
         if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_match<C3X_ELLIPSE, C3X_FP64, MODE>), dim3(grid),
-                               dim3(kMatchBlock), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_FP64>), dim3(grid), dim3(256), 0, s, m);
         else
-            hipLaunchKernelGGL((k_match<C3X_ELLIPSE, C3X_MIXED, MODE>), dim3(grid),
-                               dim3(kMatchBlock), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_MIXED>), dim3(grid), dim3(256), 0, s, m);
     }
 }
 
@@ -646,6 +973,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
 {
     const int shape = area->shape;
     const int prec = ix->precision;
+    const bool all = (mode & C3X_ALL) != 0;
     Timer tm(s);
     tm.mark();  // 0
     Arena tmp(s);
@@ -655,7 +983,9 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     void *ws = tmp.get(std::max(radix_ws_bytes(nA), scan_ws_bytes(nA + 1)));
     uint32_t *ctr = tmp.get_n<uint32_t>(8);  // bad, amb_n, tie_n, col_n, err
     unsigned long long *c64 = tmp.get_n<unsigned long long>(2);
-    ARec *arec = tmp.get_n<ARec>(nA);
+    double2 *arad = tmp.get_n<double2>(nA);
+    uint32_t *aidx = tmp.get_n<uint32_t>(nA);
+    AStat *astat = tmp.get_n<AStat>(nA);
     AEll *aell = nullptr;
     AEllR *aellr = nullptr;
     if (shape == C3X_ELLIPSE) {
@@ -663,8 +993,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         aellr = tmp.get_n<AEllR>(nA);
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
     }
-    if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arec)
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !aidx || !astat)
         return fail(C3X_ENOMEM, "A buffers");
+    R->nA = nA;
+    R->best_idx = R->mem.get_n<int32_t>(nA);
+    R->best_sep = R->mem.get_n<double>(nA);
+    if (!R->best_idx || !R->best_sep) return fail(C3X_ENOMEM, "best buffers");
     HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(uint32_t), s), "memset");
     HIPCHK(hipMemsetAsync(ctr, 0xff, sizeof(uint32_t), s), "memset");
     HIPCHK(hipMemsetAsync(c64, 0, 2 * sizeof(unsigned long long), s), "memset");
@@ -679,23 +1013,14 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     if (nA > 0) {
         if (shape == C3X_CIRCLE)
             hipLaunchKernelGGL(k_gather_a<C3X_CIRCLE>, dim3(nblk(nA, 256)), dim3(256), 0, s, srows,
-                               ra, dec, nA, area->radius_arcsec, sa, sb, pa, area->pa_zero_deg,
-                               area->pa_sense, ix->plan.L_rad, arec, aell, aellr);
+                               ra, dec, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
+                               ix->plan.L_rad, arad, aidx, aell, aellr);
         else
             hipLaunchKernelGGL(k_gather_a<C3X_ELLIPSE>, dim3(nblk(nA, 256)), dim3(256), 0, s,
-                               srows, ra, dec, nA, area->radius_arcsec, sa, sb, pa,
-                               area->pa_zero_deg, area->pa_sense, ix->plan.L_rad, arec, aell,
-                               aellr);
+                               srows, ra, dec, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
+                               ix->plan.L_rad, arad, aidx, aell, aellr);
     }
     HIPCHK(hipGetLastError(), "A records");
-    uint32_t bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, ctr, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy");
-    HIPCHK(hipStreamSynchronize(s), "A preparation");
-    if (bad != 0xffffffffu)
-        return fail(C3X_EINVAL,
-                    "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= 90, not finite, "
-                    "or ellipse axes outside 1e-6 <= b <= a <= 324000 arcsec, a <= 1000 b",
-                    bad);
     tm.mark();  // 1
 
     // ---- thresholds and common arguments
@@ -705,12 +1030,15 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.pay64 = ix->pay64;
     m.pay32 = ix->pay32;
     m.radecB = ix->radec;
-    m.arec = arec;
+    m.arad = arad;
+    m.aidx = aidx;
     m.aell = aell;
     m.aellr = aellr;
     m.nA = (int32_t)nA;
+    m.L_rad = ix->plan.L_rad;
     if (shape == C3X_CIRCLE) {
         CircleThresholds t = circle_thresholds(area->radius_arcsec, ix->plan.L_rad);
+        m.reach_deg = area->radius_arcsec / 3600.0;
         m.cr2 = t.cr2;
         m.h_r = t.h_r;
         m.t64_in = t.t64_in;
@@ -722,17 +1050,22 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_tests = c64;
     m.n_band = c64 + 1;
     m.err_flag = ctr + 4;
+    m.astat = astat;
+    m.best_idx = R->best_idx;
     unsigned grid = nblk(nA, kMatchBlock);
 
-    // ---- count pass
-    uint32_t *cnt = tmp.get_n<uint32_t>(nA);
+    // ---- count pass (+ best by the filter's chord, near-ties listed)
     uint32_t amb_cap = (uint32_t)std::max<int64_t>(4096, nA / 256);
+    uint32_t tie_cap = (uint32_t)std::max<int64_t>(4096, nA / 256);
     uint2 *amb = tmp.get_n<uint2>(amb_cap);
-    if (!cnt || !amb) return fail(C3X_ENOMEM, "count buffers");
-    m.cnt = cnt;
+    uint2 *tie = tmp.get_n<uint2>(tie_cap);
+    if (!amb || !tie) return fail(C3X_ENOMEM, "count buffers");
     m.amb_n = ctr + 1;
     m.amb = amb;
     m.amb_cap = amb_cap;
+    m.tie_n = ctr + 2;
+    m.tie = tie;
+    m.tie_cap = tie_cap;
     uint32_t hctr[8];
     unsigned long long h64[2];
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -741,44 +1074,74 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipMemcpyAsync(h64, c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipStreamSynchronize(s), "count pass");
-        if (hctr[1] <= amb_cap) break;
-        // the ambiguous list overflowed: grow it and count again
-        amb_cap = hctr[1];
-        amb = tmp.get_n<uint2>(amb_cap);
-        if (!amb) return fail(C3X_ENOMEM, "ambiguous list");
+        if (hctr[0] != 0xffffffffu)
+            return fail(C3X_EINVAL,
+                        "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= 90, not "
+                        "finite, or ellipse axes outside 1e-6 <= b <= a <= 324000 arcsec, "
+                        "a <= 1000 b",
+                        hctr[0]);
+        if (hctr[1] <= amb_cap && hctr[2] <= tie_cap) break;
+        // a list overflowed: grow it and count again
+        if (hctr[1] > amb_cap) {
+            amb_cap = hctr[1];
+            amb = tmp.get_n<uint2>(amb_cap);
+        }
+        if (hctr[2] > tie_cap) {
+            tie_cap = hctr[2];
+            tie = tmp.get_n<uint2>(tie_cap);
+        }
+        if (!amb || !tie) return fail(C3X_ENOMEM, "count lists");
         m.amb = amb;
         m.amb_cap = amb_cap;
-        HIPCHK(hipMemsetAsync(ctr + 1, 0, sizeof(uint32_t), s), "memset");
+        m.tie = tie;
+        m.tie_cap = tie_cap;
+        HIPCHK(hipMemsetAsync(ctr + 1, 0, 2 * sizeof(uint32_t), s), "memset");
         HIPCHK(hipMemsetAsync(c64, 0, 2 * sizeof(unsigned long long), s), "memset");
     }
-    uint32_t n_amb = hctr[1];
+    uint32_t n_amb = hctr[1], n_tie = hctr[2];
     R->stats.n_tests = (int64_t)h64[0];
     R->stats.n_band = (int64_t)h64[1];
-    R->stats.n_ambiguous = n_amb;
     tm.mark();  // 2
 
-    // ---- host decisions of the ambiguous pairs
+    // ---- band candidates: FP64 recheck on the GPU, the rest in binary128 on the host
+    std::vector<uint32_t> recheck_pos;  // sorted A positions whose best must be re-ranked
+    uint32_t n_host = 0;
     if (n_amb > 0) {
         AmbInfo *dinfo = tmp.get_n<AmbInfo>(n_amb);
-        if (!dinfo) return fail(C3X_ENOMEM, "ambiguous info");
-        hipLaunchKernelGGL(k_amb_info, dim3(nblk(n_amb, 256)), dim3(256), 0, s, amb, n_amb, arec,
-                           ix->radec, ix->pay64, ix->pay32, shape == C3X_ELLIPSE ? sa : nullptr,
-                           shape == C3X_ELLIPSE ? sb : nullptr, shape == C3X_ELLIPSE ? pa : nullptr,
-                           dinfo);
+        uint8_t *dv = tmp.get_n<uint8_t>(n_amb);
+        if (!dinfo || !dv) return fail(C3X_ENOMEM, "band buffers");
+        if (shape == C3X_CIRCLE)
+            hipLaunchKernelGGL(k_recheck<C3X_CIRCLE>, dim3(nblk(n_amb, 256)), dim3(256), 0, s, amb,
+                               n_amb, arad, aidx, aellr, ix->radec, ix->pay64, ix->pay32, m.h_r,
+                               nullptr, nullptr, nullptr, dinfo, dv);
+        else
+            hipLaunchKernelGGL(k_recheck<C3X_ELLIPSE>, dim3(nblk(n_amb, 256)), dim3(256), 0, s, amb,
+                               n_amb, arad, aidx, aellr, ix->radec, ix->pay64, ix->pay32, m.h_r,
+                               sa, sb, pa, dinfo, dv);
+        HIPCHK(hipGetLastError(), "band recheck");
         std::vector<AmbInfo> info(n_amb);
+        std::vector<uint8_t> vv(n_amb);
         HIPCHK(hipMemcpyAsync(info.data(), dinfo, n_amb * sizeof(AmbInfo), hipMemcpyDeviceToHost, s),
                "copy");
-        HIPCHK(hipStreamSynchronize(s), "ambiguous info");
+        HIPCHK(hipMemcpyAsync(vv.data(), dv, n_amb, hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(hipStreamSynchronize(s), "band recheck");
         std::vector<std::pair<unsigned long long, uint8_t>> ver(n_amb);
         std::vector<uint32_t> add;
         for (uint32_t k = 0; k < n_amb; ++k) {
             const AmbInfo &q = info[k];
-            int in = shape == C3X_CIRCLE
+            int in = vv[k];
+            if (in == AMBIG) {
+                ++n_host;
+                in = shape == C3X_CIRCLE
                          ? c3x_q_circle(q.raA, q.decA, q.raB, q.decB, area->radius_arcsec)
                          : c3x_q_ellipse(q.raA, q.decA, q.raB, q.decB, q.a, q.b, q.pa,
                                          area->pa_zero_deg, area->pa_sense);
+            }
             ver[k] = {((unsigned long long)q.i << 32) | q.j, (uint8_t)(in ? 1 : 0)};
-            if (in) add.push_back(q.idxA);
+            if (in) {
+                add.push_back(q.idxA);
+                recheck_pos.push_back(q.i);
+            }
         }
         std::sort(ver.begin(), ver.end());
         std::vector<unsigned long long> vk(n_amb);
@@ -796,111 +1159,42 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (!add.empty()) {
             HIPCHK(hipMemcpyAsync(dadd, add.data(), add.size() * 4, hipMemcpyHostToDevice, s), "copy");
             hipLaunchKernelGGL(k_add_counts, dim3(nblk(add.size(), 256)), dim3(256), 0, s, dadd,
-                               (uint32_t)add.size(), cnt);
+                               (uint32_t)add.size(), astat);
         }
         m.ver_key = dvk;
         m.ver_in = dvi;
         m.n_ver = n_amb;
         HIPCHK(hipStreamSynchronize(s), "verdict upload");  // host vectors go out of scope
     }
+    R->stats.n_ambiguous = n_host;
 
-    // ---- scan of the per-A counts (idxA order)
-    const bool all = (mode & C3X_ALL) != 0;
-    int64_t *off = tmp.get_n<int64_t>(nA + 1);
-    if (!off) return fail(C3X_ENOMEM, "offsets");
-    const uint32_t *scan_in = cnt;
-    if (!all) {
-        uint32_t *f = tmp.get_n<uint32_t>(nA);
-        if (!f) return fail(C3X_ENOMEM, "offsets");
-        if (nA > 0)
-            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnt, nA, f);
-        scan_in = f;
-    }
-    HIPCHK(scan_u32_to_i64(scan_in, off, nA, off + nA, ws, s), "scan");
-    int64_t P = 0;
-    HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
-    HIPCHK(hipStreamSynchronize(s), "scan");
-    tm.mark();  // 3
-
-    // ---- outputs
-    R->n_pairs = P;
-    R->nA = nA;
-    R->idxA = R->mem.get_n<int32_t>(P);
-    R->idxB = R->mem.get_n<int32_t>(P);
-    R->sep = R->mem.get_n<double>(P);
-    R->best_idx = R->mem.get_n<int32_t>(nA);
-    R->best_sep = R->mem.get_n<double>(nA);
-    if (!R->idxA || !R->idxB || !R->sep || !R->best_idx || !R->best_sep)
-        return fail(C3X_ENOMEM, "result buffers (%lld pairs)", (long long)P);
-
-    // ---- write pass
-    uint32_t tie_cap = (uint32_t)std::max<int64_t>(4096, nA / 256);
-    TieEnt *tie = (TieEnt *)tmp.get(tie_cap * sizeof(TieEnt));
-    if (!tie) return fail(C3X_ENOMEM, "tie list");
-    m.off = all ? off : nullptr;
-    m.write_pairs = all ? 1 : 0;
-    m.out_a = R->idxA;
-    m.out_b = R->idxB;
-    m.out_sep = R->sep;
-    m.best_idx = R->best_idx;
-    m.best_sep = R->best_sep;
-    m.tie_n = ctr + 2;
-    m.tie = (uint2 *)tie;
-    m.tie_cap = tie_cap;
-    if (!all) {
-        // offsets are not used by the write pass in this mode
-        m.off = off;
-    }
-    launch_match<1>(m, shape, prec, grid, s);
-    HIPCHK(hipGetLastError(), "write pass");
-    HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
-    HIPCHK(hipStreamSynchronize(s), "write pass");
-    tm.mark();  // 4
-    if (hctr[4] & (all ? 7u : 4u))
-        return fail(C3X_EDEVICE, "internal: count and write passes disagree (flags %u)", hctr[4]);
-    uint32_t n_tie = hctr[2];
-
-    // ---- best matches closer than the FP64 separation can rank: binary128
-    if ((mode & C3X_BEST) && n_tie > 0) {
-        if (n_tie > tie_cap) {
-            // rerun the write pass with room for every near-tie
-            tie_cap = n_tie;
-            tie = (TieEnt *)tmp.get(tie_cap * sizeof(TieEnt));
-            if (!tie) return fail(C3X_ENOMEM, "tie list");
-            m.tie = (uint2 *)tie;
-            m.tie_cap = tie_cap;
-            HIPCHK(hipMemsetAsync(ctr + 2, 0, sizeof(uint32_t), s), "memset");
-            launch_match<1>(m, shape, prec, grid, s);
-            HIPCHK(hipGetLastError(), "write pass");
-        }
-        std::vector<TieEnt> ties(n_tie);
-        HIPCHK(hipMemcpyAsync(ties.data(), tie, n_tie * sizeof(TieEnt), hipMemcpyDeviceToHost, s),
+    // ---- best matches the filter cannot rank: every match re-ranked in binary128
+    if (n_tie > 0) {
+        std::vector<uint2> ties(n_tie);
+        HIPCHK(hipMemcpyAsync(ties.data(), tie, n_tie * sizeof(uint2), hipMemcpyDeviceToHost, s),
                "copy");
         HIPCHK(hipStreamSynchronize(s), "ties");
-        std::vector<uint32_t> cpos(n_tie);
-        std::vector<double> clim(n_tie);
-        for (uint32_t k = 0; k < n_tie; ++k) {
-            cpos[k] = ties[k].i;
-            clim[k] = ties[k].s1 * (1.0 + 2.0 * kTieRel) + 1e-300;
-        }
-        uint32_t *dpos = tmp.get_n<uint32_t>(n_tie);
-        double *dlim = tmp.get_n<double>(n_tie);
-        if (!dpos || !dlim) return fail(C3X_ENOMEM, "tie buffers");
-        HIPCHK(hipMemcpyAsync(dpos, cpos.data(), n_tie * 4, hipMemcpyHostToDevice, s), "copy");
-        HIPCHK(hipMemcpyAsync(dlim, clim.data(), n_tie * 8, hipMemcpyHostToDevice, s), "copy");
-        uint32_t col_cap = 4 * n_tie + 64;
+        for (const uint2 &t : ties) recheck_pos.push_back(t.x);
+    }
+    if (!recheck_pos.empty()) {
+        std::sort(recheck_pos.begin(), recheck_pos.end());
+        recheck_pos.erase(std::unique(recheck_pos.begin(), recheck_pos.end()), recheck_pos.end());
+        uint32_t nc = (uint32_t)recheck_pos.size();
+        uint32_t *dpos = tmp.get_n<uint32_t>(nc);
+        if (!dpos) return fail(C3X_ENOMEM, "collect buffers");
+        HIPCHK(hipMemcpyAsync(dpos, recheck_pos.data(), nc * 4, hipMemcpyHostToDevice, s), "copy");
+        uint32_t col_cap = 8 * nc + 64;
         std::vector<ColEnt> col;
         for (int attempt = 0; attempt < 2; ++attempt) {
             ColEnt *dcol = (ColEnt *)tmp.get(col_cap * sizeof(ColEnt));
-            if (!dcol) return fail(C3X_ENOMEM, "tie candidates");
+            if (!dcol) return fail(C3X_ENOMEM, "collect buffers");
             HIPCHK(hipMemsetAsync(ctr + 3, 0, sizeof(uint32_t), s), "memset");
             m.col_pos = dpos;
-            m.col_lim = dlim;
-            m.n_col = n_tie;
+            m.n_col = nc;
             m.col_n = ctr + 3;
-            m.col = (uint4 *)dcol;
+            m.col = dcol;
             m.col_cap = col_cap;
-            launch_match<2>(m, shape, prec, nblk(n_tie, kMatchBlock), s);
+            launch_collect(m, shape, prec, s);
             HIPCHK(hipGetLastError(), "collect pass");
             uint32_t ncol = 0;
             HIPCHK(hipMemcpyAsync(&ncol, ctr + 3, 4, hipMemcpyDeviceToHost, s), "copy");
@@ -913,13 +1207,27 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             HIPCHK(hipMemcpy(col.data(), dcol, ncol * sizeof(ColEnt), hipMemcpyDeviceToHost), "copy");
             break;
         }
-        std::vector<std::vector<const ColEnt *>> per(n_tie);
+        std::vector<std::vector<const ColEnt *>> per(nc);
         for (const ColEnt &c : col) per[c.t].push_back(&c);
-        std::vector<ARec> ar(1);
-        for (uint32_t k = 0; k < n_tie; ++k) {
+        std::vector<double2> ad(nc);
+        std::vector<uint32_t> arow(nc);
+        {
+            double2 *dad = tmp.get_n<double2>(nc);
+            uint32_t *drow = tmp.get_n<uint32_t>(nc);
+            if (!dad || !drow) return fail(C3X_ENOMEM, "collect buffers");
+            hipLaunchKernelGGL(k_gather_pos, dim3(nblk(nc, 256)), dim3(256), 0, s, dpos, nc, arad,
+                               aidx, dad, drow);
+            HIPCHK(hipMemcpyAsync(ad.data(), dad, nc * sizeof(double2), hipMemcpyDeviceToHost, s),
+                   "copy");
+            HIPCHK(hipMemcpyAsync(arow.data(), drow, nc * 4, hipMemcpyDeviceToHost, s), "copy");
+            HIPCHK(hipStreamSynchronize(s), "collect gather");
+        }
+        std::vector<uint32_t> prow;
+        std::vector<int32_t> pbi;
+        std::vector<uint32_t> pbj;
+        for (uint32_t k = 0; k < nc; ++k) {
             auto &v = per[k];
-            if (v.size() < 2) continue;
-            HIPCHK(hipMemcpy(ar.data(), arec + ties[k].i, sizeof(ARec), hipMemcpyDeviceToHost), "copy");
+            if (v.empty()) continue;
             std::vector<double> r2(v.size()), d2(v.size());
             std::vector<int32_t> ib(v.size());
             for (size_t q = 0; q < v.size(); ++q) {
@@ -927,31 +1235,79 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                 d2[q] = v[q]->dec;
                 ib[q] = (int32_t)v[q]->idxB;
             }
-            int w = c3x_q_best(ar[0].ra, ar[0].dec, (int)v.size(), r2.data(), d2.data(), ib.data());
-            int32_t bi = ib[w];
-            double bs = v[w]->sep;
-            uint32_t ia = ties[k].idxA;
-            HIPCHK(hipMemcpy(R->best_idx + ia, &bi, sizeof(int32_t), hipMemcpyHostToDevice), "copy");
-            HIPCHK(hipMemcpy(R->best_sep + ia, &bs, sizeof(double), hipMemcpyHostToDevice), "copy");
+            int w = c3x_q_best(ad[k].x, ad[k].y, (int)v.size(), r2.data(), d2.data(), ib.data());
+            prow.push_back(arow[k]);
+            pbi.push_back(ib[w]);
+            pbj.push_back(v[w]->j);
         }
-        R->stats.n_best_ties = n_tie;
+        if (!prow.empty()) {
+            uint32_t np = (uint32_t)prow.size();
+            uint32_t *d1 = tmp.get_n<uint32_t>(np), *d3 = tmp.get_n<uint32_t>(np);
+            int32_t *d2 = tmp.get_n<int32_t>(np);
+            if (!d1 || !d2 || !d3) return fail(C3X_ENOMEM, "best patch");
+            HIPCHK(hipMemcpyAsync(d1, prow.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
+            HIPCHK(hipMemcpyAsync(d2, pbi.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
+            HIPCHK(hipMemcpyAsync(d3, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
+            hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3, np,
+                               R->best_idx, astat);
+            HIPCHK(hipStreamSynchronize(s), "best patch");
+        }
+        R->stats.n_best_ties = nc;
     }
-    tm.mark();  // 5
 
-    // ---- canonical order / best-only pairs
+    // ---- scan of the per-A counts (idxA order)
+    int64_t *off = tmp.get_n<int64_t>(nA + 1);
+    uint32_t *cnts = tmp.get_n<uint32_t>(nA);
+    if (!off || !cnts) return fail(C3X_ENOMEM, "offsets");
+    if (nA > 0)
+        hipLaunchKernelGGL(k_counts, dim3(nblk(nA, 256)), dim3(256), 0, s, astat, nA, all ? 0 : 1,
+                           cnts);
+    HIPCHK(scan_u32_to_i64(cnts, off, nA, off + nA, ws, s), "scan");
+    int64_t P = 0;
+    HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    HIPCHK(hipStreamSynchronize(s), "scan");
+    tm.mark();  // 3
+
+    // ---- outputs
+    R->n_pairs = P;
+    R->idxA = R->mem.get_n<int32_t>(P);
+    R->idxB = R->mem.get_n<int32_t>(P);
+    R->sep = R->mem.get_n<double>(P);
+    if (!R->idxA || !R->idxB || !R->sep)
+        return fail(C3X_ENOMEM, "result buffers (%lld pairs)", (long long)P);
+
     if (all) {
-        double ms = 0;
-        c3x_status st = order_segments(off, nA, R->idxB, R->sep, s, ms);
+        // ---- write pass
+        uint2 *pt = tmp.get_n<uint2>(P);
+        if (!pt) return fail(C3X_ENOMEM, "pair buffer (%lld pairs)", (long long)P);
+        m.off = off;
+        m.out_a = R->idxA;
+        m.tmp = pt;
+        launch_match<1>(m, shape, prec, grid, s);
+        HIPCHK(hipGetLastError(), "write pass");
+        tm.mark();  // 4
+        c3x_status st = order_long_segments(off, nA, pt, s);
         if (st != C3X_OK) return st;
-    } else if (nA > 0) {
-        hipLaunchKernelGGL(k_best_pairs, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, P, off,
-                           R->best_idx, R->best_sep, R->idxA, R->idxB, R->sep, ctr + 4);
-        HIPCHK(hipGetLastError(), "best pairs");
+        if (P > 0)
+            hipLaunchKernelGGL(k_finalize, dim3(nblk(P, 256)), dim3(256), 0, s, P, nA, ix->nB,
+                               off, R->idxA, pt, ra, dec, ix->radec, R->idxB, R->sep, ctr + 4);
+        HIPCHK(hipGetLastError(), "finalize");
+        tm.mark();  // 5
+    } else {
+        tm.mark();  // 4
+        tm.mark();  // 5
     }
+    if (nA > 0)
+        hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB,
+                           R->best_idx, astat,
+                           ra, dec, ix->radec, R->best_sep, all ? nullptr : off, P, R->idxA,
+                           R->idxB, R->sep, ctr + 4);
+    HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6
     HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
     HIPCHK(hipStreamSynchronize(s), "c3x_match");
-    if (hctr[4]) return fail(C3X_EDEVICE, "internal: inconsistent best-match output (%u)", hctr[4]);
+    if (hctr[4]) return fail(C3X_EDEVICE, "internal: count and write passes disagree (flags %u)",
+                             hctr[4]);
     c3x_stats &S = R->stats;
     S.n_a = nA;
     S.n_b = ix->nB;
@@ -962,7 +1318,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     S.ms_count = tm.ms(1, 2);
     S.ms_scan = tm.ms(2, 3);
     S.ms_write = tm.ms(3, 4);
-    S.ms_sort_pairs = tm.ms(5, 6);
+    S.ms_sort_pairs = tm.ms(4, 6);
     S.ms_total = tm.ms(0, 6);
     S.precision = prec;
     S.tile = kMatchBlock;

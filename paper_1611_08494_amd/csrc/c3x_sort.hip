@@ -6,9 +6,9 @@
 // digit-major histogram table, and a stable scatter: every round of 256
 // elements is ranked per wavefront with ballots (eight ballots match the
 // lanes that share a digit; mbcnt gives the rank among them), wave counts go
-// through LDS so later waves land after earlier ones, and the round's keys
-// are staged in LDS in digit order so that the global writes of a digit run
-// are contiguous.
+// through LDS so later waves land after earlier ones, and the whole tile is
+// staged in LDS in digit order so that the global writes of a digit run are
+// contiguous (about 16 elements per run).
 #include "c3x_internal.h"
 #include "c3x_sort.h"
 
@@ -49,79 +49,95 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_hist(const uint32_t *__res
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ __forceinline__ uint32_t block256_excl_scan(uint32_t x, uint32_t *wsum)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    __syncthreads();
+    return pre + inc - x;
+}
+
+// Stable scatter of one 4096-element tile. The tile's own digit histogram
+// (from k_digit_hist) gives where each digit's run starts inside the tile;
+// 16 rounds of 256 elements rank themselves per wave with ballots and land
+// in LDS in (digit, original order); the tile then leaves LDS in order, so
+// consecutive threads write consecutive addresses of one digit run. Wave
+// counts are triple-buffered, so each round needs one barrier.
 __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
-    const uint32_t *__restrict__ offs, int nblocks)
+    const uint32_t *__restrict__ offs, const uint32_t *__restrict__ hist, int nblocks)
 {
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t wcnt[kWaves][256];
-    __shared__ uint32_t rstart[256];   // start of each digit inside the round
-    __shared__ uint32_t skey[kSortBlock], sval[kSortBlock];
-    __shared__ uint32_t sdig[kSortBlock];
+    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+    __shared__ uint32_t gbase[256], tstart[256];
+    __shared__ uint32_t run[2][256];
+    __shared__ uint32_t wcnt[3][kWaves][256];
+    __shared__ uint32_t wsum[kWaves];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
-    base[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
-    int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    uint32_t hc = hist[(int64_t)tid * nblocks + blockIdx.x];
+    gbase[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    uint32_t ts = block256_excl_scan(hc, wsum);
+    tstart[tid] = ts;
+    run[0][tid] = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        wcnt[0][w][tid] = 0;
+        wcnt[1][w][tid] = 0;
+    }
+    __syncthreads();
     for (int r = 0; r < kSortItems; ++r) {
+        const int b = r % 3, rb = r & 1;
         int64_t e = tbase + r * kSortBlock + tid;
         bool valid = e < n;
         uint32_t k = valid ? kin[e] : 0u;
         uint32_t v = valid ? vin[e] : 0u;
         uint32_t d = (k >> shift) & 255u;
-        // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            uint64_t bb = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t bb = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? bb : ~bb;
         }
         unsigned rank = rank_in_mask(peers & lanemask_lt());
-        bool leader = valid && rank == 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        // exclusive scan of the round's digit counts -> rstart (one digit per thread)
-        uint32_t tot = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) tot += wcnt[w][tid];
-        // block exclusive scan of tot over 256 threads
-        uint32_t x = tot;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(x, o);
-            if ((tid & 63) >= o) x += y;
-        }
-        __shared__ uint32_t wsum[kWaves];
-        if ((tid & 63) == 63) wsum[wave] = x;
-        __syncthreads();
-        uint32_t pre = 0;
-        for (int w = 0; w < wave; ++w) pre += wsum[w];
-        rstart[tid] = pre + x - tot;
+        if (valid && rank == 0) wcnt[b][wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
             uint32_t before = 0;
-            for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-            uint32_t slot = rstart[d] + before + rank;   // position in digit order
-            skey[slot] = k;
-            sval[slot] = v;
-            sdig[slot] = d;
+            for (int w = 0; w < wave; ++w) before += wcnt[b][w][d];
+            uint32_t slot = tstart[d] + run[rb][d] + before + rank;
+            sk[slot] = k;
+            sv[slot] = v;
         }
-        __syncthreads();
-        int nvalid = (int)min<int64_t>(kSortBlock, max<int64_t>(0, n - (tbase + r * kSortBlock)));
-        if (tid < nvalid) {
-            uint32_t dd = sdig[tid];
-            uint32_t dst = base[dd] + (tid - rstart[dd]);
-            if (dst < (uint64_t)n) {
-                kout[dst] = skey[tid];
-                vout[dst] = sval[tid];
-            }
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) tot += wcnt[b][w][tid];
+        run[rb ^ 1][tid] = run[rb][tid] + tot;
+        const int bc = (r + 2) % 3;  // next written in round r + 2
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) wcnt[bc][w][tid] = 0;
+    }
+    __syncthreads();
+    int nt = (int)min<int64_t>(kSortTile, n - tbase);
+    for (int p = tid; p < nt; p += kSortBlock) {
+        uint32_t k = sk[p];
+        uint32_t d = (k >> shift) & 255u;
+        uint32_t dst = gbase[d] + (uint32_t)(p - tstart[d]);
+        if (dst < (uint64_t)n) {
+            kout[dst] = k;
+            vout[dst] = sv[p];
         }
-        __syncthreads();
-        base[tid] += tot;
-        __syncthreads();
     }
 }
 
@@ -278,7 +294,7 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint
         hipError_t e = scan_u32(hist, offs, 256 * nb, nullptr, sws, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, va, kb,
-                           vb, n, shift, offs, (int)nb);
+                           vb, n, shift, offs, hist, (int)nb);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint32_t *t = ka;
