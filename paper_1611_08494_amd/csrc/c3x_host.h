@@ -92,20 +92,34 @@ struct Timer {
     }
 };
 
-struct GridPlan {
+// Zone tables of one cell size. Built once per cell size and process, and
+// uploaded once per device; immutable and shared by every index using that
+// cell size (a few MB per cell size, kept until the process ends).
+struct ZoneTables {
     double cell_arcsec;
     double h_deg;
     int32_t nz;
     uint64_t ncells;
-    int32_t dshift;
-    uint32_t dsize;
     int key_bits;
     double L_rad;                 // bound on |p - cell reference| (radians, chord)
-    std::vector<uint32_t> zbase;  // nz + 1
-    std::vector<uint32_t> zn;
-    std::vector<double> zf;
-    std::vector<double> zref;     // 2 per zone
+    std::vector<ZoneInfo> zinfo;  // nz
+    std::vector<double2> zref;    // nz
 };
+
+struct GridPlan {
+    const ZoneTables *zt = nullptr;
+    double cell_arcsec;
+    double h_deg;
+    int32_t nz;
+    uint64_t ncells;
+    int key_bits;
+    double L_rad;
+    int32_t dshift;
+    uint32_t dsize;
+};
+
+// Device copies of a cell size's zone tables on the current device.
+c3x_status device_zone_tables(const ZoneTables *zt, const ZoneInfo **zinfo, const double2 **zref);
 
 }  // namespace c3x
 

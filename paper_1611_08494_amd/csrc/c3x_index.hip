@@ -16,6 +16,9 @@
 
 #include <algorithm>
 #include <new>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "c3x_host.h"
@@ -26,15 +29,13 @@ namespace c3x {
 constexpr double kSkyArcsec2 = 4.0 * kPi * (180.0 / kPi * 3600.0) * (180.0 / kPi * 3600.0);
 constexpr double kMinCellArcsec = 16.0;  // keeps the key space below 2^31 cells
 
-static void build_zones(GridPlan &p, double cell_arcsec)
+static void build_zones(ZoneTables &p, double cell_arcsec)
 {
     p.cell_arcsec = cell_arcsec;
     p.h_deg = cell_arcsec / 3600.0;
     p.nz = (int32_t)std::max(1.0, ceil(180.0 / p.h_deg));
-    p.zbase.assign(p.nz + 1, 0);
-    p.zn.assign(p.nz, 1);
-    p.zf.assign(p.nz, 0.0);
-    p.zref.assign(2 * (size_t)p.nz, 0.0);
+    p.zinfo.assign(p.nz, ZoneInfo{0, 1, 0.0});
+    p.zref.assign(p.nz, make_double2(0.0, 0.0));
     uint64_t tot = 0;
     double L = 0.0;
     for (int z = 0; z < p.nz; ++z) {
@@ -45,24 +46,82 @@ static void build_zones(GridPlan &p, double cell_arcsec)
         double ceq = cos(deq * kDeg);
         double nzf = floor(360.0 * ceq / p.h_deg);
         uint32_t n = (uint32_t)std::max(1.0, std::min(nzf, 4.0e9));
-        p.zn[z] = n;
-        p.zbase[z] = (uint32_t)std::min<uint64_t>(tot, 0xffffffffull);
+        p.zinfo[z].base = (uint32_t)std::min<uint64_t>(tot, 0xffffffffull);
+        p.zinfo[z].n = n;
+        p.zinfo[z].f = (double)n / 360.0;
         tot += n;
-        p.zf[z] = (double)n / 360.0;
         double dc = std::max(-90.0, std::min(90.0, 0.5 * (lo + hi)));
-        p.zref[2 * z] = cos(dc * kDeg);
-        p.zref[2 * z + 1] = sin(dc * kDeg);
-        // largest distance from a point of a cell to the cell's reference
-        double ddec = std::max(hi - dc, dc - lo);
+        p.zref[z] = make_double2(cos(dc * kDeg), sin(dc * kDeg));
+        // largest distance from a point of a cell to the cell's reference:
         // RA half-cell + half a reference-grid step (+1e-6 rad of slack for
         // the FP32 sine/cosine of the grid point)
+        double ddec = std::max(hi - dc, dc - lo);
         double dra = (180.0 / n + 180.0 / (1 << kRefBits)) * ceq + 1e-6 / kDeg;
         double ang = sqrt(ddec * ddec + dra * dra) * kDeg;
         L = std::max(L, ang);
     }
-    p.zbase[p.nz] = (uint32_t)std::min<uint64_t>(tot, 0xffffffffull);
     p.ncells = tot;
     p.L_rad = L * 1.01 + 1e-12;
+    uint64_t maxkey = tot ? tot - 1 : 0;
+    int bits = 0;
+    while (bits < 32 && (maxkey >> bits)) ++bits;
+    p.key_bits = bits;
+}
+
+namespace {
+struct TableCache {
+    std::mutex mu;
+    std::map<double, std::unique_ptr<ZoneTables>> host;
+    std::map<std::pair<int, const ZoneTables *>, std::pair<ZoneInfo *, double2 *>> dev;
+};
+TableCache &tables()
+{
+    static TableCache *c = new TableCache();  // never destroyed: outlives static teardown
+    return *c;
+}
+}  // namespace
+
+static const ZoneTables *zone_tables(double cell_arcsec)
+{
+    TableCache &c = tables();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.host.find(cell_arcsec);
+    if (it != c.host.end()) return it->second.get();
+    std::unique_ptr<ZoneTables> t(new (std::nothrow) ZoneTables());
+    if (!t) return nullptr;
+    build_zones(*t, cell_arcsec);
+    const ZoneTables *r = t.get();
+    c.host[cell_arcsec] = std::move(t);
+    return r;
+}
+
+c3x_status device_zone_tables(const ZoneTables *zt, const ZoneInfo **zinfo, const double2 **zref)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    TableCache &c = tables();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto key = std::make_pair(dev, zt);
+    auto it = c.dev.find(key);
+    if (it == c.dev.end()) {
+        ZoneInfo *zi = nullptr;
+        double2 *zr = nullptr;
+        hipError_t e = hipMalloc(&zi, zt->nz * sizeof(ZoneInfo));
+        if (e == hipSuccess) e = hipMalloc(&zr, zt->nz * sizeof(double2));
+        if (e == hipSuccess)
+            e = hipMemcpy(zi, zt->zinfo.data(), zt->nz * sizeof(ZoneInfo), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(zr, zt->zref.data(), zt->nz * sizeof(double2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (zi) (void)hipFree(zi);
+            if (zr) (void)hipFree(zr);
+            return fail_hip(e, "zone tables");
+        }
+        it = c.dev.emplace(key, std::make_pair(zi, zr)).first;
+    }
+    *zinfo = it->second.first;
+    *zref = it->second.second;
+    return C3X_OK;
 }
 
 // Chooses the cell side and the directory resolution. The cell is the
@@ -73,16 +132,25 @@ c3x_status plan_grid(GridPlan &p, int64_t nB, double reach_arcsec, double cell_r
     double cell = cell_req > 0.0 ? cell_req : std::max(reach_arcsec, kMinCellArcsec);
     cell = std::max(cell, 1e-3);
     cell = std::min(cell, 180.0 * 3600.0);
+    // skip, without building their tables, the cell sizes whose cell count
+    // (sky area / cell^2, within a zone count of the exact one) is far above 2^31
+    while (kSkyArcsec2 / (cell * cell) > 4.0 * 2147483648.0) cell *= 1.25;
+    const ZoneTables *zt = nullptr;
     for (int it = 0; it < 64; ++it) {
-        build_zones(p, cell);
-        if (p.ncells < (1ull << 31)) break;
+        zt = zone_tables(cell);
+        if (!zt) return fail(C3X_ENOMEM, "zone tables");
+        if (zt->ncells < (1ull << 31)) break;
         cell *= 1.25;
     }
-    if (p.ncells >= (1ull << 31)) return fail(C3X_EINVAL, "grid plan failed");
+    if (!zt || zt->ncells >= (1ull << 31)) return fail(C3X_EINVAL, "grid plan failed");
+    p.zt = zt;
+    p.cell_arcsec = zt->cell_arcsec;
+    p.h_deg = zt->h_deg;
+    p.nz = zt->nz;
+    p.ncells = zt->ncells;
+    p.key_bits = zt->key_bits;
+    p.L_rad = zt->L_rad;
     uint64_t maxkey = p.ncells - 1;
-    int bits = 0;
-    while (bits < 32 && (maxkey >> bits)) ++bits;
-    p.key_bits = bits;
     // directory: about two entries per B row, so that a bucket of the
     // uniform sky holds about one key and a lookup is one or two loads
     uint64_t want = std::max<uint64_t>(1024, (uint64_t)nB * 2);
@@ -172,25 +240,16 @@ __global__ void k_dir_hist(const uint32_t *__restrict__ keys, int64_t n, int dsh
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// Uploads the zone tables and the RA reference grid; fills ix->grid.
+// Points the index's grid at the (shared, cached) device zone tables.
 c3x_status upload_grid(c3x_index *ix, hipStream_t s)
 {
+    (void)s;
     GridPlan &p = ix->plan;
     Grid &g = ix->grid;
-    ZoneInfo *zinfo = ix->mem.get_n<ZoneInfo>(p.nz);
-    double2 *zref = ix->mem.get_n<double2>(p.nz);
-    if (!zinfo || !zref) return fail(C3X_ENOMEM, "index tables");
-    std::vector<ZoneInfo> zh(p.nz);
-    for (int z = 0; z < p.nz; ++z) {
-        zh[z].base = p.zbase[z];
-        zh[z].n = p.zn[z];
-        zh[z].f = p.zf[z];
-    }
-    hipError_t e = hipMemcpyAsync(zinfo, zh.data(), p.nz * sizeof(ZoneInfo), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(zref, p.zref.data(), p.nz * sizeof(double2), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables go out of scope
-    if (e != hipSuccess) return fail_hip(e, "index tables");
+    const ZoneInfo *zinfo = nullptr;
+    const double2 *zref = nullptr;
+    c3x_status st = device_zone_tables(p.zt, &zinfo, &zref);
+    if (st != C3X_OK) return st;
     g.h_deg = p.h_deg;
     g.inv_h = 1.0 / p.h_deg;
     g.nz = p.nz;

@@ -81,6 +81,13 @@ struct AEllR {             // what the FP64 recheck needs
     float pad;
 };
 
+// One match as the write pass leaves it: B row, sorted B position and the
+// separation in arcsec (NaN: computed later from the coordinates).
+struct alignas(16) PairTmp {
+    uint32_t idxB, j;
+    double sep;
+};
+
 // Per-A counters of the count pass (idxA order).
 struct AStat {
     uint32_t cnt;          // matches
@@ -122,7 +129,7 @@ struct MatchArgs {
     // write pass
     const int64_t *off;    // [nA + 1] idxA order
     int32_t *out_a;        // final idxA of each pair
-    uint2 *tmp;            // (idxB, sorted B pos) in enumeration order
+    PairTmp *tmp;          // matches in enumeration order
     // collect pass: sorted A positions; every match of each is listed
     const uint32_t *col_pos;
     uint32_t n_col;
@@ -332,17 +339,19 @@ __device__ __forceinline__ uint32_t key_lower_bound(const Grid &g, uint32_t k)
 }
 
 // Window of one source: the zones within reach in Dec and, unless the
-// whole zone is needed (a cap holding a pole, or an RA half-width of 180 deg
-// or more), the RA half-width dRA = asin(sin R / cos dec), the widest RA
-// extent of a cap. The pads absorb every rounding of this arithmetic, and
-// zone_of / cell_of are monotone, so the cells found are an exact superset.
+// whole zone is needed (a cap holding a pole, or a wide RA window), an upper
+// bound on the RA half-width of the cap. The exact half-width is
+// asin(sin R / cos dec); with y = R / cos_lb >= sin R / cos dec (R in
+// radians, cos_lb <= cos dec) it is at most asin(y) <= y / sqrt(1 - y^2).
+// The pads absorb every rounding of this arithmetic, and zone_of / cell_of
+// are monotone, so the cells found are an exact superset.
 struct Window {
     int zlo, zhi;
     bool full;
     double dra;
 };
 
-__device__ __forceinline__ Window window_of(const Grid &g, double dec, double cosd,
+__device__ __forceinline__ Window window_of(const Grid &g, double dec, double cos_lb,
                                             double reach_deg)
 {
     Window w;
@@ -351,14 +360,14 @@ __device__ __forceinline__ Window window_of(const Grid &g, double dec, double co
     w.zhi = zone_of(dec + rp, g);
     w.full = false;
     w.dra = 0.0;
-    if (fabs(dec) + rp >= 90.0) {
+    if (fabs(dec) + rp >= 90.0 || !(cos_lb > 0.0)) {
         w.full = true;
     } else {
-        double x = sin(kDeg * rp) / cosd;
-        if (x >= 0.9999) {
+        double y = (kDeg * rp) / cos_lb;
+        if (y >= 0.9) {
             w.full = true;
         } else {
-            w.dra = asin(x) / kDeg * (1.0 + 1e-9) + 1e-12;
+            w.dra = y / sqrt(1.0 - y * y) / kDeg * (1.0 + 1e-9) + 1e-12;
             if (w.dra >= 180.0) w.full = true;
         }
     }

@@ -179,6 +179,9 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double *__re
 
 // ---------------------------------------------------------------------------- decisions
 
+// A lane's source. cosd here is only a lower bound of cos Dec for the
+// window (from the unit vector, no extra trigonometry); the recheck kernel
+// rebuilds the source with the accurate cos Dec.
 __device__ __forceinline__ ARec load_a(const MatchArgs &m, uint32_t i, double reach_deg)
 {
     ARec a;
@@ -186,7 +189,7 @@ __device__ __forceinline__ ARec load_a(const MatchArgs &m, uint32_t i, double re
     a.ra = rd.x;
     a.dec = rd.y;
     unit_vec(a.ra, a.dec, a.x, a.y, a.z);
-    a.cosd = cos_dec_acc(a.dec);
+    a.cosd = sqrt(a.x * a.x + a.y * a.y) * (1.0 - 1e-12) - 1e-15;
     a.reach_deg = reach_deg;
     a.idx = m.aidx[i];
     a.pad = 0;
@@ -381,8 +384,17 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         } else {
             int64_t p = o + cnt;
             if (p < oe) {
+                // FP64: theta = 2 asin(c / 2) from the filter's chord (error
+                // ~1e-14 rad); mixed: computed by the finalize kernel
+                double sp = NAN;
+                if (PREC == C3X_FP64 && c2 < 1.9)
+                    sp = 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0);
                 m.out_a[p] = (int32_t)a.idx;
-                m.tmp[p] = make_uint2(b.idx, j);
+                PairTmp t;
+                t.idxB = b.idx;
+                t.j = j;
+                t.sep = sp;
+                m.tmp[p] = t;
             } else {
                 atomicOr(m.err_flag, 1u);
             }
@@ -413,16 +425,21 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         // zone rather than kept in registers.
         const uint32_t zb = (uint32_t)__builtin_amdgcn_readfirstlane((int)zlo_all);
         const int nzt = __builtin_amdgcn_readfirstlane((int)(zhi_all - zlo_all)) + 1;
+        ZoneInfo zq[kTileZones];
+#pragma unroll
+        for (int q = 0; q < kTileZones; ++q) zq[q] = m.g.zinfo[min((int)zb + q, m.g.nz - 1)];
         uint32_t lkey = 0;
         bool lvalid = false, lend = false;
-        for (int q = 0; q < nzt; ++q) {
+#pragma unroll
+        for (int q = 0; q < kTileZones; ++q) {
+            if (q >= nzt) break;
             const int z = (int)zb + q;
-            const ZoneInfo zi = m.g.zinfo[z];
+            const ZoneInfo zi = zq[q];
             uint32_t c0[2], c1[2];
             int nr = 0;
             if (active && z >= w.zlo && z <= w.zhi) nr = zone_ranges(zi, w, a.ra, c0, c1);
-#pragma unroll
-            for (int h = 0; h < 3; ++h) {
+            const int nh = __ballot(nr == 2) ? 3 : 1;  // wrap hulls only if a lane wraps
+            for (int h = 0; h < nh; ++h) {
                 uint32_t lo = 0xffffffffu, hi = 0;
                 if (h == 0 && nr == 1) {
                     lo = c0[0];
@@ -559,12 +576,13 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     }
 }
 
-// Every match of the listed sorted A positions (best-match re-ranking).
+// Every match of the listed sorted A positions (best-match re-ranking): one
+// wavefront per listed source, lanes striding over its candidate ranges.
 template <int SHAPE, int PREC>
-__global__ void k_collect(MatchArgs m)
+__global__ __launch_bounds__(64) void k_collect(MatchArgs m)
 {
     using PayT = PayOf<PREC>;
-    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t t = blockIdx.x;
     if (t >= m.n_col) return;
     const PayT *pay;
     if constexpr (PREC == C3X_FP64) pay = m.pay64;
@@ -584,8 +602,7 @@ __global__ void k_collect(MatchArgs m)
     ARec a = load_a(m, i, reach);
     CellCache cc{0xffffffffu, 0.f, 0.f, 0.f};
     for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
-        cc.key = 0xffffffffu;
-        for (uint32_t j = j0; j < j1; ++j) {
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
             int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, m.g.keys[j], b, j, c2);
@@ -680,27 +697,31 @@ __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *_
 }
 
 __global__ void k_counts(const AStat *__restrict__ st, int64_t n, int nonzero,
-                         uint32_t *__restrict__ out)
+                         uint32_t *__restrict__ out, double *__restrict__ bsep)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     uint32_t c = st[t].cnt;
     out[t] = nonzero ? (c ? 1u : 0u) : c;
+    if (bsep) bsep[t] = NAN;
 }
 
 // One thread per pair: canonical position inside the A segment (rank by
-// idxB; longer segments were sorted beforehand) and the FP64 separation.
+// idxB; longer segments were sorted beforehand), the FP64 separation (kept
+// from the write pass, else computed from the coordinates), and the best
+// match's separation.
 __global__ void k_finalize(int64_t P, int64_t nA, int64_t nB, const int64_t *__restrict__ off,
-                           const int32_t *__restrict__ ia, const uint2 *__restrict__ tmp,
+                           const int32_t *__restrict__ ia, const PairTmp *__restrict__ tmp,
                            const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ radecB, int32_t *__restrict__ ob,
-                           double *__restrict__ os, uint32_t *__restrict__ err)
+                           const double2 *__restrict__ radecB, const int32_t *__restrict__ bidx,
+                           int32_t *__restrict__ ob, double *__restrict__ os,
+                           double *__restrict__ bsep, uint32_t *__restrict__ err)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     int32_t a = ia[p];
-    uint2 my = tmp[p];
-    if (a < 0 || a >= nA || my.y >= (uint64_t)nB) {  // only after a write-pass fault
+    const PairTmp my = tmp[p];
+    if (a < 0 || a >= nA || my.j >= (uint64_t)nB) {  // only after a write-pass fault
         atomicOr(err, 16u);
         return;
     }
@@ -712,12 +733,16 @@ __global__ void k_finalize(int64_t P, int64_t nA, int64_t nB, const int64_t *__r
     int64_t r = p - o;
     if (e - o <= kRankMax) {
         r = 0;
-        for (int64_t q = o; q < e; ++q) r += tmp[q].x < my.x;
+        for (int64_t q = o; q < e; ++q) r += tmp[q].idxB < my.idxB;
     }
-    double2 rb = radecB[my.y];
-    double s = sep_arcsec_rd(raA[a], decA[a], rb.x, rb.y);
-    ob[o + r] = (int32_t)my.x;
+    double s = my.sep;
+    if (isnan(s)) {
+        double2 rb = radecB[my.j];
+        s = sep_arcsec_rd(raA[a], decA[a], rb.x, rb.y);
+    }
+    ob[o + r] = (int32_t)my.idxB;
     os[o + r] = s;
+    if (bidx[a] == (int32_t)my.idxB) bsep[a] = s;
 }
 
 // One thread per A row: separation of the best match; in BEST-only mode also
@@ -769,13 +794,16 @@ __global__ void k_seg_list(const int64_t *__restrict__ off, int64_t n, uint32_t 
     }
 }
 
-// One workgroup per segment of up to kSegLds pairs: bitonic sort by idxB.
+// One workgroup per segment of up to kSegLds pairs: bitonic sort by idxB
+// (unique within a segment) of (idxB << 32 | position) keys, then a gather.
 __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off,
                                                  const uint32_t *__restrict__ list,
-                                                 uint2 *__restrict__ tmp, uint32_t *__restrict__ huge_n,
+                                                 PairTmp *__restrict__ tmp,
+                                                 uint32_t *__restrict__ huge_n,
                                                  uint32_t *__restrict__ huge, uint32_t cap)
 {
     __shared__ unsigned long long v[kSegLds];
+    __shared__ PairTmp orig[kSegLds];
     uint32_t a = list[blockIdx.x];
     int64_t o = off[a];
     int len = (int)(off[a + 1] - o);
@@ -790,8 +818,9 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
     while (p2 < len) p2 <<= 1;
     for (int k = threadIdx.x; k < p2; k += blockDim.x) {
         if (k < len) {
-            uint2 x = tmp[o + k];
-            v[k] = ((unsigned long long)x.x << 32) | x.y;
+            PairTmp x = tmp[o + k];
+            orig[k] = x;
+            v[k] = ((unsigned long long)x.idxB << 32) | (unsigned)k;
         } else {
             v[k] = ~0ull;
         }
@@ -813,31 +842,29 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
             __syncthreads();
         }
     }
-    for (int k = threadIdx.x; k < len; k += blockDim.x)
-        tmp[o + k] = make_uint2((uint32_t)(v[k] >> 32), (uint32_t)v[k]);
+    for (int k = threadIdx.x; k < len; k += blockDim.x) tmp[o + k] = orig[(uint32_t)v[k]];
 }
 
-__global__ void k_split(const uint2 *__restrict__ t, int64_t n, uint32_t *__restrict__ k,
+__global__ void k_split(const PairTmp *__restrict__ t, int64_t n, uint32_t *__restrict__ k,
                         uint32_t *__restrict__ v)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    uint2 x = t[p];
-    k[p] = x.x;
-    v[p] = x.y;
+    k[p] = t[p].idxB;
+    v[p] = (uint32_t)p;
 }
 
-__global__ void k_merge(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t n,
-                        uint2 *__restrict__ t)
+__global__ void k_merge(const uint32_t *__restrict__ v, const PairTmp *__restrict__ copy, int64_t n,
+                        PairTmp *__restrict__ t)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) t[p] = make_uint2(k[p], v[p]);
+    if (p < n && v[p] < (uint64_t)n) t[p] = copy[v[p]];
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Sorts, by idxB, the (idxB, j) segments longer than the finalize kernel ranks.
-static c3x_status order_long_segments(const int64_t *off, int64_t nA, uint2 *tmp, hipStream_t s)
+static c3x_status order_long_segments(const int64_t *off, int64_t nA, PairTmp *tmp, hipStream_t s)
 {
     if (nA == 0) return C3X_OK;
     Arena t(s);
@@ -869,14 +896,16 @@ static c3x_status order_long_segments(const int64_t *off, int64_t nA, uint2 *tmp
         Arena t2(s);
         uint32_t *k1 = t2.get_n<uint32_t>(len), *v1 = t2.get_n<uint32_t>(len);
         uint32_t *k2 = t2.get_n<uint32_t>(len), *v2 = t2.get_n<uint32_t>(len);
+        PairTmp *copy = t2.get_n<PairTmp>(len);
         void *ws = t2.get(radix_ws_bytes(len));
-        if (!k1 || !v1 || !k2 || !v2 || !ws) return fail(C3X_ENOMEM, "segment sort");
+        if (!k1 || !v1 || !k2 || !v2 || !copy || !ws) return fail(C3X_ENOMEM, "segment sort");
+        e = hipMemcpyAsync(copy, tmp + o, len * sizeof(PairTmp), hipMemcpyDeviceToDevice, s);
         hipLaunchKernelGGL(k_split, dim3(nblk(len, 256)), dim3(256), 0, s, tmp + o, len, k1, v1);
         int in_tmp = 0;
-        e = radix_sort_pairs(k1, v1, k2, v2, len, 31, ws, s, &in_tmp);
+        if (e == hipSuccess) e = radix_sort_pairs(k1, v1, k2, v2, len, 31, ws, s, &in_tmp);
         if (e == hipSuccess)
-            hipLaunchKernelGGL(k_merge, dim3(nblk(len, 256)), dim3(256), 0, s, in_tmp ? k2 : k1,
-                               in_tmp ? v2 : v1, len, tmp + o);
+            hipLaunchKernelGGL(k_merge, dim3(nblk(len, 256)), dim3(256), 0, s, in_tmp ? v2 : v1,
+                               copy, len, tmp + o);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     if (e != hipSuccess) return fail_hip(e, "segment order");
@@ -943,18 +972,18 @@ static void launch_match(const MatchArgs &m, int shape, int prec, unsigned grid,
 
 static void launch_collect(const MatchArgs &m, int shape, int prec, hipStream_t s)
 {
-    unsigned grid = nblk(m.n_col, 256);
+    unsigned grid = m.n_col;
     if (grid == 0) return;
     if (shape == C3X_CIRCLE) {
         if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_FP64>), dim3(grid), dim3(256), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_FP64>), dim3(grid), dim3(64), 0, s, m);
         else
-            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_MIXED>), dim3(grid), dim3(256), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_MIXED>), dim3(grid), dim3(64), 0, s, m);
     } else {
         if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_FP64>), dim3(grid), dim3(256), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_FP64>), dim3(grid), dim3(64), 0, s, m);
         else
-            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_MIXED>), dim3(grid), dim3(256), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_MIXED>), dim3(grid), dim3(64), 0, s, m);
     }
 }
 
@@ -1261,7 +1290,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     if (!off || !cnts) return fail(C3X_ENOMEM, "offsets");
     if (nA > 0)
         hipLaunchKernelGGL(k_counts, dim3(nblk(nA, 256)), dim3(256), 0, s, astat, nA, all ? 0 : 1,
-                           cnts);
+                           cnts, all ? R->best_sep : nullptr);
     HIPCHK(scan_u32_to_i64(cnts, off, nA, off + nA, ws, s), "scan");
     int64_t P = 0;
     HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
@@ -1278,7 +1307,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
 
     if (all) {
         // ---- write pass
-        uint2 *pt = tmp.get_n<uint2>(P);
+        PairTmp *pt = tmp.get_n<PairTmp>(P);
         if (!pt) return fail(C3X_ENOMEM, "pair buffer (%lld pairs)", (long long)P);
         m.off = off;
         m.out_a = R->idxA;
@@ -1290,17 +1319,17 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (st != C3X_OK) return st;
         if (P > 0)
             hipLaunchKernelGGL(k_finalize, dim3(nblk(P, 256)), dim3(256), 0, s, P, nA, ix->nB,
-                               off, R->idxA, pt, ra, dec, ix->radec, R->idxB, R->sep, ctr + 4);
+                               off, R->idxA, pt, ra, dec, ix->radec, R->best_idx, R->idxB, R->sep,
+                               R->best_sep, ctr + 4);
         HIPCHK(hipGetLastError(), "finalize");
         tm.mark();  // 5
     } else {
         tm.mark();  // 4
         tm.mark();  // 5
     }
-    if (nA > 0)
+    if (nA > 0 && !all)
         hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB,
-                           R->best_idx, astat,
-                           ra, dec, ix->radec, R->best_sep, all ? nullptr : off, P, R->idxA,
+                           R->best_idx, astat, ra, dec, ix->radec, R->best_sep, off, P, R->idxA,
                            R->idxB, R->sep, ctr + 4);
     HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6

@@ -40,10 +40,16 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_hist(const uint32_t *__res
     h[threadIdx.x] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+    uint32_t kk[kSortItems];
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         int64_t e = base + r * kSortBlock + threadIdx.x;
-        if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+        kk[r] = e < n ? keys[e] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        int64_t e = base + r * kSortBlock + threadIdx.x;
+        if (e < n) atomicAdd(&h[(kk[r] >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
@@ -96,13 +102,23 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
         wcnt[0][w][tid] = 0;
         wcnt[1][w][tid] = 0;
     }
+    // all of this thread's elements are loaded up front (memory-level
+    // parallelism); the ranking rounds then work from registers
+    uint32_t kk[kSortItems], vv[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        int64_t e = tbase + r * kSortBlock + tid;
+        kk[r] = e < n ? kin[e] : 0u;
+        vv[r] = e < n ? vin[e] : 0u;
+    }
     __syncthreads();
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int b = r % 3, rb = r & 1;
         int64_t e = tbase + r * kSortBlock + tid;
         bool valid = e < n;
-        uint32_t k = valid ? kin[e] : 0u;
-        uint32_t v = valid ? vin[e] : 0u;
+        uint32_t k = kk[r];
+        uint32_t v = vv[r];
         uint32_t d = (k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll

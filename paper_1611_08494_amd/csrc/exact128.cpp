@@ -9,6 +9,7 @@
 // error of about 2^-106, so a difference from the threshold under 2^-96
 // (relative) is taken as an exact tie, which the inclusive boundary puts
 // inside and the best-match rule breaks by the lower index.
+#include <math.h>
 #include <quadmath.h>
 #include <stdint.h>
 
@@ -88,12 +89,49 @@ extern "C" int c3x_q_ellipse(double ra1, double dec1, double ra2, double dec2, d
 }
 
 // Index (into the candidate list) of the exact argmin of (theta, idx).
+// Haversine sin^2(theta/2) in FP64 with a relative error below 2^-45 (a few
+// dozen roundings of 2^-53 and the host libm's sine/cosine, each within an
+// ulp or two): RA difference taken across the 0/360 seam by an exact shift,
+// cos(dec) as the sine of the exact co-latitude above |dec| = 45.
+static double hav64(double ra1, double dec1, double ra2, double dec2)
+{
+    const double k = 0.017453292519943295;  // pi / 180
+    if (ra2 - ra1 > 180.0) ra2 -= 360.0;
+    else if (ra1 - ra2 > 180.0) ra1 -= 360.0;
+    double sa = sin((ra2 - ra1) * k * 0.5);
+    double sd = sin((dec2 - dec1) * k * 0.5);
+    double c1 = fabs(dec1) > 45.0 ? sin((90.0 - fabs(dec1)) * k) : cos(dec1 * k);
+    double c2 = fabs(dec2) > 45.0 ? sin((90.0 - fabs(dec2)) * k) : cos(dec2 * k);
+    return sd * sd + c1 * c2 * (sa * sa);
+}
+
+// Index (into the candidate list) of the exact argmin of (theta, idx).
+// An FP64 pass first drops every candidate whose haversine is above the
+// smallest by more than 2^-36 (relative; far outside the FP64 error, so the
+// exact order is certain); the survivors are ranked in binary128.
 extern "C" int c3x_q_best(double ra1, double dec1, int n, const double *ra2, const double *dec2,
                           const int32_t *idx)
 {
+    const double kKeep = 1.0 + 0x1p-36, kTiny = 0x1p-900;
+    double hmin = 0.0;
+    if (n > 1) {
+        hmin = hav64(ra1, dec1, ra2[0], dec2[0]);
+        for (int k = 1; k < n; ++k) {
+            double h = hav64(ra1, dec1, ra2[k], dec2[k]);
+            if (h < hmin) hmin = h;
+        }
+    }
+    double lim = hmin * kKeep > kTiny ? hmin * kKeep : kTiny;
+    if (n > 1) {
+        int keep = 0, last = -1;
+        for (int k = 0; k < n; ++k)
+            if (hav64(ra1, dec1, ra2[k], dec2[k]) <= lim) ++keep, last = k;
+        if (keep == 1) return last;
+    }
     int best = -1;
     q128 bt = 0;
     for (int k = 0; k < n; ++k) {
+        if (n > 1 && !(hav64(ra1, dec1, ra2[k], dec2[k]) <= lim)) continue;
         q128 t = qtheta(ra1, dec1, ra2[k], dec2[k]);
         if (best < 0) {
             best = k;

@@ -108,3 +108,47 @@ def test_binary128_against_200bit_on_near_boundary_pairs(L):
         i = k % n
         want = exact.decide_circle(c.raA[i], c.decA[i], c.raB[k], c.decB[k], 2.0)
         assert bool(Q.c3x_q_circle(c.raA[i], c.decA[i], c.raB[k], c.decB[k], 2.0)) == want
+
+
+def test_binary128_best_against_200bit(L):
+    """The host best-match ranking (FP64 pre-pass + binary128) returns the
+    oracle's 200-bit argmin of (theta, index) on candidate sets built around
+    exact ties (mirror images in Dec about the equator, in RA about the
+    0/360 seam and through the pole) and one-ulp near-ties, mixed with
+    random far candidates and shuffled."""
+    from oracle import exact
+    L.c3x_q_best.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_int32)]
+    L.c3x_q_best.restype = ctypes.c_int
+    rng = np.random.default_rng(20240611)
+    up = lambda x: float(np.nextafter(x, np.inf))
+    dn = lambda x: float(np.nextafter(x, -np.inf))
+    cases = []
+    for e in (1e-4, 3e-4, 5.5e-4):
+        cases.append((0.0, 0.0, [(e, 0.0), (360.0 - e, 0.0), (0.0, e), (0.0, -e)]))
+        cases.append((0.0, 0.0, [(e, 0.0), (360.0 - e, 0.0), (0.0, up(e)), (0.0, -dn(e))]))
+        cases.append((123.25, 0.0, [(123.25, e), (123.25, -e), (123.25 + e, 0.0)]))
+        cases.append((10.0, 90.0, [(0.0, 90.0 - e), (180.0, 90.0 - e), (77.0, up(90.0 - e))]))
+        cases.append((200.0, -45.0, [(200.0 + e, -45.0), (dn(200.0 + e), -45.0),
+                                     (200.0, -45.0 + e)]))
+    bad = []
+    for ra1, dec1, near in cases:
+        for trial in range(6):
+            far = [(float((ra1 + rng.uniform(-0.01, 0.01)) % 360.0),
+                    float(np.clip(dec1 + rng.uniform(-0.01, 0.01), -90, 90)))
+                   for _ in range(rng.integers(0, 5))]
+            pts = near + far
+            idx = rng.permutation(len(pts) * 3)[:len(pts)].astype(np.int32)
+            order = rng.permutation(len(pts))
+            r2 = np.array([pts[k][0] for k in order], dtype=np.float64)
+            d2 = np.array([pts[k][1] for k in order], dtype=np.float64)
+            ib = np.ascontiguousarray(idx[order])
+            k = L.c3x_q_best(ra1, dec1, len(pts),
+                             r2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             d2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             ib.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+            want = exact.best_of(ra1, dec1, [(int(ib[q]), r2[q], d2[q]) for q in range(len(pts))])
+            if int(ib[k]) != want:
+                bad.append((ra1, dec1, pts, int(ib[k]), want))
+    assert not bad, bad[:3]

@@ -269,3 +269,25 @@ def test_cfg2_full_size_sampled(c3x, dev, precision):
     assert np.all(np.diff(key) > 0)
     assert g["sep"].max() <= cat.radius_arcsec + 1e-9
     assert 7.0e6 < len(ia) < 8.5e6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_long_segments(c3x, dev, precision):
+    """Sources with hundreds to tens of thousands of matches each: the
+    segment ordering paths beyond the in-kernel rank (LDS bitonic sort and
+    the radix-sort fallback) must still give the canonical order."""
+    g = np.random.default_rng(11)
+    rb, db = synth.cap_uniform(g, 120_000, 40.0, -30.0, 0.3)
+    ra1, da1 = synth.cap_uniform(g, 12, 40.0, -30.0, 0.05)      # deep inside: ~40k matches
+    ra2, da2 = synth.cap_uniform(g, 40, 40.0, -30.0, 0.3)       # spread: hundreds+
+    ra3 = np.array([40.0 + 0.31 / np.cos(np.radians(30.0))])     # just outside the cap
+    da3 = np.array([-30.0])
+    rb2, db2 = synth.cap_uniform(g, 700, 200.0, 10.0, 0.05)     # a small cluster: ~700 matches
+    ra4, da4 = synth.cap_uniform(g, 5, 200.0, 10.0, 0.01)
+    cat = synth.Catalogues("long_segments", np.concatenate([ra1, ra2, ra3, ra4]),
+                           np.concatenate([da1, da2, da3, da4]), np.concatenate([rb, rb2]),
+                           np.concatenate([db, db2]), radius_arcsec=400.0)
+    o = oracle_match(cat)
+    seg = np.bincount(o.ia, minlength=cat.nA)
+    assert seg.max() > 2048 and ((seg > 64) & (seg <= 2048)).any()
+    assert_parity(gpu_match(c3x, dev, cat, precision), o)
