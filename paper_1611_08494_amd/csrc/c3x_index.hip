@@ -163,13 +163,16 @@ c3x_status plan_grid(GridPlan &p, int64_t nB, double reach_arcsec, double cell_r
 
 // ---------------------------------------------------------------------------- kernels
 
+// Keys of the B rows, and the coordinates packed in pairs so that the
+// gather after the sort reads one 16-byte record per row.
 __global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict__ dec, int64_t n,
                          Grid g, uint32_t *__restrict__ keys, uint32_t *__restrict__ rows,
-                         uint32_t *__restrict__ bad)
+                         double2 *__restrict__ packed, uint32_t *__restrict__ bad)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double a = ra[j], d = dec[j];
+    packed[j] = make_double2(a, d);
     bool ok = isfinite(a) && isfinite(d) && a >= 0.0 && a < 360.0 && fabs(d) <= 90.0;
     if (!ok) {
         atomicMin(bad, (uint32_t)j);
@@ -183,17 +186,17 @@ __global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict
 }
 
 template <int PREC>
-__global__ void k_gather_b(const uint32_t *__restrict__ rows, const double *__restrict__ ra,
-                           const double *__restrict__ dec, int64_t n, Grid g,
-                           Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
+__global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__restrict__ packed,
+                           int64_t n, Grid g, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
                            double2 *__restrict__ radec)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     uint32_t row = rows[s];
     if (row >= (uint64_t)n) row = 0;  // unreachable for a permutation; keeps reads in bounds
-    double a = ra[row], d = dec[row];
-    radec[s] = make_double2(a, d);
+    const double2 rd = packed[row];
+    const double a = rd.x, d = rd.y;
+    radec[s] = rd;
     double x, y, z;
     unit_vec(a, d, x, y, z);
     if (PREC == C3X_FP64) {
@@ -315,6 +318,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     uint32_t *rtmp = tmp.get_n<uint32_t>(n);
     void *ws = tmp.get(radix_ws_bytes(n));
     uint32_t *bad = tmp.get_n<uint32_t>(1);
+    double2 *packed = tmp.get_n<double2>(n);
     double2 *radec = ix->mem.get_n<double2>(n);
     Pay64 *p64 = nullptr;
     Pay32 *p32 = nullptr;
@@ -323,7 +327,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
     uint32_t *dcnt = tmp.get_n<uint32_t>(ix->plan.dsize);
     void *dws = tmp.get(scan_ws_bytes(ix->plan.dsize));
-    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !radec || !dir || !dcnt || !dws ||
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !radec || !dir || !dcnt || !dws ||
         (!p64 && !p32)) {
         (void)hipStreamSynchronize(s);
         delete ix;
@@ -334,7 +338,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     g.nB = (int32_t)n;
     if (n > 0)
         hipLaunchKernelGGL(k_prep_b, dim3(nblk(n, 256)), dim3(256), 0, s, ra_deg, dec_deg, n, g,
-                           keys, rows, bad);
+                           keys, rows, packed, bad);
     int in_tmp = 0;
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess)
@@ -346,10 +350,10 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     if (e == hipSuccess && n > 0) {
         if (o.precision == C3X_FP64)
             hipLaunchKernelGGL(k_gather_b<C3X_FP64>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
-                               ra_deg, dec_deg, n, g, p64, p32, radec);
+                               packed, n, g, p64, p32, radec);
         else
             hipLaunchKernelGGL(k_gather_b<C3X_MIXED>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
-                               ra_deg, dec_deg, n, g, p64, p32, radec);
+                               packed, n, g, p64, p32, radec);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemsetAsync(dcnt, 0, (size_t)ix->plan.dsize * 4, s);

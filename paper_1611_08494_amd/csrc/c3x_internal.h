@@ -88,6 +88,15 @@ struct alignas(16) PairTmp {
     double sep;
 };
 
+// A match as the single-pass kernel emits it, in enumeration order: the
+// k-th match of the A source at sorted position i. Chunks of 64 entries,
+// allocated per wavefront.
+struct alignas(16) WEnt {
+    uint32_t i, k, idxB, j;
+};
+constexpr int kEmitPools = 64;       // chunk allocation counters (spread contention)
+constexpr int kEmitPoolStride = 32;  // u32 words between two counters (128 B)
+
 // Per-A counters of the count pass (idxA order).
 struct AStat {
     uint32_t cnt;          // matches
@@ -128,8 +137,14 @@ struct MatchArgs {
     uint32_t n_ver;
     // write pass
     const int64_t *off;    // [nA + 1] idxA order
-    int32_t *out_a;        // final idxA of each pair
     PairTmp *tmp;          // matches in enumeration order
+    // single pass (count + emit): chunked match list
+    WEnt *went;            // [w_nch * 64]
+    double *wsep;          // [w_nch * 64] squared chords (FP64 path) or null
+    uint32_t *wvc;         // [w_nch] valid entries of each allocated chunk
+    uint32_t *wctr;        // [kEmitPools * kEmitPoolStride] chunks taken per pool
+    uint32_t w_nch;        // chunk capacity
+    uint32_t *w_ovf;       // set when the capacity ran out
     // collect pass: sorted A positions; every match of each is listed
     const uint32_t *col_pos;
     uint32_t n_col;

@@ -27,6 +27,7 @@
 // Decisions of the count, write and collect passes come from one device
 // function compiled with -ffp-contract=off, so they agree bit for bit.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -41,7 +42,7 @@ namespace c3x {
 
 constexpr int kMatchBlock = 256;
 constexpr int kWavesPerBlock = kMatchBlock / 64;
-constexpr int kRankMax = 64;    // segments up to this long are ordered by the finalize kernel
+constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
 constexpr int kSegLds = 2048;   // segments up to this long are sorted in LDS
 constexpr int kTileZones = 5;   // zones a cooperative tile may span; wider tiles go per lane
 static_assert(6 * kTileZones <= 64, "one lane per hull end");
@@ -64,11 +65,12 @@ __global__ void k_prep_a(const double *__restrict__ ra, const double *__restrict
                          Grid g, int shape, const double *__restrict__ sa,
                          const double *__restrict__ sb, const double *__restrict__ pa,
                          uint32_t *__restrict__ keys, uint32_t *__restrict__ rows,
-                         uint32_t *__restrict__ bad)
+                         double2 *__restrict__ packed, uint32_t *__restrict__ bad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double a = ra[i], d = dec[i];
+    packed[i] = make_double2(a, d);  // one 16-byte record per row for the gather
     bool ok = isfinite(a) && isfinite(d) && a >= 0.0 && a < 360.0 && fabs(d) <= 90.0;
     if (shape == C3X_ELLIPSE) {
         double A = sa[i], B = sb[i], P = pa[i];
@@ -106,8 +108,8 @@ __device__ __forceinline__ double ell_margin(double ar, double br, double kappa,
 // position (0, 0) and, for ellipses, a 1" circle, so every later loop stays
 // bounded even before the host sees the error.
 template <int SHAPE>
-__global__ void k_gather_a(const uint32_t *__restrict__ rows, const double *__restrict__ ra,
-                           const double *__restrict__ dec, int64_t n,
+__global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__restrict__ packed,
+                           int64_t n,
                            const double *__restrict__ sa, const double *__restrict__ sb,
                            const double *__restrict__ pa, double pa_zero, int pa_sense,
                            double L_rad, double2 *__restrict__ arad, uint32_t *__restrict__ aidx,
@@ -117,7 +119,8 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double *__re
     if (i >= n) return;
     uint32_t row = rows[i];
     if (row >= (uint64_t)n) row = 0;  // unreachable for a permutation; keeps reads in bounds
-    double r = ra[row], d = dec[row];
+    const double2 rd = packed[row];
+    double r = rd.x, d = rd.y;
     bool ok = isfinite(r) && isfinite(d) && r >= 0.0 && r < 360.0 && fabs(d) <= 90.0;
     double A = 1.0, B = 1.0, P = 0.0;
     if (SHAPE == C3X_ELLIPSE) {
@@ -301,7 +304,8 @@ __device__ __forceinline__ uint32_t lds_lower_bound(const uint32_t *k, uint32_t 
 
 // ---------------------------------------------------------------------------- count / write
 
-// MODE 0: count + best; MODE 1: write.
+// MODE 0: count + best; MODE 1: write (into offsets from the count);
+// MODE 2: count + best + every match emitted in enumeration order.
 template <int SHAPE, int PREC, int MODE>
 __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 {
@@ -310,9 +314,14 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     __shared__ uint32_t s_key[kWavesPerBlock][kStage];
     __shared__ PayT s_pay[kWavesPerBlock][kStage];
     __shared__ unsigned long long s_tests, s_band;
+    __shared__ uint32_t s_wch[kWavesPerBlock], s_wfill[kWavesPerBlock];  // emission state
     if (threadIdx.x == 0) {
         s_tests = 0;
         s_band = 0;
+    }
+    if (threadIdx.x < kWavesPerBlock) {
+        s_wch[threadIdx.x] = 0xffffffffu;  // no chunk yet
+        s_wfill[threadIdx.x] = 64;
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -355,13 +364,53 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     unsigned long long tests = 0, band = 0;
     CellCache cc{0xffffffffu, 0.f, 0.f, 0.f};
 
-    // One candidate: decide it, then count / rank it (MODE 0) or write it.
+    // Appends one match per calling lane to the wavefront's current chunk
+    // (MODE 2). Called by exactly the lanes that have a match, possibly
+    // inside divergent loops: the chunk and its fill level live in LDS and
+    // the lowest calling lane updates them; a chunk that fills up is closed
+    // and a new one is taken from the block's pool with one atomic.
+    auto emit = [&](uint32_t k, uint32_t idxB, uint32_t j, double c2) {
+        const unsigned long long hm = __ballot(1);
+        const uint32_t n = (uint32_t)__popcll(hm);
+        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+        const bool first = r == 0;
+        wave_sync();
+        const uint32_t ch = s_wch[wave], fill = s_wfill[wave];
+        const bool spill = fill + n > 64;
+        uint32_t nch = ch;
+        if (spill) {
+            uint32_t v = 0;
+            if (first) {
+                const uint32_t pool = blockIdx.x & (kEmitPools - 1);
+                v = pool + kEmitPools * atomicAdd(m.wctr + pool * kEmitPoolStride, 1u);
+                if (v >= m.w_nch) atomicOr(m.w_ovf, 1u);
+                if (ch < m.w_nch) m.wvc[ch] = 64;  // the old chunk is now full
+            }
+            nch = (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+        }
+        const uint32_t q = fill + r;
+        const uint32_t c = q < 64 ? ch : nch;
+        if (c < m.w_nch) {
+            const size_t p = (size_t)c * 64 + (q < 64 ? q : q - 64);
+            m.went[p] = WEnt{i, k, idxB, j};
+            if constexpr (PREC == C3X_FP64) m.wsep[p] = c2;
+        }
+        if (first) {
+            s_wch[wave] = spill ? nch : ch;
+            s_wfill[wave] = spill ? fill + n - 64 : fill + n;
+        }
+        wave_sync();
+    };
+
+    // One candidate: decide it, then count / rank it (MODE 0), write it
+    // (MODE 1), or both (MODE 2).
     auto visit = [&](int z, uint32_t key, const PayT &b, uint32_t j) {
         ++tests;
         double c2;
         int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, key, b, j, c2);
         if (d == AMBIG) {
-            if (MODE == 0) {
+            if (MODE != 1) {
                 ++band;
                 uint32_t slot = atomicAdd(m.amb_n, 1u);
                 if (slot < m.amb_cap) m.amb[slot] = make_uint2(i, j);
@@ -371,7 +420,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             }
         }
         if (d != IN) return;
-        if (MODE == 0) {
+        if (MODE != 1) {
+            if (MODE == 2) emit(cnt, b.idx, j, c2);  // FP64: the chord goes with the match
             ++cnt;
             if (c2 < b1 || (c2 == b1 && b.idx < bidx)) {
                 b2 = b1;
@@ -389,7 +439,6 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                 double sp = NAN;
                 if (PREC == C3X_FP64 && c2 < 1.9)
                     sp = 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0);
-                m.out_a[p] = (int32_t)a.idx;
                 PairTmp t;
                 t.idxB = b.idx;
                 t.j = j;
@@ -553,7 +602,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         }
     }
     if (active) {
-        if (MODE == 0) {
+        if (MODE != 1) {
             AStat st;
             st.cnt = cnt;
             st.best_j = bj;
@@ -566,6 +615,10 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         } else {
             if (o + cnt != oe) atomicOr(m.err_flag, 2u);
         }
+    }
+    if (MODE == 2) {  // close the wavefront's last chunk
+        wave_sync();
+        if (lane == 0 && s_wch[wave] < m.w_nch) m.wvc[s_wch[wave]] = s_wfill[wave];
     }
     if (tests) atomicAdd(&s_tests, tests);
     if (band) atomicAdd(&s_band, band);
@@ -680,10 +733,91 @@ __global__ void k_gather_pos(const uint32_t *__restrict__ pos, uint32_t n,
     orow[t] = aidx[pos[t]];
 }
 
-__global__ void k_add_counts(const uint32_t *__restrict__ rows, uint32_t n, AStat *st)
+// Band candidates found inside (sorted A position, idxA, idxB, sorted B
+// position): each is counted, and listed as the k-th match of its source.
+__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, AStat *st,
+                            WEnt *__restrict__ out)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) atomicAdd(&st[rows[t]].cnt, 1u);
+    if (t >= n) return;
+    uint4 q = in[t];
+    uint32_t k = atomicAdd(&st[q.y].cnt, 1u);
+    if (out) out[t] = WEnt{q.x, k, q.z, q.w};
+}
+
+// Moves an emitted match, with its separation, to its place in the
+// idxA-order segments. The separation is computed here, in enumeration
+// order, where the A and B records read are neighbours in the sky order:
+// from the filter's squared chord on the FP64 path (theta = 2 asin(c / 2),
+// error ~1e-14 rad), else from the coordinates.
+__device__ __forceinline__ bool place_one(const WEnt &e, const double *c2p,
+                                          const uint32_t *__restrict__ aidx,
+                                          const double2 *__restrict__ arad,
+                                          const double2 *__restrict__ radecB, int64_t nA,
+                                          int64_t nB, const int64_t *__restrict__ off, int64_t P,
+                                          PairTmp *__restrict__ tmp, uint32_t *__restrict__ err)
+{
+    if (e.i >= (uint64_t)nA || e.j >= (uint64_t)nB) {
+        atomicOr(err, 16u);
+        return false;
+    }
+    const uint32_t a = aidx[e.i];
+    const int64_t o = off[a], oe = off[a + 1];
+    const int64_t p = o + e.k;
+    if (p >= oe || oe > P) {
+        atomicOr(err, 1u);
+        return false;
+    }
+    double sep;
+    if (c2p) {
+        const double c2 = *c2p;
+        sep = c2 < 1.9 ? 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0) : (double)NAN;
+    } else {
+        sep = NAN;
+    }
+    if (isnan(sep)) {
+        const double2 ra = arad[e.i], rb = radecB[e.j];
+        sep = sep_arcsec_rd(ra.x, ra.y, rb.x, rb.y);
+    }
+    PairTmp t;
+    t.idxB = e.idxB;
+    t.j = e.j;
+    t.sep = sep;
+    tmp[p] = t;
+    return true;
+}
+
+// One thread per slot of the allocated chunks (pool p's chunks are
+// p, p + kEmitPools, ...), then one per extra (band) entry.
+__global__ __launch_bounds__(256) void k_place(const WEnt *__restrict__ went,
+                                               const double *__restrict__ wsep,
+                                               const uint32_t *__restrict__ wvc,
+                                               const uint32_t *__restrict__ wctr, uint64_t nslot,
+                                               const WEnt *__restrict__ xent, uint32_t nx,
+                                               const uint32_t *__restrict__ aidx,
+                                               const double2 *__restrict__ arad,
+                                               const double2 *__restrict__ radecB, int64_t nA,
+                                               int64_t nB, const int64_t *__restrict__ off, int64_t P,
+                                               PairTmp *__restrict__ tmp,
+                                               unsigned long long *__restrict__ placed,
+                                               uint32_t *__restrict__ err)
+{
+    __shared__ uint32_t s_n;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = false;
+    if (t < nslot) {
+        const uint64_t c = t >> 6;
+        if (c / kEmitPools < wctr[(c % kEmitPools) * kEmitPoolStride] && (t & 63) < wvc[c])
+            ok = place_one(went[t], wsep ? wsep + t : nullptr, aidx, arad, radecB, nA, nB, off, P,
+                           tmp, err);
+    } else if (t - nslot < nx) {
+        ok = place_one(xent[t - nslot], nullptr, aidx, arad, radecB, nA, nB, off, P, tmp, err);
+    }
+    if (ok) atomicAdd(&s_n, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_n) atomicAdd(placed, (unsigned long long)s_n);
 }
 
 __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
@@ -706,43 +840,53 @@ __global__ void k_counts(const AStat *__restrict__ st, int64_t n, int nonzero,
     if (bsep) bsep[t] = NAN;
 }
 
-// One thread per pair: canonical position inside the A segment (rank by
-// idxB; longer segments were sorted beforehand), the FP64 separation (kept
-// from the write pass, else computed from the coordinates), and the best
-// match's separation.
-__global__ void k_finalize(int64_t P, int64_t nA, int64_t nB, const int64_t *__restrict__ off,
-                           const int32_t *__restrict__ ia, const PairTmp *__restrict__ tmp,
-                           const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ radecB, const int32_t *__restrict__ bidx,
+// Final record of one match: idxA, idxB and the separation (computed here
+// when the pass that placed it left it undefined), and the best match's
+// separation.
+__device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp &x, int64_t nB,
+                                            const double *__restrict__ raA,
+                                            const double *__restrict__ decA,
+                                            const double2 *__restrict__ radecB,
+                                            const int32_t *__restrict__ bidx,
+                                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
+                                            double *__restrict__ os, double *__restrict__ bsep,
+                                            uint32_t *__restrict__ err)
+{
+    double s = x.sep;
+    if (isnan(s)) {
+        if (x.j >= (uint64_t)nB) {
+            atomicOr(err, 16u);
+            return;
+        }
+        double2 rb = radecB[x.j];
+        s = sep_arcsec_rd(raA[a], decA[a], rb.x, rb.y);
+    }
+    oa[q] = (int32_t)a;
+    ob[q] = (int32_t)x.idxB;
+    os[q] = s;
+    if (bidx[a] == (int32_t)x.idxB) bsep[a] = s;
+}
+
+// One thread per A row whose segment is short (<= kShortSeg): the canonical
+// position of each match is its rank by idxB inside the segment (idxB is
+// unique there). Longer segments are finished by k_seg_lds.
+__global__ void k_finalize(int64_t nA, int64_t nB, const int64_t *__restrict__ off,
+                           const PairTmp *__restrict__ tmp, const double *__restrict__ raA,
+                           const double *__restrict__ decA, const double2 *__restrict__ radecB,
+                           const int32_t *__restrict__ bidx, int32_t *__restrict__ oa,
                            int32_t *__restrict__ ob, double *__restrict__ os,
                            double *__restrict__ bsep, uint32_t *__restrict__ err)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    int32_t a = ia[p];
-    const PairTmp my = tmp[p];
-    if (a < 0 || a >= nA || my.j >= (uint64_t)nB) {  // only after a write-pass fault
-        atomicOr(err, 16u);
-        return;
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nA) return;
+    const int64_t o = off[a], e = off[a + 1];
+    if (e - o > kShortSeg || e <= o) return;
+    for (int64_t q = o; q < e; ++q) {
+        const PairTmp x = tmp[q];
+        int64_t r = 0;
+        for (int64_t y = o; y < e; ++y) r += tmp[y].idxB < x.idxB;
+        final_write(o + r, a, x, nB, raA, decA, radecB, bidx, oa, ob, os, bsep, err);
     }
-    int64_t o = off[a], e = off[a + 1];
-    if (p < o || p >= e || e > P) {
-        atomicOr(err, 16u);
-        return;
-    }
-    int64_t r = p - o;
-    if (e - o <= kRankMax) {
-        r = 0;
-        for (int64_t q = o; q < e; ++q) r += tmp[q].idxB < my.idxB;
-    }
-    double s = my.sep;
-    if (isnan(s)) {
-        double2 rb = radecB[my.j];
-        s = sep_arcsec_rd(raA[a], decA[a], rb.x, rb.y);
-    }
-    ob[o + r] = (int32_t)my.idxB;
-    os[o + r] = s;
-    if (bidx[a] == (int32_t)my.idxB) bsep[a] = s;
 }
 
 // One thread per A row: separation of the best match; in BEST-only mode also
@@ -788,61 +932,83 @@ __global__ void k_seg_list(const int64_t *__restrict__ off, int64_t n, uint32_t 
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    if (off[t + 1] - off[t] > kRankMax) {
+    if (off[t + 1] - off[t] > kShortSeg) {
         uint32_t s = atomicAdd(cnt, 1u);
         if (s < cap) list[s] = (uint32_t)t;
     }
 }
 
-// One workgroup per segment of up to kSegLds pairs: bitonic sort by idxB
-// (unique within a segment) of (idxB << 32 | position) keys, then a gather.
+// Segments longer than kShortSeg, one workgroup at a time over the list
+// (the grid does not depend on the list's length): segments of up to
+// kSegLds matches are sorted by idxB in LDS (bitonic network over
+// idxB << 32 | position; idxB is unique in a segment) and written out in
+// final form; longer ones are listed for the host-driven radix sort.
 __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off,
-                                                 const uint32_t *__restrict__ list,
-                                                 PairTmp *__restrict__ tmp,
+                                                 const uint32_t *__restrict__ cnt,
+                                                 const uint32_t *__restrict__ list, uint32_t cap,
+                                                 const PairTmp *__restrict__ tmp, int64_t nB,
+                                                 const double *__restrict__ raA,
+                                                 const double *__restrict__ decA,
+                                                 const double2 *__restrict__ radecB,
+                                                 const int32_t *__restrict__ bidx,
+                                                 int32_t *__restrict__ oa, int32_t *__restrict__ ob,
+                                                 double *__restrict__ os, double *__restrict__ bsep,
                                                  uint32_t *__restrict__ huge_n,
-                                                 uint32_t *__restrict__ huge, uint32_t cap)
+                                                 uint32_t *__restrict__ huge,
+                                                 uint32_t *__restrict__ err)
 {
     __shared__ unsigned long long v[kSegLds];
-    __shared__ PairTmp orig[kSegLds];
-    uint32_t a = list[blockIdx.x];
-    int64_t o = off[a];
-    int len = (int)(off[a + 1] - o);
-    if (len > kSegLds) {
-        if (threadIdx.x == 0) {
-            uint32_t s = atomicAdd(huge_n, 1u);
-            if (s < cap) huge[s] = a;
+    const uint32_t nseg = min(*cnt, cap);
+    for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
+        const uint32_t a = list[b];
+        const int64_t o = off[a];
+        const int len = (int)min<int64_t>(off[a + 1] - o, 1 << 30);
+        if (len > kSegLds) {
+            if (threadIdx.x == 0) {
+                uint32_t s = atomicAdd(huge_n, 1u);
+                if (s < cap) huge[s] = a;
+            }
+            continue;  // uniform over the workgroup
         }
-        return;
-    }
-    int p2 = 1;
-    while (p2 < len) p2 <<= 1;
-    for (int k = threadIdx.x; k < p2; k += blockDim.x) {
-        if (k < len) {
-            PairTmp x = tmp[o + k];
-            orig[k] = x;
-            v[k] = ((unsigned long long)x.idxB << 32) | (unsigned)k;
-        } else {
-            v[k] = ~0ull;
-        }
-    }
-    __syncthreads();
-    for (int size = 2; size <= p2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int k = threadIdx.x; k < p2; k += blockDim.x) {
-                int l = k ^ stride;
-                if (l > k) {
-                    bool up = (k & size) == 0;
-                    unsigned long long x = v[k], y = v[l];
-                    if ((x > y) == up) {
-                        v[k] = y;
-                        v[l] = x;
+        int p2 = 1;
+        while (p2 < len) p2 <<= 1;
+        for (int k = threadIdx.x; k < p2; k += blockDim.x)
+            v[k] = k < len ? ((unsigned long long)tmp[o + k].idxB << 32) | (unsigned)k : ~0ull;
+        __syncthreads();
+        for (int size = 2; size <= p2; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int k = threadIdx.x; k < p2; k += blockDim.x) {
+                    int l = k ^ stride;
+                    if (l > k) {
+                        bool up = (k & size) == 0;
+                        unsigned long long x = v[k], y = v[l];
+                        if ((x > y) == up) {
+                            v[k] = y;
+                            v[l] = x;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
+        for (int k = threadIdx.x; k < len; k += blockDim.x)
+            final_write(o + k, a, tmp[o + (uint32_t)v[k]], nB, raA, decA, radecB, bidx, oa, ob, os,
+                        bsep, err);
+        __syncthreads();  // v is reused by the next segment
     }
-    for (int k = threadIdx.x; k < len; k += blockDim.x) tmp[o + k] = orig[(uint32_t)v[k]];
+}
+
+// Final records of a segment already sorted in place (host-driven path).
+__global__ void k_seg_copy(int64_t o, int64_t len, int64_t a, const PairTmp *__restrict__ tmp,
+                           int64_t nB, const double *__restrict__ raA,
+                           const double *__restrict__ decA, const double2 *__restrict__ radecB,
+                           const int32_t *__restrict__ bidx, int32_t *__restrict__ oa,
+                           int32_t *__restrict__ ob, double *__restrict__ os,
+                           double *__restrict__ bsep, uint32_t *__restrict__ err)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < len)
+        final_write(o + k, a, tmp[o + k], nB, raA, decA, radecB, bidx, oa, ob, os, bsep, err);
 }
 
 __global__ void k_split(const PairTmp *__restrict__ t, int64_t n, uint32_t *__restrict__ k,
@@ -863,34 +1029,50 @@ __global__ void k_merge(const uint32_t *__restrict__ v, const PairTmp *__restric
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// Sorts, by idxB, the (idxB, j) segments longer than the finalize kernel ranks.
-static c3x_status order_long_segments(const int64_t *off, int64_t nA, PairTmp *tmp, hipStream_t s)
+// What the finishing kernels need.
+struct FinishArgs {
+    int64_t nA, nB;
+    const int64_t *off;
+    PairTmp *tmp;
+    const double *raA, *decA;
+    const double2 *radecB;
+    const int32_t *bidx;
+    int32_t *oa, *ob;
+    double *os, *bsep;
+    uint32_t *err;
+    uint32_t *seg_n;   // [2]: listed long segments, listed huge segments
+    uint32_t *list, *huge;
+    uint32_t cap;
+};
+
+constexpr unsigned kSegGrid = 1024;
+
+// Final records of every segment: short ones per A row, long ones per
+// workgroup; segments above kSegLds are only listed (finish_huge).
+static void finish_segments(const FinishArgs &f, hipStream_t s)
 {
-    if (nA == 0) return C3X_OK;
-    Arena t(s);
-    uint32_t cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(nA, 1), 1 << 22);
-    uint32_t *cnt = t.get_n<uint32_t>(2);
-    uint32_t *list = t.get_n<uint32_t>(cap);
-    uint32_t *huge = t.get_n<uint32_t>(cap);
-    if (!cnt || !list || !huge) return fail(C3X_ENOMEM, "segment order buffers");
-    hipError_t e = hipMemsetAsync(cnt, 0, 2 * sizeof(uint32_t), s);
-    hipLaunchKernelGGL(k_seg_list, dim3(nblk(nA, 256)), dim3(256), 0, s, off, nA, cnt, list, cap);
-    uint32_t h[2] = {0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return fail_hip(e, "segment order");
-    if (h[0] > cap) return fail(C3X_ENOMEM, "too many long segments");
-    if (h[0] == 0) return C3X_OK;
-    hipLaunchKernelGGL(k_seg_lds, dim3(h[0]), dim3(256), 0, s, off, list, tmp, cnt + 1, huge, cap);
-    e = hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return fail_hip(e, "segment order");
-    if (h[1] == 0) return C3X_OK;
-    std::vector<uint32_t> hv(h[1]);
-    e = hipMemcpy(hv.data(), huge, h[1] * sizeof(uint32_t), hipMemcpyDeviceToHost);
-    for (uint32_t k = 0; k < h[1] && e == hipSuccess; ++k) {
+    if (f.nA == 0) return;
+    hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.off, f.tmp,
+                       f.raA, f.decA, f.radecB, f.bidx, f.oa, f.ob, f.os, f.bsep, f.err);
+    hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA, f.seg_n,
+                       f.list, f.cap);
+    hipLaunchKernelGGL(k_seg_lds, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list, f.cap,
+                       f.tmp, f.nB, f.raA, f.decA, f.radecB, f.bidx, f.oa, f.ob, f.os, f.bsep,
+                       f.seg_n + 1, f.huge, f.err);
+}
+
+// Segments longer than kSegLds (counts already on the host): radix sort by
+// idxB, one segment at a time, then their final records.
+static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStream_t s)
+{
+    if (hseg[0] > f.cap || hseg[1] > f.cap) return fail(C3X_ENOMEM, "too many long segments");
+    uint32_t nh = hseg[1];
+    if (nh == 0) return C3X_OK;
+    std::vector<uint32_t> hv(nh);
+    hipError_t e = hipMemcpy(hv.data(), f.huge, nh * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    for (uint32_t k = 0; k < nh && e == hipSuccess; ++k) {
         int64_t ob[2];
-        e = hipMemcpy(ob, off + hv[k], 2 * sizeof(int64_t), hipMemcpyDeviceToHost);
+        e = hipMemcpy(ob, f.off + hv[k], 2 * sizeof(int64_t), hipMemcpyDeviceToHost);
         if (e != hipSuccess) break;
         int64_t o = ob[0], len = ob[1] - ob[0];
         Arena t2(s);
@@ -899,13 +1081,17 @@ static c3x_status order_long_segments(const int64_t *off, int64_t nA, PairTmp *t
         PairTmp *copy = t2.get_n<PairTmp>(len);
         void *ws = t2.get(radix_ws_bytes(len));
         if (!k1 || !v1 || !k2 || !v2 || !copy || !ws) return fail(C3X_ENOMEM, "segment sort");
-        e = hipMemcpyAsync(copy, tmp + o, len * sizeof(PairTmp), hipMemcpyDeviceToDevice, s);
-        hipLaunchKernelGGL(k_split, dim3(nblk(len, 256)), dim3(256), 0, s, tmp + o, len, k1, v1);
+        e = hipMemcpyAsync(copy, f.tmp + o, len * sizeof(PairTmp), hipMemcpyDeviceToDevice, s);
+        hipLaunchKernelGGL(k_split, dim3(nblk(len, 256)), dim3(256), 0, s, f.tmp + o, len, k1, v1);
         int in_tmp = 0;
         if (e == hipSuccess) e = radix_sort_pairs(k1, v1, k2, v2, len, 31, ws, s, &in_tmp);
-        if (e == hipSuccess)
+        if (e == hipSuccess) {
             hipLaunchKernelGGL(k_merge, dim3(nblk(len, 256)), dim3(256), 0, s, in_tmp ? v2 : v1,
-                               copy, len, tmp + o);
+                               copy, len, f.tmp + o);
+            hipLaunchKernelGGL(k_seg_copy, dim3(nblk(len, 256)), dim3(256), 0, s, o, len,
+                               (int64_t)hv[k], f.tmp, f.nB, f.raA, f.decA, f.radecB, f.bidx, f.oa,
+                               f.ob, f.os, f.bsep, f.err);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     if (e != hipSuccess) return fail_hip(e, "segment order");
@@ -1010,9 +1196,10 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     uint32_t *keys = tmp.get_n<uint32_t>(nA), *rows = tmp.get_n<uint32_t>(nA);
     uint32_t *ktmp = tmp.get_n<uint32_t>(nA), *rtmp = tmp.get_n<uint32_t>(nA);
     void *ws = tmp.get(std::max(radix_ws_bytes(nA), scan_ws_bytes(nA + 1)));
-    uint32_t *ctr = tmp.get_n<uint32_t>(8);  // bad, amb_n, tie_n, col_n, err
-    unsigned long long *c64 = tmp.get_n<unsigned long long>(2);
+    uint32_t *ctr = tmp.get_n<uint32_t>(8);  // bad, amb_n, tie_n, col_n, err, emit overflow
+    unsigned long long *c64 = tmp.get_n<unsigned long long>(3);  // tests, band, placed
     double2 *arad = tmp.get_n<double2>(nA);
+    double2 *packed = tmp.get_n<double2>(nA);
     uint32_t *aidx = tmp.get_n<uint32_t>(nA);
     AStat *astat = tmp.get_n<AStat>(nA);
     AEll *aell = nullptr;
@@ -1022,7 +1209,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         aellr = tmp.get_n<AEllR>(nA);
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
     }
-    if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !aidx || !astat)
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !packed || !aidx ||
+        !astat)
         return fail(C3X_ENOMEM, "A buffers");
     R->nA = nA;
     R->best_idx = R->mem.get_n<int32_t>(nA);
@@ -1030,11 +1218,11 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     if (!R->best_idx || !R->best_sep) return fail(C3X_ENOMEM, "best buffers");
     HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(uint32_t), s), "memset");
     HIPCHK(hipMemsetAsync(ctr, 0xff, sizeof(uint32_t), s), "memset");
-    HIPCHK(hipMemsetAsync(c64, 0, 2 * sizeof(unsigned long long), s), "memset");
+    HIPCHK(hipMemsetAsync(c64, 0, 3 * sizeof(unsigned long long), s), "memset");
     const double *sa = area->semi_major_arcsec, *sb = area->semi_minor_arcsec, *pa = area->pa_deg;
     if (nA > 0)
         hipLaunchKernelGGL(k_prep_a, dim3(nblk(nA, 256)), dim3(256), 0, s, ra, dec, nA, ix->grid,
-                           shape, sa, sb, pa, keys, rows, ctr);
+                           shape, sa, sb, pa, keys, rows, packed, ctr);
     HIPCHK(hipGetLastError(), "A keys");
     int in_tmp = 0;
     HIPCHK(radix_sort_pairs(keys, rows, ktmp, rtmp, nA, ix->plan.key_bits, ws, s, &in_tmp), "A sort");
@@ -1042,11 +1230,11 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     if (nA > 0) {
         if (shape == C3X_CIRCLE)
             hipLaunchKernelGGL(k_gather_a<C3X_CIRCLE>, dim3(nblk(nA, 256)), dim3(256), 0, s, srows,
-                               ra, dec, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
+                               packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
                                ix->plan.L_rad, arad, aidx, aell, aellr);
         else
             hipLaunchKernelGGL(k_gather_a<C3X_ELLIPSE>, dim3(nblk(nA, 256)), dim3(256), 0, s,
-                               srows, ra, dec, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
+                               srows, packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
                                ix->plan.L_rad, arad, aidx, aell, aellr);
     }
     HIPCHK(hipGetLastError(), "A records");
@@ -1095,13 +1283,38 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.tie_n = ctr + 2;
     m.tie = tie;
     m.tie_cap = tie_cap;
+    // All matches: one pass counts and also emits every match into chunks
+    // sized for two matches per A source plus one partly filled chunk per
+    // wavefront; if that runs out, the count stands and a second pass over
+    // the same tiles writes the matches into the offsets.
+    bool emit = false;
+    const int kPoolWords = kEmitPools * kEmitPoolStride;
+    uint32_t hwctr[kPoolWords];
+    if (all && nA > 0) {
+        uint64_t nch = (uint64_t)((2 * nA + 63) / 64) + (uint64_t)grid * kWavesPerBlock + kEmitPools;
+        // test hook: C3X_DEBUG_EMIT_CHUNKS=k caps the chunks (k = 0: no emission)
+        if (const char *ev = getenv("C3X_DEBUG_EMIT_CHUNKS")) nch = std::min<uint64_t>(nch, atoll(ev));
+        if (nch > 0 && nch < (1ull << 31)) {
+            m.went = (WEnt *)tmp.get(nch * 64 * sizeof(WEnt));
+            m.wsep = prec == C3X_FP64 ? tmp.get_n<double>(nch * 64) : nullptr;
+            m.wvc = tmp.get_n<uint32_t>(nch);
+            m.wctr = tmp.get_n<uint32_t>(kPoolWords);
+            m.w_nch = (uint32_t)nch;
+            m.w_ovf = ctr + 5;
+            emit = m.went && m.wvc && m.wctr && (prec != C3X_FP64 || m.wsep);
+            if (emit) HIPCHK(hipMemsetAsync(m.wctr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
+        }
+    }
     uint32_t hctr[8];
-    unsigned long long h64[2];
+    unsigned long long h64[3];
     for (int attempt = 0; attempt < 2; ++attempt) {
-        launch_match<0>(m, shape, prec, grid, s);
+        if (emit) launch_match<2>(m, shape, prec, grid, s);
+        else launch_match<0>(m, shape, prec, grid, s);
         HIPCHK(hipGetLastError(), "count pass");
         HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipMemcpyAsync(h64, c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
+        if (emit)
+            HIPCHK(hipMemcpyAsync(hwctr, m.wctr, sizeof(hwctr), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipStreamSynchronize(s), "count pass");
         if (hctr[0] != 0xffffffffu)
             return fail(C3X_EINVAL,
@@ -1125,8 +1338,18 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         m.tie = tie;
         m.tie_cap = tie_cap;
         HIPCHK(hipMemsetAsync(ctr + 1, 0, 2 * sizeof(uint32_t), s), "memset");
+        HIPCHK(hipMemsetAsync(ctr + 5, 0, sizeof(uint32_t), s), "memset");
         HIPCHK(hipMemsetAsync(c64, 0, 2 * sizeof(unsigned long long), s), "memset");
+        if (emit) HIPCHK(hipMemsetAsync(m.wctr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
     }
+    // emitted chunk slots to place (0 when the emission ran out of room)
+    uint64_t n_slot = 0;
+    if (emit && hctr[5] == 0) {
+        uint32_t mo = 0;
+        for (int q = 0; q < kEmitPools; ++q) mo = std::max(mo, hwctr[q * kEmitPoolStride]);
+        n_slot = (uint64_t)mo * kEmitPools * 64;
+    }
+    const bool emitted = emit && hctr[5] == 0;
     uint32_t n_amb = hctr[1], n_tie = hctr[2];
     R->stats.n_tests = (int64_t)h64[0];
     R->stats.n_band = (int64_t)h64[1];
@@ -1135,6 +1358,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     // ---- band candidates: FP64 recheck on the GPU, the rest in binary128 on the host
     std::vector<uint32_t> recheck_pos;  // sorted A positions whose best must be re-ranked
     uint32_t n_host = 0;
+    WEnt *xent = nullptr;  // band matches found inside (emitted path)
+    uint32_t n_x = 0;
     if (n_amb > 0) {
         AmbInfo *dinfo = tmp.get_n<AmbInfo>(n_amb);
         uint8_t *dv = tmp.get_n<uint8_t>(n_amb);
@@ -1155,7 +1380,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipMemcpyAsync(vv.data(), dv, n_amb, hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipStreamSynchronize(s), "band recheck");
         std::vector<std::pair<unsigned long long, uint8_t>> ver(n_amb);
-        std::vector<uint32_t> add;
+        std::vector<uint4> add;
         for (uint32_t k = 0; k < n_amb; ++k) {
             const AmbInfo &q = info[k];
             int in = vv[k];
@@ -1168,7 +1393,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             }
             ver[k] = {((unsigned long long)q.i << 32) | q.j, (uint8_t)(in ? 1 : 0)};
             if (in) {
-                add.push_back(q.idxA);
+                add.push_back(make_uint4(q.i, q.idxA, q.idxB, q.j));
                 recheck_pos.push_back(q.i);
             }
         }
@@ -1181,14 +1406,20 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         }
         unsigned long long *dvk = tmp.get_n<unsigned long long>(n_amb);
         uint8_t *dvi = tmp.get_n<uint8_t>(n_amb);
-        uint32_t *dadd = tmp.get_n<uint32_t>(add.size());
+        uint4 *dadd = tmp.get_n<uint4>(add.size());
         if (!dvk || !dvi || !dadd) return fail(C3X_ENOMEM, "verdict table");
+        if (emitted && !add.empty()) {
+            xent = tmp.get_n<WEnt>(add.size());
+            if (!xent) return fail(C3X_ENOMEM, "verdict table");
+            n_x = (uint32_t)add.size();
+        }
         HIPCHK(hipMemcpyAsync(dvk, vk.data(), n_amb * 8, hipMemcpyHostToDevice, s), "copy");
         HIPCHK(hipMemcpyAsync(dvi, vi.data(), n_amb, hipMemcpyHostToDevice, s), "copy");
         if (!add.empty()) {
-            HIPCHK(hipMemcpyAsync(dadd, add.data(), add.size() * 4, hipMemcpyHostToDevice, s), "copy");
-            hipLaunchKernelGGL(k_add_counts, dim3(nblk(add.size(), 256)), dim3(256), 0, s, dadd,
-                               (uint32_t)add.size(), astat);
+            HIPCHK(hipMemcpyAsync(dadd, add.data(), add.size() * sizeof(uint4),
+                                  hipMemcpyHostToDevice, s), "copy");
+            hipLaunchKernelGGL(k_add_pairs, dim3(nblk(add.size(), 256)), dim3(256), 0, s, dadd,
+                               (uint32_t)add.size(), astat, xent);
         }
         m.ver_key = dvk;
         m.ver_in = dvi;
@@ -1305,22 +1536,45 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     if (!R->idxA || !R->idxB || !R->sep)
         return fail(C3X_ENOMEM, "result buffers (%lld pairs)", (long long)P);
 
+    FinishArgs fa{};
     if (all) {
-        // ---- write pass
+        // ---- emitted matches to their segments, or the write pass
         PairTmp *pt = tmp.get_n<PairTmp>(P);
         if (!pt) return fail(C3X_ENOMEM, "pair buffer (%lld pairs)", (long long)P);
-        m.off = off;
-        m.out_a = R->idxA;
-        m.tmp = pt;
-        launch_match<1>(m, shape, prec, grid, s);
-        HIPCHK(hipGetLastError(), "write pass");
+        if (emitted) {
+            uint64_t nt = n_slot + n_x;
+            if (nt > 0)
+                hipLaunchKernelGGL(k_place, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
+                                   m.went, m.wsep, m.wvc, m.wctr, n_slot, xent, n_x, aidx, arad,
+                                   ix->radec, nA, ix->nB, off, P, pt, c64 + 2, ctr + 4);
+            HIPCHK(hipGetLastError(), "place");
+        } else {
+            m.off = off;
+            m.tmp = pt;
+            launch_match<1>(m, shape, prec, grid, s);
+            HIPCHK(hipGetLastError(), "write pass");
+        }
         tm.mark();  // 4
-        c3x_status st = order_long_segments(off, nA, pt, s);
-        if (st != C3X_OK) return st;
-        if (P > 0)
-            hipLaunchKernelGGL(k_finalize, dim3(nblk(P, 256)), dim3(256), 0, s, P, nA, ix->nB,
-                               off, R->idxA, pt, ra, dec, ix->radec, R->best_idx, R->idxB, R->sep,
-                               R->best_sep, ctr + 4);
+        // ---- canonical order inside each segment, final records
+        fa.nA = nA;
+        fa.nB = ix->nB;
+        fa.off = off;
+        fa.tmp = pt;
+        fa.raA = ra;
+        fa.decA = dec;
+        fa.radecB = ix->radec;
+        fa.bidx = R->best_idx;
+        fa.oa = R->idxA;
+        fa.ob = R->idxB;
+        fa.os = R->sep;
+        fa.bsep = R->best_sep;
+        fa.err = ctr + 4;
+        fa.seg_n = ctr + 6;
+        fa.cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(nA, 1), 1 << 22);
+        fa.list = tmp.get_n<uint32_t>(fa.cap);
+        fa.huge = tmp.get_n<uint32_t>(fa.cap);
+        if (!fa.list || !fa.huge) return fail(C3X_ENOMEM, "segment lists");
+        finish_segments(fa, s);
         HIPCHK(hipGetLastError(), "finalize");
         tm.mark();  // 5
     } else {
@@ -1334,9 +1588,21 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6
     HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
+    HIPCHK(hipMemcpyAsync(h64, c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
     HIPCHK(hipStreamSynchronize(s), "c3x_match");
+    if (all) {
+        c3x_status st = finish_huge(fa, hctr + 6, s);
+        if (st != C3X_OK) return st;
+        if (hctr[7]) {
+            HIPCHK(hipMemcpyAsync(hctr + 4, ctr + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                   "copy");
+            HIPCHK(hipStreamSynchronize(s), "c3x_match");
+        }
+    }
     if (hctr[4]) return fail(C3X_EDEVICE, "internal: count and write passes disagree (flags %u)",
                              hctr[4]);
+    if (all && emitted && h64[2] != (unsigned long long)P)
+        return fail(C3X_EDEVICE, "internal: %llu of %lld matches placed", h64[2], (long long)P);
     c3x_stats &S = R->stats;
     S.n_a = nA;
     S.n_b = ix->nB;

@@ -291,3 +291,29 @@ def test_long_segments(c3x, dev, precision):
     seg = np.bincount(o.ia, minlength=cat.nA)
     assert seg.max() > 2048 and ((seg > 64) & (seg <= 2048)).any()
     assert_parity(gpu_match(c3x, dev, cat, precision), o)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("chunks", ["0", "5"])
+def test_write_pass_fallback(c3x, dev, cfg2_small, cfg2_small_oracle, precision, chunks,
+                             monkeypatch):
+    """With no room (0 chunks) or too little room (5 chunks of 64) for the
+    single pass to emit its matches, the count stands and the second pass
+    writes them: the result is the same."""
+    monkeypatch.setenv("C3X_DEBUG_EMIT_CHUNKS", chunks)
+    assert_parity(gpu_match(c3x, dev, cfg2_small, precision), cfg2_small_oracle)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dense_emission(c3x, dev, precision):
+    """Sources with 0 to about a dozen matches each inside one dense patch
+    (about two per source, close to the emission's sizing), so that most
+    wavefronts fill several emission chunks and chunks split mid-step."""
+    g = np.random.default_rng(12)
+    rb, db = synth.cap_uniform(g, 200_000, 300.0, 45.0, 0.2)
+    ra, da = synth.cap_uniform(g, 30_000, 300.0, 45.0, 0.22)
+    cat = synth.Catalogues("dense_emission", ra, da, rb, db, radius_arcsec=2.2)
+    o = oracle_match(cat)
+    seg = np.bincount(o.ia, minlength=cat.nA)
+    assert seg.max() >= 8 and 1.5 * cat.nA < len(o.ia) < 2 * cat.nA
+    assert_parity(gpu_match(c3x, dev, cat, precision), o)
