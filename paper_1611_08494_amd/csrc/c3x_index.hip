@@ -199,15 +199,14 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
     radec[s] = rd;
     double x, y, z;
     unit_vec(a, d, x, y, z);
-    if (PREC == C3X_FP64) {
-        Pay64 q;
-        q.x = x;
-        q.y = y;
-        q.z = z;
-        q.idx = row;
-        q.pad = 0;
-        p64[s] = q;
-    } else {
+    Pay64 q8;
+    q8.x = x;
+    q8.y = y;
+    q8.z = z;
+    q8.idx = row;
+    q8.pad = 0;
+    p64[s] = q8;
+    if (PREC == C3X_MIXED) {
         int zz = zone_of(d, g);
         uint32_t c = cell_of(zz, a, g);
         double rx, ry, rz;
@@ -322,13 +321,15 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     double2 *radec = ix->mem.get_n<double2>(n);
     Pay64 *p64 = nullptr;
     Pay32 *p32 = nullptr;
-    if (o.precision == C3X_FP64) p64 = ix->mem.get_n<Pay64>(n);
-    else p32 = ix->mem.get_n<Pay32>(n);
+    // FP64 unit vectors for both paths (the mixed path's matches take their
+    // separation from them), FP32 offsets for the mixed filter
+    p64 = ix->mem.get_n<Pay64>(n);
+    if (o.precision == C3X_MIXED) p32 = ix->mem.get_n<Pay32>(n);
     uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
     uint32_t *dcnt = tmp.get_n<uint32_t>(ix->plan.dsize);
     void *dws = tmp.get(scan_ws_bytes(ix->plan.dsize));
     if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !radec || !dir || !dcnt || !dws ||
-        (!p64 && !p32)) {
+        !p64 || (o.precision == C3X_MIXED && !p32)) {
         (void)hipStreamSynchronize(s);
         delete ix;
         return fail(C3X_ENOMEM, "index buffers");

@@ -88,19 +88,27 @@ struct alignas(16) PairTmp {
     double sep;
 };
 
-// A match as the single-pass kernel emits it, in enumeration order: the
-// k-th match of the A source at sorted position i. Chunks of 64 entries,
-// allocated per wavefront.
+// A band candidate found inside, listed as the k-th match of the A source
+// at sorted position i.
 struct alignas(16) WEnt {
     uint32_t i, k, idxB, j;
 };
-constexpr int kEmitPools = 64;       // chunk allocation counters (spread contention)
+// A match beyond a row's table slots: the k-th match of A row idxA, with
+// its coded separation (see sep_code).
+struct alignas(8) OvEnt {
+    uint32_t idxA, k, idxB, j;
+    double code;
+};
+constexpr int kTab = 2;              // table slots per A row
+constexpr int kEmitPools = 64;       // overflow-list counters (spread contention)
 constexpr int kEmitPoolStride = 32;  // u32 words between two counters (128 B)
 
 // Per-A counters of the count pass (idxA order).
-struct AStat {
-    uint32_t cnt;          // matches
+struct alignas(16) AStat {
+    uint32_t cnt;          // matches (filter + band)
+    uint32_t nf;           // matches decided by the filter
     uint32_t best_j;       // sorted B position of the best match
+    uint32_t pad;
 };
 
 // Everything a match kernel needs; passed by value.
@@ -138,13 +146,14 @@ struct MatchArgs {
     // write pass
     const int64_t *off;    // [nA + 1] idxA order
     PairTmp *tmp;          // matches in enumeration order
-    // single pass (count + emit): chunked match list
-    WEnt *went;            // [w_nch * 64]
-    double *wsep;          // [w_nch * 64] squared chords (FP64 path) or null
-    uint32_t *wvc;         // [w_nch] valid entries of each allocated chunk
-    uint32_t *wctr;        // [kEmitPools * kEmitPoolStride] chunks taken per pool
-    uint32_t w_nch;        // chunk capacity
-    uint32_t *w_ovf;       // set when the capacity ran out
+    // count + emit (MODE 2): a row's first kTab matches go to its table
+    // slots (idxA-major), later ones to the overflow list
+    PairTmp *table;        // [nA * kTab]
+    OvEnt *ovl;            // kEmitPools regions of ov_pool entries
+    uint32_t *octr;        // [kEmitPools * kEmitPoolStride] entries taken per region
+    uint32_t ov_pool;      // entries per region
+    uint32_t *ov_flag;     // set when a region ran out
+    unsigned long long *n_placed;  // matches written (table, list or segments)
     // collect pass: sorted A positions; every match of each is listed
     const uint32_t *col_pos;
     uint32_t n_col;

@@ -304,8 +304,24 @@ __device__ __forceinline__ uint32_t lds_lower_bound(const uint32_t *k, uint32_t 
 
 // ---------------------------------------------------------------------------- count / write
 
-// MODE 0: count + best; MODE 1: write (into offsets from the count);
-// MODE 2: count + best + every match emitted in enumeration order.
+// A match's separation as the match passes leave it, without trigonometry:
+// from the FP64 chord c < 1.38 the code -c^2 (the separation is 2 asin(c / 2),
+// error ~1e-14 rad), 0 for c = 0, otherwise NaN (computed later from the
+// coordinates).
+__device__ __forceinline__ double sep_code(double c2)
+{
+    if (c2 < 1.9) return c2 > 0.0 ? -c2 : 0.0;
+    return NAN;
+}
+
+__device__ __forceinline__ double sep_from_chord2(double c2)
+{
+    return 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0);
+}
+
+// MODE 0: count + best; MODE 1: write every filter match into the
+// offsets from the count; MODE 2: count + best, each filter match written
+// to its row's table slot (the first kTab) or to the overflow list.
 template <int SHAPE, int PREC, int MODE>
 __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 {
@@ -313,15 +329,11 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     constexpr int kStage = PREC == C3X_FP64 ? 192 : 256;  // B staged per wavefront
     __shared__ uint32_t s_key[kWavesPerBlock][kStage];
     __shared__ PayT s_pay[kWavesPerBlock][kStage];
-    __shared__ unsigned long long s_tests, s_band;
-    __shared__ uint32_t s_wch[kWavesPerBlock], s_wfill[kWavesPerBlock];  // emission state
+    __shared__ unsigned long long s_tests, s_band, s_placed;
     if (threadIdx.x == 0) {
         s_tests = 0;
         s_band = 0;
-    }
-    if (threadIdx.x < kWavesPerBlock) {
-        s_wch[threadIdx.x] = 0xffffffffu;  // no chunk yet
-        s_wfill[threadIdx.x] = 64;
+        s_placed = 0;
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -359,52 +371,55 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     int64_t o = 0, oe = 0;
     if (MODE == 1 && active) {
         o = m.off[a.idx];
-        oe = m.off[a.idx + 1];
+        oe = o + m.astat[a.idx].nf;  // band matches are placed separately
     }
-    unsigned long long tests = 0, band = 0;
+    unsigned long long tests = 0, band = 0, placed = 0;
     CellCache cc{0xffffffffu, 0.f, 0.f, 0.f};
 
-    // Appends one match per calling lane to the wavefront's current chunk
-    // (MODE 2). Called by exactly the lanes that have a match, possibly
-    // inside divergent loops: the chunk and its fill level live in LDS and
-    // the lowest calling lane updates them; a chunk that fills up is closed
-    // and a new one is taken from the block's pool with one atomic.
-    auto emit = [&](uint32_t k, uint32_t idxB, uint32_t j, double c2) {
+    // A filter match as written: the separation coded from the FP64 chord
+    // (the FP64 path's filter chord; the mixed path recomputes it from the
+    // FP64 unit vectors).
+    auto coded = [&](const PayT &b, uint32_t j, double c2) -> PairTmp {
+        double c64 = c2;
+        if constexpr (PREC != C3X_FP64) {
+            const Pay64 b8 = m.pay64[j];
+            const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
+            c64 = fma(dx, dx, fma(dy, dy, dz * dz));
+        }
+        PairTmp t;
+        t.idxB = b.idx;
+        t.j = j;
+        t.sep = sep_code(c64);
+        return t;
+    };
+
+    // The k-th filter match of this lane's row beyond its table slots:
+    // appended to the block's region of the overflow list, one atomic per
+    // group of lanes calling together (possibly inside divergent loops).
+    auto overflow = [&](uint32_t k, const PairTmp &t) {
         const unsigned long long hm = __ballot(1);
-        const uint32_t n = (uint32_t)__popcll(hm);
         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-        const bool first = r == 0;
-        wave_sync();
-        const uint32_t ch = s_wch[wave], fill = s_wfill[wave];
-        const bool spill = fill + n > 64;
-        uint32_t nch = ch;
-        if (spill) {
-            uint32_t v = 0;
-            if (first) {
-                const uint32_t pool = blockIdx.x & (kEmitPools - 1);
-                v = pool + kEmitPools * atomicAdd(m.wctr + pool * kEmitPoolStride, 1u);
-                if (v >= m.w_nch) atomicOr(m.w_ovf, 1u);
-                if (ch < m.w_nch) m.wvc[ch] = 64;  // the old chunk is now full
-            }
-            nch = (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+        const uint32_t pool = blockIdx.x & (kEmitPools - 1);
+        uint32_t base = 0;
+        if (r == 0) base = atomicAdd(m.octr + pool * kEmitPoolStride, (uint32_t)__popcll(hm));
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+        const uint32_t slot = base + r;
+        if (slot < m.ov_pool) {
+            OvEnt v;
+            v.idxA = a.idx;
+            v.k = k;
+            v.idxB = t.idxB;
+            v.j = t.j;
+            v.code = t.sep;
+            m.ovl[(size_t)pool * m.ov_pool + slot] = v;
+        } else {
+            atomicOr(m.ov_flag, 1u);
         }
-        const uint32_t q = fill + r;
-        const uint32_t c = q < 64 ? ch : nch;
-        if (c < m.w_nch) {
-            const size_t p = (size_t)c * 64 + (q < 64 ? q : q - 64);
-            m.went[p] = WEnt{i, k, idxB, j};
-            if constexpr (PREC == C3X_FP64) m.wsep[p] = c2;
-        }
-        if (first) {
-            s_wch[wave] = spill ? nch : ch;
-            s_wfill[wave] = spill ? fill + n - 64 : fill + n;
-        }
-        wave_sync();
     };
 
     // One candidate: decide it, then count / rank it (MODE 0), write it
-    // (MODE 1), or both (MODE 2).
+    // (MODE 1), or both (MODE 2). Band candidates are only listed.
     auto visit = [&](int z, uint32_t key, const PayT &b, uint32_t j) {
         ++tests;
         double c2;
@@ -414,14 +429,20 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                 ++band;
                 uint32_t slot = atomicAdd(m.amb_n, 1u);
                 if (slot < m.amb_cap) m.amb[slot] = make_uint2(i, j);
-                d = OUT;
-            } else {
-                d = verdict(m, i, j);
             }
+            return;
         }
         if (d != IN) return;
+        if (MODE == 2) {
+            const PairTmp t = coded(b, j, c2);
+            if (cnt < (uint32_t)kTab) {
+                m.table[(size_t)a.idx * kTab + cnt] = t;
+                ++placed;
+            } else {
+                overflow(cnt, t);
+            }
+        }
         if (MODE != 1) {
-            if (MODE == 2) emit(cnt, b.idx, j, c2);  // FP64: the chord goes with the match
             ++cnt;
             if (c2 < b1 || (c2 == b1 && b.idx < bidx)) {
                 b2 = b1;
@@ -434,16 +455,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         } else {
             int64_t p = o + cnt;
             if (p < oe) {
-                // FP64: theta = 2 asin(c / 2) from the filter's chord (error
-                // ~1e-14 rad); mixed: computed by the finalize kernel
-                double sp = NAN;
-                if (PREC == C3X_FP64 && c2 < 1.9)
-                    sp = 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0);
-                PairTmp t;
-                t.idxB = b.idx;
-                t.j = j;
-                t.sep = sp;
-                m.tmp[p] = t;
+                m.tmp[p] = coded(b, j, c2);
+                ++placed;
             } else {
                 atomicOr(m.err_flag, 1u);
             }
@@ -605,7 +618,9 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         if (MODE != 1) {
             AStat st;
             st.cnt = cnt;
+            st.nf = cnt;
             st.best_j = bj;
+            st.pad = 0;
             m.astat[a.idx] = st;
             m.best_idx[a.idx] = cnt ? (int32_t)bidx : -1;
             if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), m.L_rad)) {
@@ -616,16 +631,14 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             if (o + cnt != oe) atomicOr(m.err_flag, 2u);
         }
     }
-    if (MODE == 2) {  // close the wavefront's last chunk
-        wave_sync();
-        if (lane == 0 && s_wch[wave] < m.w_nch) m.wvc[s_wch[wave]] = s_wfill[wave];
-    }
+    if (placed) atomicAdd(&s_placed, placed);
     if (tests) atomicAdd(&s_tests, tests);
     if (band) atomicAdd(&s_band, band);
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (s_tests) atomicAdd(m.n_tests, s_tests);
-        if (s_band) atomicAdd(m.n_band, s_band);
+        if (s_tests && MODE != 1) atomicAdd(m.n_tests, s_tests);
+        if (s_band && MODE != 1) atomicAdd(m.n_band, s_band);
+        if (s_placed) atomicAdd(m.n_placed, s_placed);
     }
 }
 
@@ -745,79 +758,73 @@ __global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, AStat *st,
     if (out) out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
-// Moves an emitted match, with its separation, to its place in the
-// idxA-order segments. The separation is computed here, in enumeration
-// order, where the A and B records read are neighbours in the sky order:
-// from the filter's squared chord on the FP64 path (theta = 2 asin(c / 2),
-// error ~1e-14 rad), else from the coordinates.
-__device__ __forceinline__ bool place_one(const WEnt &e, const double *c2p,
-                                          const uint32_t *__restrict__ aidx,
-                                          const double2 *__restrict__ arad,
-                                          const double2 *__restrict__ radecB, int64_t nA,
-                                          int64_t nB, const int64_t *__restrict__ off, int64_t P,
-                                          PairTmp *__restrict__ tmp, uint32_t *__restrict__ err)
+// Separation from the coordinates, out of line: only the rare paths (band
+// matches, separations the write pass leaves undefined) need it.
+__device__ __noinline__ double sep_rare(double ra1, double dec1, double ra2, double dec2)
 {
+    return sep_arcsec_rd(ra1, dec1, ra2, dec2);
+}
+
+// One thread per used slot of overflow region blockIdx.y: the k-th match of
+// row idxA to offset off[idxA] + k of the segments.
+__global__ void k_place_ov(const OvEnt *__restrict__ ovl, uint32_t ov_pool,
+                           const uint32_t *__restrict__ octr, int64_t nA,
+                           const int64_t *__restrict__ off, int64_t P, PairTmp *__restrict__ tmp,
+                           unsigned long long *__restrict__ placed, uint32_t *__restrict__ err)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= min(octr[blockIdx.y * kEmitPoolStride], ov_pool)) return;
+    const OvEnt v = ovl[(size_t)blockIdx.y * ov_pool + t];
+    if (v.idxA >= (uint64_t)nA) {
+        atomicOr(err, 16u);
+        return;
+    }
+    const int64_t o = off[v.idxA], oe = off[v.idxA + 1];
+    const int64_t p = o + v.k;
+    if (v.k < (uint32_t)kTab || p >= oe || oe > P) {
+        atomicOr(err, 1u);
+        return;
+    }
+    PairTmp x;
+    x.idxB = v.idxB;
+    x.j = v.j;
+    x.sep = v.code;
+    tmp[p] = x;
+    atomicAdd(placed, 1ull);
+}
+
+// One thread per band match found inside: to its row's table slot (k <
+// kTab, when the single pass filled the table) or its place in the
+// idxA-order segments, with its separation.
+__global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
+                          const uint32_t *__restrict__ aidx, const double2 *__restrict__ arad,
+                          const double2 *__restrict__ radecB, int64_t nA, int64_t nB,
+                          const int64_t *__restrict__ off, int64_t P, PairTmp *__restrict__ table,
+                          PairTmp *__restrict__ tmp, unsigned long long *__restrict__ placed,
+                          uint32_t *__restrict__ err)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nx) return;
+    const WEnt e = xent[t];
     if (e.i >= (uint64_t)nA || e.j >= (uint64_t)nB) {
         atomicOr(err, 16u);
-        return false;
+        return;
     }
     const uint32_t a = aidx[e.i];
     const int64_t o = off[a], oe = off[a + 1];
     const int64_t p = o + e.k;
     if (p >= oe || oe > P) {
         atomicOr(err, 1u);
-        return false;
+        return;
     }
-    double sep;
-    if (c2p) {
-        const double c2 = *c2p;
-        sep = c2 < 1.9 ? 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0) : (double)NAN;
-    } else {
-        sep = NAN;
-    }
-    if (isnan(sep)) {
-        const double2 ra = arad[e.i], rb = radecB[e.j];
-        sep = sep_arcsec_rd(ra.x, ra.y, rb.x, rb.y);
-    }
-    PairTmp t;
-    t.idxB = e.idxB;
-    t.j = e.j;
-    t.sep = sep;
-    tmp[p] = t;
-    return true;
-}
-
-// One thread per slot of the allocated chunks (pool p's chunks are
-// p, p + kEmitPools, ...), then one per extra (band) entry.
-__global__ __launch_bounds__(256) void k_place(const WEnt *__restrict__ went,
-                                               const double *__restrict__ wsep,
-                                               const uint32_t *__restrict__ wvc,
-                                               const uint32_t *__restrict__ wctr, uint64_t nslot,
-                                               const WEnt *__restrict__ xent, uint32_t nx,
-                                               const uint32_t *__restrict__ aidx,
-                                               const double2 *__restrict__ arad,
-                                               const double2 *__restrict__ radecB, int64_t nA,
-                                               int64_t nB, const int64_t *__restrict__ off, int64_t P,
-                                               PairTmp *__restrict__ tmp,
-                                               unsigned long long *__restrict__ placed,
-                                               uint32_t *__restrict__ err)
-{
-    __shared__ uint32_t s_n;
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool ok = false;
-    if (t < nslot) {
-        const uint64_t c = t >> 6;
-        if (c / kEmitPools < wctr[(c % kEmitPools) * kEmitPoolStride] && (t & 63) < wvc[c])
-            ok = place_one(went[t], wsep ? wsep + t : nullptr, aidx, arad, radecB, nA, nB, off, P,
-                           tmp, err);
-    } else if (t - nslot < nx) {
-        ok = place_one(xent[t - nslot], nullptr, aidx, arad, radecB, nA, nB, off, P, tmp, err);
-    }
-    if (ok) atomicAdd(&s_n, 1u);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_n) atomicAdd(placed, (unsigned long long)s_n);
+    const double2 ra = arad[e.i], rb = radecB[e.j];
+    PairTmp x;
+    x.idxB = e.idxB;
+    x.j = e.j;
+    x.sep = sep_rare(ra.x, ra.y, rb.x, rb.y);
+    if (table && e.k < (uint32_t)kTab) table[(size_t)a * kTab + e.k] = x;
+    else tmp[p] = x;
+    atomicAdd(placed, 1ull);
 }
 
 __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
@@ -853,13 +860,15 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
                                             uint32_t *__restrict__ err)
 {
     double s = x.sep;
-    if (isnan(s)) {
+    if (s < 0.0) {  // coded by the write pass (see sep_code)
+        s = sep_from_chord2(-s);
+    } else if (isnan(s)) {
         if (x.j >= (uint64_t)nB) {
             atomicOr(err, 16u);
             return;
         }
         double2 rb = radecB[x.j];
-        s = sep_arcsec_rd(raA[a], decA[a], rb.x, rb.y);
+        s = sep_rare(raA[a], decA[a], rb.x, rb.y);
     }
     oa[q] = (int32_t)a;
     ob[q] = (int32_t)x.idxB;
@@ -867,24 +876,38 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
     if (bidx[a] == (int32_t)x.idxB) bsep[a] = s;
 }
 
-// One thread per A row whose segment is short (<= kShortSeg): the canonical
-// position of each match is its rank by idxB inside the segment (idxB is
-// unique there). Longer segments are finished by k_seg_lds.
+// One thread per A row. A row's k-th match is in its table slot for k <
+// kTab (when the single pass filled the table) and at offset off + k of its
+// segment otherwise. A short segment (<= kShortSeg) is finished here: the
+// canonical position of each match is its rank by idxB (unique in a
+// segment). A longer one has its table slots copied into the segment, which
+// k_seg_lds then finishes.
 __global__ void k_finalize(int64_t nA, int64_t nB, const int64_t *__restrict__ off,
-                           const PairTmp *__restrict__ tmp, const double *__restrict__ raA,
-                           const double *__restrict__ decA, const double2 *__restrict__ radecB,
-                           const int32_t *__restrict__ bidx, int32_t *__restrict__ oa,
-                           int32_t *__restrict__ ob, double *__restrict__ os,
-                           double *__restrict__ bsep, uint32_t *__restrict__ err)
+                           const PairTmp *__restrict__ table, PairTmp *__restrict__ tmp,
+                           const double *__restrict__ raA, const double *__restrict__ decA,
+                           const double2 *__restrict__ radecB, const int32_t *__restrict__ bidx,
+                           int32_t *__restrict__ oa, int32_t *__restrict__ ob,
+                           double *__restrict__ os, double *__restrict__ bsep,
+                           uint32_t *__restrict__ err)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nA) return;
-    const int64_t o = off[a], e = off[a + 1];
-    if (e - o > kShortSeg || e <= o) return;
-    for (int64_t q = o; q < e; ++q) {
-        const PairTmp x = tmp[q];
-        int64_t r = 0;
-        for (int64_t y = o; y < e; ++y) r += tmp[y].idxB < x.idxB;
+    const int64_t o = off[a], len = off[a + 1] - o;
+    if (len <= 0) return;
+    const int nt = table ? (int)min<int64_t>(len, kTab) : 0;
+    const PairTmp *row = table + (table ? a * kTab : 0);
+    if (len > kShortSeg) {
+        for (int q = 0; q < nt; ++q) tmp[o + q] = row[q];
+        return;
+    }
+    if (len == 1) {
+        final_write(o, a, nt ? row[0] : tmp[o], nB, raA, decA, radecB, bidx, oa, ob, os, bsep, err);
+        return;
+    }
+    for (int q = 0; q < len; ++q) {
+        const PairTmp x = q < nt ? row[q] : tmp[o + q];
+        int r = 0;
+        for (int y = 0; y < len; ++y) r += (y < nt ? row[y].idxB : tmp[o + y].idxB) < x.idxB;
         final_write(o + r, a, x, nB, raA, decA, radecB, bidx, oa, ob, os, bsep, err);
     }
 }
@@ -1033,6 +1056,7 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 struct FinishArgs {
     int64_t nA, nB;
     const int64_t *off;
+    const PairTmp *table;
     PairTmp *tmp;
     const double *raA, *decA;
     const double2 *radecB;
@@ -1052,8 +1076,9 @@ constexpr unsigned kSegGrid = 1024;
 static void finish_segments(const FinishArgs &f, hipStream_t s)
 {
     if (f.nA == 0) return;
-    hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.off, f.tmp,
-                       f.raA, f.decA, f.radecB, f.bidx, f.oa, f.ob, f.os, f.bsep, f.err);
+    hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.off,
+                       f.table, f.tmp, f.raA, f.decA, f.radecB, f.bidx, f.oa, f.ob, f.os, f.bsep,
+                       f.err);
     hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA, f.seg_n,
                        f.list, f.cap);
     hipLaunchKernelGGL(k_seg_lds, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list, f.cap,
@@ -1283,30 +1308,33 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.tie_n = ctr + 2;
     m.tie = tie;
     m.tie_cap = tie_cap;
-    // All matches: one pass counts and also emits every match into chunks
-    // sized for two matches per A source plus one partly filled chunk per
-    // wavefront; if that runs out, the count stands and a second pass over
-    // the same tiles writes the matches into the offsets.
+    // All matches: the pass that counts also writes them -- a row's first
+    // kTab matches into its table slots, later ones into the overflow list
+    // (kEmitPools regions; block b uses region b mod kEmitPools). If a
+    // region runs out, the count stands and the write pass puts every
+    // match into the offsets instead.
+    m.n_placed = c64 + 2;
+    m.ov_flag = ctr + 5;
     bool emit = false;
     const int kPoolWords = kEmitPools * kEmitPoolStride;
-    uint32_t hwctr[kPoolWords];
     if (all && nA > 0) {
-        uint64_t nch = (uint64_t)((2 * nA + 63) / 64) + (uint64_t)grid * kWavesPerBlock + kEmitPools;
-        // test hook: C3X_DEBUG_EMIT_CHUNKS=k caps the chunks (k = 0: no emission)
-        if (const char *ev = getenv("C3X_DEBUG_EMIT_CHUNKS")) nch = std::min<uint64_t>(nch, atoll(ev));
-        if (nch > 0 && nch < (1ull << 31)) {
-            m.went = (WEnt *)tmp.get(nch * 64 * sizeof(WEnt));
-            m.wsep = prec == C3X_FP64 ? tmp.get_n<double>(nch * 64) : nullptr;
-            m.wvc = tmp.get_n<uint32_t>(nch);
-            m.wctr = tmp.get_n<uint32_t>(kPoolWords);
-            m.w_nch = (uint32_t)nch;
-            m.w_ovf = ctr + 5;
-            emit = m.went && m.wvc && m.wctr && (prec != C3X_FP64 || m.wsep);
-            if (emit) HIPCHK(hipMemsetAsync(m.wctr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
+        uint64_t per = (uint64_t)std::max<int64_t>(nA / 8 / kEmitPools, 4096);
+        // test hook: C3X_DEBUG_OVERFLOW_SLOTS=k gives each region k slots (0: no table)
+        if (const char *ev = getenv("C3X_DEBUG_OVERFLOW_SLOTS"))
+            per = (uint64_t)std::max<long long>(atoll(ev), -1);
+        const bool no_table = getenv("C3X_DEBUG_OVERFLOW_SLOTS") && per == 0;
+        if (!no_table && per < (1ull << 26)) {
+            m.table = tmp.get_n<PairTmp>((size_t)nA * kTab);
+            m.ovl = tmp.get_n<OvEnt>(per * kEmitPools);
+            m.octr = tmp.get_n<uint32_t>(kPoolWords);
+            m.ov_pool = (uint32_t)per;
+            emit = m.table && m.ovl && m.octr;
+            if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
         }
     }
     uint32_t hctr[8];
     unsigned long long h64[3];
+    std::vector<uint32_t> hoctr(kPoolWords);
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (emit) launch_match<2>(m, shape, prec, grid, s);
         else launch_match<0>(m, shape, prec, grid, s);
@@ -1314,7 +1342,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipMemcpyAsync(h64, c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
         if (emit)
-            HIPCHK(hipMemcpyAsync(hwctr, m.wctr, sizeof(hwctr), hipMemcpyDeviceToHost, s), "copy");
+            HIPCHK(hipMemcpyAsync(hoctr.data(), m.octr, kPoolWords * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipStreamSynchronize(s), "count pass");
         if (hctr[0] != 0xffffffffu)
             return fail(C3X_EINVAL,
@@ -1339,17 +1368,19 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         m.tie_cap = tie_cap;
         HIPCHK(hipMemsetAsync(ctr + 1, 0, 2 * sizeof(uint32_t), s), "memset");
         HIPCHK(hipMemsetAsync(ctr + 5, 0, sizeof(uint32_t), s), "memset");
-        HIPCHK(hipMemsetAsync(c64, 0, 2 * sizeof(unsigned long long), s), "memset");
-        if (emit) HIPCHK(hipMemsetAsync(m.wctr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
+        HIPCHK(hipMemsetAsync(c64, 0, 3 * sizeof(unsigned long long), s), "memset");
+        if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
     }
-    // emitted chunk slots to place (0 when the emission ran out of room)
-    uint64_t n_slot = 0;
-    if (emit && hctr[5] == 0) {
-        uint32_t mo = 0;
-        for (int q = 0; q < kEmitPools; ++q) mo = std::max(mo, hwctr[q * kEmitPoolStride]);
-        n_slot = (uint64_t)mo * kEmitPools * 64;
-    }
+    // the table and list hold every filter match unless a region ran out
     const bool emitted = emit && hctr[5] == 0;
+    uint32_t ov_used = 0;
+    if (emitted)
+        for (int q = 0; q < kEmitPools; ++q)
+            ov_used = std::max(ov_used, std::min(hoctr[q * kEmitPoolStride], m.ov_pool));
+    if (!emitted) {
+        m.table = nullptr;
+        HIPCHK(hipMemsetAsync(c64 + 2, 0, sizeof(unsigned long long), s), "memset");
+    }
     uint32_t n_amb = hctr[1], n_tie = hctr[2];
     R->stats.n_tests = (int64_t)h64[0];
     R->stats.n_band = (int64_t)h64[1];
@@ -1358,7 +1389,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     // ---- band candidates: FP64 recheck on the GPU, the rest in binary128 on the host
     std::vector<uint32_t> recheck_pos;  // sorted A positions whose best must be re-ranked
     uint32_t n_host = 0;
-    WEnt *xent = nullptr;  // band matches found inside (emitted path)
+    WEnt *xent = nullptr;  // band matches found inside (all-matches mode)
     uint32_t n_x = 0;
     if (n_amb > 0) {
         AmbInfo *dinfo = tmp.get_n<AmbInfo>(n_amb);
@@ -1408,7 +1439,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         uint8_t *dvi = tmp.get_n<uint8_t>(n_amb);
         uint4 *dadd = tmp.get_n<uint4>(add.size());
         if (!dvk || !dvi || !dadd) return fail(C3X_ENOMEM, "verdict table");
-        if (emitted && !add.empty()) {
+        if (all && !add.empty()) {
             xent = tmp.get_n<WEnt>(add.size());
             if (!xent) return fail(C3X_ENOMEM, "verdict table");
             n_x = (uint32_t)add.size();
@@ -1538,27 +1569,29 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
 
     FinishArgs fa{};
     if (all) {
-        // ---- emitted matches to their segments, or the write pass
+        // ---- overflow list and band matches to their places, or the write pass
         PairTmp *pt = tmp.get_n<PairTmp>(P);
         if (!pt) return fail(C3X_ENOMEM, "pair buffer (%lld pairs)", (long long)P);
         if (emitted) {
-            uint64_t nt = n_slot + n_x;
-            if (nt > 0)
-                hipLaunchKernelGGL(k_place, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
-                                   m.went, m.wsep, m.wvc, m.wctr, n_slot, xent, n_x, aidx, arad,
-                                   ix->radec, nA, ix->nB, off, P, pt, c64 + 2, ctr + 4);
-            HIPCHK(hipGetLastError(), "place");
+            if (ov_used > 0)
+                hipLaunchKernelGGL(k_place_ov, dim3(nblk(ov_used, 256), kEmitPools), dim3(256), 0,
+                                   s, m.ovl, m.ov_pool, m.octr, nA, off, P, pt, c64 + 2, ctr + 4);
         } else {
             m.off = off;
             m.tmp = pt;
             launch_match<1>(m, shape, prec, grid, s);
-            HIPCHK(hipGetLastError(), "write pass");
         }
+        HIPCHK(hipGetLastError(), "write pass");
+        if (n_x > 0)
+            hipLaunchKernelGGL(k_place_x, dim3(nblk(n_x, 256)), dim3(256), 0, s, xent, n_x, aidx,
+                               arad, ix->radec, nA, ix->nB, off, P, m.table, pt, c64 + 2, ctr + 4);
+        HIPCHK(hipGetLastError(), "band matches");
         tm.mark();  // 4
         // ---- canonical order inside each segment, final records
         fa.nA = nA;
         fa.nB = ix->nB;
         fa.off = off;
+        fa.table = m.table;
         fa.tmp = pt;
         fa.raA = ra;
         fa.decA = dec;
@@ -1601,7 +1634,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     }
     if (hctr[4]) return fail(C3X_EDEVICE, "internal: count and write passes disagree (flags %u)",
                              hctr[4]);
-    if (all && emitted && h64[2] != (unsigned long long)P)
+    if (all && h64[2] != (unsigned long long)P)
         return fail(C3X_EDEVICE, "internal: %llu of %lld matches placed", h64[2], (long long)P);
     c3x_stats &S = R->stats;
     S.n_a = nA;

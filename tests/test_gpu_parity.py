@@ -294,21 +294,22 @@ def test_long_segments(c3x, dev, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("chunks", ["0", "5"])
-def test_write_pass_fallback(c3x, dev, cfg2_small, cfg2_small_oracle, precision, chunks,
+@pytest.mark.parametrize("slots", ["0", "1", "100000"])
+def test_write_pass_fallback(c3x, dev, cfg2_small, cfg2_small_oracle, precision, slots,
                              monkeypatch):
-    """With no room (0 chunks) or too little room (5 chunks of 64) for the
-    single pass to emit its matches, the count stands and the second pass
-    writes them: the result is the same."""
-    monkeypatch.setenv("C3X_DEBUG_EMIT_CHUNKS", chunks)
+    """Without the table (0), with overflow regions too small for the
+    matches beyond a row's table slots (1 slot each), and with ample ones:
+    when the single pass cannot keep every match the count stands and the
+    write pass puts them in place. The result is the same."""
+    monkeypatch.setenv("C3X_DEBUG_OVERFLOW_SLOTS", slots)
     assert_parity(gpu_match(c3x, dev, cfg2_small, precision), cfg2_small_oracle)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_dense_emission(c3x, dev, precision):
     """Sources with 0 to about a dozen matches each inside one dense patch
-    (about two per source, close to the emission's sizing), so that most
-    wavefronts fill several emission chunks and chunks split mid-step."""
+    (about 1.5 per source): many rows fill their table slots and spill into
+    the overflow list."""
     g = np.random.default_rng(12)
     rb, db = synth.cap_uniform(g, 200_000, 300.0, 45.0, 0.2)
     ra, da = synth.cap_uniform(g, 30_000, 300.0, 45.0, 0.22)
