@@ -34,7 +34,7 @@ static void build_zones(ZoneTables &p, double cell_arcsec)
     p.cell_arcsec = cell_arcsec;
     p.h_deg = cell_arcsec / 3600.0;
     p.nz = (int32_t)std::max(1.0, ceil(180.0 / p.h_deg));
-    p.zinfo.assign(p.nz, ZoneInfo{0, 1, 0.0});
+    p.zinfo.assign(p.nz, ZoneInfo{0, 1, 0.0, 0.0, 0.0});
     p.zref.assign(p.nz, make_double2(0.0, 0.0));
     uint64_t tot = 0;
     double L = 0.0;
@@ -49,12 +49,13 @@ static void build_zones(ZoneTables &p, double cell_arcsec)
         p.zinfo[z].base = (uint32_t)std::min<uint64_t>(tot, 0xffffffffull);
         p.zinfo[z].n = n;
         p.zinfo[z].f = (double)n / 360.0;
+        p.zinfo[z].g = ldexp(1.0, kRefBits) / (double)n;
         tot += n;
         double dc = std::max(-90.0, std::min(90.0, 0.5 * (lo + hi)));
         p.zref[z] = make_double2(cos(dc * kDeg), sin(dc * kDeg));
-        // largest distance from a point of a cell to the cell's reference:
-        // RA half-cell + half a reference-grid step (+1e-6 rad of slack for
-        // the FP32 sine/cosine of the grid point)
+        // largest distance from a point of a cell to its reference: RA
+        // half-cell + half a reference-grid step (+1e-6 rad of slack for the
+        // FP32 sine/cosine of the grid point)
         double ddec = std::max(hi - dc, dc - lo);
         double dra = (180.0 / n + 180.0 / (1 << kRefBits)) * ceq + 1e-6 / kDeg;
         double ang = sqrt(ddec * ddec + dra * dra) * kDeg;
@@ -210,7 +211,7 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
         int zz = zone_of(d, g);
         uint32_t c = cell_of(zz, a, g);
         double rx, ry, rz;
-        cell_ref(zz, c, g, rx, ry, rz);
+        ref_vec(zz, ref_step(g.zinfo[zz], c), g, rx, ry, rz);
         Pay32 q;
         q.x = (float)(x - rx);
         q.y = (float)(y - ry);

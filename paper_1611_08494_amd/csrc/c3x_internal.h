@@ -25,7 +25,7 @@ constexpr double kU = 1.1102230246251565e-16;   // 2^-53
 constexpr double kU32 = 5.9604644775390625e-08; // 2^-24
 constexpr double kE40 = 9.094947017729282e-13;  // 2^-40
 constexpr double kE38 = 3.637978807091713e-12;  // 2^-38
-constexpr int kRefBits = 16;                     // RA reference grid, 2^16 points
+constexpr int kRefBits = 10;                     // RA reference grid, 2^10 points
 
 enum Decision : int { OUT = 0, IN = 1, AMBIG = 2 };
 
@@ -33,6 +33,8 @@ enum Decision : int { OUT = 0, IN = 1, AMBIG = 2 };
 struct alignas(16) ZoneInfo {
     uint32_t base, n;
     double f;              // n / 360
+    double g;              // 2^kRefBits / n
+    double pad;
 };
 
 // Grid of declination zones split into RA cells (the paper's cells,
@@ -103,13 +105,28 @@ constexpr int kTab = 2;              // table slots per A row
 constexpr int kEmitPools = 64;       // overflow-list counters (spread contention)
 constexpr int kEmitPoolStride = 32;  // u32 words between two counters (128 B)
 
-// Per-A counters of the count pass (idxA order).
-struct alignas(16) AStat {
-    uint32_t cnt;          // matches (filter + band)
-    uint32_t nf;           // matches decided by the filter
-    uint32_t best_j;       // sorted B position of the best match
-    uint32_t pad;
+// Per-A record of the count pass (idxA order), one aligned 32-byte store
+// per row: the best match and the row's first kTab matches.
+struct alignas(32) RowRec {
+    int32_t best;          // idxB of the best match, -1: none
+    uint32_t best_j;       // its sorted B position
+    uint32_t b[kTab];      // idxB of the row's first matches
+    double c[kTab];        // their coded separations (see sep_code)
 };
+static_assert(sizeof(RowRec) == 32, "one 32-byte store per row");
+
+// Candidate B ranges of one sorted A source, found once when A is prepared:
+// zone zlo + q holds the sorted B positions [j0[q], j0[q] + n[q]). zlo < 0:
+// not precomputed (an RA window split at 0/360, more than kRZ zones, or a
+// range longer than 65535); the match kernels then walk the cells on the fly.
+constexpr int kRZ = 3;
+struct alignas(8) ARange {
+    uint32_t j0[kRZ];
+    uint16_t n[kRZ];
+    uint16_t pad;
+    int32_t zlo;
+};
+static_assert(sizeof(ARange) == 24, "24-byte range record");
 
 // Everything a match kernel needs; passed by value.
 struct MatchArgs {
@@ -121,6 +138,7 @@ struct MatchArgs {
     const uint32_t *aidx;  // sorted A rows
     const AEll *aell;
     const AEllR *aellr;
+    const ARange *arng;    // [nA] sorted A order
     int32_t nA;
     double reach_deg;      // circle reach
     // circle thresholds on the squared chord
@@ -131,8 +149,8 @@ struct MatchArgs {
     int32_t r_zero;        // radius exactly 0
     double L_rad;          // bound on |p - cell reference| (FP32 error model)
     // count pass
-    AStat *astat;          // [nA] idxA order
-    int32_t *best_idx;     // [nA] idxA order
+    uint32_t *cnts;        // [nA] matches per row (idxA order)
+    RowRec *rec;           // [nA] idxA order
     uint32_t *amb_n;       // band candidates: (sorted A pos, sorted B pos)
     uint2 *amb;
     uint32_t amb_cap;
@@ -146,9 +164,8 @@ struct MatchArgs {
     // write pass
     const int64_t *off;    // [nA + 1] idxA order
     PairTmp *tmp;          // matches in enumeration order
-    // count + emit (MODE 2): a row's first kTab matches go to its table
-    // slots (idxA-major), later ones to the overflow list
-    PairTmp *table;        // [nA * kTab]
+    // count + emit (MODE 2): a row's first kTab matches go to its record,
+    // later ones to the overflow list
     OvEnt *ovl;            // kEmitPools regions of ov_pool entries
     uint32_t *octr;        // [kEmitPools * kEmitPoolStride] entries taken per region
     uint32_t ov_pool;      // entries per region
@@ -191,20 +208,24 @@ __device__ __forceinline__ uint32_t cell_of(int z, double ra, const Grid &g)
     return cell_in(g.zinfo[z], ra);
 }
 
-// Reference vector of cell (z, c): the zone's reference Dec (table) and the
-// point of a 2^16-step RA grid nearest the cell centre (integer arithmetic,
-// then an FP32 sincospi of the exact dyadic angle). It is only a fixed point
-// near the cell shared by every kernel: its accuracy does not matter, only
-// that all kernels get the same bits and that |p - ref| stays below L.
-__device__ __forceinline__ void cell_ref(int z, uint32_t c, const Grid &g, double &rx,
-                                         double &ry, double &rz)
+// Reference vectors of the FP32 filter: in zone z, the zone's reference Dec
+// (table) and the centre of the step of a 2^kRefBits-step RA grid that holds
+// the cell's centre (one FP64 product, then an FP32 sincospi of the exact
+// dyadic angle). Cells of one grid step share their reference. It is only a
+// fixed point near the cell shared by every kernel: its accuracy does not
+// matter, only that all kernels get the same bits and that |p - ref| stays
+// below L.
+__device__ __forceinline__ uint32_t ref_step(const ZoneInfo &zi, uint32_t c)
 {
-    uint64_t n = g.zinfo[z].n;
-    uint64_t gidx = (((uint64_t)(2 * c + 1) << kRefBits) + n) / (2 * n);
-    gidx &= (1u << kRefBits) - 1;
+    return (uint32_t)(((double)c + 0.5) * zi.g) & ((1u << kRefBits) - 1u);
+}
+
+__device__ __forceinline__ void ref_vec(int z, uint32_t step, const Grid &g, double &rx,
+                                        double &ry, double &rz)
+{
     double2 zr = g.zref[z];
     float sa, ca;
-    sincospif((float)gidx * (1.0f / (float)(1 << (kRefBits - 1))), &sa, &ca);
+    sincospif((float)(2u * step + 1u) * (1.0f / (float)(1u << kRefBits)), &sa, &ca);
     rx = zr.x * (double)ca;
     ry = zr.x * (double)sa;
     rz = zr.y;

@@ -44,8 +44,6 @@ constexpr int kMatchBlock = 256;
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
 constexpr int kSegLds = 2048;   // segments up to this long are sorted in LDS
-constexpr int kTileZones = 5;   // zones a cooperative tile may span; wider tiles go per lane
-static_assert(6 * kTileZones <= 64, "one lane per hull end");
 
 struct alignas(16) ColEnt {
     uint32_t t, idxB, j, pad;
@@ -104,6 +102,50 @@ __device__ __forceinline__ double ell_margin(double ar, double br, double kappa,
     return m > 0.25 ? 1e30 : m;
 }
 
+// Candidate ranges of a source at (ra, dec) with reach reach_deg: the
+// window the match kernels would walk (same functions, same inputs), its
+// cell ranges turned into sorted B positions now, with every zone's
+// directory lookups independent of the others.
+__device__ __forceinline__ ARange a_ranges(const Grid &g, double ra, double dec, double reach_deg)
+{
+    ARange rg;
+    rg.zlo = -1;
+    rg.pad = 0;
+    double x, y, z;
+    unit_vec(ra, dec, x, y, z);
+    const double cosd = sqrt(x * x + y * y) * (1.0 - 1e-12) - 1e-15;
+    const Window w = window_of(g, dec, cosd, reach_deg);
+    bool ok = w.zhi - w.zlo < kRZ;
+    uint32_t k0[kRZ], k1[kRZ];
+#pragma unroll
+    for (int q = 0; q < kRZ; ++q) {
+        k0[q] = k1[q] = 0;
+        const int zz = w.zlo + q;
+        if (zz <= w.zhi && ok) {
+            const ZoneInfo zi = g.zinfo[zz];
+            uint32_t c0[2], c1[2];
+            const int nr = zone_ranges(zi, w, ra, c0, c1);
+            ok = nr == 1;
+            k0[q] = zi.base + c0[0];
+            k1[q] = zi.base + c1[0] + 1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kRZ; ++q) {
+        uint32_t j0 = 0, j1 = 0;
+        if (w.zlo + q <= w.zhi && ok) {
+            j0 = key_lower_bound(g, k0[q]);
+            j1 = key_lower_bound(g, k1[q]);
+        }
+        if (j1 < j0) j1 = j0;
+        ok = ok && j1 - j0 < 65535u;
+        rg.j0[q] = j0;
+        rg.n[q] = (uint16_t)(ok ? j1 - j0 : 0u);
+    }
+    if (ok) rg.zlo = w.zlo;
+    return rg;
+}
+
 // Invalid rows (already reported through k_prep_a's flag) are given the
 // position (0, 0) and, for ellipses, a 1" circle, so every later loop stays
 // bounded even before the host sees the error.
@@ -112,8 +154,10 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
                            int64_t n,
                            const double *__restrict__ sa, const double *__restrict__ sb,
                            const double *__restrict__ pa, double pa_zero, int pa_sense,
-                           double L_rad, double2 *__restrict__ arad, uint32_t *__restrict__ aidx,
-                           AEll *__restrict__ aell, AEllR *__restrict__ aellr)
+                           double L_rad, Grid g, double reach_deg,
+                           double2 *__restrict__ arad, uint32_t *__restrict__ aidx,
+                           AEll *__restrict__ aell, AEllR *__restrict__ aellr,
+                           ARange *__restrict__ arng)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -139,6 +183,7 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
     }
     arad[i] = make_double2(r, d);
     aidx[i] = row;
+    arng[i] = a_ranges(g, r, d, SHAPE == C3X_ELLIPSE ? A / 3600.0 : reach_deg);
     if (SHAPE == C3X_ELLIPSE) {
         double T = pa_zero + (double)pa_sense * P;
         double st, ct;
@@ -204,7 +249,9 @@ struct LaneF32 {            // FP32 copies of the ellipse frame
 };
 
 struct CellCache {          // A's offset from the reference of the current B cell
-    uint32_t key;
+    uint32_t key;          // cell key last seen
+    uint32_t ref;          // its reference: zone << kRefBits | RA-grid step (zones < 2^22:
+                           // square-ish cells and fewer than 2^31 of them)
     float ax, ay, az;
 };
 
@@ -215,7 +262,8 @@ struct CellCache {          // A's offset from the reference of the current B ce
 template <int SHAPE, int PREC>
 __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const AEll &e,
                                       const AEllR &er, const LaneF32 &f, CellCache &cc, int z,
-                                      uint32_t key, const PayOf<PREC> &b, uint32_t j, double &c2o)
+                                      const ZoneInfo &zi, uint32_t key, const PayOf<PREC> &b,
+                                      uint32_t j, double &c2o)
 {
     int d;
     if constexpr (PREC == C3X_FP64) {
@@ -235,11 +283,16 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
     } else {
         if (key != cc.key) {
             cc.key = key;
-            double rx, ry, rz;
-            cell_ref(z, key - m.g.zinfo[z].base, m.g, rx, ry, rz);
-            cc.ax = (float)(a.x - rx);
-            cc.ay = (float)(a.y - ry);
-            cc.az = (float)(a.z - rz);
+            const uint32_t st = ref_step(zi, key - zi.base);
+            const uint32_t rf = ((uint32_t)z << kRefBits) | st;
+            if (rf != cc.ref) {
+                cc.ref = rf;
+                double rx, ry, rz;
+                ref_vec(z, st, m.g, rx, ry, rz);
+                cc.ax = (float)(a.x - rx);
+                cc.ay = (float)(a.y - ry);
+                cc.az = (float)(a.z - rz);
+            }
         }
         float dx = b.x - cc.ax, dy = b.y - cc.ay, dz = b.z - cc.az;
         float c2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -291,27 +344,17 @@ __device__ __forceinline__ double c2_err(double c, double L)
     }
 }
 
-__device__ __forceinline__ uint32_t lds_lower_bound(const uint32_t *k, uint32_t n, uint32_t v)
-{
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (k[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------------------- count / write
 
 // A match's separation as the match passes leave it, without trigonometry:
 // from the FP64 chord c < 1.38 the code -c^2 (the separation is 2 asin(c / 2),
-// error ~1e-14 rad), 0 for c = 0, otherwise NaN (computed later from the
-// coordinates).
-__device__ __forceinline__ double sep_code(double c2)
+// error ~1e-14 rad), 0 for c = 0, otherwise a quiet NaN carrying the sorted
+// B position j (the separation is then computed from the coordinates).
+// Non-negative values are separations in arcsec.
+__device__ __forceinline__ double sep_code(double c2, uint32_t j)
 {
     if (c2 < 1.9) return c2 > 0.0 ? -c2 : 0.0;
-    return NAN;
+    return __longlong_as_double((long long)(0x7ff8000000000000ull | j));
 }
 
 __device__ __forceinline__ double sep_from_chord2(double c2)
@@ -320,15 +363,12 @@ __device__ __forceinline__ double sep_from_chord2(double c2)
 }
 
 // MODE 0: count + best; MODE 1: write every filter match into the
-// offsets from the count; MODE 2: count + best, each filter match written
-// to its row's table slot (the first kTab) or to the overflow list.
+// offsets from the count; MODE 2: count + best, the row's first kTab filter
+// matches kept for its record, later ones written to the overflow list.
 template <int SHAPE, int PREC, int MODE>
 __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 {
     using PayT = PayOf<PREC>;
-    constexpr int kStage = PREC == C3X_FP64 ? 192 : 256;  // B staged per wavefront
-    __shared__ uint32_t s_key[kWavesPerBlock][kStage];
-    __shared__ PayT s_pay[kWavesPerBlock][kStage];
     __shared__ unsigned long long s_tests, s_band, s_placed;
     if (threadIdx.x == 0) {
         s_tests = 0;
@@ -336,12 +376,9 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         s_placed = 0;
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const PayT *pay;
     if constexpr (PREC == C3X_FP64) pay = m.pay64;
     else pay = m.pay32;
-    uint32_t *sk = s_key[wave];
-    PayT *sp = s_pay[wave];
 
     const uint32_t i = blockIdx.x * kMatchBlock + threadIdx.x;
     const bool active = i < (uint32_t)m.nA;
@@ -349,7 +386,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     AEll e{};
     AEllR er{};
     LaneF32 f{};
-    Window w{0, -1, false, 0.0};
+    ARange rg{};
     if (active) {
         double reach = m.reach_deg;
         if constexpr (SHAPE == C3X_ELLIPSE) {
@@ -359,22 +396,23 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
                         (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
         }
+        rg = m.arng[i];
         a = load_a(m, i, reach);
-        w = window_of(m.g, a.dec, a.cosd, a.reach_deg);
     }
-    uint32_t zlo_all = wave_min_u32(active ? (uint32_t)w.zlo : 0xffffffffu);
-    uint32_t zhi_all = wave_max_u32(active ? (uint32_t)w.zhi : 0u);
 
     uint32_t cnt = 0;
     double b1 = INFINITY, b2 = INFINITY;
     uint32_t bidx = 0xffffffffu, bj = 0;
+    uint32_t tb0 = 0, tb1 = 0;  // MODE 2: the row's first two matches
+    double tc0 = 0.0, tc1 = 0.0;
+    static_assert(kTab == 2, "two record slots");
     int64_t o = 0, oe = 0;
     if (MODE == 1 && active) {
         o = m.off[a.idx];
-        oe = o + m.astat[a.idx].nf;  // band matches are placed separately
+        oe = m.off[a.idx + 1];
     }
     unsigned long long tests = 0, band = 0, placed = 0;
-    CellCache cc{0xffffffffu, 0.f, 0.f, 0.f};
+    CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
 
     // A filter match as written: the separation coded from the FP64 chord
     // (the FP64 path's filter chord; the mixed path recomputes it from the
@@ -389,7 +427,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         PairTmp t;
         t.idxB = b.idx;
         t.j = j;
-        t.sep = sep_code(c64);
+        t.sep = sep_code(c64, j);
         return t;
     };
 
@@ -420,10 +458,10 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 
     // One candidate: decide it, then count / rank it (MODE 0), write it
     // (MODE 1), or both (MODE 2). Band candidates are only listed.
-    auto visit = [&](int z, uint32_t key, const PayT &b, uint32_t j) {
+    auto visit = [&](int z, const ZoneInfo &zi, uint32_t key, const PayT &b, uint32_t j) {
         ++tests;
         double c2;
-        int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, key, b, j, c2);
+        int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, zi, key, b, j, c2);
         if (d == AMBIG) {
             if (MODE != 1) {
                 ++band;
@@ -435,9 +473,12 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         if (d != IN) return;
         if (MODE == 2) {
             const PairTmp t = coded(b, j, c2);
-            if (cnt < (uint32_t)kTab) {
-                m.table[(size_t)a.idx * kTab + cnt] = t;
-                ++placed;
+            if (cnt == 0) {
+                tb0 = t.idxB;
+                tc0 = t.sep;
+            } else if (cnt == 1) {
+                tb1 = t.idxB;
+                tc1 = t.sep;
             } else {
                 overflow(cnt, t);
             }
@@ -464,171 +505,58 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         }
     };
 
-    if (zhi_all >= zlo_all && zhi_all - zlo_all >= (uint32_t)kTileZones) {
-        // A tile spread over many zones (sparse sky near the poles): each
-        // lane walks its own few zones with direct loads.
-        if (active)
+    if (active) {
+        if (rg.zlo >= 0) {
+            // the ranges found when A was prepared; candidates are loaded
+            // kBatch at a time so that their loads overlap
+            constexpr int kBatch = 4;
+#pragma unroll 1
+            for (int q = 0; q < kRZ; ++q) {
+                const uint32_t j0 = q == 0 ? rg.j0[0] : (q == 1 ? rg.j0[1] : rg.j0[2]);
+                const uint32_t nq = q == 0 ? rg.n[0] : (q == 1 ? rg.n[1] : rg.n[2]);
+                if (nq == 0) continue;
+                const int z = rg.zlo + q;
+                const ZoneInfo zi = m.g.zinfo[z];
+                for (uint32_t t = 0; t < nq; t += kBatch) {
+                    PayT bb[kBatch];
+                    uint32_t kk[kBatch];
+#pragma unroll
+                    for (int u = 0; u < kBatch; ++u) {
+                        const uint32_t jj = j0 + min(t + u, nq - 1);
+                        bb[u] = pay[jj];
+                        kk[u] = m.g.keys[jj];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatch; ++u)
+                        if (t + u < nq) visit(z, zi, kk[u], bb[u], j0 + t + u);
+                }
+            }
+        } else {
+            // split at RA 0/360, many zones or long ranges: walk the cells
             for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
-                cc.key = 0xffffffffu;
+                const ZoneInfo zi = m.g.zinfo[z];
+                cc.key = cc.ref = 0xffffffffu;
                 for (uint32_t j = j0; j < j1; ++j) {
                     const PayT b = pay[j];
-                    visit(z, m.g.keys[j], b, j);
+                    visit(z, zi, m.g.keys[j], b, j);
                 }
             });
-    } else if (zhi_all >= zlo_all) {
-        // Cooperative tile. In each of the tile's zones the lanes' cell
-        // windows are gathered into up to three hulls -- plain windows, the
-        // [0, b] pieces and the [a, n-1] pieces of windows split at RA 0/360
-        // (so a tile near RA 0 does not stage its whole zone) -- each one key
-        // range of B. All range ends are looked up at once (lane 6q+2h and
-        // 6q+2h+1 for hull h of zone q), every range is staged in LDS behind
-        // one wave barrier, and each lane binary-searches its own cells in
-        // the segment of the matching hull. Lane windows are recomputed per
-        // zone rather than kept in registers.
-        const uint32_t zb = (uint32_t)__builtin_amdgcn_readfirstlane((int)zlo_all);
-        const int nzt = __builtin_amdgcn_readfirstlane((int)(zhi_all - zlo_all)) + 1;
-        ZoneInfo zq[kTileZones];
-#pragma unroll
-        for (int q = 0; q < kTileZones; ++q) zq[q] = m.g.zinfo[min((int)zb + q, m.g.nz - 1)];
-        uint32_t lkey = 0;
-        bool lvalid = false, lend = false;
-#pragma unroll
-        for (int q = 0; q < kTileZones; ++q) {
-            if (q >= nzt) break;
-            const int z = (int)zb + q;
-            const ZoneInfo zi = zq[q];
-            uint32_t c0[2], c1[2];
-            int nr = 0;
-            if (active && z >= w.zlo && z <= w.zhi) nr = zone_ranges(zi, w, a.ra, c0, c1);
-            const int nh = __ballot(nr == 2) ? 3 : 1;  // wrap hulls only if a lane wraps
-            for (int h = 0; h < nh; ++h) {
-                uint32_t lo = 0xffffffffu, hi = 0;
-                if (h == 0 && nr == 1) {
-                    lo = c0[0];
-                    hi = c1[0];
-                } else if (h > 0 && nr == 2) {
-                    lo = c0[h - 1];
-                    hi = c1[h - 1];
-                }
-                lo = wave_min_u32(lo);
-                hi = wave_max_u32(hi);
-                if (lane >> 1 == 3 * q + h && lo <= hi) {
-                    lvalid = true;
-                    lend = lane & 1;
-                    lkey = lend ? zi.base + hi + 1 : zi.base + lo;
-                }
-            }
-        }
-        const uint32_t lres = lvalid ? key_bound(m.g, lkey, lend) : 0u;
-        // ends of hull h of zone q (wave-uniform)
-        auto ends = [&](int q, int h, uint32_t &j0, uint32_t &j1) {
-            j0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)lres, 2 * (3 * q + h)));
-            j1 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)lres, 2 * (3 * q + h) + 1));
-            if (j1 < j0) j1 = j0;
-        };
-        uint32_t T = 0;
-        for (int q = 0; q < nzt; ++q)
-#pragma unroll
-            for (int h = 0; h < 3; ++h) {
-                uint32_t j0, j1;
-                ends(q, h, j0, j1);
-                T += j1 - j0;
-            }
-        if (T <= (uint32_t)kStage) {
-            uint32_t seg = 0;
-            for (int q = 0; q < nzt; ++q)
-#pragma unroll
-                for (int h = 0; h < 3; ++h) {
-                    uint32_t j0, j1;
-                    ends(q, h, j0, j1);
-                    for (uint32_t s = lane; s < j1 - j0; s += 64) {
-                        sk[seg + s] = m.g.keys[j0 + s];
-                        sp[seg + s] = pay[j0 + s];
-                    }
-                    seg += j1 - j0;
-                }
-            wave_sync();
-            seg = 0;
-            for (int q = 0; q < nzt; ++q) {
-                const int z = (int)zb + q;
-                const ZoneInfo zi = m.g.zinfo[z];
-                uint32_t c0[2], c1[2];
-                int nr = 0;
-                if (active && z >= w.zlo && z <= w.zhi) nr = zone_ranges(zi, w, a.ra, c0, c1);
-                cc.key = 0xffffffffu;
-#pragma unroll
-                for (int h = 0; h < 3; ++h) {
-                    uint32_t j0, j1;
-                    ends(q, h, j0, j1);
-                    const uint32_t segn = j1 - j0;
-                    int k = -1;
-                    if (h == 0 && nr == 1) k = 0;
-                    else if (h > 0 && nr == 2) k = h - 1;
-                    if (segn > 0 && k >= 0) {
-                        const uint32_t ka = k ? c0[1] : c0[0], kb = k ? c1[1] : c1[0];
-                        uint32_t s0 = seg + lds_lower_bound(sk + seg, segn, zi.base + ka);
-                        uint32_t s1 = seg + lds_lower_bound(sk + seg, segn, zi.base + kb + 1);
-                        for (uint32_t s = s0; s < s1; ++s) {
-                            const PayT b = sp[s];
-                            visit(z, sk[s], b, j0 + (s - seg));
-                        }
-                    }
-                    seg += segn;
-                }
-            }
-        } else {
-            // more than fits in LDS at once: hull by hull, in chunks
-            for (int q = 0; q < nzt; ++q) {
-                const int z = (int)zb + q;
-                const ZoneInfo zi = m.g.zinfo[z];
-                uint32_t c0[2], c1[2];
-                int nr = 0;
-                if (active && z >= w.zlo && z <= w.zhi) nr = zone_ranges(zi, w, a.ra, c0, c1);
-#pragma unroll
-                for (int h = 0; h < 3; ++h) {
-                    uint32_t j0, j1;
-                    ends(q, h, j0, j1);
-                    int k = -1;
-                    if (h == 0 && nr == 1) k = 0;
-                    else if (h > 0 && nr == 2) k = h - 1;
-                    const uint32_t ka = k == 1 ? c0[1] : c0[0], kb = k == 1 ? c1[1] : c1[0];
-                    cc.key = 0xffffffffu;
-                    for (uint32_t c = j0; c < j1; c += kStage) {
-                        const uint32_t nst = min((uint32_t)kStage, j1 - c);
-                        wave_sync();
-                        for (uint32_t s = lane; s < nst; s += 64) {
-                            sk[s] = m.g.keys[c + s];
-                            sp[s] = pay[c + s];
-                        }
-                        wave_sync();
-                        if (k >= 0) {
-                            uint32_t s0 = lds_lower_bound(sk, nst, zi.base + ka);
-                            uint32_t s1 = lds_lower_bound(sk, nst, zi.base + kb + 1);
-                            for (uint32_t s = s0; s < s1; ++s) {
-                                const PayT b = sp[s];
-                                visit(z, sk[s], b, c + s);
-                            }
-                        }
-                    }
-                }
-            }
         }
     }
-    if (active) {
-        if (MODE != 1) {
-            AStat st;
-            st.cnt = cnt;
-            st.nf = cnt;
-            st.best_j = bj;
-            st.pad = 0;
-            m.astat[a.idx] = st;
-            m.best_idx[a.idx] = cnt ? (int32_t)bidx : -1;
-            if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), m.L_rad)) {
-                uint32_t slot = atomicAdd(m.tie_n, 1u);
-                if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
-            }
-        } else {
-            if (o + cnt != oe) atomicOr(m.err_flag, 2u);
+    if (active && MODE != 1) {
+        m.cnts[a.idx] = cnt;
+        RowRec r;
+        r.best = cnt ? (int32_t)bidx : -1;
+        r.best_j = bj;
+        r.b[0] = tb0;
+        r.b[1] = tb1;
+        r.c[0] = tc0;
+        r.c[1] = tc1;
+        m.rec[a.idx] = r;
+        if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
+        if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), m.L_rad)) {
+            uint32_t slot = atomicAdd(m.tie_n, 1u);
+            if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
         }
     }
     if (placed) atomicAdd(&s_placed, placed);
@@ -666,12 +594,13 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
                     (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
     }
     ARec a = load_a(m, i, reach);
-    CellCache cc{0xffffffffu, 0.f, 0.f, 0.f};
+    CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
     for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
+        const ZoneInfo zi = m.g.zinfo[z];
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
-            int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, m.g.keys[j], b, j, c2);
+            int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, zi, m.g.keys[j], b, j, c2);
             if (d == AMBIG) d = verdict(m, i, j);
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
@@ -688,6 +617,101 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
             }
         }
     });
+}
+
+// (c2, idxB, j) candidates of the FP64 re-ranking, ordered by (c2, idxB).
+struct Cand {
+    double c2;
+    uint32_t idxB, j;
+};
+__device__ __forceinline__ bool cand_less(const Cand &x, const Cand &y)
+{
+    return x.c2 < y.c2 || (x.c2 == y.c2 && x.idxB < y.idxB);
+}
+__device__ __forceinline__ Cand cand_shfl_xor(const Cand &x, int o)
+{
+    Cand y;
+    const long long b = __double_as_longlong(x.c2);
+    y.c2 = __longlong_as_double(((long long)(uint32_t)__shfl_xor((int)(b >> 32), o) << 32) |
+                                (uint32_t)__shfl_xor((int)(uint32_t)b, o));
+    y.idxB = (uint32_t)__shfl_xor((int)x.idxB, o);
+    y.j = (uint32_t)__shfl_xor((int)x.j, o);
+    return y;
+}
+
+// Best-match re-ranking of the listed sorted A positions (rows whose two
+// nearest filter matches are within the filter's error, and rows with band
+// matches found inside): one wavefront per row. Every match is re-decided
+// (filter, then the band verdicts) and ranked by its FP64 squared chord
+// from the FP64 unit vectors (error c2_err<FP64>); when the runner-up is
+// further than 4 such errors the best is certain and written to the row's
+// record, otherwise the row is listed for the host's binary128 ranking.
+template <int SHAPE, int PREC>
+__global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__restrict__ pos,
+                                               uint32_t n, uint32_t *__restrict__ unc_n,
+                                               uint32_t *__restrict__ unc)
+{
+    using PayT = PayOf<PREC>;
+    const uint32_t t = blockIdx.x;
+    if (t >= n) return;
+    const PayT *pay;
+    if constexpr (PREC == C3X_FP64) pay = m.pay64;
+    else pay = m.pay32;
+    const uint32_t i = pos[t];
+    AEll e{};
+    AEllR er{};
+    LaneF32 f{};
+    double reach = m.reach_deg;
+    if constexpr (SHAPE == C3X_ELLIPSE) {
+        e = m.aell[i];
+        er = m.aellr[i];
+        reach = er.a_arcsec / 3600.0;
+        f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
+                    (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
+    }
+    const ARec a = load_a(m, i, reach);
+    CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
+    Cand b1{INFINITY, 0xffffffffu, 0u}, b2{INFINITY, 0xffffffffu, 0u};
+    for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
+        const ZoneInfo zi = m.g.zinfo[z];
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
+            const PayT b = pay[j];
+            double c2;
+            int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, zi, m.g.keys[j], b, j, c2);
+            if (d == AMBIG) d = verdict(m, i, j);
+            if (d != IN) continue;
+            const Pay64 b8 = m.pay64[j];
+            const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
+            const Cand c{fma(dx, dx, fma(dy, dy, dz * dz)), b8.idx, j};
+            if (cand_less(c, b1)) {
+                b2 = b1;
+                b1 = c;
+            } else if (cand_less(c, b2)) {
+                b2 = c;
+            }
+        }
+    });
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const Cand y1 = cand_shfl_xor(b1, o), y2 = cand_shfl_xor(b2, o);
+        const bool mine = cand_less(b1, y1);
+        const Cand lo = mine ? b1 : y1, hi = mine ? y1 : b1;
+        Cand s2 = cand_less(b2, y2) ? b2 : y2;
+        if (cand_less(hi, s2)) s2 = hi;
+        b1 = lo;
+        b2 = s2;
+    }
+    if (threadIdx.x == 0 && b1.idxB != 0xffffffffu) {
+        const uint32_t row = m.aidx[i];
+        const bool sure = b2.idxB == 0xffffffffu ||
+                          b2.c2 - b1.c2 > 4.0 * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
+        if (sure) {
+            m.rec[row].best = (int32_t)b1.idxB;
+            m.rec[row].best_j = b1.j;
+        } else {
+            unc[atomicAdd(unc_n, 1u)] = i;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------- small kernels
@@ -748,13 +772,13 @@ __global__ void k_gather_pos(const uint32_t *__restrict__ pos, uint32_t n,
 
 // Band candidates found inside (sorted A position, idxA, idxB, sorted B
 // position): each is counted, and listed as the k-th match of its source.
-__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, AStat *st,
+__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, uint32_t *cnts,
                             WEnt *__restrict__ out)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     uint4 q = in[t];
-    uint32_t k = atomicAdd(&st[q.y].cnt, 1u);
+    uint32_t k = atomicAdd(&cnts[q.y], 1u);
     if (out) out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
@@ -793,14 +817,15 @@ __global__ void k_place_ov(const OvEnt *__restrict__ ovl, uint32_t ov_pool,
     atomicAdd(placed, 1ull);
 }
 
-// One thread per band match found inside: to its row's table slot (k <
-// kTab, when the single pass filled the table) or its place in the
-// idxA-order segments, with its separation.
+// One thread per band match found inside: to its row's record (k < kTab,
+// when the single pass filled the records) or its place in the idxA-order
+// segments, with its separation.
 __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
                           const uint32_t *__restrict__ aidx, const double2 *__restrict__ arad,
                           const double2 *__restrict__ radecB, int64_t nA, int64_t nB,
-                          const int64_t *__restrict__ off, int64_t P, PairTmp *__restrict__ table,
-                          PairTmp *__restrict__ tmp, unsigned long long *__restrict__ placed,
+                          const int64_t *__restrict__ off, int64_t P, RowRec *__restrict__ rec,
+                          int use_rec, PairTmp *__restrict__ tmp,
+                          unsigned long long *__restrict__ placed,
                           uint32_t *__restrict__ err)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -822,70 +847,100 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
     x.idxB = e.idxB;
     x.j = e.j;
     x.sep = sep_rare(ra.x, ra.y, rb.x, rb.y);
-    if (table && e.k < (uint32_t)kTab) table[(size_t)a * kTab + e.k] = x;
-    else tmp[p] = x;
+    if (use_rec && e.k < (uint32_t)kTab) {
+        rec[a].b[e.k] = x.idxB;
+        rec[a].c[e.k] = x.sep;
+    } else {
+        tmp[p] = x;
+    }
     atomicAdd(placed, 1ull);
 }
 
 __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
-                             const uint32_t *__restrict__ bj, uint32_t n, int32_t *best_idx,
-                             AStat *st)
+                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    best_idx[rows[t]] = bi[t];
-    st[rows[t]].best_j = bj[t];
+    rec[rows[t]].best = bi[t];
+    rec[rows[t]].best_j = bj[t];
 }
 
-__global__ void k_counts(const AStat *__restrict__ st, int64_t n, int nonzero,
-                         uint32_t *__restrict__ out, double *__restrict__ bsep)
+// BEST-only output: one record per row that has a match.
+__global__ void k_nonzero(const uint32_t *__restrict__ cnts, int64_t n, uint32_t *__restrict__ out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    uint32_t c = st[t].cnt;
-    out[t] = nonzero ? (c ? 1u : 0u) : c;
-    if (bsep) bsep[t] = NAN;
+    if (t < n) out[t] = cnts[t] ? 1u : 0u;
 }
 
-// Final record of one match: idxA, idxB and the separation (computed here
-// when the pass that placed it left it undefined), and the best match's
-// separation.
+// Separation (arcsec) of a coded match (see sep_code). A chord below 0.1
+// uses the Maclaurin series of arcsin, 2 asin(x) = 2x (1 + x^2/6 + 3x^4/40
+// + ...), x = c/2, to x^15 (truncation below 1e-20 relative); larger chords
+// and the coordinate form are left to decode_rare.
+__device__ __forceinline__ double theta_small(double c2)
+{
+    const double x2 = 0.25 * c2;
+    double p = 143.0 / 10240.0;
+    p = fma(p, x2, 231.0 / 13312.0);
+    p = fma(p, x2, 63.0 / 2816.0);
+    p = fma(p, x2, 35.0 / 1152.0);
+    p = fma(p, x2, 5.0 / 112.0);
+    p = fma(p, x2, 3.0 / 40.0);
+    p = fma(p, x2, 1.0 / 6.0);
+    p = fma(p, x2, 1.0);
+    return sqrt(c2) * p * (180.0 / kPi * 3600.0);
+}
+
+__device__ __noinline__ double decode_rare(double code, double raA, double decA,
+                                           const double2 *__restrict__ radecB, int64_t nB,
+                                           uint32_t *__restrict__ err)
+{
+    if (code < 0.0) return 2.0 * asin(0.5 * sqrt(-code)) * (180.0 / kPi * 3600.0);
+    const uint32_t j = (uint32_t)__double_as_longlong(code);
+    if (j >= (uint64_t)nB) {
+        atomicOr(err, 16u);
+        return NAN;
+    }
+    const double2 rb = radecB[j];
+    return sep_arcsec_rd(raA, decA, rb.x, rb.y);
+}
+
+// Final record of one match: idxA, idxB and the decoded separation; the
+// best match's separation too. RARE: the separations may need decode_rare
+// (radius or ellipse beyond a few degrees); otherwise every code is a
+// small chord.
+template <bool RARE>
 __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp &x, int64_t nB,
                                             const double *__restrict__ raA,
                                             const double *__restrict__ decA,
-                                            const double2 *__restrict__ radecB,
-                                            const int32_t *__restrict__ bidx,
+                                            const double2 *__restrict__ radecB, int32_t best,
                                             int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                                             double *__restrict__ os, double *__restrict__ bsep,
                                             uint32_t *__restrict__ err)
 {
     double s = x.sep;
-    if (s < 0.0) {  // coded by the write pass (see sep_code)
-        s = sep_from_chord2(-s);
-    } else if (isnan(s)) {
-        if (x.j >= (uint64_t)nB) {
-            atomicOr(err, 16u);
-            return;
-        }
-        double2 rb = radecB[x.j];
-        s = sep_rare(raA[a], decA[a], rb.x, rb.y);
+    if (!(s >= 0.0)) {
+        if (s > -0.01) s = theta_small(-s);
+        else if (RARE) s = decode_rare(s, raA[a], decA[a], radecB, nB, err);
+        else atomicOr(err, 32u);
     }
     oa[q] = (int32_t)a;
     ob[q] = (int32_t)x.idxB;
     os[q] = s;
-    if (bidx[a] == (int32_t)x.idxB) bsep[a] = s;
+    if (best == (int32_t)x.idxB) bsep[a] = s;
 }
 
-// One thread per A row. A row's k-th match is in its table slot for k <
-// kTab (when the single pass filled the table) and at offset off + k of its
-// segment otherwise. A short segment (<= kShortSeg) is finished here: the
+// One thread per A row: its best match and, in all-matches mode, its
+// segment. A row's k-th match is in its record for k < kTab (when the
+// single pass filled the records) and at offset off + k of its segment
+// otherwise. A short segment (<= kShortSeg) is finished here: the
 // canonical position of each match is its rank by idxB (unique in a
-// segment). A longer one has its table slots copied into the segment, which
-// k_seg_lds then finishes.
+// segment). A longer one has its record's matches copied into the segment,
+// which k_seg_lds then finishes.
+template <bool RARE>
 __global__ void k_finalize(int64_t nA, int64_t nB, const int64_t *__restrict__ off,
-                           const PairTmp *__restrict__ table, PairTmp *__restrict__ tmp,
+                           const RowRec *__restrict__ rec, int use_rec, PairTmp *__restrict__ tmp,
                            const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ radecB, const int32_t *__restrict__ bidx,
+                           const double2 *__restrict__ radecB, int32_t *__restrict__ best_idx,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                            double *__restrict__ os, double *__restrict__ bsep,
                            uint32_t *__restrict__ err)
@@ -893,42 +948,54 @@ __global__ void k_finalize(int64_t nA, int64_t nB, const int64_t *__restrict__ o
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nA) return;
     const int64_t o = off[a], len = off[a + 1] - o;
-    if (len <= 0) return;
-    const int nt = table ? (int)min<int64_t>(len, kTab) : 0;
-    const PairTmp *row = table + (table ? a * kTab : 0);
-    if (len > kShortSeg) {
-        for (int q = 0; q < nt; ++q) tmp[o + q] = row[q];
+    bsep[a] = NAN;
+    if (len <= 0) {
+        best_idx[a] = -1;
         return;
     }
-    if (len == 1) {
-        final_write(o, a, nt ? row[0] : tmp[o], nB, raA, decA, radecB, bidx, oa, ob, os, bsep, err);
+    const RowRec r = rec[a];
+    best_idx[a] = r.best;
+    const int nt = use_rec ? (int)min<int64_t>(len, kTab) : 0;
+    auto get = [&](int q) -> PairTmp {
+        if (q < nt) {
+            PairTmp x;
+            x.idxB = r.b[q];
+            x.j = 0;
+            x.sep = r.c[q];
+            return x;
+        }
+        return tmp[o + q];
+    };
+    if (len > kShortSeg) {
+        for (int q = 0; q < nt; ++q) tmp[o + q] = get(q);
         return;
     }
     for (int q = 0; q < len; ++q) {
-        const PairTmp x = q < nt ? row[q] : tmp[o + q];
-        int r = 0;
-        for (int y = 0; y < len; ++y) r += (y < nt ? row[y].idxB : tmp[o + y].idxB) < x.idxB;
-        final_write(o + r, a, x, nB, raA, decA, radecB, bidx, oa, ob, os, bsep, err);
+        const PairTmp x = get(q);
+        int rk = 0;
+        for (int y = 0; y < len; ++y) rk += get(y).idxB < x.idxB;
+        final_write<RARE>(o + rk, a, x, nB, raA, decA, radecB, r.best, oa, ob, os, bsep, err);
     }
 }
 
-// One thread per A row: separation of the best match; in BEST-only mode also
+// BEST-only mode, one thread per A row: the best match, its separation and
 // the compacted (idxA, idxB, sep) pair.
-__global__ void k_best_sep(int64_t n, int64_t nB, const int32_t *__restrict__ bidx,
-                           const AStat *__restrict__ st, const double *__restrict__ raA,
-                           const double *__restrict__ decA, const double2 *__restrict__ radecB,
+__global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec,
+                           const double *__restrict__ raA, const double *__restrict__ decA,
+                           const double2 *__restrict__ radecB, int32_t *__restrict__ bidx,
                            double *__restrict__ bsep, const int64_t *__restrict__ off, int64_t P,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                            double *__restrict__ os, uint32_t *__restrict__ err)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    int32_t b = bidx[t];
+    const int32_t b = off[t + 1] > off[t] ? rec[t].best : -1;
+    bidx[t] = b;
     if (b < 0) {
         bsep[t] = NAN;
         return;
     }
-    uint32_t bj = st[t].best_j;
+    uint32_t bj = rec[t].best_j;
     if (bj >= (uint64_t)nB) {
         atomicOr(err, 16u);
         return;
@@ -966,6 +1033,7 @@ __global__ void k_seg_list(const int64_t *__restrict__ off, int64_t n, uint32_t 
 // kSegLds matches are sorted by idxB in LDS (bitonic network over
 // idxB << 32 | position; idxB is unique in a segment) and written out in
 // final form; longer ones are listed for the host-driven radix sort.
+template <bool RARE>
 __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off,
                                                  const uint32_t *__restrict__ cnt,
                                                  const uint32_t *__restrict__ list, uint32_t cap,
@@ -973,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                                                  const double *__restrict__ raA,
                                                  const double *__restrict__ decA,
                                                  const double2 *__restrict__ radecB,
-                                                 const int32_t *__restrict__ bidx,
+                                                 const RowRec *__restrict__ rec,
                                                  int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                                                  double *__restrict__ os, double *__restrict__ bsep,
                                                  uint32_t *__restrict__ huge_n,
@@ -1014,9 +1082,10 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                 __syncthreads();
             }
         }
+        const int32_t best = rec[a].best;
         for (int k = threadIdx.x; k < len; k += blockDim.x)
-            final_write(o + k, a, tmp[o + (uint32_t)v[k]], nB, raA, decA, radecB, bidx, oa, ob, os,
-                        bsep, err);
+            final_write<RARE>(o + k, a, tmp[o + (uint32_t)v[k]], nB, raA, decA, radecB, best, oa,
+                              ob, os, bsep, err);
         __syncthreads();  // v is reused by the next segment
     }
 }
@@ -1025,13 +1094,14 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
 __global__ void k_seg_copy(int64_t o, int64_t len, int64_t a, const PairTmp *__restrict__ tmp,
                            int64_t nB, const double *__restrict__ raA,
                            const double *__restrict__ decA, const double2 *__restrict__ radecB,
-                           const int32_t *__restrict__ bidx, int32_t *__restrict__ oa,
+                           const RowRec *__restrict__ rec, int32_t *__restrict__ oa,
                            int32_t *__restrict__ ob, double *__restrict__ os,
                            double *__restrict__ bsep, uint32_t *__restrict__ err)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < len)
-        final_write(o + k, a, tmp[o + k], nB, raA, decA, radecB, bidx, oa, ob, os, bsep, err);
+        final_write<true>(o + k, a, tmp[o + k], nB, raA, decA, radecB, rec[a].best, oa, ob, os,
+                          bsep, err);
 }
 
 __global__ void k_split(const PairTmp *__restrict__ t, int64_t n, uint32_t *__restrict__ k,
@@ -1056,11 +1126,12 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 struct FinishArgs {
     int64_t nA, nB;
     const int64_t *off;
-    const PairTmp *table;
+    const RowRec *rec;
+    int use_rec, rare;
     PairTmp *tmp;
     const double *raA, *decA;
     const double2 *radecB;
-    const int32_t *bidx;
+    int32_t *best_idx;
     int32_t *oa, *ob;
     double *os, *bsep;
     uint32_t *err;
@@ -1076,14 +1147,20 @@ constexpr unsigned kSegGrid = 1024;
 static void finish_segments(const FinishArgs &f, hipStream_t s)
 {
     if (f.nA == 0) return;
-    hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.off,
-                       f.table, f.tmp, f.raA, f.decA, f.radecB, f.bidx, f.oa, f.ob, f.os, f.bsep,
-                       f.err);
-    hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA, f.seg_n,
-                       f.list, f.cap);
-    hipLaunchKernelGGL(k_seg_lds, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list, f.cap,
-                       f.tmp, f.nB, f.raA, f.decA, f.radecB, f.bidx, f.oa, f.ob, f.os, f.bsep,
-                       f.seg_n + 1, f.huge, f.err);
+#define C3X_FIN(R)                                                                                \
+    do {                                                                                          \
+        hipLaunchKernelGGL(k_finalize<R>, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB,      \
+                           f.off, f.rec, f.use_rec, f.tmp, f.raA, f.decA, f.radecB, f.best_idx,   \
+                           f.oa, f.ob, f.os, f.bsep, f.err);                                      \
+        hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA,        \
+                           f.seg_n, f.list, f.cap);                                               \
+        hipLaunchKernelGGL(k_seg_lds<R>, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list,  \
+                           f.cap, f.tmp, f.nB, f.raA, f.decA, f.radecB, f.rec, f.oa, f.ob, f.os,  \
+                           f.bsep, f.seg_n + 1, f.huge, f.err);                                   \
+    } while (0)
+    if (f.rare) C3X_FIN(true);
+    else C3X_FIN(false);
+#undef C3X_FIN
 }
 
 // Segments longer than kSegLds (counts already on the host): radix sort by
@@ -1114,7 +1191,7 @@ static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStre
             hipLaunchKernelGGL(k_merge, dim3(nblk(len, 256)), dim3(256), 0, s, in_tmp ? v2 : v1,
                                copy, len, f.tmp + o);
             hipLaunchKernelGGL(k_seg_copy, dim3(nblk(len, 256)), dim3(256), 0, s, o, len,
-                               (int64_t)hv[k], f.tmp, f.nB, f.raA, f.decA, f.radecB, f.bidx, f.oa,
+                               (int64_t)hv[k], f.tmp, f.nB, f.raA, f.decA, f.radecB, f.rec, f.oa,
                                f.ob, f.os, f.bsep, f.err);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1181,6 +1258,22 @@ static void launch_match(const MatchArgs &m, int shape, int prec, unsigned grid,
 #undef C3X_LAUNCH
 }
 
+static void launch_rerank(const MatchArgs &m, int shape, int prec, const uint32_t *pos,
+                          uint32_t n, uint32_t *unc_n, uint32_t *unc, hipStream_t s)
+{
+    if (n == 0) return;
+#define C3X_RR(SH, PR) \
+    hipLaunchKernelGGL((k_rerank<SH, PR>), dim3(n), dim3(64), 0, s, m, pos, n, unc_n, unc)
+    if (shape == C3X_CIRCLE) {
+        if (prec == C3X_FP64) C3X_RR(C3X_CIRCLE, C3X_FP64);
+        else C3X_RR(C3X_CIRCLE, C3X_MIXED);
+    } else {
+        if (prec == C3X_FP64) C3X_RR(C3X_ELLIPSE, C3X_FP64);
+        else C3X_RR(C3X_ELLIPSE, C3X_MIXED);
+    }
+#undef C3X_RR
+}
+
 static void launch_collect(const MatchArgs &m, int shape, int prec, hipStream_t s)
 {
     unsigned grid = m.n_col;
@@ -1225,8 +1318,10 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     unsigned long long *c64 = tmp.get_n<unsigned long long>(3);  // tests, band, placed
     double2 *arad = tmp.get_n<double2>(nA);
     double2 *packed = tmp.get_n<double2>(nA);
+    ARange *arng = tmp.get_n<ARange>(nA);
     uint32_t *aidx = tmp.get_n<uint32_t>(nA);
-    AStat *astat = tmp.get_n<AStat>(nA);
+    uint32_t *cnts = tmp.get_n<uint32_t>(nA);
+    RowRec *rec = tmp.get_n<RowRec>(nA);
     AEll *aell = nullptr;
     AEllR *aellr = nullptr;
     if (shape == C3X_ELLIPSE) {
@@ -1235,7 +1330,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
     }
     if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !packed || !aidx ||
-        !astat)
+        !cnts || !rec || !arng)
         return fail(C3X_ENOMEM, "A buffers");
     R->nA = nA;
     R->best_idx = R->mem.get_n<int32_t>(nA);
@@ -1253,14 +1348,15 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     HIPCHK(radix_sort_pairs(keys, rows, ktmp, rtmp, nA, ix->plan.key_bits, ws, s, &in_tmp), "A sort");
     uint32_t *srows = in_tmp ? rtmp : rows;
     if (nA > 0) {
+        const double reach = shape == C3X_CIRCLE ? area->radius_arcsec / 3600.0 : 0.0;
         if (shape == C3X_CIRCLE)
             hipLaunchKernelGGL(k_gather_a<C3X_CIRCLE>, dim3(nblk(nA, 256)), dim3(256), 0, s, srows,
                                packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
-                               ix->plan.L_rad, arad, aidx, aell, aellr);
+                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng);
         else
             hipLaunchKernelGGL(k_gather_a<C3X_ELLIPSE>, dim3(nblk(nA, 256)), dim3(256), 0, s,
                                srows, packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
-                               ix->plan.L_rad, arad, aidx, aell, aellr);
+                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng);
     }
     HIPCHK(hipGetLastError(), "A records");
     tm.mark();  // 1
@@ -1276,6 +1372,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.aidx = aidx;
     m.aell = aell;
     m.aellr = aellr;
+    m.arng = arng;
     m.nA = (int32_t)nA;
     m.L_rad = ix->plan.L_rad;
     if (shape == C3X_CIRCLE) {
@@ -1292,8 +1389,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_tests = c64;
     m.n_band = c64 + 1;
     m.err_flag = ctr + 4;
-    m.astat = astat;
-    m.best_idx = R->best_idx;
+    m.cnts = cnts;
+    m.rec = rec;
     unsigned grid = nblk(nA, kMatchBlock);
 
     // ---- count pass (+ best by the filter's chord, near-ties listed)
@@ -1309,7 +1406,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.tie = tie;
     m.tie_cap = tie_cap;
     // All matches: the pass that counts also writes them -- a row's first
-    // kTab matches into its table slots, later ones into the overflow list
+    // kTab matches into its record, later ones into the overflow list
     // (kEmitPools regions; block b uses region b mod kEmitPools). If a
     // region runs out, the count stands and the write pass puts every
     // match into the offsets instead.
@@ -1319,16 +1416,15 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     const int kPoolWords = kEmitPools * kEmitPoolStride;
     if (all && nA > 0) {
         uint64_t per = (uint64_t)std::max<int64_t>(nA / 8 / kEmitPools, 4096);
-        // test hook: C3X_DEBUG_OVERFLOW_SLOTS=k gives each region k slots (0: no table)
+        // test hook: C3X_DEBUG_OVERFLOW_SLOTS=k gives each region k slots (0: none,
+        // every match goes through the write pass)
         if (const char *ev = getenv("C3X_DEBUG_OVERFLOW_SLOTS"))
             per = (uint64_t)std::max<long long>(atoll(ev), -1);
-        const bool no_table = getenv("C3X_DEBUG_OVERFLOW_SLOTS") && per == 0;
-        if (!no_table && per < (1ull << 26)) {
-            m.table = tmp.get_n<PairTmp>((size_t)nA * kTab);
+        if (per > 0 && per < (1ull << 26)) {
             m.ovl = tmp.get_n<OvEnt>(per * kEmitPools);
             m.octr = tmp.get_n<uint32_t>(kPoolWords);
             m.ov_pool = (uint32_t)per;
-            emit = m.table && m.ovl && m.octr;
+            emit = m.ovl && m.octr;
             if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
         }
     }
@@ -1371,16 +1467,13 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipMemsetAsync(c64, 0, 3 * sizeof(unsigned long long), s), "memset");
         if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
     }
-    // the table and list hold every filter match unless a region ran out
+    // the records and the list hold every filter match unless a region ran out
     const bool emitted = emit && hctr[5] == 0;
     uint32_t ov_used = 0;
     if (emitted)
         for (int q = 0; q < kEmitPools; ++q)
             ov_used = std::max(ov_used, std::min(hoctr[q * kEmitPoolStride], m.ov_pool));
-    if (!emitted) {
-        m.table = nullptr;
-        HIPCHK(hipMemsetAsync(c64 + 2, 0, sizeof(unsigned long long), s), "memset");
-    }
+    if (!emitted) HIPCHK(hipMemsetAsync(c64 + 2, 0, sizeof(unsigned long long), s), "memset");
     uint32_t n_amb = hctr[1], n_tie = hctr[2];
     R->stats.n_tests = (int64_t)h64[0];
     R->stats.n_band = (int64_t)h64[1];
@@ -1450,7 +1543,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             HIPCHK(hipMemcpyAsync(dadd, add.data(), add.size() * sizeof(uint4),
                                   hipMemcpyHostToDevice, s), "copy");
             hipLaunchKernelGGL(k_add_pairs, dim3(nblk(add.size(), 256)), dim3(256), 0, s, dadd,
-                               (uint32_t)add.size(), astat, xent);
+                               (uint32_t)add.size(), cnts, xent);
         }
         m.ver_key = dvk;
         m.ver_in = dvi;
@@ -1459,7 +1552,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     }
     R->stats.n_ambiguous = n_host;
 
-    // ---- best matches the filter cannot rank: every match re-ranked in binary128
+    // ---- best matches the filter cannot rank: re-ranked in FP64 on the GPU, and
+    // what FP64 cannot separate, every match re-ranked in binary128 on the host
     if (n_tie > 0) {
         std::vector<uint2> ties(n_tie);
         HIPCHK(hipMemcpyAsync(ties.data(), tie, n_tie * sizeof(uint2), hipMemcpyDeviceToHost, s),
@@ -1467,13 +1561,25 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipStreamSynchronize(s), "ties");
         for (const uint2 &t : ties) recheck_pos.push_back(t.x);
     }
+    uint32_t nc = 0;
+    uint32_t *dpos = nullptr;
     if (!recheck_pos.empty()) {
         std::sort(recheck_pos.begin(), recheck_pos.end());
         recheck_pos.erase(std::unique(recheck_pos.begin(), recheck_pos.end()), recheck_pos.end());
-        uint32_t nc = (uint32_t)recheck_pos.size();
-        uint32_t *dpos = tmp.get_n<uint32_t>(nc);
-        if (!dpos) return fail(C3X_ENOMEM, "collect buffers");
-        HIPCHK(hipMemcpyAsync(dpos, recheck_pos.data(), nc * 4, hipMemcpyHostToDevice, s), "copy");
+        const uint32_t nr = (uint32_t)recheck_pos.size();
+        R->stats.n_best_ties = nr;
+        uint32_t *dall = tmp.get_n<uint32_t>(nr);
+        dpos = tmp.get_n<uint32_t>(nr);
+        if (!dall || !dpos) return fail(C3X_ENOMEM, "re-ranking buffers");
+        HIPCHK(hipMemcpyAsync(dall, recheck_pos.data(), nr * 4, hipMemcpyHostToDevice, s), "copy");
+        HIPCHK(hipMemsetAsync(ctr + 3, 0, sizeof(uint32_t), s), "memset");
+        launch_rerank(m, shape, prec, dall, nr, ctr + 3, dpos, s);
+        HIPCHK(hipGetLastError(), "re-ranking");
+        HIPCHK(hipMemcpyAsync(&nc, ctr + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(hipStreamSynchronize(s), "re-ranking");
+        nc = std::min(nc, nr);
+    }
+    if (nc > 0) {
         uint32_t col_cap = 8 * nc + 64;
         std::vector<ColEnt> col;
         for (int attempt = 0; attempt < 2; ++attempt) {
@@ -1540,20 +1646,23 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             HIPCHK(hipMemcpyAsync(d2, pbi.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             HIPCHK(hipMemcpyAsync(d3, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3, np,
-                               R->best_idx, astat);
+                               rec);
             HIPCHK(hipStreamSynchronize(s), "best patch");
         }
-        R->stats.n_best_ties = nc;
     }
 
     // ---- scan of the per-A counts (idxA order)
     int64_t *off = tmp.get_n<int64_t>(nA + 1);
-    uint32_t *cnts = tmp.get_n<uint32_t>(nA);
-    if (!off || !cnts) return fail(C3X_ENOMEM, "offsets");
-    if (nA > 0)
-        hipLaunchKernelGGL(k_counts, dim3(nblk(nA, 256)), dim3(256), 0, s, astat, nA, all ? 0 : 1,
-                           cnts, all ? R->best_sep : nullptr);
-    HIPCHK(scan_u32_to_i64(cnts, off, nA, off + nA, ws, s), "scan");
+    const uint32_t *scan_in = cnts;
+    if (!all) {  // one output row per A row with a match
+        uint32_t *nz = tmp.get_n<uint32_t>(nA);
+        if (!nz) return fail(C3X_ENOMEM, "offsets");
+        if (nA > 0)
+            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
+        scan_in = nz;
+    }
+    if (!off) return fail(C3X_ENOMEM, "offsets");
+    HIPCHK(scan_u32_to_i64(scan_in, off, nA, off + nA, ws, s), "scan");
     int64_t P = 0;
     HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     HIPCHK(hipStreamSynchronize(s), "scan");
@@ -1584,19 +1693,23 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipGetLastError(), "write pass");
         if (n_x > 0)
             hipLaunchKernelGGL(k_place_x, dim3(nblk(n_x, 256)), dim3(256), 0, s, xent, n_x, aidx,
-                               arad, ix->radec, nA, ix->nB, off, P, m.table, pt, c64 + 2, ctr + 4);
+                               arad, ix->radec, nA, ix->nB, off, P, rec, emitted ? 1 : 0, pt, c64 + 2,
+                               ctr + 4);
         HIPCHK(hipGetLastError(), "band matches");
         tm.mark();  // 4
         // ---- canonical order inside each segment, final records
         fa.nA = nA;
         fa.nB = ix->nB;
         fa.off = off;
-        fa.table = m.table;
+        fa.rec = rec;
+        fa.use_rec = emitted ? 1 : 0;
+        // separations beyond a few degrees need the general decoding
+        fa.rare = shape == C3X_ELLIPSE || area->radius_arcsec >= 5.0 * 3600.0;
         fa.tmp = pt;
         fa.raA = ra;
         fa.decA = dec;
         fa.radecB = ix->radec;
-        fa.bidx = R->best_idx;
+        fa.best_idx = R->best_idx;
         fa.oa = R->idxA;
         fa.ob = R->idxB;
         fa.os = R->sep;
@@ -1615,9 +1728,9 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         tm.mark();  // 5
     }
     if (nA > 0 && !all)
-        hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB,
-                           R->best_idx, astat, ra, dec, ix->radec, R->best_sep, off, P, R->idxA,
-                           R->idxB, R->sep, ctr + 4);
+        hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB, rec, ra,
+                           dec, ix->radec, R->best_idx, R->best_sep, off, P, R->idxA, R->idxB,
+                           R->sep, ctr + 4);
     HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6
     HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
