@@ -109,6 +109,14 @@ typedef struct c3x_index c3x_index;
 typedef struct c3x_result c3x_result;
 typedef struct c3x_batch c3x_batch;
 
+/* One job of a batch: rows [a_off, a_off + nA) of catalogue A against rows
+ * [b_off, b_off + nB) of catalogue B, circle of radius_arcsec (0 or in
+ * [1e-6, 3600]). Jobs are independent; their row ranges may overlap. */
+typedef struct {
+    int64_t a_off, nA, b_off, nB;
+    double radius_arcsec;
+} c3x_job;
+
 /* Counters and phase times of one call (milliseconds from HIP events). */
 typedef struct {
     int64_t n_a, n_b;
@@ -171,6 +179,43 @@ c3x_status c3x_index_stats(const c3x_index *ix, c3x_stats *s);
 
 void c3x_result_free(c3x_result *r);
 void c3x_index_free(c3x_index *ix);
+
+/* Batched form: many independent circular cross-matches (each one the
+ * "Sky" case of Section 2.1 with all and best matches, Section 2.2) in one
+ * graph launch; the paper's partition of the work over concurrent processes
+ * (Section 2.3) becomes one shared index and one launch of each kernel.
+ *
+ * c3x_batch_plan: raA/decA and raB/decB are device FP64 arrays (degrees)
+ * holding every row the jobs name; jobs is a host array of n_jobs entries
+ * (1 <= n_jobs <= 2^22; total nA and total nB each <= 2^31 - 1). The
+ * arrays must stay valid and unchanged in size until c3x_batch_free; the
+ * plan reads them again on every run. Each job's sources must lie within
+ * 10 degrees of their mean direction. opts: precision (FP64 or MIXED);
+ * cell_arcsec, tile and stream are not used (the plan picks cell sizes by
+ * timing a few scales, C3X_BATCH_CELL_SCALE fixes one, and works on a
+ * stream of its own). The plan runs the batch once (its result is ready)
+ * and captures the pipeline into a hipGraph. Errors: EINVAL (bad job, bad
+ * coordinate, a job too spread out), ERANGE (totals), ENOMEM, EDEVICE.
+ * The batch owns its device memory until c3x_batch_free.
+ *
+ * c3x_batch_run: replays the graph after the work already queued on
+ * `stream` (hipStream_t, NULL = null stream) and waits for it. Fails with
+ * EINVAL when the inputs no longer fit the plan (a source outside its
+ * job's planned sky box, or list sizes that changed): plan again.
+ *
+ * c3x_batch_result: a new result holding the last run's output; pairs in
+ * (job, idxA, idxB) order with job-local row indices, best_idxB job-local
+ * (-1: none). c3x_batch_offsets fills n_jobs + 1 host entries: job j's
+ * pairs are [pair_off[j], pair_off[j + 1]); job j's best entries start at
+ * the sum of nA over the jobs before it. */
+c3x_status c3x_batch_plan(const c3x_job *jobs, int32_t n_jobs, const double *raA,
+                          const double *decA, const double *raB, const double *decB,
+                          c3x_frame frame, const c3x_opts *opts, c3x_batch **out);
+c3x_status c3x_batch_run(c3x_batch *b, void *stream);
+c3x_status c3x_batch_result(const c3x_batch *b, c3x_result **out);
+c3x_status c3x_batch_offsets(const c3x_batch *b, int64_t *pair_off);
+c3x_status c3x_batch_stats(const c3x_batch *b, c3x_stats *s);
+void c3x_batch_free(c3x_batch *b);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *c3x_last_error(void);

@@ -2,12 +2,14 @@
 
 Python face of libc3x.so: ``build_index`` over catalogue B and ``match`` of
 catalogue A against it, circle or per-source ellipse areas, "all" and "best"
-selections, equatorial or galactic frames. All computation happens in the
+selections, equatorial or galactic frames; ``Batch`` for many independent
+circular jobs in one graph launch. All computation happens in the
 HIP library; torch tensors only carry device memory and streams.
 """
 from ._binding import (  # noqa: F401
     ALL,
     BEST,
+    Batch,
     CIRCLE,
     ELLIPSE,
     EQUATORIAL,

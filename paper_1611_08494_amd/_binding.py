@@ -41,6 +41,11 @@ class Area(ctypes.Structure):
     ]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("a_off", ctypes.c_int64), ("nA", ctypes.c_int64), ("b_off", ctypes.c_int64),
+                ("nB", ctypes.c_int64), ("radius_arcsec", ctypes.c_double)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int),
@@ -97,6 +102,19 @@ def lib():
     L.c3x_result_free.restype = None
     L.c3x_index_free.argtypes = [vp]
     L.c3x_index_free.restype = None
+    L.c3x_batch_plan.argtypes = [ctypes.POINTER(Job), i32, vp, vp, vp, vp, ctypes.c_int,
+                                 ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.c3x_batch_plan.restype = ctypes.c_int
+    L.c3x_batch_run.argtypes = [vp, vp]
+    L.c3x_batch_run.restype = ctypes.c_int
+    L.c3x_batch_result.argtypes = [vp, ctypes.POINTER(vp)]
+    L.c3x_batch_result.restype = ctypes.c_int
+    L.c3x_batch_offsets.argtypes = [vp, ctypes.POINTER(i64)]
+    L.c3x_batch_offsets.restype = ctypes.c_int
+    L.c3x_batch_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.c3x_batch_stats.restype = ctypes.c_int
+    L.c3x_batch_free.argtypes = [vp]
+    L.c3x_batch_free.restype = None
     L.c3x_last_error.restype = ctypes.c_char_p
     L.c3x_version.restype = ctypes.c_char_p
     L.c3x_abi_version.restype = ctypes.c_int
@@ -235,6 +253,82 @@ def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
     finally:
         lib().c3x_result_free(h)
     return MatchResult(ia, ib, sep, bi, bs, st.as_dict())
+
+
+def _fetch(h, dev) -> MatchResult:
+    torch = _torch()
+    npairs = ctypes.c_int64()
+    na = ctypes.c_int64()
+    check(lib().c3x_result_sizes(h, ctypes.byref(npairs), ctypes.byref(na)))
+    P = npairs.value
+    ia = torch.empty(P, dtype=torch.int32, device=dev)
+    ib = torch.empty(P, dtype=torch.int32, device=dev)
+    sep = torch.empty(P, dtype=torch.float64, device=dev)
+    bi = torch.empty(na.value, dtype=torch.int32, device=dev)
+    bs = torch.empty(na.value, dtype=torch.float64, device=dev)
+    check(lib().c3x_result_copy(h, ia.data_ptr(), ib.data_ptr(), sep.data_ptr(), bi.data_ptr(),
+                                bs.data_ptr(), None))
+    torch.cuda.synchronize(dev)
+    st = Stats()
+    check(lib().c3x_result_stats(h, ctypes.byref(st)))
+    return MatchResult(ia, ib, sep, bi, bs, st.as_dict())
+
+
+class Batch:
+    """A planned batch of independent circular cross-matches (c3x_batch_*).
+    ``jobs`` rows are (a_off, nA, b_off, nB, radius_arcsec). The input
+    tensors are kept alive here: the batch reads them on every run."""
+
+    def __init__(self, jobs, raA, decA, raB, decB, frame: int = EQUATORIAL,
+                 precision: int = MIXED):
+        self._keep = [_dev_f64(x, n) for x, n in ((raA, "raA"), (decA, "decA"), (raB, "raB"),
+                                                    (decB, "decB"))]
+        rows = [tuple(r) for r in jobs]
+        self.n_jobs = len(rows)
+        arr = (Job * max(1, self.n_jobs))()
+        for k, (ao, na, bo, nb, r) in enumerate(rows):
+            arr[k] = Job(int(ao), int(na), int(bo), int(nb), float(r))
+        self._jobs = rows
+        o = Opts(precision=int(precision), cell_arcsec=0.0, tile=0, stream=None)
+        h = ctypes.c_void_p()
+        ra_, de_, rb_, db_ = self._keep
+        check(lib().c3x_batch_plan(arr, self.n_jobs, ra_.data_ptr(), de_.data_ptr(),
+                                   rb_.data_ptr(), db_.data_ptr(), int(frame), ctypes.byref(o),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.device = ra_.device
+
+    def run(self, stream=None):
+        check(lib().c3x_batch_run(self._h, _stream_ptr(stream)))
+
+    def result(self) -> MatchResult:
+        h = ctypes.c_void_p()
+        check(lib().c3x_batch_result(self._h, ctypes.byref(h)))
+        try:
+            return _fetch(h, self.device)
+        finally:
+            lib().c3x_result_free(h)
+
+    def pair_offsets(self):
+        out = (ctypes.c_int64 * (self.n_jobs + 1))()
+        check(lib().c3x_batch_offsets(self._h, out))
+        return list(out)
+
+    def stats(self) -> dict:
+        st = Stats()
+        check(lib().c3x_batch_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def free(self):
+        if self._h:
+            lib().c3x_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def version() -> str:

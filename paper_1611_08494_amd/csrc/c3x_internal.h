@@ -128,6 +128,33 @@ struct alignas(8) ARange {
 };
 static_assert(sizeof(ARange) == 24, "24-byte range record");
 
+// One job of a batch (device job table). Its A and B rows are taken into a
+// local frame whose first axis is the job's mean direction (c, e, n: centre,
+// east, north), where the job's data lie within a few degrees of (0, 0);
+// there a plain (dec', ra') grid of square cells of side h covers the box
+// [-Dr, Dr) x [-Dc, Dc) without poles or RA wrap. Cell (row, col) has key
+// key_base + row * ncol + col in one key space shared by all jobs.
+struct alignas(16) BJob {
+    int64_t a_off, b_off;          // caller rows of the job
+    uint32_t a_ent, b_ent;         // first A / B entry of the job
+    uint32_t nA, nB;
+    uint32_t key_base, ncol, nrow, pad0;
+    double cx, cy, cz, ex, ey, ez, nx, ny, nz;
+    double Dr, Dc, h, inv_h;       // grid box and cell side (degrees)
+    double reach_deg, h_r, cr2, L; // radius, sin^2(r/2), 4 sin^2(r/2), max |p - c|
+    double r_arcsec;               // the radius as given
+    double t64_in, t64_out;
+    float t32_in, t32_out;
+    int32_t r_zero, pad1;
+};
+
+// Thresholds of the circle filters of one source.
+struct Thr {
+    double t64_in, t64_out;
+    float t32_in, t32_out;
+    int32_t r_zero;
+};
+
 // Everything a match kernel needs; passed by value.
 struct MatchArgs {
     Grid g;
@@ -139,6 +166,8 @@ struct MatchArgs {
     const AEll *aell;
     const AEllR *aellr;
     const ARange *arng;    // [nA] sorted A order
+    const BJob *jobs;      // batch: job table, and the job of each sorted A
+    const uint32_t *ajob;
     int32_t nA;
     double reach_deg;      // circle reach
     // circle thresholds on the squared chord
@@ -157,10 +186,12 @@ struct MatchArgs {
     uint32_t *tie_n;       // near-tie best matches: (sorted A pos, row)
     uint2 *tie;
     uint32_t tie_cap;
-    // verdicts of the band candidates: sorted keys (i << 32 | j)
+    // verdicts of the band candidates: sorted keys (i << 32 | j); in a batch
+    // only the host-decided ones, their count in n_ver_dev
     const unsigned long long *ver_key;
     const uint8_t *ver_in;
     uint32_t n_ver;
+    const uint32_t *n_ver_dev;
     // write pass
     const int64_t *off;    // [nA + 1] idxA order
     PairTmp *tmp;          // matches in enumeration order

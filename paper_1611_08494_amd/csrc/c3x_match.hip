@@ -244,6 +244,31 @@ __device__ __forceinline__ ARec load_a(const MatchArgs &m, uint32_t i, double re
     return a;
 }
 
+// Thresholds and FP32 error bound of sorted A position i: the call's, or
+// its job's in a batch.
+template <bool BATCH>
+__device__ __forceinline__ Thr lane_thr(const MatchArgs &m, uint32_t i, double &L)
+{
+    Thr t;
+    if constexpr (BATCH) {
+        const BJob &jb = m.jobs[m.ajob[i]];
+        t.t64_in = jb.t64_in;
+        t.t64_out = jb.t64_out;
+        t.t32_in = jb.t32_in;
+        t.t32_out = jb.t32_out;
+        t.r_zero = jb.r_zero;
+        L = jb.L;
+    } else {
+        t.t64_in = m.t64_in;
+        t.t64_out = m.t64_out;
+        t.t32_in = m.t32_in;
+        t.t32_out = m.t32_out;
+        t.r_zero = m.r_zero;
+        L = m.L_rad;
+    }
+    return t;
+}
+
 struct LaneF32 {            // FP32 copies of the ellipse frame
     float ux, uy, uz, vx, vy, vz, ia, ib;
 };
@@ -255,15 +280,49 @@ struct CellCache {          // A's offset from the reference of the current B ce
     float ax, ay, az;
 };
 
+// Batch: every B offset is from the job's centre, so is the lane's.
+__device__ __forceinline__ void batch_ref(const MatchArgs &m, uint32_t i, const ARec &a,
+                                          CellCache &cc)
+{
+    const BJob &jb = m.jobs[m.ajob[i]];
+    cc.ax = (float)(a.x - jb.cx);
+    cc.ay = (float)(a.y - jb.cy);
+    cc.az = (float)(a.z - jb.cz);
+}
+
+// Calls f(z, j0, j1) for each candidate range of sorted A position i: the
+// ranges found when A was prepared, else (single calls only) a walk of the
+// cells. Returns false for a batch source without ranges.
+template <bool BATCH, typename F>
+__device__ __forceinline__ bool cand_ranges(const MatchArgs &m, uint32_t i, const ARec &a, F &&f)
+{
+    const ARange rg = m.arng[i];
+    if (rg.zlo >= 0) {
+#pragma unroll 1
+        for (int q = 0; q < kRZ; ++q) {
+            const uint32_t j0 = q == 0 ? rg.j0[0] : (q == 1 ? rg.j0[1] : rg.j0[2]);
+            const uint32_t nq = q == 0 ? rg.n[0] : (q == 1 ? rg.n[1] : rg.n[2]);
+            if (nq) f(rg.zlo + q, j0, j0 + nq);
+        }
+        return true;
+    }
+    if constexpr (BATCH) {
+        return false;
+    } else {
+        for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, f);
+        return true;
+    }
+}
+
 // Fast certified filter of one candidate: IN, OUT, or AMBIG when the pair
 // lies inside the filter's error band (then the FP64 relative-accuracy
 // recheck decides it, in k_recheck). Also returns the filter's squared chord.
 // Radius 0 is decided structurally here (same point), without a band.
-template <int SHAPE, int PREC>
+template <int SHAPE, int PREC, bool BATCH>
 __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const AEll &e,
-                                      const AEllR &er, const LaneF32 &f, CellCache &cc, int z,
-                                      const ZoneInfo &zi, uint32_t key, const PayOf<PREC> &b,
-                                      uint32_t j, double &c2o)
+                                      const AEllR &er, const LaneF32 &f, CellCache &cc,
+                                      const Thr &th, int z, const ZoneInfo &zi, uint32_t key,
+                                      const PayOf<PREC> &b, uint32_t j, double &c2o)
 {
     int d;
     if constexpr (PREC == C3X_FP64) {
@@ -271,7 +330,7 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
         double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
         c2o = c2;
         if constexpr (SHAPE == C3X_CIRCLE) {
-            d = c2 <= m.t64_in ? IN : (c2 > m.t64_out ? OUT : AMBIG);
+            d = c2 <= th.t64_in ? IN : (c2 > th.t64_out ? OUT : AMBIG);
         } else {
             double su = fma(dx, e.ux, fma(dy, e.uy, dz * e.uz));
             double sv = fma(dx, e.vx, fma(dy, e.vy, dz * e.vz));
@@ -281,7 +340,8 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
             d = qf <= 1.0 - er.m64 ? IN : (qf > 1.0 + er.m64 ? OUT : AMBIG);
         }
     } else {
-        if (key != cc.key) {
+        // batch: the offsets are from the job's centre, set once per lane
+        if (!BATCH && key != cc.key) {
             cc.key = key;
             const uint32_t st = ref_step(zi, key - zi.base);
             const uint32_t rf = ((uint32_t)z << kRefBits) | st;
@@ -298,7 +358,7 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
         float c2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         c2o = (double)c2;
         if constexpr (SHAPE == C3X_CIRCLE) {
-            d = c2 <= m.t32_in ? IN : (c2 > m.t32_out ? OUT : AMBIG);
+            d = c2 <= th.t32_in ? IN : (c2 > th.t32_out ? OUT : AMBIG);
         } else {
             float su = fmaf(dx, f.ux, fmaf(dy, f.uy, dz * f.uz));
             float sv = fmaf(dx, f.vx, fmaf(dy, f.vy, dz * f.vz));
@@ -310,7 +370,7 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
         }
     }
     if constexpr (SHAPE == C3X_CIRCLE) {
-        if (m.r_zero) d = same_point(a, m.radecB[j]) ? IN : OUT;
+        if (th.r_zero) d = same_point(a, m.radecB[j]) ? IN : OUT;
     }
     return d;
 }
@@ -318,15 +378,31 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
 __device__ __forceinline__ int verdict(const MatchArgs &m, uint32_t i, uint32_t j)
 {
     unsigned long long k = ((unsigned long long)i << 32) | j;
-    uint32_t lo = 0, hi = m.n_ver;
+    uint32_t lo = 0, hi = m.n_ver_dev ? min(*m.n_ver_dev, m.n_ver) : m.n_ver;
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
         if (m.ver_key[mid] < k) lo = mid + 1;
         else hi = mid;
     }
-    if (lo < m.n_ver && m.ver_key[lo] == k) return m.ver_in[lo] ? IN : OUT;
+    if (lo < hi && m.ver_key[lo] == k) return m.ver_in[lo] ? IN : OUT;
     atomicOr(m.err_flag, 4u);
     return OUT;
+}
+
+// Verdict of a band candidate: in a single call, the table built from the
+// recheck; in a batch, the FP64 recheck again (the same decision the recheck
+// kernel took), then the host-decided table for what it leaves open.
+template <bool BATCH>
+__device__ __forceinline__ int band_verdict(const MatchArgs &m, uint32_t i, uint32_t j,
+                                            const ARec &a)
+{
+    if constexpr (BATCH) {
+        ARec q = a;
+        q.cosd = cos_dec_acc(a.dec);
+        const int d = recheck_circle(q, m.radecB[j], m.jobs[m.ajob[i]].h_r);
+        if (d != AMBIG) return d;
+    }
+    return verdict(m, i, j);
 }
 
 // Error bound of the filter's squared chord at chord c (see circle_thresholds).
@@ -365,7 +441,8 @@ __device__ __forceinline__ double sep_from_chord2(double c2)
 // MODE 0: count + best; MODE 1: write every filter match into the
 // offsets from the count; MODE 2: count + best, the row's first kTab filter
 // matches kept for its record, later ones written to the overflow list.
-template <int SHAPE, int PREC, int MODE>
+// BATCH: a batch of jobs (per-source thresholds and centre, local grids).
+template <int SHAPE, int PREC, int MODE, bool BATCH>
 __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 {
     using PayT = PayOf<PREC>;
@@ -399,6 +476,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         rg = m.arng[i];
         a = load_a(m, i, reach);
     }
+    double Lr = 0.0;
+    const Thr th = lane_thr<BATCH>(m, active ? i : 0u, Lr);
 
     uint32_t cnt = 0;
     double b1 = INFINITY, b2 = INFINITY;
@@ -413,6 +492,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     }
     unsigned long long tests = 0, band = 0, placed = 0;
     CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
+    if (BATCH && active) batch_ref(m, i, a, cc);
 
     // A filter match as written: the separation coded from the FP64 chord
     // (the FP64 path's filter chord; the mixed path recomputes it from the
@@ -461,7 +541,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     auto visit = [&](int z, const ZoneInfo &zi, uint32_t key, const PayT &b, uint32_t j) {
         ++tests;
         double c2;
-        int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, zi, key, b, j, c2);
+        int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, key, b, j, c2);
         if (d == AMBIG) {
             if (MODE != 1) {
                 ++band;
@@ -516,7 +596,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                 const uint32_t nq = q == 0 ? rg.n[0] : (q == 1 ? rg.n[1] : rg.n[2]);
                 if (nq == 0) continue;
                 const int z = rg.zlo + q;
-                const ZoneInfo zi = m.g.zinfo[z];
+                ZoneInfo zi{};
+                if (!BATCH) zi = m.g.zinfo[z];
                 for (uint32_t t = 0; t < nq; t += kBatch) {
                     PayT bb[kBatch];
                     uint32_t kk[kBatch];
@@ -531,6 +612,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                         if (t + u < nq) visit(z, zi, kk[u], bb[u], j0 + t + u);
                 }
             }
+        } else if constexpr (BATCH) {
+            atomicOr(m.err_flag, 64u);  // the plan guarantees ranges
         } else {
             // split at RA 0/360, many zones or long ranges: walk the cells
             for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
@@ -554,7 +637,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         r.c[1] = tc1;
         m.rec[a.idx] = r;
         if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
-        if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), m.L_rad)) {
+        if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), Lr)) {
             uint32_t slot = atomicAdd(m.tie_n, 1u);
             if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
         }
@@ -572,7 +655,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 
 // Every match of the listed sorted A positions (best-match re-ranking): one
 // wavefront per listed source, lanes striding over its candidate ranges.
-template <int SHAPE, int PREC>
+template <int SHAPE, int PREC, bool BATCH>
 __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
 {
     using PayT = PayOf<PREC>;
@@ -595,13 +678,17 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
     }
     ARec a = load_a(m, i, reach);
     CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
-    for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
-        const ZoneInfo zi = m.g.zinfo[z];
+    if (BATCH) batch_ref(m, i, a, cc);
+    double Lr;
+    const Thr th = lane_thr<BATCH>(m, i, Lr);
+    cand_ranges<BATCH>(m, i, a, [&](int z, uint32_t j0, uint32_t j1) {
+        ZoneInfo zi{};
+        if (!BATCH) zi = m.g.zinfo[z];
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
-            int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, zi, m.g.keys[j], b, j, c2);
-            if (d == AMBIG) d = verdict(m, i, j);
+            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, m.g.keys[j], b, j, c2);
+            if (d == AMBIG) d = band_verdict<BATCH>(m, i, j, a);
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
             if (slot < m.col_cap) {
@@ -646,18 +733,15 @@ __device__ __forceinline__ Cand cand_shfl_xor(const Cand &x, int o)
 // from the FP64 unit vectors (error c2_err<FP64>); when the runner-up is
 // further than 4 such errors the best is certain and written to the row's
 // record, otherwise the row is listed for the host's binary128 ranking.
-template <int SHAPE, int PREC>
-__global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__restrict__ pos,
-                                               uint32_t n, uint32_t *__restrict__ unc_n,
-                                               uint32_t *__restrict__ unc)
+template <int SHAPE, int PREC, bool BATCH>
+__device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
+                                           uint32_t *__restrict__ unc_n,
+                                           uint32_t *__restrict__ unc)
 {
     using PayT = PayOf<PREC>;
-    const uint32_t t = blockIdx.x;
-    if (t >= n) return;
     const PayT *pay;
     if constexpr (PREC == C3X_FP64) pay = m.pay64;
     else pay = m.pay32;
-    const uint32_t i = pos[t];
     AEll e{};
     AEllR er{};
     LaneF32 f{};
@@ -671,14 +755,18 @@ __global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__re
     }
     const ARec a = load_a(m, i, reach);
     CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
+    if (BATCH) batch_ref(m, i, a, cc);
+    double Lr;
+    const Thr th = lane_thr<BATCH>(m, i, Lr);
     Cand b1{INFINITY, 0xffffffffu, 0u}, b2{INFINITY, 0xffffffffu, 0u};
-    for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
-        const ZoneInfo zi = m.g.zinfo[z];
+    cand_ranges<BATCH>(m, i, a, [&](int z, uint32_t j0, uint32_t j1) {
+        ZoneInfo zi{};
+        if (!BATCH) zi = m.g.zinfo[z];
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
-            int d = decide<SHAPE, PREC>(m, a, e, er, f, cc, z, zi, m.g.keys[j], b, j, c2);
-            if (d == AMBIG) d = verdict(m, i, j);
+            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, m.g.keys[j], b, j, c2);
+            if (d == AMBIG) d = band_verdict<BATCH>(m, i, j, a);
             if (d != IN) continue;
             const Pay64 b8 = m.pay64[j];
             const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
@@ -702,7 +790,7 @@ __global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__re
         b2 = s2;
     }
     if (threadIdx.x == 0 && b1.idxB != 0xffffffffu) {
-        const uint32_t row = m.aidx[i];
+        const uint32_t row = a.idx;
         const bool sure = b2.idxB == 0xffffffffu ||
                           b2.c2 - b1.c2 > 4.0 * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
         if (sure) {
@@ -712,6 +800,19 @@ __global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__re
             unc[atomicAdd(unc_n, 1u)] = i;
         }
     }
+}
+
+// One wavefront per listed row (grid-stride over the list; the count may
+// live on the device).
+template <int SHAPE, int PREC, bool BATCH>
+__global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__restrict__ pos,
+                                               uint32_t n, const uint32_t *__restrict__ n_dev,
+                                               uint32_t *__restrict__ unc_n,
+                                               uint32_t *__restrict__ unc)
+{
+    const uint32_t nn = n_dev ? min(n, *n_dev) : n;
+    for (uint32_t t = blockIdx.x; t < nn; t += gridDim.x)
+        rerank_one<SHAPE, PREC, BATCH>(m, pos[t], unc_n, unc);
 }
 
 // ---------------------------------------------------------------------------- small kernels
@@ -821,6 +922,7 @@ __global__ void k_place_ov(const OvEnt *__restrict__ ovl, uint32_t ov_pool,
 // when the single pass filled the records) or its place in the idxA-order
 // segments, with its separation.
 __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
+                          const uint32_t *__restrict__ nx_dev,
                           const uint32_t *__restrict__ aidx, const double2 *__restrict__ arad,
                           const double2 *__restrict__ radecB, int64_t nA, int64_t nB,
                           const int64_t *__restrict__ off, int64_t P, RowRec *__restrict__ rec,
@@ -829,7 +931,7 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
                           uint32_t *__restrict__ err)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nx) return;
+    if (t >= nx || (nx_dev && t >= *nx_dev)) return;
     const WEnt e = xent[t];
     if (e.i >= (uint64_t)nA || e.j >= (uint64_t)nB) {
         atomicOr(err, 16u);
@@ -937,7 +1039,7 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
 // segment). A longer one has its record's matches copied into the segment,
 // which k_seg_lds then finishes.
 template <bool RARE>
-__global__ void k_finalize(int64_t nA, int64_t nB, const int64_t *__restrict__ off,
+__global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *__restrict__ off,
                            const RowRec *__restrict__ rec, int use_rec, PairTmp *__restrict__ tmp,
                            const double *__restrict__ raA, const double *__restrict__ decA,
                            const double2 *__restrict__ radecB, int32_t *__restrict__ best_idx,
@@ -949,6 +1051,10 @@ __global__ void k_finalize(int64_t nA, int64_t nB, const int64_t *__restrict__ o
     if (a >= nA) return;
     const int64_t o = off[a], len = off[a + 1] - o;
     bsep[a] = NAN;
+    if (o + len > pcap) {  // outputs sized for fewer pairs (a batch replay)
+        atomicOr(err, 1u);
+        return;
+    }
     if (len <= 0) {
         best_idx[a] = -1;
         return;
@@ -1038,6 +1144,7 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                                                  const uint32_t *__restrict__ cnt,
                                                  const uint32_t *__restrict__ list, uint32_t cap,
                                                  const PairTmp *__restrict__ tmp, int64_t nB,
+                                                 int64_t pcap,
                                                  const double *__restrict__ raA,
                                                  const double *__restrict__ decA,
                                                  const double2 *__restrict__ radecB,
@@ -1053,6 +1160,7 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
     for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
         const uint32_t a = list[b];
         const int64_t o = off[a];
+        if (off[a + 1] > pcap) continue;  // reported by the finalize kernel
         const int len = (int)min<int64_t>(off[a + 1] - o, 1 << 30);
         if (len > kSegLds) {
             if (threadIdx.x == 0) {
@@ -1125,6 +1233,7 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 // What the finishing kernels need.
 struct FinishArgs {
     int64_t nA, nB;
+    int64_t pcap;          // pairs the outputs hold
     const int64_t *off;
     const RowRec *rec;
     int use_rec, rare;
@@ -1150,13 +1259,13 @@ static void finish_segments(const FinishArgs &f, hipStream_t s)
 #define C3X_FIN(R)                                                                                \
     do {                                                                                          \
         hipLaunchKernelGGL(k_finalize<R>, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB,      \
-                           f.off, f.rec, f.use_rec, f.tmp, f.raA, f.decA, f.radecB, f.best_idx,   \
-                           f.oa, f.ob, f.os, f.bsep, f.err);                                      \
+                           f.pcap, f.off, f.rec, f.use_rec, f.tmp, f.raA, f.decA, f.radecB,       \
+                           f.best_idx, f.oa, f.ob, f.os, f.bsep, f.err);                          \
         hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA,        \
                            f.seg_n, f.list, f.cap);                                               \
         hipLaunchKernelGGL(k_seg_lds<R>, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list,  \
-                           f.cap, f.tmp, f.nB, f.raA, f.decA, f.radecB, f.rec, f.oa, f.ob, f.os,  \
-                           f.bsep, f.seg_n + 1, f.huge, f.err);                                   \
+                           f.cap, f.tmp, f.nB, f.pcap, f.raA, f.decA, f.radecB, f.rec, f.oa,      \
+                           f.ob, f.os, f.bsep, f.seg_n + 1, f.huge, f.err);                       \
     } while (0)
     if (f.rare) C3X_FIN(true);
     else C3X_FIN(false);
@@ -1247,7 +1356,7 @@ static void launch_match(const MatchArgs &m, int shape, int prec, unsigned grid,
 {
     if (grid == 0) return;
 #define C3X_LAUNCH(SH, PR) \
-    hipLaunchKernelGGL((k_match<SH, PR, MODE>), dim3(grid), dim3(kMatchBlock), 0, s, m)
+    hipLaunchKernelGGL((k_match<SH, PR, MODE, false>), dim3(grid), dim3(kMatchBlock), 0, s, m)
     if (shape == C3X_CIRCLE) {
         if (prec == C3X_FP64) C3X_LAUNCH(C3X_CIRCLE, C3X_FP64);
         else C3X_LAUNCH(C3X_CIRCLE, C3X_MIXED);
@@ -1263,7 +1372,8 @@ static void launch_rerank(const MatchArgs &m, int shape, int prec, const uint32_
 {
     if (n == 0) return;
 #define C3X_RR(SH, PR) \
-    hipLaunchKernelGGL((k_rerank<SH, PR>), dim3(n), dim3(64), 0, s, m, pos, n, unc_n, unc)
+    hipLaunchKernelGGL((k_rerank<SH, PR, false>), dim3(n), dim3(64), 0, s, m, pos, n, nullptr, \
+                       unc_n, unc)
     if (shape == C3X_CIRCLE) {
         if (prec == C3X_FP64) C3X_RR(C3X_CIRCLE, C3X_FP64);
         else C3X_RR(C3X_CIRCLE, C3X_MIXED);
@@ -1280,14 +1390,14 @@ static void launch_collect(const MatchArgs &m, int shape, int prec, hipStream_t 
     if (grid == 0) return;
     if (shape == C3X_CIRCLE) {
         if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_FP64>), dim3(grid), dim3(64), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_FP64, false>), dim3(grid), dim3(64), 0, s, m);
         else
-            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_MIXED>), dim3(grid), dim3(64), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_MIXED, false>), dim3(grid), dim3(64), 0, s, m);
     } else {
         if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_FP64>), dim3(grid), dim3(64), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_FP64, false>), dim3(grid), dim3(64), 0, s, m);
         else
-            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_MIXED>), dim3(grid), dim3(64), 0, s, m);
+            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_MIXED, false>), dim3(grid), dim3(64), 0, s, m);
     }
 }
 
@@ -1692,7 +1802,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         }
         HIPCHK(hipGetLastError(), "write pass");
         if (n_x > 0)
-            hipLaunchKernelGGL(k_place_x, dim3(nblk(n_x, 256)), dim3(256), 0, s, xent, n_x, aidx,
+            hipLaunchKernelGGL(k_place_x, dim3(nblk(n_x, 256)), dim3(256), 0, s, xent, n_x, nullptr,
+                               aidx,
                                arad, ix->radec, nA, ix->nB, off, P, rec, emitted ? 1 : 0, pt, c64 + 2,
                                ctr + 4);
         HIPCHK(hipGetLastError(), "band matches");
@@ -1700,6 +1811,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         // ---- canonical order inside each segment, final records
         fa.nA = nA;
         fa.nB = ix->nB;
+        fa.pcap = P;
         fa.off = off;
         fa.rec = rec;
         fa.use_rec = emitted ? 1 : 0;
@@ -1847,3 +1959,6 @@ extern "C" c3x_status c3x_result_stats(const c3x_result *r, c3x_stats *st)
 }
 
 extern "C" void c3x_result_free(c3x_result *r) { delete r; }
+
+// The batched form: its kernels and entry points use the ones above.
+#include "c3x_batch.hip"

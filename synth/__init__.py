@@ -10,6 +10,7 @@ from .catalogues import (  # noqa: F401
     cap_uniform,
     destination,
     jitter,
+    sphere_uniform,
     cfg1_patch,
     cfg2_fullsky,
     cfg3_galactic_ellipses,

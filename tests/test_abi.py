@@ -59,6 +59,27 @@ def test_argument_errors_need_no_device(L):
     assert L.c3x_result_sizes(None, None, None) == b.EINVAL
 
 
+def test_batch_argument_errors_need_no_device(L):
+    from paper_1611_08494_amd import _binding as b
+    b.lib()  # argument types
+    h = ctypes.c_void_p()
+    jobs = (b.Job * 2)(b.Job(0, 10, 0, 10, 1.0), b.Job(10, 5, 10, 5, 1.0))
+    assert L.c3x_batch_plan(jobs, 0, None, None, None, None, 0, None, ctypes.byref(h)) == b.EINVAL
+    assert h.value is None
+    bad = (b.Job * 1)(b.Job(-1, 10, 0, 10, 1.0))
+    assert L.c3x_batch_plan(bad, 1, None, None, None, None, 0, None, ctypes.byref(h)) == b.EINVAL
+    assert b"negative" in L.c3x_last_error()
+    wide = (b.Job * 1)(b.Job(0, 10, 0, 10, 7200.0))
+    assert L.c3x_batch_plan(wide, 1, None, None, None, None, 0, None, ctypes.byref(h)) == b.EINVAL
+    assert b"radius" in L.c3x_last_error()
+    big = (b.Job * 2)(b.Job(0, 1 << 30, 0, 1, 1.0), b.Job(0, 1 << 30, 0, 1, 1.0))
+    assert L.c3x_batch_plan(big, 2, None, None, None, None, 0, None, ctypes.byref(h)) == b.ERANGE
+    assert L.c3x_batch_plan(jobs, 2, None, None, None, None, 0, None, ctypes.byref(h)) == b.EINVAL
+    assert b"NULL" in L.c3x_last_error()
+    assert L.c3x_batch_run(None, None) == b.EINVAL
+    assert L.c3x_batch_result(None, None) == b.EINVAL
+
+
 def _q(L):
     L.c3x_q_circle.argtypes = [ctypes.c_double] * 5
     L.c3x_q_circle.restype = ctypes.c_int
