@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the positional cross-match hot path on one MI355X.
 
-Workload: the full-sky catalogue pair, 10M A x 10M B (8M uniform on the
-sphere plus two dense 1M caps, one straddling RA = 0/360 and one holding the
-north pole; B = 6M jittered copies of A rows + 4M random), radius 2", all +
-best matches. One step = c3x_build_index over B + c3x_match of A (both
-catalogues already resident in HBM), i.e. every phase of the path: keying,
-sorting, directory, A preparation, count, scan, write, best, ordering.
+Default workload (the headline line): the full-sky catalogue pair, 10M A x
+10M B (8M uniform on the sphere plus two dense 1M caps, one straddling RA =
+0/360 and one holding the north pole; B = 6M jittered copies of A rows + 4M
+random), radius 2", all + best matches. One step = c3x_build_index over B +
+c3x_match of A (both catalogues already resident in HBM): keying, sorting,
+directory, A preparation, count and emission, band recheck, scan,
+placement, best, ordering.
 
 The headline value is A-sources matched per second of the mixed path (FP32
 filter + FP64 recheck); the FP64 path, pair tests per second, the roofline of
 the dominant kernel and the CPU oracle timed on this host are reported beside
-it. Prints one JSON line.
+it. --config picks the other workloads (one JSON line each):
+  cfg1  10k x 10k patch, r = 1" (launch-latency bound; microseconds)
+  cfg3  100k galactic ellipses against 50M in-band sources, all matches
+  cfg4  4,096 independent circular jobs in one graph launch (batched form)
+  cfg5  200M x 200M full sky with galactic-plane clustering, r = 1.5"
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "A-sources matched/s + pair tests/s, mixed vs FP64 path (exact pair set)"
 
 
 def parse():
@@ -33,6 +40,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"], default="cfg2")
     p.add_argument("--scale", type=float, default=1.0,
                    help="shrink the workload (testing only; the reported line uses 1.0)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -43,13 +51,22 @@ def parse():
     return p.parse_args()
 
 
-def run_path(c3x, torch, tens, cat, precision, steps, warmup):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def mean(xs):
+    return sum(xs) / max(1, len(xs))
+
+
+def run_path(c3x, torch, tens, cat, precision, steps, warmup, area_kw, frame, mode):
     raA, decA, raB, decB = tens
     last = {}
 
     def step():
-        ix = c3x.build_index(raB, decB, reach_hint_arcsec=cat.radius_arcsec, precision=precision)
-        r = c3x.match(ix, raA, decA, radius_arcsec=cat.radius_arcsec, mode=c3x.ALL | c3x.BEST)
+        ix = c3x.build_index(raB, decB, frame=frame, reach_hint_arcsec=cat.reach_arcsec(),
+                             precision=precision)
+        r = c3x.match(ix, raA, decA, frame=frame, mode=mode, **area_kw)
         last["index"] = ix.stats()
         ix.free()
         last["r"] = r
@@ -68,8 +85,234 @@ def run_path(c3x, torch, tens, cat, precision, steps, warmup):
     return ms, last["r"], kstats
 
 
-def mean(xs):
-    return sum(xs) / max(1, len(xs))
+def path_summary(cat, ms, r, ks):
+    ist = [k[0] for k in ks]
+    mst = [k[1] for k in ks]
+    return dict(
+        ms_per_step=ms,
+        a_per_s=cat.nA / (ms / 1e3),
+        pair_tests=int(mst[-1]["n_tests"]),
+        pair_tests_per_s=mst[-1]["n_tests"] / (ms / 1e3),
+        n_pairs=int(r.n_pairs),
+        n_band=int(mst[-1]["n_band"]),
+        n_ambiguous=int(mst[-1]["n_ambiguous"]),
+        n_best_ties=int(mst[-1]["n_best_ties"]),
+        phases_ms=dict(
+            index=mean([s["ms_index"] for s in ist]),
+            a_prep=mean([s["ms_a_prep"] for s in mst]),
+            count=mean([s["ms_count"] for s in mst]),
+            scan=mean([s["ms_scan"] for s in mst]),
+            write=mean([s["ms_write"] for s in mst]),
+            order=mean([s["ms_sort_pairs"] for s in mst]),
+            match_total=mean([s["ms_total"] for s in mst]),
+        ),
+        cell_arcsec=ist[-1]["cell_arcsec"],
+        n_cells=int(ist[-1]["n_cells"]),
+    )
+
+
+def oracle_baseline(cat, area_kw_np, threads, sample_rows, what):
+    """The CPU oracle (plain C, FP64 certified + mpmath) on the first
+    ``sample_rows`` A rows against all of B, timed on this host."""
+    import numpy as np
+    import oracle
+    n = min(cat.nA, sample_rows)
+    kw = dict(area_kw_np)
+    for k in ("a", "b", "pa"):
+        if k in kw:
+            kw[k] = np.ascontiguousarray(kw[k][:n])
+    t = time.perf_counter()
+    o = oracle.match(cat.raA[:n], cat.decA[:n], cat.raB, cat.decB, nthreads=threads, **kw)
+    dt = time.perf_counter() - t
+    return {"value": round(n / dt, 1), "unit": "A-sources/s", "cores": int(o.threads),
+            "kind": "oracle", "sample": f"{what}: first {n} A rows against all {cat.nB} B rows "
+            f"(index build included), {dt:.1f}s wall"}, o
+
+
+def single_config(a, c3x, torch, np, name):
+    import synth
+    gen = {"cfg1": lambda: synth.cfg1_patch(),
+           "cfg2": lambda: synth.cfg2_fullsky(scale=a.scale),
+           "cfg3": lambda: synth.cfg3_galactic_ellipses(scale=a.scale),
+           "cfg5": lambda: synth.cfg5_scale(scale=a.scale)}[name]
+    t = time.perf_counter()
+    cat = gen()
+    log(f"generated {cat.name} ({cat.nA} A, {cat.nB} B) in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    tens = [torch.as_tensor(x, device=dev) for x in (cat.raA, cat.decA, cat.raB, cat.decB)]
+    frame = c3x.GALACTIC if cat.frame == 1 else c3x.EQUATORIAL
+    if cat.shape == 1:
+        area_kw = dict(shape=c3x.ELLIPSE, a=torch.as_tensor(cat.a_arcsec, device=dev),
+                       b=torch.as_tensor(cat.b_arcsec, device=dev),
+                       pa=torch.as_tensor(cat.pa_deg, device=dev), pa_zero_deg=cat.pa_zero_deg,
+                       pa_sense=cat.pa_sense)
+        area_np = dict(shape=1, a=cat.a_arcsec, b=cat.b_arcsec, pa=cat.pa_deg,
+                       pa_zero_deg=cat.pa_zero_deg, pa_sense=cat.pa_sense)
+        mode = c3x.ALL
+    else:
+        area_kw = dict(shape=c3x.CIRCLE, radius_arcsec=cat.radius_arcsec)
+        area_np = dict(shape=0, radius_arcsec=cat.radius_arcsec)
+        mode = c3x.ALL | c3x.BEST
+    torch.cuda.synchronize()
+    if a.calib_copy_mb:
+        n = a.calib_copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {a.calib_copy_mb} MiB done")
+        del src, dst
+
+    paths = {}
+    order = {"both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"]}[a.precision]
+    for pname in order:
+        prec = c3x.MIXED if pname == "mixed" else c3x.FP64
+        ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup, area_kw, frame, mode)
+        paths[pname] = path_summary(cat, ms, r, ks)
+        log(f"{pname}: {ms:.3f} ms/step, {paths[pname]['phases_ms']}")
+        del r
+
+    head = paths[order[0]]
+    # Dominant kernel of the path: the single pass that counts and emits the
+    # matches (k_match<..., 2>, one launch per step); its duration is the
+    # library's HIP-event timer around that launch (same stream). Algorithmic
+    # bytes per launch: every A record read once (sorted coordinates 16 B,
+    # row 4 B, candidate ranges 24 B) and its count and record written (4 +
+    # 32 B); every B payload read at least once (16 B mixed, 32 B FP64, plus
+    # the 4 B key).
+    hp = head["phases_ms"]
+    pay = 16 if order[0] == "mixed" else 32
+    alg_bytes = cat.nA * (16 + 4 + 24 + 4 + 32) + cat.nB * (pay + 4)
+    achieved = alg_bytes / (hp["count"] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_match (count + emit pass)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": int(alg_bytes),
+                "kernel_ms": round(hp["count"], 4)}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        threads = a.cpu_threads or min(16, os.cpu_count() or 1)
+        sample = {"cfg1": cat.nA, "cfg2": cat.nA, "cfg3": 20_000, "cfg5": 2_000_000}[name]
+        cpu, o = oracle_baseline(cat, area_np, threads, sample, name)
+        if sample >= cat.nA and int(len(o.ia)) != head["n_pairs"]:
+            log(f"WARNING: oracle pairs {len(o.ia)} != GPU {head['n_pairs']}")
+
+    workloads = {
+        "cfg1": "1 deg patch 10k A x 10k B, r=1\", all+best, index build + match per step",
+        "cfg2": "full-sky 10M A x 10M B + dense caps (RA 0/360, north pole), r=2\", all+best, "
+                "index build + match per step",
+        "cfg3": "galactic band 100k ellipse A (a 5-60\") x 50M B, all matches, index build + "
+                "match per step",
+        "cfg5": "full-sky 200M A x 200M B, galactic-plane clustering, r=1.5\", all+best, index "
+                "build + match per step",
+    }
+    line = {
+        "metric": METRIC,
+        "value": round(head["a_per_s"], 1),
+        "unit": "A-sources/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if order[0] == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": workloads[name], "nA": cat.nA, "nB": cat.nB,
+                   "scale": a.scale, "parallelism": "single GPU"},
+        "pair_tests_per_s": round(head["pair_tests_per_s"], 1),
+        "paths": paths,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if "fp64" in paths and "mixed" in paths:
+        line["speedup_mixed_vs_fp64"] = round(paths["fp64"]["ms_per_step"] /
+                                              paths["mixed"]["ms_per_step"], 3)
+    return line
+
+
+def batch_config(a, c3x, torch, np):
+    import synth
+    t = time.perf_counter()
+    cat = synth.cfg4_jobs(scale=a.scale)
+    jobs = [tuple(int(v) for v in r[:4]) + (float(r[4]),) for r in cat.jobs]
+    log(f"generated {cat.name}: {len(jobs)} jobs, {cat.nA} A, {cat.nB} B in "
+        f"{time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    tens = [torch.as_tensor(x, device=dev) for x in (cat.raA, cat.decA, cat.raB, cat.decB)]
+    torch.cuda.synchronize()
+    paths = {}
+    order = {"both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"]}[a.precision]
+    for pname in order:
+        prec = c3x.MIXED if pname == "mixed" else c3x.FP64
+        t = time.perf_counter()
+        b = c3x.Batch(jobs, *tens, precision=prec)
+        plan_s = time.perf_counter() - t
+        for _ in range(a.warmup):
+            b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gms = []
+        for _ in range(a.steps):
+            b.run()
+            gms.append(b.stats()["ms_total"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / a.steps
+        st = b.stats()
+        paths[pname] = dict(ms_per_step=ms, graph_ms=mean(gms), a_per_s=cat.nA / (ms / 1e3),
+                            pair_tests=int(st["n_tests"]),
+                            pair_tests_per_s=st["n_tests"] / (ms / 1e3),
+                            n_pairs=int(st["n_pairs"]), n_band=int(st["n_band"]),
+                            n_ambiguous=int(st["n_ambiguous"]),
+                            n_best_ties=int(st["n_best_ties"]), plan_s=round(plan_s, 2),
+                            cell_scale=st["cell_arcsec"])
+        log(f"{pname}: {ms:.3f} ms/step (graph {mean(gms):.3f} ms), plan {plan_s:.1f}s")
+        b.free()
+    head = paths[order[0]]
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        threads = a.cpu_threads or min(16, os.cpu_count() or 1)
+        t = time.perf_counter()
+        n = 0
+        for (ao, na, bo, nb, r) in jobs:
+            oracle.match(cat.raA[ao:ao + na], cat.decA[ao:ao + na], cat.raB[bo:bo + nb],
+                         cat.decB[bo:bo + nb], radius_arcsec=r, nthreads=threads)
+            n += na
+            if time.perf_counter() - t > 20.0:
+                break
+        dt = time.perf_counter() - t
+        cpu = {"value": round(n / dt, 1), "unit": "A-sources/s", "cores": threads,
+               "kind": "oracle", "sample": f"cfg4: jobs in order until 20 s ({n} A rows), "
+               f"{dt:.1f}s wall"}
+    line = {
+        "metric": METRIC,
+        "value": round(head["a_per_s"], 1),
+        "unit": "A-sources/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if order[0] == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(jobs)} circular jobs (nA lognormal median 2k, "
+                               "nB = 10 nA, 0.5 deg caps, r U[0.5, 10)\"), one graph launch "
+                               "per step", "nA": cat.nA, "nB": cat.nB, "scale": a.scale,
+                   "parallelism": "single GPU"},
+        "pair_tests_per_s": round(head["pair_tests_per_s"], 1),
+        "paths": paths,
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    if "fp64" in paths and "mixed" in paths:
+        line["speedup_mixed_vs_fp64"] = round(paths["fp64"]["ms_per_step"] /
+                                              paths["mixed"]["ms_per_step"], 3)
+    return line
 
 
 def main():
@@ -83,113 +326,11 @@ def main():
     import torch
 
     import paper_1611_08494_amd as c3x
-    import synth
 
-    dev = torch.device("cuda:0")
-    t = time.perf_counter()
-    cat = synth.cfg2_fullsky(scale=a.scale)
-    gen_s = time.perf_counter() - t
-    print(f"[bench] generated {cat.name} in {gen_s:.1f}s", file=sys.stderr, flush=True)
-    tens = [torch.as_tensor(x, device=dev) for x in (cat.raA, cat.decA, cat.raB, cat.decB)]
-    torch.cuda.synchronize()
-    if a.calib_copy_mb:
-        n = a.calib_copy_mb * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {a.calib_copy_mb} MiB done", file=sys.stderr)
-        del src, dst
-
-    paths = {}
-    order = {"both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"]}[a.precision]
-    for name in order:
-        prec = c3x.MIXED if name == "mixed" else c3x.FP64
-        ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup)
-        ist = [k[0] for k in ks]
-        mst = [k[1] for k in ks]
-        paths[name] = dict(
-            ms_per_step=ms,
-            a_per_s=cat.nA / (ms / 1e3),
-            pair_tests=int(mst[-1]["n_tests"]),
-            pair_tests_per_s=mst[-1]["n_tests"] / (ms / 1e3),
-            n_pairs=int(r.n_pairs),
-            n_band=int(mst[-1]["n_band"]),
-            n_ambiguous=int(mst[-1]["n_ambiguous"]),
-            n_best_ties=int(mst[-1]["n_best_ties"]),
-            phases_ms=dict(
-                index=mean([s["ms_index"] for s in ist]),
-                a_prep=mean([s["ms_a_prep"] for s in mst]),
-                count=mean([s["ms_count"] for s in mst]),
-                scan=mean([s["ms_scan"] for s in mst]),
-                write=mean([s["ms_write"] for s in mst]),
-                order=mean([s["ms_sort_pairs"] for s in mst]),
-                match_total=mean([s["ms_total"] for s in mst]),
-            ),
-            cell_arcsec=ist[-1]["cell_arcsec"],
-            n_cells=int(ist[-1]["n_cells"]),
-        )
-        print(f"[bench] {name}: {ms:.3f} ms/step, {paths[name]['phases_ms']}", file=sys.stderr,
-              flush=True)
-        del r
-
-    head = paths[order[0]]
-    # Dominant kernel of the headline path (rocprofv3 kernel trace): the
-    # write pass of the match, k_match<..., write>. Its duration is the
-    # library's HIP-event phase timer around that launch (same stream).
-    # Algorithmic bytes per launch: every A read once and its best match
-    # written (16 + 12 B), every B payload + key read once (16 + 4 B mixed,
-    # 32 + 4 B FP64), every pair written once (16 B).
-    hp = head["phases_ms"]
-    pay = 16 if order[0] == "mixed" else 32
-    alg_bytes = cat.nA * (16 + 12) + cat.nB * (pay + 4) + head["n_pairs"] * 16
-    achieved = alg_bytes / (hp["write"] / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_match (write pass)",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes_per_launch": int(alg_bytes),
-                "kernel_ms": round(hp["write"], 4)}
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        import oracle
-        threads = a.cpu_threads or min(16, os.cpu_count() or 1)
-        t = time.perf_counter()
-        o = oracle.match(cat.raA, cat.decA, cat.raB, cat.decB, radius_arcsec=cat.radius_arcsec,
-                         nthreads=threads)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(cat.nA / dt, 1), "unit": "A-sources/s", "cores": int(o.threads),
-               "kind": "oracle", "sample": f"whole workload ({cat.nA} A x {cat.nB} B), "
-               f"{dt:.1f}s wall", "n_pairs": int(len(o.ia))}
-        if int(len(o.ia)) != head["n_pairs"]:
-            print(f"[bench] WARNING: oracle pairs {len(o.ia)} != GPU {head['n_pairs']}",
-                  file=sys.stderr)
-
-    line = {
-        "metric": "A-sources matched/s + pair tests/s, mixed vs FP64 path (exact pair set)",
-        "value": round(head["a_per_s"], 1),
-        "unit": "A-sources/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(head["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if order[0] == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": "full-sky 10M A x 10M B + dense caps (RA 0/360, north pole), "
-                               "r=2\", all+best, index build + match per step",
-                   "nA": cat.nA, "nB": cat.nB, "radius_arcsec": cat.radius_arcsec,
-                   "scale": a.scale, "parallelism": "single GPU"},
-        "pair_tests_per_s": round(head["pair_tests_per_s"], 1),
-        "paths": paths,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    if "fp64" in paths and "mixed" in paths:
-        line["speedup_mixed_vs_fp64"] = round(paths["fp64"]["ms_per_step"] /
-                                              paths["mixed"]["ms_per_step"], 3)
+    if a.config == "cfg4":
+        line = batch_config(a, c3x, torch, np)
+    else:
+        line = single_config(a, c3x, torch, np, a.config)
     print(json.dumps(line))
 
 

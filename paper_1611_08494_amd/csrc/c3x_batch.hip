@@ -1010,11 +1010,48 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     if (st != C3X_OK) return st;
     clear_error();
 
-    // first run: sizes the outputs
-    BCHK(batch_front(b), "batch pipeline");
+    // first run: sizes the lists (grown and run again while one overflows)
+    // and the outputs
     int64_t P = 0;
-    BCHK(hipMemcpyAsync(&P, b->off + NA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
-    BCHK(hipStreamSynchronize(s), "batch pipeline");
+    for (int attempt = 0;; ++attempt) {
+        BCHK(batch_front(b), "batch pipeline");
+        uint32_t hc[16];
+        std::vector<uint32_t> oc(kEmitPools * kEmitPoolStride);
+        BCHK(hipMemcpyAsync(&P, b->off + NA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+        BCHK(hipMemcpyAsync(hc, b->ctr, sizeof(hc), hipMemcpyDeviceToHost, s), "copy");
+        BCHK(hipMemcpyAsync(oc.data(), b->octr, oc.size() * 4, hipMemcpyDeviceToHost, s), "copy");
+        BCHK(hipStreamSynchronize(s), "batch pipeline");
+        uint32_t ov_need = 0;
+        for (int q = 0; q < kEmitPools; ++q) ov_need = std::max(ov_need, oc[q * kEmitPoolStride]);
+        const bool grow_amb = hc[1] > b->amb_cap, grow_tie = hc[2] > b->tie_cap;
+        const bool grow_bin = hc[8] > b->bin_cap, grow_hl = hc[9] > b->hl_cap;
+        const bool grow_ov = ov_need > b->ov_pool;
+        if (!(grow_amb || grow_tie || grow_bin || grow_hl || grow_ov)) break;
+        if (attempt >= 3) return fail(C3X_ENOMEM, "batch lists keep growing");
+        if (grow_amb) {
+            b->amb_cap = hc[1] + hc[1] / 8 + 1024;
+            b->amb = M.get_n<uint2>(b->amb_cap);
+        }
+        if (grow_tie) {
+            b->tie_cap = hc[2] + hc[2] / 8 + 1024;
+            b->tie = M.get_n<uint2>(b->tie_cap);
+        }
+        if (grow_bin || grow_amb) {
+            b->bin_cap = std::max(b->amb_cap, hc[8] + hc[8] / 8 + 1024);
+            b->bin = M.get_n<uint4>(b->bin_cap);
+            b->xent = M.get_n<WEnt>(b->bin_cap);
+        }
+        if (grow_hl) return fail(C3X_ENOMEM, "more than %u candidates need binary128 in one "
+                                             "batch", b->hl_cap);
+        if (grow_ov) {
+            b->ov_pool = ov_need + ov_need / 8 + 4096;
+            b->ovl = M.get_n<OvEnt>((int64_t)b->ov_pool * kEmitPools);
+        }
+        b->pos = M.get_n<uint32_t>((int64_t)b->tie_cap + b->bin_cap);
+        b->unc = M.get_n<uint32_t>((int64_t)b->tie_cap + b->bin_cap);
+        if (!b->amb || !b->tie || !b->bin || !b->xent || !b->ovl || !b->pos || !b->unc)
+            return fail(C3X_ENOMEM, "batch lists");
+    }
     b->P_cap = P;
     b->pt = M.get_n<PairTmp>(P);
     b->oa = M.get_n<int32_t>(P);
@@ -1057,8 +1094,11 @@ static c3x_status batch_finish(c3x_batch *b)
         return fail(C3X_EINVAL, "batch inputs moved outside the planned sky boxes: plan again");
     if ((hc[0] & kBFlagCap) || hc[1] > b->amb_cap || hc[2] > b->tie_cap || hc[5] ||
         hc[9] > b->hl_cap || P != b->P_cap)
-        return fail(C3X_EINVAL, "batch inputs changed since the plan (list sizes differ): plan "
-                                "again");
+        return fail(C3X_EINVAL,
+                    "batch inputs changed since the plan (pairs %lld of %lld planned; band list "
+                    "%u of %u, tie list %u of %u, overflow %u): plan again",
+                    (long long)P, (long long)b->P_cap, hc[1], b->amb_cap, hc[2], b->tie_cap,
+                    hc[5]);
     if (hc[7]) return fail(C3X_EINVAL, "a batch source has more than 2048 matches: use c3x_match");
     if (hc[4] || h64[2] != (unsigned long long)P)
         return fail(C3X_EDEVICE, "internal: batch placement flags %u, %llu of %lld placed", hc[4],

@@ -378,13 +378,14 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
 __device__ __forceinline__ int verdict(const MatchArgs &m, uint32_t i, uint32_t j)
 {
     unsigned long long k = ((unsigned long long)i << 32) | j;
-    uint32_t lo = 0, hi = m.n_ver_dev ? min(*m.n_ver_dev, m.n_ver) : m.n_ver;
+    const uint32_t n = m.n_ver_dev ? min(*m.n_ver_dev, m.n_ver) : m.n_ver;
+    uint32_t lo = 0, hi = n;
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
         if (m.ver_key[mid] < k) lo = mid + 1;
         else hi = mid;
     }
-    if (lo < hi && m.ver_key[lo] == k) return m.ver_in[lo] ? IN : OUT;
+    if (lo < n && m.ver_key[lo] == k) return m.ver_in[lo] ? IN : OUT;
     atomicOr(m.err_flag, 4u);
     return OUT;
 }
