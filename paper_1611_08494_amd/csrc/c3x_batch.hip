@@ -132,6 +132,14 @@ __global__ void k_bsum(const BJob *__restrict__ jobs, const uint32_t *__restrict
     }
 }
 
+// Job of every entry (entries of job j: [pref[j], pref[j + 1])).
+__global__ void k_bjob_fill(const uint32_t *__restrict__ pref, int nj, int64_t n,
+                            uint32_t *__restrict__ ejob)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) ejob[e] = job_of(pref, nj, (uint32_t)e);
+}
+
 // Largest angle (deg, as ordered bits of a non-negative double) between an
 // entry and its job's centre.
 __global__ void k_bext(const BJob *__restrict__ jobs, const uint32_t *__restrict__ pref, int nj,
@@ -153,14 +161,14 @@ __global__ void k_bext(const BJob *__restrict__ jobs, const uint32_t *__restrict
 
 // Cell key of every entry, with the entry number as value. Entries outside
 // their job's planned box are reported (the plan no longer fits the data).
-__global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restrict__ pref, int nj,
+__global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restrict__ ejob,
                         const double *__restrict__ ra, const double *__restrict__ dec, int64_t n,
                         bool isB, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                         uint32_t *__restrict__ flags)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const uint32_t j = job_of(pref, nj, (uint32_t)e);
+    const uint32_t j = ejob[e];
     const BJob &jb = jobs[j];
     const int64_t row = entry_row(jb, (uint32_t)e, isB);
     double a = ra[row], d = dec[row];
@@ -183,16 +191,18 @@ __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restric
 // Sorted B payloads: FP64 unit vector, FP32 offset from the job centre, the
 // coordinates; idx is the B entry.
 __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__restrict__ jobs,
-                            const uint32_t *__restrict__ pref, int nj,
+                            const uint32_t *__restrict__ ejob,
                             const double *__restrict__ ra, const double *__restrict__ dec,
                             int64_t n, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
                             double2 *__restrict__ radec)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // a job's sorted entries take its own entries' places (keys are job-major),
+    // and one XCD reads one job's rows
+    const int64_t s = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (s >= n) return;
     uint32_t e = rows[s];
     if (e >= (uint64_t)n) e = 0;  // unreachable for a permutation
-    const uint32_t j = job_of(pref, nj, e);
+    const uint32_t j = ejob[s];
     const BJob &jb = jobs[j];
     const int64_t row = entry_row(jb, e, true);
     const double a = ra[row], d = dec[row];
@@ -221,17 +231,17 @@ __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__res
 // asin(sin r / cos dec'_max) of ra', padded for rounding, as sorted B
 // positions.
 __global__ void k_bgather_a(const uint32_t *__restrict__ rows, const BJob *__restrict__ jobs,
-                            const uint32_t *__restrict__ pref, int nj,
+                            const uint32_t *__restrict__ ejob,
                             const double *__restrict__ ra, const double *__restrict__ dec,
                             int64_t n, Grid g, double2 *__restrict__ arad,
                             uint32_t *__restrict__ aidx, uint32_t *__restrict__ ajob,
                             ARange *__restrict__ arng)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (s >= n) return;
     uint32_t e = rows[s];
     if (e >= (uint64_t)n) e = 0;
-    const uint32_t j = job_of(pref, nj, e);
+    const uint32_t j = ejob[s];
     const BJob &jb = jobs[j];
     const int64_t row = entry_row(jb, e, false);
     double a = ra[row], d = dec[row];
@@ -365,24 +375,24 @@ __global__ void k_brows(const uint2 *__restrict__ tie, const uint32_t *__restric
 }
 
 // Pair and best outputs in job-local rows.
-__global__ void k_blocal_pairs(const BJob *__restrict__ jobs, const uint32_t *__restrict__ prefA,
-                               int nj, const int64_t *__restrict__ P, int64_t cap,
+__global__ void k_blocal_pairs(const BJob *__restrict__ jobs, const uint32_t *__restrict__ ejobA,
+                               const int64_t *__restrict__ P, int64_t cap,
                                int32_t *__restrict__ ia, int32_t *__restrict__ ib)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= min(*P, cap)) return;
     const uint32_t a = (uint32_t)ia[p];
-    const BJob &jb = jobs[job_of(prefA, nj, a)];
+    const BJob &jb = jobs[ejobA[a]];
     ia[p] = (int32_t)(a - jb.a_ent);
     ib[p] = (int32_t)((uint32_t)ib[p] - jb.b_ent);
 }
 
-__global__ void k_blocal_best(const BJob *__restrict__ jobs, const uint32_t *__restrict__ prefA,
-                              int nj, int64_t n, int32_t *__restrict__ best)
+__global__ void k_blocal_best(const BJob *__restrict__ jobs, const uint32_t *__restrict__ ejobA,
+                              int64_t n, int32_t *__restrict__ best)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n || best[a] < 0) return;
-    const BJob &jb = jobs[job_of(prefA, nj, (uint32_t)a)];
+    const BJob &jb = jobs[ejobA[a]];
     best[a] = (int32_t)((uint32_t)best[a] - jb.b_ent);
 }
 
@@ -452,6 +462,7 @@ struct c3x_batch {
     // job table
     BJob *djobs = nullptr;
     uint32_t *prefA = nullptr, *prefB = nullptr;
+    uint32_t *ejobA = nullptr, *ejobB = nullptr;  // job of each entry (and sorted position)
     // B index
     uint32_t *bk = nullptr, *bv = nullptr, *bk2 = nullptr, *bv2 = nullptr;
     void *bws = nullptr;
@@ -601,7 +612,7 @@ static hipError_t batch_front(c3x_batch *b)
     // B: keys, sort, payloads, directory
     const int64_t NB = b->NB, NA = b->NA;
     if (NB > 0)
-        hipLaunchKernelGGL(k_bkeys, dim3(nblk(NB, 256)), dim3(256), 0, s, b->djobs, b->prefB, nj,
+        hipLaunchKernelGGL(k_bkeys, dim3(nblk(NB, 256)), dim3(256), 0, s, b->djobs, b->ejobB,
                            b->raB, b->decB, NB, true, b->bk, b->bv, b->ctr);
     int in_tmp = 0;
     hipError_t e = radix_sort_pairs(b->bk, b->bv, b->bk2, b->bv2, NB, b->key_bits, b->bws, s,
@@ -612,7 +623,7 @@ static hipError_t batch_front(c3x_batch *b)
     b->g.keys = skeys;
     if (NB > 0)
         hipLaunchKernelGGL(k_bgather_b, dim3(nblk(NB, 256)), dim3(256), 0, s, srows, b->djobs,
-                           b->prefB, nj, b->raB, b->decB, NB, b->p64, b->p32, b->radecB);
+                           b->ejobB, b->raB, b->decB, NB, b->p64, b->p32, b->radecB);
     hipLaunchKernelGGL(k_bfill, dim3(nblk(b->g.dsize, 256)), dim3(256), 0, s, b->dcnt,
                        (int64_t)b->g.dsize, 0u);
     if (NB > 0)
@@ -622,14 +633,14 @@ static hipError_t batch_front(c3x_batch *b)
     if (e != hipSuccess) return e;
     // A: keys, sort, records and candidate ranges
     if (NA > 0)
-        hipLaunchKernelGGL(k_bkeys, dim3(nblk(NA, 256)), dim3(256), 0, s, b->djobs, b->prefA, nj,
+        hipLaunchKernelGGL(k_bkeys, dim3(nblk(NA, 256)), dim3(256), 0, s, b->djobs, b->ejobA,
                            b->raA, b->decA, NA, false, b->ak, b->av, b->ctr);
     e = radix_sort_pairs(b->ak, b->av, b->ak2, b->av2, NA, b->key_bits, b->aws, s, &in_tmp);
     if (e != hipSuccess) return e;
     const uint32_t *arows = in_tmp ? b->av2 : b->av;
     if (NA > 0)
         hipLaunchKernelGGL(k_bgather_a, dim3(nblk(NA, 256)), dim3(256), 0, s, arows, b->djobs,
-                           b->prefA, nj, b->raA, b->decA, NA, b->g, b->arad, b->aidx, b->ajob,
+                           b->ejobA, b->raA, b->decA, NA, b->g, b->arad, b->aidx, b->ajob,
                            b->arng);
     // count + emit
     MatchArgs m = batch_args(b);
@@ -722,9 +733,9 @@ static hipError_t batch_back(c3x_batch *b)
     fa.huge = b->seg_huge;
     finish_segments(fa, s);
     hipLaunchKernelGGL(k_blocal_pairs, dim3(nblk(std::max<int64_t>(b->P_cap, 1), 256)), dim3(256),
-                       0, s, b->djobs, b->prefA, b->nj, b->off + NA, b->P_cap, b->oa, b->ob);
+                       0, s, b->djobs, b->ejobA, b->off + NA, b->P_cap, b->oa, b->ob);
     hipLaunchKernelGGL(k_blocal_best, dim3(nblk(std::max<int64_t>(NA, 1), 256)), dim3(256), 0, s,
-                       b->djobs, b->prefA, b->nj, NA, b->obest);
+                       b->djobs, b->ejobA, NA, b->obest);
     hipLaunchKernelGGL(k_bjob_off, dim3(nblk(b->nj + 1, 256)), dim3(256), 0, s, b->djobs, b->nj,
                        b->off, NA, b->joboff);
     return hipGetLastError();
@@ -787,6 +798,52 @@ static c3x_status batch_grids(c3x_batch *b, double kappa)
         if (e_ != hipSuccess) return fail_hip(e_, what);   \
     } while (0)
 
+// Runs the front half and grows every list that overflowed, until none does.
+static c3x_status batch_size_lists(c3x_batch *b)
+{
+    hipStream_t s = b->s;
+    auto &M = b->mem;
+    for (int attempt = 0;; ++attempt) {
+        BCHK(batch_front(b), "batch pipeline");
+        uint32_t hc[16];
+        std::vector<uint32_t> oc(kEmitPools * kEmitPoolStride);
+        BCHK(hipMemcpyAsync(hc, b->ctr, sizeof(hc), hipMemcpyDeviceToHost, s), "copy");
+        BCHK(hipMemcpyAsync(oc.data(), b->octr, oc.size() * 4, hipMemcpyDeviceToHost, s), "copy");
+        BCHK(hipStreamSynchronize(s), "batch pipeline");
+        uint32_t ov_need = 0;
+        for (int q = 0; q < kEmitPools; ++q) ov_need = std::max(ov_need, oc[q * kEmitPoolStride]);
+        const bool grow_amb = hc[1] > b->amb_cap, grow_tie = hc[2] > b->tie_cap;
+        const bool grow_bin = hc[8] > b->bin_cap, grow_hl = hc[9] > b->hl_cap;
+        const bool grow_ov = ov_need > b->ov_pool;
+        if (!(grow_amb || grow_tie || grow_bin || grow_hl || grow_ov)) break;
+        if (attempt >= 3) return fail(C3X_ENOMEM, "batch lists keep growing");
+        if (grow_amb) {
+            b->amb_cap = hc[1] + hc[1] / 8 + 1024;
+            b->amb = M.get_n<uint2>(b->amb_cap);
+        }
+        if (grow_tie) {
+            b->tie_cap = hc[2] + hc[2] / 8 + 1024;
+            b->tie = M.get_n<uint2>(b->tie_cap);
+        }
+        if (grow_bin || grow_amb) {
+            b->bin_cap = std::max(b->amb_cap, hc[8] + hc[8] / 8 + 1024);
+            b->bin = M.get_n<uint4>(b->bin_cap);
+            b->xent = M.get_n<WEnt>(b->bin_cap);
+        }
+        if (grow_hl) return fail(C3X_ENOMEM, "more than %u candidates need binary128 in one "
+                                             "batch", b->hl_cap);
+        if (grow_ov) {
+            b->ov_pool = ov_need + ov_need / 8 + 4096;
+            b->ovl = M.get_n<OvEnt>((int64_t)b->ov_pool * kEmitPools);
+        }
+        b->pos = M.get_n<uint32_t>((int64_t)b->tie_cap + b->bin_cap);
+        b->unc = M.get_n<uint32_t>((int64_t)b->tie_cap + b->bin_cap);
+        if (!b->amb || !b->tie || !b->bin || !b->xent || !b->ovl || !b->pos || !b->unc)
+            return fail(C3X_ENOMEM, "batch lists");
+    }
+    return C3X_OK;
+}
+
 static c3x_status batch_plan_impl(c3x_batch *b)
 {
     hipStream_t s = b->s;
@@ -821,6 +878,15 @@ static c3x_status batch_plan_impl(c3x_batch *b)
         return fail(C3X_ENOMEM, "batch plan buffers");
     BCHK(hipMemcpyAsync(b->prefA, pa.data(), (nj + 1) * 4, hipMemcpyHostToDevice, s), "copy");
     BCHK(hipMemcpyAsync(b->prefB, pb.data(), (nj + 1) * 4, hipMemcpyHostToDevice, s), "copy");
+    b->ejobA = b->mem.get_n<uint32_t>(std::max<int64_t>(NA, 1));
+    b->ejobB = b->mem.get_n<uint32_t>(std::max<int64_t>(NB, 1));
+    if (!b->ejobA || !b->ejobB) return fail(C3X_ENOMEM, "batch job tables");
+    if (NA > 0)
+        hipLaunchKernelGGL(k_bjob_fill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->prefA, nj, NA,
+                           b->ejobA);
+    if (NB > 0)
+        hipLaunchKernelGGL(k_bjob_fill, dim3(nblk(NB, 256)), dim3(256), 0, s, b->prefB, nj, NB,
+                           b->ejobB);
     BCHK(hipMemcpyAsync(b->djobs, b->hjobs.data(), nj * sizeof(BJob), hipMemcpyHostToDevice, s),
          "copy");
     BCHK(hipMemsetAsync(sums, 0, 3 * nj * sizeof(double), s), "memset");
@@ -980,6 +1046,17 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->g.dir = b->dir;
     b->g.nB = (int32_t)NB;
 
+    // lists sized at the default cell scale first, so that the timed runs
+    // below do not overflow them
+    {
+        c3x_status st = batch_grids(b, 1.0);
+        if (st == C3X_OK) {
+            st = batch_size_lists(b);
+            if (st != C3X_OK) return st;
+        }
+        clear_error();
+    }
+
     // autotuner: time the index + count half at a few cell scales
     const char *fixed = getenv("C3X_BATCH_CELL_SCALE");
     std::vector<double> scales = {0.5, 1.0, 2.0, 4.0};
@@ -1012,46 +1089,11 @@ static c3x_status batch_plan_impl(c3x_batch *b)
 
     // first run: sizes the lists (grown and run again while one overflows)
     // and the outputs
+    st = batch_size_lists(b);
+    if (st != C3X_OK) return st;
     int64_t P = 0;
-    for (int attempt = 0;; ++attempt) {
-        BCHK(batch_front(b), "batch pipeline");
-        uint32_t hc[16];
-        std::vector<uint32_t> oc(kEmitPools * kEmitPoolStride);
-        BCHK(hipMemcpyAsync(&P, b->off + NA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
-        BCHK(hipMemcpyAsync(hc, b->ctr, sizeof(hc), hipMemcpyDeviceToHost, s), "copy");
-        BCHK(hipMemcpyAsync(oc.data(), b->octr, oc.size() * 4, hipMemcpyDeviceToHost, s), "copy");
-        BCHK(hipStreamSynchronize(s), "batch pipeline");
-        uint32_t ov_need = 0;
-        for (int q = 0; q < kEmitPools; ++q) ov_need = std::max(ov_need, oc[q * kEmitPoolStride]);
-        const bool grow_amb = hc[1] > b->amb_cap, grow_tie = hc[2] > b->tie_cap;
-        const bool grow_bin = hc[8] > b->bin_cap, grow_hl = hc[9] > b->hl_cap;
-        const bool grow_ov = ov_need > b->ov_pool;
-        if (!(grow_amb || grow_tie || grow_bin || grow_hl || grow_ov)) break;
-        if (attempt >= 3) return fail(C3X_ENOMEM, "batch lists keep growing");
-        if (grow_amb) {
-            b->amb_cap = hc[1] + hc[1] / 8 + 1024;
-            b->amb = M.get_n<uint2>(b->amb_cap);
-        }
-        if (grow_tie) {
-            b->tie_cap = hc[2] + hc[2] / 8 + 1024;
-            b->tie = M.get_n<uint2>(b->tie_cap);
-        }
-        if (grow_bin || grow_amb) {
-            b->bin_cap = std::max(b->amb_cap, hc[8] + hc[8] / 8 + 1024);
-            b->bin = M.get_n<uint4>(b->bin_cap);
-            b->xent = M.get_n<WEnt>(b->bin_cap);
-        }
-        if (grow_hl) return fail(C3X_ENOMEM, "more than %u candidates need binary128 in one "
-                                             "batch", b->hl_cap);
-        if (grow_ov) {
-            b->ov_pool = ov_need + ov_need / 8 + 4096;
-            b->ovl = M.get_n<OvEnt>((int64_t)b->ov_pool * kEmitPools);
-        }
-        b->pos = M.get_n<uint32_t>((int64_t)b->tie_cap + b->bin_cap);
-        b->unc = M.get_n<uint32_t>((int64_t)b->tie_cap + b->bin_cap);
-        if (!b->amb || !b->tie || !b->bin || !b->xent || !b->ovl || !b->pos || !b->unc)
-            return fail(C3X_ENOMEM, "batch lists");
-    }
+    BCHK(hipMemcpyAsync(&P, b->off + NA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    BCHK(hipStreamSynchronize(s), "batch pipeline");
     b->P_cap = P;
     b->pt = M.get_n<PairTmp>(P);
     b->oa = M.get_n<int32_t>(P);

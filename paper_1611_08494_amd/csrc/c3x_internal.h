@@ -123,10 +123,16 @@ constexpr int kRZ = 3;
 struct alignas(8) ARange {
     uint32_t j0[kRZ];
     uint16_t n[kRZ];
-    uint16_t pad;
+    uint16_t pad;          // 1: counted by a wavefront of its own
     int32_t zlo;
 };
 static_assert(sizeof(ARange) == 24, "24-byte range record");
+
+// A row counted by a wavefront of its own (marked when A is prepared).
+__device__ __forceinline__ bool wide_row(const ARange &r)
+{
+    return r.pad != 0;
+}
 
 // One job of a batch (device job table). Its A and B rows are taken into a
 // local frame whose first axis is the job's mean direction (c, e, n: centre,
@@ -208,6 +214,10 @@ struct MatchArgs {
     uint32_t *col_n;
     void *col;
     uint32_t col_cap;
+    // rows counted by the wavefront-per-source kernel (sorted A positions)
+    const uint32_t *wide;
+    const uint32_t *wide_n;
+    uint32_t wide_min;     // 0: none
     // counters
     unsigned long long *n_tests;
     unsigned long long *n_band;
@@ -217,6 +227,17 @@ struct MatchArgs {
 // ----------------------------------------------------------------------------
 // device geometry
 // ----------------------------------------------------------------------------
+
+// Logical block of a 1-D grid such that each XCD takes one contiguous
+// share: the dispatcher deals workgroups to the 8 XCDs in turn, so block b
+// runs on XCD b % 8, and neighbouring data (one catalogue slice, one L2)
+// stays on one XCD.
+__device__ __forceinline__ uint32_t xcd_block()
+{
+    const uint32_t n = gridDim.x, b = blockIdx.x;
+    const uint32_t per = n >> 3, rem = n & 7u, x = b & 7u;
+    return x * per + min(x, rem) + (b >> 3);
+}
 
 __device__ __forceinline__ int zone_of(double dec, const Grid &g)
 {

@@ -31,6 +31,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -41,6 +42,8 @@
 namespace c3x {
 
 constexpr int kMatchBlock = 256;
+constexpr uint32_t kWideMin = 32;  // candidates from which a row gets a wavefront of its own
+constexpr int64_t kFewRows = 1 << 21;  // fewer A rows: one lane each leaves the device idle
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
 constexpr int kSegLds = 2048;   // segments up to this long are sorted in LDS
@@ -157,7 +160,8 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
                            double L_rad, Grid g, double reach_deg,
                            double2 *__restrict__ arad, uint32_t *__restrict__ aidx,
                            AEll *__restrict__ aell, AEllR *__restrict__ aellr,
-                           ARange *__restrict__ arng)
+                           ARange *__restrict__ arng, uint32_t wide_min, bool few,
+                           uint32_t *__restrict__ wide, uint32_t *__restrict__ wide_n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -183,7 +187,37 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
     }
     arad[i] = make_double2(r, d);
     aidx[i] = row;
-    arng[i] = a_ranges(g, r, d, SHAPE == C3X_ELLIPSE ? A / 3600.0 : reach_deg);
+    ARange rg = a_ranges(g, r, d, SHAPE == C3X_ELLIPSE ? A / 3600.0 : reach_deg);
+    if (wide_min) {
+        // rows for the wavefront-per-source kernel: a window walked cell by
+        // cell, 16 wide_min candidates or more, or wide_min or more and either
+        // at least 4 times the mean of the wavefront's rows (one lane each, the
+        // wavefront would wait on it) or too few rows (few) for one lane each
+        // to fill the device
+        const uint32_t nc = (uint32_t)rg.n[0] + rg.n[1] + rg.n[2];
+        uint32_t sum = rg.zlo < 0 ? 0u : nc, cnt = 1;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            sum += __shfl_xor(sum, o);
+            cnt += __shfl_xor(cnt, o);
+        }
+        const bool wd = rg.zlo < 0 || nc >= 16 * wide_min ||
+                        (nc >= wide_min && (few || (uint64_t)nc * cnt >= 4ull * sum));
+        rg.pad = wd ? 1 : 0;
+        const unsigned long long wm = __ballot(wd);
+        if (wm) {
+            const int l0 = __builtin_ffsll((long long)wm) - 1;
+            const int lane = (int)(threadIdx.x & 63u);
+            uint32_t base = 0;
+            if (lane == l0) base = atomicAdd(wide_n, (uint32_t)__popcll(wm));
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, l0);
+            if (wd)
+                wide[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(wm >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)wm, 0u))] =
+                    (uint32_t)i;
+        }
+    }
+    arng[i] = rg;
     if (SHAPE == C3X_ELLIPSE) {
         double T = pa_zero + (double)pa_sense * P;
         double st, ct;
@@ -390,19 +424,19 @@ __device__ __forceinline__ int verdict(const MatchArgs &m, uint32_t i, uint32_t 
     return OUT;
 }
 
-// Verdict of a band candidate: in a single call, the table built from the
-// recheck; in a batch, the FP64 recheck again (the same decision the recheck
-// kernel took), then the host-decided table for what it leaves open.
-template <bool BATCH>
+// Verdict of a band candidate: the FP64 recheck again (the decision the
+// recheck kernel took), then the table of host decisions for what it leaves
+// open.
+template <int SHAPE, bool BATCH>
 __device__ __forceinline__ int band_verdict(const MatchArgs &m, uint32_t i, uint32_t j,
                                             const ARec &a)
 {
-    if constexpr (BATCH) {
-        ARec q = a;
-        q.cosd = cos_dec_acc(a.dec);
-        const int d = recheck_circle(q, m.radecB[j], m.jobs[m.ajob[i]].h_r);
-        if (d != AMBIG) return d;
-    }
+    ARec q = a;
+    q.cosd = cos_dec_acc(a.dec);
+    int d;
+    if constexpr (SHAPE == C3X_ELLIPSE) d = recheck_ellipse(q, m.aellr[i], m.radecB[j]);
+    else d = recheck_circle(q, m.radecB[j], BATCH ? m.jobs[m.ajob[i]].h_r : m.h_r);
+    if (d != AMBIG) return d;
     return verdict(m, i, j);
 }
 
@@ -459,7 +493,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     else pay = m.pay32;
 
     const uint32_t i = blockIdx.x * kMatchBlock + threadIdx.x;
-    const bool active = i < (uint32_t)m.nA;
+    bool active = i < (uint32_t)m.nA;
     ARec a{};
     AEll e{};
     AEllR er{};
@@ -477,6 +511,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         rg = m.arng[i];
         a = load_a(m, i, reach);
     }
+    // rows listed for the wavefront-per-source kernel are its to count
+    if (MODE != 1 && !BATCH && active && m.wide_min && wide_row(rg)) active = false;
     double Lr = 0.0;
     const Thr th = lane_thr<BATCH>(m, active ? i : 0u, Lr);
 
@@ -532,9 +568,9 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             v.j = t.j;
             v.code = t.sep;
             m.ovl[(size_t)pool * m.ov_pool + slot] = v;
-        } else {
-            atomicOr(m.ov_flag, 1u);
         }
+        // a full region: one flag write per group, not one per match
+        if (__ballot(slot >= m.ov_pool) && r == 0) atomicOr(m.ov_flag, 1u);
     };
 
     // One candidate: decide it, then count / rank it (MODE 0), write it
@@ -654,6 +690,225 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     }
 }
 
+// Sources with many candidates (large areas, dense fields): one wavefront
+// per listed source, lanes striding over its candidate ranges, so that the
+// loads of a range are coalesced and no lane waits for a longer neighbour.
+// Same outputs as k_match in MODE 0 / 2 for those rows: count, best by the
+// filter's chord (near-ties listed), band candidates listed, the first kTab
+// matches in the record and later ones in the overflow list.
+__device__ __forceinline__ uint32_t rl_u32(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ double rl_f64(double v, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = rl_u32((uint32_t)u, l), hi = rl_u32((uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Lane rank among the lanes of mask hm below this one.
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long hm)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+}
+
+template <int SHAPE, int PREC, int MODE>
+__global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
+{
+    static_assert(MODE == 0 || MODE == 2, "count (+ emit) passes only");
+    using PayT = PayOf<PREC>;
+    __shared__ unsigned long long s_tests, s_band, s_placed;
+    if (threadIdx.x == 0) {
+        s_tests = 0;
+        s_band = 0;
+        s_placed = 0;
+    }
+    __syncthreads();
+    const PayT *pay;
+    if constexpr (PREC == C3X_FP64) pay = m.pay64;
+    else pay = m.pay32;
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nw = min(*m.wide_n, (uint32_t)m.nA);
+    const uint32_t pool = wave & (kEmitPools - 1);
+    unsigned long long tests = 0, band = 0, placed = 0;
+
+    for (uint32_t w = wave; w < nw; w += nwaves) {
+        const uint32_t i = min(m.wide[w], (uint32_t)m.nA - 1u);
+        double reach = m.reach_deg;
+        AEll e{};
+        AEllR er{};
+        LaneF32 f{};
+        if constexpr (SHAPE == C3X_ELLIPSE) {
+            e = m.aell[i];
+            er = m.aellr[i];
+            reach = er.a_arcsec / 3600.0;
+            f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
+                        (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
+        }
+        const ARec a = load_a(m, i, reach);
+        double Lr = 0.0;
+        const Thr th = lane_thr<false>(m, i, Lr);
+        CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
+        uint32_t cnt = 0;  // wave-uniform
+        double b1 = INFINITY, b2 = INFINITY;
+        uint32_t bidx = 0xffffffffu, bj = 0;
+        uint32_t tb0 = 0, tb1 = 0;
+        double tc0 = 0.0, tc1 = 0.0;
+
+        auto range = [&](int z, uint32_t j0, uint32_t j1) {
+            const ZoneInfo zi = m.g.zinfo[z];
+            for (uint32_t t = j0; t < j1; t += 64) {
+                const uint32_t j = t + (uint32_t)lane;
+                const bool on = j < j1;
+                int d = OUT;
+                double c2 = INFINITY;
+                PayT b{};
+                if (on) {
+                    b = pay[j];
+                    const uint32_t key = PREC == C3X_FP64 ? 0u : m.g.keys[j];
+                    ++tests;
+                    d = decide<SHAPE, PREC, false>(m, a, e, er, f, cc, th, z, zi, key, b, j, c2);
+                }
+                const unsigned long long am = __ballot(d == AMBIG);
+                if (am) {
+                    uint32_t base = 0;
+                    if (lane == __builtin_ffsll((long long)am) - 1)
+                        base = atomicAdd(m.amb_n, (uint32_t)__popcll(am));
+                    base = rl_u32(base, __builtin_ffsll((long long)am) - 1);
+                    if (d == AMBIG) {
+                        ++band;
+                        const uint32_t slot = base + lane_rank(am);
+                        if (slot < m.amb_cap) m.amb[slot] = make_uint2(i, j);
+                    }
+                }
+                const unsigned long long im = __ballot(d == IN);
+                if (!im) continue;
+                if (d == IN) {
+                    if (c2 < b1 || (c2 == b1 && b.idx < bidx)) {
+                        b2 = b1;
+                        b1 = c2;
+                        bidx = b.idx;
+                        bj = j;
+                    } else if (c2 < b2) {
+                        b2 = c2;
+                    }
+                }
+                if (MODE == 2) {
+                    const uint32_t k = cnt + lane_rank(im);
+                    PairTmp pt{};
+                    if (d == IN) {
+                        double c64 = c2;
+                        if constexpr (PREC != C3X_FP64) {
+                            const Pay64 b8 = m.pay64[j];
+                            const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
+                            c64 = fma(dx, dx, fma(dy, dy, dz * dz));
+                        }
+                        pt.idxB = b.idx;
+                        pt.j = j;
+                        pt.sep = sep_code(c64, j);
+                    }
+                    if (cnt < (uint32_t)kTab) {
+                        // the record's slots: the first lanes of this group
+                        unsigned long long r = im;
+                        for (uint32_t q = cnt; q < (uint32_t)kTab && r; ++q) {
+                            const int l = __builtin_ffsll((long long)r) - 1;
+                            r &= r - 1;
+                            const uint32_t ib = rl_u32(pt.idxB, l);
+                            const double cd = rl_f64(pt.sep, l);
+                            if (q == 0) {
+                                tb0 = ib;
+                                tc0 = cd;
+                            } else {
+                                tb1 = ib;
+                                tc1 = cd;
+                            }
+                        }
+                    }
+                    const unsigned long long om = __ballot(d == IN && k >= (uint32_t)kTab);
+                    if (om) {
+                        const int l0 = __builtin_ffsll((long long)om) - 1;
+                        uint32_t base = 0;
+                        if (lane == l0)
+                            base = atomicAdd(m.octr + pool * kEmitPoolStride,
+                                             (uint32_t)__popcll(om));
+                        base = rl_u32(base, l0);
+                        const uint32_t slot = base + lane_rank(om);
+                        const bool mine = d == IN && k >= (uint32_t)kTab;
+                        if (mine && slot < m.ov_pool) {
+                            OvEnt v;
+                            v.idxA = a.idx;
+                            v.k = k;
+                            v.idxB = pt.idxB;
+                            v.j = pt.j;
+                            v.code = pt.sep;
+                            m.ovl[(size_t)pool * m.ov_pool + slot] = v;
+                        }
+                        if (__ballot(mine && slot >= m.ov_pool) && lane == l0)
+                            atomicOr(m.ov_flag, 1u);
+                    }
+                }
+                cnt += (uint32_t)__popcll(im);
+            }
+        };
+        const ARange rg = m.arng[i];
+        if (rg.zlo >= 0) {
+#pragma unroll 1
+            for (int q = 0; q < kRZ; ++q) {
+                const uint32_t j0 = q == 0 ? rg.j0[0] : (q == 1 ? rg.j0[1] : rg.j0[2]);
+                const uint32_t nq = q == 0 ? rg.n[0] : (q == 1 ? rg.n[1] : rg.n[2]);
+                if (nq) range(rg.zlo + q, j0, j0 + nq);
+            }
+        } else {
+            for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, range);
+        }
+
+        // the best two chords of the wave: minimum by (chord, idxB), then the
+        // smallest of the rest
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double ob1 = __shfl_xor(b1, o), ob2 = __shfl_xor(b2, o);
+            const uint32_t oidx = __shfl_xor(bidx, o), oj = __shfl_xor(bj, o);
+            if (ob1 < b1 || (ob1 == b1 && oidx < bidx)) {
+                b2 = fmin(b1, fmin(b2, ob2));
+                b1 = ob1;
+                bidx = oidx;
+                bj = oj;
+            } else {
+                b2 = fmin(ob1, fmin(b2, ob2));
+            }
+        }
+        if (lane == 0) {
+            m.cnts[a.idx] = cnt;
+            RowRec r;
+            r.best = cnt ? (int32_t)bidx : -1;
+            r.best_j = bj;
+            r.b[0] = tb0;
+            r.b[1] = tb1;
+            r.c[0] = tc0;
+            r.c[1] = tc1;
+            m.rec[a.idx] = r;
+            if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
+            if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), Lr)) {
+                const uint32_t slot = atomicAdd(m.tie_n, 1u);
+                if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
+            }
+        }
+    }
+    if (placed) atomicAdd(&s_placed, placed);
+    if (tests) atomicAdd(&s_tests, tests);
+    if (band) atomicAdd(&s_band, band);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_tests) atomicAdd(m.n_tests, s_tests);
+        if (s_band) atomicAdd(m.n_band, s_band);
+        if (s_placed) atomicAdd(m.n_placed, s_placed);
+    }
+}
+
 // Every match of the listed sorted A positions (best-match re-ranking): one
 // wavefront per listed source, lanes striding over its candidate ranges.
 template <int SHAPE, int PREC, bool BATCH>
@@ -689,7 +944,7 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
             const PayT b = pay[j];
             double c2;
             int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, m.g.keys[j], b, j, c2);
-            if (d == AMBIG) d = band_verdict<BATCH>(m, i, j, a);
+            if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
             if (slot < m.col_cap) {
@@ -767,7 +1022,7 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
             const PayT b = pay[j];
             double c2;
             int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, m.g.keys[j], b, j, c2);
-            if (d == AMBIG) d = band_verdict<BATCH>(m, i, j, a);
+            if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             const Pay64 b8 = m.pay64[j];
             const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
@@ -821,16 +1076,21 @@ __global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__re
 // One thread per band candidate: the FP64 relative-accuracy recheck (error
 // <= ~90 u against a 2^-40 margin). Writes 0 (out), 1 (in) or 2 (still
 // undecided: the host decides it in binary128), with what the host needs.
+// FP64 recheck of the band candidates the count pass listed (their number
+// is on the device): those it finds inside join the matches list `in`, those
+// it cannot decide go to `hl` for binary128 on the host; outside ones drop.
 template <int SHAPE>
-__global__ void k_recheck(const uint2 *__restrict__ band, uint32_t n, const double2 *__restrict__ arad,
+__global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__restrict__ n_band,
+                          uint32_t cap, const double2 *__restrict__ arad,
                           const uint32_t *__restrict__ aidx, const AEllR *__restrict__ aellr,
                           const double2 *__restrict__ radecB, const Pay64 *__restrict__ p64,
                           const Pay32 *__restrict__ p32, double h_r, const double *__restrict__ sa,
                           const double *__restrict__ sb, const double *__restrict__ pa,
-                          AmbInfo *__restrict__ out, uint8_t *__restrict__ v)
+                          uint4 *__restrict__ in, uint32_t *__restrict__ n_in,
+                          AmbInfo *__restrict__ hl, uint32_t *__restrict__ n_hl)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+    if (t >= min(*n_band, cap)) return;
     uint2 q = band[t];
     double2 ad = arad[q.x];
     uint32_t row = aidx[q.x];
@@ -846,7 +1106,12 @@ __global__ void k_recheck(const uint2 *__restrict__ band, uint32_t n, const doub
     int d;
     if (SHAPE == C3X_CIRCLE) d = recheck_circle(a, rb, h_r);
     else d = recheck_ellipse(a, aellr[q.x], rb);
-    v[t] = (uint8_t)d;
+    if (d == OUT) return;
+    const uint32_t idxB = p64 ? p64[q.y].idx : p32[q.y].idx;
+    if (d == IN) {
+        in[atomicAdd(n_in, 1u)] = make_uint4(q.x, row, idxB, q.y);  // at most one per band entry
+        return;
+    }
     AmbInfo r;
     r.raA = ad.x;
     r.decA = ad.y;
@@ -858,8 +1123,19 @@ __global__ void k_recheck(const uint2 *__restrict__ band, uint32_t n, const doub
     r.i = q.x;
     r.j = q.y;
     r.idxA = row;
-    r.idxB = p64 ? p64[q.y].idx : p32[q.y].idx;
-    out[t] = r;
+    r.idxB = idxB;
+    hl[atomicAdd(n_hl, 1u)] = r;
+}
+
+// Sorted A positions whose best match is re-ranked: the near-ties, then the
+// rows that gained a band match.
+__global__ void k_rerank_rows(const uint2 *__restrict__ tie, uint32_t n_tie,
+                              const uint4 *__restrict__ bin, uint32_t n_bin,
+                              uint32_t *__restrict__ pos)
+{
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_tie) pos[t] = tie[t].x;
+    else if (t < n_tie + n_bin) pos[t] = bin[t - n_tie].x;
 }
 
 __global__ void k_gather_pos(const uint32_t *__restrict__ pos, uint32_t n,
@@ -899,24 +1175,31 @@ __global__ void k_place_ov(const OvEnt *__restrict__ ovl, uint32_t ov_pool,
                            unsigned long long *__restrict__ placed, uint32_t *__restrict__ err)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= min(octr[blockIdx.y * kEmitPoolStride], ov_pool)) return;
-    const OvEnt v = ovl[(size_t)blockIdx.y * ov_pool + t];
-    if (v.idxA >= (uint64_t)nA) {
-        atomicOr(err, 16u);
-        return;
+    bool ok = t < min(octr[blockIdx.y * kEmitPoolStride], ov_pool);
+    if (ok) {
+        const OvEnt v = ovl[(size_t)blockIdx.y * ov_pool + t];
+        if (v.idxA >= (uint64_t)nA) {
+            atomicOr(err, 16u);
+            ok = false;
+        } else {
+            const int64_t o = off[v.idxA], oe = off[v.idxA + 1];
+            const int64_t p = o + v.k;
+            if (v.k < (uint32_t)kTab || p >= oe || oe > P) {
+                atomicOr(err, 1u);
+                ok = false;
+            } else {
+                PairTmp x;
+                x.idxB = v.idxB;
+                x.j = v.j;
+                x.sep = v.code;
+                tmp[p] = x;
+            }
+        }
     }
-    const int64_t o = off[v.idxA], oe = off[v.idxA + 1];
-    const int64_t p = o + v.k;
-    if (v.k < (uint32_t)kTab || p >= oe || oe > P) {
-        atomicOr(err, 1u);
-        return;
-    }
-    PairTmp x;
-    x.idxB = v.idxB;
-    x.j = v.j;
-    x.sep = v.code;
-    tmp[p] = x;
-    atomicAdd(placed, 1ull);
+    // one count per wavefront
+    const unsigned long long pm = __ballot(ok);
+    if (pm && (threadIdx.x & 63u) == (uint32_t)(__builtin_ffsll((long long)pm) - 1))
+        atomicAdd(placed, (unsigned long long)__popcll(pm));
 }
 
 // One thread per band match found inside: to its row's record (k < kTab,
@@ -1368,6 +1651,25 @@ static void launch_match(const MatchArgs &m, int shape, int prec, unsigned grid,
 #undef C3X_LAUNCH
 }
 
+template <int MODE>
+static void launch_wide(const MatchArgs &m, int shape, int prec, hipStream_t s)
+{
+    if (!m.wide_min || m.nA == 0) return;
+    // a fixed grid of wavefronts striding over the list (its length is on
+    // the device): 16 per compute unit, what stays resident
+    const unsigned grid = (unsigned)std::min<int64_t>((m.nA + 3) / 4, 1024);
+#define C3X_LAUNCH(SH, PR) \
+    hipLaunchKernelGGL((k_match_wide<SH, PR, MODE>), dim3(grid), dim3(256), 0, s, m)
+    if (shape == C3X_CIRCLE) {
+        if (prec == C3X_FP64) C3X_LAUNCH(C3X_CIRCLE, C3X_FP64);
+        else C3X_LAUNCH(C3X_CIRCLE, C3X_MIXED);
+    } else {
+        if (prec == C3X_FP64) C3X_LAUNCH(C3X_ELLIPSE, C3X_FP64);
+        else C3X_LAUNCH(C3X_ELLIPSE, C3X_MIXED);
+    }
+#undef C3X_LAUNCH
+}
+
 static void launch_rerank(const MatchArgs &m, int shape, int prec, const uint32_t *pos,
                           uint32_t n, uint32_t *unc_n, uint32_t *unc, hipStream_t s)
 {
@@ -1412,6 +1714,10 @@ using namespace c3x;
         if (e_ != hipSuccess) return fail_hip(e_, what); \
     } while (0)
 
+// Overflow-list demand of recent calls, in entries per 1024 A rows: sizes the
+// next call's regions so that steady workloads keep the single pass.
+static std::atomic<uint64_t> g_ov_hint{0};
+
 static c3x_status match_impl(const c3x_index *ix, const double *ra, const double *dec, int64_t nA,
                              const c3x_area *area, unsigned mode, hipStream_t s, c3x_result *R)
 {
@@ -1425,7 +1731,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     uint32_t *keys = tmp.get_n<uint32_t>(nA), *rows = tmp.get_n<uint32_t>(nA);
     uint32_t *ktmp = tmp.get_n<uint32_t>(nA), *rtmp = tmp.get_n<uint32_t>(nA);
     void *ws = tmp.get(std::max(radix_ws_bytes(nA), scan_ws_bytes(nA + 1)));
-    uint32_t *ctr = tmp.get_n<uint32_t>(8);  // bad, amb_n, tie_n, col_n, err, emit overflow
+    // bad, amb_n, tie_n, col_n, err, emit overflow, segments (2), wide rows
+    uint32_t *ctr = tmp.get_n<uint32_t>(16);
     unsigned long long *c64 = tmp.get_n<unsigned long long>(3);  // tests, band, placed
     double2 *arad = tmp.get_n<double2>(nA);
     double2 *packed = tmp.get_n<double2>(nA);
@@ -1447,7 +1754,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     R->best_idx = R->mem.get_n<int32_t>(nA);
     R->best_sep = R->mem.get_n<double>(nA);
     if (!R->best_idx || !R->best_sep) return fail(C3X_ENOMEM, "best buffers");
-    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(uint32_t), s), "memset");
+    HIPCHK(hipMemsetAsync(ctr, 0, 16 * sizeof(uint32_t), s), "memset");
     HIPCHK(hipMemsetAsync(ctr, 0xff, sizeof(uint32_t), s), "memset");
     HIPCHK(hipMemsetAsync(c64, 0, 3 * sizeof(unsigned long long), s), "memset");
     const double *sa = area->semi_major_arcsec, *sb = area->semi_minor_arcsec, *pa = area->pa_deg;
@@ -1458,16 +1765,25 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     int in_tmp = 0;
     HIPCHK(radix_sort_pairs(keys, rows, ktmp, rtmp, nA, ix->plan.key_bits, ws, s, &in_tmp), "A sort");
     uint32_t *srows = in_tmp ? rtmp : rows;
+    // rows with at least wide_min candidates (or a window walked cell by
+    // cell) are counted by one wavefront each; C3X_WIDE_MIN=0 turns it off
+    uint32_t wide_min = kWideMin;
+    if (const char *ev = getenv("C3X_WIDE_MIN")) wide_min = (uint32_t)std::max(0, atoi(ev));
+    const bool few = nA < kFewRows;
+    uint32_t *wide = wide_min ? ktmp : nullptr;  // the key buffer is free after the sort
+    if (in_tmp) wide = wide_min ? keys : nullptr;
     if (nA > 0) {
         const double reach = shape == C3X_CIRCLE ? area->radius_arcsec / 3600.0 : 0.0;
         if (shape == C3X_CIRCLE)
             hipLaunchKernelGGL(k_gather_a<C3X_CIRCLE>, dim3(nblk(nA, 256)), dim3(256), 0, s, srows,
                                packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
-                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng);
+                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng,
+                               wide_min, few, wide, ctr + 8);
         else
             hipLaunchKernelGGL(k_gather_a<C3X_ELLIPSE>, dim3(nblk(nA, 256)), dim3(256), 0, s,
                                srows, packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
-                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng);
+                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng,
+                               wide_min, few, wide, ctr + 8);
     }
     HIPCHK(hipGetLastError(), "A records");
     tm.mark();  // 1
@@ -1502,6 +1818,9 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.err_flag = ctr + 4;
     m.cnts = cnts;
     m.rec = rec;
+    m.wide = wide;
+    m.wide_n = ctr + 8;
+    m.wide_min = wide_min;
     unsigned grid = nblk(nA, kMatchBlock);
 
     // ---- count pass (+ best by the filter's chord, near-ties listed)
@@ -1526,7 +1845,11 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     bool emit = false;
     const int kPoolWords = kEmitPools * kEmitPoolStride;
     if (all && nA > 0) {
+        // regions sized from the need seen by recent calls (entries per 1024
+        // A rows), at least nA / 8 entries in all
+        const uint64_t hint = g_ov_hint.load(std::memory_order_relaxed);
         uint64_t per = (uint64_t)std::max<int64_t>(nA / 8 / kEmitPools, 4096);
+        per = std::max<uint64_t>(per, ((uint64_t)nA * hint / 1024 + kEmitPools - 1) / kEmitPools);
         // test hook: C3X_DEBUG_OVERFLOW_SLOTS=k gives each region k slots (0: none,
         // every match goes through the write pass)
         if (const char *ev = getenv("C3X_DEBUG_OVERFLOW_SLOTS"))
@@ -1539,13 +1862,36 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
         }
     }
-    uint32_t hctr[8];
+    // band candidates decided by the FP64 recheck right after the count:
+    // inside ones (bin) join the matches, open ones (hl) go to the host
+    uint4 *bin = tmp.get_n<uint4>(amb_cap);
+    AmbInfo *hl = tmp.get_n<AmbInfo>(amb_cap);
+    if (!bin || !hl) return fail(C3X_ENOMEM, "band buffers");
+    auto recheck = [&]() {
+        if (shape == C3X_CIRCLE)
+            hipLaunchKernelGGL(k_recheck<C3X_CIRCLE>, dim3(nblk(amb_cap, 256)), dim3(256), 0, s,
+                               m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
+                               ix->pay32, m.h_r, nullptr, nullptr, nullptr, bin, ctr + 9, hl,
+                               ctr + 10);
+        else
+            hipLaunchKernelGGL(k_recheck<C3X_ELLIPSE>, dim3(nblk(amb_cap, 256)), dim3(256), 0, s,
+                               m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
+                               ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10);
+    };
+    uint32_t hctr[16];
     unsigned long long h64[3];
     std::vector<uint32_t> hoctr(kPoolWords);
     for (int attempt = 0; attempt < 2; ++attempt) {
-        if (emit) launch_match<2>(m, shape, prec, grid, s);
-        else launch_match<0>(m, shape, prec, grid, s);
+        if (emit) {
+            launch_match<2>(m, shape, prec, grid, s);
+            launch_wide<2>(m, shape, prec, s);
+        } else {
+            launch_match<0>(m, shape, prec, grid, s);
+            launch_wide<0>(m, shape, prec, s);
+        }
         HIPCHK(hipGetLastError(), "count pass");
+        if (nA > 0) recheck();
+        HIPCHK(hipGetLastError(), "band recheck");
         HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipMemcpyAsync(h64, c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
         if (emit)
@@ -1563,133 +1909,140 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (hctr[1] > amb_cap) {
             amb_cap = hctr[1];
             amb = tmp.get_n<uint2>(amb_cap);
+            bin = tmp.get_n<uint4>(amb_cap);
+            hl = tmp.get_n<AmbInfo>(amb_cap);
         }
         if (hctr[2] > tie_cap) {
             tie_cap = hctr[2];
             tie = tmp.get_n<uint2>(tie_cap);
         }
-        if (!amb || !tie) return fail(C3X_ENOMEM, "count lists");
+        if (!amb || !tie || !bin || !hl) return fail(C3X_ENOMEM, "count lists");
         m.amb = amb;
         m.amb_cap = amb_cap;
         m.tie = tie;
         m.tie_cap = tie_cap;
         HIPCHK(hipMemsetAsync(ctr + 1, 0, 2 * sizeof(uint32_t), s), "memset");
         HIPCHK(hipMemsetAsync(ctr + 5, 0, sizeof(uint32_t), s), "memset");
+        HIPCHK(hipMemsetAsync(ctr + 9, 0, 2 * sizeof(uint32_t), s), "memset");
         HIPCHK(hipMemsetAsync(c64, 0, 3 * sizeof(unsigned long long), s), "memset");
         if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
     }
     // the records and the list hold every filter match unless a region ran out
     const bool emitted = emit && hctr[5] == 0;
+    if (emit && nA > 0 && !getenv("C3X_DEBUG_OVERFLOW_SLOTS")) {
+        // the busiest region's demand (counted even past its end), with a margin
+        uint64_t need = 0;
+        for (int q = 0; q < kEmitPools; ++q) need = std::max<uint64_t>(need, hoctr[q * kEmitPoolStride]);
+        const uint64_t obs = need * kEmitPools * 1024 * 5 / 4 / (uint64_t)nA;
+        const uint64_t old = g_ov_hint.load(std::memory_order_relaxed);
+        g_ov_hint.store(std::min<uint64_t>(std::max(obs, old / 2), 64 * 1024),
+                        std::memory_order_relaxed);
+    }
     uint32_t ov_used = 0;
     if (emitted)
         for (int q = 0; q < kEmitPools; ++q)
             ov_used = std::max(ov_used, std::min(hoctr[q * kEmitPoolStride], m.ov_pool));
     if (!emitted) HIPCHK(hipMemsetAsync(c64 + 2, 0, sizeof(unsigned long long), s), "memset");
-    uint32_t n_amb = hctr[1], n_tie = hctr[2];
+    const uint32_t n_tie = hctr[2];
+    uint32_t n_bin = std::min(hctr[9], amb_cap);
+    const uint32_t n_host = std::min(hctr[10], amb_cap);
     R->stats.n_tests = (int64_t)h64[0];
     R->stats.n_band = (int64_t)h64[1];
     tm.mark();  // 2
 
-    // ---- band candidates: FP64 recheck on the GPU, the rest in binary128 on the host
-    std::vector<uint32_t> recheck_pos;  // sorted A positions whose best must be re-ranked
-    uint32_t n_host = 0;
-    WEnt *xent = nullptr;  // band matches found inside (all-matches mode)
-    uint32_t n_x = 0;
-    if (n_amb > 0) {
-        AmbInfo *dinfo = tmp.get_n<AmbInfo>(n_amb);
-        uint8_t *dv = tmp.get_n<uint8_t>(n_amb);
-        if (!dinfo || !dv) return fail(C3X_ENOMEM, "band buffers");
-        if (shape == C3X_CIRCLE)
-            hipLaunchKernelGGL(k_recheck<C3X_CIRCLE>, dim3(nblk(n_amb, 256)), dim3(256), 0, s, amb,
-                               n_amb, arad, aidx, aellr, ix->radec, ix->pay64, ix->pay32, m.h_r,
-                               nullptr, nullptr, nullptr, dinfo, dv);
-        else
-            hipLaunchKernelGGL(k_recheck<C3X_ELLIPSE>, dim3(nblk(n_amb, 256)), dim3(256), 0, s, amb,
-                               n_amb, arad, aidx, aellr, ix->radec, ix->pay64, ix->pay32, m.h_r,
-                               sa, sb, pa, dinfo, dv);
-        HIPCHK(hipGetLastError(), "band recheck");
-        std::vector<AmbInfo> info(n_amb);
-        std::vector<uint8_t> vv(n_amb);
-        HIPCHK(hipMemcpyAsync(info.data(), dinfo, n_amb * sizeof(AmbInfo), hipMemcpyDeviceToHost, s),
+    // ---- band candidates the FP64 recheck left open: binary128 on the host;
+    // its verdicts go to a sorted table the re-ranking passes look up. The
+    // host vectors live to the end of the call (the copies are asynchronous).
+    std::vector<AmbInfo> info;
+    std::vector<unsigned long long> vk;
+    std::vector<uint8_t> vi;
+    std::vector<uint4> hadd;
+    if (n_host > 0) {
+        info.resize(n_host);
+        HIPCHK(hipMemcpyAsync(info.data(), hl, n_host * sizeof(AmbInfo), hipMemcpyDeviceToHost, s),
                "copy");
-        HIPCHK(hipMemcpyAsync(vv.data(), dv, n_amb, hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipStreamSynchronize(s), "band recheck");
-        std::vector<std::pair<unsigned long long, uint8_t>> ver(n_amb);
-        std::vector<uint4> add;
-        for (uint32_t k = 0; k < n_amb; ++k) {
+        std::vector<std::pair<unsigned long long, uint8_t>> ver(n_host);
+        for (uint32_t k = 0; k < n_host; ++k) {
             const AmbInfo &q = info[k];
-            int in = vv[k];
-            if (in == AMBIG) {
-                ++n_host;
-                in = shape == C3X_CIRCLE
-                         ? c3x_q_circle(q.raA, q.decA, q.raB, q.decB, area->radius_arcsec)
-                         : c3x_q_ellipse(q.raA, q.decA, q.raB, q.decB, q.a, q.b, q.pa,
-                                         area->pa_zero_deg, area->pa_sense);
-            }
+            const int in = shape == C3X_CIRCLE
+                               ? c3x_q_circle(q.raA, q.decA, q.raB, q.decB, area->radius_arcsec)
+                               : c3x_q_ellipse(q.raA, q.decA, q.raB, q.decB, q.a, q.b, q.pa,
+                                               area->pa_zero_deg, area->pa_sense);
             ver[k] = {((unsigned long long)q.i << 32) | q.j, (uint8_t)(in ? 1 : 0)};
-            if (in) {
-                add.push_back(make_uint4(q.i, q.idxA, q.idxB, q.j));
-                recheck_pos.push_back(q.i);
-            }
+            if (in) hadd.push_back(make_uint4(q.i, q.idxA, q.idxB, q.j));
         }
         std::sort(ver.begin(), ver.end());
-        std::vector<unsigned long long> vk(n_amb);
-        std::vector<uint8_t> vi(n_amb);
-        for (uint32_t k = 0; k < n_amb; ++k) {
+        vk.resize(n_host);
+        vi.resize(n_host);
+        for (uint32_t k = 0; k < n_host; ++k) {
             vk[k] = ver[k].first;
             vi[k] = ver[k].second;
         }
-        unsigned long long *dvk = tmp.get_n<unsigned long long>(n_amb);
-        uint8_t *dvi = tmp.get_n<uint8_t>(n_amb);
-        uint4 *dadd = tmp.get_n<uint4>(add.size());
-        if (!dvk || !dvi || !dadd) return fail(C3X_ENOMEM, "verdict table");
-        if (all && !add.empty()) {
-            xent = tmp.get_n<WEnt>(add.size());
-            if (!xent) return fail(C3X_ENOMEM, "verdict table");
-            n_x = (uint32_t)add.size();
-        }
-        HIPCHK(hipMemcpyAsync(dvk, vk.data(), n_amb * 8, hipMemcpyHostToDevice, s), "copy");
-        HIPCHK(hipMemcpyAsync(dvi, vi.data(), n_amb, hipMemcpyHostToDevice, s), "copy");
-        if (!add.empty()) {
-            HIPCHK(hipMemcpyAsync(dadd, add.data(), add.size() * sizeof(uint4),
+        unsigned long long *dvk = tmp.get_n<unsigned long long>(n_host);
+        uint8_t *dvi = tmp.get_n<uint8_t>(n_host);
+        if (!dvk || !dvi) return fail(C3X_ENOMEM, "verdict table");
+        HIPCHK(hipMemcpyAsync(dvk, vk.data(), n_host * 8, hipMemcpyHostToDevice, s), "copy");
+        HIPCHK(hipMemcpyAsync(dvi, vi.data(), n_host, hipMemcpyHostToDevice, s), "copy");
+        if (!hadd.empty()) {  // the band list has room: each entry joins at most once
+            HIPCHK(hipMemcpyAsync(bin + n_bin, hadd.data(), hadd.size() * sizeof(uint4),
                                   hipMemcpyHostToDevice, s), "copy");
-            hipLaunchKernelGGL(k_add_pairs, dim3(nblk(add.size(), 256)), dim3(256), 0, s, dadd,
-                               (uint32_t)add.size(), cnts, xent);
+            n_bin += (uint32_t)hadd.size();
         }
         m.ver_key = dvk;
         m.ver_in = dvi;
-        m.n_ver = n_amb;
-        HIPCHK(hipStreamSynchronize(s), "verdict upload");  // host vectors go out of scope
+        m.n_ver = n_host;
     }
     R->stats.n_ambiguous = n_host;
-
-    // ---- best matches the filter cannot rank: re-ranked in FP64 on the GPU, and
-    // what FP64 cannot separate, every match re-ranked in binary128 on the host
-    if (n_tie > 0) {
-        std::vector<uint2> ties(n_tie);
-        HIPCHK(hipMemcpyAsync(ties.data(), tie, n_tie * sizeof(uint2), hipMemcpyDeviceToHost, s),
-               "copy");
-        HIPCHK(hipStreamSynchronize(s), "ties");
-        for (const uint2 &t : ties) recheck_pos.push_back(t.x);
+    // band matches: counted, and listed as the k-th match of their row
+    WEnt *xent = nullptr;
+    const uint32_t n_x = all ? n_bin : 0;
+    if (n_bin > 0) {
+        if (all) {
+            xent = tmp.get_n<WEnt>(n_bin);
+            if (!xent) return fail(C3X_ENOMEM, "band matches");
+        }
+        hipLaunchKernelGGL(k_add_pairs, dim3(nblk(n_bin, 256)), dim3(256), 0, s, bin, n_bin, cnts,
+                           xent);
     }
-    uint32_t nc = 0;
+
+    // ---- best matches the filter cannot rank (near-ties, rows with a band
+    // match): re-ranked in FP64 on the GPU; rows FP64 cannot separate are
+    // listed (ctr[3]) for binary128 on the host
+    const uint32_t nr = n_tie + n_bin;
+    R->stats.n_best_ties = nr;
     uint32_t *dpos = nullptr;
-    if (!recheck_pos.empty()) {
-        std::sort(recheck_pos.begin(), recheck_pos.end());
-        recheck_pos.erase(std::unique(recheck_pos.begin(), recheck_pos.end()), recheck_pos.end());
-        const uint32_t nr = (uint32_t)recheck_pos.size();
-        R->stats.n_best_ties = nr;
+    if (nr > 0) {
         uint32_t *dall = tmp.get_n<uint32_t>(nr);
         dpos = tmp.get_n<uint32_t>(nr);
         if (!dall || !dpos) return fail(C3X_ENOMEM, "re-ranking buffers");
-        HIPCHK(hipMemcpyAsync(dall, recheck_pos.data(), nr * 4, hipMemcpyHostToDevice, s), "copy");
+        hipLaunchKernelGGL(k_rerank_rows, dim3(nblk(nr, 256)), dim3(256), 0, s, tie, n_tie, bin,
+                           n_bin, dall);
         HIPCHK(hipMemsetAsync(ctr + 3, 0, sizeof(uint32_t), s), "memset");
         launch_rerank(m, shape, prec, dall, nr, ctr + 3, dpos, s);
         HIPCHK(hipGetLastError(), "re-ranking");
-        HIPCHK(hipMemcpyAsync(&nc, ctr + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy");
-        HIPCHK(hipStreamSynchronize(s), "re-ranking");
-        nc = std::min(nc, nr);
     }
+
+    // ---- scan of the per-A counts (idxA order)
+    int64_t *off = tmp.get_n<int64_t>(nA + 1);
+    const uint32_t *scan_in = cnts;
+    if (!all) {  // one output row per A row with a match
+        uint32_t *nz = tmp.get_n<uint32_t>(nA);
+        if (!nz) return fail(C3X_ENOMEM, "offsets");
+        if (nA > 0)
+            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
+        scan_in = nz;
+    }
+    if (!off) return fail(C3X_ENOMEM, "offsets");
+    HIPCHK(scan_u32_to_i64(scan_in, off, nA, off + nA, ws, s), "scan");
+    int64_t P = 0;
+    uint32_t nc = 0;
+    HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    if (nr > 0) HIPCHK(hipMemcpyAsync(&nc, ctr + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy");
+    HIPCHK(hipStreamSynchronize(s), "scan");
+    nc = std::min(nc, nr);
+
+    // ---- rows FP64 could not rank: every match listed, ranked in binary128
     if (nc > 0) {
         uint32_t col_cap = 8 * nc + 64;
         std::vector<ColEnt> col;
@@ -1762,21 +2115,6 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         }
     }
 
-    // ---- scan of the per-A counts (idxA order)
-    int64_t *off = tmp.get_n<int64_t>(nA + 1);
-    const uint32_t *scan_in = cnts;
-    if (!all) {  // one output row per A row with a match
-        uint32_t *nz = tmp.get_n<uint32_t>(nA);
-        if (!nz) return fail(C3X_ENOMEM, "offsets");
-        if (nA > 0)
-            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
-        scan_in = nz;
-    }
-    if (!off) return fail(C3X_ENOMEM, "offsets");
-    HIPCHK(scan_u32_to_i64(scan_in, off, nA, off + nA, ws, s), "scan");
-    int64_t P = 0;
-    HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
-    HIPCHK(hipStreamSynchronize(s), "scan");
     tm.mark();  // 3
 
     // ---- outputs

@@ -3,12 +3,12 @@
 //
 // Sort: 8-bit digits, only as many passes as the key range needs. Each pass
 // is a digit histogram per 4096-element tile (LDS atomics), a scan of the
-// digit-major histogram table, and a stable scatter: every round of 256
-// elements is ranked per wavefront with ballots (eight ballots match the
-// lanes that share a digit; mbcnt gives the rank among them), wave counts go
-// through LDS so later waves land after earlier ones, and the whole tile is
-// staged in LDS in digit order so that the global writes of a digit run are
-// contiguous (about 16 elements per run).
+// digit-major histogram table, and a stable scatter: each wavefront ranks
+// its quarter of the tile with ballots (eight ballots match the lanes that
+// share a digit; mbcnt gives the rank among them) against its own digit
+// counters, one prefix over the wavefronts orders the quarters, and the
+// whole tile is staged in LDS in digit order so that the global writes of a
+// digit run are contiguous (about 16 elements per run).
 #include "c3x_internal.h"
 #include "c3x_sort.h"
 
@@ -74,75 +74,84 @@ __device__ __forceinline__ uint32_t block256_excl_scan(uint32_t x, uint32_t *wsu
 }
 
 // Stable scatter of one 4096-element tile. The tile's own digit histogram
-// (from k_digit_hist) gives where each digit's run starts inside the tile;
-// 16 rounds of 256 elements rank themselves per wave with ballots and land
-// in LDS in (digit, original order); the tile then leaves LDS in order, so
-// consecutive threads write consecutive addresses of one digit run. Wave
-// counts are triple-buffered, so each round needs one barrier.
+// (from k_digit_hist) gives where each digit's run starts inside the tile.
+// Each wavefront ranks its own contiguous quarter of the tile, 64 elements
+// a round, with no barrier between rounds: eight ballots match the lanes
+// that share a digit, mbcnt ranks them, and a per-wavefront digit counter in
+// LDS (read by the group, advanced by its last lane) gives the group's place
+// among the wavefront's earlier elements of that digit. One prefix over the
+// four wavefronts' counters then places every element in LDS in (digit,
+// original order); the tile leaves LDS in order, so consecutive threads
+// write consecutive addresses of one digit run.
 __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
     const uint32_t *__restrict__ offs, const uint32_t *__restrict__ hist, int nblocks)
 {
+    constexpr int kPerWave = kSortTile / kWaves;  // 1024
+    constexpr int kRounds = kPerWave / 64;        // 16
     __shared__ uint32_t sk[kSortTile], sv[kSortTile];
     __shared__ uint32_t gbase[256], tstart[256];
-    __shared__ uint32_t run[2][256];
-    __shared__ uint32_t wcnt[3][kWaves][256];
+    __shared__ uint32_t wc[kWaves][256];
     __shared__ uint32_t wsum[kWaves];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    const int64_t wbase = tbase + (int64_t)wave * kPerWave + __lane_id();
     uint32_t hc = hist[(int64_t)tid * nblocks + blockIdx.x];
     gbase[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
     uint32_t ts = block256_excl_scan(hc, wsum);
     tstart[tid] = ts;
-    run[0][tid] = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        wcnt[0][w][tid] = 0;
-        wcnt[1][w][tid] = 0;
-    }
+    for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
     // all of this thread's elements are loaded up front (memory-level
     // parallelism); the ranking rounds then work from registers
-    uint32_t kk[kSortItems], vv[kSortItems];
+    uint32_t kk[kRounds], vv[kRounds], loc[kRounds];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        int64_t e = tbase + r * kSortBlock + tid;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t e = wbase + r * 64;
         kk[r] = e < n ? kin[e] : 0u;
         vv[r] = e < n ? vin[e] : 0u;
     }
     __syncthreads();
+    uint32_t *cnt = wc[wave];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int b = r % 3, rb = r & 1;
-        int64_t e = tbase + r * kSortBlock + tid;
-        bool valid = e < n;
-        uint32_t k = kk[r];
-        uint32_t v = vv[r];
-        uint32_t d = (k >> shift) & 255u;
+    for (int r = 0; r < kRounds; ++r) {
+        const bool valid = wbase + r * 64 < n;
+        const uint32_t d = (kk[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            uint64_t bb = __ballot((d >> bit) & 1u);
+            const uint64_t bb = __ballot((d >> bit) & 1u);
             peers &= ((d >> bit) & 1u) ? bb : ~bb;
         }
-        unsigned rank = rank_in_mask(peers & lanemask_lt());
-        if (valid && rank == 0) wcnt[b][wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t before = 0;
-            for (int w = 0; w < wave; ++w) before += wcnt[b][w][d];
-            uint32_t slot = tstart[d] + run[rb][d] + before + rank;
-            sk[slot] = k;
-            sv[slot] = v;
+        const unsigned rank = rank_in_mask(peers & lanemask_lt());
+        const unsigned grp = (unsigned)__popcll(peers);
+        // the group's read of its counter comes before its last lane's update
+        // (one wavefront's LDS operations complete in order)
+        const uint32_t c = valid ? cnt[d] : 0u;
+        loc[r] = c + rank;
+        if (valid && rank + 1 == grp) cnt[d] = c + grp;
+    }
+    __syncthreads();
+    {  // thread tid = digit: where each wavefront's elements of it start
+        uint32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t t = wc[w][tid];
+            wc[w][tid] = acc;
+            acc += t;
         }
-        uint32_t tot = 0;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) tot += wcnt[b][w][tid];
-        run[rb ^ 1][tid] = run[rb][tid] + tot;
-        const int bc = (r + 2) % 3;  // next written in round r + 2
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) wcnt[bc][w][tid] = 0;
+    for (int r = 0; r < kRounds; ++r) {
+        if (wbase + r * 64 < n) {
+            const uint32_t d = (kk[r] >> shift) & 255u;
+            const uint32_t slot = tstart[d] + cnt[d] + loc[r];
+            sk[slot] = kk[r];
+            sv[slot] = vv[r];
+        }
     }
     __syncthreads();
     int nt = (int)min<int64_t>(kSortTile, n - tbase);

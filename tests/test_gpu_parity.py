@@ -318,3 +318,28 @@ def test_dense_emission(c3x, dev, precision):
     seg = np.bincount(o.ia, minlength=cat.nA)
     assert seg.max() >= 8 and 1.5 * cat.nA < len(o.ia) < 2 * cat.nA
     assert_parity(gpu_match(c3x, dev, cat, precision), o)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("wide_min", ["0", "1", "4"])
+def test_wavefront_rows(c3x, dev, cfg2_small, cfg2_small_oracle, cfg3_small, precision, wide_min,
+                        monkeypatch):
+    """Rows counted one lane each (0), every row by a wavefront of its own (1),
+    and a split at 4 candidates: the same pairs, best matches, band decisions
+    and near-tie re-ranking, in all-matches and best-only modes."""
+    monkeypatch.setenv("C3X_WIDE_MIN", wide_min)
+    assert_parity(gpu_match(c3x, dev, cfg2_small, precision), cfg2_small_oracle)
+    g = gpu_match(c3x, dev, cfg2_small, precision, mode=2)
+    m = cfg2_small_oracle.best_idx >= 0
+    assert np.array_equal(g["ib"], cfg2_small_oracle.best_idx[m])
+    assert np.array_equal(g["best"], cfg2_small_oracle.best_idx)
+    assert_parity(gpu_match(c3x, dev, cfg3_small, precision), oracle_match(cfg3_small))
+    cat = synth.adversarial_circle(radius_arcsec=1.0, n_centres=64)
+    g = gpu_match(c3x, dev, cat, precision)
+    assert_parity(g, oracle_match(cat))
+    assert g["stats"]["n_band"] > 0
+    r = np.random.default_rng(5)
+    rb, db = synth.cap_uniform(r, 60_000, 300.0, 45.0, 0.1)
+    ra, da = synth.cap_uniform(r, 8_000, 300.0, 45.0, 0.11)
+    cat = synth.Catalogues("dense_wave", ra, da, rb, db, radius_arcsec=4.0)
+    assert_parity(gpu_match(c3x, dev, cat, precision), oracle_match(cat))
