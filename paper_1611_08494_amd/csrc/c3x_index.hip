@@ -211,7 +211,7 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
         int zz = zone_of(d, g);
         uint32_t c = cell_of(zz, a, g);
         double rx, ry, rz;
-        ref_vec(zz, ref_step(g.zinfo[zz], c), g, rx, ry, rz);
+        ref_vec(g.zref[zz], ref_step(g.zinfo[zz], c), rx, ry, rz);
         Pay32 q;
         q.x = (float)(x - rx);
         q.y = (float)(y - ry);

@@ -272,10 +272,9 @@ __device__ __forceinline__ uint32_t ref_step(const ZoneInfo &zi, uint32_t c)
     return (uint32_t)(((double)c + 0.5) * zi.g) & ((1u << kRefBits) - 1u);
 }
 
-__device__ __forceinline__ void ref_vec(int z, uint32_t step, const Grid &g, double &rx,
-                                        double &ry, double &rz)
+__device__ __forceinline__ void ref_vec(double2 zr, uint32_t step, double &rx, double &ry,
+                                        double &rz)
 {
-    double2 zr = g.zref[z];
     float sa, ca;
     sincospif((float)(2u * step + 1u) * (1.0f / (float)(1u << kRefBits)), &sa, &ca);
     rx = zr.x * (double)ca;
@@ -283,11 +282,14 @@ __device__ __forceinline__ void ref_vec(int z, uint32_t step, const Grid &g, dou
     rz = zr.y;
 }
 
+// Unit vector of (ra, dec) in degrees. The angles go to sincospi in half
+// turns (x / 180): its reduction is exact, so there is no large-argument
+// path; each component carries a few units of FP64 rounding.
 __device__ __forceinline__ void unit_vec(double ra, double dec, double &x, double &y, double &z)
 {
     double sa, ca, sd, cd;
-    sincos(ra * kDeg, &sa, &ca);
-    sincos(dec * kDeg, &sd, &cd);
+    sincospi(ra * (1.0 / 180.0), &sa, &ca);
+    sincospi(dec * (1.0 / 180.0), &sd, &cd);
     x = cd * ca;
     y = cd * sa;
     z = sd;

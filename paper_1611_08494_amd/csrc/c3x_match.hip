@@ -355,8 +355,8 @@ __device__ __forceinline__ bool cand_ranges(const MatchArgs &m, uint32_t i, cons
 template <int SHAPE, int PREC, bool BATCH>
 __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const AEll &e,
                                       const AEllR &er, const LaneF32 &f, CellCache &cc,
-                                      const Thr &th, int z, const ZoneInfo &zi, uint32_t key,
-                                      const PayOf<PREC> &b, uint32_t j, double &c2o)
+                                      const Thr &th, int z, const ZoneInfo &zi, double2 zr,
+                                      uint32_t key, const PayOf<PREC> &b, uint32_t j, double &c2o)
 {
     int d;
     if constexpr (PREC == C3X_FP64) {
@@ -382,7 +382,7 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
             if (rf != cc.ref) {
                 cc.ref = rf;
                 double rx, ry, rz;
-                ref_vec(z, st, m.g, rx, ry, rz);
+                ref_vec(zr, st, rx, ry, rz);
                 cc.ax = (float)(a.x - rx);
                 cc.ay = (float)(a.y - ry);
                 cc.az = (float)(a.z - rz);
@@ -535,15 +535,15 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     // (the FP64 path's filter chord; the mixed path recomputes it from the
     // FP64 unit vectors).
     auto coded = [&](const PayT &b, uint32_t j, double c2) -> PairTmp {
+        PairTmp t;
+        t.idxB = b.idx;
+        t.j = j;
         double c64 = c2;
         if constexpr (PREC != C3X_FP64) {
             const Pay64 b8 = m.pay64[j];
             const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
             c64 = fma(dx, dx, fma(dy, dy, dz * dz));
         }
-        PairTmp t;
-        t.idxB = b.idx;
-        t.j = j;
         t.sep = sep_code(c64, j);
         return t;
     };
@@ -575,10 +575,11 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 
     // One candidate: decide it, then count / rank it (MODE 0), write it
     // (MODE 1), or both (MODE 2). Band candidates are only listed.
-    auto visit = [&](int z, const ZoneInfo &zi, uint32_t key, const PayT &b, uint32_t j) {
+    auto visit = [&](int z, const ZoneInfo &zi, double2 zr, uint32_t key, const PayT &b,
+                     uint32_t j) {
         ++tests;
         double c2;
-        int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, key, b, j, c2);
+        int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j, c2);
         if (d == AMBIG) {
             if (MODE != 1) {
                 ++band;
@@ -634,7 +635,9 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                 if (nq == 0) continue;
                 const int z = rg.zlo + q;
                 ZoneInfo zi{};
+                double2 zr{};
                 if (!BATCH) zi = m.g.zinfo[z];
+                if (!BATCH && PREC != C3X_FP64) zr = m.g.zref[z];
                 for (uint32_t t = 0; t < nq; t += kBatch) {
                     PayT bb[kBatch];
                     uint32_t kk[kBatch];
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                     }
 #pragma unroll
                     for (int u = 0; u < kBatch; ++u)
-                        if (t + u < nq) visit(z, zi, kk[u], bb[u], j0 + t + u);
+                        if (t + u < nq) visit(z, zi, zr, kk[u], bb[u], j0 + t + u);
                 }
             }
         } else if constexpr (BATCH) {
@@ -655,10 +658,11 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             // split at RA 0/360, many zones or long ranges: walk the cells
             for_each_range(m.g, a.ra, a.dec, a.cosd, a.reach_deg, [&](int z, uint32_t j0, uint32_t j1) {
                 const ZoneInfo zi = m.g.zinfo[z];
+                const double2 zr = PREC != C3X_FP64 ? m.g.zref[z] : double2{};
                 cc.key = cc.ref = 0xffffffffu;
                 for (uint32_t j = j0; j < j1; ++j) {
                     const PayT b = pay[j];
-                    visit(z, zi, m.g.keys[j], b, j);
+                    visit(z, zi, zr, m.g.keys[j], b, j);
                 }
             });
         }
@@ -761,6 +765,7 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
 
         auto range = [&](int z, uint32_t j0, uint32_t j1) {
             const ZoneInfo zi = m.g.zinfo[z];
+            const double2 zr = PREC != C3X_FP64 ? m.g.zref[z] : double2{};
             for (uint32_t t = j0; t < j1; t += 64) {
                 const uint32_t j = t + (uint32_t)lane;
                 const bool on = j < j1;
@@ -771,7 +776,7 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                     b = pay[j];
                     const uint32_t key = PREC == C3X_FP64 ? 0u : m.g.keys[j];
                     ++tests;
-                    d = decide<SHAPE, PREC, false>(m, a, e, er, f, cc, th, z, zi, key, b, j, c2);
+                    d = decide<SHAPE, PREC, false>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j, c2);
                 }
                 const unsigned long long am = __ballot(d == AMBIG);
                 if (am) {
@@ -801,14 +806,14 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                     const uint32_t k = cnt + lane_rank(im);
                     PairTmp pt{};
                     if (d == IN) {
+                        pt.idxB = b.idx;
+                        pt.j = j;
                         double c64 = c2;
                         if constexpr (PREC != C3X_FP64) {
                             const Pay64 b8 = m.pay64[j];
                             const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
                             c64 = fma(dx, dx, fma(dy, dy, dz * dz));
                         }
-                        pt.idxB = b.idx;
-                        pt.j = j;
                         pt.sep = sep_code(c64, j);
                     }
                     if (cnt < (uint32_t)kTab) {
@@ -939,11 +944,13 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
     const Thr th = lane_thr<BATCH>(m, i, Lr);
     cand_ranges<BATCH>(m, i, a, [&](int z, uint32_t j0, uint32_t j1) {
         ZoneInfo zi{};
+        double2 zr{};
         if (!BATCH) zi = m.g.zinfo[z];
+        if (!BATCH && PREC != C3X_FP64) zr = m.g.zref[z];
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
-            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, m.g.keys[j], b, j, c2);
+            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j, c2);
             if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
@@ -1017,11 +1024,13 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
     Cand b1{INFINITY, 0xffffffffu, 0u}, b2{INFINITY, 0xffffffffu, 0u};
     cand_ranges<BATCH>(m, i, a, [&](int z, uint32_t j0, uint32_t j1) {
         ZoneInfo zi{};
+        double2 zr{};
         if (!BATCH) zi = m.g.zinfo[z];
+        if (!BATCH && PREC != C3X_FP64) zr = m.g.zref[z];
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
-            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, m.g.keys[j], b, j, c2);
+            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j, c2);
             if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             const Pay64 b8 = m.pay64[j];
@@ -1346,26 +1355,36 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
     const RowRec r = rec[a];
     best_idx[a] = r.best;
     const int nt = use_rec ? (int)min<int64_t>(len, kTab) : 0;
-    auto get = [&](int q) -> PairTmp {
-        if (q < nt) {
-            PairTmp x;
-            x.idxB = r.b[q];
-            x.j = 0;
-            x.sep = r.c[q];
-            return x;
-        }
-        return tmp[o + q];
-    };
+    static_assert(kTab == 2, "two record slots");
+    // the record's two slots are handled one by one: no indexed copy of the
+    // record (it would live in scratch)
+    PairTmp x0, x1;
+    x0.idxB = r.b[0];
+    x0.j = 0;
+    x0.sep = r.c[0];
+    x1.idxB = r.b[1];
+    x1.j = 0;
+    x1.sep = r.c[1];
     if (len > kShortSeg) {
-        for (int q = 0; q < nt; ++q) tmp[o + q] = get(q);
+        if (nt > 0) tmp[o] = x0;
+        if (nt > 1) tmp[o + 1] = x1;
         return;
     }
-    for (int q = 0; q < len; ++q) {
-        const PairTmp x = get(q);
+    // canonical position of a match: its rank by idxB (unique in a row)
+    auto rank_of = [&](uint32_t ib) {
         int rk = 0;
-        for (int y = 0; y < len; ++y) rk += get(y).idxB < x.idxB;
-        final_write<RARE>(o + rk, a, x, nB, raA, decA, radecB, r.best, oa, ob, os, bsep, err);
-    }
+        if (nt > 0) rk += x0.idxB < ib;
+        if (nt > 1) rk += x1.idxB < ib;
+        for (int y = nt; y < len; ++y) rk += tmp[o + y].idxB < ib;
+        return rk;
+    };
+    auto put = [&](const PairTmp &x) {
+        final_write<RARE>(o + rank_of(x.idxB), a, x, nB, raA, decA, radecB, r.best, oa, ob, os,
+                          bsep, err);
+    };
+    if (nt > 0) put(x0);
+    if (nt > 1) put(x1);
+    for (int q = nt; q < len; ++q) put(tmp[o + q]);
 }
 
 // BEST-only mode, one thread per A row: the best match, its separation and
