@@ -164,7 +164,7 @@ __global__ void k_bext(const BJob *__restrict__ jobs, const uint32_t *__restrict
 __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restrict__ ejob,
                         const double *__restrict__ ra, const double *__restrict__ dec, int64_t n,
                         bool isB, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                        uint32_t *__restrict__ flags)
+                        double2 *__restrict__ packed, uint32_t *__restrict__ flags)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -177,6 +177,7 @@ __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restric
         a = 0.0;
         d = 0.0;
     }
+    packed[e] = make_double2(a, d);  // one 16-byte record per entry for the gathers
     double x, y, z, lra, ldec;
     unit_vec(a, d, x, y, z);
     local_radec(jb, x, y, z, lra, ldec);
@@ -191,8 +192,7 @@ __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restric
 // Sorted B payloads: FP64 unit vector, FP32 offset from the job centre, the
 // coordinates; idx is the B entry.
 __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__restrict__ jobs,
-                            const uint32_t *__restrict__ ejob,
-                            const double *__restrict__ ra, const double *__restrict__ dec,
+                            const uint32_t *__restrict__ ejob, const double2 *__restrict__ packed,
                             int64_t n, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
                             double2 *__restrict__ radec)
 {
@@ -202,11 +202,10 @@ __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__res
     if (s >= n) return;
     uint32_t e = rows[s];
     if (e >= (uint64_t)n) e = 0;  // unreachable for a permutation
-    const uint32_t j = ejob[s];
-    const BJob &jb = jobs[j];
-    const int64_t row = entry_row(jb, e, true);
-    const double a = ra[row], d = dec[row];
-    radec[s] = make_double2(a, d);
+    const BJob &jb = jobs[ejob[s]];
+    const double2 ad = packed[e];
+    const double a = ad.x, d = ad.y;
+    radec[s] = ad;
     double x, y, z;
     unit_vec(a, d, x, y, z);
     Pay64 q;
@@ -231,8 +230,7 @@ __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__res
 // asin(sin r / cos dec'_max) of ra', padded for rounding, as sorted B
 // positions.
 __global__ void k_bgather_a(const uint32_t *__restrict__ rows, const BJob *__restrict__ jobs,
-                            const uint32_t *__restrict__ ejob,
-                            const double *__restrict__ ra, const double *__restrict__ dec,
+                            const uint32_t *__restrict__ ejob, const double2 *__restrict__ packed,
                             int64_t n, Grid g, double2 *__restrict__ arad,
                             uint32_t *__restrict__ aidx, uint32_t *__restrict__ ajob,
                             ARange *__restrict__ arng)
@@ -243,13 +241,9 @@ __global__ void k_bgather_a(const uint32_t *__restrict__ rows, const BJob *__res
     if (e >= (uint64_t)n) e = 0;
     const uint32_t j = ejob[s];
     const BJob &jb = jobs[j];
-    const int64_t row = entry_row(jb, e, false);
-    double a = ra[row], d = dec[row];
-    if (!(isfinite(a) && isfinite(d) && a >= 0.0 && a < 360.0 && fabs(d) <= 90.0)) {
-        a = 0.0;
-        d = 0.0;
-    }
-    arad[s] = make_double2(a, d);
+    const double2 ad = packed[e];  // checked (else zeroed) by the key pass
+    const double a = ad.x, d = ad.y;
+    arad[s] = ad;
     aidx[s] = e;
     ajob[s] = j;
     double x, y, z, lra, ldec;
@@ -264,7 +258,7 @@ __global__ void k_bgather_a(const uint32_t *__restrict__ rows, const BJob *__res
     const uint32_t c0 = clampu((lra - dra + jb.Dc) * jb.inv_h, jb.ncol);
     const uint32_t c1 = clampu((lra + dra + jb.Dc) * jb.inv_h, jb.ncol);
     ARange rg;
-    rg.pad = 0;
+    rg.wide = 0;
     rg.zlo = (int32_t)r0;
     bool ok = r1 - r0 < (uint32_t)kRZ && cl > 0.0 && yq < 0.9;
 #pragma unroll
@@ -469,6 +463,7 @@ struct c3x_batch {
     Pay64 *p64 = nullptr;
     Pay32 *p32 = nullptr;
     double2 *radecB = nullptr;
+    double2 *packA = nullptr, *packB = nullptr;  // entry-order coordinates
     uint32_t *dir = nullptr, *dcnt = nullptr;
     void *dws = nullptr;
     int key_bits = 32;
@@ -613,7 +608,7 @@ static hipError_t batch_front(c3x_batch *b)
     const int64_t NB = b->NB, NA = b->NA;
     if (NB > 0)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NB, 256)), dim3(256), 0, s, b->djobs, b->ejobB,
-                           b->raB, b->decB, NB, true, b->bk, b->bv, b->ctr);
+                           b->raB, b->decB, NB, true, b->bk, b->bv, b->packB, b->ctr);
     int in_tmp = 0;
     hipError_t e = radix_sort_pairs(b->bk, b->bv, b->bk2, b->bv2, NB, b->key_bits, b->bws, s,
                                     &in_tmp);
@@ -623,7 +618,7 @@ static hipError_t batch_front(c3x_batch *b)
     b->g.keys = skeys;
     if (NB > 0)
         hipLaunchKernelGGL(k_bgather_b, dim3(nblk(NB, 256)), dim3(256), 0, s, srows, b->djobs,
-                           b->ejobB, b->raB, b->decB, NB, b->p64, b->p32, b->radecB);
+                           b->ejobB, b->packB, NB, b->p64, b->p32, b->radecB);
     hipLaunchKernelGGL(k_bfill, dim3(nblk(b->g.dsize, 256)), dim3(256), 0, s, b->dcnt,
                        (int64_t)b->g.dsize, 0u);
     if (NB > 0)
@@ -634,14 +629,13 @@ static hipError_t batch_front(c3x_batch *b)
     // A: keys, sort, records and candidate ranges
     if (NA > 0)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NA, 256)), dim3(256), 0, s, b->djobs, b->ejobA,
-                           b->raA, b->decA, NA, false, b->ak, b->av, b->ctr);
+                           b->raA, b->decA, NA, false, b->ak, b->av, b->packA, b->ctr);
     e = radix_sort_pairs(b->ak, b->av, b->ak2, b->av2, NA, b->key_bits, b->aws, s, &in_tmp);
     if (e != hipSuccess) return e;
     const uint32_t *arows = in_tmp ? b->av2 : b->av;
     if (NA > 0)
         hipLaunchKernelGGL(k_bgather_a, dim3(nblk(NA, 256)), dim3(256), 0, s, arows, b->djobs,
-                           b->ejobA, b->raA, b->decA, NA, b->g, b->arad, b->aidx, b->ajob,
-                           b->arng);
+                           b->ejobA, b->packA, NA, b->g, b->arad, b->aidx, b->ajob, b->arng);
     // count + emit
     MatchArgs m = batch_args(b);
     const unsigned grid = nblk(NA, kMatchBlock);
@@ -986,6 +980,8 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->p64 = M.get_n<Pay64>(NB);
     if (b->prec == C3X_MIXED) b->p32 = M.get_n<Pay32>(NB);
     b->radecB = M.get_n<double2>(NB);
+    b->packB = M.get_n<double2>(std::max<int64_t>(NB, 1));
+    b->packA = M.get_n<double2>(std::max<int64_t>(NA, 1));
     const int64_t dmax = std::max<int64_t>(1024, 2 * NB) + 2;
     b->dir = M.get_n<uint32_t>(dmax);
     b->dcnt = M.get_n<uint32_t>(dmax);
@@ -1030,7 +1026,8 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->obsep = M.get_n<double>(NA);
     b->joboff = M.get_n<int64_t>(nj + 1);
     bool ok = b->bk && b->bv && b->bk2 && b->bv2 && b->bws && b->p64 &&
-              (b->prec != C3X_MIXED || b->p32) && b->radecB && b->dir && b->dcnt && b->dws &&
+              (b->prec != C3X_MIXED || b->p32) && b->radecB && b->packA && b->packB &&
+              b->dir && b->dcnt && b->dws &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
               b->arng && b->cnts && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
               b->hl && b->xent && b->pos && b->unc && b->d_hin && b->d_vi && b->d_vk &&

@@ -123,7 +123,7 @@ constexpr int kRZ = 3;
 struct alignas(8) ARange {
     uint32_t j0[kRZ];
     uint16_t n[kRZ];
-    uint16_t pad;          // 1: counted by a wavefront of its own
+    uint16_t wide;         // 1: counted by a wavefront of its own
     int32_t zlo;
 };
 static_assert(sizeof(ARange) == 24, "24-byte range record");
@@ -131,7 +131,7 @@ static_assert(sizeof(ARange) == 24, "24-byte range record");
 // A row counted by a wavefront of its own (marked when A is prepared).
 __device__ __forceinline__ bool wide_row(const ARange &r)
 {
-    return r.pad != 0;
+    return r.wide != 0;
 }
 
 // One job of a batch (device job table). Its A and B rows are taken into a

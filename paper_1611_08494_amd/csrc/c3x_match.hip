@@ -113,7 +113,7 @@ __device__ __forceinline__ ARange a_ranges(const Grid &g, double ra, double dec,
 {
     ARange rg;
     rg.zlo = -1;
-    rg.pad = 0;
+    rg.wide = 0;
     double x, y, z;
     unit_vec(ra, dec, x, y, z);
     const double cosd = sqrt(x * x + y * y) * (1.0 - 1e-12) - 1e-15;
@@ -203,7 +203,7 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
         }
         const bool wd = rg.zlo < 0 || nc >= 16 * wide_min ||
                         (nc >= wide_min && (few || (uint64_t)nc * cnt >= 4ull * sum));
-        rg.pad = wd ? 1 : 0;
+        rg.wide = wd ? 1 : 0;
         const unsigned long long wm = __ballot(wd);
         if (wm) {
             const int l0 = __builtin_ffsll((long long)wm) - 1;
