@@ -173,6 +173,15 @@ c3x_status c3x_result_copy(const c3x_result *r, int32_t *idxA, int32_t *idxB,
                            double *sep_arcsec, int32_t *best_idxB, double *best_sep_arcsec,
                            void *stream);
 
+/* Device views of a result's arrays, owned by the result: valid until
+ * c3x_result_free (which first waits for the device, so that no queued work
+ * still reads them). Layout as for c3x_result_copy; any output may be NULL.
+ * The arrays are complete once the stream of the call that made the result
+ * has reached the point where that call returned. */
+c3x_status c3x_result_views(const c3x_result *r, const int32_t **idxA, const int32_t **idxB,
+                            const double **sep_arcsec, const int32_t **best_idxB,
+                            const double **best_sep_arcsec);
+
 /* Counters and timings of the call that produced r (or of an index). */
 c3x_status c3x_result_stats(const c3x_result *r, c3x_stats *s);
 c3x_status c3x_index_stats(const c3x_index *ix, c3x_stats *s);

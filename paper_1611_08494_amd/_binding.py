@@ -94,6 +94,9 @@ def lib():
     L.c3x_result_sizes.restype = ctypes.c_int
     L.c3x_result_copy.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.c3x_result_copy.restype = ctypes.c_int
+    pvp = ctypes.POINTER(vp)
+    L.c3x_result_views.argtypes = [vp, pvp, pvp, pvp, pvp, pvp]
+    L.c3x_result_views.restype = ctypes.c_int
     L.c3x_result_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.c3x_result_stats.restype = ctypes.c_int
     L.c3x_index_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -208,14 +211,59 @@ def build_index(ra, dec, frame: int = EQUATORIAL, reach_hint_arcsec: float = 0.0
     return Index(h, ra.shape[0], frame, precision)
 
 
+class _ResultOwner:
+    """Keeps a c3x_result alive while tensors view its device arrays."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        if self.handle:
+            lib().c3x_result_free(self.handle)
+            self.handle = None
+
+
+class _DeviceArray:
+    """One of a result's arrays, exposed without a copy (CUDA array interface;
+    the tensor made from it keeps it, and so the result, alive)."""
+
+    def __init__(self, owner, ptr, n, typestr):
+        self.owner = owner
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr,
+                                         "data": (ptr, False), "version": 2}
+
+
+def _views(h, dev) -> MatchResult:
+    """Tensors over the result's own device arrays; the result is freed when
+    the last of them goes."""
+    torch = _torch()
+    owner = _ResultOwner(h)
+    npairs = ctypes.c_int64()
+    na = ctypes.c_int64()
+    check(lib().c3x_result_sizes(h, ctypes.byref(npairs), ctypes.byref(na)))
+    ptrs = [ctypes.c_void_p() for _ in range(5)]
+    check(lib().c3x_result_views(h, *[ctypes.byref(p) for p in ptrs]))
+    st = Stats()
+    check(lib().c3x_result_stats(h, ctypes.byref(st)))
+    out = []
+    for p, n, ts, dt in zip(ptrs, (npairs.value,) * 3 + (na.value,) * 2,
+                            ("<i4", "<i4", "<f8", "<i4", "<f8"),
+                            (torch.int32, torch.int32, torch.float64, torch.int32,
+                             torch.float64)):
+        if n == 0 or not p.value:
+            out.append(torch.empty(n, dtype=dt, device=dev))
+        else:
+            out.append(torch.as_tensor(_DeviceArray(owner, p.value, n, ts), device=dev))
+    return MatchResult(*out, st.as_dict())
+
+
 def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
           radius_arcsec: float = 1.0, a=None, b=None, pa=None, pa_zero_deg: float = 0.0,
-          pa_sense: int = 1, mode: int = ALL | BEST, stream=None,
-          raw: bool = False) -> MatchResult:
+          pa_sense: int = 1, mode: int = ALL | BEST, stream=None) -> MatchResult:
     """Cross-matches catalogue A (ra, dec) against ``index``. Returns device
     tensors: idxA, idxB (int32), sep (float64 arcsec) in canonical order and
-    best_idx (int32, -1 if unmatched), best_sep (float64, NaN) per A row."""
-    torch = _torch()
+    best_idx (int32, -1 if unmatched), best_sep (float64, NaN) per A row.
+    The tensors view the result's own device arrays (no copy)."""
     ra = _dev_f64(ra, "ra")
     dec = _dev_f64(dec, "dec")
     if ra.shape != dec.shape:
@@ -235,43 +283,7 @@ def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
     h = ctypes.c_void_p()
     check(lib().c3x_match(index.handle, ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(frame),
                           ctypes.byref(ar), int(mode), ctypes.byref(o), ctypes.byref(h)))
-    try:
-        npairs = ctypes.c_int64()
-        na = ctypes.c_int64()
-        check(lib().c3x_result_sizes(h, ctypes.byref(npairs), ctypes.byref(na)))
-        dev = ra.device
-        P = npairs.value
-        ia = torch.empty(P, dtype=torch.int32, device=dev)
-        ib = torch.empty(P, dtype=torch.int32, device=dev)
-        sep = torch.empty(P, dtype=torch.float64, device=dev)
-        bi = torch.empty(na.value, dtype=torch.int32, device=dev)
-        bs = torch.empty(na.value, dtype=torch.float64, device=dev)
-        check(lib().c3x_result_copy(h, ia.data_ptr(), ib.data_ptr(), sep.data_ptr(), bi.data_ptr(),
-                                    bs.data_ptr(), sp))
-        st = Stats()
-        check(lib().c3x_result_stats(h, ctypes.byref(st)))
-    finally:
-        lib().c3x_result_free(h)
-    return MatchResult(ia, ib, sep, bi, bs, st.as_dict())
-
-
-def _fetch(h, dev) -> MatchResult:
-    torch = _torch()
-    npairs = ctypes.c_int64()
-    na = ctypes.c_int64()
-    check(lib().c3x_result_sizes(h, ctypes.byref(npairs), ctypes.byref(na)))
-    P = npairs.value
-    ia = torch.empty(P, dtype=torch.int32, device=dev)
-    ib = torch.empty(P, dtype=torch.int32, device=dev)
-    sep = torch.empty(P, dtype=torch.float64, device=dev)
-    bi = torch.empty(na.value, dtype=torch.int32, device=dev)
-    bs = torch.empty(na.value, dtype=torch.float64, device=dev)
-    check(lib().c3x_result_copy(h, ia.data_ptr(), ib.data_ptr(), sep.data_ptr(), bi.data_ptr(),
-                                bs.data_ptr(), None))
-    torch.cuda.synchronize(dev)
-    st = Stats()
-    check(lib().c3x_result_stats(h, ctypes.byref(st)))
-    return MatchResult(ia, ib, sep, bi, bs, st.as_dict())
+    return _views(h, ra.device)
 
 
 class Batch:
@@ -304,10 +316,7 @@ class Batch:
     def result(self) -> MatchResult:
         h = ctypes.c_void_p()
         check(lib().c3x_batch_result(self._h, ctypes.byref(h)))
-        try:
-            return _fetch(h, self.device)
-        finally:
-            lib().c3x_result_free(h)
+        return _views(h, self.device)
 
     def pair_offsets(self):
         out = (ctypes.c_int64 * (self.n_jobs + 1))()

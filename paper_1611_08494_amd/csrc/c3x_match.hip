@@ -1751,8 +1751,13 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     uint32_t *ktmp = tmp.get_n<uint32_t>(nA), *rtmp = tmp.get_n<uint32_t>(nA);
     void *ws = tmp.get(std::max(radix_ws_bytes(nA), scan_ws_bytes(nA + 1)));
     // bad, amb_n, tie_n, col_n, err, emit overflow, segments (2), wide rows
-    uint32_t *ctr = tmp.get_n<uint32_t>(16);
-    unsigned long long *c64 = tmp.get_n<unsigned long long>(3);  // tests, band, placed
+    // one block of counters, read back with one copy: 16 u32, 3 u64 (tests,
+    // band, placed), then the overflow regions' counters
+    constexpr int kPoolWords = kEmitPools * kEmitPoolStride;
+    constexpr size_t kCtrBytes = 128 + kPoolWords * sizeof(uint32_t);
+    uint8_t *cblk = (uint8_t *)tmp.get(kCtrBytes);
+    uint32_t *ctr = (uint32_t *)cblk;
+    unsigned long long *c64 = (unsigned long long *)(cblk + 64);
     double2 *arad = tmp.get_n<double2>(nA);
     double2 *packed = tmp.get_n<double2>(nA);
     ARange *arng = tmp.get_n<ARange>(nA);
@@ -1773,9 +1778,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     R->best_idx = R->mem.get_n<int32_t>(nA);
     R->best_sep = R->mem.get_n<double>(nA);
     if (!R->best_idx || !R->best_sep) return fail(C3X_ENOMEM, "best buffers");
-    HIPCHK(hipMemsetAsync(ctr, 0, 16 * sizeof(uint32_t), s), "memset");
+    HIPCHK(hipMemsetAsync(cblk, 0, kCtrBytes, s), "memset");
     HIPCHK(hipMemsetAsync(ctr, 0xff, sizeof(uint32_t), s), "memset");
-    HIPCHK(hipMemsetAsync(c64, 0, 3 * sizeof(unsigned long long), s), "memset");
     const double *sa = area->semi_major_arcsec, *sb = area->semi_minor_arcsec, *pa = area->pa_deg;
     if (nA > 0)
         hipLaunchKernelGGL(k_prep_a, dim3(nblk(nA, 256)), dim3(256), 0, s, ra, dec, nA, ix->grid,
@@ -1862,7 +1866,6 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_placed = c64 + 2;
     m.ov_flag = ctr + 5;
     bool emit = false;
-    const int kPoolWords = kEmitPools * kEmitPoolStride;
     if (all && nA > 0) {
         // regions sized from the need seen by recent calls (entries per 1024
         // A rows), at least nA / 8 entries in all
@@ -1875,10 +1878,9 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             per = (uint64_t)std::max<long long>(atoll(ev), -1);
         if (per > 0 && per < (1ull << 26)) {
             m.ovl = tmp.get_n<OvEnt>(per * kEmitPools);
-            m.octr = tmp.get_n<uint32_t>(kPoolWords);
+            m.octr = (uint32_t *)(cblk + 128);
             m.ov_pool = (uint32_t)per;
             emit = m.ovl && m.octr;
-            if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
         }
     }
     // band candidates decided by the FP64 recheck right after the count:
@@ -1897,6 +1899,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                                m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
                                ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10);
     };
+    std::vector<uint8_t> hblk(kCtrBytes);
     uint32_t hctr[16];
     unsigned long long h64[3];
     std::vector<uint32_t> hoctr(kPoolWords);
@@ -1911,12 +1914,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipGetLastError(), "count pass");
         if (nA > 0) recheck();
         HIPCHK(hipGetLastError(), "band recheck");
-        HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
-        HIPCHK(hipMemcpyAsync(h64, c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
-        if (emit)
-            HIPCHK(hipMemcpyAsync(hoctr.data(), m.octr, kPoolWords * sizeof(uint32_t),
-                                  hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(hipMemcpyAsync(hblk.data(), cblk, emit ? kCtrBytes : 128, hipMemcpyDeviceToHost, s),
+               "copy");
         HIPCHK(hipStreamSynchronize(s), "count pass");
+        memcpy(hctr, hblk.data(), sizeof(hctr));
+        memcpy(h64, hblk.data() + 64, sizeof(h64));
+        if (emit) memcpy(hoctr.data(), hblk.data() + 128, kPoolWords * sizeof(uint32_t));
         if (hctr[0] != 0xffffffffu)
             return fail(C3X_EINVAL,
                         "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= 90, not "
@@ -2316,7 +2319,27 @@ extern "C" c3x_status c3x_result_stats(const c3x_result *r, c3x_stats *st)
     return C3X_OK;
 }
 
-extern "C" void c3x_result_free(c3x_result *r) { delete r; }
+extern "C" c3x_status c3x_result_views(const c3x_result *r, const int32_t **idxA,
+                                       const int32_t **idxB, const double **sep_arcsec,
+                                       const int32_t **best_idxB, const double **best_sep_arcsec)
+{
+    if (!r) return fail(C3X_EINVAL, "NULL result");
+    if (idxA) *idxA = r->idxA;
+    if (idxB) *idxB = r->idxB;
+    if (sep_arcsec) *sep_arcsec = r->sep;
+    if (best_idxB) *best_idxB = r->best_idx;
+    if (best_sep_arcsec) *best_sep_arcsec = r->best_sep;
+    return C3X_OK;
+}
+
+extern "C" void c3x_result_free(c3x_result *r)
+{
+    if (!r) return;
+    // views may still be read by queued work on any stream: its blocks go
+    // back to the cache only when the device is idle
+    (void)hipDeviceSynchronize();
+    delete r;
+}
 
 // The batched form: its kernels and entry points use the ones above.
 #include "c3x_batch.hip"

@@ -28,7 +28,7 @@ def L():
 def test_header_declares_the_boundary():
     fns = header_functions()
     for f in ("c3x_build_index", "c3x_match", "c3x_result_sizes", "c3x_result_copy",
-              "c3x_result_stats", "c3x_result_free", "c3x_index_free", "c3x_last_error",
+              "c3x_result_views", "c3x_result_stats", "c3x_result_free", "c3x_index_free", "c3x_last_error",
               "c3x_version", "c3x_abi_version", "c3x_index_stats"):
         assert f in fns
 
@@ -57,6 +57,9 @@ def test_argument_errors_need_no_device(L):
     assert L.c3x_match(None, None, None, 0, 0, ctypes.byref(area), 3, None,
                        ctypes.byref(h)) == b.EINVAL
     assert L.c3x_result_sizes(None, None, None) == b.EINVAL
+    b.lib()  # argument types
+    assert L.c3x_result_views(None, None, None, None, None, None) == b.EINVAL
+    L.c3x_result_free(None)  # a no-op
 
 
 def test_batch_argument_errors_need_no_device(L):
