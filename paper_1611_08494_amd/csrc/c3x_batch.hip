@@ -345,12 +345,12 @@ __global__ void k_bapply(const BAmb *__restrict__ hl, const uint32_t *__restrict
 
 // Band matches: counted, and listed as the k-th match of their row.
 __global__ void k_badd(const uint4 *__restrict__ bin, const uint32_t *__restrict__ n_bin,
-                       uint32_t cap, uint32_t *cnts, WEnt *__restrict__ out)
+                       uint32_t cap, RowRec *rec, WEnt *__restrict__ out)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= min(*n_bin, cap)) return;
     const uint4 q = bin[t];
-    const uint32_t k = atomicAdd(&cnts[q.y], 1u);
+    const uint32_t k = atomicAdd(&rec[q.y].cnt, 1u);
     out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
@@ -474,7 +474,6 @@ struct c3x_batch {
     double2 *arad = nullptr;
     uint32_t *aidx = nullptr, *ajob = nullptr;
     ARange *arng = nullptr;
-    uint32_t *cnts = nullptr;
     RowRec *rec = nullptr;
     // lists
     uint2 *amb = nullptr, *tie = nullptr;
@@ -500,7 +499,7 @@ struct c3x_batch {
     // counters: 0 flags, 1 amb_n, 2 tie_n, 3 unc_n, 4 err, 5 ov_flag, 6-7 seg_n,
     // 8 n_bin, 9 n_hl, 10 n_pos, 11 bad job
     uint32_t *ctr = nullptr;
-    unsigned long long *c64 = nullptr;  // tests, band, placed
+    unsigned long long *c64 = nullptr;  // statistics copies (tests, band, placed)
     // outputs
     int64_t *off = nullptr;
     void *sws = nullptr;
@@ -571,7 +570,7 @@ static MatchArgs batch_args(c3x_batch *b)
     m.jobs = b->djobs;
     m.ajob = b->ajob;
     m.nA = (int32_t)b->NA;
-    m.cnts = b->cnts;
+    m.best_only = 0;
     m.rec = b->rec;
     m.amb_n = b->ctr + 1;
     m.amb = b->amb;
@@ -601,7 +600,8 @@ static hipError_t batch_front(c3x_batch *b)
     hipStream_t s = b->s;
     const int nj = b->nj;
     hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, b->ctr, (int64_t)16, 0u);
-    hipLaunchKernelGGL(k_bfill64, dim3(1), dim3(64), 0, s, b->c64, (int64_t)4);
+    hipLaunchKernelGGL(k_bfill64, dim3(kStatSlots * kStatStride / 64), dim3(64), 0, s, b->c64,
+                       (int64_t)kStatSlots * kStatStride);
     hipLaunchKernelGGL(k_bfill, dim3(nblk(kEmitPools * kEmitPoolStride, 256)), dim3(256), 0, s,
                        b->octr, (int64_t)kEmitPools * kEmitPoolStride, 0u);
     // B: keys, sort, payloads, directory
@@ -667,7 +667,7 @@ static hipError_t batch_front(c3x_batch *b)
     hipLaunchKernelGGL(k_bapply, dim3(nblk(b->hl_cap, 256)), dim3(256), 0, s, b->hl, b->ctr + 9,
                        b->hl_cap, b->d_hin, b->bin, b->ctr + 8, b->bin_cap, b->ctr);
     hipLaunchKernelGGL(k_badd, dim3(nblk(b->bin_cap, 256)), dim3(256), 0, s, b->bin, b->ctr + 8,
-                       b->bin_cap, b->cnts, b->xent);
+                       b->bin_cap, b->rec, b->xent);
     // best matches the filter cannot rank: FP64 on the GPU; what FP64 cannot
     // separate is listed (c3x_batch_result ranks it in binary128)
     const uint32_t npos = b->tie_cap + b->bin_cap;
@@ -682,7 +682,8 @@ static hipError_t batch_front(c3x_batch *b)
                            b->pos, npos, b->ctr + 10, b->ctr + 3, b->unc);
     // counts -> offsets (off[NA] = P)
     if (NA > 0) {
-        e = scan_u32_to_i64(b->cnts, b->off, NA, b->off + NA, b->sws, s);
+        e = scan_u32_to_i64(&b->rec->cnt, sizeof(RowRec) / sizeof(uint32_t), b->off, NA,
+                            b->off + NA, b->sws, s);
         if (e != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL(k_bfill64, dim3(1), dim3(64), 0, s, (unsigned long long *)b->off,
@@ -995,7 +996,6 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->aidx = M.get_n<uint32_t>(NA);
     b->ajob = M.get_n<uint32_t>(NA);
     b->arng = M.get_n<ARange>(NA);
-    b->cnts = M.get_n<uint32_t>(NA);
     b->rec = M.get_n<RowRec>(NA);
     b->amb_cap = (uint32_t)std::min<int64_t>(NA / 16 + 4096, 1 << 26);
     b->tie_cap = (uint32_t)std::min<int64_t>(NA / 16 + 4096, 1 << 26);
@@ -1016,7 +1016,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->d_vk = M.get_n<unsigned long long>(b->hl_cap);
     b->d_nv = M.get_n<uint32_t>(1);
     b->ctr = M.get_n<uint32_t>(16);
-    b->c64 = M.get_n<unsigned long long>(4);
+    b->c64 = M.get_n<unsigned long long>(kStatSlots * kStatStride);
     b->off = M.get_n<int64_t>(NA + 1);
     b->sws = M.get(scan_ws_bytes(NA + 1));
     b->seg_cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(NA, 1), 1 << 22);
@@ -1029,7 +1029,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
               (b->prec != C3X_MIXED || b->p32) && b->radecB && b->packA && b->packB &&
               b->dir && b->dcnt && b->dws &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
-              b->arng && b->cnts && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
+              b->arng && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
               b->hl && b->xent && b->pos && b->unc && b->d_hin && b->d_vi && b->d_vk &&
               b->d_nv && b->ctr && b->c64 && b->off && b->sws && b->seg_list && b->seg_huge &&
               b->obest && b->obsep && b->joboff;
@@ -1123,12 +1123,15 @@ static c3x_status batch_finish(c3x_batch *b)
 {
     hipStream_t s = b->s;
     uint32_t hc[16];
-    unsigned long long h64[4];
+    std::vector<unsigned long long> hs(kStatSlots * kStatStride);
+    unsigned long long h64[3];
     int64_t P = 0;
     BCHK(hipMemcpyAsync(hc, b->ctr, sizeof(hc), hipMemcpyDeviceToHost, s), "copy");
-    BCHK(hipMemcpyAsync(h64, b->c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
+    BCHK(hipMemcpyAsync(hs.data(), b->c64, hs.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s), "copy");
     BCHK(hipMemcpyAsync(&P, b->off + b->NA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     BCHK(hipStreamSynchronize(s), "batch result");
+    stat_sums(hs.data(), h64);
     if (hc[0] & kBFlagStale)
         return fail(C3X_EINVAL, "batch inputs moved outside the planned sky boxes: plan again");
     if ((hc[0] & kBFlagCap) || hc[1] > b->amb_cap || hc[2] > b->tie_cap || hc[5] ||

@@ -102,15 +102,28 @@ struct alignas(8) OvEnt {
     double code;
 };
 constexpr int kTab = 2;              // table slots per A row
+// Statistics counters (candidates tested, band candidates, matches placed):
+// 64 copies on separate 128-byte lines, block b adding to copy b mod 64, so
+// that one address does not take every block's atomic; the host sums them.
+constexpr int kStatSlots = 64;
+constexpr int kStatStride = 16;      // u64 words per copy
+enum { kStatTests = 0, kStatBand = 1, kStatPlaced = 2 };
+__device__ __forceinline__ unsigned long long *stat_slot(unsigned long long *field)
+{
+    return field + (size_t)(blockIdx.x & (kStatSlots - 1)) * kStatStride;
+}
 constexpr int kEmitPools = 64;       // overflow-list counters (spread contention)
 constexpr int kEmitPoolStride = 32;  // u32 words between two counters (128 B)
 
 // Per-A record of the count pass (idxA order), one aligned 32-byte store
-// per row: the best match and the row's first kTab matches.
+// per row (a whole sector: a row's count kept apart would be a scattered
+// 4-byte store of its own): the best match, the count and the row's first
+// kTab matches. Best-only calls keep no matches; b[0] then holds the best
+// match's sorted B position.
 struct alignas(32) RowRec {
     int32_t best;          // idxB of the best match, -1: none
-    uint32_t best_j;       // its sorted B position
-    uint32_t b[kTab];      // idxB of the row's first matches
+    uint32_t cnt;          // matches of the row
+    uint32_t b[kTab];      // idxB of the row's first matches (best only: b[0] = best's j)
     double c[kTab];        // their coded separations (see sep_code)
 };
 static_assert(sizeof(RowRec) == 32, "one 32-byte store per row");
@@ -184,8 +197,8 @@ struct MatchArgs {
     int32_t r_zero;        // radius exactly 0
     double L_rad;          // bound on |p - cell reference| (FP32 error model)
     // count pass
-    uint32_t *cnts;        // [nA] matches per row (idxA order)
-    RowRec *rec;           // [nA] idxA order
+    RowRec *rec;           // [nA] idxA order: count, best, first matches
+    int32_t best_only;     // no table: rec.b[0] keeps the best's sorted position
     uint32_t *amb_n;       // band candidates: (sorted A pos, sorted B pos)
     uint2 *amb;
     uint32_t amb_cap;
@@ -366,8 +379,9 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// FP64 relative-accuracy recheck of the circle (error <= ~90 u against a
-// 2^-40 margin: see the library design notes).
+// FP64 relative-accuracy recheck of the circle: the haversine carries at
+// most ~90 u of error (a few units per trigonometric call and product), far
+// inside its 2^-40 margin.
 __device__ __forceinline__ int recheck_circle(const ARec &a, double2 rb, double h_r)
 {
     double cd2 = cos_dec_acc(rb.y);

@@ -44,6 +44,10 @@ namespace c3x {
 constexpr int kMatchBlock = 256;
 constexpr uint32_t kWideMin = 32;  // candidates from which a row gets a wavefront of its own
 constexpr int64_t kFewRows = 1 << 21;  // fewer A rows: one lane each leaves the device idle
+constexpr uint32_t kTileMin = 8;     // longest row of a wavefront before its union is tried
+constexpr uint32_t kTileRatio = 4;   // union at most this many times the longest row
+constexpr int kTileZones = 6;        // zones a wavefront's union may span
+constexpr uint32_t kTileChunk = 128; // candidates staged in LDS per wavefront at a time
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
 constexpr int kSegLds = 2048;   // segments up to this long are sorted in LDS
@@ -473,6 +477,76 @@ __device__ __forceinline__ double sep_from_chord2(double c2)
     return 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0);
 }
 
+// ---------------------------------------------------------------------------- wavefront helpers
+
+// Lane l's value, for every lane (l wavefront-uniform).
+__device__ __forceinline__ uint32_t rl_u32(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ double rl_f64(double v, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = rl_u32((uint32_t)u, l), hi = rl_u32((uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ Pay64 rl_pay(const Pay64 &p, int l)
+{
+    Pay64 r;
+    r.x = rl_f64(p.x, l);
+    r.y = rl_f64(p.y, l);
+    r.z = rl_f64(p.z, l);
+    r.idx = rl_u32(p.idx, l);
+    r.pad = 0;
+    return r;
+}
+__device__ __forceinline__ Pay32 rl_pay(const Pay32 &p, int l)
+{
+    Pay32 r;
+    r.x = __uint_as_float(rl_u32(__float_as_uint(p.x), l));
+    r.y = __uint_as_float(rl_u32(__float_as_uint(p.y), l));
+    r.z = __uint_as_float(rl_u32(__float_as_uint(p.z), l));
+    r.idx = rl_u32(p.idx, l);
+    return r;
+}
+
+// Lane rank among the lanes of mask hm below this one.
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long hm)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+}
+
+// A lane's ranges as plain values (no indexed copy of the record).
+struct LaneRanges {
+    uint32_t j0a, j0b, j0c, na, nb, nc;
+    int zlo;
+};
+__device__ __forceinline__ LaneRanges lane_ranges(const ARange &rg, bool part)
+{
+    LaneRanges r;
+    r.j0a = rg.j0[0];
+    r.j0b = rg.j0[1];
+    r.j0c = rg.j0[2];
+    r.na = part ? rg.n[0] : 0u;
+    r.nb = part ? rg.n[1] : 0u;
+    r.nc = part ? rg.n[2] : 0u;
+    r.zlo = rg.zlo;
+    return r;
+}
+
+// A lane's sorted-B range in zone z: [lo, hi), empty (lo = hi = 0) when its
+// ranges do not reach z.
+__device__ __forceinline__ void zone_range(const LaneRanges &r, int z, uint32_t &lo, uint32_t &hi)
+{
+    static_assert(kRZ == 3, "three zones");
+    const int q = z - r.zlo;
+    const uint32_t j0 = q == 0 ? r.j0a : (q == 1 ? r.j0b : r.j0c);
+    const uint32_t n = q == 0 ? r.na : (q == 1 ? r.nb : (q == 2 ? r.nc : 0u));
+    lo = n ? j0 : 0u;
+    hi = n ? j0 + n : 0u;
+}
+
 // MODE 0: count + best; MODE 1: write every filter match into the
 // offsets from the count; MODE 2: count + best, the row's first kTab filter
 // matches kept for its record, later ones written to the overflow list.
@@ -482,6 +556,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 {
     using PayT = PayOf<PREC>;
     __shared__ unsigned long long s_tests, s_band, s_placed;
+    __shared__ PayT s_pay[kMatchBlock / 64][kTileChunk];     // dense wavefronts' chunks
+    __shared__ uint32_t s_key[kMatchBlock / 64][kTileChunk];
     if (threadIdx.x == 0) {
         s_tests = 0;
         s_band = 0;
@@ -623,7 +699,65 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         }
     };
 
-    if (active) {
+    // Dense wavefronts: when the rows of a wavefront share their candidates
+    // (the union of their ranges is at most kTileRatio times the longest
+    // row's), the union is staged in LDS a chunk at a time, read once and
+    // coalesced; each lane then walks its own ranges from LDS, in the same
+    // order as the lane-by-lane loop below.
+    bool tiled = false;
+    int tz0 = 0, tz1 = -1;
+    const bool part = active && rg.zlo >= 0;
+    const LaneRanges lr = lane_ranges(rg, part);
+    {
+        const uint32_t own = part ? (uint32_t)rg.n[0] + rg.n[1] + rg.n[2] : 0u;
+        const uint32_t mx = wave_max_u32(own);
+        const bool walk = __ballot(active && rg.zlo < 0) != 0;
+        if (!walk && mx >= kTileMin) {
+            tz0 = (int)wave_min_u32(part ? (uint32_t)rg.zlo : 0xffffffffu);
+            tz1 = (int)wave_max_u32(part ? (uint32_t)(rg.zlo + kRZ - 1) : 0u);
+            if (tz1 - tz0 < kTileZones) {
+                uint32_t un = 0;
+                for (int z = tz0; z <= tz1; ++z) {
+                    uint32_t lo, hi;
+                    zone_range(lr, z, lo, hi);
+                    const uint32_t ulo = wave_min_u32(hi > lo ? lo : 0xffffffffu);
+                    const uint32_t uhi = wave_max_u32(hi);
+                    if (uhi > ulo) un += uhi - ulo;
+                }
+                tiled = un <= kTileRatio * mx;
+            }
+        }
+    }
+    if (tiled) {
+        const uint32_t lane = threadIdx.x & 63u;
+        PayT *sp = s_pay[threadIdx.x >> 6];
+        uint32_t *sk = s_key[threadIdx.x >> 6];
+        for (int z = tz0; z <= tz1; ++z) {
+            uint32_t lo, hi;
+            zone_range(lr, z, lo, hi);
+            const uint32_t ulo = wave_min_u32(hi > lo ? lo : 0xffffffffu);
+            const uint32_t uhi = wave_max_u32(hi);
+            if (uhi <= ulo) continue;
+            ZoneInfo zi{};
+            double2 zr{};
+            if (!BATCH) zi = m.g.zinfo[z];
+            if (!BATCH && PREC != C3X_FP64) zr = m.g.zref[z];
+            for (uint32_t base = ulo; base < uhi; base += kTileChunk) {
+                const uint32_t nb = min(kTileChunk, uhi - base);
+                for (uint32_t t = lane; t < nb; t += 64) {
+                    sp[t] = pay[base + t];
+                    if (PREC != C3X_FP64) sk[t] = m.g.keys[base + t];
+                }
+                wave_sync();
+                const uint32_t a1 = min(hi, base + nb);
+                for (uint32_t j = max(lo, base); j < a1; ++j) {
+                    const PayT b = sp[j - base];
+                    visit(z, zi, zr, PREC == C3X_FP64 ? 0u : sk[j - base], b, j);
+                }
+                wave_sync();  // the chunk is read before the next one lands
+            }
+        }
+    } else if (active) {
         if (rg.zlo >= 0) {
             // the ranges found when A was prepared; candidates are loaded
             // kBatch at a time so that their loads overlap
@@ -668,11 +802,10 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         }
     }
     if (active && MODE != 1) {
-        m.cnts[a.idx] = cnt;
         RowRec r;
         r.best = cnt ? (int32_t)bidx : -1;
-        r.best_j = bj;
-        r.b[0] = tb0;
+        r.cnt = cnt;
+        r.b[0] = MODE == 0 ? bj : tb0;
         r.b[1] = tb1;
         r.c[0] = tc0;
         r.c[1] = tc1;
@@ -688,9 +821,9 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     if (band) atomicAdd(&s_band, band);
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (s_tests && MODE != 1) atomicAdd(m.n_tests, s_tests);
-        if (s_band && MODE != 1) atomicAdd(m.n_band, s_band);
-        if (s_placed) atomicAdd(m.n_placed, s_placed);
+        if (s_tests && MODE != 1) atomicAdd(stat_slot(m.n_tests), s_tests);
+        if (s_band && MODE != 1) atomicAdd(stat_slot(m.n_band), s_band);
+        if (s_placed) atomicAdd(stat_slot(m.n_placed), s_placed);
     }
 }
 
@@ -700,23 +833,6 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 // Same outputs as k_match in MODE 0 / 2 for those rows: count, best by the
 // filter's chord (near-ties listed), band candidates listed, the first kTab
 // matches in the record and later ones in the overflow list.
-__device__ __forceinline__ uint32_t rl_u32(uint32_t v, int l)
-{
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
-__device__ __forceinline__ double rl_f64(double v, int l)
-{
-    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-    const uint32_t lo = rl_u32((uint32_t)u, l), hi = rl_u32((uint32_t)(u >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Lane rank among the lanes of mask hm below this one.
-__device__ __forceinline__ uint32_t lane_rank(unsigned long long hm)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-}
 
 template <int SHAPE, int PREC, int MODE>
 __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
@@ -887,11 +1003,10 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
             }
         }
         if (lane == 0) {
-            m.cnts[a.idx] = cnt;
             RowRec r;
             r.best = cnt ? (int32_t)bidx : -1;
-            r.best_j = bj;
-            r.b[0] = tb0;
+            r.cnt = cnt;
+            r.b[0] = MODE == 0 ? bj : tb0;
             r.b[1] = tb1;
             r.c[0] = tc0;
             r.c[1] = tc1;
@@ -908,9 +1023,9 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
     if (band) atomicAdd(&s_band, band);
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (s_tests) atomicAdd(m.n_tests, s_tests);
-        if (s_band) atomicAdd(m.n_band, s_band);
-        if (s_placed) atomicAdd(m.n_placed, s_placed);
+        if (s_tests) atomicAdd(stat_slot(m.n_tests), s_tests);
+        if (s_band) atomicAdd(stat_slot(m.n_band), s_band);
+        if (s_placed) atomicAdd(stat_slot(m.n_placed), s_placed);
     }
 }
 
@@ -1060,7 +1175,7 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
                           b2.c2 - b1.c2 > 4.0 * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
         if (sure) {
             m.rec[row].best = (int32_t)b1.idxB;
-            m.rec[row].best_j = b1.j;
+            if (m.best_only) m.rec[row].b[0] = b1.j;
         } else {
             unc[atomicAdd(unc_n, 1u)] = i;
         }
@@ -1159,13 +1274,13 @@ __global__ void k_gather_pos(const uint32_t *__restrict__ pos, uint32_t n,
 
 // Band candidates found inside (sorted A position, idxA, idxB, sorted B
 // position): each is counted, and listed as the k-th match of its source.
-__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, uint32_t *cnts,
+__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, RowRec *rec,
                             WEnt *__restrict__ out)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     uint4 q = in[t];
-    uint32_t k = atomicAdd(&cnts[q.y], 1u);
+    uint32_t k = atomicAdd(&rec[q.y].cnt, 1u);
     if (out) out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
@@ -1208,7 +1323,7 @@ __global__ void k_place_ov(const OvEnt *__restrict__ ovl, uint32_t ov_pool,
     // one count per wavefront
     const unsigned long long pm = __ballot(ok);
     if (pm && (threadIdx.x & 63u) == (uint32_t)(__builtin_ffsll((long long)pm) - 1))
-        atomicAdd(placed, (unsigned long long)__popcll(pm));
+        atomicAdd(stat_slot(placed), (unsigned long long)__popcll(pm));
 }
 
 // One thread per band match found inside: to its row's record (k < kTab,
@@ -1248,23 +1363,24 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
     } else {
         tmp[p] = x;
     }
-    atomicAdd(placed, 1ull);
+    atomicAdd(stat_slot(placed), 1ull);
 }
 
 __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
-                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec)
+                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec,
+                             int best_only)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     rec[rows[t]].best = bi[t];
-    rec[rows[t]].best_j = bj[t];
+    if (best_only) rec[rows[t]].b[0] = bj[t];
 }
 
 // BEST-only output: one record per row that has a match.
-__global__ void k_nonzero(const uint32_t *__restrict__ cnts, int64_t n, uint32_t *__restrict__ out)
+__global__ void k_nonzero(const RowRec *__restrict__ rec, int64_t n, uint32_t *__restrict__ out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) out[t] = cnts[t] ? 1u : 0u;
+    if (t < n) out[t] = rec[t].cnt ? 1u : 0u;
 }
 
 // Separation (arcsec) of a coded match (see sep_code). A chord below 0.1
@@ -1404,7 +1520,7 @@ __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec
         bsep[t] = NAN;
         return;
     }
-    uint32_t bj = rec[t].best_j;
+    uint32_t bj = rec[t].b[0];
     if (bj >= (uint64_t)nB) {
         atomicOr(err, 16u);
         return;
@@ -1733,6 +1849,14 @@ using namespace c3x;
         if (e_ != hipSuccess) return fail_hip(e_, what); \
     } while (0)
 
+// Sums of the statistics copies: out[0] tests, out[1] band, out[2] placed.
+static void stat_sums(const unsigned long long *h, unsigned long long out[3])
+{
+    out[0] = out[1] = out[2] = 0;
+    for (int q = 0; q < kStatSlots; ++q)
+        for (int f = 0; f < 3; ++f) out[f] += h[q * kStatStride + f];
+}
+
 // Overflow-list demand of recent calls, in entries per 1024 A rows: sizes the
 // next call's regions so that steady workloads keep the single pass.
 static std::atomic<uint64_t> g_ov_hint{0};
@@ -1751,18 +1875,19 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     uint32_t *ktmp = tmp.get_n<uint32_t>(nA), *rtmp = tmp.get_n<uint32_t>(nA);
     void *ws = tmp.get(std::max(radix_ws_bytes(nA), scan_ws_bytes(nA + 1)));
     // bad, amb_n, tie_n, col_n, err, emit overflow, segments (2), wide rows
-    // one block of counters, read back with one copy: 16 u32, 3 u64 (tests,
-    // band, placed), then the overflow regions' counters
+    // one block of counters, read back with one copy: 16 u32, the statistics
+    // copies (tests, band, placed), then the overflow regions' counters
     constexpr int kPoolWords = kEmitPools * kEmitPoolStride;
-    constexpr size_t kCtrBytes = 128 + kPoolWords * sizeof(uint32_t);
+    constexpr size_t kStatBytes = kStatSlots * kStatStride * sizeof(unsigned long long);
+    constexpr size_t kOctrAt = 128 + kStatBytes;
+    constexpr size_t kCtrBytes = kOctrAt + kPoolWords * sizeof(uint32_t);
     uint8_t *cblk = (uint8_t *)tmp.get(kCtrBytes);
     uint32_t *ctr = (uint32_t *)cblk;
-    unsigned long long *c64 = (unsigned long long *)(cblk + 64);
+    unsigned long long *c64 = (unsigned long long *)(cblk + 128);
     double2 *arad = tmp.get_n<double2>(nA);
     double2 *packed = tmp.get_n<double2>(nA);
     ARange *arng = tmp.get_n<ARange>(nA);
     uint32_t *aidx = tmp.get_n<uint32_t>(nA);
-    uint32_t *cnts = tmp.get_n<uint32_t>(nA);
     RowRec *rec = tmp.get_n<RowRec>(nA);
     AEll *aell = nullptr;
     AEllR *aellr = nullptr;
@@ -1772,7 +1897,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
     }
     if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !packed || !aidx ||
-        !cnts || !rec || !arng)
+        !rec || !arng)
         return fail(C3X_ENOMEM, "A buffers");
     R->nA = nA;
     R->best_idx = R->mem.get_n<int32_t>(nA);
@@ -1839,7 +1964,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_tests = c64;
     m.n_band = c64 + 1;
     m.err_flag = ctr + 4;
-    m.cnts = cnts;
+    m.best_only = !all;
     m.rec = rec;
     m.wide = wide;
     m.wide_n = ctr + 8;
@@ -1878,7 +2003,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             per = (uint64_t)std::max<long long>(atoll(ev), -1);
         if (per > 0 && per < (1ull << 26)) {
             m.ovl = tmp.get_n<OvEnt>(per * kEmitPools);
-            m.octr = (uint32_t *)(cblk + 128);
+            m.octr = (uint32_t *)(cblk + kOctrAt);
             m.ov_pool = (uint32_t)per;
             emit = m.ovl && m.octr;
         }
@@ -1914,12 +2039,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipGetLastError(), "count pass");
         if (nA > 0) recheck();
         HIPCHK(hipGetLastError(), "band recheck");
-        HIPCHK(hipMemcpyAsync(hblk.data(), cblk, emit ? kCtrBytes : 128, hipMemcpyDeviceToHost, s),
-               "copy");
+        HIPCHK(hipMemcpyAsync(hblk.data(), cblk, emit ? kCtrBytes : kOctrAt,
+                              hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipStreamSynchronize(s), "count pass");
         memcpy(hctr, hblk.data(), sizeof(hctr));
-        memcpy(h64, hblk.data() + 64, sizeof(h64));
-        if (emit) memcpy(hoctr.data(), hblk.data() + 128, kPoolWords * sizeof(uint32_t));
+        stat_sums((const unsigned long long *)(hblk.data() + 128), h64);
+        if (emit) memcpy(hoctr.data(), hblk.data() + kOctrAt, kPoolWords * sizeof(uint32_t));
         if (hctr[0] != 0xffffffffu)
             return fail(C3X_EINVAL,
                         "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= 90, not "
@@ -1946,7 +2071,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipMemsetAsync(ctr + 1, 0, 2 * sizeof(uint32_t), s), "memset");
         HIPCHK(hipMemsetAsync(ctr + 5, 0, sizeof(uint32_t), s), "memset");
         HIPCHK(hipMemsetAsync(ctr + 9, 0, 2 * sizeof(uint32_t), s), "memset");
-        HIPCHK(hipMemsetAsync(c64, 0, 3 * sizeof(unsigned long long), s), "memset");
+        HIPCHK(hipMemsetAsync(c64, 0, kStatBytes, s), "memset");
         if (emit) HIPCHK(hipMemsetAsync(m.octr, 0, kPoolWords * sizeof(uint32_t), s), "memset");
     }
     // the records and the list hold every filter match unless a region ran out
@@ -1964,7 +2089,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     if (emitted)
         for (int q = 0; q < kEmitPools; ++q)
             ov_used = std::max(ov_used, std::min(hoctr[q * kEmitPoolStride], m.ov_pool));
-    if (!emitted) HIPCHK(hipMemsetAsync(c64 + 2, 0, sizeof(unsigned long long), s), "memset");
+    // (tests and band are read; the write pass counts the placed matches anew)
+    if (!emitted) HIPCHK(hipMemsetAsync(c64, 0, kStatBytes, s), "memset");
     const uint32_t n_tie = hctr[2];
     uint32_t n_bin = std::min(hctr[9], amb_cap);
     const uint32_t n_host = std::min(hctr[10], amb_cap);
@@ -2024,7 +2150,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             xent = tmp.get_n<WEnt>(n_bin);
             if (!xent) return fail(C3X_ENOMEM, "band matches");
         }
-        hipLaunchKernelGGL(k_add_pairs, dim3(nblk(n_bin, 256)), dim3(256), 0, s, bin, n_bin, cnts,
+        hipLaunchKernelGGL(k_add_pairs, dim3(nblk(n_bin, 256)), dim3(256), 0, s, bin, n_bin, rec,
                            xent);
     }
 
@@ -2047,16 +2173,19 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
 
     // ---- scan of the per-A counts (idxA order)
     int64_t *off = tmp.get_n<int64_t>(nA + 1);
-    const uint32_t *scan_in = cnts;
+    // the counts are read in place from the records (stride 8 words)
+    const uint32_t *scan_in = &rec->cnt;
+    int64_t scan_stride = sizeof(RowRec) / sizeof(uint32_t);
     if (!all) {  // one output row per A row with a match
         uint32_t *nz = tmp.get_n<uint32_t>(nA);
         if (!nz) return fail(C3X_ENOMEM, "offsets");
         if (nA > 0)
-            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
+            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, rec, nA, nz);
         scan_in = nz;
+        scan_stride = 1;
     }
     if (!off) return fail(C3X_ENOMEM, "offsets");
-    HIPCHK(scan_u32_to_i64(scan_in, off, nA, off + nA, ws, s), "scan");
+    HIPCHK(scan_u32_to_i64(scan_in, scan_stride, off, nA, off + nA, ws, s), "scan");
     int64_t P = 0;
     uint32_t nc = 0;
     HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
@@ -2132,7 +2261,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             HIPCHK(hipMemcpyAsync(d2, pbi.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             HIPCHK(hipMemcpyAsync(d3, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3, np,
-                               rec);
+                               rec, (int)!all);
             HIPCHK(hipStreamSynchronize(s), "best patch");
         }
     }
@@ -2206,9 +2335,10 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                            R->sep, ctr + 4);
     HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6
-    HIPCHK(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s), "copy");
-    HIPCHK(hipMemcpyAsync(h64, c64, sizeof(h64), hipMemcpyDeviceToHost, s), "copy");
+    HIPCHK(hipMemcpyAsync(hblk.data(), cblk, kOctrAt, hipMemcpyDeviceToHost, s), "copy");
     HIPCHK(hipStreamSynchronize(s), "c3x_match");
+    memcpy(hctr, hblk.data(), sizeof(hctr));
+    stat_sums((const unsigned long long *)(hblk.data() + 128), h64);
     if (all) {
         c3x_status st = finish_huge(fa, hctr + 6, s);
         if (st != C3X_OK) return st;

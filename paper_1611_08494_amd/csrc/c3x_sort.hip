@@ -197,14 +197,15 @@ __device__ __forceinline__ T block_excl_scan(T x, T &total)
 }
 
 template <typename Ti, typename To>
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const Ti *__restrict__ in, int64_t n,
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const Ti *__restrict__ in,
+                                                            int64_t stride, int64_t n,
                                                             To *__restrict__ part)
 {
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     To s = 0;
     for (int r = 0; r < kScanItems; ++r) {
         int64_t e = base + r * kScanBlock + threadIdx.x;
-        if (e < n) s += (To)in[e];
+        if (e < n) s += (To)in[e * stride];
     }
     To tot;
     block_excl_scan<To>(s, tot);
@@ -227,7 +228,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_partials(To *part, int64_t 
 }
 
 template <typename Ti, typename To>
-__global__ __launch_bounds__(kScanBlock) void k_scan_final(const Ti *__restrict__ in, int64_t n,
+__global__ __launch_bounds__(kScanBlock) void k_scan_final(const Ti *__restrict__ in,
+                                                           int64_t stride, int64_t n,
                                                            const To *__restrict__ part,
                                                            To *__restrict__ out)
 {
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const Ti *__restrict_
     for (int r = 0; r < kScanItems; ++r) {
         int i = r * kScanBlock + threadIdx.x;
         int64_t e = base + i;
-        tile[i] = e < n ? (To)in[e] : (To)0;
+        tile[i] = e < n ? (To)in[e * stride] : (To)0;
     }
     __syncthreads();
     To v[kScanItems];
@@ -268,7 +270,8 @@ size_t scan_ws_bytes(int64_t n)
 }
 
 template <typename Ti, typename To>
-static hipError_t scan_impl(const Ti *in, To *out, int64_t n, To *total, void *ws, hipStream_t s)
+static hipError_t scan_impl(const Ti *in, int64_t stride, To *out, int64_t n, To *total, void *ws,
+                            hipStream_t s)
 {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     To *part = (To *)ws;
@@ -276,24 +279,24 @@ static hipError_t scan_impl(const Ti *in, To *out, int64_t n, To *total, void *w
         if (total) return hipMemsetAsync(total, 0, sizeof(To), s);
         return hipSuccess;
     }
-    hipLaunchKernelGGL((k_scan_reduce<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
-                       part);
+    hipLaunchKernelGGL((k_scan_reduce<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in,
+                       stride, n, part);
     hipLaunchKernelGGL((k_scan_partials<To>), dim3(1), dim3(kScanBlock), 0, s, part, nb, total);
-    hipLaunchKernelGGL((k_scan_final<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
-                       part, out);
+    hipLaunchKernelGGL((k_scan_final<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in,
+                       stride, n, part, out);
     return hipGetLastError();
 }
 
-hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total, void *ws,
-                           hipStream_t s)
+hipError_t scan_u32_to_i64(const uint32_t *in, int64_t stride, int64_t *out, int64_t n,
+                           int64_t *total, void *ws, hipStream_t s)
 {
-    return scan_impl<uint32_t, int64_t>(in, out, n, total, ws, s);
+    return scan_impl<uint32_t, int64_t>(in, stride, out, n, total, ws, s);
 }
 
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *ws,
                     hipStream_t s)
 {
-    return scan_impl<uint32_t, uint32_t>(in, out, n, total, ws, s);
+    return scan_impl<uint32_t, uint32_t>(in, 1, out, n, total, ws, s);
 }
 
 size_t radix_ws_bytes(int64_t n)
