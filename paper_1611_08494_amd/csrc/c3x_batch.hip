@@ -345,12 +345,12 @@ __global__ void k_bapply(const BAmb *__restrict__ hl, const uint32_t *__restrict
 
 // Band matches: counted, and listed as the k-th match of their row.
 __global__ void k_badd(const uint4 *__restrict__ bin, const uint32_t *__restrict__ n_bin,
-                       uint32_t cap, RowRec *rec, WEnt *__restrict__ out)
+                       uint32_t cap, uint32_t *cnts, WEnt *__restrict__ out)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= min(*n_bin, cap)) return;
     const uint4 q = bin[t];
-    const uint32_t k = atomicAdd(&rec[q.y].cnt, 1u);
+    const uint32_t k = atomicAdd(&cnts[q.y], 1u);
     out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
@@ -474,6 +474,7 @@ struct c3x_batch {
     double2 *arad = nullptr;
     uint32_t *aidx = nullptr, *ajob = nullptr;
     ARange *arng = nullptr;
+    uint32_t *cnts = nullptr;
     RowRec *rec = nullptr;
     // lists
     uint2 *amb = nullptr, *tie = nullptr;
@@ -570,7 +571,7 @@ static MatchArgs batch_args(c3x_batch *b)
     m.jobs = b->djobs;
     m.ajob = b->ajob;
     m.nA = (int32_t)b->NA;
-    m.best_only = 0;
+    m.cnts = b->cnts;
     m.rec = b->rec;
     m.amb_n = b->ctr + 1;
     m.amb = b->amb;
@@ -667,7 +668,7 @@ static hipError_t batch_front(c3x_batch *b)
     hipLaunchKernelGGL(k_bapply, dim3(nblk(b->hl_cap, 256)), dim3(256), 0, s, b->hl, b->ctr + 9,
                        b->hl_cap, b->d_hin, b->bin, b->ctr + 8, b->bin_cap, b->ctr);
     hipLaunchKernelGGL(k_badd, dim3(nblk(b->bin_cap, 256)), dim3(256), 0, s, b->bin, b->ctr + 8,
-                       b->bin_cap, b->rec, b->xent);
+                       b->bin_cap, b->cnts, b->xent);
     // best matches the filter cannot rank: FP64 on the GPU; what FP64 cannot
     // separate is listed (c3x_batch_result ranks it in binary128)
     const uint32_t npos = b->tie_cap + b->bin_cap;
@@ -682,8 +683,7 @@ static hipError_t batch_front(c3x_batch *b)
                            b->pos, npos, b->ctr + 10, b->ctr + 3, b->unc);
     // counts -> offsets (off[NA] = P)
     if (NA > 0) {
-        e = scan_u32_to_i64(&b->rec->cnt, sizeof(RowRec) / sizeof(uint32_t), b->off, NA,
-                            b->off + NA, b->sws, s);
+        e = scan_u32_to_i64(b->cnts, 1, b->off, NA, b->off + NA, b->sws, s);
         if (e != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL(k_bfill64, dim3(1), dim3(64), 0, s, (unsigned long long *)b->off,
@@ -996,6 +996,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->aidx = M.get_n<uint32_t>(NA);
     b->ajob = M.get_n<uint32_t>(NA);
     b->arng = M.get_n<ARange>(NA);
+    b->cnts = M.get_n<uint32_t>(NA);
     b->rec = M.get_n<RowRec>(NA);
     b->amb_cap = (uint32_t)std::min<int64_t>(NA / 16 + 4096, 1 << 26);
     b->tie_cap = (uint32_t)std::min<int64_t>(NA / 16 + 4096, 1 << 26);
@@ -1029,7 +1030,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
               (b->prec != C3X_MIXED || b->p32) && b->radecB && b->packA && b->packB &&
               b->dir && b->dcnt && b->dws &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
-              b->arng && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
+              b->arng && b->cnts && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
               b->hl && b->xent && b->pos && b->unc && b->d_hin && b->d_vi && b->d_vk &&
               b->d_nv && b->ctr && b->c64 && b->off && b->sws && b->seg_list && b->seg_huge &&
               b->obest && b->obsep && b->joboff;

@@ -116,14 +116,11 @@ constexpr int kEmitPools = 64;       // overflow-list counters (spread contentio
 constexpr int kEmitPoolStride = 32;  // u32 words between two counters (128 B)
 
 // Per-A record of the count pass (idxA order), one aligned 32-byte store
-// per row (a whole sector: a row's count kept apart would be a scattered
-// 4-byte store of its own): the best match, the count and the row's first
-// kTab matches. Best-only calls keep no matches; b[0] then holds the best
-// match's sorted B position.
+// per row: the best match and the row's first kTab matches.
 struct alignas(32) RowRec {
     int32_t best;          // idxB of the best match, -1: none
-    uint32_t cnt;          // matches of the row
-    uint32_t b[kTab];      // idxB of the row's first matches (best only: b[0] = best's j)
+    uint32_t best_j;       // its sorted B position
+    uint32_t b[kTab];      // idxB of the row's first matches
     double c[kTab];        // their coded separations (see sep_code)
 };
 static_assert(sizeof(RowRec) == 32, "one 32-byte store per row");
@@ -197,8 +194,8 @@ struct MatchArgs {
     int32_t r_zero;        // radius exactly 0
     double L_rad;          // bound on |p - cell reference| (FP32 error model)
     // count pass
-    RowRec *rec;           // [nA] idxA order: count, best, first matches
-    int32_t best_only;     // no table: rec.b[0] keeps the best's sorted position
+    uint32_t *cnts;        // [nA] matches per row (idxA order)
+    RowRec *rec;           // [nA] idxA order
     uint32_t *amb_n;       // band candidates: (sorted A pos, sorted B pos)
     uint2 *amb;
     uint32_t amb_cap;

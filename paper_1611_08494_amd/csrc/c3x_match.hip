@@ -802,10 +802,11 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         }
     }
     if (active && MODE != 1) {
+        m.cnts[a.idx] = cnt;
         RowRec r;
         r.best = cnt ? (int32_t)bidx : -1;
-        r.cnt = cnt;
-        r.b[0] = MODE == 0 ? bj : tb0;
+        r.best_j = bj;
+        r.b[0] = tb0;
         r.b[1] = tb1;
         r.c[0] = tc0;
         r.c[1] = tc1;
@@ -1003,10 +1004,11 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
             }
         }
         if (lane == 0) {
+            m.cnts[a.idx] = cnt;
             RowRec r;
             r.best = cnt ? (int32_t)bidx : -1;
-            r.cnt = cnt;
-            r.b[0] = MODE == 0 ? bj : tb0;
+            r.best_j = bj;
+            r.b[0] = tb0;
             r.b[1] = tb1;
             r.c[0] = tc0;
             r.c[1] = tc1;
@@ -1175,7 +1177,7 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
                           b2.c2 - b1.c2 > 4.0 * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
         if (sure) {
             m.rec[row].best = (int32_t)b1.idxB;
-            if (m.best_only) m.rec[row].b[0] = b1.j;
+            m.rec[row].best_j = b1.j;
         } else {
             unc[atomicAdd(unc_n, 1u)] = i;
         }
@@ -1274,13 +1276,13 @@ __global__ void k_gather_pos(const uint32_t *__restrict__ pos, uint32_t n,
 
 // Band candidates found inside (sorted A position, idxA, idxB, sorted B
 // position): each is counted, and listed as the k-th match of its source.
-__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, RowRec *rec,
+__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, uint32_t *cnts,
                             WEnt *__restrict__ out)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     uint4 q = in[t];
-    uint32_t k = atomicAdd(&rec[q.y].cnt, 1u);
+    uint32_t k = atomicAdd(&cnts[q.y], 1u);
     if (out) out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
@@ -1367,20 +1369,19 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
 }
 
 __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
-                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec,
-                             int best_only)
+                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     rec[rows[t]].best = bi[t];
-    if (best_only) rec[rows[t]].b[0] = bj[t];
+    rec[rows[t]].best_j = bj[t];
 }
 
 // BEST-only output: one record per row that has a match.
-__global__ void k_nonzero(const RowRec *__restrict__ rec, int64_t n, uint32_t *__restrict__ out)
+__global__ void k_nonzero(const uint32_t *__restrict__ cnts, int64_t n, uint32_t *__restrict__ out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) out[t] = rec[t].cnt ? 1u : 0u;
+    if (t < n) out[t] = cnts[t] ? 1u : 0u;
 }
 
 // Separation (arcsec) of a coded match (see sep_code). A chord below 0.1
@@ -1520,7 +1521,7 @@ __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec
         bsep[t] = NAN;
         return;
     }
-    uint32_t bj = rec[t].b[0];
+    uint32_t bj = rec[t].best_j;
     if (bj >= (uint64_t)nB) {
         atomicOr(err, 16u);
         return;
@@ -1888,6 +1889,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     double2 *packed = tmp.get_n<double2>(nA);
     ARange *arng = tmp.get_n<ARange>(nA);
     uint32_t *aidx = tmp.get_n<uint32_t>(nA);
+    uint32_t *cnts = tmp.get_n<uint32_t>(nA);
     RowRec *rec = tmp.get_n<RowRec>(nA);
     AEll *aell = nullptr;
     AEllR *aellr = nullptr;
@@ -1897,7 +1899,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
     }
     if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !packed || !aidx ||
-        !rec || !arng)
+        !cnts || !rec || !arng)
         return fail(C3X_ENOMEM, "A buffers");
     R->nA = nA;
     R->best_idx = R->mem.get_n<int32_t>(nA);
@@ -1964,7 +1966,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_tests = c64;
     m.n_band = c64 + 1;
     m.err_flag = ctr + 4;
-    m.best_only = !all;
+    m.cnts = cnts;
     m.rec = rec;
     m.wide = wide;
     m.wide_n = ctr + 8;
@@ -2150,7 +2152,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             xent = tmp.get_n<WEnt>(n_bin);
             if (!xent) return fail(C3X_ENOMEM, "band matches");
         }
-        hipLaunchKernelGGL(k_add_pairs, dim3(nblk(n_bin, 256)), dim3(256), 0, s, bin, n_bin, rec,
+        hipLaunchKernelGGL(k_add_pairs, dim3(nblk(n_bin, 256)), dim3(256), 0, s, bin, n_bin, cnts,
                            xent);
     }
 
@@ -2173,19 +2175,16 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
 
     // ---- scan of the per-A counts (idxA order)
     int64_t *off = tmp.get_n<int64_t>(nA + 1);
-    // the counts are read in place from the records (stride 8 words)
-    const uint32_t *scan_in = &rec->cnt;
-    int64_t scan_stride = sizeof(RowRec) / sizeof(uint32_t);
+    const uint32_t *scan_in = cnts;
     if (!all) {  // one output row per A row with a match
         uint32_t *nz = tmp.get_n<uint32_t>(nA);
         if (!nz) return fail(C3X_ENOMEM, "offsets");
         if (nA > 0)
-            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, rec, nA, nz);
+            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
         scan_in = nz;
-        scan_stride = 1;
     }
     if (!off) return fail(C3X_ENOMEM, "offsets");
-    HIPCHK(scan_u32_to_i64(scan_in, scan_stride, off, nA, off + nA, ws, s), "scan");
+    HIPCHK(scan_u32_to_i64(scan_in, 1, off, nA, off + nA, ws, s), "scan");
     int64_t P = 0;
     uint32_t nc = 0;
     HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
@@ -2261,7 +2260,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             HIPCHK(hipMemcpyAsync(d2, pbi.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             HIPCHK(hipMemcpyAsync(d3, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3, np,
-                               rec, (int)!all);
+                               rec);
             HIPCHK(hipStreamSynchronize(s), "best patch");
         }
     }
