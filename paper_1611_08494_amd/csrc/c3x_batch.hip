@@ -631,7 +631,11 @@ static hipError_t batch_front(c3x_batch *b)
     if (NA > 0)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NA, 256)), dim3(256), 0, s, b->djobs, b->ejobA,
                            b->raA, b->decA, NA, false, b->ak, b->av, b->packA, b->ctr);
-    e = radix_sort_pairs(b->ak, b->av, b->ak2, b->av2, NA, b->key_bits, b->aws, s, &in_tmp);
+    // A in the order of its top key bits (its order changes no result)
+    // (a job's entries stay together: keys are job-major and the sort stable)
+    const int a_lo = std::max(0, b->key_bits - kAKeyBits);
+    e = radix_sort_pairs_bits(b->ak, b->av, b->ak2, b->av2, NA, a_lo, b->key_bits, b->aws, s,
+                              &in_tmp);
     if (e != hipSuccess) return e;
     const uint32_t *arows = in_tmp ? b->av2 : b->av;
     if (NA > 0)

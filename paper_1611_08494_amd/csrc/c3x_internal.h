@@ -354,28 +354,6 @@ __device__ __forceinline__ double sep_arcsec_rd(double ra1, double dec1, double 
     return th * (180.0 / kPi * 3600.0);
 }
 
-// ---------------------------------------------------------------------------- wavefront helpers
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-    return v;
-}
-// Orders the LDS writes of a wavefront before its later LDS reads.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // FP64 relative-accuracy recheck of the circle: the haversine carries at
 // most ~90 u of error (a few units per trigonometric call and product), far
 // inside its 2^-40 margin.

@@ -44,10 +44,7 @@ namespace c3x {
 constexpr int kMatchBlock = 256;
 constexpr uint32_t kWideMin = 32;  // candidates from which a row gets a wavefront of its own
 constexpr int64_t kFewRows = 1 << 21;  // fewer A rows: one lane each leaves the device idle
-constexpr uint32_t kTileMin = 8;     // longest row of a wavefront before its union is tried
-constexpr uint32_t kTileRatio = 4;   // union at most this many times the longest row
-constexpr int kTileZones = 6;        // zones a wavefront's union may span
-constexpr uint32_t kTileChunk = 128; // candidates staged in LDS per wavefront at a time
+constexpr int kAKeyBits = 24;          // key bits that order catalogue A
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
 constexpr int kSegLds = 2048;   // segments up to this long are sorted in LDS
@@ -490,61 +487,11 @@ __device__ __forceinline__ double rl_f64(double v, int l)
     const uint32_t lo = rl_u32((uint32_t)u, l), hi = rl_u32((uint32_t)(u >> 32), l);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-__device__ __forceinline__ Pay64 rl_pay(const Pay64 &p, int l)
-{
-    Pay64 r;
-    r.x = rl_f64(p.x, l);
-    r.y = rl_f64(p.y, l);
-    r.z = rl_f64(p.z, l);
-    r.idx = rl_u32(p.idx, l);
-    r.pad = 0;
-    return r;
-}
-__device__ __forceinline__ Pay32 rl_pay(const Pay32 &p, int l)
-{
-    Pay32 r;
-    r.x = __uint_as_float(rl_u32(__float_as_uint(p.x), l));
-    r.y = __uint_as_float(rl_u32(__float_as_uint(p.y), l));
-    r.z = __uint_as_float(rl_u32(__float_as_uint(p.z), l));
-    r.idx = rl_u32(p.idx, l);
-    return r;
-}
-
 // Lane rank among the lanes of mask hm below this one.
 __device__ __forceinline__ uint32_t lane_rank(unsigned long long hm)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-}
-
-// A lane's ranges as plain values (no indexed copy of the record).
-struct LaneRanges {
-    uint32_t j0a, j0b, j0c, na, nb, nc;
-    int zlo;
-};
-__device__ __forceinline__ LaneRanges lane_ranges(const ARange &rg, bool part)
-{
-    LaneRanges r;
-    r.j0a = rg.j0[0];
-    r.j0b = rg.j0[1];
-    r.j0c = rg.j0[2];
-    r.na = part ? rg.n[0] : 0u;
-    r.nb = part ? rg.n[1] : 0u;
-    r.nc = part ? rg.n[2] : 0u;
-    r.zlo = rg.zlo;
-    return r;
-}
-
-// A lane's sorted-B range in zone z: [lo, hi), empty (lo = hi = 0) when its
-// ranges do not reach z.
-__device__ __forceinline__ void zone_range(const LaneRanges &r, int z, uint32_t &lo, uint32_t &hi)
-{
-    static_assert(kRZ == 3, "three zones");
-    const int q = z - r.zlo;
-    const uint32_t j0 = q == 0 ? r.j0a : (q == 1 ? r.j0b : r.j0c);
-    const uint32_t n = q == 0 ? r.na : (q == 1 ? r.nb : (q == 2 ? r.nc : 0u));
-    lo = n ? j0 : 0u;
-    hi = n ? j0 + n : 0u;
 }
 
 // MODE 0: count + best; MODE 1: write every filter match into the
@@ -556,8 +503,6 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
 {
     using PayT = PayOf<PREC>;
     __shared__ unsigned long long s_tests, s_band, s_placed;
-    __shared__ PayT s_pay[kMatchBlock / 64][kTileChunk];     // dense wavefronts' chunks
-    __shared__ uint32_t s_key[kMatchBlock / 64][kTileChunk];
     if (threadIdx.x == 0) {
         s_tests = 0;
         s_band = 0;
@@ -699,65 +644,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         }
     };
 
-    // Dense wavefronts: when the rows of a wavefront share their candidates
-    // (the union of their ranges is at most kTileRatio times the longest
-    // row's), the union is staged in LDS a chunk at a time, read once and
-    // coalesced; each lane then walks its own ranges from LDS, in the same
-    // order as the lane-by-lane loop below.
-    bool tiled = false;
-    int tz0 = 0, tz1 = -1;
-    const bool part = active && rg.zlo >= 0;
-    const LaneRanges lr = lane_ranges(rg, part);
-    {
-        const uint32_t own = part ? (uint32_t)rg.n[0] + rg.n[1] + rg.n[2] : 0u;
-        const uint32_t mx = wave_max_u32(own);
-        const bool walk = __ballot(active && rg.zlo < 0) != 0;
-        if (!walk && mx >= kTileMin) {
-            tz0 = (int)wave_min_u32(part ? (uint32_t)rg.zlo : 0xffffffffu);
-            tz1 = (int)wave_max_u32(part ? (uint32_t)(rg.zlo + kRZ - 1) : 0u);
-            if (tz1 - tz0 < kTileZones) {
-                uint32_t un = 0;
-                for (int z = tz0; z <= tz1; ++z) {
-                    uint32_t lo, hi;
-                    zone_range(lr, z, lo, hi);
-                    const uint32_t ulo = wave_min_u32(hi > lo ? lo : 0xffffffffu);
-                    const uint32_t uhi = wave_max_u32(hi);
-                    if (uhi > ulo) un += uhi - ulo;
-                }
-                tiled = un <= kTileRatio * mx;
-            }
-        }
-    }
-    if (tiled) {
-        const uint32_t lane = threadIdx.x & 63u;
-        PayT *sp = s_pay[threadIdx.x >> 6];
-        uint32_t *sk = s_key[threadIdx.x >> 6];
-        for (int z = tz0; z <= tz1; ++z) {
-            uint32_t lo, hi;
-            zone_range(lr, z, lo, hi);
-            const uint32_t ulo = wave_min_u32(hi > lo ? lo : 0xffffffffu);
-            const uint32_t uhi = wave_max_u32(hi);
-            if (uhi <= ulo) continue;
-            ZoneInfo zi{};
-            double2 zr{};
-            if (!BATCH) zi = m.g.zinfo[z];
-            if (!BATCH && PREC != C3X_FP64) zr = m.g.zref[z];
-            for (uint32_t base = ulo; base < uhi; base += kTileChunk) {
-                const uint32_t nb = min(kTileChunk, uhi - base);
-                for (uint32_t t = lane; t < nb; t += 64) {
-                    sp[t] = pay[base + t];
-                    if (PREC != C3X_FP64) sk[t] = m.g.keys[base + t];
-                }
-                wave_sync();
-                const uint32_t a1 = min(hi, base + nb);
-                for (uint32_t j = max(lo, base); j < a1; ++j) {
-                    const PayT b = sp[j - base];
-                    visit(z, zi, zr, PREC == C3X_FP64 ? 0u : sk[j - base], b, j);
-                }
-                wave_sync();  // the chunk is read before the next one lands
-            }
-        }
-    } else if (active) {
+    if (active) {
         if (rg.zlo >= 0) {
             // the ranges found when A was prepared; candidates are loaded
             // kBatch at a time so that their loads overlap
@@ -1913,7 +1800,13 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                            shape, sa, sb, pa, keys, rows, packed, ctr);
     HIPCHK(hipGetLastError(), "A keys");
     int in_tmp = 0;
-    HIPCHK(radix_sort_pairs(keys, rows, ktmp, rtmp, nA, ix->plan.key_bits, ws, s, &in_tmp), "A sort");
+    // A is ordered by its top 24 key bits only (three passes): runs of up to
+    // 2^(bits - 24) cells along a zone keep a wavefront's sources together,
+    // and no result depends on the order of A
+    const int a_lo = std::max(0, ix->plan.key_bits - kAKeyBits);
+    HIPCHK(radix_sort_pairs_bits(keys, rows, ktmp, rtmp, nA, a_lo, ix->plan.key_bits, ws, s,
+                                 &in_tmp),
+           "A sort");
     uint32_t *srows = in_tmp ? rtmp : rows;
     // rows with at least wide_min candidates (or a window walked cell by
     // cell) are counted by one wavefront each; C3X_WIDE_MIN=0 turns it off

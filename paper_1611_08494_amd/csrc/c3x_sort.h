@@ -12,6 +12,11 @@ size_t radix_ws_bytes(int64_t n);
 // up in (keys, vals) if *in_tmp == 0 on return, else in (ktmp, vtmp).
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
                             int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp);
+// The same, ordering by key bits [lo_bit, nbits) only (stable: keys equal
+// in those bits keep their order).
+hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
+                                 int64_t n, int lo_bit, int nbits, void *ws, hipStream_t s,
+                                 int *in_tmp);
 
 size_t scan_ws_bytes(int64_t n);
 // Exclusive scans; *total (device, may be NULL) receives the sum. The

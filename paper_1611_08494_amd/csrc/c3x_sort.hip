@@ -309,14 +309,21 @@ size_t radix_ws_bytes(int64_t n)
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
                             int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp)
 {
+    return radix_sort_pairs_bits(keys, vals, ktmp, vtmp, n, 0, nbits, ws, s, in_tmp);
+}
+
+hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
+                                 int64_t n, int lo_bit, int nbits, void *ws, hipStream_t s,
+                                 int *in_tmp)
+{
     *in_tmp = 0;
-    if (n <= 1 || nbits <= 0) return hipSuccess;
+    if (n <= 1 || nbits <= lo_bit) return hipSuccess;
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + 256 * nb;
     void *sws = (void *)(offs + 256 * nb);
     uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
-    for (int shift = 0; shift < nbits; shift += 8) {
+    for (int shift = lo_bit; shift < nbits; shift += 8) {
         hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, n, shift,
                            hist, (int)nb);
         hipError_t e = scan_u32(hist, offs, 256 * nb, nullptr, sws, s);
