@@ -22,8 +22,10 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,6 +34,35 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM counters of the count pass on the headline workload (rocprofv3 --pmc
+# FETCH_SIZE, WRITE_SIZE), committed with the digest of the sources they were
+# taken on; reported as roofline.traffic only while those sources are unchanged.
+COUNTERS = os.path.join(ROOT, "profiles", "k_match_fullsky_10Mx10M_hbm_counters.md")
+MATCH_SOURCES = ("paper_1611_08494_amd/csrc/c3x_match.hip",
+                 "paper_1611_08494_amd/csrc/c3x_internal.h")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in MATCH_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(path_name: str):
+    """HBM bytes per launch of the count pass from the committed counter
+    summary, if it was taken on the kernel as built; else None."""
+    try:
+        with open(COUNTERS) as f:
+            text = f.read()
+    except OSError:
+        return None
+    d = re.search(r"source digest: ([0-9a-f]+)", text)
+    t = re.search(rf"traffic {path_name}: (\d+) bytes", text)
+    if d and t and d.group(1) == kernel_source_digest():
+        return int(t.group(1))
+    return None
 METRIC = "A-sources matched/s + pair tests/s, mixed vs FP64 path (exact pair set)"
 
 
@@ -186,7 +217,9 @@ def single_config(a, c3x, torch, np, name):
     achieved = alg_bytes / (hp["count"] / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_match (count + emit pass)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": committed_traffic(order[0]) if name == "cfg2" and a.scale == 1.0
+                else None,
                 "algorithmic_bytes_per_launch": int(alg_bytes),
                 "kernel_ms": round(hp["count"], 4)}
 
