@@ -136,6 +136,7 @@ typedef struct {
     double ms_total;
     int32_t precision;
     int32_t tile;
+    double ms_count_kernel;   /* the count kernel's own launch (one lane per source) */
 } c3x_stats;
 
 /* Builds the sky index over catalogue B: validates the rows, assigns each to

@@ -65,6 +65,7 @@ class Stats(ctypes.Structure):
         ("ms_count", ctypes.c_double), ("ms_scan", ctypes.c_double),
         ("ms_write", ctypes.c_double), ("ms_sort_pairs", ctypes.c_double),
         ("ms_total", ctypes.c_double), ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
+        ("ms_count_kernel", ctypes.c_double),
     ]
 
     def as_dict(self):

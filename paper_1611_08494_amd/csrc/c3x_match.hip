@@ -1923,14 +1923,15 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     uint32_t hctr[16];
     unsigned long long h64[3];
     std::vector<uint32_t> hoctr(kPoolWords);
+    Timer tk(s);  // the count kernel alone (the last attempt's launch)
     for (int attempt = 0; attempt < 2; ++attempt) {
-        if (emit) {
-            launch_match<2>(m, shape, prec, grid, s);
-            launch_wide<2>(m, shape, prec, s);
-        } else {
-            launch_match<0>(m, shape, prec, grid, s);
-            launch_wide<0>(m, shape, prec, s);
-        }
+        tk.n = 0;
+        tk.mark();
+        if (emit) launch_match<2>(m, shape, prec, grid, s);
+        else launch_match<0>(m, shape, prec, grid, s);
+        tk.mark();
+        if (emit) launch_wide<2>(m, shape, prec, s);
+        else launch_wide<0>(m, shape, prec, s);
         HIPCHK(hipGetLastError(), "count pass");
         if (nA > 0) recheck();
         HIPCHK(hipGetLastError(), "band recheck");
@@ -2252,6 +2253,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     S.cell_arcsec = ix->plan.cell_arcsec;
     S.ms_a_prep = tm.ms(0, 1);
     S.ms_count = tm.ms(1, 2);
+    S.ms_count_kernel = tk.ms(0, 1);
     S.ms_scan = tm.ms(2, 3);
     S.ms_write = tm.ms(3, 4);
     S.ms_sort_pairs = tm.ms(4, 6);
