@@ -572,6 +572,7 @@ static MatchArgs batch_args(c3x_batch *b)
     m.ajob = b->ajob;
     m.nA = (int32_t)b->NA;
     m.cnts = b->cnts;
+    m.best_only = 0;
     m.rec = b->rec;
     m.amb_n = b->ctr + 1;
     m.amb = b->amb;

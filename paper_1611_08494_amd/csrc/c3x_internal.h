@@ -101,7 +101,7 @@ struct alignas(8) OvEnt {
     uint32_t idxA, k, idxB, j;
     double code;
 };
-constexpr int kTab = 2;              // table slots per A row
+constexpr int kTab = 1;              // table slots per A row
 // Statistics counters (candidates tested, band candidates, matches placed):
 // 64 copies on separate 128-byte lines, block b adding to copy b mod 64, so
 // that one address does not take every block's atomic; the host sums them.
@@ -115,15 +115,16 @@ __device__ __forceinline__ unsigned long long *stat_slot(unsigned long long *fie
 constexpr int kEmitPools = 64;       // overflow-list counters (spread contention)
 constexpr int kEmitPoolStride = 32;  // u32 words between two counters (128 B)
 
-// Per-A record of the count pass (idxA order), one aligned 32-byte store
-// per row: the best match and the row's first kTab matches.
-struct alignas(32) RowRec {
+// Per-A record of the count pass (idxA order), one aligned 16-byte store
+// per row (the records are written scattered, in idxA order: a small record
+// keeps that cheap): the best match and the row's first match. Best-only
+// calls keep no match there; b[0] holds the best match's sorted B position.
+struct alignas(16) RowRec {
     int32_t best;          // idxB of the best match, -1: none
-    uint32_t best_j;       // its sorted B position
-    uint32_t b[kTab];      // idxB of the row's first matches
-    double c[kTab];        // their coded separations (see sep_code)
+    uint32_t b[kTab];      // idxB of the row's first match (best only: the best's j)
+    double c[kTab];        // its coded separation (see sep_code)
 };
-static_assert(sizeof(RowRec) == 32, "one 32-byte store per row");
+static_assert(sizeof(RowRec) == 16, "one 16-byte store per row");
 
 // Candidate B ranges of one sorted A source, found once when A is prepared:
 // zone zlo + q holds the sorted B positions [j0[q], j0[q] + n[q]). zlo < 0:
@@ -196,6 +197,7 @@ struct MatchArgs {
     // count pass
     uint32_t *cnts;        // [nA] matches per row (idxA order)
     RowRec *rec;           // [nA] idxA order
+    int32_t best_only;     // no table: rec.b[0] keeps the best's sorted position
     uint32_t *amb_n;       // band candidates: (sorted A pos, sorted B pos)
     uint2 *amb;
     uint32_t amb_cap;

@@ -540,9 +540,9 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     uint32_t cnt = 0;
     double b1 = INFINITY, b2 = INFINITY;
     uint32_t bidx = 0xffffffffu, bj = 0;
-    uint32_t tb0 = 0, tb1 = 0;  // MODE 2: the row's first two matches
-    double tc0 = 0.0, tc1 = 0.0;
-    static_assert(kTab == 2, "two record slots");
+    uint32_t tb0 = 0;  // MODE 2: the row's first match
+    double tc0 = 0.0;
+    static_assert(kTab == 1, "one record slot");
     int64_t o = 0, oe = 0;
     if (MODE == 1 && active) {
         o = m.off[a.idx];
@@ -615,9 +615,6 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             if (cnt == 0) {
                 tb0 = t.idxB;
                 tc0 = t.sep;
-            } else if (cnt == 1) {
-                tb1 = t.idxB;
-                tc1 = t.sep;
             } else {
                 overflow(cnt, t);
             }
@@ -692,11 +689,8 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         m.cnts[a.idx] = cnt;
         RowRec r;
         r.best = cnt ? (int32_t)bidx : -1;
-        r.best_j = bj;
-        r.b[0] = tb0;
-        r.b[1] = tb1;
+        r.b[0] = MODE == 0 ? bj : tb0;
         r.c[0] = tc0;
-        r.c[1] = tc1;
         m.rec[a.idx] = r;
         if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
         if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), Lr)) {
@@ -764,8 +758,8 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
         uint32_t cnt = 0;  // wave-uniform
         double b1 = INFINITY, b2 = INFINITY;
         uint32_t bidx = 0xffffffffu, bj = 0;
-        uint32_t tb0 = 0, tb1 = 0;
-        double tc0 = 0.0, tc1 = 0.0;
+        uint32_t tb0 = 0;
+        double tc0 = 0.0;
 
         auto range = [&](int z, uint32_t j0, uint32_t j1) {
             const ZoneInfo zi = m.g.zinfo[z];
@@ -820,22 +814,10 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                         }
                         pt.sep = sep_code(c64, j);
                     }
-                    if (cnt < (uint32_t)kTab) {
-                        // the record's slots: the first lanes of this group
-                        unsigned long long r = im;
-                        for (uint32_t q = cnt; q < (uint32_t)kTab && r; ++q) {
-                            const int l = __builtin_ffsll((long long)r) - 1;
-                            r &= r - 1;
-                            const uint32_t ib = rl_u32(pt.idxB, l);
-                            const double cd = rl_f64(pt.sep, l);
-                            if (q == 0) {
-                                tb0 = ib;
-                                tc0 = cd;
-                            } else {
-                                tb1 = ib;
-                                tc1 = cd;
-                            }
-                        }
+                    if (cnt == 0) {  // the record's slot: the group's first lane
+                        const int l = __builtin_ffsll((long long)im) - 1;
+                        tb0 = rl_u32(pt.idxB, l);
+                        tc0 = rl_f64(pt.sep, l);
                     }
                     const unsigned long long om = __ballot(d == IN && k >= (uint32_t)kTab);
                     if (om) {
@@ -894,11 +876,8 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
             m.cnts[a.idx] = cnt;
             RowRec r;
             r.best = cnt ? (int32_t)bidx : -1;
-            r.best_j = bj;
-            r.b[0] = tb0;
-            r.b[1] = tb1;
+            r.b[0] = MODE == 0 ? bj : tb0;
             r.c[0] = tc0;
-            r.c[1] = tc1;
             m.rec[a.idx] = r;
             if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
             if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), Lr)) {
@@ -1064,7 +1043,7 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
                           b2.c2 - b1.c2 > 4.0 * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
         if (sure) {
             m.rec[row].best = (int32_t)b1.idxB;
-            m.rec[row].best_j = b1.j;
+            if (m.best_only) m.rec[row].b[0] = b1.j;
         } else {
             unc[atomicAdd(unc_n, 1u)] = i;
         }
@@ -1256,12 +1235,13 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
 }
 
 __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
-                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec)
+                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec,
+                             int best_only)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     rec[rows[t]].best = bi[t];
-    rec[rows[t]].best_j = bj[t];
+    if (best_only) rec[rows[t]].b[0] = bj[t];
 }
 
 // BEST-only output: one record per row that has a match.
@@ -1359,26 +1339,19 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
     const RowRec r = rec[a];
     best_idx[a] = r.best;
     const int nt = use_rec ? (int)min<int64_t>(len, kTab) : 0;
-    static_assert(kTab == 2, "two record slots");
-    // the record's two slots are handled one by one: no indexed copy of the
-    // record (it would live in scratch)
-    PairTmp x0, x1;
+    static_assert(kTab == 1, "one record slot");
+    PairTmp x0;  // the record's slot
     x0.idxB = r.b[0];
     x0.j = 0;
     x0.sep = r.c[0];
-    x1.idxB = r.b[1];
-    x1.j = 0;
-    x1.sep = r.c[1];
     if (len > kShortSeg) {
         if (nt > 0) tmp[o] = x0;
-        if (nt > 1) tmp[o + 1] = x1;
         return;
     }
     // canonical position of a match: its rank by idxB (unique in a row)
     auto rank_of = [&](uint32_t ib) {
         int rk = 0;
         if (nt > 0) rk += x0.idxB < ib;
-        if (nt > 1) rk += x1.idxB < ib;
         for (int y = nt; y < len; ++y) rk += tmp[o + y].idxB < ib;
         return rk;
     };
@@ -1387,7 +1360,6 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
                           bsep, err);
     };
     if (nt > 0) put(x0);
-    if (nt > 1) put(x1);
     for (int q = nt; q < len; ++q) put(tmp[o + q]);
 }
 
@@ -1408,7 +1380,7 @@ __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec
         bsep[t] = NAN;
         return;
     }
-    uint32_t bj = rec[t].best_j;
+    uint32_t bj = rec[t].b[0];
     if (bj >= (uint64_t)nB) {
         atomicOr(err, 16u);
         return;
@@ -1860,6 +1832,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_band = c64 + 1;
     m.err_flag = ctr + 4;
     m.cnts = cnts;
+    m.best_only = !all;
     m.rec = rec;
     m.wide = wide;
     m.wide_n = ctr + 8;
@@ -2154,7 +2127,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             HIPCHK(hipMemcpyAsync(d2, pbi.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             HIPCHK(hipMemcpyAsync(d3, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3, np,
-                               rec);
+                               rec, (int)!all);
             HIPCHK(hipStreamSynchronize(s), "best patch");
         }
     }
