@@ -212,11 +212,11 @@ def single_config(a, c3x, torch, np, name):
     # recheck and the read-back). Algorithmic
     # bytes per launch: every A record read once (sorted coordinates 16 B,
     # row 4 B, candidate ranges 24 B) and its count and record written (4 +
-    # 32 B); every B payload read at least once (16 B mixed, 32 B FP64, plus
+    # 16 B); every B payload read at least once (16 B mixed, 32 B FP64, plus
     # the 4 B key).
     hp = head["phases_ms"]
     pay = 16 if order[0] == "mixed" else 32
-    alg_bytes = cat.nA * (16 + 4 + 24 + 4 + 32) + cat.nB * (pay + 4)
+    alg_bytes = cat.nA * (16 + 4 + 24 + 4 + 16) + cat.nB * (pay + 4)
     achieved = alg_bytes / (hp["count_kernel"] / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_match (count + emit pass)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -18,6 +18,7 @@ constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;  // 4096
 constexpr int kWaves = kSortBlock / 64;
+constexpr int64_t kRowScanTiles = 8192;  // 32M elements
 
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
@@ -86,7 +87,8 @@ __device__ __forceinline__ uint32_t block256_excl_scan(uint32_t x, uint32_t *wsu
 __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
-    const uint32_t *__restrict__ offs, const uint32_t *__restrict__ hist, int nblocks)
+    const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tot,
+    const uint32_t *__restrict__ hist, int nblocks)
 {
     constexpr int kPerWave = kSortTile / kWaves;  // 1024
     constexpr int kRounds = kPerWave / 64;        // 16
@@ -99,7 +101,11 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
     const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
     const int64_t wbase = tbase + (int64_t)wave * kPerWave + __lane_id();
     uint32_t hc = hist[(int64_t)tid * nblocks + blockIdx.x];
-    gbase[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    uint32_t gb = offs[(int64_t)tid * nblocks + blockIdx.x];
+    // offsets within each digit's row of tiles (tot: the rows' totals, whose
+    // prefix places the digits), or global offsets (tot null)
+    if (tot) gb += block256_excl_scan(tot[tid], wsum);
+    gbase[tid] = gb;
     uint32_t ts = block256_excl_scan(hc, wsum);
     tstart[tid] = ts;
 #pragma unroll
@@ -263,6 +269,27 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const Ti *__restrict_
     }
 }
 
+// Per digit (one workgroup each): the exclusive prefix of its row of tile
+// counts, and the row's total. With the digits' totals the scatter places
+// each tile's runs; three launches a pass instead of a full-table scan.
+__global__ __launch_bounds__(kScanBlock) void k_digit_rows(const uint32_t *__restrict__ hist,
+                                                           int nb, uint32_t *__restrict__ offs,
+                                                           uint32_t *__restrict__ tot)
+{
+    const uint32_t *row = hist + (int64_t)blockIdx.x * nb;
+    uint32_t *orow = offs + (int64_t)blockIdx.x * nb;
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kScanBlock) {
+        const int t = base + (int)threadIdx.x;
+        const uint32_t x = t < nb ? row[t] : 0u;
+        uint32_t chunk;
+        const uint32_t ex = block_excl_scan<uint32_t>(x, chunk);
+        if (t < nb) orow[t] = carry + ex;
+        carry += chunk;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
 size_t scan_ws_bytes(int64_t n)
 {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -303,7 +330,7 @@ size_t radix_ws_bytes(int64_t n)
 {
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     size_t hist = (size_t)256 * (size_t)(nb > 0 ? nb : 1) * sizeof(uint32_t);
-    return 2 * hist + scan_ws_bytes(256 * (nb > 0 ? nb : 1)) + 256;
+    return 2 * hist + 256 * sizeof(uint32_t) + scan_ws_bytes(256 * (nb > 0 ? nb : 1)) + 256;
 }
 
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
@@ -321,15 +348,23 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + 256 * nb;
-    void *sws = (void *)(offs + 256 * nb);
+    uint32_t *tot = offs + 256 * nb;
+    void *sws = (void *)(tot + 256);
+    // up to this many tiles, one workgroup per digit scans its row
+    const bool rows = nb <= kRowScanTiles;
     uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
     for (int shift = lo_bit; shift < nbits; shift += 8) {
         hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, n, shift,
                            hist, (int)nb);
-        hipError_t e = scan_u32(hist, offs, 256 * nb, nullptr, sws, s);
+        hipError_t e = hipSuccess;
+        if (rows)
+            hipLaunchKernelGGL(k_digit_rows, dim3(256), dim3(kScanBlock), 0, s, hist, (int)nb,
+                               offs, tot);
+        else
+            e = scan_u32(hist, offs, 256 * nb, nullptr, sws, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, va, kb,
-                           vb, n, shift, offs, hist, (int)nb);
+                           vb, n, shift, offs, rows ? tot : nullptr, hist, (int)nb);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint32_t *t = ka;
