@@ -115,6 +115,24 @@ void *dev_alloc(size_t bytes)
     return p;
 }
 
+// Pinned host staging for a call's small read-backs (counters, sizes): a
+// pinned destination lets the copy go straight to host memory. One buffer
+// per host thread, kept for the process; null if it cannot be had.
+uint8_t *pinned_stage(size_t bytes)
+{
+    thread_local uint8_t *p = nullptr;
+    thread_local size_t cap = 0;
+    if (cap < bytes) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        if (hipHostMalloc((void **)&p, bytes) == hipSuccess) cap = bytes;
+        else p = nullptr;
+        (void)hipGetLastError();
+    }
+    return p;
+}
+
 void dev_free(void *p)
 {
     if (!p) return;

@@ -22,6 +22,9 @@ void clear_error();
 // returns, so a block is never handed out while a kernel may still use it.
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+// Pinned host staging for a call's small read-backs (one buffer per host
+// thread, kept for the process); null if it cannot be had.
+uint8_t *pinned_stage(size_t bytes);
 
 // RAII owner of device blocks allocated during one call.
 // With a stream set, the destructor first waits for that stream, so blocks

@@ -365,9 +365,13 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     if (e == hipSuccess) e = scan_u32(dcnt, dir, ix->plan.dsize, nullptr, dws, s);
     tm.mark();
     uint32_t bad_h = 0xffffffffu;
+    uint32_t *hbad = (uint32_t *)pinned_stage(64);
+    if (!hbad) hbad = &bad_h;
+    *hbad = 0xffffffffu;
     if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&bad_h, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    bad_h = *hbad;
     if (e != hipSuccess) {
         (void)hipStreamSynchronize(s);
         delete ix;

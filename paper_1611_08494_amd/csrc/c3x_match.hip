@@ -1244,6 +1244,31 @@ __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *_
     if (best_only) rec[rows[t]].b[0] = bj[t];
 }
 
+// Best matches decided on the host after the outputs exist: the row's best
+// idxB, and its separation as written in the row's segment (ordered by idxB).
+__global__ void k_patch_out(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
+                            uint32_t n, const int64_t *__restrict__ off,
+                            const int32_t *__restrict__ ob, const double *__restrict__ os,
+                            int32_t *__restrict__ best_idx, double *__restrict__ best_sep,
+                            uint32_t *__restrict__ err)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t a = rows[t];
+    int64_t lo = off[a], hi = off[a + 1];
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (ob[mid] < bi[t]) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < off[a + 1] && ob[lo] == bi[t]) {
+        best_idx[a] = bi[t];
+        best_sep[a] = os[lo];
+    } else {
+        atomicOr(err, 128u);
+    }
+}
+
 // BEST-only output: one record per row that has a match.
 __global__ void k_nonzero(const uint32_t *__restrict__ cnts, int64_t n, uint32_t *__restrict__ out)
 {
@@ -1892,7 +1917,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                                m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
                                ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10);
     };
-    std::vector<uint8_t> hblk(kCtrBytes);
+    std::vector<uint8_t> hvec;
+    uint8_t *hb = pinned_stage(kCtrBytes + 64);
+    if (!hb) {
+        hvec.resize(kCtrBytes + 64);
+        hb = hvec.data();
+    }
     uint32_t hctr[16];
     unsigned long long h64[3];
     std::vector<uint32_t> hoctr(kPoolWords);
@@ -1908,12 +1938,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipGetLastError(), "count pass");
         if (nA > 0) recheck();
         HIPCHK(hipGetLastError(), "band recheck");
-        HIPCHK(hipMemcpyAsync(hblk.data(), cblk, emit ? kCtrBytes : kOctrAt,
+        HIPCHK(hipMemcpyAsync(hb, cblk, emit ? kCtrBytes : kOctrAt,
                               hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(hipStreamSynchronize(s), "count pass");
-        memcpy(hctr, hblk.data(), sizeof(hctr));
-        stat_sums((const unsigned long long *)(hblk.data() + 128), h64);
-        if (emit) memcpy(hoctr.data(), hblk.data() + kOctrAt, kPoolWords * sizeof(uint32_t));
+        memcpy(hctr, hb, sizeof(hctr));
+        stat_sums((const unsigned long long *)(hb + 128), h64);
+        if (emit) memcpy(hoctr.data(), hb + kOctrAt, kPoolWords * sizeof(uint32_t));
         if (hctr[0] != 0xffffffffu)
             return fail(C3X_EINVAL,
                         "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= 90, not "
@@ -2040,27 +2070,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         HIPCHK(hipGetLastError(), "re-ranking");
     }
 
-    // ---- scan of the per-A counts (idxA order)
-    int64_t *off = tmp.get_n<int64_t>(nA + 1);
-    const uint32_t *scan_in = cnts;
-    if (!all) {  // one output row per A row with a match
-        uint32_t *nz = tmp.get_n<uint32_t>(nA);
-        if (!nz) return fail(C3X_ENOMEM, "offsets");
-        if (nA > 0)
-            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
-        scan_in = nz;
-    }
-    if (!off) return fail(C3X_ENOMEM, "offsets");
-    HIPCHK(scan_u32_to_i64(scan_in, 1, off, nA, off + nA, ws, s), "scan");
-    int64_t P = 0;
-    uint32_t nc = 0;
-    HIPCHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
-    if (nr > 0) HIPCHK(hipMemcpyAsync(&nc, ctr + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy");
-    HIPCHK(hipStreamSynchronize(s), "scan");
-    nc = std::min(nc, nr);
+    // ---- rows FP64 could not rank (nc of them, listed in dpos): every match
+    // listed, ranked in binary128 on the host, and their best patched -- in
+    // the records before the outputs exist, or in the outputs afterwards
+    int64_t *off = nullptr;
+    auto resolve_unranked = [&](uint32_t nc, bool after_outputs) -> c3x_status {
 
-    // ---- rows FP64 could not rank: every match listed, ranked in binary128
-    if (nc > 0) {
         uint32_t col_cap = 8 * nc + 64;
         std::vector<ColEnt> col;
         for (int attempt = 0; attempt < 2; ++attempt) {
@@ -2126,9 +2141,51 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             HIPCHK(hipMemcpyAsync(d1, prow.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             HIPCHK(hipMemcpyAsync(d2, pbi.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             HIPCHK(hipMemcpyAsync(d3, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
-            hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3, np,
-                               rec, (int)!all);
+            if (after_outputs)
+                hipLaunchKernelGGL(k_patch_out, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, np,
+                                   off, R->idxB, R->sep, R->best_idx, R->best_sep, ctr + 4);
+            else
+                hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3,
+                                   np, rec, (int)!all);
             HIPCHK(hipStreamSynchronize(s), "best patch");
+        }
+        return C3X_OK;
+    };
+
+    // ---- scan of the per-A counts (idxA order). In all-matches mode with
+    // every filter match emitted, the total is known from the count pass
+    // (first matches in the records, the overflow list, the band matches)
+    // and the outputs go ahead without waiting for the scan.
+    off = tmp.get_n<int64_t>(nA + 1);
+    const uint32_t *scan_in = cnts;
+    if (!all) {  // one output row per A row with a match
+        uint32_t *nz = tmp.get_n<uint32_t>(nA);
+        if (!nz) return fail(C3X_ENOMEM, "offsets");
+        if (nA > 0)
+            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
+        scan_in = nz;
+    }
+    if (!off) return fail(C3X_ENOMEM, "offsets");
+    HIPCHK(scan_u32_to_i64(scan_in, 1, off, nA, off + nA, ws, s), "scan");
+    const bool early = all && emitted;
+    int64_t P = 0;
+    int64_t *hP = (int64_t *)(hb + kCtrBytes);
+    if (early) {
+        uint64_t ov_total = 0;
+        for (int q = 0; q < kEmitPools; ++q) ov_total += hoctr[q * kEmitPoolStride];
+        P = (int64_t)(h64[2] + ov_total + n_bin);
+    } else {
+        uint32_t *hnc = (uint32_t *)(hb + kCtrBytes + 8);
+        *hnc = 0;
+        HIPCHK(hipMemcpyAsync(hP, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+        if (nr > 0)
+            HIPCHK(hipMemcpyAsync(hnc, ctr + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(hipStreamSynchronize(s), "scan");
+        P = *hP;
+        const uint32_t nc = std::min(*hnc, nr);
+        if (nc > 0) {
+            c3x_status st = resolve_unranked(nc, false);
+            if (st != C3X_OK) return st;
         }
     }
 
@@ -2201,10 +2258,14 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                            R->sep, ctr + 4);
     HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6
-    HIPCHK(hipMemcpyAsync(hblk.data(), cblk, kOctrAt, hipMemcpyDeviceToHost, s), "copy");
+    HIPCHK(hipMemcpyAsync(hb, cblk, kOctrAt, hipMemcpyDeviceToHost, s), "copy");
+    if (early) HIPCHK(hipMemcpyAsync(hP, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     HIPCHK(hipStreamSynchronize(s), "c3x_match");
-    memcpy(hctr, hblk.data(), sizeof(hctr));
-    stat_sums((const unsigned long long *)(hblk.data() + 128), h64);
+    memcpy(hctr, hb, sizeof(hctr));
+    stat_sums((const unsigned long long *)(hb + 128), h64);
+    if (early && *hP != P)
+        return fail(C3X_EDEVICE, "internal: %lld matches counted, %lld expected", (long long)*hP,
+                    (long long)P);
     if (all) {
         c3x_status st = finish_huge(fa, hctr + 6, s);
         if (st != C3X_OK) return st;
@@ -2218,6 +2279,17 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                              hctr[4]);
     if (all && h64[2] != (unsigned long long)P)
         return fail(C3X_EDEVICE, "internal: %llu of %lld matches placed", h64[2], (long long)P);
+    if (early) {  // rows FP64 could not rank, now that the outputs exist
+        const uint32_t nc = std::min(hctr[3], nr);
+        if (nc > 0) {
+            c3x_status st = resolve_unranked(nc, true);
+            if (st != C3X_OK) return st;
+            HIPCHK(hipMemcpyAsync(hctr + 4, ctr + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                   "copy");
+            HIPCHK(hipStreamSynchronize(s), "c3x_match");
+            if (hctr[4]) return fail(C3X_EDEVICE, "internal: best patch (flags %u)", hctr[4]);
+        }
+    }
     c3x_stats &S = R->stats;
     S.n_a = nA;
     S.n_b = ix->nB;
