@@ -355,7 +355,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}): the cross-match is "
-              "measured at N=1; sharding across GPUs is described in DESIGN.md, not run.",
+              "measured at N=1; splitting the sky across GPUs is a design, not run here.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

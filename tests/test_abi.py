@@ -176,3 +176,15 @@ def test_binary128_best_against_200bit(L):
             if int(ib[k]) != want:
                 bad.append((ra1, dec1, pts, int(ib[k]), want))
     assert not bad, bad[:3]
+
+
+def test_bench_reports_traffic_only_for_the_measured_kernel(monkeypatch):
+    """roofline.traffic comes from the committed counter summary only while
+    the count kernel's sources are the ones it was measured on."""
+    import bench
+    got = bench.committed_traffic("mixed")
+    if got is not None:  # the summary matches the sources as committed
+        assert got > 0
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 16)
+    assert bench.committed_traffic("mixed") is None
+    assert bench.committed_traffic("fp64") is None

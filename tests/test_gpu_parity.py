@@ -343,3 +343,26 @@ def test_wavefront_rows(c3x, dev, cfg2_small, cfg2_small_oracle, cfg3_small, pre
     ra, da = synth.cap_uniform(r, 8_000, 300.0, 45.0, 0.11)
     cat = synth.Catalogues("dense_wave", ra, da, rb, db, radius_arcsec=4.0)
     assert_parity(gpu_match(c3x, dev, cat, precision), oracle_match(cat))
+
+
+def test_result_views_outlive_the_result_object(c3x, dev, cfg2_small):
+    """The output tensors view the library's own arrays: they stay valid
+    after the result object is gone and while other calls run, and the
+    arrays go back to the library when the last tensor goes."""
+    import gc
+    import torch
+    print("[gpu] result views lifetime", flush=True)
+    t = [_t(x, dev) for x in (cfg2_small.raA, cfg2_small.decA, cfg2_small.raB, cfg2_small.decB)]
+    ix = c3x.build_index(t[2], t[3], reach_hint_arcsec=cfg2_small.radius_arcsec)
+    r = c3x.match(ix, t[0], t[1], radius_arcsec=cfg2_small.radius_arcsec)
+    ia, sep = r.idxA, r.sep
+    want_ia, want_sep = ia.cpu().numpy().copy(), sep.cpu().numpy().copy()
+    del r
+    gc.collect()
+    for _ in range(3):  # later calls must not reuse the viewed arrays
+        r2 = c3x.match(ix, t[0], t[1], radius_arcsec=2 * cfg2_small.radius_arcsec)
+        del r2
+    torch.cuda.synchronize()
+    assert np.array_equal(ia.cpu().numpy(), want_ia)
+    assert np.array_equal(sep.cpu().numpy(), want_sep)
+    ix.free()
