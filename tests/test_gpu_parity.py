@@ -347,8 +347,7 @@ def test_wavefront_rows(c3x, dev, cfg2_small, cfg2_small_oracle, cfg3_small, pre
 
 def test_result_views_outlive_the_result_object(c3x, dev, cfg2_small):
     """The output tensors view the library's own arrays: they stay valid
-    after the result object is gone and while other calls run, and the
-    arrays go back to the library when the last tensor goes."""
+    after the result object is gone and while other calls run."""
     import gc
     import torch
     print("[gpu] result views lifetime", flush=True)
