@@ -211,12 +211,13 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
         int zz = zone_of(d, g);
         uint32_t c = cell_of(zz, a, g);
         double rx, ry, rz;
-        ref_vec(g.zref[zz], ref_step(g.zinfo[zz], c), rx, ry, rz);
+        const uint32_t st = ref_step(g.zinfo[zz], c);
+        ref_vec(g.zref[zz], st, rx, ry, rz);
         Pay32 q;
         q.x = (float)(x - rx);
         q.y = (float)(y - ry);
         q.z = (float)(z - rz);
-        q.idx = row;
+        q.idx = row | ((st & 1u) << 31);  // the step's parity: a window spans at most two
         p32[s] = q;
     }
 }

@@ -59,8 +59,10 @@ struct alignas(32) Pay64 {
 };
 struct alignas(16) Pay32 {
     float x, y, z;
-    uint32_t idx;
+    uint32_t idx;          // B row | (low bit of the reference's RA step) << 31
 };
+__device__ __forceinline__ uint32_t pay_row(const Pay32 &b) { return b.idx & 0x7fffffffu; }
+__device__ __forceinline__ uint32_t pay_row(const Pay64 &b) { return b.idx; }
 
 // One A source as a match lane sees it: position, unit vector (z = sin Dec),
 // cos Dec with small relative error near the poles, reach of its area.
@@ -134,7 +136,9 @@ constexpr int kRZ = 3;
 struct alignas(8) ARange {
     uint32_t j0[kRZ];
     uint16_t n[kRZ];
-    uint16_t wide;         // 1: counted by a wavefront of its own
+    uint16_t wide;         // bit 0: counted by a wavefront of its own; bits 2q+2, 2q+3:
+                           // zone q's cells span two FP32 reference steps, and the
+                           // other one is below the source's own (see a_ranges)
     int32_t zlo;
 };
 static_assert(sizeof(ARange) == 24, "24-byte range record");
@@ -142,7 +146,7 @@ static_assert(sizeof(ARange) == 24, "24-byte range record");
 // A row counted by a wavefront of its own (marked when A is prepared).
 __device__ __forceinline__ bool wide_row(const ARange &r)
 {
-    return r.wide != 0;
+    return (r.wide & 1u) != 0;
 }
 
 // One job of a batch (device job table). Its A and B rows are taken into a

@@ -45,6 +45,7 @@ constexpr int kMatchBlock = 256;
 constexpr uint32_t kWideMin = 32;  // candidates from which a row gets a wavefront of its own
 constexpr int64_t kFewRows = 1 << 21;  // fewer A rows: one lane each leaves the device idle
 constexpr int kAKeyBits = 24;          // key bits that order catalogue A
+constexpr uint32_t kNoKey = 0xffffffffu;  // no cell key: the lane's FP32 offsets are set
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
 constexpr int kSegLds = 2048;   // segments up to this long are sorted in LDS
@@ -110,11 +111,17 @@ __device__ __forceinline__ double ell_margin(double ar, double br, double kappa,
 // window the match kernels would walk (same functions, same inputs), its
 // cell ranges turned into sorted B positions now, with every zone's
 // directory lookups independent of the others.
-__device__ __forceinline__ ARange a_ranges(const Grid &g, double ra, double dec, double reach_deg)
+// Also flags, per zone, how its cells lie on the FP32 reference steps: a
+// window inside one step, or across two (the source's own step and the one
+// above or below it), is told apart by the parity each B payload carries;
+// multi is set when a window crosses more than two steps.
+__device__ __forceinline__ ARange a_ranges(const Grid &g, double ra, double dec, double reach_deg,
+                                           bool &multi)
 {
     ARange rg;
     rg.zlo = -1;
     rg.wide = 0;
+    multi = false;
     double x, y, z;
     unit_vec(ra, dec, x, y, z);
     const double cosd = sqrt(x * x + y * y) * (1.0 - 1e-12) - 1e-15;
@@ -132,6 +139,10 @@ __device__ __forceinline__ ARange a_ranges(const Grid &g, double ra, double dec,
             ok = nr == 1;
             k0[q] = zi.base + c0[0];
             k1[q] = zi.base + c1[0] + 1;
+            const uint32_t s0 = ref_step(zi, c0[0]), s1 = ref_step(zi, c1[0]);
+            const uint32_t sa = ref_step(zi, cell_in(zi, ra));
+            if (s1 > s0 + 1u) multi = true;
+            if (s1 != s0) rg.wide |= (uint16_t)((sa == s1 ? 3u : 1u) << (2 * q + 2));
         }
     }
 #pragma unroll
@@ -188,7 +199,9 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
     }
     arad[i] = make_double2(r, d);
     aidx[i] = row;
-    ARange rg = a_ranges(g, r, d, SHAPE == C3X_ELLIPSE ? A / 3600.0 : reach_deg);
+    bool multi;
+    ARange rg = a_ranges(g, r, d, SHAPE == C3X_ELLIPSE ? A / 3600.0 : reach_deg, multi);
+    if (multi) rg.wide |= 2u;  // the mixed filter reads this row's cell keys
     if (wide_min) {
         // rows for the wavefront-per-source kernel: a window walked cell by
         // cell, 16 wide_min candidates or more, or wide_min or more and either
@@ -204,7 +217,7 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
         }
         const bool wd = rg.zlo < 0 || nc >= 16 * wide_min ||
                         (nc >= wide_min && (few || (uint64_t)nc * cnt >= 4ull * sum));
-        rg.wide = wd ? 1 : 0;
+        rg.wide = (uint16_t)((rg.wide & ~1u) | (wd ? 1u : 0u));
         const unsigned long long wm = __ballot(wd);
         if (wm) {
             const int l0 = __builtin_ffsll((long long)wm) - 1;
@@ -557,7 +570,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     // FP64 unit vectors).
     auto coded = [&](const PayT &b, uint32_t j, double c2) -> PairTmp {
         PairTmp t;
-        t.idxB = b.idx;
+        t.idxB = pay_row(b);
         t.j = j;
         double c64 = c2;
         if constexpr (PREC != C3X_FP64) {
@@ -621,10 +634,10 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         }
         if (MODE != 1) {
             ++cnt;
-            if (c2 < b1 || (c2 == b1 && b.idx < bidx)) {
+            if (c2 < b1 || (c2 == b1 && pay_row(b) < bidx)) {
                 b2 = b1;
                 b1 = c2;
-                bidx = b.idx;
+                bidx = pay_row(b);
                 bj = j;
             } else if (c2 < b2) {
                 b2 = c2;
@@ -656,6 +669,34 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                 double2 zr{};
                 if (!BATCH) zi = m.g.zinfo[z];
                 if (!BATCH && PREC != C3X_FP64) zr = m.g.zref[z];
+                // mixed: the zone's cells lie on one or two FP32 reference
+                // steps (the source's own, and the one above or below it);
+                // the lane's offsets from both are formed once here, and
+                // each candidate's parity bit picks one -- no cell keys
+                const bool par = PREC != C3X_FP64 && !BATCH && !(rg.wide & 2u);
+                float oax = 0.f, oay = 0.f, oaz = 0.f, oox = 0.f, ooy = 0.f, ooz = 0.f;
+                uint32_t pa = 0;
+                if (par) {
+                    const uint32_t sa = ref_step(zi, cell_in(zi, a.ra));
+                    const uint32_t bits = (rg.wide >> (2 * q + 2)) & 3u;
+                    const uint32_t so = bits == 1u ? sa + 1u : (bits == 3u ? sa - 1u : sa);
+                    double rx, ry, rz;
+                    ref_vec(zr, sa, rx, ry, rz);
+                    oax = (float)(a.x - rx);
+                    oay = (float)(a.y - ry);
+                    oaz = (float)(a.z - rz);
+                    oox = oax;
+                    ooy = oay;
+                    ooz = oaz;
+                    if (so != sa) {
+                        ref_vec(zr, so, rx, ry, rz);
+                        oox = (float)(a.x - rx);
+                        ooy = (float)(a.y - ry);
+                        ooz = (float)(a.z - rz);
+                    }
+                    pa = sa & 1u;
+                    cc.key = kNoKey;
+                }
                 for (uint32_t t = 0; t < nq; t += kBatch) {
                     PayT bb[kBatch];
                     uint32_t kk[kBatch];
@@ -663,11 +704,19 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
                     for (int u = 0; u < kBatch; ++u) {
                         const uint32_t jj = j0 + min(t + u, nq - 1);
                         bb[u] = pay[jj];
-                        kk[u] = m.g.keys[jj];
+                        kk[u] = (PREC == C3X_FP64 || BATCH || par) ? kNoKey : m.g.keys[jj];
                     }
 #pragma unroll
                     for (int u = 0; u < kBatch; ++u)
-                        if (t + u < nq) visit(z, zi, zr, kk[u], bb[u], j0 + t + u);
+                        if (t + u < nq) {
+                            if (par) {
+                                const bool other = (bb[u].idx >> 31) != pa;
+                                cc.ax = other ? oox : oax;
+                                cc.ay = other ? ooy : oay;
+                                cc.az = other ? ooz : oaz;
+                            }
+                            visit(z, zi, zr, kk[u], bb[u], j0 + t + u);
+                        }
                 }
             }
         } else if constexpr (BATCH) {
@@ -791,10 +840,10 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                 const unsigned long long im = __ballot(d == IN);
                 if (!im) continue;
                 if (d == IN) {
-                    if (c2 < b1 || (c2 == b1 && b.idx < bidx)) {
+                    if (c2 < b1 || (c2 == b1 && pay_row(b) < bidx)) {
                         b2 = b1;
                         b1 = c2;
-                        bidx = b.idx;
+                        bidx = pay_row(b);
                         bj = j;
                     } else if (c2 < b2) {
                         b2 = c2;
@@ -804,7 +853,7 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                     const uint32_t k = cnt + lane_rank(im);
                     PairTmp pt{};
                     if (d == IN) {
-                        pt.idxB = b.idx;
+                        pt.idxB = pay_row(b);
                         pt.j = j;
                         double c64 = c2;
                         if constexpr (PREC != C3X_FP64) {
@@ -941,7 +990,7 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
                 double2 rb = m.radecB[j];
                 ColEnt ce;
                 ce.t = t;
-                ce.idxB = b.idx;
+                ce.idxB = pay_row(b);
                 ce.j = j;
                 ce.pad = 0;
                 ce.ra = rb.x;
@@ -1099,7 +1148,7 @@ __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__rest
     if (SHAPE == C3X_CIRCLE) d = recheck_circle(a, rb, h_r);
     else d = recheck_ellipse(a, aellr[q.x], rb);
     if (d == OUT) return;
-    const uint32_t idxB = p64 ? p64[q.y].idx : p32[q.y].idx;
+    const uint32_t idxB = p64 ? p64[q.y].idx : pay_row(p32[q.y]);
     if (d == IN) {
         in[atomicAdd(n_in, 1u)] = make_uint4(q.x, row, idxB, q.y);  // at most one per band entry
         return;
