@@ -63,14 +63,16 @@ __device__ __forceinline__ int64_t entry_row(const BJob &jb, uint32_t e, bool is
 }
 
 // (ra', dec') in degrees of unit vector p in job jb's local frame.
-__device__ __forceinline__ void local_radec(const BJob &jb, double x, double y, double z,
-                                            double &lra, double &ldec)
+// Tangent-plane coordinates of unit vector p in job jb's frame.
+__device__ __forceinline__ void local_plane(const BJob &jb, double x, double y, double z,
+                                            double &px, double &py)
 {
     const double u = x * jb.cx + y * jb.cy + z * jb.cz;
     const double v = x * jb.ex + y * jb.ey + z * jb.ez;
     const double w = x * jb.nx + y * jb.ny + z * jb.nz;
-    lra = atan2(v, u) * (180.0 / kPi);
-    ldec = atan2(w, sqrt(u * u + v * v)) * (180.0 / kPi);
+    const double iu = 1.0 / u;
+    px = v * iu;
+    py = w * iu;
 }
 
 __device__ __forceinline__ uint32_t clampu(double t, uint32_t n)
@@ -178,10 +180,10 @@ __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restric
         d = 0.0;
     }
     packed[e] = make_double2(a, d);  // one 16-byte record per entry for the gathers
-    double x, y, z, lra, ldec;
+    double x, y, z, px, py;
     unit_vec(a, d, x, y, z);
-    local_radec(jb, x, y, z, lra, ldec);
-    const double tr = (ldec + jb.Dr) * jb.inv_h, tc = (lra + jb.Dc) * jb.inv_h;
+    local_plane(jb, x, y, z, px, py);
+    const double tr = (py + jb.T) * jb.inv_h, tc = (px + jb.T) * jb.inv_h;
     if (!(tr >= 0.0 && tr < (double)jb.nrow && tc >= 0.0 && tc < (double)jb.ncol))
         atomicOr(flags, kBFlagStale);
     const uint32_t r = clampu(tr, jb.nrow), c = clampu(tc, jb.ncol);
@@ -246,21 +248,19 @@ __global__ void k_bgather_a(const uint32_t *__restrict__ rows, const BJob *__res
     arad[s] = ad;
     aidx[s] = e;
     ajob[s] = j;
-    double x, y, z, lra, ldec;
+    double x, y, z, px, py;
     unit_vec(a, d, x, y, z);
-    local_radec(jb, x, y, z, lra, ldec);
-    const double rp = jb.reach_deg * (1.0 + 1e-9) + 1e-12;
-    const uint32_t r0 = clampu((ldec - rp + jb.Dr) * jb.inv_h, jb.nrow);
-    const uint32_t r1 = clampu((ldec + rp + jb.Dr) * jb.inv_h, jb.nrow);
-    const double cl = cos((fabs(ldec) + rp) * (kPi / 180.0)) * (1.0 - 1e-12) - 1e-15;
-    const double yq = (kDeg * rp) / cl;
-    const double dra = yq / sqrt(1.0 - yq * yq) / kDeg * (1.0 + 1e-9) + 1e-12;
-    const uint32_t c0 = clampu((lra - dra + jb.Dc) * jb.inv_h, jb.ncol);
-    const uint32_t c1 = clampu((lra + dra + jb.Dc) * jb.inv_h, jb.ncol);
+    local_plane(jb, x, y, z, px, py);
+    // B within the radius of A lies within wd of it on the plane along each
+    // axis (wd bounds the projection's stretch over the job's cap, with pads)
+    const uint32_t r0 = clampu((py - jb.wd + jb.T) * jb.inv_h, jb.nrow);
+    const uint32_t r1 = clampu((py + jb.wd + jb.T) * jb.inv_h, jb.nrow);
+    const uint32_t c0 = clampu((px - jb.wd + jb.T) * jb.inv_h, jb.ncol);
+    const uint32_t c1 = clampu((px + jb.wd + jb.T) * jb.inv_h, jb.ncol);
     ARange rg;
     rg.wide = 0;
     rg.zlo = (int32_t)r0;
-    bool ok = r1 - r0 < (uint32_t)kRZ && cl > 0.0 && yq < 0.9;
+    bool ok = r1 - r0 < (uint32_t)kRZ;
 #pragma unroll
     for (int q = 0; q < kRZ; ++q) {
         uint32_t j0 = 0, j1 = 0;
@@ -741,32 +741,30 @@ static hipError_t batch_back(c3x_batch *b)
     return hipGetLastError();
 }
 
-// Grids of every job for cell scale kappa: the cell side is kappa times the
-// mean spacing of the job's B sources, at least the radius (so a window
-// spans at most three rows) and at least 1e-4 arcsec; all cells must fit
-// 32-bit keys.
+// Grids of every job for cell scale kappa (tangent-plane units): the cell
+// side is kappa times the mean spacing of the job's B sources, at least the
+// window half-width (so a window spans at most three rows) and at least
+// 1e-4 arcsec; all cells must fit 32-bit keys.
 static c3x_status batch_grids(c3x_batch *b, double kappa)
 {
     uint64_t base = 0;
     for (int j = 0; j < b->nj; ++j) {
         BJob &jb = b->hjobs[j];
-        const double D = jb.Dr;  // extent + radius + pad (deg), set by the plan
-        const double area = 4.0 * D * D;
+        const double T = jb.T;  // box half-side, set by the plan
+        const double area = 4.0 * T * T;
         const double spacing = sqrt(area / (double)std::max<uint32_t>(jb.nB, 1u));
-        double h = std::max(kappa * spacing, jb.reach_deg * (1.0 + 1e-6) + 1e-12);
-        h = std::max(h, 1e-4 / 3600.0);
-        const double Dc = D / cos(D * kDeg);
-        double nr = ceil(2.0 * D / h), nc = ceil(2.0 * Dc / h);
+        double h = std::max(kappa * spacing, jb.wd * (1.0 + 1e-6) + 1e-12);
+        h = std::max(h, 1e-4 / 3600.0 * kDeg);
+        double nr = ceil(2.0 * T / h), nc = nr;
         // keep each job's grid modest: at most ~4 cells per B source + 1024
         const double lim = 4.0 * (double)jb.nB + 1024.0;
-        while (nr * nc > lim && h < D) {
+        while (nr * nc > lim && h < T) {
             h *= 1.25;
-            nr = ceil(2.0 * D / h);
-            nc = ceil(2.0 * Dc / h);
+            nr = ceil(2.0 * T / h);
+            nc = nr;
         }
         jb.h = h;
         jb.inv_h = 1.0 / h;
-        jb.Dc = Dc;
         jb.nrow = (uint32_t)std::max(1.0, nr);
         jb.ncol = (uint32_t)std::max(1.0, nc);
         jb.key_base = (uint32_t)std::min<uint64_t>(base, 0xffffffffull);
@@ -964,7 +962,14 @@ static c3x_status batch_plan_impl(c3x_batch *b)
                         j, D, kMaxJobExtentDeg);
         jb.reach_deg = r / 3600.0;
         jb.r_arcsec = r;
-        jb.Dr = D * (1.0 + 1e-6) + jb.reach_deg * 2.0 + 1e-9;
+        // on the tangent plane: the box holds every source (angle <= D) with a
+        // margin of two radii; the window half-width is the radius times the
+        // largest stretch of the projection within angle D + radius
+        // (sec^2), padded for rounding
+        const double Dmax = (D * (1.0 + 1e-6) + jb.reach_deg * 2.0 + 1e-9) * kDeg;
+        jb.T = tan(Dmax);
+        const double cmax = cos(Dmax);
+        jb.wd = jb.reach_deg * kDeg / (cmax * cmax) * (1.0 + 1e-9) + 1e-12;
         CircleThresholds t;
         jb.L = 2.0 * sin(0.5 * (D + 1e-6) * kDeg) + 1e-12;
         t = circle_thresholds(r, jb.L);

@@ -149,11 +149,11 @@ __device__ __forceinline__ bool wide_row(const ARange &r)
     return (r.wide & 1u) != 0;
 }
 
-// One job of a batch (device job table). Its A and B rows are taken into a
-// local frame whose first axis is the job's mean direction (c, e, n: centre,
-// east, north), where the job's data lie within a few degrees of (0, 0);
-// there a plain (dec', ra') grid of square cells of side h covers the box
-// [-Dr, Dr) x [-Dc, Dc) without poles or RA wrap. Cell (row, col) has key
+// One job of a batch (device job table). Its A and B rows are projected on
+// the plane tangent to the job's mean direction c (gnomonic: p -> (p.e / p.c,
+// p.n / p.c), e and n the east and north axes at c), where the job's data lie
+// within tan(10 deg) of the origin, without poles or RA wrap; a grid of
+// square cells of side h covers the box [-T, T)^2. Cell (row, col) has key
 // key_base + row * ncol + col in one key space shared by all jobs.
 struct alignas(16) BJob {
     int64_t a_off, b_off;          // caller rows of the job
@@ -161,7 +161,8 @@ struct alignas(16) BJob {
     uint32_t nA, nB;
     uint32_t key_base, ncol, nrow, pad0;
     double cx, cy, cz, ex, ey, ez, nx, ny, nz;
-    double Dr, Dc, h, inv_h;       // grid box and cell side (degrees)
+    double T, wd, h, inv_h;        // box half-side, window half-width, cell side
+                                   // (tangent-plane units)
     double reach_deg, h_r, cr2, L; // radius, sin^2(r/2), 4 sin^2(r/2), max |p - c|
     double r_arcsec;               // the radius as given
     double t64_in, t64_out;
