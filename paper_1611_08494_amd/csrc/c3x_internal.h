@@ -203,6 +203,9 @@ struct MatchArgs {
     uint32_t *cnts;        // [nA] matches per row (idxA order)
     RowRec *rec;           // [nA] idxA order
     int32_t best_only;     // no table: rec.b[0] keeps the best's sorted position
+    int32_t cnts_zeroed;   // cnts cleared beforehand: rows without a filter
+                           // match store neither count nor record (every
+                           // reader of a record checks the row's count first)
     uint32_t *amb_n;       // band candidates: (sorted A pos, sorted B pos)
     uint2 *amb;
     uint32_t amb_cap;

@@ -734,7 +734,10 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             });
         }
     }
-    if (active && MODE != 1) {
+    // a row's count and record are scattered stores (idxA order), the
+    // costliest of the pass: rows without a match skip them when the counts
+    // start at zero
+    if (active && MODE != 1 && (cnt || !m.cnts_zeroed)) {
         m.cnts[a.idx] = cnt;
         RowRec r;
         r.best = cnt ? (int32_t)bidx : -1;
@@ -1906,6 +1909,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_band = c64 + 1;
     m.err_flag = ctr + 4;
     m.cnts = cnts;
+    m.cnts_zeroed = 1;
     m.best_only = !all;
     m.rec = rec;
     m.wide = wide;
@@ -1975,6 +1979,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     uint32_t hctr[16];
     unsigned long long h64[3];
     std::vector<uint32_t> hoctr(kPoolWords);
+    if (nA > 0) HIPCHK(hipMemsetAsync(cnts, 0, (size_t)nA * sizeof(uint32_t), s), "memset");
     Timer tk(s);  // the count kernel alone (the last attempt's launch)
     for (int attempt = 0; attempt < 2; ++attempt) {
         tk.n = 0;
