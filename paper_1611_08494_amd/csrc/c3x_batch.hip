@@ -572,6 +572,7 @@ static MatchArgs batch_args(c3x_batch *b)
     m.ajob = b->ajob;
     m.nA = (int32_t)b->NA;
     m.cnts = b->cnts;
+    m.cnts_zeroed = 1;  // cleared by a fill kernel before the count pass
     m.best_only = 0;
     m.rec = b->rec;
     m.amb_n = b->ctr + 1;
@@ -646,6 +647,7 @@ static hipError_t batch_front(c3x_batch *b)
     MatchArgs m = batch_args(b);
     const unsigned grid = nblk(NA, kMatchBlock);
     if (grid) {
+        hipLaunchKernelGGL(k_bfill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->cnts, NA, 0u);
         if (b->prec == C3X_FP64)
             hipLaunchKernelGGL((k_match<C3X_CIRCLE, C3X_FP64, 2, true>), dim3(grid),
                                dim3(kMatchBlock), 0, s, m);
