@@ -1,14 +1,21 @@
 // c3x_sort.hip -- LSD radix sort of (u32 key, u32 value) pairs and prefix
 // scans, written for 64-wide CDNA wavefronts.
 //
-// Sort: 8-bit digits, only as many passes as the key range needs. Each pass
-// is a digit histogram per 4096-element tile (LDS atomics), a scan of the
-// digit-major histogram table, and a stable scatter: each wavefront ranks
-// its quarter of the tile with ballots (eight ballots match the lanes that
-// share a digit; mbcnt gives the rank among them) against its own digit
-// counters, one prefix over the wavefronts orders the quarters, and the
-// whole tile is staged in LDS in digit order so that the global writes of a
-// digit run are contiguous (about 16 elements per run).
+// Sort: 8-bit digits, only as many passes as the key range needs. One
+// kernel first counts every pass's digits over the whole input (the keys are
+// read once for all passes). Each pass is then one launch over 4096-element
+// tiles taken in order from a counter: a tile ranks its elements (each
+// wavefront ranks its quarter with ballots -- eight ballots match the lanes
+// that share a digit, mbcnt ranks them -- against its own digit counters),
+// publishes its digit counts, and finds how many elements of each digit the
+// earlier tiles hold by looking back over their published counts (a chained
+// scan with decoupled look-back); the tile is staged in LDS in digit order
+// so that the global writes of a digit run are contiguous. Inputs of up to
+// 32M elements (and of 2^30 or more) instead count each pass's digits per
+// tile into a table, scan it, and scatter: there the table is small enough
+// to scan with one workgroup per digit, which costs less than the look-back.
+#include <algorithm>
+
 #include "c3x_internal.h"
 #include "c3x_sort.h"
 
@@ -47,10 +54,21 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_hist(const uint32_t *__res
         int64_t e = base + r * kSortBlock + threadIdx.x;
         kk[r] = e < n ? keys[e] : 0xffffffffu;
     }
+    // a wavefront whose valid lanes share the digit adds them with one atomic
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        int64_t e = base + r * kSortBlock + threadIdx.x;
-        if (e < n) atomicAdd(&h[(kk[r] >> shift) & 255u], 1u);
+        const int64_t e = base + r * kSortBlock + threadIdx.x;
+        const bool valid = e < n;
+        const uint64_t vm = __ballot(valid);
+        if (vm == 0) continue;
+        const int lead = __builtin_ffsll((long long)vm) - 1;
+        const uint32_t d = (kk[r] >> shift) & 255u;
+        const uint32_t d0 = (uint32_t)__shfl((int)d, lead);
+        if (__ballot(valid && d != d0) == 0) {
+            if ((int)__lane_id() == lead) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[d], 1u);
+        }
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
@@ -170,6 +188,190 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
             vout[dst] = sv[p];
         }
     }
+}
+
+// Every pass's digit counts over the whole input, accumulated per wavefront
+// in LDS and added to ghist[pass][digit] once per block. Where the valid
+// lanes of a wavefront share a digit (grouped input, such as a batch's
+// job-major keys) one lane adds them all: 64 atomics on one LDS address
+// would serialise.
+__global__ __launch_bounds__(kSortBlock) void k_digit_hist_all(const uint32_t *__restrict__ keys,
+                                                               int64_t n, int lo_bit, int npass,
+                                                               uint32_t *__restrict__ ghist)
+{
+    __shared__ uint32_t h[kWaves][4][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int w = 0; w < kWaves; ++w)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) h[w][p][tid] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * kSortBlock * 4;
+    for (int64_t b = (int64_t)blockIdx.x * kSortBlock * 4 + tid; b < n; b += stride) {
+        uint32_t kk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = b + u * kSortBlock;
+            kk[u] = e < n ? keys[e] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool valid = b + u * kSortBlock < n;
+            const uint64_t vm = __ballot(valid);
+            if (vm == 0) break;  // wavefront-uniform
+            const int lead = __builtin_ffsll((long long)vm) - 1;
+            for (int p = 0; p < npass; ++p) {
+                const uint32_t d = (kk[u] >> (lo_bit + 8 * p)) & 255u;
+                const uint32_t d0 = (uint32_t)__shfl((int)d, lead);
+                if (__ballot(valid && d != d0) == 0) {
+                    if ((int)__lane_id() == lead) atomicAdd(&h[wave][p][d0], (uint32_t)__popcll(vm));
+                } else if (valid) {
+                    atomicAdd(&h[wave][p][d], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < npass; ++p) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) c += h[w][p][tid];
+        if (c) atomicAdd(&ghist[p * 256 + tid], c);
+    }
+}
+
+// Look-back status word of one (tile, digit): the flag in the top two bits
+// (0 not yet published, 1 the tile's own count, 2 the count of this and
+// every earlier tile), the count in the low 30.
+constexpr uint32_t kStAgg = 1u << 30, kStInc = 2u << 30, kStVal = (1u << 30) - 1u;
+constexpr uint32_t kSpinLimit = 1u << 16;  // polls before a look-back gives up
+
+__device__ __forceinline__ void st_publish(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t st_read(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One pass over the tiles: stable scatter of the tile counter's next tile
+// by the digit at `shift`. ghist: this pass's digit totals; tctr: this
+// pass's tile counter; status: nb x 256 look-back words (all zero at entry).
+// A tile waits only on tiles that took their numbers before it (and so are
+// running or done); a wait that exceeds kSpinLimit polls gives up, leaving
+// a wrong order but no access out of bounds.
+__global__ __launch_bounds__(kSortBlock) void k_onesweep(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ ghist, uint32_t *__restrict__ tctr, uint32_t *status, int nb)
+{
+    constexpr int kPerWave = kSortTile / kWaves;  // 1024
+    constexpr int kRounds = kPerWave / 64;        // 16
+    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+    __shared__ uint32_t gbase[256], tstart[256];
+    __shared__ uint32_t wc[kWaves][256];
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    if (tid == 0) s_tile = atomicAdd(tctr, 1u);
+    // where each digit starts in the output
+    const uint32_t dbase = block256_excl_scan(ghist[tid], wsum);
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= (uint32_t)nb) return;  // the counter was not cleared: nothing is touched
+    const int64_t tbase = (int64_t)tile * kSortTile;
+    const int64_t wbase = tbase + (int64_t)wave * kPerWave + __lane_id();
+    uint32_t kk[kRounds], vv[kRounds], loc[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t e = wbase + r * 64;
+        kk[r] = e < n ? kin[e] : 0u;
+        vv[r] = e < n ? vin[e] : 0u;
+    }
+    uint32_t *cnt = wc[wave];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const bool valid = wbase + r * 64 < n;
+        const uint32_t d = (kk[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bb = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? bb : ~bb;
+        }
+        const unsigned rank = rank_in_mask(peers & lanemask_lt());
+        const unsigned grp = (unsigned)__popcll(peers);
+        // the group's read of its counter comes before its last lane's update
+        // (one wavefront's LDS operations complete in order)
+        const uint32_t c = valid ? cnt[d] : 0u;
+        loc[r] = c + rank;
+        if (valid && rank + 1 == grp) cnt[d] = c + grp;
+    }
+    __syncthreads();
+    // thread tid = digit: where each wavefront's elements of it start, and
+    // the tile's count of it
+    uint32_t acc = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t t = wc[w][tid];
+        wc[w][tid] = acc;
+        acc += t;
+    }
+    uint32_t *mine = status + (size_t)tile * 256 + tid;
+    uint32_t excl = 0;
+    if (tile == 0) {
+        st_publish(mine, kStInc | acc);
+    } else {
+        st_publish(mine, kStAgg | acc);
+        int64_t p = (int64_t)tile - 1;
+        uint32_t spins = 0;
+        while (p >= 0) {
+            const uint32_t v = st_read(status + (size_t)p * 256 + tid);
+            const uint32_t fl = v & ~kStVal;
+            if (fl == 0u) {
+                if (++spins > kSpinLimit) break;
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += v & kStVal;
+            if (fl == kStInc) break;
+            --p;
+        }
+        st_publish(mine, kStInc | ((excl + acc) & kStVal));
+    }
+    gbase[tid] = dbase + excl;
+    tstart[tid] = block256_excl_scan(acc, wsum);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (wbase + r * 64 < n) {
+            const uint32_t d = (kk[r] >> shift) & 255u;
+            const uint32_t slot = tstart[d] + cnt[d] + loc[r];
+            sk[slot] = kk[r];
+            sv[slot] = vv[r];
+        }
+    }
+    __syncthreads();
+    const int nt = (int)min<int64_t>(kSortTile, n - tbase);
+    for (int q = tid; q < nt; q += kSortBlock) {
+        const uint32_t k = sk[q];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t dst = gbase[d] + (uint32_t)(q - tstart[d]);
+        if (dst < (uint64_t)n) {
+            kout[dst] = k;
+            vout[dst] = sv[q];
+        }
+    }
+}
+
+__global__ void k_sort_clear(uint32_t *__restrict__ p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0u;
 }
 
 // ---------------------------------------------------------------------------- scans
@@ -326,11 +528,20 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tota
     return scan_impl<uint32_t, uint32_t>(in, 1, out, n, total, ws, s);
 }
 
+// One-sweep workspace: ghist[4][256], tile counters[64], status[4][nb][256].
+constexpr int64_t kOneSweepMax = (int64_t)1 << 30;  // counts fit the status words
+static size_t onesweep_words(int64_t nb, int npass)
+{
+    return (size_t)4 * 256 + 64 + (size_t)npass * 256 * (size_t)nb;
+}
+
 size_t radix_ws_bytes(int64_t n)
 {
     int64_t nb = (n + kSortTile - 1) / kSortTile;
-    size_t hist = (size_t)256 * (size_t)(nb > 0 ? nb : 1) * sizeof(uint32_t);
-    return 2 * hist + 256 * sizeof(uint32_t) + scan_ws_bytes(256 * (nb > 0 ? nb : 1)) + 256;
+    if (nb < 1) nb = 1;
+    size_t hist = (size_t)256 * (size_t)nb * sizeof(uint32_t);
+    const size_t table = 2 * hist + 256 * sizeof(uint32_t) + scan_ws_bytes(256 * nb) + 256;
+    return std::max(table, onesweep_words(nb, 4) * sizeof(uint32_t));
 }
 
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
@@ -346,6 +557,32 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
     *in_tmp = 0;
     if (n <= 1 || nbits <= lo_bit) return hipSuccess;
     int64_t nb = (n + kSortTile - 1) / kSortTile;
+    // up to kRowScanTiles tiles, one workgroup per digit scans its row of the
+    // table cheaply and the look-back's latency does not pay; above, the
+    // table needs a full scan and one sweep is faster
+    if (nb > kRowScanTiles && n < kOneSweepMax) {
+        const int npass = (nbits - lo_bit + 7) / 8;  // at most 4
+        uint32_t *ghist = (uint32_t *)ws;
+        uint32_t *tctr = ghist + 4 * 256;
+        uint32_t *status = tctr + 64;
+        const int64_t words = (int64_t)onesweep_words(nb, npass);
+        hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
+                           ghist, words);
+        const unsigned hb = (unsigned)std::min<int64_t>((n + 4 * kSortBlock - 1) / (4 * kSortBlock),
+                                                        2048);
+        hipLaunchKernelGGL(k_digit_hist_all, dim3(hb), dim3(kSortBlock), 0, s, keys, n, lo_bit,
+                           npass, ghist);
+        uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
+        for (int p = 0; p < npass; ++p) {
+            hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, va, kb,
+                               vb, n, lo_bit + 8 * p, ghist + 256 * p, tctr + p,
+                               status + (size_t)p * 256 * (size_t)nb, (int)nb);
+            std::swap(ka, kb);
+            std::swap(va, vb);
+            *in_tmp ^= 1;
+        }
+        return hipGetLastError();
+    }
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + 256 * nb;
     uint32_t *tot = offs + 256 * nb;

@@ -4,8 +4,9 @@ Pair sets and best-match indices must be identical; separations agree to
 1e-6 arcsec. Covered: the 10k x 10k patch in full, both precisions; the
 closed-form fixtures; adversarial near-boundary rows; scaled-down full-sky
 (RA wrap, polar cap) and galactic-ellipse workloads; several cell sizes;
-BEST-only output; radius 0 and duplicates; empty inputs; error paths; and
-sampled rows of the full 10M x 10M full-sky workload.
+BEST-only output; radius 0 and duplicates; empty inputs; error paths;
+sampled rows of the full 10M x 10M full-sky workload; and sampled rows of a
+34M x 34M full-sky draw (sorted by the one-sweep passes).
 """
 import os
 import sys
@@ -269,6 +270,42 @@ def test_cfg2_full_size_sampled(c3x, dev, precision):
     assert np.all(np.diff(key) > 0)
     assert g["sep"].max() <= cat.radius_arcsec + 1e-9
     assert 7.0e6 < len(ia) < 8.5e6
+
+
+@pytest.fixture(scope="module")
+def fullsky_34m():
+    """A 34M x 34M draw of the full-sky workload (dense caps included): both
+    catalogues exceed 32M rows (8,301 tiles of 4,096), so the index and the
+    A order are sorted by the one-sweep radix passes (tile prefixes found by
+    look-back)."""
+    import oracle
+    cat = synth.cfg2_fullsky(scale=3.4)
+    rng = np.random.default_rng(11)
+    dense = np.nonzero(cat.decA > 88.0)[0]
+    rows = np.unique(np.concatenate([rng.choice(cat.nA, 1500, replace=False),
+                                     rng.choice(dense, 500, replace=False)]))
+    o = oracle.match(cat.raA[rows], cat.decA[rows], cat.raB, cat.decB,
+                     radius_arcsec=cat.radius_arcsec)
+    return cat, rows, o
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", [1, 0])
+def test_one_sweep_sorts_34m_sampled(c3x, dev, fullsky_34m, precision):
+    """Sampled rows of a 34M x 34M cross-match against the oracle over the
+    whole of B, and the full result's canonical order."""
+    cat, rows, o = fullsky_34m
+    g = gpu_match(c3x, dev, cat, precision)
+    sel = np.isin(g["ia"], rows)
+    remap = np.searchsorted(rows, g["ia"][sel])
+    assert np.array_equal(remap, o.ia)
+    assert np.array_equal(g["ib"][sel], o.ib)
+    assert np.abs(g["sep"][sel] - o.sep).max() <= SEP_TOL
+    assert np.array_equal(g["best"][rows], o.best_idx)
+    key = g["ia"].astype(np.int64) * (1 << 31) + g["ib"]
+    assert np.all(np.diff(key) > 0)
+    assert g["sep"].max() <= cat.radius_arcsec + 1e-9
+    assert len(g["ia"]) > 0.5 * cat.nA
 
 
 @pytest.mark.parametrize("precision", [0, 1])
