@@ -116,10 +116,24 @@ def run_path(c3x, torch, tens, cat, precision, steps, warmup, area_kw, frame, mo
     return ms, last["r"], kstats
 
 
-def path_summary(cat, ms, r, ks):
+def count_pass_bytes(cat, r, pay):
+    """Algorithmic bytes of one count-pass launch: every A record read once
+    (sorted coordinates 16 B, row 4 B, candidate ranges 24 B); a count and a
+    record (4 + 16 B) written for each row with a match (rows without one
+    store nothing); every B payload read at least once (16 B mixed, 32 B
+    FP64) with its 4-byte key."""
+    import torch
+    matched = int((torch.as_tensor(r.best_idx) >= 0).sum().item())
+    return cat.nA * (16 + 4 + 24) + matched * (4 + 16) + cat.nB * (pay + 4), matched
+
+
+def path_summary(cat, ms, r, ks, pay):
     ist = [k[0] for k in ks]
     mst = [k[1] for k in ks]
+    alg, matched = count_pass_bytes(cat, r, pay)
     return dict(
+        rows_matched=matched,
+        count_pass_algorithmic_bytes=int(alg),
         ms_per_step=ms,
         a_per_s=cat.nA / (ms / 1e3),
         pair_tests=int(mst[-1]["n_tests"]),
@@ -200,7 +214,7 @@ def single_config(a, c3x, torch, np, name):
     for pname in order:
         prec = c3x.MIXED if pname == "mixed" else c3x.FP64
         ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup, area_kw, frame, mode)
-        paths[pname] = path_summary(cat, ms, r, ks)
+        paths[pname] = path_summary(cat, ms, r, ks, 16 if pname == "mixed" else 32)
         log(f"{pname}: {ms:.3f} ms/step, {paths[pname]['phases_ms']}")
         del r
 
@@ -209,14 +223,9 @@ def single_config(a, c3x, torch, np, name):
     # matches (k_match<..., 2>, one launch per step); its duration is the
     # library's pair of HIP events around that launch alone, on the stream it
     # runs on (the count phase adds the wavefront-per-row kernel, the band
-    # recheck and the read-back). Algorithmic
-    # bytes per launch: every A record read once (sorted coordinates 16 B,
-    # row 4 B, candidate ranges 24 B) and its count and record written (4 +
-    # 16 B); every B payload read at least once (16 B mixed, 32 B FP64, plus
-    # the 4 B key).
+    # recheck and the read-back). Algorithmic bytes: count_pass_bytes.
     hp = head["phases_ms"]
-    pay = 16 if order[0] == "mixed" else 32
-    alg_bytes = cat.nA * (16 + 4 + 24 + 4 + 16) + cat.nB * (pay + 4)
+    alg_bytes = head["count_pass_algorithmic_bytes"]
     achieved = alg_bytes / (hp["count_kernel"] / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_match (count + emit pass)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
