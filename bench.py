@@ -127,6 +127,25 @@ def count_pass_bytes(cat, r, pay):
     return cat.nA * (16 + 4 + 24) + matched * (4 + 16) + cat.nB * (pay + 4), matched
 
 
+def time_unmatched(c3x, torch, cat, r, steps):
+    """The join types' own step (c3x_result_unmatched, selection ALL) on a
+    result: mean time over `steps` calls, each of which returns with its
+    counts. Algorithmic bytes: the flags cleared (1 B per row of either
+    catalogue), every stored pair read (8 B), the flags read twice (count,
+    then compaction), 4 B written per unmatched row."""
+    c3x.unmatched(r, c3x.ALL)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        ua, ub = c3x.unmatched(r, c3x.ALL)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    nu = int(ua.shape[0]) + int(ub.shape[0])
+    alg = 3 * (cat.nA + cat.nB) + 8 * int(r.n_pairs) + 4 * nu
+    return {"ms": round(ms, 4), "unmatched_a": int(ua.shape[0]), "unmatched_b": int(ub.shape[0]),
+            "algorithmic_bytes": alg, "GB_per_s": round(alg / (ms / 1e3) / 1e9, 1)}
+
+
 def path_summary(cat, ms, r, ks, pay):
     ist = [k[0] for k in ks]
     mst = [k[1] for k in ks]
@@ -215,6 +234,8 @@ def single_config(a, c3x, torch, np, name):
         prec = c3x.MIXED if pname == "mixed" else c3x.FP64
         ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup, area_kw, frame, mode)
         paths[pname] = path_summary(cat, ms, r, ks, 16 if pname == "mixed" else 32)
+        if mode & c3x.ALL:
+            paths[pname]["join_unmatched"] = time_unmatched(c3x, torch, cat, r, a.steps)
         log(f"{pname}: {ms:.3f} ms/step, {paths[pname]['phases_ms']}")
         del r
 

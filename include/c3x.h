@@ -183,6 +183,29 @@ c3x_status c3x_result_views(const c3x_result *r, const int32_t **idxA, const int
                             const double **sep_arcsec, const int32_t **best_idxB,
                             const double **best_sep_arcsec);
 
+/* Rows without a stored match, from which every join type of Section 2.2
+ * ("Match selection and join types") is assembled with the stored pairs:
+ *   1 and 2        the stored pairs;
+ *   1 or 2         the pairs, the unmatched A rows and the unmatched B rows;
+ *   All from 1 (2) the pairs and the unmatched A (B) rows;
+ *   1 not 2 (2 not 1)  the unmatched A (B) rows;
+ *   1 xor 2        the unmatched A rows and the unmatched B rows.
+ * selection picks the stored pairs: C3X_ALL, every match (r made with
+ * C3X_ALL); C3X_BEST, each matched A row with its best match (r made with
+ * C3X_BEST). An A row is unmatched when it has no match (under either
+ * selection); a B row when no stored pair names it (under C3X_BEST: it is
+ * no A row's best match). On return *rowsA (*rowsB) points to the ascending
+ * int32 row indices of the unmatched A (B) rows, *n_rowsA (*n_rowsB) of
+ * them: device arrays owned by r, valid until c3x_result_free and
+ * overwritten by the next call on r. Work is ordered on `stream` (NULL: the
+ * null stream), which is synchronised before the call returns. Only
+ * results of c3x_match qualify (a batch result holds job-local rows).
+ * Errors: C3X_EINVAL (NULL argument, batch result, selection not C3X_ALL or
+ * C3X_BEST or not in r's mode), C3X_ENOMEM, C3X_EDEVICE. */
+c3x_status c3x_result_unmatched(c3x_result *r, unsigned selection, void *stream,
+                                const int32_t **rowsA, int64_t *n_rowsA,
+                                const int32_t **rowsB, int64_t *n_rowsB);
+
 /* Counters and timings of the call that produced r (or of an index). */
 c3x_status c3x_result_stats(const c3x_result *r, c3x_stats *s);
 c3x_status c3x_index_stats(const c3x_index *ix, c3x_stats *s);

@@ -2,8 +2,9 @@
 
 Python face of libc3x.so: ``build_index`` over catalogue B and ``match`` of
 catalogue A against it, circle or per-source ellipse areas, "all" and "best"
-selections, equatorial or galactic frames; ``Batch`` for many independent
-circular jobs in one graph launch. All computation happens in the
+selections, equatorial or galactic frames; ``unmatched`` and ``join`` for
+the join types of the paper's Section 2.2 (rows without a stored match);
+``Batch`` for many independent circular jobs in one graph launch. All computation happens in the
 HIP library; torch tensors only carry device memory and streams.
 """
 from ._binding import (  # noqa: F401
@@ -20,8 +21,11 @@ from ._binding import (  # noqa: F401
     C3XError,
     Index,
     MatchResult,
+    JOIN_PARTS,
     build_index,
+    join,
     lib,
     match,
+    unmatched,
     version,
 )

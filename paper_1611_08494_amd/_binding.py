@@ -98,6 +98,9 @@ def lib():
     pvp = ctypes.POINTER(vp)
     L.c3x_result_views.argtypes = [vp, pvp, pvp, pvp, pvp, pvp]
     L.c3x_result_views.restype = ctypes.c_int
+    L.c3x_result_unmatched.argtypes = [vp, ctypes.c_uint, vp, pvp, ctypes.POINTER(i64), pvp,
+                                       ctypes.POINTER(i64)]
+    L.c3x_result_unmatched.restype = ctypes.c_int
     L.c3x_result_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.c3x_result_stats.restype = ctypes.c_int
     L.c3x_index_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -185,13 +188,14 @@ class Index:
 
 
 class MatchResult:
-    def __init__(self, idxA, idxB, sep, best_idx, best_sep, stats):
+    def __init__(self, idxA, idxB, sep, best_idx, best_sep, stats, owner=None):
         self.idxA = idxA
         self.idxB = idxB
         self.sep = sep
         self.best_idx = best_idx
         self.best_sep = best_sep
         self.stats = stats
+        self._owner = owner  # the c3x_result behind the views
 
     @property
     def n_pairs(self) -> int:
@@ -255,7 +259,7 @@ def _views(h, dev) -> MatchResult:
             out.append(torch.empty(n, dtype=dt, device=dev))
         else:
             out.append(torch.as_tensor(_DeviceArray(owner, p.value, n, ts), device=dev))
-    return MatchResult(*out, st.as_dict())
+    return MatchResult(*out, st.as_dict(), owner=owner)
 
 
 def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
@@ -339,6 +343,62 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+def unmatched(result: MatchResult, selection: int = ALL, stream=None):
+    """Rows in no stored pair (c3x_result_unmatched): int32 device tensors of
+    the unmatched A rows and the unmatched B rows, ascending. selection ALL
+    stores every match, BEST each A row's best pair. The tensors view
+    arrays owned by the result (a later call on it overwrites them)."""
+    torch = _torch()
+    owner = result._owner
+    if owner is None or not owner.handle:
+        raise ValueError("result has no library handle")
+    pa, pb = ctypes.c_void_p(), ctypes.c_void_p()
+    na, nb = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().c3x_result_unmatched(owner.handle, int(selection), _stream_ptr(stream),
+                                     ctypes.byref(pa), ctypes.byref(na), ctypes.byref(pb),
+                                     ctypes.byref(nb)))
+    dev = result.best_idx.device
+    out = []
+    for p, n in ((pa, na.value), (pb, nb.value)):
+        if n == 0 or not p.value:
+            out.append(torch.empty(0, dtype=torch.int32, device=dev))
+        else:
+            out.append(torch.as_tensor(_DeviceArray(owner, p.value, n, "<i4"), device=dev))
+    return out[0], out[1]
+
+
+# join type -> (stored pairs, unmatched A rows, unmatched B rows), Section 2.2
+JOIN_PARTS = {
+    "1and2": (True, False, False),
+    "1or2": (True, True, True),
+    "all1": (True, True, False),
+    "all2": (True, False, True),
+    "1not2": (False, True, False),
+    "2not1": (False, False, True),
+    "1xor2": (False, True, True),
+}
+
+
+def join(result: MatchResult, how: str, selection: int = ALL, stream=None) -> dict:
+    """The rows of join type ``how`` (keys of JOIN_PARTS) as a dict of the
+    parts it keeps (None for the parts it leaves out): the stored pairs --
+    selection ALL: "idxA", "idxB", "sep" (every match); selection BEST:
+    "best_idx", "best_sep" (A row a with best_idx[a] when >= 0) -- and the
+    unmatched rows "rowsA", "rowsB". Only assembles what the result and
+    c3x_result_unmatched hold."""
+    if how not in JOIN_PARTS:
+        raise ValueError(f"join must be one of {sorted(JOIN_PARTS)}")
+    keep_p, keep_a, keep_b = JOIN_PARTS[how]
+    ua, ub = unmatched(result, selection, stream)
+    out = {"idxA": None, "idxB": None, "sep": None, "best_idx": None, "best_sep": None,
+           "rowsA": ua if keep_a else None, "rowsB": ub if keep_b else None}
+    if keep_p and selection == ALL:
+        out.update(idxA=result.idxA, idxB=result.idxB, sep=result.sep)
+    elif keep_p:
+        out.update(best_idx=result.best_idx, best_sep=result.best_sep)
+    return out
 
 
 def version() -> str:

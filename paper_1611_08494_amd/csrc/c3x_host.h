@@ -146,11 +146,13 @@ struct c3x_result {
     int device;
     int64_t n_pairs;
     int64_t nA;
+    int64_t nB = -1;  // rows of catalogue B (c3x_match results; -1 for a batch)
     unsigned mode;
     c3x::Arena mem;
     int32_t *idxA = nullptr, *idxB = nullptr;
     double *sep = nullptr;
     int32_t *best_idx = nullptr;
     double *best_sep = nullptr;
+    int32_t *unA = nullptr, *unB = nullptr;  // unmatched rows (c3x_result_unmatched)
     c3x_stats stats;
 };

@@ -2398,6 +2398,7 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
     (void)hipGetDevice(&R->device);
     memset(&R->stats, 0, sizeof(R->stats));
     R->mode = mode;
+    R->nB = ix->nB;
     c3x_status st = match_impl(ix, ra_deg, dec_deg, nA, area, mode, s, R);
     if (st != C3X_OK) {
         (void)hipStreamSynchronize(s);

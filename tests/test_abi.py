@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
     fns = header_functions()
     for f in ("c3x_build_index", "c3x_match", "c3x_result_sizes", "c3x_result_copy",
               "c3x_result_views", "c3x_result_stats", "c3x_result_free", "c3x_index_free", "c3x_last_error",
-              "c3x_version", "c3x_abi_version", "c3x_index_stats"):
+              "c3x_version", "c3x_abi_version", "c3x_index_stats", "c3x_result_unmatched"):
         assert f in fns
 
 
@@ -59,6 +59,7 @@ def test_argument_errors_need_no_device(L):
     assert L.c3x_result_sizes(None, None, None) == b.EINVAL
     b.lib()  # argument types
     assert L.c3x_result_views(None, None, None, None, None, None) == b.EINVAL
+    assert L.c3x_result_unmatched(None, 1, None, None, None, None, None) == b.EINVAL
     L.c3x_result_free(None)  # a no-op
 
 
