@@ -146,6 +146,33 @@ def time_unmatched(c3x, torch, cat, r, steps):
             "algorithmic_bytes": alg, "GB_per_s": round(alg / (ms / 1e3) / 1e9, 1)}
 
 
+CONCENTRIC_SCALES = [0.5, 1.0, 1.5, 2.0]
+
+
+def time_concentric(c3x, torch, tens, cat, precision, steps, area_kw, frame):
+    """ClumpPopulator's concentric ellipses (c3x_match_concentric) at
+    CONCENTRIC_SCALES over one index: mean time of a call (one certified
+    elliptical match per scale plus the level marking), and the pairs per
+    level."""
+    raA, decA, raB, decB = tens
+    ix = c3x.build_index(raB, decB, frame=frame, reach_hint_arcsec=cat.reach_arcsec(),
+                         precision=precision)
+    kw = dict(a=area_kw["a"], b=area_kw["b"], pa=area_kw["pa"], scales=CONCENTRIC_SCALES,
+              frame=frame, pa_zero_deg=area_kw["pa_zero_deg"], pa_sense=area_kw["pa_sense"],
+              mode=c3x.ALL)
+    r = c3x.match_concentric(ix, raA, decA, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        r = c3x.match_concentric(ix, raA, decA, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    per = torch.bincount(r.level.long(), minlength=len(CONCENTRIC_SCALES)).tolist()
+    ix.free()
+    return {"scales": CONCENTRIC_SCALES, "ms": round(ms, 3), "pairs": int(r.n_pairs),
+            "pairs_per_level": per}
+
+
 def path_summary(cat, ms, r, ks, pay):
     ist = [k[0] for k in ks]
     mst = [k[1] for k in ks]
@@ -236,8 +263,11 @@ def single_config(a, c3x, torch, np, name):
         paths[pname] = path_summary(cat, ms, r, ks, 16 if pname == "mixed" else 32)
         if mode & c3x.ALL:
             paths[pname]["join_unmatched"] = time_unmatched(c3x, torch, cat, r, a.steps)
-        log(f"{pname}: {ms:.3f} ms/step, {paths[pname]['phases_ms']}")
         del r
+        if cat.shape == 1:
+            paths[pname]["concentric"] = time_concentric(c3x, torch, tens, cat, prec, a.steps,
+                                                         area_kw, frame)
+        log(f"{pname}: {ms:.3f} ms/step, {paths[pname]['phases_ms']}")
 
     head = paths[order[0]]
     # Dominant kernel of the path: the single pass that counts and emits the

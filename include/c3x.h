@@ -183,6 +183,30 @@ c3x_status c3x_result_views(const c3x_result *r, const int32_t **idxA, const int
                             const double **sep_arcsec, const int32_t **best_idxB,
                             const double **best_sep_arcsec);
 
+/* Concentric ellipses (Section 3, ClumpPopulator): each A source's ellipse
+ * (area->shape must be C3X_ELLIPSE) is also taken at the scale factors
+ * scales[0] < scales[1] < ... < scales[n_scales - 1] (host array, finite,
+ * > 0, 1 <= n_scales <= 64): ellipse m has semi-axes a * scales[m] and
+ * b * scales[m] (FP64 products), the source's centre and position angle.
+ * The result is c3x_match's for the largest ellipse (mode must include
+ * C3X_ALL; C3X_BEST adds the best matches within it), and each of its pairs
+ * has a level: the smallest m whose ellipse holds the B source (the
+ * ellipses are nested), read with c3x_result_levels. Every ellipse is a
+ * certified c3x_match over the same index (one call per scale), so the
+ * scaled axes must satisfy c3x_match's ellipse domain. The returned
+ * result's stats are those of the largest ellipse's call. Errors: those of
+ * c3x_match; C3X_EINVAL also for a circle, a mode without C3X_ALL, or bad
+ * scales. */
+c3x_status c3x_match_concentric(const c3x_index *ix, const double *ra_deg, const double *dec_deg,
+                                int64_t nA, c3x_frame frame, const c3x_area *area,
+                                const double *scales, int32_t n_scales, unsigned mode,
+                                const c3x_opts *opts, c3x_result **out);
+
+/* Per-pair levels of a c3x_match_concentric result: int32 device array of
+ * n_pairs entries in the pairs' order, owned by r. EINVAL for other
+ * results. */
+c3x_status c3x_result_levels(const c3x_result *r, const int32_t **level);
+
 /* Rows without a stored match, from which every join type of Section 2.2
  * ("Match selection and join types") is assembled with the stored pairs:
  *   1 and 2        the stored pairs;

@@ -2,7 +2,8 @@
 
 Python face of libc3x.so: ``build_index`` over catalogue B and ``match`` of
 catalogue A against it, circle or per-source ellipse areas, "all" and "best"
-selections, equatorial or galactic frames; ``unmatched`` and ``join`` for
+selections, equatorial or galactic frames; ``match_concentric`` for
+ClumpPopulator's concentric ellipses (Section 3); ``unmatched`` and ``join`` for
 the join types of the paper's Section 2.2 (rows without a stored match);
 ``Batch`` for many independent circular jobs in one graph launch. All computation happens in the
 HIP library; torch tensors only carry device memory and streams.
@@ -26,6 +27,7 @@ from ._binding import (  # noqa: F401
     join,
     lib,
     match,
+    match_concentric,
     unmatched,
     version,
 )

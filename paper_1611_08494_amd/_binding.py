@@ -100,6 +100,12 @@ def lib():
     L.c3x_result_views.restype = ctypes.c_int
     L.c3x_result_unmatched.argtypes = [vp, ctypes.c_uint, vp, pvp, ctypes.POINTER(i64), pvp,
                                        ctypes.POINTER(i64)]
+    L.c3x_match_concentric.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.POINTER(Area),
+                                       ctypes.POINTER(dbl), i32, ctypes.c_uint,
+                                       ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.c3x_match_concentric.restype = ctypes.c_int
+    L.c3x_result_levels.argtypes = [vp, pvp]
+    L.c3x_result_levels.restype = ctypes.c_int
     L.c3x_result_unmatched.restype = ctypes.c_int
     L.c3x_result_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.c3x_result_stats.restype = ctypes.c_int
@@ -289,6 +295,41 @@ def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
     check(lib().c3x_match(index.handle, ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(frame),
                           ctypes.byref(ar), int(mode), ctypes.byref(o), ctypes.byref(h)))
     return _views(h, ra.device)
+
+
+def match_concentric(index: Index, ra, dec, a, b, pa, scales, frame: int = EQUATORIAL,
+                     pa_zero_deg: float = 0.0, pa_sense: int = 1, mode: int = ALL | BEST,
+                     stream=None) -> MatchResult:
+    """Concentric ellipses (c3x_match_concentric): the result of the largest
+    scaled ellipse, with ``level`` (int32 device tensor, one entry per pair):
+    the index in ``scales`` (ascending) of the smallest ellipse holding the
+    pair's B source."""
+    torch = _torch()
+    ra = _dev_f64(ra, "ra")
+    dec = _dev_f64(dec, "dec")
+    if ra.shape != dec.shape:
+        raise ValueError("ra and dec differ in length")
+    for nm, v in (("a", a), ("b", b), ("pa", pa)):
+        if _dev_f64(v, nm).shape != ra.shape:
+            raise ValueError(f"{nm} must have one entry per A row")
+    ar = Area(shape=ELLIPSE, radius_arcsec=0.0, pa_zero_deg=float(pa_zero_deg),
+              pa_sense=int(pa_sense))
+    ar.semi_major_arcsec = a.data_ptr()
+    ar.semi_minor_arcsec = b.data_ptr()
+    ar.pa_deg = pa.data_ptr()
+    ks = (ctypes.c_double * len(scales))(*[float(k) for k in scales])
+    o = Opts(precision=int(index.precision), cell_arcsec=0.0, tile=0, stream=_stream_ptr(stream))
+    h = ctypes.c_void_p()
+    check(lib().c3x_match_concentric(index.handle, ra.data_ptr(), dec.data_ptr(), ra.shape[0],
+                                     int(frame), ctypes.byref(ar), ks, len(scales), int(mode),
+                                     ctypes.byref(o), ctypes.byref(h)))
+    r = _views(h, ra.device)
+    p = ctypes.c_void_p()
+    check(lib().c3x_result_levels(r._owner.handle, ctypes.byref(p)))
+    n = r.n_pairs
+    r.level = (torch.as_tensor(_DeviceArray(r._owner, p.value, n, "<i4"), device=ra.device)
+               if n and p.value else torch.empty(0, dtype=torch.int32, device=ra.device))
+    return r
 
 
 class Batch:

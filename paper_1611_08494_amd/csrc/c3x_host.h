@@ -154,5 +154,7 @@ struct c3x_result {
     int32_t *best_idx = nullptr;
     double *best_sep = nullptr;
     int32_t *unA = nullptr, *unB = nullptr;  // unmatched rows (c3x_result_unmatched)
+    int32_t *level = nullptr;  // per pair: smallest scale holding it (c3x_match_concentric)
+    int n_scales = 0;
     c3x_stats stats;
 };

@@ -29,7 +29,8 @@ def test_header_declares_the_boundary():
     fns = header_functions()
     for f in ("c3x_build_index", "c3x_match", "c3x_result_sizes", "c3x_result_copy",
               "c3x_result_views", "c3x_result_stats", "c3x_result_free", "c3x_index_free", "c3x_last_error",
-              "c3x_version", "c3x_abi_version", "c3x_index_stats", "c3x_result_unmatched"):
+              "c3x_version", "c3x_abi_version", "c3x_index_stats", "c3x_result_unmatched",
+              "c3x_match_concentric", "c3x_result_levels"):
         assert f in fns
 
 
@@ -60,6 +61,12 @@ def test_argument_errors_need_no_device(L):
     b.lib()  # argument types
     assert L.c3x_result_views(None, None, None, None, None, None) == b.EINVAL
     assert L.c3x_result_unmatched(None, 1, None, None, None, None, None) == b.EINVAL
+    assert L.c3x_match_concentric(None, None, None, 0, 0, None, None, 0, 1, None, None) == b.EINVAL
+    h2 = ctypes.c_void_p()
+    assert L.c3x_match_concentric(None, None, None, 0, 0, None, None, 0, 1, None,
+                                  ctypes.byref(h2)) == b.EINVAL
+    assert h2.value is None
+    assert L.c3x_result_levels(None, None) == b.EINVAL
     L.c3x_result_free(None)  # a no-op
 
 
