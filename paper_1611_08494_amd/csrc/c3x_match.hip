@@ -1554,36 +1554,6 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
     }
 }
 
-// Final records of a segment already sorted in place (host-driven path).
-__global__ void k_seg_copy(int64_t o, int64_t len, int64_t a, const PairTmp *__restrict__ tmp,
-                           int64_t nB, const double *__restrict__ raA,
-                           const double *__restrict__ decA, const double2 *__restrict__ radecB,
-                           const RowRec *__restrict__ rec, int32_t *__restrict__ oa,
-                           int32_t *__restrict__ ob, double *__restrict__ os,
-                           double *__restrict__ bsep, uint32_t *__restrict__ err)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < len)
-        final_write<true>(o + k, a, tmp[o + k], nB, raA, decA, radecB, rec[a].best, oa, ob, os,
-                          bsep, err);
-}
-
-__global__ void k_split(const PairTmp *__restrict__ t, int64_t n, uint32_t *__restrict__ k,
-                        uint32_t *__restrict__ v)
-{
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    k[p] = t[p].idxB;
-    v[p] = (uint32_t)p;
-}
-
-__global__ void k_merge(const uint32_t *__restrict__ v, const PairTmp *__restrict__ copy, int64_t n,
-                        PairTmp *__restrict__ t)
-{
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n && v[p] < (uint64_t)n) t[p] = copy[v[p]];
-}
-
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // What the finishing kernels need.
@@ -1628,39 +1598,111 @@ static void finish_segments(const FinishArgs &f, hipStream_t s)
 #undef C3X_FIN
 }
 
-// Segments longer than kSegLds (counts already on the host): radix sort by
-// idxB, one segment at a time, then their final records.
+// Segments longer than kSegLds (their count already on the host), all at
+// once: their entries gathered into one array (key idxB, value the entry's
+// place in that array), sorted by idxB, then stably by segment, and each
+// written to its place in its segment.
+__global__ void k_huge_len(const uint32_t *__restrict__ huge, uint32_t nh,
+                           const int64_t *__restrict__ off, uint32_t *__restrict__ len)
+{
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= nh) return;
+    const uint32_t a = huge[h];
+    len[h] = (uint32_t)(off[a + 1] - off[a]);
+}
+
+__global__ void k_huge_gather(const uint32_t *__restrict__ huge, uint32_t nh,
+                              const int64_t *__restrict__ off, const uint32_t *__restrict__ base,
+                              const PairTmp *__restrict__ tmp, uint32_t *__restrict__ key,
+                              uint32_t *__restrict__ val, uint32_t *__restrict__ seg)
+{
+    for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+        const uint32_t a = huge[h];
+        const int64_t o = off[a], len = off[a + 1] - o;
+        const uint32_t b = base[h];
+        for (int64_t k = threadIdx.x; k < len; k += blockDim.x) {
+            key[b + k] = tmp[o + k].idxB;
+            val[b + k] = b + (uint32_t)k;
+            seg[b + k] = h;
+        }
+    }
+}
+
+__global__ void k_huge_segkey(const uint32_t *__restrict__ val, const uint32_t *__restrict__ seg,
+                              uint32_t n, uint32_t *__restrict__ key)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) key[t] = seg[val[t]];
+}
+
+// Entry i of the final order: gathered entry e = val[i] of segment h, whose
+// row is huge[h]; it goes to rank i - base[h] of that row's segment.
+__global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
+                             const uint32_t *__restrict__ seg, const uint32_t *__restrict__ base,
+                             const uint32_t *__restrict__ huge, const int64_t *__restrict__ off,
+                             const PairTmp *__restrict__ tmp, int64_t nB,
+                             const double *__restrict__ raA, const double *__restrict__ decA,
+                             const double2 *__restrict__ radecB, const RowRec *__restrict__ rec,
+                             int32_t *__restrict__ oa, int32_t *__restrict__ ob,
+                             double *__restrict__ os, double *__restrict__ bsep,
+                             uint32_t *__restrict__ err)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t e = val[i];
+    if (e >= n) {
+        atomicOr(err, 16u);
+        return;
+    }
+    const uint32_t h = seg[e];
+    const uint32_t a = huge[h];
+    const int64_t o = off[a];
+    final_write<true>(o + (i - base[h]), a, tmp[o + (e - base[h])], nB, raA, decA, radecB,
+                      rec[a].best, oa, ob, os, bsep, err);
+}
+
 static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStream_t s)
 {
     if (hseg[0] > f.cap || hseg[1] > f.cap) return fail(C3X_ENOMEM, "too many long segments");
-    uint32_t nh = hseg[1];
+    const uint32_t nh = hseg[1];
     if (nh == 0) return C3X_OK;
-    std::vector<uint32_t> hv(nh);
-    hipError_t e = hipMemcpy(hv.data(), f.huge, nh * sizeof(uint32_t), hipMemcpyDeviceToHost);
-    for (uint32_t k = 0; k < nh && e == hipSuccess; ++k) {
-        int64_t ob[2];
-        e = hipMemcpy(ob, f.off + hv[k], 2 * sizeof(int64_t), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) break;
-        int64_t o = ob[0], len = ob[1] - ob[0];
-        Arena t2(s);
-        uint32_t *k1 = t2.get_n<uint32_t>(len), *v1 = t2.get_n<uint32_t>(len);
-        uint32_t *k2 = t2.get_n<uint32_t>(len), *v2 = t2.get_n<uint32_t>(len);
-        PairTmp *copy = t2.get_n<PairTmp>(len);
-        void *ws = t2.get(radix_ws_bytes(len));
-        if (!k1 || !v1 || !k2 || !v2 || !copy || !ws) return fail(C3X_ENOMEM, "segment sort");
-        e = hipMemcpyAsync(copy, f.tmp + o, len * sizeof(PairTmp), hipMemcpyDeviceToDevice, s);
-        hipLaunchKernelGGL(k_split, dim3(nblk(len, 256)), dim3(256), 0, s, f.tmp + o, len, k1, v1);
-        int in_tmp = 0;
-        if (e == hipSuccess) e = radix_sort_pairs(k1, v1, k2, v2, len, 31, ws, s, &in_tmp);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_merge, dim3(nblk(len, 256)), dim3(256), 0, s, in_tmp ? v2 : v1,
-                               copy, len, f.tmp + o);
-            hipLaunchKernelGGL(k_seg_copy, dim3(nblk(len, 256)), dim3(256), 0, s, o, len,
-                               (int64_t)hv[k], f.tmp, f.nB, f.raA, f.decA, f.radecB, f.rec, f.oa,
-                               f.ob, f.os, f.bsep, f.err);
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    Arena t2(s);
+    uint32_t *len = t2.get_n<uint32_t>(nh), *base = t2.get_n<uint32_t>(nh);
+    uint32_t *tot = t2.get_n<uint32_t>(1);
+    void *sws = t2.get(scan_ws_bytes(nh));
+    if (!len || !base || !tot || !sws) return fail(C3X_ENOMEM, "segment order");
+    hipLaunchKernelGGL(k_huge_len, dim3(nblk(nh, 256)), dim3(256), 0, s, f.huge, nh, f.off, len);
+    hipError_t e = scan_u32(len, base, nh, tot, sws, s);
+    uint32_t n = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&n, tot, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "segment order");
+    uint32_t *k1 = t2.get_n<uint32_t>(n), *v1 = t2.get_n<uint32_t>(n);
+    uint32_t *k2 = t2.get_n<uint32_t>(n), *v2 = t2.get_n<uint32_t>(n);
+    uint32_t *seg = t2.get_n<uint32_t>(n);
+    void *ws = t2.get(radix_ws_bytes(n));
+    if (!k1 || !v1 || !k2 || !v2 || !seg || !ws) return fail(C3X_ENOMEM, "segment order");
+    hipLaunchKernelGGL(k_huge_gather, dim3(std::min<uint32_t>(nh, 4096)), dim3(256), 0, s, f.huge,
+                       nh, f.off, base, f.tmp, k1, v1, seg);
+    // by idxB (stable), then by segment (stable): each segment in idxB order
+    int in1 = 0, in2 = 0;
+    e = radix_sort_pairs(k1, v1, k2, v2, n, 31, ws, s, &in1);
+    uint32_t *ka = in1 ? k2 : k1, *va = in1 ? v2 : v1;  // sorted by idxB
+    uint32_t *kb = in1 ? k1 : k2, *vb = in1 ? v1 : v2;  // free
+    int segbits = 1;
+    while (segbits < 32 && (nh - 1) >> segbits) ++segbits;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_huge_segkey, dim3(nblk(n, 256)), dim3(256), 0, s, va, seg, n, kb);
+        e = radix_sort_pairs(kb, va, ka, vb, n, segbits, ws, s, &in2);
     }
+    if (e == hipSuccess) {
+        const uint32_t *vf = in2 ? vb : va;
+        hipLaunchKernelGGL(k_huge_write, dim3(nblk(n, 256)), dim3(256), 0, s, vf, n, seg, base,
+                           f.huge, f.off, f.tmp, f.nB, f.raA, f.decA, f.radecB, f.rec, f.oa, f.ob,
+                           f.os, f.bsep, f.err);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_hip(e, "segment order");
     return C3X_OK;
 }
@@ -1797,6 +1839,8 @@ static void stat_sums(const unsigned long long *h, unsigned long long out[3])
 // Overflow-list demand of recent calls, in entries per 1024 A rows: sizes the
 // next call's regions so that steady workloads keep the single pass.
 static std::atomic<uint64_t> g_ov_hint{0};
+constexpr uint64_t kOvFloorBytes = 1ull << 30;  // overflow regions: floor of 256 entries a row up to this
+constexpr uint64_t kOvMaxBytes = 4ull << 30;    // and never more than this
 
 static c3x_status match_impl(const c3x_index *ix, const double *ra, const double *dec, int64_t nA,
                              const c3x_area *area, unsigned mode, hipStream_t s, c3x_result *R)
@@ -1939,10 +1983,17 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     bool emit = false;
     if (all && nA > 0) {
         // regions sized from the need seen by recent calls (entries per 1024
-        // A rows), at least nA / 8 entries in all
+        // A rows); at least 256 entries per row while that stays within
+        // kOvFloorBytes, at least nA / 8 in all, and at most kOvMaxBytes (an
+        // unused entry costs nothing but memory; a full region costs a
+        // second, write-only pass)
         const uint64_t hint = g_ov_hint.load(std::memory_order_relaxed);
+        const uint64_t floor_n = std::min<uint64_t>((uint64_t)nA * 256,
+                                                    kOvFloorBytes / sizeof(OvEnt));
         uint64_t per = (uint64_t)std::max<int64_t>(nA / 8 / kEmitPools, 4096);
+        per = std::max<uint64_t>(per, (floor_n + kEmitPools - 1) / kEmitPools);
         per = std::max<uint64_t>(per, ((uint64_t)nA * hint / 1024 + kEmitPools - 1) / kEmitPools);
+        per = std::min<uint64_t>(per, kOvMaxBytes / sizeof(OvEnt) / kEmitPools);
         // test hook: C3X_DEBUG_OVERFLOW_SLOTS=k gives each region k slots (0: none,
         // every match goes through the write pass)
         if (const char *ev = getenv("C3X_DEBUG_OVERFLOW_SLOTS"))
@@ -2035,7 +2086,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         for (int q = 0; q < kEmitPools; ++q) need = std::max<uint64_t>(need, hoctr[q * kEmitPoolStride]);
         const uint64_t obs = need * kEmitPools * 1024 * 5 / 4 / (uint64_t)nA;
         const uint64_t old = g_ov_hint.load(std::memory_order_relaxed);
-        g_ov_hint.store(std::min<uint64_t>(std::max(obs, old / 2), 64 * 1024),
+        g_ov_hint.store(std::min<uint64_t>(std::max(obs, old / 2), 1024 * 1024),
                         std::memory_order_relaxed);
     }
     uint32_t ov_used = 0;
