@@ -9,8 +9,9 @@
 //   k_prep_b    validate rows, key + row index          16 B in, 8 B out
 //   radix sort  (key, row) by key, ceil(bits/8) passes   16 B per pass
 //   k_gather_b  payload in sorted order                   16 B in, 36/52 B out
-//   k_dir_hist  bucket histogram of key >> dshift, then an exclusive scan:
-//               dir[q] = number of keys in buckets below q
+//   k_dir_fill  dir[q] = number of keys in buckets below q, written straight
+//               from the sorted keys: each position fills the buckets between
+//               its predecessor's and its own (long gaps by k_dir_fill_gaps)
 #include <math.h>
 #include <string.h>
 
@@ -222,23 +223,37 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
     }
 }
 
-// Bucket histogram over the sorted keys: lanes holding the same bucket are
-// adjacent, so each run is added once by its first lane.
-__global__ void k_dir_hist(const uint32_t *__restrict__ keys, int64_t n, int dshift,
-                           uint32_t *__restrict__ cnt)
+// The directory from the sorted keys: position s (0 <= s <= n; s = n stands
+// for the end) is the first key of every bucket q with bucket(keys[s-1]) < q
+// <= bucket(keys[s]) (the end: every bucket up to dsize - 1), so it writes
+// dir[q] = s for those q. Gaps of more than kDirGap buckets are listed
+// (first, last, s) for k_dir_fill_gaps, so that no lane walks a long
+// stretch of empty sky.
+constexpr uint32_t kDirGap = 64;
+
+__global__ void k_dir_fill(const uint32_t *__restrict__ keys, int64_t n, int dshift,
+                           uint32_t dsize, uint32_t *__restrict__ dir, uint3 *__restrict__ gaps,
+                           uint32_t *__restrict__ n_gaps, uint32_t gap_cap)
 {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = s < n;
-    uint32_t q = valid ? keys[s] >> dshift : 0xffffffffu;
-    uint32_t prev = __shfl_up(q, 1);
-    unsigned lane = __lane_id();
-    bool lead = valid && (lane == 0 || prev != q);
-    uint64_t L = __ballot(lead);
-    uint64_t V = __ballot(valid);
-    if (lead) {
-        uint64_t after = lane == 63 ? 0ull : (L >> (lane + 1)) << (lane + 1);
-        unsigned end = after ? (unsigned)__ffsll((long long)after) - 1 : (unsigned)(64 - __clzll((long long)V));
-        atomicAdd(&cnt[q], end - lane);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > n) return;
+    const int64_t hi = t < n ? (int64_t)(keys[t] >> dshift) : (int64_t)dsize - 1;
+    const int64_t lo = t > 0 ? (int64_t)(keys[t - 1] >> dshift) : -1;
+    if (hi - lo <= (int64_t)kDirGap) {
+        for (int64_t q = lo + 1; q <= hi; ++q) dir[q] = (uint32_t)t;
+    } else {
+        const uint32_t slot = atomicAdd(n_gaps, 1u);
+        if (slot < gap_cap) gaps[slot] = make_uint3((uint32_t)(lo + 1), (uint32_t)hi, (uint32_t)t);
+    }
+}
+
+__global__ void k_dir_fill_gaps(const uint3 *__restrict__ gaps, const uint32_t *__restrict__ n_gaps,
+                                uint32_t gap_cap, uint32_t *__restrict__ dir)
+{
+    const uint32_t ng = min(*n_gaps, gap_cap);
+    for (uint32_t g = blockIdx.x; g < ng; g += gridDim.x) {
+        const uint3 v = gaps[g];
+        for (uint32_t q = v.x + threadIdx.x; q <= v.y && q >= v.x; q += blockDim.x) dir[q] = v.z;
     }
 }
 
@@ -328,9 +343,11 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     p64 = ix->mem.get_n<Pay64>(n);
     if (o.precision == C3X_MIXED) p32 = ix->mem.get_n<Pay32>(n);
     uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
-    uint32_t *dcnt = tmp.get_n<uint32_t>(ix->plan.dsize);
-    void *dws = tmp.get(scan_ws_bytes(ix->plan.dsize));
-    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !radec || !dir || !dcnt || !dws ||
+    // every gap listed spans more than kDirGap buckets
+    const uint32_t gap_cap = ix->plan.dsize / kDirGap + 2;
+    uint3 *gaps = tmp.get_n<uint3>(gap_cap);
+    uint32_t *n_gaps = tmp.get_n<uint32_t>(1);
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !radec || !dir || !gaps || !n_gaps ||
         !p64 || (o.precision == C3X_MIXED && !p32)) {
         (void)hipStreamSynchronize(s);
         delete ix;
@@ -359,11 +376,14 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
                                packed, n, g, p64, p32, radec);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipMemsetAsync(dcnt, 0, (size_t)ix->plan.dsize * 4, s);
-    if (e == hipSuccess && n > 0)
-        hipLaunchKernelGGL(k_dir_hist, dim3(nblk(n, 256)), dim3(256), 0, s, keys, n,
-                           ix->plan.dshift, dcnt);
-    if (e == hipSuccess) e = scan_u32(dcnt, dir, ix->plan.dsize, nullptr, dws, s);
+    if (e == hipSuccess) e = hipMemsetAsync(n_gaps, 0, sizeof(uint32_t), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_dir_fill, dim3(nblk(n + 1, 256)), dim3(256), 0, s, keys, n,
+                           ix->plan.dshift, ix->plan.dsize, dir, gaps, n_gaps, gap_cap);
+        hipLaunchKernelGGL(k_dir_fill_gaps, dim3(std::min<uint32_t>(gap_cap, 8192)), dim3(256), 0,
+                           s, gaps, n_gaps, gap_cap, dir);
+        e = hipGetLastError();
+    }
     tm.mark();
     uint32_t bad_h = 0xffffffffu;
     uint32_t *hbad = (uint32_t *)pinned_stage(64);
