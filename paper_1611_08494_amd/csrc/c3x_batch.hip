@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "c3x_batch_kernels.h"
+#include "c3x_dir.h"
 
 namespace c3x {
 
@@ -390,26 +391,6 @@ __global__ void k_blocal_best(const BJob *__restrict__ jobs, const uint32_t *__r
     best[a] = (int32_t)((uint32_t)best[a] - jb.b_ent);
 }
 
-// Directory counts over the sorted B keys (one atomic per run of equal
-// buckets in a wavefront).
-__global__ void k_bdir_hist(const uint32_t *__restrict__ keys, int64_t n, int dshift,
-                            uint32_t *__restrict__ cnt)
-{
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = s < n;
-    const uint32_t q = valid ? keys[s] >> dshift : 0xffffffffu;
-    const uint32_t prev = (uint32_t)__shfl_up((int)q, 1);
-    const unsigned lane = __lane_id();
-    const bool lead = valid && (lane == 0 || prev != q);
-    const uint64_t L = __ballot(lead), V = __ballot(valid);
-    if (lead) {
-        const uint64_t after = lane == 63 ? 0ull : (L >> (lane + 1)) << (lane + 1);
-        const unsigned end = after ? (unsigned)__ffsll((long long)after) - 1
-                                   : (unsigned)(64 - __clzll((long long)V));
-        atomicAdd(&cnt[q], end - lane);
-    }
-}
-
 // New best of a row the host ranked: job-local index and separation.
 __global__ void k_bpatch(const uint32_t *__restrict__ pos, const uint32_t *__restrict__ bj,
                          uint32_t n, const uint32_t *__restrict__ aidx,
@@ -464,8 +445,9 @@ struct c3x_batch {
     Pay32 *p32 = nullptr;
     double2 *radecB = nullptr;
     double2 *packA = nullptr, *packB = nullptr;  // entry-order coordinates
-    uint32_t *dir = nullptr, *dcnt = nullptr;
-    void *dws = nullptr;
+    uint32_t *dir = nullptr;
+    uint3 *gaps = nullptr;  // directory gaps longer than kDirGap buckets
+    uint32_t *n_gaps = nullptr, gap_cap = 0;
     int key_bits = 32;
     Grid g{};
     // A
@@ -622,13 +604,13 @@ static hipError_t batch_front(c3x_batch *b)
     if (NB > 0)
         hipLaunchKernelGGL(k_bgather_b, dim3(nblk(NB, 256)), dim3(256), 0, s, srows, b->djobs,
                            b->ejobB, b->packB, NB, b->p64, b->p32, b->radecB);
-    hipLaunchKernelGGL(k_bfill, dim3(nblk(b->g.dsize, 256)), dim3(256), 0, s, b->dcnt,
-                       (int64_t)b->g.dsize, 0u);
-    if (NB > 0)
-        hipLaunchKernelGGL(k_bdir_hist, dim3(nblk(NB, 256)), dim3(256), 0, s, skeys, NB,
-                           b->g.dshift, b->dcnt);
-    e = scan_u32(b->dcnt, b->dir, b->g.dsize, nullptr, b->dws, s);
-    if (e != hipSuccess) return e;
+    // the directory straight from the sorted keys (the gap counter cleared by
+    // a kernel: this runs inside the graph)
+    hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, b->n_gaps, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_dir_fill, dim3(nblk(NB + 1, 256)), dim3(256), 0, s, skeys, NB,
+                       b->g.dshift, b->g.dsize, b->dir, b->gaps, b->n_gaps, b->gap_cap);
+    hipLaunchKernelGGL(k_dir_fill_gaps, dim3(std::min<uint32_t>(b->gap_cap, 8192)), dim3(256), 0,
+                       s, b->gaps, b->n_gaps, b->gap_cap, b->dir);
     // A: keys, sort, records and candidate ranges
     if (NA > 0)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NA, 256)), dim3(256), 0, s, b->djobs, b->ejobA,
@@ -997,8 +979,9 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->packA = M.get_n<double2>(std::max<int64_t>(NA, 1));
     const int64_t dmax = std::max<int64_t>(1024, 2 * NB) + 2;
     b->dir = M.get_n<uint32_t>(dmax);
-    b->dcnt = M.get_n<uint32_t>(dmax);
-    b->dws = M.get(scan_ws_bytes(dmax));
+    b->gap_cap = (uint32_t)(dmax / kDirGap + 2);
+    b->gaps = M.get_n<uint3>(b->gap_cap);
+    b->n_gaps = M.get_n<uint32_t>(1);
     b->ak = M.get_n<uint32_t>(NA);
     b->av = M.get_n<uint32_t>(NA);
     b->ak2 = M.get_n<uint32_t>(NA);
@@ -1040,7 +1023,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->joboff = M.get_n<int64_t>(nj + 1);
     bool ok = b->bk && b->bv && b->bk2 && b->bv2 && b->bws && b->p64 &&
               (b->prec != C3X_MIXED || b->p32) && b->radecB && b->packA && b->packB &&
-              b->dir && b->dcnt && b->dws &&
+              b->dir && b->gaps && b->n_gaps &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
               b->arng && b->cnts && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
               b->hl && b->xent && b->pos && b->unc && b->d_hin && b->d_vi && b->d_vk &&

@@ -22,6 +22,7 @@
 #include <mutex>
 #include <vector>
 
+#include "c3x_dir.h"
 #include "c3x_host.h"
 #include "c3x_sort.h"
 
@@ -220,40 +221,6 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
         q.z = (float)(z - rz);
         q.idx = row | ((st & 1u) << 31);  // the step's parity: a window spans at most two
         p32[s] = q;
-    }
-}
-
-// The directory from the sorted keys: position s (0 <= s <= n; s = n stands
-// for the end) is the first key of every bucket q with bucket(keys[s-1]) < q
-// <= bucket(keys[s]) (the end: every bucket up to dsize - 1), so it writes
-// dir[q] = s for those q. Gaps of more than kDirGap buckets are listed
-// (first, last, s) for k_dir_fill_gaps, so that no lane walks a long
-// stretch of empty sky.
-constexpr uint32_t kDirGap = 64;
-
-__global__ void k_dir_fill(const uint32_t *__restrict__ keys, int64_t n, int dshift,
-                           uint32_t dsize, uint32_t *__restrict__ dir, uint3 *__restrict__ gaps,
-                           uint32_t *__restrict__ n_gaps, uint32_t gap_cap)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > n) return;
-    const int64_t hi = t < n ? (int64_t)(keys[t] >> dshift) : (int64_t)dsize - 1;
-    const int64_t lo = t > 0 ? (int64_t)(keys[t - 1] >> dshift) : -1;
-    if (hi - lo <= (int64_t)kDirGap) {
-        for (int64_t q = lo + 1; q <= hi; ++q) dir[q] = (uint32_t)t;
-    } else {
-        const uint32_t slot = atomicAdd(n_gaps, 1u);
-        if (slot < gap_cap) gaps[slot] = make_uint3((uint32_t)(lo + 1), (uint32_t)hi, (uint32_t)t);
-    }
-}
-
-__global__ void k_dir_fill_gaps(const uint3 *__restrict__ gaps, const uint32_t *__restrict__ n_gaps,
-                                uint32_t gap_cap, uint32_t *__restrict__ dir)
-{
-    const uint32_t ng = min(*n_gaps, gap_cap);
-    for (uint32_t g = blockIdx.x; g < ng; g += gridDim.x) {
-        const uint3 v = gaps[g];
-        for (uint32_t q = v.x + threadIdx.x; q <= v.y && q >= v.x; q += blockDim.x) dir[q] = v.z;
     }
 }
 
