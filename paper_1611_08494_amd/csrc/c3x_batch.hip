@@ -162,12 +162,12 @@ __global__ void k_bext(const BJob *__restrict__ jobs, const uint32_t *__restrict
     atomicMax(&ext[j], (unsigned long long)__double_as_longlong(ang));
 }
 
-// Cell key of every entry, with the entry number as value. Entries outside
+// Cell key of every entry (its value in the sort: the entry number). Entries outside
 // their job's planned box are reported (the plan no longer fits the data).
 __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restrict__ ejob,
                         const double *__restrict__ ra, const double *__restrict__ dec, int64_t n,
-                        bool isB, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                        double2 *__restrict__ packed, uint32_t *__restrict__ flags)
+                        bool isB, uint32_t *__restrict__ keys, double2 *__restrict__ packed,
+                        uint32_t *__restrict__ flags)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -189,7 +189,6 @@ __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restric
         atomicOr(flags, kBFlagStale);
     const uint32_t r = clampu(tr, jb.nrow), c = clampu(tc, jb.ncol);
     keys[e] = jb.key_base + r * jb.ncol + c;
-    vals[e] = (uint32_t)e;
 }
 
 // Sorted B payloads: FP64 unit vector, FP32 offset from the job centre, the
@@ -593,10 +592,10 @@ static hipError_t batch_front(c3x_batch *b)
     const int64_t NB = b->NB, NA = b->NA;
     if (NB > 0)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NB, 256)), dim3(256), 0, s, b->djobs, b->ejobB,
-                           b->raB, b->decB, NB, true, b->bk, b->bv, b->packB, b->ctr);
+                           b->raB, b->decB, NB, true, b->bk, b->packB, b->ctr);
     int in_tmp = 0;
     hipError_t e = radix_sort_pairs(b->bk, b->bv, b->bk2, b->bv2, NB, b->key_bits, b->bws, s,
-                                    &in_tmp);
+                                    &in_tmp, /*vals_are_index=*/true);
     if (e != hipSuccess) return e;
     const uint32_t *skeys = in_tmp ? b->bk2 : b->bk;
     const uint32_t *srows = in_tmp ? b->bv2 : b->bv;
@@ -614,12 +613,12 @@ static hipError_t batch_front(c3x_batch *b)
     // A: keys, sort, records and candidate ranges
     if (NA > 0)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NA, 256)), dim3(256), 0, s, b->djobs, b->ejobA,
-                           b->raA, b->decA, NA, false, b->ak, b->av, b->packA, b->ctr);
+                           b->raA, b->decA, NA, false, b->ak, b->packA, b->ctr);
     // A in the order of its top key bits (its order changes no result)
     // (a job's entries stay together: keys are job-major and the sort stable)
     const int a_lo = std::max(0, b->key_bits - kAKeyBits);
     e = radix_sort_pairs_bits(b->ak, b->av, b->ak2, b->av2, NA, a_lo, b->key_bits, b->aws, s,
-                              &in_tmp);
+                              &in_tmp, /*vals_are_index=*/true);
     if (e != hipSuccess) return e;
     const uint32_t *arows = in_tmp ? b->av2 : b->av;
     if (NA > 0)

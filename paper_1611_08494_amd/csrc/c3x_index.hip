@@ -169,8 +169,8 @@ c3x_status plan_grid(GridPlan &p, int64_t nB, double reach_arcsec, double cell_r
 // Keys of the B rows, and the coordinates packed in pairs so that the
 // gather after the sort reads one 16-byte record per row.
 __global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict__ dec, int64_t n,
-                         Grid g, uint32_t *__restrict__ keys, uint32_t *__restrict__ rows,
-                         double2 *__restrict__ packed, uint32_t *__restrict__ bad)
+                         Grid g, uint32_t *__restrict__ keys, double2 *__restrict__ packed,
+                         uint32_t *__restrict__ bad)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -184,8 +184,7 @@ __global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict
     }
     int z = zone_of(d, g);
     const ZoneInfo zi = g.zinfo[z];
-    keys[j] = zi.base + cell_in(zi, a);
-    rows[j] = (uint32_t)j;
+    keys[j] = zi.base + cell_in(zi, a);  // its value in the sort: the row j itself
 }
 
 template <int PREC>
@@ -325,11 +324,12 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     g.nB = (int32_t)n;
     if (n > 0)
         hipLaunchKernelGGL(k_prep_b, dim3(nblk(n, 256)), dim3(256), 0, s, ra_deg, dec_deg, n, g,
-                           keys, rows, packed, bad);
+                           keys, packed, bad);
     int in_tmp = 0;
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess)
-        e = radix_sort_pairs(keys, rows, ktmp, rtmp, n, ix->plan.key_bits, ws, s, &in_tmp);
+        e = radix_sort_pairs(keys, rows, ktmp, rtmp, n, ix->plan.key_bits, ws, s, &in_tmp,
+                             /*vals_are_index=*/true);
     if (e == hipSuccess && in_tmp) {
         e = hipMemcpyAsync(keys, ktmp, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
         rows = rtmp;

@@ -67,8 +67,8 @@ using PayOf = typename std::conditional<PREC == C3X_FP64, Pay64, Pay32>::type;
 __global__ void k_prep_a(const double *__restrict__ ra, const double *__restrict__ dec, int64_t n,
                          Grid g, int shape, const double *__restrict__ sa,
                          const double *__restrict__ sb, const double *__restrict__ pa,
-                         uint32_t *__restrict__ keys, uint32_t *__restrict__ rows,
-                         double2 *__restrict__ packed, uint32_t *__restrict__ bad)
+                         uint32_t *__restrict__ keys, double2 *__restrict__ packed,
+                         uint32_t *__restrict__ bad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -87,8 +87,7 @@ __global__ void k_prep_a(const double *__restrict__ ra, const double *__restrict
     }
     int z = zone_of(d, g);
     const ZoneInfo zi = g.zinfo[z];
-    keys[i] = zi.base + cell_in(zi, a);
-    rows[i] = (uint32_t)i;
+    keys[i] = zi.base + cell_in(zi, a);  // its value in the sort: the row i itself
 }
 
 // Margin on the ellipse form Q for a filter whose tangent-plane components
@@ -1890,7 +1889,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     const double *sa = area->semi_major_arcsec, *sb = area->semi_minor_arcsec, *pa = area->pa_deg;
     if (nA > 0)
         hipLaunchKernelGGL(k_prep_a, dim3(nblk(nA, 256)), dim3(256), 0, s, ra, dec, nA, ix->grid,
-                           shape, sa, sb, pa, keys, rows, packed, ctr);
+                           shape, sa, sb, pa, keys, packed, ctr);
     HIPCHK(hipGetLastError(), "A keys");
     int in_tmp = 0;
     // A is ordered by its top 24 key bits only (three passes): runs of up to
@@ -1898,7 +1897,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     // and no result depends on the order of A
     const int a_lo = std::max(0, ix->plan.key_bits - kAKeyBits);
     HIPCHK(radix_sort_pairs_bits(keys, rows, ktmp, rtmp, nA, a_lo, ix->plan.key_bits, ws, s,
-                                 &in_tmp),
+                                 &in_tmp, /*vals_are_index=*/true),
            "A sort");
     uint32_t *srows = in_tmp ? rtmp : rows;
     // rows with at least wide_min candidates (or a window walked cell by

@@ -9,14 +9,17 @@ namespace c3x {
 // Workspace for radix_sort_pairs over n elements.
 size_t radix_ws_bytes(int64_t n);
 // Stable LSD sort of (keys, vals) on the low nbits bits. The sorted data end
-// up in (keys, vals) if *in_tmp == 0 on return, else in (ktmp, vtmp).
+// up in (keys, vals) if *in_tmp == 0 on return, else in (ktmp, vtmp). With
+// vals_are_index the values are the elements' own indices 0..n-1 and vals
+// need not hold them (it is still the buffer the passes use).
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
-                            int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp);
+                            int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp,
+                            bool vals_are_index = false);
 // The same, ordering by key bits [lo_bit, nbits) only (stable: keys equal
 // in those bits keep their order).
 hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
                                  int64_t n, int lo_bit, int nbits, void *ws, hipStream_t s,
-                                 int *in_tmp);
+                                 int *in_tmp, bool vals_are_index = false);
 
 size_t scan_ws_bytes(int64_t n);
 // Exclusive scans; *total (device, may be NULL) receives the sum. The

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
     for (int r = 0; r < kRounds; ++r) {
         const int64_t e = wbase + r * 64;
         kk[r] = e < n ? kin[e] : 0u;
-        vv[r] = e < n ? vin[e] : 0u;
+        vv[r] = e < n ? (vin ? vin[e] : (uint32_t)e) : 0u;  // no vin: the index
     }
     __syncthreads();
     uint32_t *cnt = wc[wave];
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     for (int r = 0; r < kRounds; ++r) {
         const int64_t e = wbase + r * 64;
         kk[r] = e < n ? kin[e] : 0u;
-        vv[r] = e < n ? vin[e] : 0u;
+        vv[r] = e < n ? (vin ? vin[e] : (uint32_t)e) : 0u;  // no vin: the index
     }
     uint32_t *cnt = wc[wave];
 #pragma unroll
@@ -366,6 +366,12 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
             vout[dst] = sv[q];
         }
     }
+}
+
+__global__ void k_sort_iota(uint32_t *__restrict__ p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = (uint32_t)t;
 }
 
 __global__ void k_sort_clear(uint32_t *__restrict__ p, int64_t n)
@@ -545,17 +551,27 @@ size_t radix_ws_bytes(int64_t n)
 }
 
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
-                            int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp)
+                            int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp,
+                            bool vals_are_index)
 {
-    return radix_sort_pairs_bits(keys, vals, ktmp, vtmp, n, 0, nbits, ws, s, in_tmp);
+    return radix_sort_pairs_bits(keys, vals, ktmp, vtmp, n, 0, nbits, ws, s, in_tmp,
+                                 vals_are_index);
 }
 
 hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
                                  int64_t n, int lo_bit, int nbits, void *ws, hipStream_t s,
-                                 int *in_tmp)
+                                 int *in_tmp, bool vals_are_index)
 {
     *in_tmp = 0;
-    if (n <= 1 || nbits <= lo_bit) return hipSuccess;
+    if (n <= 0) return hipSuccess;
+    if (n == 1 || nbits <= lo_bit) {  // nothing to order: the values as they stand
+        if (vals_are_index)
+            hipLaunchKernelGGL(k_sort_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                               vals, n);
+        return hipGetLastError();
+    }
+    // the first pass reads no values when they are the elements' own indices
+    const uint32_t *vfirst = vals_are_index ? nullptr : vals;
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     // up to kRowScanTiles tiles, one workgroup per digit scans its row of the
     // table cheaply and the look-back's latency does not pay; above, the
@@ -574,8 +590,9 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
                            npass, ghist);
         uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
         for (int p = 0; p < npass; ++p) {
-            hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, va, kb,
-                               vb, n, lo_bit + 8 * p, ghist + 256 * p, tctr + p,
+            hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka,
+                               p == 0 ? vfirst : va, kb, vb, n, lo_bit + 8 * p, ghist + 256 * p,
+                               tctr + p,
                                status + (size_t)p * 256 * (size_t)nb, (int)nb);
             std::swap(ka, kb);
             std::swap(va, vb);
@@ -600,8 +617,9 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
         else
             e = scan_u32(hist, offs, 256 * nb, nullptr, sws, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka, va, kb,
-                           vb, n, shift, offs, rows ? tot : nullptr, hist, (int)nb);
+        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka,
+                           shift == lo_bit ? vfirst : va, kb, vb, n, shift, offs,
+                           rows ? tot : nullptr, hist, (int)nb);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint32_t *t = ka;
