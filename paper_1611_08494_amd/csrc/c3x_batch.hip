@@ -446,7 +446,7 @@ struct c3x_batch {
     double2 *packA = nullptr, *packB = nullptr;  // entry-order coordinates
     uint32_t *dir = nullptr;
     uint3 *gaps = nullptr;  // directory gaps longer than kDirGap buckets
-    uint32_t *n_gaps = nullptr, gap_cap = 0;
+    uint32_t *n_gaps = nullptr, gap_cap = 0, big_cap = 0;
     int key_bits = 32;
     Grid g{};
     // A
@@ -605,11 +605,12 @@ static hipError_t batch_front(c3x_batch *b)
                            b->ejobB, b->packB, NB, b->p64, b->p32, b->radecB);
     // the directory straight from the sorted keys (the gap counter cleared by
     // a kernel: this runs inside the graph)
-    hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, b->n_gaps, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, b->n_gaps, (int64_t)2, 0u);
     hipLaunchKernelGGL(k_dir_fill, dim3(nblk(NB + 1, 256)), dim3(256), 0, s, skeys, NB,
-                       b->g.dshift, b->g.dsize, b->dir, b->gaps, b->n_gaps, b->gap_cap);
-    hipLaunchKernelGGL(k_dir_fill_gaps, dim3(std::min<uint32_t>(b->gap_cap, 8192)), dim3(256), 0,
-                       s, b->gaps, b->n_gaps, b->gap_cap, b->dir);
+                       b->g.dshift, b->g.dsize, b->dir, b->gaps, b->n_gaps, b->gap_cap,
+                       b->big_cap);
+    hipLaunchKernelGGL(k_dir_fill_gaps, dim3(4096), dim3(256), 0, s, b->gaps, b->n_gaps,
+                       b->gap_cap, b->big_cap, b->dir);
     // A: keys, sort, records and candidate ranges
     if (NA > 0)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NA, 256)), dim3(256), 0, s, b->djobs, b->ejobA,
@@ -978,9 +979,10 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->packA = M.get_n<double2>(std::max<int64_t>(NA, 1));
     const int64_t dmax = std::max<int64_t>(1024, 2 * NB) + 2;
     b->dir = M.get_n<uint32_t>(dmax);
-    b->gap_cap = (uint32_t)(dmax / kDirGap + 2);
-    b->gaps = M.get_n<uint3>(b->gap_cap);
-    b->n_gaps = M.get_n<uint32_t>(1);
+    b->gap_cap = dir_gap_cap((uint32_t)dmax);
+    b->big_cap = dir_big_cap((uint32_t)dmax);
+    b->gaps = M.get_n<uint3>((int64_t)b->gap_cap + b->big_cap);
+    b->n_gaps = M.get_n<uint32_t>(2);
     b->ak = M.get_n<uint32_t>(NA);
     b->av = M.get_n<uint32_t>(NA);
     b->ak2 = M.get_n<uint32_t>(NA);

@@ -309,10 +309,9 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     p64 = ix->mem.get_n<Pay64>(n);
     if (o.precision == C3X_MIXED) p32 = ix->mem.get_n<Pay32>(n);
     uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
-    // every gap listed spans more than kDirGap buckets
-    const uint32_t gap_cap = ix->plan.dsize / kDirGap + 2;
-    uint3 *gaps = tmp.get_n<uint3>(gap_cap);
-    uint32_t *n_gaps = tmp.get_n<uint32_t>(1);
+    const uint32_t gap_cap = dir_gap_cap(ix->plan.dsize), big_cap = dir_big_cap(ix->plan.dsize);
+    uint3 *gaps = tmp.get_n<uint3>((int64_t)gap_cap + big_cap);
+    uint32_t *n_gaps = tmp.get_n<uint32_t>(2);
     if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !radec || !dir || !gaps || !n_gaps ||
         !p64 || (o.precision == C3X_MIXED && !p32)) {
         (void)hipStreamSynchronize(s);
@@ -343,12 +342,12 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
                                packed, n, g, p64, p32, radec);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipMemsetAsync(n_gaps, 0, sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(n_gaps, 0, 2 * sizeof(uint32_t), s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_dir_fill, dim3(nblk(n + 1, 256)), dim3(256), 0, s, keys, n,
-                           ix->plan.dshift, ix->plan.dsize, dir, gaps, n_gaps, gap_cap);
-        hipLaunchKernelGGL(k_dir_fill_gaps, dim3(std::min<uint32_t>(gap_cap, 8192)), dim3(256), 0,
-                           s, gaps, n_gaps, gap_cap, dir);
+                           ix->plan.dshift, ix->plan.dsize, dir, gaps, n_gaps, gap_cap, big_cap);
+        hipLaunchKernelGGL(k_dir_fill_gaps, dim3(4096), dim3(256), 0, s, gaps, n_gaps, gap_cap,
+                           big_cap, dir);
         e = hipGetLastError();
     }
     tm.mark();
