@@ -191,12 +191,11 @@ __global__ void k_bkeys(const BJob *__restrict__ jobs, const uint32_t *__restric
     keys[e] = jb.key_base + r * jb.ncol + c;
 }
 
-// Sorted B payloads: FP64 unit vector, FP32 offset from the job centre, the
-// coordinates; idx is the B entry.
+// Sorted B payloads: FP64 unit vector, FP32 offset from the job centre; idx
+// is the B entry (its coordinates stay in packB, in entry order).
 __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__restrict__ jobs,
                             const uint32_t *__restrict__ ejob, const double2 *__restrict__ packed,
-                            int64_t n, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
-                            double2 *__restrict__ radec)
+                            int64_t n, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32)
 {
     // a job's sorted entries take its own entries' places (keys are job-major),
     // and one XCD reads one job's rows
@@ -207,7 +206,6 @@ __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__res
     const BJob &jb = jobs[ejob[s]];
     const double2 ad = packed[e];
     const double a = ad.x, d = ad.y;
-    radec[s] = ad;
     double x, y, z;
     unit_vec(a, d, x, y, z);
     Pay64 q;
@@ -283,7 +281,7 @@ __global__ void k_bgather_a(const uint32_t *__restrict__ rows, const BJob *__res
 __global__ void k_brecheck(const uint2 *__restrict__ band, const uint32_t *__restrict__ n_band,
                            uint32_t cap, const double2 *__restrict__ arad,
                            const uint32_t *__restrict__ aidx, const uint32_t *__restrict__ ajob,
-                           const BJob *__restrict__ jobs, const double2 *__restrict__ radecB,
+                           const BJob *__restrict__ jobs, const double2 *__restrict__ coordB,
                            const Pay64 *__restrict__ p64, uint4 *__restrict__ bin,
                            uint32_t *__restrict__ n_bin, uint32_t bin_cap,
                            BAmb *__restrict__ hl, uint32_t *__restrict__ n_hl, uint32_t hl_cap,
@@ -293,7 +291,7 @@ __global__ void k_brecheck(const uint2 *__restrict__ band, const uint32_t *__res
     if (t >= min(*n_band, cap)) return;
     const uint2 q = band[t];
     const double2 ad = arad[q.x];
-    const double2 rb = radecB[q.y];
+    const double2 rb = coordB[p64[q.y].idx];
     const BJob &jb = jobs[ajob[q.x]];
     ARec a;
     a.ra = ad.x;
@@ -393,7 +391,7 @@ __global__ void k_blocal_best(const BJob *__restrict__ jobs, const uint32_t *__r
 // New best of a row the host ranked: job-local index and separation.
 __global__ void k_bpatch(const uint32_t *__restrict__ pos, const uint32_t *__restrict__ bj,
                          uint32_t n, const uint32_t *__restrict__ aidx,
-                         const double2 *__restrict__ arad, const double2 *__restrict__ radecB,
+                         const double2 *__restrict__ arad, const double2 *__restrict__ coordB,
                          const Pay64 *__restrict__ p64, const BJob *__restrict__ jobs,
                          const uint32_t *__restrict__ ajob, int32_t *__restrict__ best,
                          double *__restrict__ bsep)
@@ -404,7 +402,7 @@ __global__ void k_bpatch(const uint32_t *__restrict__ pos, const uint32_t *__res
     const uint32_t a = aidx[i];
     const BJob &jb = jobs[ajob[i]];
     best[a] = (int32_t)(p64[j].idx - jb.b_ent);
-    const double2 ra = arad[i], rb = radecB[j];
+    const double2 ra = arad[i], rb = coordB[p64[j].idx];
     bsep[a] = sep_arcsec_rd(ra.x, ra.y, rb.x, rb.y);
 }
 
@@ -442,7 +440,7 @@ struct c3x_batch {
     void *bws = nullptr;
     Pay64 *p64 = nullptr;
     Pay32 *p32 = nullptr;
-    double2 *radecB = nullptr;
+    double2 *coordB = nullptr;  // B coordinates in entry order (packB)
     double2 *packA = nullptr, *packB = nullptr;  // entry-order coordinates
     uint32_t *dir = nullptr;
     uint3 *gaps = nullptr;  // directory gaps longer than kDirGap buckets
@@ -545,7 +543,7 @@ static MatchArgs batch_args(c3x_batch *b)
     m.g = b->g;
     m.pay64 = b->p64;
     m.pay32 = b->p32;
-    m.radecB = b->radecB;
+    m.coordB = b->coordB;
     m.arad = b->arad;
     m.aidx = b->aidx;
     m.arng = b->arng;
@@ -602,7 +600,7 @@ static hipError_t batch_front(c3x_batch *b)
     b->g.keys = skeys;
     if (NB > 0)
         hipLaunchKernelGGL(k_bgather_b, dim3(nblk(NB, 256)), dim3(256), 0, s, srows, b->djobs,
-                           b->ejobB, b->packB, NB, b->p64, b->p32, b->radecB);
+                           b->ejobB, b->packB, NB, b->p64, b->p32);
     // the directory straight from the sorted keys (the gap counter cleared by
     // a kernel: this runs inside the graph)
     hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, b->n_gaps, (int64_t)2, 0u);
@@ -639,7 +637,7 @@ static hipError_t batch_front(c3x_batch *b)
     }
     // band candidates: FP64 recheck, then the host decides what is left
     hipLaunchKernelGGL(k_brecheck, dim3(nblk(b->amb_cap, 256)), dim3(256), 0, s, b->amb,
-                       b->ctr + 1, b->amb_cap, b->arad, b->aidx, b->ajob, b->djobs, b->radecB,
+                       b->ctr + 1, b->amb_cap, b->arad, b->aidx, b->ajob, b->djobs, b->coordB,
                        b->p64, b->bin, b->ctr + 8, b->bin_cap, b->hl, b->ctr + 9, b->hl_cap,
                        b->ctr);
     e = hipMemcpyAsync(b->h_cnt, b->ctr + 9, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
@@ -691,7 +689,8 @@ static hipError_t batch_back(c3x_batch *b)
                            b->ovl, b->ov_pool, b->octr, NA, b->off, b->P_cap, b->pt, b->c64 + 2,
                            b->ctr + 4);
     hipLaunchKernelGGL(k_place_x, dim3(nblk(b->bin_cap, 256)), dim3(256), 0, s, b->xent,
-                       b->bin_cap, b->ctr + 8, b->aidx, b->arad, b->radecB, NA, b->NB, b->off,
+                       b->bin_cap, b->ctr + 8, b->aidx, b->arad, b->coordB, b->p64, NA, b->NB,
+                       b->off,
                        b->P_cap, b->rec, 1, b->pt, b->c64 + 2, b->ctr + 4);
     FinishArgs fa{};
     fa.nA = NA;
@@ -704,7 +703,8 @@ static hipError_t batch_back(c3x_batch *b)
     fa.tmp = b->pt;
     fa.raA = nullptr;
     fa.decA = nullptr;
-    fa.radecB = b->radecB;
+    fa.coordB = b->coordB;
+    fa.payB = b->p64;
     fa.best_idx = b->obest;
     fa.oa = b->oa;
     fa.ob = b->ob;
@@ -974,8 +974,8 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->bws = M.get(radix_ws_bytes(NB));
     b->p64 = M.get_n<Pay64>(NB);
     if (b->prec == C3X_MIXED) b->p32 = M.get_n<Pay32>(NB);
-    b->radecB = M.get_n<double2>(NB);
     b->packB = M.get_n<double2>(std::max<int64_t>(NB, 1));
+    b->coordB = b->packB;  // B coordinates in entry order, reached through p64[j].idx
     b->packA = M.get_n<double2>(std::max<int64_t>(NA, 1));
     const int64_t dmax = std::max<int64_t>(1024, 2 * NB) + 2;
     b->dir = M.get_n<uint32_t>(dmax);
@@ -1023,7 +1023,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->obsep = M.get_n<double>(NA);
     b->joboff = M.get_n<int64_t>(nj + 1);
     bool ok = b->bk && b->bv && b->bk2 && b->bv2 && b->bws && b->p64 &&
-              (b->prec != C3X_MIXED || b->p32) && b->radecB && b->packA && b->packB &&
+              (b->prec != C3X_MIXED || b->p32) && b->coordB && b->packA && b->packB &&
               b->dir && b->gaps && b->n_gaps &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
               b->arng && b->cnts && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
@@ -1208,7 +1208,7 @@ static c3x_status batch_finish(c3x_batch *b)
         BCHK(hipMemcpyAsync(d1, prow.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
         BCHK(hipMemcpyAsync(d2, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
         hipLaunchKernelGGL(k_bpatch, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, np, b->aidx,
-                           b->arad, b->radecB, b->p64, b->djobs, b->ajob, b->obest, b->obsep);
+                           b->arad, b->coordB, b->p64, b->djobs, b->ajob, b->obest, b->obsep);
         BCHK(hipGetLastError(), "best patch");
         BCHK(hipStreamSynchronize(s), "best patch");
     }

@@ -138,7 +138,7 @@ struct c3x_index {
     uint32_t *keys = nullptr;
     c3x::Pay64 *pay64 = nullptr;
     c3x::Pay32 *pay32 = nullptr;
-    double2 *radec = nullptr;
+    double2 *radec = nullptr;  // B coordinates in input order (row pay64[j].idx)
     c3x_stats stats;
 };
 

@@ -189,8 +189,7 @@ __global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict
 
 template <int PREC>
 __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__restrict__ packed,
-                           int64_t n, Grid g, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
-                           double2 *__restrict__ radec)
+                           int64_t n, Grid g, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -198,7 +197,6 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
     if (row >= (uint64_t)n) row = 0;  // unreachable for a permutation; keeps reads in bounds
     const double2 rd = packed[row];
     const double a = rd.x, d = rd.y;
-    radec[s] = rd;
     double x, y, z;
     unit_vec(a, d, x, y, z);
     Pay64 q8;
@@ -300,8 +298,9 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     uint32_t *rtmp = tmp.get_n<uint32_t>(n);
     void *ws = tmp.get(radix_ws_bytes(n));
     uint32_t *bad = tmp.get_n<uint32_t>(1);
-    double2 *packed = tmp.get_n<double2>(n);
-    double2 *radec = ix->mem.get_n<double2>(n);
+    // the coordinates in input order: the gathers' source, then kept by the
+    // index (the rare paths reach them through pay64[j].idx)
+    double2 *packed = ix->mem.get_n<double2>(n);
     Pay64 *p64 = nullptr;
     Pay32 *p32 = nullptr;
     // FP64 unit vectors for both paths (the mixed path's matches take their
@@ -312,7 +311,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     const uint32_t gap_cap = dir_gap_cap(ix->plan.dsize), big_cap = dir_big_cap(ix->plan.dsize);
     uint3 *gaps = tmp.get_n<uint3>((int64_t)gap_cap + big_cap);
     uint32_t *n_gaps = tmp.get_n<uint32_t>(2);
-    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !radec || !dir || !gaps || !n_gaps ||
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !dir || !gaps || !n_gaps ||
         !p64 || (o.precision == C3X_MIXED && !p32)) {
         (void)hipStreamSynchronize(s);
         delete ix;
@@ -336,10 +335,10 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     if (e == hipSuccess && n > 0) {
         if (o.precision == C3X_FP64)
             hipLaunchKernelGGL(k_gather_b<C3X_FP64>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
-                               packed, n, g, p64, p32, radec);
+                               packed, n, g, p64, p32);
         else
             hipLaunchKernelGGL(k_gather_b<C3X_MIXED>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
-                               packed, n, g, p64, p32, radec);
+                               packed, n, g, p64, p32);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemsetAsync(n_gaps, 0, 2 * sizeof(uint32_t), s);
@@ -372,7 +371,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     ix->keys = keys;
     ix->pay64 = p64;
     ix->pay32 = p32;
-    ix->radec = radec;
+    ix->radec = packed;
     ix->grid.keys = keys;
     ix->grid.dir = dir;
     ix->grid.nB = (int32_t)n;

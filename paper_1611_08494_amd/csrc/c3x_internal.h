@@ -5,7 +5,8 @@
 //   pay64[nB]  {f64 x, y, z; u32 idx; u32 pad}   FP64 unit vector (32 B)
 //   pay32[nB]  {f32 dx, dy, dz; u32 idx}          FP32 offset from the cell's
 //                                                 reference vector (16 B)
-//   radec[nB]  {f64 ra, dec}                      original coordinates
+//   radec[nB]  {f64 ra, dec}                      coordinates in input order
+//                                                 (sorted position j: row pay64[j].idx)
 //   dir[Q+1]   u32   dir[q] = #keys with (key >> dshift) < q
 // Catalogue A is keyed on the same grid and sorted, so a wavefront of
 // threads covers neighbouring sky and reads neighbouring cells of B.
@@ -182,7 +183,7 @@ struct MatchArgs {
     Grid g;
     const Pay64 *pay64;
     const Pay32 *pay32;
-    const double2 *radecB;
+    const double2 *coordB;
     const double2 *arad;   // sorted A coordinates
     const uint32_t *aidx;  // sorted A rows
     const AEll *aell;

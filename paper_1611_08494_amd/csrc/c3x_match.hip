@@ -417,7 +417,7 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
         }
     }
     if constexpr (SHAPE == C3X_CIRCLE) {
-        if (th.r_zero) d = same_point(a, m.radecB[j]) ? IN : OUT;
+        if (th.r_zero) d = same_point(a, m.coordB[m.pay64[j].idx]) ? IN : OUT;
     }
     return d;
 }
@@ -447,8 +447,8 @@ __device__ __forceinline__ int band_verdict(const MatchArgs &m, uint32_t i, uint
     ARec q = a;
     q.cosd = cos_dec_acc(a.dec);
     int d;
-    if constexpr (SHAPE == C3X_ELLIPSE) d = recheck_ellipse(q, m.aellr[i], m.radecB[j]);
-    else d = recheck_circle(q, m.radecB[j], BATCH ? m.jobs[m.ajob[i]].h_r : m.h_r);
+    if constexpr (SHAPE == C3X_ELLIPSE) d = recheck_ellipse(q, m.aellr[i], m.coordB[m.pay64[j].idx]);
+    else d = recheck_circle(q, m.coordB[m.pay64[j].idx], BATCH ? m.jobs[m.ajob[i]].h_r : m.h_r);
     if (d != AMBIG) return d;
     return verdict(m, i, j);
 }
@@ -989,7 +989,7 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
             if (slot < m.col_cap) {
-                double2 rb = m.radecB[j];
+                double2 rb = m.coordB[m.pay64[j].idx];
                 ColEnt ce;
                 ce.t = t;
                 ce.idxB = pay_row(b);
@@ -1126,7 +1126,7 @@ template <int SHAPE>
 __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__restrict__ n_band,
                           uint32_t cap, const double2 *__restrict__ arad,
                           const uint32_t *__restrict__ aidx, const AEllR *__restrict__ aellr,
-                          const double2 *__restrict__ radecB, const Pay64 *__restrict__ p64,
+                          const double2 *__restrict__ coordB, const Pay64 *__restrict__ p64,
                           const Pay32 *__restrict__ p32, double h_r, const double *__restrict__ sa,
                           const double *__restrict__ sb, const double *__restrict__ pa,
                           uint4 *__restrict__ in, uint32_t *__restrict__ n_in,
@@ -1137,7 +1137,7 @@ __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__rest
     uint2 q = band[t];
     double2 ad = arad[q.x];
     uint32_t row = aidx[q.x];
-    double2 rb = radecB[q.y];
+    double2 rb = coordB[p64[q.y].idx];
     ARec a;
     a.ra = ad.x;
     a.dec = ad.y;
@@ -1251,7 +1251,8 @@ __global__ void k_place_ov(const OvEnt *__restrict__ ovl, uint32_t ov_pool,
 __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
                           const uint32_t *__restrict__ nx_dev,
                           const uint32_t *__restrict__ aidx, const double2 *__restrict__ arad,
-                          const double2 *__restrict__ radecB, int64_t nA, int64_t nB,
+                          const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
+                          int64_t nA, int64_t nB,
                           const int64_t *__restrict__ off, int64_t P, RowRec *__restrict__ rec,
                           int use_rec, PairTmp *__restrict__ tmp,
                           unsigned long long *__restrict__ placed,
@@ -1271,7 +1272,7 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
         atomicOr(err, 1u);
         return;
     }
-    const double2 ra = arad[e.i], rb = radecB[e.j];
+    const double2 ra = arad[e.i], rb = coordB[payB[e.j].idx];
     PairTmp x;
     x.idxB = e.idxB;
     x.j = e.j;
@@ -1346,7 +1347,8 @@ __device__ __forceinline__ double theta_small(double c2)
 }
 
 __device__ __noinline__ double decode_rare(double code, double raA, double decA,
-                                           const double2 *__restrict__ radecB, int64_t nB,
+                                           const double2 *__restrict__ coordB,
+                                           const Pay64 *__restrict__ payB, int64_t nB,
                                            uint32_t *__restrict__ err)
 {
     if (code < 0.0) return 2.0 * asin(0.5 * sqrt(-code)) * (180.0 / kPi * 3600.0);
@@ -1355,7 +1357,7 @@ __device__ __noinline__ double decode_rare(double code, double raA, double decA,
         atomicOr(err, 16u);
         return NAN;
     }
-    const double2 rb = radecB[j];
+    const double2 rb = coordB[payB[j].idx];
     return sep_arcsec_rd(raA, decA, rb.x, rb.y);
 }
 
@@ -1367,7 +1369,8 @@ template <bool RARE>
 __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp &x, int64_t nB,
                                             const double *__restrict__ raA,
                                             const double *__restrict__ decA,
-                                            const double2 *__restrict__ radecB, int32_t best,
+                                            const double2 *__restrict__ coordB,
+                                            const Pay64 *__restrict__ payB, int32_t best,
                                             int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                                             double *__restrict__ os, double *__restrict__ bsep,
                                             uint32_t *__restrict__ err)
@@ -1375,7 +1378,7 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
     double s = x.sep;
     if (!(s >= 0.0)) {
         if (s > -0.01) s = theta_small(-s);
-        else if (RARE) s = decode_rare(s, raA[a], decA[a], radecB, nB, err);
+        else if (RARE) s = decode_rare(s, raA[a], decA[a], coordB, payB, nB, err);
         else atomicOr(err, 32u);
     }
     oa[q] = (int32_t)a;
@@ -1395,7 +1398,8 @@ template <bool RARE>
 __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *__restrict__ off,
                            const RowRec *__restrict__ rec, int use_rec, PairTmp *__restrict__ tmp,
                            const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ radecB, int32_t *__restrict__ best_idx,
+                           const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
+                           int32_t *__restrict__ best_idx,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                            double *__restrict__ os, double *__restrict__ bsep,
                            uint32_t *__restrict__ err)
@@ -1432,7 +1436,7 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
         return rk;
     };
     auto put = [&](const PairTmp &x) {
-        final_write<RARE>(o + rank_of(x.idxB), a, x, nB, raA, decA, radecB, r.best, oa, ob, os,
+        final_write<RARE>(o + rank_of(x.idxB), a, x, nB, raA, decA, coordB, payB, r.best, oa, ob, os,
                           bsep, err);
     };
     if (nt > 0) put(x0);
@@ -1443,7 +1447,8 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
 // the compacted (idxA, idxB, sep) pair.
 __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec,
                            const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ radecB, int32_t *__restrict__ bidx,
+                           const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
+                           int32_t *__restrict__ bidx,
                            double *__restrict__ bsep, const int64_t *__restrict__ off, int64_t P,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                            double *__restrict__ os, uint32_t *__restrict__ err)
@@ -1461,7 +1466,7 @@ __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec
         atomicOr(err, 16u);
         return;
     }
-    double2 rb = radecB[bj];
+    double2 rb = coordB[payB[bj].idx];
     double s = sep_arcsec_rd(raA[t], decA[t], rb.x, rb.y);
     bsep[t] = s;
     if (off) {
@@ -1502,7 +1507,8 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                                                  int64_t pcap,
                                                  const double *__restrict__ raA,
                                                  const double *__restrict__ decA,
-                                                 const double2 *__restrict__ radecB,
+                                                 const double2 *__restrict__ coordB,
+                                                 const Pay64 *__restrict__ payB,
                                                  const RowRec *__restrict__ rec,
                                                  int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                                                  double *__restrict__ os, double *__restrict__ bsep,
@@ -1547,7 +1553,7 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
         }
         const int32_t best = rec[a].best;
         for (int k = threadIdx.x; k < len; k += blockDim.x)
-            final_write<RARE>(o + k, a, tmp[o + (uint32_t)v[k]], nB, raA, decA, radecB, best, oa,
+            final_write<RARE>(o + k, a, tmp[o + (uint32_t)v[k]], nB, raA, decA, coordB, payB, best, oa,
                               ob, os, bsep, err);
         __syncthreads();  // v is reused by the next segment
     }
@@ -1564,7 +1570,8 @@ struct FinishArgs {
     int use_rec, rare;
     PairTmp *tmp;
     const double *raA, *decA;
-    const double2 *radecB;
+    const double2 *coordB;  // B coordinates in input order
+    const Pay64 *payB;      // sorted B payloads: payB[j].idx is B's input row
     int32_t *best_idx;
     int32_t *oa, *ob;
     double *os, *bsep;
@@ -1584,12 +1591,13 @@ static void finish_segments(const FinishArgs &f, hipStream_t s)
 #define C3X_FIN(R)                                                                                \
     do {                                                                                          \
         hipLaunchKernelGGL(k_finalize<R>, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB,      \
-                           f.pcap, f.off, f.rec, f.use_rec, f.tmp, f.raA, f.decA, f.radecB,       \
+                           f.pcap, f.off, f.rec, f.use_rec, f.tmp, f.raA, f.decA, f.coordB,       \
+                           f.payB,                                                                \
                            f.best_idx, f.oa, f.ob, f.os, f.bsep, f.err);                          \
         hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA,        \
                            f.seg_n, f.list, f.cap);                                               \
         hipLaunchKernelGGL(k_seg_lds<R>, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list,  \
-                           f.cap, f.tmp, f.nB, f.pcap, f.raA, f.decA, f.radecB, f.rec, f.oa,      \
+                           f.cap, f.tmp, f.nB, f.pcap, f.raA, f.decA, f.coordB, f.payB, f.rec, f.oa,\
                            f.ob, f.os, f.bsep, f.seg_n + 1, f.huge, f.err);                       \
     } while (0)
     if (f.rare) C3X_FIN(true);
@@ -1641,7 +1649,8 @@ __global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
                              const uint32_t *__restrict__ huge, const int64_t *__restrict__ off,
                              const PairTmp *__restrict__ tmp, int64_t nB,
                              const double *__restrict__ raA, const double *__restrict__ decA,
-                             const double2 *__restrict__ radecB, const RowRec *__restrict__ rec,
+                             const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
+                             const RowRec *__restrict__ rec,
                              int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                              double *__restrict__ os, double *__restrict__ bsep,
                              uint32_t *__restrict__ err)
@@ -1656,7 +1665,7 @@ __global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
     const uint32_t h = seg[e];
     const uint32_t a = huge[h];
     const int64_t o = off[a];
-    final_write<true>(o + (i - base[h]), a, tmp[o + (e - base[h])], nB, raA, decA, radecB,
+    final_write<true>(o + (i - base[h]), a, tmp[o + (e - base[h])], nB, raA, decA, coordB, payB,
                       rec[a].best, oa, ob, os, bsep, err);
 }
 
@@ -1697,7 +1706,7 @@ static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStre
     if (e == hipSuccess) {
         const uint32_t *vf = in2 ? vb : va;
         hipLaunchKernelGGL(k_huge_write, dim3(nblk(n, 256)), dim3(256), 0, s, vf, n, seg, base,
-                           f.huge, f.off, f.tmp, f.nB, f.raA, f.decA, f.radecB, f.rec, f.oa, f.ob,
+                           f.huge, f.off, f.tmp, f.nB, f.raA, f.decA, f.coordB, f.payB, f.rec, f.oa, f.ob,
                            f.os, f.bsep, f.err);
         e = hipGetLastError();
     }
@@ -1929,7 +1938,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.g = ix->grid;
     m.pay64 = ix->pay64;
     m.pay32 = ix->pay32;
-    m.radecB = ix->radec;
+    m.coordB = ix->radec;
     m.arad = arad;
     m.aidx = aidx;
     m.aell = aell;
@@ -2321,7 +2330,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (n_x > 0)
             hipLaunchKernelGGL(k_place_x, dim3(nblk(n_x, 256)), dim3(256), 0, s, xent, n_x, nullptr,
                                aidx,
-                               arad, ix->radec, nA, ix->nB, off, P, rec, emitted ? 1 : 0, pt, c64 + 2,
+                               arad, ix->radec, ix->pay64, nA, ix->nB, off, P, rec, emitted ? 1 : 0, pt, c64 + 2,
                                ctr + 4);
         HIPCHK(hipGetLastError(), "band matches");
         tm.mark();  // 4
@@ -2337,7 +2346,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         fa.tmp = pt;
         fa.raA = ra;
         fa.decA = dec;
-        fa.radecB = ix->radec;
+        fa.coordB = ix->radec;
+        fa.payB = ix->pay64;
         fa.best_idx = R->best_idx;
         fa.oa = R->idxA;
         fa.ob = R->idxB;
@@ -2358,7 +2368,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     }
     if (nA > 0 && !all)
         hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB, rec, ra,
-                           dec, ix->radec, R->best_idx, R->best_sep, off, P, R->idxA, R->idxB,
+                           dec, ix->radec, ix->pay64, R->best_idx, R->best_sep, off, P, R->idxA,
+                           R->idxB,
                            R->sep, ctr + 4);
     HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6
