@@ -239,6 +239,19 @@ def _best(raA, decA, raB, decB, ia, ib, sep, nA):
     return best_idx, best_sep, int(tie_rows.shape[0])
 
 
+def seps(raA, decA, raB, decB, ia, ib) -> np.ndarray:
+    """The oracle's FP64 separation (arcsec) of the pairs (ia[k], ib[k])."""
+    raA, decA, raB, decB = (np.ascontiguousarray(v, dtype=np.float64)
+                            for v in (raA, decA, raB, decB))
+    ia = np.ascontiguousarray(ia, dtype=np.int32)
+    ib = np.ascontiguousarray(ib, dtype=np.int32)
+    out = np.empty(ia.shape[0], dtype=np.float64)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib().c3o_seps(_dp(raA), _dp(decA), _dp(raB), _dp(decB), ia.ctypes.data_as(ip),
+                   ib.ctypes.data_as(ip), ia.shape[0], _dp(out))
+    return out
+
+
 def decide(ra1, dec1, ra2, dec2, shape=0, radius_arcsec=1.0, a=0.0, b=0.0, pa=0.0,
            pa_zero_deg=0.0, pa_sense=1) -> int:
     """FP64 certified decision of one pair: 0 out, 1 in, 2 ambiguous."""
