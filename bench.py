@@ -1,22 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the positional cross-match hot path on one MI355X.
 
-Default workload (the headline line): the full-sky catalogue pair, 10M A x
-10M B (8M uniform on the sphere plus two dense 1M caps, one straddling RA =
-0/360 and one holding the north pole; B = 6M jittered copies of A rows + 4M
-random), radius 2", all + best matches. One step = c3x_build_index over B +
-c3x_match of A (both catalogues already resident in HBM): keying, sorting,
-directory, A preparation, count and emission, band recheck, scan,
-placement, best, ordering.
+Default workload (the headline line): the largest single-GPU
+configuration, 200M A x 200M B on the full sky with galactic-plane
+clustering (density proportional to 1 + 20 exp(-|b| / 5 deg); B = 100M
+jittered copies of A rows + 100M random from the same density), radius
+1.5", all + best matches. One step = c3x_build_index over B + c3x_match of
+A (both catalogues already resident in HBM): keying, sorting, directory, A
+preparation, count and emission, band recheck, scan, placement, best,
+ordering. The 10M x 10M full-sky workload with its dense caps (RA 0/360 and
+the north pole, r = 2") is measured in the same run and reported under
+"extra" (--no-extra skips it).
 
 The headline value is A-sources matched per second of the mixed path (FP32
 filter + FP64 recheck); the FP64 path, pair tests per second, the roofline of
 the dominant kernel and the CPU oracle timed on this host are reported beside
 it. --config picks the other workloads (one JSON line each):
   cfg1  10k x 10k patch, r = 1" (launch-latency bound; microseconds)
+  cfg2  10M x 10M full sky + dense caps, r = 2"
   cfg3  100k galactic ellipses against 50M in-band sources, all matches
   cfg4  4,096 independent circular jobs in one graph launch (batched form)
-  cfg5  200M x 200M full sky with galactic-plane clustering, r = 1.5"
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -34,10 +37,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM counters of the count pass on the headline workload (rocprofv3 --pmc
-# FETCH_SIZE, WRITE_SIZE), committed with the digest of the sources they were
-# taken on; reported as roofline.traffic only while those sources are unchanged.
-COUNTERS = os.path.join(ROOT, "profiles", "k_match_fullsky_10Mx10M_hbm_counters.md")
+# HBM counters of the count pass per workload (rocprofv3 --pmc FETCH_SIZE,
+# WRITE_SIZE), committed with the digest of the sources they were taken on;
+# reported as roofline.traffic only while those sources are unchanged.
+COUNTERS = {
+    "cfg2": os.path.join(ROOT, "profiles", "k_match_fullsky_10Mx10M_hbm_counters.md"),
+    "cfg5": os.path.join(ROOT, "profiles", "k_match_plane_200Mx200M_hbm_counters.md"),
+}
 MATCH_SOURCES = ("paper_1611_08494_amd/csrc/c3x_match.hip",
                  "paper_1611_08494_amd/csrc/c3x_internal.h")
 
@@ -50,11 +56,13 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(path_name: str):
-    """HBM bytes per launch of the count pass from the committed counter
-    summary, if it was taken on the kernel as built; else None."""
+def committed_traffic(config: str, path_name: str):
+    """HBM bytes per launch of the count pass on a workload from the committed
+    counter summary, if it was taken on the kernel as built; else None."""
+    if config not in COUNTERS:
+        return None
     try:
-        with open(COUNTERS) as f:
+        with open(COUNTERS[config]) as f:
             text = f.read()
     except OSError:
         return None
@@ -71,7 +79,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"], default="cfg2")
+    p.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"], default="cfg5")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the 10M x 10M full-sky line reported beside the default one")
     p.add_argument("--scale", type=float, default=1.0,
                    help="shrink the workload (testing only; the reported line uses 1.0)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -116,15 +126,31 @@ def run_path(c3x, torch, tens, cat, precision, steps, warmup, area_kw, frame, mo
     return ms, last["r"], kstats
 
 
-def count_pass_bytes(cat, r, pay):
-    """Algorithmic bytes of one count-pass launch: every A record read once
-    (sorted coordinates 16 B, row 4 B, candidate ranges 24 B); a count and a
-    record (4 + 16 B) written for each row with a match (rows without one
-    store nothing); every B payload read at least once (16 B mixed, 32 B
-    FP64) with its 4-byte key."""
-    import torch
-    matched = int((torch.as_tensor(r.best_idx) >= 0).sum().item())
-    return cat.nA * (16 + 4 + 24) + matched * (4 + 16) + cat.nB * (pay + 4), matched
+def algorithmic_bytes(cat, n_pairs, pay, best):
+    """Bytes the method must move for one cross-match (per B: 16 B of
+    coordinates in and its 16 B (mixed) or 32 B (FP64) payload out; per A:
+    16 B in, 24 B of ellipse parameters in, 12 B of best match out (BEST);
+    per pair: 16 B out)."""
+    per_a = 16 + (24 if cat.shape == 1 else 0) + (12 if best else 0)
+    return cat.nB * (16 + pay) + cat.nA * per_a + int(n_pairs) * 16
+
+
+def host_cores():
+    """CPUs this process may run on, the host's count and its CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return avail, os.cpu_count() or 1, model
 
 
 def time_unmatched(c3x, torch, cat, r, steps):
@@ -173,13 +199,13 @@ def time_concentric(c3x, torch, tens, cat, precision, steps, area_kw, frame):
             "pairs_per_level": per}
 
 
-def path_summary(cat, ms, r, ks, pay):
+def path_summary(cat, ms, r, ks, pay, best):
     ist = [k[0] for k in ks]
     mst = [k[1] for k in ks]
-    alg, matched = count_pass_bytes(cat, r, pay)
+    alg = algorithmic_bytes(cat, r.n_pairs, pay, best)
     return dict(
-        rows_matched=matched,
-        count_pass_algorithmic_bytes=int(alg),
+        algorithmic_bytes=int(alg),
+        step_hbm_frac=round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         ms_per_step=ms,
         a_per_s=cat.nA / (ms / 1e3),
         pair_tests=int(mst[-1]["n_tests"]),
@@ -188,6 +214,7 @@ def path_summary(cat, ms, r, ks, pay):
         n_band=int(mst[-1]["n_band"]),
         n_ambiguous=int(mst[-1]["n_ambiguous"]),
         n_best_ties=int(mst[-1]["n_best_ties"]),
+        n_sort_retries=int(max(s["n_sort_retries"] for s in ist + mst)),
         phases_ms=dict(
             index=mean([s["ms_index"] for s in ist]),
             a_prep=mean([s["ms_a_prep"] for s in mst]),
@@ -216,8 +243,10 @@ def oracle_baseline(cat, area_kw_np, threads, sample_rows, what):
     t = time.perf_counter()
     o = oracle.match(cat.raA[:n], cat.decA[:n], cat.raB, cat.decB, nthreads=threads, **kw)
     dt = time.perf_counter() - t
+    _, ncpu, model = host_cores()
     return {"value": round(n / dt, 1), "unit": "A-sources/s", "cores": int(o.threads),
-            "kind": "oracle", "sample": f"{what}: first {n} A rows against all {cat.nB} B rows "
+            "kind": "oracle", "host_cpus": ncpu, "cpu_model": model,
+            "sample": f"{what}: first {n} A rows against all {cat.nB} B rows "
             f"(index build included), {dt:.1f}s wall"}, o
 
 
@@ -260,7 +289,8 @@ def single_config(a, c3x, torch, np, name):
     for pname in order:
         prec = c3x.MIXED if pname == "mixed" else c3x.FP64
         ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup, area_kw, frame, mode)
-        paths[pname] = path_summary(cat, ms, r, ks, 16 if pname == "mixed" else 32)
+        paths[pname] = path_summary(cat, ms, r, ks, 16 if pname == "mixed" else 32,
+                                    bool(mode & c3x.BEST))
         if mode & c3x.ALL:
             paths[pname]["join_unmatched"] = time_unmatched(c3x, torch, cat, r, a.steps)
         del r
@@ -274,21 +304,24 @@ def single_config(a, c3x, torch, np, name):
     # matches (k_match<..., 2>, one launch per step); its duration is the
     # library's pair of HIP events around that launch alone, on the stream it
     # runs on (the count phase adds the wavefront-per-row kernel, the band
-    # recheck and the read-back). Algorithmic bytes: count_pass_bytes.
+    # recheck and the read-back). Algorithmic bytes per launch: those of the
+    # whole cross-match (algorithmic_bytes), since the one launch reads every
+    # A and every B payload and decides every pair.
     hp = head["phases_ms"]
-    alg_bytes = head["count_pass_algorithmic_bytes"]
+    alg_bytes = head["algorithmic_bytes"]
     achieved = alg_bytes / (hp["count_kernel"] / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_match (count + emit pass)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": committed_traffic(order[0]) if name == "cfg2" and a.scale == 1.0
-                else None,
+                "traffic": committed_traffic(name, order[0]) if a.scale == 1.0 else None,
                 "algorithmic_bytes_per_launch": int(alg_bytes),
-                "kernel_ms": round(hp["count_kernel"], 4)}
+                "kernel_ms": round(hp["count_kernel"], 4),
+                "step_frac": head["step_hbm_frac"]}
 
     cpu = None
     if not a.no_cpu_baseline:
-        threads = a.cpu_threads or min(16, os.cpu_count() or 1)
+        avail, _, _ = host_cores()
+        threads = a.cpu_threads or avail
         sample = {"cfg1": cat.nA, "cfg2": cat.nA, "cfg3": 20_000, "cfg5": 2_000_000}[name]
         cpu, o = oracle_baseline(cat, area_np, threads, sample, name)
         if sample >= cat.nA and int(len(o.ia)) != head["n_pairs"]:
@@ -370,7 +403,8 @@ def batch_config(a, c3x, torch, np):
     cpu = None
     if not a.no_cpu_baseline:
         import oracle
-        threads = a.cpu_threads or min(16, os.cpu_count() or 1)
+        avail, ncpu, model = host_cores()
+        threads = a.cpu_threads or avail
         t = time.perf_counter()
         n = 0
         for (ao, na, bo, nb, r) in jobs:
@@ -381,8 +415,8 @@ def batch_config(a, c3x, torch, np):
                 break
         dt = time.perf_counter() - t
         cpu = {"value": round(n / dt, 1), "unit": "A-sources/s", "cores": threads,
-               "kind": "oracle", "sample": f"cfg4: jobs in order until 20 s ({n} A rows), "
-               f"{dt:.1f}s wall"}
+               "kind": "oracle", "host_cpus": ncpu, "cpu_model": model,
+               "sample": f"cfg4: jobs in order until 20 s ({n} A rows), {dt:.1f}s wall"}
     line = {
         "metric": METRIC,
         "value": round(head["a_per_s"], 1),
@@ -427,6 +461,15 @@ def main():
         line = batch_config(a, c3x, torch, np)
     else:
         line = single_config(a, c3x, torch, np, a.config)
+    if a.config == "cfg5" and not a.no_extra:
+        # the 10M x 10M full-sky workload beside the headline (its CPU
+        # baseline included: the oracle runs it whole in seconds)
+        torch.cuda.empty_cache()
+        x = single_config(a, c3x, torch, np, "cfg2")
+        line["extra"] = {"cfg2": {k: x[k] for k in ("value", "unit", "ms_per_step", "dtype",
+                                                     "config", "pair_tests_per_s", "paths",
+                                                     "roofline", "cpu_baseline",
+                                                     "speedup_mixed_vs_fp64") if k in x}}
     print(json.dumps(line))
 
 

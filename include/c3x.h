@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define C3X_ABI_VERSION 1
+#define C3X_ABI_VERSION 2
 
 typedef enum {
     C3X_OK = 0,
@@ -137,12 +137,16 @@ typedef struct {
     int32_t precision;
     int32_t tile;
     double ms_count_kernel;   /* the count kernel's own launch (one lane per source) */
+    int32_t n_sort_retries;   /* 1: a large radix sort's look-back gave up and the call's
+                                 work was redone with the table schedule */
+    int32_t pad;
 } c3x_stats;
 
-/* Builds the sky index over catalogue B: validates the rows, assigns each to
- * a zone/RA cell (Section 2.3, "the objects of the second catalogue are
- * assigned to one of the cells"), sorts B by cell with an LDS radix sort,
- * and builds the cell directory. ra_deg/dec_deg: device float64[nB].
+/* Builds the sky index over catalogue B: validates the rows, puts each row
+ * in the zone/RA cell its coordinates fall in (the partition of Section
+ * 2.3), sorts B by cell with an LDS radix sort, and builds the cell
+ * directory. A large sort whose bounded look-back gave up is redone with the
+ * table schedule (stats n_sort_retries = 1), never returned out of order. ra_deg/dec_deg: device float64[nB].
  * reach_hint_arcsec: the largest radius or semi-major axis expected (sizes
  * the cells; any reach still works). opts may be NULL.
  * Errors: C3X_EINVAL (bad row: message names it; bad frame or options),

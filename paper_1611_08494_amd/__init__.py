@@ -28,6 +28,7 @@ from ._binding import (  # noqa: F401
     lib,
     match,
     match_concentric,
+    result_copy,
     unmatched,
     version,
 )

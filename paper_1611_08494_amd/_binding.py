@@ -66,6 +66,8 @@ class Stats(ctypes.Structure):
         ("ms_write", ctypes.c_double), ("ms_sort_pairs", ctypes.c_double),
         ("ms_total", ctypes.c_double), ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("ms_count_kernel", ctypes.c_double),
+        ("n_sort_retries", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -295,6 +297,30 @@ def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
     check(lib().c3x_match(index.handle, ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(frame),
                           ctypes.byref(ar), int(mode), ctypes.byref(o), ctypes.byref(h)))
     return _views(h, ra.device)
+
+
+def result_copy(result: MatchResult, idxA=None, idxB=None, sep=None, best_idx=None,
+                best_sep=None, stream=None):
+    """c3x_result_copy: copies the result's arrays into the given contiguous
+    tensors (host or device; int32 idxA/idxB/best_idx, float64 sep/best_sep;
+    n_pairs or nA entries). Any may be None."""
+    torch = _torch()
+    owner = result._owner
+    if owner is None or not owner.handle:
+        raise ValueError("result has no library handle")
+    npairs, na = result.n_pairs, int(result.best_idx.shape[0])
+    ptrs = []
+    for t, n, dt, nm in ((idxA, npairs, torch.int32, "idxA"), (idxB, npairs, torch.int32, "idxB"),
+                         (sep, npairs, torch.float64, "sep"),
+                         (best_idx, na, torch.int32, "best_idx"),
+                         (best_sep, na, torch.float64, "best_sep")):
+        if t is None:
+            ptrs.append(None)
+            continue
+        if t.dtype != dt or not t.is_contiguous() or t.numel() < n:
+            raise TypeError(f"{nm} must be a contiguous {dt} tensor of at least {n} entries")
+        ptrs.append(t.data_ptr())
+    check(lib().c3x_result_copy(owner.handle, *ptrs, _stream_ptr(stream)))
 
 
 def match_concentric(index: Index, ra, dec, a, b, pa, scales, frame: int = EQUATORIAL,

@@ -477,7 +477,7 @@ struct c3x_batch {
     unsigned long long *d_vk = nullptr;
     uint32_t *d_nv = nullptr;
     // counters: 0 flags, 1 amb_n, 2 tie_n, 3 unc_n, 4 err, 5 ov_flag, 6-7 seg_n,
-    // 8 n_bin, 9 n_hl, 10 n_pos, 11 bad job
+    // 8 n_bin, 9 n_hl, 10 n_pos, 11 bad job, 12 collect count, 13 sort give-up
     uint32_t *ctr = nullptr;
     unsigned long long *c64 = nullptr;  // statistics copies (tests, band, placed)
     // outputs
@@ -493,6 +493,9 @@ struct c3x_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool ran = false;
+    // large sorts may take the one-sweep schedule; cleared for good once a
+    // look-back gave up (the graph is then captured again without it)
+    bool onesweep = true;
     c3x_stats stats{};
     double cell_scale = 1.0;
     std::vector<int64_t> hjoboff;
@@ -592,8 +595,9 @@ static hipError_t batch_front(c3x_batch *b)
         hipLaunchKernelGGL(k_bkeys, dim3(nblk(NB, 256)), dim3(256), 0, s, b->djobs, b->ejobB,
                            b->raB, b->decB, NB, true, b->bk, b->packB, b->ctr);
     int in_tmp = 0;
+    uint32_t *sort_fail = b->onesweep ? b->ctr + 13 : nullptr;
     hipError_t e = radix_sort_pairs(b->bk, b->bv, b->bk2, b->bv2, NB, b->key_bits, b->bws, s,
-                                    &in_tmp, /*vals_are_index=*/true);
+                                    &in_tmp, /*vals_are_index=*/true, sort_fail);
     if (e != hipSuccess) return e;
     const uint32_t *skeys = in_tmp ? b->bk2 : b->bk;
     const uint32_t *srows = in_tmp ? b->bv2 : b->bv;
@@ -617,7 +621,7 @@ static hipError_t batch_front(c3x_batch *b)
     // (a job's entries stay together: keys are job-major and the sort stable)
     const int a_lo = std::max(0, b->key_bits - kAKeyBits);
     e = radix_sort_pairs_bits(b->ak, b->av, b->ak2, b->av2, NA, a_lo, b->key_bits, b->aws, s,
-                              &in_tmp, /*vals_are_index=*/true);
+                              &in_tmp, /*vals_are_index=*/true, sort_fail);
     if (e != hipSuccess) return e;
     const uint32_t *arows = in_tmp ? b->av2 : b->av;
     if (NA > 0)
@@ -792,6 +796,7 @@ static c3x_status batch_size_lists(c3x_batch *b)
         BCHK(hipMemcpyAsync(hc, b->ctr, sizeof(hc), hipMemcpyDeviceToHost, s), "copy");
         BCHK(hipMemcpyAsync(oc.data(), b->octr, oc.size() * 4, hipMemcpyDeviceToHost, s), "copy");
         BCHK(hipStreamSynchronize(s), "batch pipeline");
+        if (hc[13]) return kSortGaveUp;
         uint32_t ov_need = 0;
         for (int q = 0; q < kEmitPools; ++q) ov_need = std::max(ov_need, oc[q * kEmitPoolStride]);
         const bool grow_amb = hc[1] > b->amb_cap, grow_tie = hc[2] > b->tie_cap;
@@ -823,6 +828,29 @@ static c3x_status batch_size_lists(c3x_batch *b)
         if (!b->amb || !b->tie || !b->bin || !b->xent || !b->ovl || !b->pos || !b->unc)
             return fail(C3X_ENOMEM, "batch lists");
     }
+    return C3X_OK;
+}
+
+// The whole pipeline as one graph (replacing any earlier capture).
+static c3x_status batch_capture(c3x_batch *b)
+{
+    hipStream_t s = b->s;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
+    hipError_t e = batch_front(b);
+    if (e == hipSuccess) e = batch_back(b);
+    hipGraph_t gr = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &gr);
+    if (e != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail_hip(e, "graph capture");
+    }
+    if (e2 != hipSuccess) return fail_hip(e2, "graph capture");
+    b->graph = gr;
+    BCHK(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0), "graph instantiate");
     return C3X_OK;
 }
 
@@ -1098,20 +1126,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     BCHK(hipStreamSynchronize(s), "batch pipeline");
     b->ran = true;
 
-    // the whole pipeline as one graph
-    BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
-    hipError_t e = batch_front(b);
-    if (e == hipSuccess) e = batch_back(b);
-    hipGraph_t gr = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s, &gr);
-    if (e != hipSuccess) {
-        if (gr) (void)hipGraphDestroy(gr);
-        return fail_hip(e, "graph capture");
-    }
-    if (e2 != hipSuccess) return fail_hip(e2, "graph capture");
-    b->graph = gr;
-    BCHK(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0), "graph instantiate");
-    return C3X_OK;
+    return batch_capture(b);
 }
 
 // Reads the run's flags and counts; ranks on the host (binary128) the rows
@@ -1129,6 +1144,7 @@ static c3x_status batch_finish(c3x_batch *b)
     BCHK(hipMemcpyAsync(&P, b->off + b->NA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     BCHK(hipStreamSynchronize(s), "batch result");
     stat_sums(hs.data(), h64);
+    if (hc[13]) return kSortGaveUp;  // nothing of this run is used
     if (hc[0] & kBFlagStale)
         return fail(C3X_EINVAL, "batch inputs moved outside the planned sky boxes: plan again");
     if ((hc[0] & kBFlagCap) || hc[1] > b->amb_cap || hc[2] > b->tie_cap || hc[5] ||
@@ -1248,28 +1264,39 @@ extern "C" c3x_status c3x_batch_plan(const c3x_job *jobs, int32_t n_jobs, const 
         return fail(C3X_EINVAL, "NULL coordinate array");
     // the inputs may still be in flight on another stream
     if (hipDeviceSynchronize() != hipSuccess) return fail(C3X_EDEVICE, "device synchronize");
-    c3x_batch *b = new (std::nothrow) c3x_batch();
-    if (!b) return fail(C3X_ENOMEM, "host allocation");
-    (void)hipGetDevice(&b->device);
-    b->prec = o.precision;
-    b->nj = n_jobs;
-    b->NA = SA;
-    b->NB = SB;
-    b->raA = raA;
-    b->decA = decA;
-    b->raB = raB;
-    b->decB = decB;
-    b->jobs.assign(jobs, jobs + n_jobs);
-    if (hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) != hipSuccess) {
+    c3x_batch *b = nullptr;
+    c3x_status st = C3X_OK;
+    // a plan whose one-sweep sort gave up its look-back is made again with
+    // the table schedule
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        b = new (std::nothrow) c3x_batch();
+        if (!b) return fail(C3X_ENOMEM, "host allocation");
+        (void)hipGetDevice(&b->device);
+        b->onesweep = attempt == 0;
+        b->prec = o.precision;
+        b->nj = n_jobs;
+        b->NA = SA;
+        b->NB = SB;
+        b->raA = raA;
+        b->decA = decA;
+        b->raB = raB;
+        b->decB = decB;
+        b->jobs.assign(jobs, jobs + n_jobs);
+        if (hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return fail(C3X_EDEVICE, "stream");
+        }
+        st = batch_plan_impl(b);
+        if (st == C3X_OK) st = batch_finish(b);
+        if (st != kSortGaveUp) break;
         delete b;
-        return fail(C3X_EDEVICE, "stream");
+        b = nullptr;
     }
-    c3x_status st = batch_plan_impl(b);
-    if (st == C3X_OK) st = batch_finish(b);
     if (st != C3X_OK) {
         delete b;
-        return st;
+        return st == kSortGaveUp ? fail(C3X_EDEVICE, "internal: sort gave up twice") : st;
     }
+    b->stats.n_sort_retries = b->onesweep ? 0 : 1;
     b->stats.n_a = SA;
     b->stats.n_b = SB;
     b->stats.n_pairs = b->P;
@@ -1300,7 +1327,22 @@ extern "C" c3x_status c3x_batch_run(c3x_batch *b, void *stream)
     if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
     c3x_status st = e == hipSuccess ? C3X_OK : fail_hip(e, "c3x_batch_run");
     if (st == C3X_OK) st = batch_finish(b);
-    if (st == C3X_OK && timed) {
+    const bool retried = st == kSortGaveUp;
+    if (retried) {
+        // a one-sweep look-back gave up during the replay: the graph is
+        // captured again with the table schedule and replayed
+        b->onesweep = false;
+        b->stats.n_sort_retries = 1;
+        st = batch_capture(b);
+        if (st == C3X_OK) {
+            e = hipGraphLaunch(b->exec, b->s);
+            if (e == hipSuccess) e = hipEventRecord(ev, b->s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+            st = e == hipSuccess ? batch_finish(b) : fail_hip(e, "c3x_batch_run");
+        }
+        if (st == kSortGaveUp) st = fail(C3X_EDEVICE, "internal: table sort reported a give-up");
+    }
+    if (st == C3X_OK && timed && !retried) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, t0, t1) == hipSuccess) b->stats.ms_total = ms;
     }

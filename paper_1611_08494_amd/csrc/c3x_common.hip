@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -60,14 +61,20 @@ size_t size_class(size_t n)
 }
 }  // namespace
 
+// Test hook: the k-th device allocation from the moment it is armed fails
+// (C3X_DEBUG_FAIL_ALLOC=k arms it at the first allocation of the process;
+// c3x_debug_fail_alloc(k) arms it at any time, 0 disarms).
+static std::mutex g_fail_mu;
+static int g_fail_left = -1;  // -1: not yet read from the environment
+
 static int fail_alloc_countdown()
 {
-    // Test hook: C3X_DEBUG_FAIL_ALLOC=k makes the k-th allocation fail.
-    static int left = [] {
+    std::lock_guard<std::mutex> g(g_fail_mu);
+    if (g_fail_left < 0) {
         const char *e = getenv("C3X_DEBUG_FAIL_ALLOC");
-        return e ? atoi(e) : 0;
-    }();
-    if (left > 0 && --left == 0) return 1;
+        g_fail_left = e ? std::max(0, atoi(e)) : 0;
+    }
+    if (g_fail_left > 0 && --g_fail_left == 0) return 1;
     return 0;
 }
 
@@ -152,8 +159,16 @@ const char *c3x_last_error(void) { return c3x::g_err; }
 const char *c3x_version(void) { return "c3x 0.1 (gfx950)"; }
 int c3x_abi_version(void) { return C3X_ABI_VERSION; }
 
-// Releases every cached device block (not part of the public header; used by
-// tests that check for leaks).
+// Arms the allocation-failure hook: the k-th device allocation from now
+// fails (0 disarms). Not part of the public header; used by tests.
+void c3x_debug_fail_alloc(int k)
+{
+    std::lock_guard<std::mutex> g(c3x::g_fail_mu);
+    c3x::g_fail_left = k > 0 ? k : 0;
+}
+
+// Number of device blocks handed out and not yet returned to the cache (not
+// part of the public header; used by tests that check for leaks).
 int c3x_debug_live_blocks(void)
 {
     c3x::Cache &k = c3x::cache();

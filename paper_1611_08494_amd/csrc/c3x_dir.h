@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace c3x {
 
 // The directory from the sorted keys: position s (0 <= s <= n; s = n stands
@@ -34,8 +36,11 @@ static __global__ void k_dir_fill(const uint32_t *__restrict__ keys, int64_t n, 
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > n) return;
-    const int64_t hi = t < n ? (int64_t)(keys[t] >> dshift) : (int64_t)dsize - 1;
-    const int64_t lo = t > 0 ? (int64_t)(keys[t - 1] >> dshift) : -1;
+    // buckets clamped to the directory: keys out of order or out of range
+    // (a sort that gave up, whose index is discarded) still write in bounds
+    const int64_t top = (int64_t)dsize - 1;
+    const int64_t hi = t < n ? std::min<int64_t>(keys[t] >> dshift, top) : top;
+    const int64_t lo = t > 0 ? std::min<int64_t>(keys[t - 1] >> dshift, top) : -1;
     if (hi - lo <= (int64_t)kDirGap) {
         for (int64_t q = lo + 1; q <= hi; ++q) dir[q] = (uint32_t)t;
     } else if (hi - lo <= (int64_t)kDirBig) {

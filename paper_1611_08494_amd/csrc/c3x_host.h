@@ -12,6 +12,11 @@
 
 namespace c3x {
 
+// Internal status (never returned across the ABI): a one-sweep radix sort
+// gave up its look-back, so the call's work is redone with the table
+// schedule.
+constexpr c3x_status kSortGaveUp = (c3x_status)7;  // within the enum's value range
+
 // Thread-local error message; returns the status for convenience.
 c3x_status fail(c3x_status st, const char *fmt, ...);
 c3x_status fail_hip(hipError_t e, const char *what);

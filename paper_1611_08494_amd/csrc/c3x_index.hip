@@ -1,6 +1,6 @@
-// c3x_index.hip -- sky index over catalogue B (paper Section 2.3: "the
-// objects of the second catalogue are assigned to one of the cells defined
-// by the partitioning procedure, according to their coordinates").
+// c3x_index.hip -- sky index over catalogue B (paper Section 2.3: each row
+// of the second catalogue is put in the partition cell its coordinates fall
+// in).
 //
 // The flat grid of the paper becomes declination zones of height h, each cut
 // into n_z RA cells of true width >= h at the zone's edge nearest the
@@ -248,13 +248,12 @@ c3x_status upload_grid(c3x_index *ix, hipStream_t s)
 
 using namespace c3x;
 
-extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_deg, int64_t nB,
-                                      c3x_frame frame, double reach_hint_arcsec,
-                                      const c3x_opts *opts, c3x_index **out)
+// onesweep: large sorts may take the one-sweep schedule (kSortGaveUp if its
+// look-back gave up; the caller then builds again without it).
+static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, int64_t nB,
+                                   c3x_frame frame, double reach_hint_arcsec,
+                                   const c3x_opts *opts, bool onesweep, c3x_index **out)
 {
-    clear_error();
-    if (!out) return fail(C3X_EINVAL, "out is NULL");
-    *out = nullptr;
     if (nB < 0) return fail(C3X_EINVAL, "nB < 0");
     if (nB > 2147483647LL) return fail(C3X_ERANGE, "nB above 2^31 - 1");
     if (nB > 0 && (!ra_deg || !dec_deg)) return fail(C3X_EINVAL, "NULL coordinate array");
@@ -297,7 +296,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     uint32_t *ktmp = tmp.get_n<uint32_t>(n);
     uint32_t *rtmp = tmp.get_n<uint32_t>(n);
     void *ws = tmp.get(radix_ws_bytes(n));
-    uint32_t *bad = tmp.get_n<uint32_t>(1);
+    uint32_t *bad = tmp.get_n<uint32_t>(2);  // first bad row; sort give-up
     // the coordinates in input order: the gathers' source, then kept by the
     // index (the rare paths reach them through pay64[j].idx)
     double2 *packed = ix->mem.get_n<double2>(n);
@@ -318,6 +317,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
         return fail(C3X_ENOMEM, "index buffers");
     }
     hipError_t e = hipMemsetAsync(bad, 0xff, sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(bad + 1, 0, sizeof(uint32_t), s);
     Grid g = ix->grid;
     g.nB = (int32_t)n;
     if (n > 0)
@@ -327,7 +327,7 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess)
         e = radix_sort_pairs(keys, rows, ktmp, rtmp, n, ix->plan.key_bits, ws, s, &in_tmp,
-                             /*vals_are_index=*/true);
+                             /*vals_are_index=*/true, onesweep ? bad + 1 : nullptr);
     if (e == hipSuccess && in_tmp) {
         e = hipMemcpyAsync(keys, ktmp, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
         rows = rtmp;
@@ -350,23 +350,30 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
         e = hipGetLastError();
     }
     tm.mark();
-    uint32_t bad_h = 0xffffffffu;
+    uint32_t bad_h[2] = {0xffffffffu, 0u};
     uint32_t *hbad = (uint32_t *)pinned_stage(64);
-    if (!hbad) hbad = &bad_h;
-    *hbad = 0xffffffffu;
+    if (!hbad) hbad = bad_h;
+    hbad[0] = 0xffffffffu;
+    hbad[1] = 0u;
     if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hbad, bad, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    bad_h = *hbad;
+    const uint32_t sort_gave_up = hbad[1];
+    bad_h[0] = hbad[0];
     if (e != hipSuccess) {
         (void)hipStreamSynchronize(s);
         delete ix;
         return fail_hip(e, "c3x_build_index");
     }
-    if (bad_h != 0xffffffffu) {
+    if (sort_gave_up) {
+        delete ix;
+        return kSortGaveUp;
+    }
+    if (bad_h[0] != 0xffffffffu) {
         delete ix;
         return fail(C3X_EINVAL, "catalogue B row %u: coordinate outside RA [0,360), |Dec| <= 90 "
-                                "or not finite", bad_h);
+                                "or not finite", bad_h[0]);
     }
     ix->keys = keys;
     ix->pay64 = p64;
@@ -384,6 +391,22 @@ extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_de
     S.precision = (int32_t)o.precision;
     *out = ix;
     return C3X_OK;
+}
+
+extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_deg, int64_t nB,
+                                      c3x_frame frame, double reach_hint_arcsec,
+                                      const c3x_opts *opts, c3x_index **out)
+{
+    clear_error();
+    if (!out) return fail(C3X_EINVAL, "out is NULL");
+    *out = nullptr;
+    c3x_status st = build_index_impl(ra_deg, dec_deg, nB, frame, reach_hint_arcsec, opts, true, out);
+    if (st != kSortGaveUp) return st;
+    // the one-sweep sort gave up its look-back: build again with the table
+    // schedule, which never waits
+    st = build_index_impl(ra_deg, dec_deg, nB, frame, reach_hint_arcsec, opts, false, out);
+    if (st == C3X_OK) (*out)->stats.n_sort_retries = 1;
+    return st;
 }
 
 extern "C" void c3x_index_free(c3x_index *ix) { delete ix; }

@@ -405,30 +405,14 @@ __device__ __forceinline__ bool same_point(const ARec &a, double2 rb)
     return a.dec == rb.y && (a.ra == rb.x || fabs(a.dec) == 90.0);
 }
 
-// Bound of a staged key range: a start (end = false) or an exclusive end
-// (end = true) at most as tight as lower_bound(k). When k's directory bucket
-// holds at most 8 keys the bucket's own bound is returned (no search); the
-// lanes find their exact cells inside the staged range anyway.
-__device__ __forceinline__ uint32_t key_bound(const Grid &g, uint32_t k, bool end)
-{
-    uint32_t q = k >> g.dshift;
-    if (q + 1 >= g.dsize) return (uint32_t)g.nB;
-    uint32_t lo = g.dir[q], hi = min(g.dir[q + 1], (uint32_t)g.nB);
-    if (hi - lo <= 8u || lo >= hi) return end ? hi : lo;
-    while (lo < hi) {
-        uint32_t m = lo + ((hi - lo) >> 1);
-        if (g.keys[m] < k) lo = m + 1;
-        else hi = m;
-    }
-    return lo;
-}
-
-// First sorted position whose key is >= k (keys ascending).
+// First sorted position whose key is >= k (keys ascending). The result
+// never exceeds nB, whatever the directory holds (an index whose sort gave
+// up is discarded, but the kernels already queued on it stay in bounds).
 __device__ __forceinline__ uint32_t key_lower_bound(const Grid &g, uint32_t k)
 {
     uint32_t q = k >> g.dshift;
     if (q + 1 >= g.dsize) return (uint32_t)g.nB;
-    uint32_t lo = g.dir[q], hi = min(g.dir[q + 1], (uint32_t)g.nB);
+    uint32_t hi = min(g.dir[q + 1], (uint32_t)g.nB), lo = min(g.dir[q], hi);
     while (lo < hi) {
         uint32_t m = lo + ((hi - lo) >> 1);
         if (g.keys[m] < k) lo = m + 1;

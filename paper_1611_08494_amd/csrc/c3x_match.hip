@@ -1576,6 +1576,7 @@ struct FinishArgs {
     int32_t *oa, *ob;
     double *os, *bsep;
     uint32_t *err;
+    uint32_t *sort_fail;  // cleared device word for the segment sorts (null: table schedule)
     uint32_t *seg_n;   // [2]: listed long segments, listed huge segments
     uint32_t *list, *huge;
     uint32_t cap;
@@ -1664,9 +1665,16 @@ __global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
     }
     const uint32_t h = seg[e];
     const uint32_t a = huge[h];
-    const int64_t o = off[a];
-    final_write<true>(o + (i - base[h]), a, tmp[o + (e - base[h])], nB, raA, decA, coordB, payB,
-                      rec[a].best, oa, ob, os, bsep, err);
+    const int64_t o = off[a], len = off[a + 1] - o;
+    // ranks outside the segment only come from a sort that gave up (the
+    // call is then redone): nothing is written
+    const int64_t rk = (int64_t)i - (int64_t)base[h], src = (int64_t)e - (int64_t)base[h];
+    if (rk < 0 || rk >= len || src < 0 || src >= len) {
+        atomicOr(err, 16u);
+        return;
+    }
+    final_write<true>(o + rk, a, tmp[o + src], nB, raA, decA, coordB, payB, rec[a].best, oa, ob,
+                      os, bsep, err);
 }
 
 static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStream_t s)
@@ -1694,14 +1702,14 @@ static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStre
                        nh, f.off, base, f.tmp, k1, v1, seg);
     // by idxB (stable), then by segment (stable): each segment in idxB order
     int in1 = 0, in2 = 0;
-    e = radix_sort_pairs(k1, v1, k2, v2, n, 31, ws, s, &in1);
+    e = radix_sort_pairs(k1, v1, k2, v2, n, 31, ws, s, &in1, false, f.sort_fail);
     uint32_t *ka = in1 ? k2 : k1, *va = in1 ? v2 : v1;  // sorted by idxB
     uint32_t *kb = in1 ? k1 : k2, *vb = in1 ? v1 : v2;  // free
     int segbits = 1;
     while (segbits < 32 && (nh - 1) >> segbits) ++segbits;
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_huge_segkey, dim3(nblk(n, 256)), dim3(256), 0, s, va, seg, n, kb);
-        e = radix_sort_pairs(kb, va, ka, vb, n, segbits, ws, s, &in2);
+        e = radix_sort_pairs(kb, va, ka, vb, n, segbits, ws, s, &in2, false, f.sort_fail);
     }
     if (e == hipSuccess) {
         const uint32_t *vf = in2 ? vb : va;
@@ -1710,9 +1718,12 @@ static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStre
                            f.os, f.bsep, f.err);
         e = hipGetLastError();
     }
+    uint32_t gave_up = 0;
+    if (e == hipSuccess && f.sort_fail)
+        e = hipMemcpyAsync(&gave_up, f.sort_fail, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_hip(e, "segment order");
-    return C3X_OK;
+    return gave_up ? kSortGaveUp : C3X_OK;
 }
 
 // Margins of the circle filters on the squared chord: FP64 unit vectors
@@ -1850,8 +1861,12 @@ static std::atomic<uint64_t> g_ov_hint{0};
 constexpr uint64_t kOvFloorBytes = 1ull << 30;  // overflow regions: floor of 256 entries a row up to this
 constexpr uint64_t kOvMaxBytes = 4ull << 30;    // and never more than this
 
+// onesweep: large sorts may take the one-sweep schedule; kSortGaveUp when
+// one of them gave up its look-back (the caller then redoes the call
+// without it).
 static c3x_status match_impl(const c3x_index *ix, const double *ra, const double *dec, int64_t nA,
-                             const c3x_area *area, unsigned mode, hipStream_t s, c3x_result *R)
+                             const c3x_area *area, unsigned mode, hipStream_t s, bool onesweep,
+                             c3x_result *R)
 {
     const int shape = area->shape;
     const int prec = ix->precision;
@@ -1905,8 +1920,9 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     // 2^(bits - 24) cells along a zone keep a wavefront's sources together,
     // and no result depends on the order of A
     const int a_lo = std::max(0, ix->plan.key_bits - kAKeyBits);
+    // ctr[11]: set when a one-sweep sort gave up (read back after the count)
     HIPCHK(radix_sort_pairs_bits(keys, rows, ktmp, rtmp, nA, a_lo, ix->plan.key_bits, ws, s,
-                                 &in_tmp, /*vals_are_index=*/true),
+                                 &in_tmp, /*vals_are_index=*/true, onesweep ? ctr + 11 : nullptr),
            "A sort");
     uint32_t *srows = in_tmp ? rtmp : rows;
     // rows with at least wide_min candidates (or a window walked cell by
@@ -2057,6 +2073,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         memcpy(hctr, hb, sizeof(hctr));
         stat_sums((const unsigned long long *)(hb + 128), h64);
         if (emit) memcpy(hoctr.data(), hb + kOctrAt, kPoolWords * sizeof(uint32_t));
+        if (hctr[11]) return kSortGaveUp;
         if (hctr[0] != 0xffffffffu)
             return fail(C3X_EINVAL,
                         "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= 90, not "
@@ -2354,6 +2371,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         fa.os = R->sep;
         fa.bsep = R->best_sep;
         fa.err = ctr + 4;
+        fa.sort_fail = onesweep ? ctr + 11 : nullptr;
         fa.seg_n = ctr + 6;
         fa.cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(nA, 1), 1 << 22);
         fa.list = tmp.get_n<uint32_t>(fa.cap);
@@ -2460,7 +2478,21 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
     memset(&R->stats, 0, sizeof(R->stats));
     R->mode = mode;
     R->nB = ix->nB;
-    c3x_status st = match_impl(ix, ra_deg, dec_deg, nA, area, mode, s, R);
+    c3x_status st = match_impl(ix, ra_deg, dec_deg, nA, area, mode, s, true, R);
+    if (st == kSortGaveUp) {
+        // a one-sweep sort gave up its look-back: the call again, with the
+        // table schedule (which never waits), into a fresh result
+        (void)hipStreamSynchronize(s);
+        delete R;
+        R = new (std::nothrow) c3x_result();
+        if (!R) return fail(C3X_ENOMEM, "host allocation");
+        (void)hipGetDevice(&R->device);
+        memset(&R->stats, 0, sizeof(R->stats));
+        R->mode = mode;
+        R->nB = ix->nB;
+        st = match_impl(ix, ra_deg, dec_deg, nA, area, mode, s, false, R);
+        R->stats.n_sort_retries = 1;
+    }
     if (st != C3X_OK) {
         (void)hipStreamSynchronize(s);
         delete R;

@@ -14,6 +14,17 @@
 // 32M elements (and of 2^30 or more) instead count each pass's digits per
 // tile into a table, scan it, and scatter: there the table is small enough
 // to scan with one workgroup per digit, which costs less than the look-back.
+//
+// A look-back waits only on tiles that took their numbers earlier (so are
+// running or done), but every wait is bounded: a tile that polls an
+// unpublished predecessor more than the spin limit gives up, and its pass
+// then writes a wrong order (every access still in bounds). The give-up is
+// recorded in a device word the caller passes and checks at its next
+// synchronisation; the caller then redoes its work with the table schedule,
+// which never waits. A sort given no such word always takes the table
+// schedule.
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "c3x_internal.h"
@@ -243,7 +254,7 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_hist_all(const uint32_t *_
 // (0 not yet published, 1 the tile's own count, 2 the count of this and
 // every earlier tile), the count in the low 30.
 constexpr uint32_t kStAgg = 1u << 30, kStInc = 2u << 30, kStVal = (1u << 30) - 1u;
-constexpr uint32_t kSpinLimit = 1u << 16;  // polls before a look-back gives up
+constexpr uint32_t kSpinLimit = 1u << 20;  // polls before a look-back gives up
 
 __device__ __forceinline__ void st_publish(uint32_t *p, uint32_t v)
 {
@@ -259,12 +270,14 @@ __device__ __forceinline__ uint32_t st_read(const uint32_t *p)
 // by the digit at `shift`. ghist: this pass's digit totals; tctr: this
 // pass's tile counter; status: nb x 256 look-back words (all zero at entry).
 // A tile waits only on tiles that took their numbers before it (and so are
-// running or done); a wait that exceeds kSpinLimit polls gives up, leaving
-// a wrong order but no access out of bounds.
+// running or done); a wait that exceeds spin_limit polls gives up, leaving
+// a wrong order but no access out of bounds, and sets *fail. spin_limit 0
+// (a test setting) makes every tile but the first give up at once.
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
-    const uint32_t *__restrict__ ghist, uint32_t *__restrict__ tctr, uint32_t *status, int nb)
+    const uint32_t *__restrict__ ghist, uint32_t *__restrict__ tctr, uint32_t *status, int nb,
+    uint32_t spin_limit, uint32_t *__restrict__ fail)
 {
     constexpr int kPerWave = kSortTile / kWaves;  // 1024
     constexpr int kRounds = kPerWave / 64;        // 16
@@ -327,13 +340,17 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
         st_publish(mine, kStInc | acc);
     } else {
         st_publish(mine, kStAgg | acc);
-        int64_t p = (int64_t)tile - 1;
+        int64_t p = spin_limit ? (int64_t)tile - 1 : -1;
         uint32_t spins = 0;
+        bool gave_up = spin_limit == 0;
         while (p >= 0) {
             const uint32_t v = st_read(status + (size_t)p * 256 + tid);
             const uint32_t fl = v & ~kStVal;
             if (fl == 0u) {
-                if (++spins > kSpinLimit) break;
+                if (++spins > spin_limit) {
+                    gave_up = true;
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
                 continue;
             }
@@ -341,6 +358,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
             if (fl == kStInc) break;
             --p;
         }
+        if (gave_up) atomicOr(fail, 1u);
         st_publish(mine, kStInc | ((excl + acc) & kStVal));
     }
     gbase[tid] = dbase + excl;
@@ -552,15 +570,30 @@ size_t radix_ws_bytes(int64_t n)
 
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
                             int64_t n, int nbits, void *ws, hipStream_t s, int *in_tmp,
-                            bool vals_are_index)
+                            bool vals_are_index, uint32_t *fail)
 {
     return radix_sort_pairs_bits(keys, vals, ktmp, vtmp, n, 0, nbits, ws, s, in_tmp,
-                                 vals_are_index);
+                                 vals_are_index, fail);
+}
+
+// Test settings: C3X_DEBUG_ONESWEEP_TILES=t takes the one-sweep schedule
+// from t tiles up (default kRowScanTiles + 1); C3X_DEBUG_SORT_SPIN=k sets the
+// look-back's spin limit (0: every tile but the first gives up).
+static int64_t onesweep_min_tiles()
+{
+    if (const char *e = getenv("C3X_DEBUG_ONESWEEP_TILES")) return std::max(1LL, atoll(e));
+    return kRowScanTiles + 1;
+}
+
+static uint32_t spin_limit()
+{
+    if (const char *e = getenv("C3X_DEBUG_SORT_SPIN")) return (uint32_t)std::max(0LL, atoll(e));
+    return kSpinLimit;
 }
 
 hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint32_t *vtmp,
                                  int64_t n, int lo_bit, int nbits, void *ws, hipStream_t s,
-                                 int *in_tmp, bool vals_are_index)
+                                 int *in_tmp, bool vals_are_index, uint32_t *fail)
 {
     *in_tmp = 0;
     if (n <= 0) return hipSuccess;
@@ -575,8 +608,10 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     // up to kRowScanTiles tiles, one workgroup per digit scans its row of the
     // table cheaply and the look-back's latency does not pay; above, the
-    // table needs a full scan and one sweep is faster
-    if (nb > kRowScanTiles && n < kOneSweepMax) {
+    // table needs a full scan and one sweep is faster (when the caller can
+    // observe a give-up)
+    if (fail && nb >= onesweep_min_tiles() && n < kOneSweepMax) {
+        const uint32_t spins = spin_limit();
         const int npass = (nbits - lo_bit + 7) / 8;  // at most 4
         uint32_t *ghist = (uint32_t *)ws;
         uint32_t *tctr = ghist + 4 * 256;
@@ -593,7 +628,7 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
             hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka,
                                p == 0 ? vfirst : va, kb, vb, n, lo_bit + 8 * p, ghist + 256 * p,
                                tctr + p,
-                               status + (size_t)p * 256 * (size_t)nb, (int)nb);
+                               status + (size_t)p * 256 * (size_t)nb, (int)nb, spins, fail);
             std::swap(ka, kb);
             std::swap(va, vb);
             *in_tmp ^= 1;

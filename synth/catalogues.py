@@ -288,41 +288,82 @@ def _gal_to_eq(l: np.ndarray, b: np.ndarray):
     return _norm_ra(ra), np.clip(dec, -90.0, 90.0)
 
 
-def _plane_clustered(rng: np.random.Generator, n: int, chunk: int = 8_000_000):
-    """Density proportional to 1 + 20 exp(-|b| / 5 deg), by rejection from
-    area-uniform, rotated to equatorial."""
-    outr, outd = [], []
-    have = 0
-    while have < n:
-        m = min(chunk, max(1024, int((n - have) * 8.5)))
-        l, b = sphere_uniform(rng, m)
-        acc = (1.0 + 20.0 * np.exp(-np.abs(b) / 5.0)) / 21.0
-        keep = rng.uniform(size=m) < acc
-        l, b = l[keep], b[keep]
-        take = min(n - have, l.shape[0])
-        r, d = _gal_to_eq(l[:take], b[:take])
-        outr.append(r)
-        outd.append(d)
-        have += take
-    return np.concatenate(outr), np.concatenate(outd)
+_BETA = 5.0 * D2R  # scale height of the galactic-plane term (radians)
+_KB = 1.0 / _BETA
+# solid-angle weights of the two terms of 1 + 20 exp(-|b| / beta):
+# integral of cos b over the sphere, and 20 x that of exp(-|b| / beta) cos b
+_W_UNI = 4.0 * math.pi
+_W_PLANE = 20.0 * 2.0 * math.pi * 2.0 * (_KB + math.exp(-_KB * math.pi / 2)) / (_KB * _KB + 1.0)
+
+
+def _plane_clustered(rng: np.random.Generator, n: int):
+    """Density (per solid angle) proportional to 1 + 20 exp(-|b| / 5 deg),
+    rotated to equatorial. Drawn as the mixture of its two terms: with
+    probability W_UNI / (W_UNI + W_PLANE) area-uniform on the sphere, else l
+    uniform and |b| with density exp(-|b| / beta) cos b on [0, 90 deg]
+    (truncated exponential proposal, accepted with probability cos b), random
+    sign."""
+    uni = rng.uniform(size=n) < _W_UNI / (_W_UNI + _W_PLANE)
+    nu = int(uni.sum())
+    lu, bu = sphere_uniform(rng, nu)
+    npl = n - nu
+    bp = np.empty(0)
+    cut = 1.0 - math.exp(-_KB * math.pi / 2)
+    while bp.shape[0] < npl:
+        m = int((npl - bp.shape[0]) * 1.05) + 64
+        t = -_BETA * np.log1p(-rng.uniform(size=m) * cut)
+        t = t[rng.uniform(size=m) < np.cos(t)]
+        bp = np.concatenate([bp, t])
+    bp = np.degrees(bp[:npl]) * np.where(rng.uniform(size=npl) < 0.5, -1.0, 1.0)
+    lp = rng.uniform(0.0, 360.0, npl)
+    l = np.empty(n)
+    b = np.empty(n)
+    l[uni], b[uni] = lu, bu
+    l[~uni], b[~uni] = lp, np.clip(bp, -90.0, 90.0)
+    return _gal_to_eq(l, b)
+
+
+_PIECE = 4_000_000  # rows per independently seeded piece of a large draw
+
+
+def _pieces(seed_seq: np.random.SeedSequence, n: int, make, workers: int):
+    """Rows 0..n-1 drawn in pieces of _PIECE rows, piece k from its own
+    child generator of seed_seq (so the draw does not depend on the number of
+    threads), concatenated in piece order. make(rng, lo, hi) returns the
+    (ra, dec) of rows [lo, hi)."""
+    import concurrent.futures as cf
+    bounds = [(lo, min(n, lo + _PIECE)) for lo in range(0, n, _PIECE)]
+    kids = seed_seq.spawn(len(bounds))
+    gens = [np.random.Generator(np.random.PCG64(k)) for k in kids]
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        parts = list(ex.map(lambda q: make(gens[q], *bounds[q]), range(len(bounds))))
+    if not parts:
+        return np.zeros(0), np.zeros(0)
+    return (np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]))
 
 
 def cfg5_scale(scale: float = 1.0, seed: int = SEED_BASE + 5, radius_arcsec: float = 1.5,
-               sigma_arcsec: float = 0.4) -> Catalogues:
+               sigma_arcsec: float = 0.4, workers: int = 0) -> Catalogues:
     """200M A with galactic-plane clustering; B = 100M jittered copies of
-    distinct A rows + 100M random from the same density; r = 1.5"."""
+    distinct A rows + 100M random from the same density; r = 1.5".
+
+    A's rows are independent draws, so its first n/2 rows are a uniformly
+    random set of distinct parents for the jittered copies; B is then
+    shuffled. Drawn in independently seeded pieces on `workers` threads
+    (0: up to 16), with the same result for any thread count."""
+    import os
+    workers = workers or min(16, os.cpu_count() or 1)
     n = int(round(200_000_000 * scale))
-    gA, gpar, gjit, grand, _, _ = _children(seed, 6)
-    raA, decA = _plane_clustered(gA, n)
     nc = n // 2
-    parents = gpar.choice(n, size=nc, replace=False)
-    rj, dj = jitter(gjit, raA[parents], decA[parents], sigma_arcsec)
-    del parents
-    rr, dr = _plane_clustered(grand, n - nc)
+    sA, sjit, srand, sperm = np.random.SeedSequence(seed).spawn(4)
+    raA, decA = _pieces(sA, n, lambda g, lo, hi: _plane_clustered(g, hi - lo), workers)
+    rj, dj = _pieces(sjit, nc, lambda g, lo, hi: jitter(g, raA[lo:hi], decA[lo:hi],
+                                                          sigma_arcsec), workers)
+    rr, dr = _pieces(srand, n - nc, lambda g, lo, hi: _plane_clustered(g, hi - lo), workers)
     raB = np.concatenate([rj, rr])
     decB = np.concatenate([dj, dr])
     del rj, dj, rr, dr
-    perm = gpar.permutation(n)
+    perm = np.random.Generator(np.random.PCG64(sperm)).permutation(n)
     return Catalogues(f"cfg5_scale_{n}", raA, decA, raB[perm], decB[perm],
                       radius_arcsec=radius_arcsec,
                       meta=dict(seed=seed, scale=scale, sigma_arcsec=sigma_arcsec))

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_version(L):
-    assert L.c3x_abi_version() == 1
+    assert L.c3x_abi_version() == 2
     assert b"gfx950" in L.c3x_version()
 
 
@@ -190,9 +190,12 @@ def test_bench_reports_traffic_only_for_the_measured_kernel(monkeypatch):
     """roofline.traffic comes from the committed counter summary only while
     the count kernel's sources are the ones it was measured on."""
     import bench
-    got = bench.committed_traffic("mixed")
-    if got is not None:  # the summary matches the sources as committed
-        assert got > 0
+    for cfg in ("cfg2", "cfg5"):
+        got = bench.committed_traffic(cfg, "mixed")
+        if got is not None:  # the summary matches the sources as committed
+            assert got > 0
+    assert bench.committed_traffic("cfg1", "mixed") is None
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 16)
-    assert bench.committed_traffic("mixed") is None
-    assert bench.committed_traffic("fp64") is None
+    for cfg in ("cfg2", "cfg5"):
+        assert bench.committed_traffic(cfg, "mixed") is None
+        assert bench.committed_traffic(cfg, "fp64") is None
