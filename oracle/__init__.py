@@ -113,7 +113,7 @@ def _area(shape, radius_arcsec, a, b, pa, pa_zero_deg, pa_sense):
     ar.pa_zero_deg = float(pa_zero_deg)
     ar.pa_sense = int(pa_sense)
     keep = []
-    if shape == 1:
+    if shape in (1, 2):
         for name, v in (("a_arcsec", a), ("b_arcsec", b), ("pa_deg", pa)):
             v = np.ascontiguousarray(v, dtype=np.float64)
             keep.append(v)
@@ -123,8 +123,8 @@ def _area(shape, radius_arcsec, a, b, pa, pa_zero_deg, pa_sense):
 
 def validate(raA, decA, raB, decB, shape, radius_arcsec, a, b, pa, pa_sense):
     """Input domain of the cross-match: RA in [0, 360), |Dec| <= 90, finite;
-    radius 0 or in [1e-6", 90 deg]; ellipse 1e-6" <= b <= a <= 90 deg,
-    a/b <= 1000, PA finite; pa_sense +1 or -1."""
+    radius 0 or in [1e-6", 90 deg]; ellipse semi-axes or rectangle half-sides
+    1e-6" <= b <= a <= 90 deg, a/b <= 1000, PA finite; pa_sense +1 or -1."""
     for name, ra, de in (("A", raA, decA), ("B", raB, decB)):
         if not (np.all(np.isfinite(ra)) and np.all(np.isfinite(de))):
             raise ValueError(f"catalogue {name}: non-finite coordinate")
@@ -134,6 +134,8 @@ def validate(raA, decA, raB, decB, shape, radius_arcsec, a, b, pa, pa_sense):
             raise ValueError(f"catalogue {name}: |Dec| > 90")
     if pa_sense not in (1, -1):
         raise ValueError("pa_sense must be +1 or -1")
+    if shape not in (0, 1, 2):
+        raise ValueError("shape must be 0 (circle), 1 (ellipse) or 2 (rectangle)")
     if shape == 0:
         r = float(radius_arcsec)
         if not (r == 0.0 or (1e-6 <= r <= 324000.0)):
@@ -165,7 +167,10 @@ def match(raA, decA, raB, decB, shape: int = 0, radius_arcsec: float = 1.0,
     if nthreads is None:
         nthreads = os.cpu_count() or 1
     if zone_deg is None:
-        reach = (float(np.max(a)) if (shape == 1 and nA) else float(radius_arcsec)) / 3600.0
+        if shape == 2 and nA:
+            reach = float(np.max(np.hypot(a, b))) / 3600.0
+        else:
+            reach = (float(np.max(a)) if (shape == 1 and nA) else float(radius_arcsec)) / 3600.0
         zone_deg = max(reach, 180.0 / 4_000_000)
     ar, keep = _area(shape, radius_arcsec, a, b, pa, pa_zero_deg, pa_sense)
     out = _Out()
@@ -190,6 +195,9 @@ def match(raA, decA, raB, decB, shape: int = 0, radius_arcsec: float = 1.0,
         if shape == 1:
             ok = exact.decide_ellipse(raA[i], decA[i], raB[j], decB[j], a[i], b[i], pa[i],
                                       pa_zero_deg, pa_sense)
+        elif shape == 2:
+            ok = exact.decide_rect(raA[i], decA[i], raB[j], decB[j], a[i], b[i], pa[i],
+                                   pa_zero_deg, pa_sense)
         else:
             ok = exact.decide_circle(raA[i], decA[i], raB[j], decB[j], radius_arcsec)
         keep_amb.append(ok)
@@ -272,4 +280,6 @@ def decide_exact(ra1, dec1, ra2, dec2, shape=0, radius_arcsec=1.0, a=0.0, b=0.0,
         return k == 1
     if shape == 1:
         return exact.decide_ellipse(ra1, dec1, ra2, dec2, a, b, pa, pa_zero_deg, pa_sense)
+    if shape == 2:
+        return exact.decide_rect(ra1, dec1, ra2, dec2, a, b, pa, pa_zero_deg, pa_sense)
     return exact.decide_circle(ra1, dec1, ra2, dec2, radius_arcsec)

@@ -23,6 +23,10 @@
  *            rotation are the two extra PA parameters of Section 2.1).
  *            This is the azimuthal-equidistant reading: distances along the
  *            sphere, so a = b gives back theta <= a exactly.
+ *   rectangle: (i, j) in S  <=>  |u| <= a_i and |v| <= b_i           (inclusive)
+ *            with (u, v) as for the ellipse: a_i and b_i are the half-sides
+ *            along and across the orientation T_i (Section 2.1 names the
+ *            rectangular region beside the ellipse and the circle).
  *
  * How: each candidate is decided in FP64 with a proven error bound. The
  * computed quantity (the haversine of theta, or the ellipse form Q) carries a
@@ -48,7 +52,12 @@
  *   absolute error <= ~30 u sin(theta) (every term is bounded by 2 sin
  *   theta, see below), T adds ~17u, so su, sv carry <= ~100 u sin(theta);
  *   Q then has relative error <= ~(300 + 200 a/b) u near Q = 1. The margin
- *   E_ell = 2^-38 (1 + a/b) keeps a ~64x safety factor. (Bound on the second
+ *   E_ell = 2^-38 (1 + a/b) keeps a ~64x safety factor. Rectangle: the two
+ *   forms Qu = (theta/sin theta)^2 (su/a)^2 and Qv (the same with sv/b) are
+ *   decided separately against 1; near Qu = 1, |su| ~ a and sin theta <=
+ *   sqrt(a^2 + b^2) <= 1.42 a, near Qv = 1, |sv| ~ b and sin theta <= a + b,
+ *   so each carries at most ~300 (1 + a/b) u relative and the same margin
+ *   E_ell keeps a ~100x safety factor. (Bound on the second
  *   term of q.n: for |dRA| <= 90 deg, cos d2 sin^2(dRA/2) <= sin theta /
  *   sqrt 2; for |dRA| > 90 deg theta is the largest side of the triangle
  *   (pole, A, B), so cos d2 <= sin theta.)
@@ -97,7 +106,7 @@ typedef struct {
 } c3o_out;
 
 typedef struct {
-    int shape;               /* 0 circle, 1 ellipse */
+    int shape;               /* 0 circle, 1 ellipse, 2 rectangle */
     double radius_arcsec;
     const double *a_arcsec, *b_arcsec, *pa_deg;
     double pa_zero_deg;
@@ -219,6 +228,44 @@ static int decide_ellipse(const opt *p, const opt *q, const ell_par *e)
     if (Q <= 1.0 - e->e) return O_IN;
     if (Q > 1.0 + e->e) return O_OUT;
     return O_AMBIG;
+}
+
+/* Rectangle of half-sides a (along T) and b (across): |u| <= a and
+ * |v| <= b. ep->h_a is the haversine of the half-diagonal here. */
+static ell_par mk_rect(double a_arcsec, double b_arcsec, double pa, double pa_zero, int sense)
+{
+    ell_par e = mk_ell(a_arcsec, b_arcsec, pa, pa_zero, sense);
+    double d = sqrt(a_arcsec * a_arcsec + b_arcsec * b_arcsec) * (1.0 + 1e-15);
+    double s = sin(KHALF * (d / 3600.0));
+    e.h_a = s * s;
+    return e;
+}
+
+static int decide_rect(const opt *p, const opt *q, const ell_par *e)
+{
+    double h = hav_of(p, q);
+    if (h == 0.0) return O_IN;
+    /* beyond the half-diagonal: outside the rectangle */
+    if (h > e->h_a * (1.0 + E64)) return O_OUT;
+    double tn, te;
+    tangent(p, q, &tn, &te);
+    double th = 2.0 * asin(sqrt(h));
+    double sth = 2.0 * sqrt(h) * sqrt(1.0 - h);
+    double f = th / sth;
+    double su = tn * e->ct + te * e->st;
+    double sv = te * e->ct - tn * e->st;
+    double x = su / e->ar, y = sv / e->br;
+    double Qu = (f * f) * (x * x), Qv = (f * f) * (y * y);
+    if (Qu > 1.0 + e->e || Qv > 1.0 + e->e) return O_OUT;
+    if (Qu <= 1.0 - e->e && Qv <= 1.0 - e->e) return O_IN;
+    return O_AMBIG;
+}
+
+static int decide_area(const opt *p, const opt *q, int shape, const ell_par *e, double h_r)
+{
+    if (shape == 1) return decide_ellipse(p, q, e);
+    if (shape == 2) return decide_rect(p, q, e);
+    return decide_circle(p, q, h_r);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -402,6 +449,10 @@ static int cmp_hit(const void *x, const void *y)
 static double reach_deg(const c3o_area *ar, int64_t i)
 {
     if (ar->shape == 1) return ar->a_arcsec[i] / 3600.0;
+    if (ar->shape == 2) {
+        double a = ar->a_arcsec[i], b = ar->b_arcsec[i];
+        return sqrt(a * a + b * b) * (1.0 + 1e-15) / 3600.0;  /* the half-diagonal */
+    }
     return ar->radius_arcsec / 3600.0;
 }
 
@@ -419,14 +470,17 @@ static void *run_chunk(void *arg)
     for (int64_t i = jb->a0; i < jb->a1 && !jb->err; i++) {
         const opt *p = &jb->A[i];
         ell_par ep;
+        memset(&ep, 0, sizeof(ep));
         if (ar->shape == 1)
             ep = mk_ell(ar->a_arcsec[i], ar->b_arcsec[i], ar->pa_deg[i], ar->pa_zero_deg, ar->pa_sense);
+        else if (ar->shape == 2)
+            ep = mk_rect(ar->a_arcsec[i], ar->b_arcsec[i], ar->pa_deg[i], ar->pa_zero_deg, ar->pa_sense);
         int64_t nh = 0;
 #define CONSIDER(J)                                                              \
     do {                                                                         \
         int64_t jj_ = (J);                                                       \
         const opt *q_ = &jb->B[jj_];                                             \
-        int k_ = ar->shape == 1 ? decide_ellipse(p, q_, &ep) : decide_circle(p, q_, h_r); \
+        int k_ = decide_area(p, q_, ar->shape, &ep, h_r);                       \
         jb->tests++;                                                             \
         if (k_ != O_OUT) {                                                       \
             if (nh == hcap) {                                                    \
@@ -637,6 +691,11 @@ int c3o_decide(double ra1, double dec1, double ra2, double dec2, const c3o_area 
         ell_par e = mk_ell(area->a_arcsec[i], area->b_arcsec[i], area->pa_deg[i],
                            area->pa_zero_deg, area->pa_sense);
         return decide_ellipse(&p, &q, &e);
+    }
+    if (area->shape == 2) {
+        ell_par e = mk_rect(area->a_arcsec[i], area->b_arcsec[i], area->pa_deg[i],
+                            area->pa_zero_deg, area->pa_sense);
+        return decide_rect(&p, &q, &e);
     }
     double s = sin(KHALF * (area->radius_arcsec / 3600.0));
     return decide_circle(&p, &q, s * s);

@@ -10,6 +10,8 @@ as exact reals:
 * ellipse: (theta/sin theta)^2 [(su/a)^2 + (sv/b)^2] <= 1, with (su, sv) the
   tangent-plane components of B seen from A rotated by T = pa_zero +
   pa_sense * PA (north towards east). a = b reduces to theta <= a.
+* rectangle: (theta/sin theta) |su| <= a and (theta/sin theta) |sv| <= b
+  (half-sides a along T, b across).
 * best   : argmin over the matches of (theta, j), exact; an exact tie goes to
   the lower j (Section 2.2 keeps "only the best pairs"; the tie rule is the
   reading taken here).
@@ -82,6 +84,41 @@ def decide_circle(ra1, dec1, ra2, dec2, r_arcsec) -> bool:
         return diff < 0
 
 
+def axis_xy(ra1, dec1, ra2, dec2, a_arcsec, b_arcsec, pa_deg, pa_zero_deg=0.0, pa_sense=1):
+    """(u/a, v/b) at 200 bits: the azimuthal-equidistant coordinates of B seen
+    from A (theta times the cosine and sine of the bearing from the axis T)
+    over the semi-axes (half-sides); (0, 0) at theta = 0."""
+    with _prec():
+        k = _k()
+        d1, d2, dd, da = _pieces(ra1, dec1, ra2, dec2)
+        h = mpmath.sin(dd / 2) ** 2 + mpmath.cos(d1) * mpmath.cos(d2) * mpmath.sin(da / 2) ** 2
+        if h <= 0:
+            return mpf(0), mpf(0)
+        th = 2 * mpmath.asin(mpmath.sqrt(h))
+        tn = mpmath.sin(dd) + 2 * mpmath.sin(d1) * mpmath.cos(d2) * mpmath.sin(da / 2) ** 2
+        te = mpmath.cos(d2) * mpmath.sin(da)
+        T = (mpf(float(pa_zero_deg)) + int(pa_sense) * mpf(float(pa_deg))) * k
+        su = tn * mpmath.cos(T) + te * mpmath.sin(T)
+        sv = te * mpmath.cos(T) - tn * mpmath.sin(T)
+        A = mpf(float(a_arcsec)) / 3600 * k
+        B = mpf(float(b_arcsec)) / 3600 * k
+        f = th / mpmath.sin(th)
+        return f * su / A, f * sv / B
+
+
+def decide_rect(ra1, dec1, ra2, dec2, a_arcsec, b_arcsec, pa_deg, pa_zero_deg=0.0,
+                pa_sense=1) -> bool:
+    """Rectangle of half-sides a (along T) and b (across): |u| <= a and
+    |v| <= b, each boundary inclusive (a value within TIE_REL of it counts as
+    on it)."""
+    with _prec():
+        x, y = axis_xy(ra1, dec1, ra2, dec2, a_arcsec, b_arcsec, pa_deg, pa_zero_deg, pa_sense)
+        for t in (abs(x), abs(y)):
+            if t > 1 and abs(t - 1) > TIE_REL:
+                return False
+        return True
+
+
 def ellipse_q(ra1, dec1, ra2, dec2, a_arcsec, b_arcsec, pa_deg, pa_zero_deg=0.0, pa_sense=1):
     """The ellipse form Q (1 on the boundary) at 200 bits."""
     with _prec():
@@ -143,7 +180,10 @@ def brute(raA, decA, raB, decB, shape=0, radius_arcsec=1.0, a=None, b=None, pa=N
     best: List[int] = []
     k = math.pi / 180
     for i in range(raA.shape[0]):
-        reach = (a[i] if shape == 1 else radius_arcsec) / 3600.0 * k
+        if shape == 2:
+            reach = math.hypot(a[i], b[i]) / 3600.0 * k
+        else:
+            reach = (a[i] if shape == 1 else radius_arcsec) / 3600.0 * k
         dd = (decB - decA[i]) * k
         da = (raB - raA[i]) * k
         h = np.sin(dd / 2) ** 2 + np.cos(decA[i] * k) * np.cos(decB * k) * np.sin(da / 2) ** 2
@@ -154,6 +194,9 @@ def brute(raA, decA, raB, decB, shape=0, radius_arcsec=1.0, a=None, b=None, pa=N
             if shape == 1:
                 ok = decide_ellipse(raA[i], decA[i], raB[j], decB[j], a[i], b[i], pa[i],
                                     pa_zero_deg, pa_sense)
+            elif shape == 2:
+                ok = decide_rect(raA[i], decA[i], raB[j], decB[j], a[i], b[i], pa[i],
+                                 pa_zero_deg, pa_sense)
             else:
                 ok = decide_circle(raA[i], decA[i], raB[j], decB[j], radius_arcsec)
             if ok:
