@@ -82,6 +82,10 @@ def parse():
     p.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"], default="cfg5")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the 10M x 10M full-sky line reported beside the default one")
+    p.add_argument("--no-per-job", action="store_true",
+                   help="batched workload: skip timing the jobs as separate calls")
+    p.add_argument("--core-only", action="store_true",
+                   help="time the step only (no join-type or concentric-ellipse timings)")
     p.add_argument("--scale", type=float, default=1.0,
                    help="shrink the workload (testing only; the reported line uses 1.0)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -291,10 +295,10 @@ def single_config(a, c3x, torch, np, name):
         ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup, area_kw, frame, mode)
         paths[pname] = path_summary(cat, ms, r, ks, 16 if pname == "mixed" else 32,
                                     bool(mode & c3x.BEST))
-        if mode & c3x.ALL:
+        if mode & c3x.ALL and not a.core_only:
             paths[pname]["join_unmatched"] = time_unmatched(c3x, torch, cat, r, a.steps)
         del r
-        if cat.shape == 1:
+        if cat.shape == 1 and not a.core_only:
             paths[pname]["concentric"] = time_concentric(c3x, torch, tens, cat, prec, a.steps,
                                                          area_kw, frame)
         log(f"{pname}: {ms:.3f} ms/step, {paths[pname]['phases_ms']}")
@@ -362,6 +366,27 @@ def single_config(a, c3x, torch, np, name):
     return line
 
 
+def per_job_ms(c3x, torch, tens, jobs, prec, reps=2):
+    """The batch's jobs as separate calls: for each job c3x_build_index over
+    its B rows and c3x_match of its A rows (all + best) on slices of the
+    same device arrays; the last of `reps` passes over all jobs is timed."""
+    raA, decA, raB, decB = tens
+    ms = 0.0
+    for rep in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for (ao, na, bo, nb, r) in jobs:
+            ix = c3x.build_index(raB[bo:bo + nb], decB[bo:bo + nb], reach_hint_arcsec=r,
+                                 precision=prec)
+            res = c3x.match(ix, raA[ao:ao + na], decA[ao:ao + na], radius_arcsec=r,
+                            mode=c3x.ALL | c3x.BEST)
+            ix.free()
+            del res
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+    return ms
+
+
 def batch_config(a, c3x, torch, np):
     import synth
     t = time.perf_counter()
@@ -399,6 +424,11 @@ def batch_config(a, c3x, torch, np):
                             cell_scale=st["cell_arcsec"])
         log(f"{pname}: {ms:.3f} ms/step (graph {mean(gms):.3f} ms), plan {plan_s:.1f}s")
         b.free()
+        if not a.no_per_job:
+            pj = per_job_ms(c3x, torch, tens, jobs, prec)
+            paths[pname]["per_job_ms"] = round(pj, 3)
+            paths[pname]["batched_speedup_vs_per_job"] = round(pj / ms, 3)
+            log(f"{pname}: the same jobs as separate calls {pj:.3f} ms")
     head = paths[order[0]]
     cpu = None
     if not a.no_cpu_baseline:

@@ -22,6 +22,7 @@
  *            T_i = pa_zero_deg + pa_sense * pa_deg[i] is the direction of
  *            the semi-major axis (Section 2.1: the PA has a zero-point and a
  *            direction of rotation). a = b gives theta <= a.
+ *   rectangle: j matches i  <=>  |u| <= a_i and |v| <= b_i (half-sides).
  *   Boundaries are inclusive. best(i) is the match with the smallest exact
  *   theta; an exact tie goes to the lower B row.
  * Every decision is certified: the GPU decides in FP32 (MIXED) or FP64 with
@@ -71,8 +72,12 @@ typedef enum {
  * match must share it. */
 typedef enum { C3X_EQUATORIAL = 0, C3X_GALACTIC = 1 } c3x_frame;
 
-/* Region shape (Section 2.1: the circle as a special ellipse). */
-typedef enum { C3X_CIRCLE = 0, C3X_ELLIPSE = 1 } c3x_shape;
+/* Region shape (Section 2.1: an elliptical, circular -- the special ellipse
+ * -- or rectangular region). C3X_RECT: |u| <= a and |v| <= b in the
+ * ellipse's frame (see the semantics above), a the half-side along the
+ * orientation T, b across it; the area arrays and their domain are the
+ * ellipse's (semi_major_arcsec = a, semi_minor_arcsec = b). */
+typedef enum { C3X_CIRCLE = 0, C3X_ELLIPSE = 1, C3X_RECT = 2 } c3x_shape;
 
 /* Match selection (Section 2.2). OR-able. ALL writes every pair; BEST fills
  * the per-A best arrays; BEST alone writes one pair per matched A row. */
@@ -85,9 +90,9 @@ typedef enum { C3X_FP64 = 0, C3X_MIXED = 1 } c3x_precision;
 typedef struct {
     c3x_shape shape;
     double radius_arcsec;            /* CIRCLE: fixed radius */
-    const double *semi_major_arcsec; /* ELLIPSE: device, nA entries */
-    const double *semi_minor_arcsec; /* ELLIPSE: device, nA entries */
-    const double *pa_deg;            /* ELLIPSE: device, nA entries */
+    const double *semi_major_arcsec; /* ELLIPSE, RECT: device, nA entries */
+    const double *semi_minor_arcsec; /* ELLIPSE, RECT: device, nA entries */
+    const double *pa_deg;            /* ELLIPSE, RECT: device, nA entries */
     double pa_zero_deg;              /* T = pa_zero_deg + pa_sense * PA */
     int pa_sense;                    /* +1 or -1 */
 } c3x_area;
@@ -233,6 +238,29 @@ c3x_status c3x_result_levels(const c3x_result *r, const int32_t **level);
 c3x_status c3x_result_unmatched(c3x_result *r, unsigned selection, void *stream,
                                 const int32_t **rowsA, int64_t *n_rowsA,
                                 const int32_t **rowsB, int64_t *n_rowsB);
+
+/* Symmetric best pairs (Section 2.2, the "best" match selection, read as
+ * the pairs that are each other's nearest match). Seen from catalogue B,
+ * each B row's nearest A row is the one at the smallest exact angle among
+ * the A rows whose areas hold it (an exact tie goes to the lower A row);
+ * (i, j) is a symmetric best pair when j is the best match of A row i and i
+ * is the nearest A row of B row j. Each row of either catalogue is in at
+ * most one such pair. r must come from c3x_match with mode C3X_ALL |
+ * C3X_BEST; raA/decA and raB/decB are the device arrays of that call (nA
+ * and nB entries), read only to rank, in binary128 on the host, the B rows
+ * whose nearest A rows the stored FP64 separations cannot tell apart (within
+ * 2.5e-8" + 2^-38 relative). On return *idxA, *idxB, *sep (device arrays
+ * owned by r, valid until c3x_result_free and overwritten by the next call
+ * on r) hold the *n_pairs symmetric pairs in ascending A row, with the
+ * pair's stored separation (arcsec); *best_a_of_b (may be NULL) the nearest
+ * A row of every B row (-1: in no pair). Work is ordered on `stream` (NULL:
+ * the null stream), which is synchronised before the call returns.
+ * Errors: C3X_EINVAL (NULL argument, batch result, mode without both
+ * C3X_ALL and C3X_BEST), C3X_ENOMEM, C3X_EDEVICE. */
+c3x_status c3x_result_mutual(c3x_result *r, const double *raA, const double *decA,
+                             const double *raB, const double *decB, void *stream,
+                             const int32_t **idxA, const int32_t **idxB, const double **sep,
+                             int64_t *n_pairs, const int32_t **best_a_of_b);
 
 /* Counters and timings of the call that produced r (or of an index). */
 c3x_status c3x_result_stats(const c3x_result *r, c3x_stats *s);

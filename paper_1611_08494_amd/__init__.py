@@ -1,10 +1,11 @@
 """MI355X positional cross-match (the "Sky" case of the C^3 tool, arXiv:1611.08494).
 
 Python face of libc3x.so: ``build_index`` over catalogue B and ``match`` of
-catalogue A against it, circle or per-source ellipse areas, "all" and "best"
+catalogue A against it, circle, per-source ellipse or rectangle areas, "all" and "best"
 selections, equatorial or galactic frames; ``match_concentric`` for
 ClumpPopulator's concentric ellipses (Section 3); ``unmatched`` and ``join`` for
 the join types of the paper's Section 2.2 (rows without a stored match);
+``mutual`` for the symmetric best pairs (each other's nearest match);
 ``Batch`` for many independent circular jobs in one graph launch. All computation happens in the
 HIP library; torch tensors only carry device memory and streams.
 """
@@ -19,6 +20,7 @@ from ._binding import (  # noqa: F401
     GALACTIC,
     LIB_PATH,
     MIXED,
+    RECT,
     C3XError,
     Index,
     MatchResult,
@@ -28,6 +30,7 @@ from ._binding import (  # noqa: F401
     lib,
     match,
     match_concentric,
+    mutual,
     result_copy,
     unmatched,
     version,

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "_build", "libc3x.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EFRAME = range(6)
 EQUATORIAL, GALACTIC = 0, 1
-CIRCLE, ELLIPSE = 0, 1
+CIRCLE, ELLIPSE, RECT = 0, 1, 2
 ALL, BEST = 1, 2
 FP64, MIXED = 0, 1
 _STATUS = {0: "C3X_OK", 1: "C3X_EINVAL", 2: "C3X_ERANGE", 3: "C3X_ENOMEM", 4: "C3X_EDEVICE",
@@ -106,6 +106,9 @@ def lib():
                                        ctypes.POINTER(dbl), i32, ctypes.c_uint,
                                        ctypes.POINTER(Opts), ctypes.POINTER(vp)]
     L.c3x_match_concentric.restype = ctypes.c_int
+    L.c3x_result_mutual.argtypes = [vp, vp, vp, vp, vp, vp, pvp, pvp, pvp, ctypes.POINTER(i64),
+                                    pvp]
+    L.c3x_result_mutual.restype = ctypes.c_int
     L.c3x_result_levels.argtypes = [vp, pvp]
     L.c3x_result_levels.restype = ctypes.c_int
     L.c3x_result_unmatched.restype = ctypes.c_int
@@ -283,7 +286,7 @@ def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
         raise ValueError("ra and dec differ in length")
     ar = Area(shape=int(shape), radius_arcsec=float(radius_arcsec), pa_zero_deg=float(pa_zero_deg),
               pa_sense=int(pa_sense))
-    if shape == ELLIPSE:
+    if shape in (ELLIPSE, RECT):
         for nm, v in (("a", a), ("b", b), ("pa", pa)):
             v = _dev_f64(v, nm)
             if v.shape != ra.shape:
@@ -434,6 +437,35 @@ def unmatched(result: MatchResult, selection: int = ALL, stream=None):
         else:
             out.append(torch.as_tensor(_DeviceArray(owner, p.value, n, "<i4"), device=dev))
     return out[0], out[1]
+
+
+def mutual(result: MatchResult, raA, decA, raB, decB, stream=None):
+    """Symmetric best pairs (c3x_result_mutual) of a result made with ALL |
+    BEST, given the coordinate tensors of that match: int32 idxA, idxB and
+    float64 sep of the pairs that are each other's nearest match (ascending
+    A row), and best_a_of_b, the nearest A row of every B row (-1: none).
+    The tensors view arrays owned by the result (a later call on it
+    overwrites them)."""
+    torch = _torch()
+    owner = result._owner
+    if owner is None or not owner.handle:
+        raise ValueError("result has no library handle")
+    ts = [_dev_f64(x, n) for x, n in ((raA, "raA"), (decA, "decA"), (raB, "raB"), (decB, "decB"))]
+    pa, pb, ps, pbb = (ctypes.c_void_p() for _ in range(4))
+    n = ctypes.c_int64()
+    check(lib().c3x_result_mutual(owner.handle, *[t.data_ptr() for t in ts], _stream_ptr(stream),
+                                  ctypes.byref(pa), ctypes.byref(pb), ctypes.byref(ps),
+                                  ctypes.byref(n), ctypes.byref(pbb)))
+    dev = result.best_idx.device
+    out = []
+    for p, m, ts_, dt in ((pa, n.value, "<i4", torch.int32), (pb, n.value, "<i4", torch.int32),
+                          (ps, n.value, "<f8", torch.float64),
+                          (pbb, int(ts[2].shape[0]), "<i4", torch.int32)):
+        if m == 0 or not p.value:
+            out.append(torch.empty(0 if p is not pbb else m, dtype=dt, device=dev))
+        else:
+            out.append(torch.as_tensor(_DeviceArray(owner, p.value, m, ts_), device=dev))
+    return tuple(out)
 
 
 # join type -> (stored pairs, unmatched A rows, unmatched B rows), Section 2.2

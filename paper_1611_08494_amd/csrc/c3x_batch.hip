@@ -208,13 +208,15 @@ __global__ void k_bgather_b(const uint32_t *__restrict__ rows, const BJob *__res
     const double a = ad.x, d = ad.y;
     double x, y, z;
     unit_vec(a, d, x, y, z);
-    Pay64 q;
-    q.x = x;
-    q.y = y;
-    q.z = z;
-    q.idx = e;
-    q.pad = 0;
-    p64[s] = q;
+    if (p64) {
+        Pay64 q;
+        q.x = x;
+        q.y = y;
+        q.z = z;
+        q.idx = e;
+        q.pad = 0;
+        p64[s] = q;
+    }
     if (p32) {
         Pay32 f;
         f.x = (float)(x - jb.cx);
@@ -282,7 +284,7 @@ __global__ void k_brecheck(const uint2 *__restrict__ band, const uint32_t *__res
                            uint32_t cap, const double2 *__restrict__ arad,
                            const uint32_t *__restrict__ aidx, const uint32_t *__restrict__ ajob,
                            const BJob *__restrict__ jobs, const double2 *__restrict__ coordB,
-                           const Pay64 *__restrict__ p64, uint4 *__restrict__ bin,
+                           BRows brows, uint4 *__restrict__ bin,
                            uint32_t *__restrict__ n_bin, uint32_t bin_cap,
                            BAmb *__restrict__ hl, uint32_t *__restrict__ n_hl, uint32_t hl_cap,
                            uint32_t *__restrict__ flags)
@@ -291,7 +293,8 @@ __global__ void k_brecheck(const uint2 *__restrict__ band, const uint32_t *__res
     if (t >= min(*n_band, cap)) return;
     const uint2 q = band[t];
     const double2 ad = arad[q.x];
-    const double2 rb = coordB[p64[q.y].idx];
+    const uint32_t idxB = brows(q.y);
+    const double2 rb = coordB[idxB];
     const BJob &jb = jobs[ajob[q.x]];
     ARec a;
     a.ra = ad.x;
@@ -304,7 +307,7 @@ __global__ void k_brecheck(const uint2 *__restrict__ band, const uint32_t *__res
     const int d = recheck_circle(a, rb, jb.h_r);
     if (d == IN) {
         const uint32_t s = atomicAdd(n_bin, 1u);
-        if (s < bin_cap) bin[s] = make_uint4(q.x, a.idx, p64[q.y].idx, q.y);
+        if (s < bin_cap) bin[s] = make_uint4(q.x, a.idx, idxB, q.y);
         else atomicOr(flags, kBFlagCap);
     } else if (d == AMBIG) {
         const uint32_t s = atomicAdd(n_hl, 1u);
@@ -318,7 +321,7 @@ __global__ void k_brecheck(const uint2 *__restrict__ band, const uint32_t *__res
             h.i = q.x;
             h.j = q.y;
             h.idxA = a.idx;
-            h.idxB = p64[q.y].idx;
+            h.idxB = idxB;
             hl[s] = h;
         } else {
             atomicOr(flags, kBFlagCap);
@@ -392,7 +395,7 @@ __global__ void k_blocal_best(const BJob *__restrict__ jobs, const uint32_t *__r
 __global__ void k_bpatch(const uint32_t *__restrict__ pos, const uint32_t *__restrict__ bj,
                          uint32_t n, const uint32_t *__restrict__ aidx,
                          const double2 *__restrict__ arad, const double2 *__restrict__ coordB,
-                         const Pay64 *__restrict__ p64, const BJob *__restrict__ jobs,
+                         BRows brows, const BJob *__restrict__ jobs,
                          const uint32_t *__restrict__ ajob, int32_t *__restrict__ best,
                          double *__restrict__ bsep)
 {
@@ -401,8 +404,9 @@ __global__ void k_bpatch(const uint32_t *__restrict__ pos, const uint32_t *__res
     const uint32_t i = pos[t], j = bj[t];
     const uint32_t a = aidx[i];
     const BJob &jb = jobs[ajob[i]];
-    best[a] = (int32_t)(p64[j].idx - jb.b_ent);
-    const double2 ra = arad[i], rb = coordB[p64[j].idx];
+    const uint32_t e = brows(j);
+    best[a] = (int32_t)(e - jb.b_ent);
+    const double2 ra = arad[i], rb = coordB[e];
     bsep[a] = sep_arcsec_rd(ra.x, ra.y, rb.x, rb.y);
 }
 
@@ -642,7 +646,8 @@ static hipError_t batch_front(c3x_batch *b)
     // band candidates: FP64 recheck, then the host decides what is left
     hipLaunchKernelGGL(k_brecheck, dim3(nblk(b->amb_cap, 256)), dim3(256), 0, s, b->amb,
                        b->ctr + 1, b->amb_cap, b->arad, b->aidx, b->ajob, b->djobs, b->coordB,
-                       b->p64, b->bin, b->ctr + 8, b->bin_cap, b->hl, b->ctr + 9, b->hl_cap,
+                       BRows{b->p64, b->p32}, b->bin, b->ctr + 8, b->bin_cap, b->hl, b->ctr + 9,
+                       b->hl_cap,
                        b->ctr);
     e = hipMemcpyAsync(b->h_cnt, b->ctr + 9, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
@@ -693,7 +698,7 @@ static hipError_t batch_back(c3x_batch *b)
                            b->ovl, b->ov_pool, b->octr, NA, b->off, b->P_cap, b->pt, b->c64 + 2,
                            b->ctr + 4);
     hipLaunchKernelGGL(k_place_x, dim3(nblk(b->bin_cap, 256)), dim3(256), 0, s, b->xent,
-                       b->bin_cap, b->ctr + 8, b->aidx, b->arad, b->coordB, b->p64, NA, b->NB,
+                       b->bin_cap, b->ctr + 8, b->aidx, b->arad, b->coordB, NA, b->NB,
                        b->off,
                        b->P_cap, b->rec, 1, b->pt, b->c64 + 2, b->ctr + 4);
     FinishArgs fa{};
@@ -703,12 +708,10 @@ static hipError_t batch_back(c3x_batch *b)
     fa.off = b->off;
     fa.rec = b->rec;
     fa.use_rec = 1;
-    fa.rare = 0;
+    fa.defer = b->prec == C3X_MIXED ? 1 : 0;
     fa.tmp = b->pt;
-    fa.raA = nullptr;
-    fa.decA = nullptr;
+    fa.coordA = b->packA;  // A coordinates in entry order
     fa.coordB = b->coordB;
-    fa.payB = b->p64;
     fa.best_idx = b->obest;
     fa.oa = b->oa;
     fa.ob = b->ob;
@@ -1000,10 +1003,11 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->bk2 = M.get_n<uint32_t>(NB);
     b->bv2 = M.get_n<uint32_t>(NB);
     b->bws = M.get(radix_ws_bytes(NB));
-    b->p64 = M.get_n<Pay64>(NB);
+    // one payload: FP64 unit vectors, or FP32 offsets from the job centres
     if (b->prec == C3X_MIXED) b->p32 = M.get_n<Pay32>(NB);
+    else b->p64 = M.get_n<Pay64>(NB);
     b->packB = M.get_n<double2>(std::max<int64_t>(NB, 1));
-    b->coordB = b->packB;  // B coordinates in entry order, reached through p64[j].idx
+    b->coordB = b->packB;  // B coordinates in entry order, reached through the payload's row
     b->packA = M.get_n<double2>(std::max<int64_t>(NA, 1));
     const int64_t dmax = std::max<int64_t>(1024, 2 * NB) + 2;
     b->dir = M.get_n<uint32_t>(dmax);
@@ -1050,8 +1054,8 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->obest = M.get_n<int32_t>(NA);
     b->obsep = M.get_n<double>(NA);
     b->joboff = M.get_n<int64_t>(nj + 1);
-    bool ok = b->bk && b->bv && b->bk2 && b->bv2 && b->bws && b->p64 &&
-              (b->prec != C3X_MIXED || b->p32) && b->coordB && b->packA && b->packB &&
+    bool ok = b->bk && b->bv && b->bk2 && b->bv2 && b->bws && (b->p64 || b->p32) &&
+              b->coordB && b->packA && b->packB &&
               b->dir && b->gaps && b->n_gaps &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
               b->arng && b->cnts && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
@@ -1224,7 +1228,8 @@ static c3x_status batch_finish(c3x_batch *b)
         BCHK(hipMemcpyAsync(d1, prow.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
         BCHK(hipMemcpyAsync(d2, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
         hipLaunchKernelGGL(k_bpatch, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, np, b->aidx,
-                           b->arad, b->coordB, b->p64, b->djobs, b->ajob, b->obest, b->obsep);
+                           b->arad, b->coordB, BRows{b->p64, b->p32}, b->djobs, b->ajob, b->obest,
+                           b->obsep);
         BCHK(hipGetLastError(), "best patch");
         BCHK(hipStreamSynchronize(s), "best patch");
     }

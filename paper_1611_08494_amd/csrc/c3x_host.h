@@ -160,6 +160,10 @@ struct c3x_result {
     double *best_sep = nullptr;
     int32_t *unA = nullptr, *unB = nullptr;  // unmatched rows (c3x_result_unmatched)
     int32_t *level = nullptr;  // per pair: smallest scale holding it (c3x_match_concentric)
+    // symmetric best pairs (c3x_result_mutual): pairs and each B row's nearest A row
+    int32_t *muA = nullptr, *muB = nullptr, *muBA = nullptr;
+    double *muS = nullptr;
+    int64_t n_mutual = 0;
     int n_scales = 0;
     c3x_stats stats;
 };

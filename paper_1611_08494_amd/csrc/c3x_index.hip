@@ -8,7 +8,7 @@
 // needs in one zone are one contiguous key range. Phases (one stream):
 //   k_prep_b    validate rows, key + row index          16 B in, 8 B out
 //   radix sort  (key, row) by key, ceil(bits/8) passes   16 B per pass
-//   k_gather_b  payload in sorted order                   16 B in, 36/52 B out
+//   k_gather_b  payload in sorted order                   20 B in, 32/16 B out
 //   k_dir_fill  dir[q] = number of keys in buckets below q, written straight
 //               from the sorted keys: each position fills the buckets between
 //               its predecessor's and its own (long gaps by k_dir_fill_gaps)
@@ -199,14 +199,15 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
     const double a = rd.x, d = rd.y;
     double x, y, z;
     unit_vec(a, d, x, y, z);
-    Pay64 q8;
-    q8.x = x;
-    q8.y = y;
-    q8.z = z;
-    q8.idx = row;
-    q8.pad = 0;
-    p64[s] = q8;
-    if (PREC == C3X_MIXED) {
+    if (PREC == C3X_FP64) {
+        Pay64 q8;
+        q8.x = x;
+        q8.y = y;
+        q8.z = z;
+        q8.idx = row;
+        q8.pad = 0;
+        p64[s] = q8;
+    } else {
         int zz = zone_of(d, g);
         uint32_t c = cell_of(zz, a, g);
         double rx, ry, rz;
@@ -298,20 +299,21 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     void *ws = tmp.get(radix_ws_bytes(n));
     uint32_t *bad = tmp.get_n<uint32_t>(2);  // first bad row; sort give-up
     // the coordinates in input order: the gathers' source, then kept by the
-    // index (the rare paths reach them through pay64[j].idx)
+    // index (the band recheck and the separations of the mixed path read
+    // them through the payload's row)
     double2 *packed = ix->mem.get_n<double2>(n);
     Pay64 *p64 = nullptr;
     Pay32 *p32 = nullptr;
-    // FP64 unit vectors for both paths (the mixed path's matches take their
-    // separation from them), FP32 offsets for the mixed filter
-    p64 = ix->mem.get_n<Pay64>(n);
-    if (o.precision == C3X_MIXED) p32 = ix->mem.get_n<Pay32>(n);
+    // one payload per index: FP64 unit vectors, or FP32 offsets from the
+    // cell references (the mixed filter)
+    if (o.precision == C3X_FP64) p64 = ix->mem.get_n<Pay64>(n);
+    else p32 = ix->mem.get_n<Pay32>(n);
     uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
     const uint32_t gap_cap = dir_gap_cap(ix->plan.dsize), big_cap = dir_big_cap(ix->plan.dsize);
     uint3 *gaps = tmp.get_n<uint3>((int64_t)gap_cap + big_cap);
     uint32_t *n_gaps = tmp.get_n<uint32_t>(2);
     if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !dir || !gaps || !n_gaps ||
-        !p64 || (o.precision == C3X_MIXED && !p32)) {
+        (!p64 && !p32)) {
         (void)hipStreamSynchronize(s);
         delete ix;
         return fail(C3X_ENOMEM, "index buffers");

@@ -2,11 +2,13 @@
 //
 // Data layout in HBM (all device arrays, catalogue B sorted by cell key):
 //   keys[nB]   u32   cell key = zbase[zone] + RA cell (zone-major)
-//   pay64[nB]  {f64 x, y, z; u32 idx; u32 pad}   FP64 unit vector (32 B)
+//   pay64[nB]  {f64 x, y, z; u32 idx; u32 pad}   FP64 unit vector (32 B),
+//                                                 FP64 index only
 //   pay32[nB]  {f32 dx, dy, dz; u32 idx}          FP32 offset from the cell's
-//                                                 reference vector (16 B)
+//                                                 reference vector (16 B), mixed
+//                                                 index only
 //   radec[nB]  {f64 ra, dec}                      coordinates in input order
-//                                                 (sorted position j: row pay64[j].idx)
+//                                                 (sorted position j: row brow(j))
 //   dir[Q+1]   u32   dir[q] = #keys with (key >> dshift) < q
 // Catalogue A is keyed on the same grid and sorted, so a wavefront of
 // threads covers neighbouring sky and reads neighbouring cells of B.
@@ -245,6 +247,22 @@ struct MatchArgs {
     uint32_t *err_flag;    // 1: write overflow, 2: count mismatch, 4: missing verdict
 };
 
+// B row of sorted position j: from the FP64 payload when the index has one,
+// else from the FP32 payload (the mixed index keeps no FP64 payload; its
+// matches take FP64 geometry from the coordinates, coordB[row]).
+struct BRows {
+    const Pay64 *p64;
+    const Pay32 *p32;
+    __device__ __forceinline__ uint32_t operator()(uint32_t j) const
+    {
+        return p64 ? p64[j].idx : (p32[j].idx & 0x7fffffffu);
+    }
+};
+__device__ __forceinline__ uint32_t brow(const MatchArgs &m, uint32_t j)
+{
+    return BRows{m.pay64, m.pay32}(j);
+}
+
 // ----------------------------------------------------------------------------
 // device geometry
 // ----------------------------------------------------------------------------
@@ -400,6 +418,45 @@ __device__ __forceinline__ int recheck_ellipse(const ARec &a, const AEllR &e, do
     return AMBIG;
 }
 
+// Rectangle of half-sides a (along the orientation) and b (across):
+// |u| <= a and |v| <= b, each form (theta / sin theta)^2 (su / a)^2 and
+// (theta / sin theta)^2 (sv / b)^2 decided on its own, with the ellipse's
+// relative accuracy and margin (near the u side |su| ~ a and sin theta <=
+// 1.42 a, near the v side |sv| ~ b and sin theta <= a + b).
+__device__ __forceinline__ int recheck_rect(const ARec &a, const AEllR &e, double2 rb)
+{
+    double cd2 = cos_dec_acc(rb.y);
+    double h = haversine(a.ra, a.dec, a.cosd, rb.x, rb.y, cd2);
+    if (h == 0.0) return IN;
+    const double diag = sqrt(e.a_arcsec * e.a_arcsec + e.b_arcsec * e.b_arcsec) * (1.0 + 1e-15);
+    double sa = sin(kHalfDeg * (diag / 3600.0));
+    if (h > (sa * sa) * (1.0 + kE40)) return OUT;
+    double tn, te;
+    tangent_ne(a.ra, a.dec, a.z, rb.x, rb.y, cd2, tn, te);
+    double th = 2.0 * asin(sqrt(h));
+    double sth = 2.0 * sqrt(h) * sqrt(1.0 - h);
+    double f = th / sth;
+    double su = tn * e.ct + te * e.st;
+    double sv = te * e.ct - tn * e.st;
+    double x = su / (kDeg * (e.a_arcsec / 3600.0));
+    double y = sv / (kDeg * (e.b_arcsec / 3600.0));
+    double qu = (f * f) * (x * x), qv = (f * f) * (y * y);
+    double m = kE38 * (1.0 + e.a_arcsec / e.b_arcsec);
+    if (qu > 1.0 + m || qv > 1.0 + m) return OUT;
+    if (qu <= 1.0 - m && qv <= 1.0 - m) return IN;
+    return AMBIG;
+}
+
+// Reach (degrees) of a per-source area: the semi-major axis of an ellipse,
+// the half-diagonal of a rectangle (padded for its rounding).
+__device__ __host__ __forceinline__ double area_reach_deg(int shape, double a_arcsec,
+                                                          double b_arcsec)
+{
+    if (shape == C3X_RECT)
+        return sqrt(a_arcsec * a_arcsec + b_arcsec * b_arcsec) * (1.0 + 1e-15) / 3600.0;
+    return a_arcsec / 3600.0;
+}
+
 __device__ __forceinline__ bool same_point(const ARec &a, double2 rb)
 {
     return a.dec == rb.y && (a.ra == rb.x || fabs(a.dec) == 90.0);
@@ -527,6 +584,8 @@ void set_error(const char *fmt, ...);
 extern "C" int c3x_q_circle(double ra1, double dec1, double ra2, double dec2, double r_arcsec);
 extern "C" int c3x_q_ellipse(double ra1, double dec1, double ra2, double dec2, double a_arcsec,
                              double b_arcsec, double pa_deg, double pa_zero_deg, int pa_sense);
+extern "C" int c3x_q_rect(double ra1, double dec1, double ra2, double dec2, double a_arcsec,
+                          double b_arcsec, double pa_deg, double pa_zero_deg, int pa_sense);
 extern "C" int c3x_q_best(double ra1, double dec1, int n, const double *ra2, const double *dec2,
                           const int32_t *idx);
 extern "C" void c3x_q_thresholds(double r_arcsec, double *h_r, double *cr2);

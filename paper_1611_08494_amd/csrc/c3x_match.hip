@@ -75,7 +75,7 @@ __global__ void k_prep_a(const double *__restrict__ ra, const double *__restrict
     double a = ra[i], d = dec[i];
     packed[i] = make_double2(a, d);  // one 16-byte record per row for the gather
     bool ok = isfinite(a) && isfinite(d) && a >= 0.0 && a < 360.0 && fabs(d) <= 90.0;
-    if (shape == C3X_ELLIPSE) {
+    if (shape != C3X_CIRCLE) {
         double A = sa[i], B = sb[i], P = pa[i];
         ok = ok && isfinite(A) && isfinite(B) && isfinite(P) && B >= 1e-6 && B <= A &&
              A <= 324000.0 && A <= 1000.0 * B;
@@ -90,18 +90,23 @@ __global__ void k_prep_a(const double *__restrict__ ra, const double *__restrict
     keys[i] = zi.base + cell_in(zi, a);  // its value in the sort: the row i itself
 }
 
-// Margin on the ellipse form Q for a filter whose tangent-plane components
-// carry an absolute error <= c * kappa + lambda (c the chord). Covers the
-// rounding of Q, the truncation of (theta / sin theta)^2 ~ 1 + c^2 / 3 and a
-// factor-2 safety; returns a huge value when the filter cannot decide.
-__device__ __forceinline__ double ell_margin(double ar, double br, double kappa, double lambda,
-                                             double u_round)
+// Margin on the ellipse form Q (or on each of the rectangle's forms Qu, Qv)
+// for a filter whose tangent-plane components carry an absolute error
+// <= c * kappa + lambda (c the chord, at most cmax where a decision is near:
+// a for the ellipse, the half-diagonal for the rectangle). The error of
+// su / a is then <= (c kappa + lambda) / a <= kappa cmax / a + lambda / a and
+// that of sv / b <= kappa cmax / b + lambda / b; cmax / b <= 1 + a / b for
+// both shapes. Covers the rounding of Q, the truncation of
+// (theta / sin theta)^2 ~ 1 + c^2 / 3 and a factor-2 safety; returns a huge
+// value when the filter cannot decide.
+__device__ __forceinline__ double ell_margin(double ar, double br, double cmax, double kappa,
+                                             double lambda, double u_round)
 {
     double ia = 1.0 / ar, ib = 1.0 / br;
     double k1 = kappa * (1.0 + ar / br) * 1.01;
     double l1 = 1.5 * lambda * (ia + ib);
     double rho = 2.0 * k1 + 2.0 * l1 + (k1 + l1) * (k1 + l1) + 6.0 * u_round;
-    double trunc = 0.2 * (ar * ar) * (ar * ar);
+    double trunc = 0.2 * (cmax * cmax) * (cmax * cmax);
     double m = 2.0 * (2.0 * rho + trunc);
     return m > 0.25 ? 1e30 : m;
 }
@@ -182,7 +187,7 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
     double r = rd.x, d = rd.y;
     bool ok = isfinite(r) && isfinite(d) && r >= 0.0 && r < 360.0 && fabs(d) <= 90.0;
     double A = 1.0, B = 1.0, P = 0.0;
-    if (SHAPE == C3X_ELLIPSE) {
+    if (SHAPE != C3X_CIRCLE) {
         A = sa[row];
         B = sb[row];
         P = pa[row];
@@ -199,7 +204,8 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
     arad[i] = make_double2(r, d);
     aidx[i] = row;
     bool multi;
-    ARange rg = a_ranges(g, r, d, SHAPE == C3X_ELLIPSE ? A / 3600.0 : reach_deg, multi);
+    ARange rg = a_ranges(g, r, d, SHAPE == C3X_CIRCLE ? reach_deg : area_reach_deg(SHAPE, A, B),
+                         multi);
     if (multi) rg.wide |= 2u;  // the mixed filter reads this row's cell keys
     if (wide_min) {
         // rows for the wavefront-per-source kernel: a window walked cell by
@@ -231,7 +237,7 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
         }
     }
     arng[i] = rg;
-    if (SHAPE == C3X_ELLIPSE) {
+    if (SHAPE != C3X_CIRCLE) {
         double T = pa_zero + (double)pa_sense * P;
         double st, ct;
         sincos(T * kDeg, &st, &ct);
@@ -249,6 +255,7 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
         e.vy = ey * ct - ny * st;
         e.vz = -nz * st;
         double ar = kDeg * (A / 3600.0), br = kDeg * (B / 3600.0);
+        const double cmax = SHAPE == C3X_RECT ? sqrt(ar * ar + br * br) : ar;
         e.ia = 1.0 / ar;
         e.ib = 1.0 / br;
         aell[i] = e;
@@ -261,11 +268,11 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
         const double s3 = 1.7320508075688772;
         double kappa64 = s3 * 64.0 * kU + s3 * kU + 4.0 * kU;
         double lambda64 = 2.0 * s3 * ev;
-        q.m64 = ell_margin(ar, br, kappa64, lambda64, kU);
+        q.m64 = ell_margin(ar, br, cmax, kappa64, lambda64, kU);
         const double e32 = kU32 * 1.0001;
         double kappa32 = s3 * (e32 + 64.0 * kU) + 2.0 * s3 * e32 + 4.0 * e32;
         double lambda32 = 2.0 * s3 * e32 * L_rad + 2.0 * s3 * ev;
-        double m32 = ell_margin(ar, br, kappa32, lambda32, e32);
+        double m32 = ell_margin(ar, br, cmax, kappa32, lambda32, e32);
         q.m32 = m32 > 0.25 ? 0.0f : (float)(m32 * 1.0001);
         q.pad = 0.f;
         aellr[i] = q;
@@ -382,9 +389,16 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
             double su = fma(dx, e.ux, fma(dy, e.uy, dz * e.uz));
             double sv = fma(dx, e.vx, fma(dy, e.vy, dz * e.vz));
             double xu = su * e.ia, xv = sv * e.ib;
-            double q = fma(xu, xu, xv * xv);
-            double qf = q * fma(c2, 1.0 / 3.0, 1.0);
-            d = qf <= 1.0 - er.m64 ? IN : (qf > 1.0 + er.m64 ? OUT : AMBIG);
+            const double t = fma(c2, 1.0 / 3.0, 1.0);
+            if constexpr (SHAPE == C3X_ELLIPSE) {
+                double qf = fma(xu, xu, xv * xv) * t;
+                d = qf <= 1.0 - er.m64 ? IN : (qf > 1.0 + er.m64 ? OUT : AMBIG);
+            } else {  // rectangle: |u| <= a and |v| <= b, each form on its own
+                double qu = (xu * xu) * t, qv = (xv * xv) * t;
+                d = (qu > 1.0 + er.m64 || qv > 1.0 + er.m64)
+                        ? OUT
+                        : ((qu <= 1.0 - er.m64 && qv <= 1.0 - er.m64) ? IN : AMBIG);
+            }
         }
     } else {
         // batch: the offsets are from the job's centre, set once per lane
@@ -410,14 +424,22 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
             float su = fmaf(dx, f.ux, fmaf(dy, f.uy, dz * f.uz));
             float sv = fmaf(dx, f.vx, fmaf(dy, f.vy, dz * f.vz));
             float xu = su * f.ia, xv = sv * f.ib;
-            float q = fmaf(xu, xu, xv * xv);
-            float qf = q * fmaf(c2, 1.0f / 3.0f, 1.0f);
+            const float t = fmaf(c2, 1.0f / 3.0f, 1.0f);
             float mm = er.m32;
-            d = mm == 0.0f ? AMBIG : (qf <= 1.0f - mm ? IN : (qf > 1.0f + mm ? OUT : AMBIG));
+            if constexpr (SHAPE == C3X_ELLIPSE) {
+                float qf = fmaf(xu, xu, xv * xv) * t;
+                d = mm == 0.0f ? AMBIG : (qf <= 1.0f - mm ? IN : (qf > 1.0f + mm ? OUT : AMBIG));
+            } else {
+                float qu = (xu * xu) * t, qv = (xv * xv) * t;
+                d = mm == 0.0f ? AMBIG
+                               : ((qu > 1.0f + mm || qv > 1.0f + mm)
+                                      ? OUT
+                                      : ((qu <= 1.0f - mm && qv <= 1.0f - mm) ? IN : AMBIG));
+            }
         }
     }
     if constexpr (SHAPE == C3X_CIRCLE) {
-        if (th.r_zero) d = same_point(a, m.coordB[m.pay64[j].idx]) ? IN : OUT;
+        if (th.r_zero) d = same_point(a, m.coordB[pay_row(b)]) ? IN : OUT;
     }
     return d;
 }
@@ -447,8 +469,10 @@ __device__ __forceinline__ int band_verdict(const MatchArgs &m, uint32_t i, uint
     ARec q = a;
     q.cosd = cos_dec_acc(a.dec);
     int d;
-    if constexpr (SHAPE == C3X_ELLIPSE) d = recheck_ellipse(q, m.aellr[i], m.coordB[m.pay64[j].idx]);
-    else d = recheck_circle(q, m.coordB[m.pay64[j].idx], BATCH ? m.jobs[m.ajob[i]].h_r : m.h_r);
+    const double2 rb = m.coordB[brow(m, j)];
+    if constexpr (SHAPE == C3X_ELLIPSE) d = recheck_ellipse(q, m.aellr[i], rb);
+    else if constexpr (SHAPE == C3X_RECT) d = recheck_rect(q, m.aellr[i], rb);
+    else d = recheck_circle(q, rb, BATCH ? m.jobs[m.ajob[i]].h_r : m.h_r);
     if (d != AMBIG) return d;
     return verdict(m, i, j);
 }
@@ -472,13 +496,18 @@ __device__ __forceinline__ double c2_err(double c, double L)
 
 // A match's separation as the match passes leave it, without trigonometry:
 // from the FP64 chord c < 1.38 the code -c^2 (the separation is 2 asin(c / 2),
-// error ~1e-14 rad), 0 for c = 0, otherwise a quiet NaN carrying the sorted
-// B position j (the separation is then computed from the coordinates).
-// Non-negative values are separations in arcsec.
-__device__ __forceinline__ double sep_code(double c2, uint32_t j)
+// error ~1e-14 rad), 0 for c = 0, otherwise a quiet NaN: the separation is
+// then computed from the coordinates of A and of the match's B row (the
+// mixed path codes every match so: it has no FP64 payload to take a chord
+// from). Non-negative values are separations in arcsec.
+__device__ __forceinline__ double sep_code(double c2)
 {
     if (c2 < 1.9) return c2 > 0.0 ? -c2 : 0.0;
-    return __longlong_as_double((long long)(0x7ff8000000000000ull | j));
+    return __longlong_as_double((long long)0x7ff8000000000000ull);
+}
+__device__ __forceinline__ double sep_code_coords()
+{
+    return __longlong_as_double((long long)0x7ff8000000000000ull);
 }
 
 __device__ __forceinline__ double sep_from_chord2(double c2)
@@ -534,10 +563,10 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     ARange rg{};
     if (active) {
         double reach = m.reach_deg;
-        if constexpr (SHAPE == C3X_ELLIPSE) {
+        if constexpr (SHAPE != C3X_CIRCLE) {
             e = m.aell[i];
             er = m.aellr[i];
-            reach = er.a_arcsec / 3600.0;
+            reach = area_reach_deg(SHAPE, er.a_arcsec, er.b_arcsec);
             f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
                         (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
         }
@@ -564,20 +593,15 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
     if (BATCH && active) batch_ref(m, i, a, cc);
 
-    // A filter match as written: the separation coded from the FP64 chord
-    // (the FP64 path's filter chord; the mixed path recomputes it from the
-    // FP64 unit vectors).
+    // A filter match as written: the separation coded from the FP64 path's
+    // filter chord; the mixed path leaves it to the coordinates (the final
+    // pass computes it from both rows' positions).
     auto coded = [&](const PayT &b, uint32_t j, double c2) -> PairTmp {
         PairTmp t;
         t.idxB = pay_row(b);
         t.j = j;
-        double c64 = c2;
-        if constexpr (PREC != C3X_FP64) {
-            const Pay64 b8 = m.pay64[j];
-            const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
-            c64 = fma(dx, dx, fma(dy, dy, dz * dz));
-        }
-        t.sep = sep_code(c64, j);
+        if constexpr (PREC == C3X_FP64) t.sep = sep_code(c2);
+        else t.sep = sep_code_coords();
         return t;
     };
 
@@ -795,10 +819,10 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
         AEll e{};
         AEllR er{};
         LaneF32 f{};
-        if constexpr (SHAPE == C3X_ELLIPSE) {
+        if constexpr (SHAPE != C3X_CIRCLE) {
             e = m.aell[i];
             er = m.aellr[i];
-            reach = er.a_arcsec / 3600.0;
+            reach = area_reach_deg(SHAPE, er.a_arcsec, er.b_arcsec);
             f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
                         (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
         }
@@ -857,13 +881,8 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                     if (d == IN) {
                         pt.idxB = pay_row(b);
                         pt.j = j;
-                        double c64 = c2;
-                        if constexpr (PREC != C3X_FP64) {
-                            const Pay64 b8 = m.pay64[j];
-                            const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
-                            c64 = fma(dx, dx, fma(dy, dy, dz * dz));
-                        }
-                        pt.sep = sep_code(c64, j);
+                        if constexpr (PREC == C3X_FP64) pt.sep = sep_code(c2);
+                        else pt.sep = sep_code_coords();
                     }
                     if (cnt == 0) {  // the record's slot: the group's first lane
                         const int l = __builtin_ffsll((long long)im) - 1;
@@ -964,10 +983,10 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
     AEllR er{};
     LaneF32 f{};
     double reach = m.reach_deg;
-    if constexpr (SHAPE == C3X_ELLIPSE) {
+    if constexpr (SHAPE != C3X_CIRCLE) {
         e = m.aell[i];
         er = m.aellr[i];
-        reach = er.a_arcsec / 3600.0;
+        reach = area_reach_deg(SHAPE, er.a_arcsec, er.b_arcsec);
         f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
                     (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
     }
@@ -989,7 +1008,7 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
             if (slot < m.col_cap) {
-                double2 rb = m.coordB[m.pay64[j].idx];
+                double2 rb = m.coordB[pay_row(b)];
                 ColEnt ce;
                 ce.t = t;
                 ce.idxB = pay_row(b);
@@ -1043,10 +1062,10 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
     AEllR er{};
     LaneF32 f{};
     double reach = m.reach_deg;
-    if constexpr (SHAPE == C3X_ELLIPSE) {
+    if constexpr (SHAPE != C3X_CIRCLE) {
         e = m.aell[i];
         er = m.aellr[i];
-        reach = er.a_arcsec / 3600.0;
+        reach = area_reach_deg(SHAPE, er.a_arcsec, er.b_arcsec);
         f = LaneF32{(float)e.ux, (float)e.uy, (float)e.uz, (float)e.vx,
                     (float)e.vy, (float)e.vz, (float)e.ia, (float)e.ib};
     }
@@ -1067,9 +1086,19 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
             int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j, c2);
             if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
-            const Pay64 b8 = m.pay64[j];
-            const double dx = b8.x - a.x, dy = b8.y - a.y, dz = b8.z - a.z;
-            const Cand c{fma(dx, dx, fma(dy, dy, dz * dz)), b8.idx, j};
+            // the FP64 unit vector: the FP64 payload's, or made the same way
+            // (unit_vec of the row's coordinates) for the mixed index
+            double bx, by, bz;
+            if constexpr (PREC == C3X_FP64) {
+                bx = b.x;
+                by = b.y;
+                bz = b.z;
+            } else {
+                const double2 rb = m.coordB[pay_row(b)];
+                unit_vec(rb.x, rb.y, bx, by, bz);
+            }
+            const double dx = bx - a.x, dy = by - a.y, dz = bz - a.z;
+            const Cand c{fma(dx, dx, fma(dy, dy, dz * dz)), pay_row(b), j};
             if (cand_less(c, b1)) {
                 b2 = b1;
                 b1 = c;
@@ -1137,7 +1166,8 @@ __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__rest
     uint2 q = band[t];
     double2 ad = arad[q.x];
     uint32_t row = aidx[q.x];
-    double2 rb = coordB[p64[q.y].idx];
+    const uint32_t idxB = BRows{p64, p32}(q.y);
+    double2 rb = coordB[idxB];
     ARec a;
     a.ra = ad.x;
     a.dec = ad.y;
@@ -1148,9 +1178,9 @@ __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__rest
     a.pad = 0;
     int d;
     if (SHAPE == C3X_CIRCLE) d = recheck_circle(a, rb, h_r);
+    else if (SHAPE == C3X_RECT) d = recheck_rect(a, aellr[q.x], rb);
     else d = recheck_ellipse(a, aellr[q.x], rb);
     if (d == OUT) return;
-    const uint32_t idxB = p64 ? p64[q.y].idx : pay_row(p32[q.y]);
     if (d == IN) {
         in[atomicAdd(n_in, 1u)] = make_uint4(q.x, row, idxB, q.y);  // at most one per band entry
         return;
@@ -1251,8 +1281,7 @@ __global__ void k_place_ov(const OvEnt *__restrict__ ovl, uint32_t ov_pool,
 __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
                           const uint32_t *__restrict__ nx_dev,
                           const uint32_t *__restrict__ aidx, const double2 *__restrict__ arad,
-                          const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
-                          int64_t nA, int64_t nB,
+                          const double2 *__restrict__ coordB, int64_t nA, int64_t nB,
                           const int64_t *__restrict__ off, int64_t P, RowRec *__restrict__ rec,
                           int use_rec, PairTmp *__restrict__ tmp,
                           unsigned long long *__restrict__ placed,
@@ -1261,7 +1290,7 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nx || (nx_dev && t >= *nx_dev)) return;
     const WEnt e = xent[t];
-    if (e.i >= (uint64_t)nA || e.j >= (uint64_t)nB) {
+    if (e.i >= (uint64_t)nA || e.idxB >= (uint64_t)nB) {
         atomicOr(err, 16u);
         return;
     }
@@ -1272,7 +1301,7 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
         atomicOr(err, 1u);
         return;
     }
-    const double2 ra = arad[e.i], rb = coordB[payB[e.j].idx];
+    const double2 ra = arad[e.i], rb = coordB[e.idxB];
     PairTmp x;
     x.idxB = e.idxB;
     x.j = e.j;
@@ -1331,7 +1360,7 @@ __global__ void k_nonzero(const uint32_t *__restrict__ cnts, int64_t n, uint32_t
 // Separation (arcsec) of a coded match (see sep_code). A chord below 0.1
 // uses the Maclaurin series of arcsin, 2 asin(x) = 2x (1 + x^2/6 + 3x^4/40
 // + ...), x = c/2, to x^15 (truncation below 1e-20 relative); larger chords
-// and the coordinate form are left to decode_rare.
+// and the coordinate form are left to final_write.
 __device__ __forceinline__ double theta_small(double c2)
 {
     const double x2 = 0.25 * c2;
@@ -1346,40 +1375,50 @@ __device__ __forceinline__ double theta_small(double c2)
     return sqrt(c2) * p * (180.0 / kPi * 3600.0);
 }
 
-__device__ __noinline__ double decode_rare(double code, double raA, double decA,
-                                           const double2 *__restrict__ coordB,
-                                           const Pay64 *__restrict__ payB, int64_t nB,
-                                           uint32_t *__restrict__ err)
+// Separation (arcsec) from the coordinates of A (pa) and of B (pb): the
+// FP64 chord of their unit vectors (a few units of rounding per component:
+// ~1e-10 arcsec), the full formula near the antipode.
+__device__ __noinline__ double sep_from_coords(double2 pa, double2 pb)
 {
-    if (code < 0.0) return 2.0 * asin(0.5 * sqrt(-code)) * (180.0 / kPi * 3600.0);
-    const uint32_t j = (uint32_t)__double_as_longlong(code);
-    if (j >= (uint64_t)nB) {
-        atomicOr(err, 16u);
-        return NAN;
-    }
-    const double2 rb = coordB[payB[j].idx];
-    return sep_arcsec_rd(raA, decA, rb.x, rb.y);
+    double ax, ay, az, bx, by, bz;
+    unit_vec(pa.x, pa.y, ax, ay, az);
+    unit_vec(pb.x, pb.y, bx, by, bz);
+    const double dx = bx - ax, dy = by - ay, dz = bz - az;
+    const double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (c2 < 0.01) return theta_small(c2);
+    if (c2 < 1.9) return 2.0 * asin(0.5 * sqrt(c2)) * (180.0 / kPi * 3600.0);
+    return sep_arcsec_rd(pa.x, pa.y, pb.x, pb.y);
 }
 
 // Final record of one match: idxA, idxB and the decoded separation; the
-// best match's separation too. RARE: the separations may need decode_rare
-// (radius or ellipse beyond a few degrees); otherwise every code is a
-// small chord.
-template <bool RARE>
+// best match's separation too. coordA: A coordinates by output row a;
+// coordB: B coordinates by output idxB (before any job-local renumbering).
+// defer: a separation to take from the coordinates is left as the code
+// (NaN) for k_sep_coords, which computes them all in one parallel pass.
 __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp &x, int64_t nB,
-                                            const double *__restrict__ raA,
-                                            const double *__restrict__ decA,
-                                            const double2 *__restrict__ coordB,
-                                            const Pay64 *__restrict__ payB, int32_t best,
+                                            const double2 *__restrict__ coordA,
+                                            const double2 *__restrict__ coordB, int32_t best,
                                             int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                                             double *__restrict__ os, double *__restrict__ bsep,
-                                            uint32_t *__restrict__ err)
+                                            uint32_t *__restrict__ err, bool defer)
 {
     double s = x.sep;
     if (!(s >= 0.0)) {
-        if (s > -0.01) s = theta_small(-s);
-        else if (RARE) s = decode_rare(s, raA[a], decA[a], coordB, payB, nB, err);
-        else atomicOr(err, 32u);
+        if (s > -0.01) {
+            s = theta_small(-s);
+        } else if (s < 0.0) {
+            s = 2.0 * asin(0.5 * sqrt(-s)) * (180.0 / kPi * 3600.0);
+        } else if (defer) {
+            oa[q] = (int32_t)a;
+            ob[q] = (int32_t)x.idxB;
+            os[q] = sep_code_coords();
+            return;
+        } else if (x.idxB < (uint64_t)nB) {
+            s = sep_from_coords(coordA[a], coordB[x.idxB]);
+        } else {
+            atomicOr(err, 16u);
+            s = NAN;
+        }
     }
     oa[q] = (int32_t)a;
     ob[q] = (int32_t)x.idxB;
@@ -1394,15 +1433,13 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
 // canonical position of each match is its rank by idxB (unique in a
 // segment). A longer one has its record's matches copied into the segment,
 // which k_seg_lds then finishes.
-template <bool RARE>
 __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *__restrict__ off,
                            const RowRec *__restrict__ rec, int use_rec, PairTmp *__restrict__ tmp,
-                           const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
+                           const double2 *__restrict__ coordA, const double2 *__restrict__ coordB,
                            int32_t *__restrict__ best_idx,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                            double *__restrict__ os, double *__restrict__ bsep,
-                           uint32_t *__restrict__ err)
+                           uint32_t *__restrict__ err, int defer)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nA) return;
@@ -1436,8 +1473,8 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
         return rk;
     };
     auto put = [&](const PairTmp &x) {
-        final_write<RARE>(o + rank_of(x.idxB), a, x, nB, raA, decA, coordB, payB, r.best, oa, ob, os,
-                          bsep, err);
+        final_write(o + rank_of(x.idxB), a, x, nB, coordA, coordB, r.best, oa, ob, os, bsep, err,
+                    defer != 0);
     };
     if (nt > 0) put(x0);
     for (int q = nt; q < len; ++q) put(tmp[o + q]);
@@ -1447,7 +1484,7 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
 // the compacted (idxA, idxB, sep) pair.
 __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec,
                            const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
+                           const double2 *__restrict__ coordB, BRows brows,
                            int32_t *__restrict__ bidx,
                            double *__restrict__ bsep, const int64_t *__restrict__ off, int64_t P,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
@@ -1466,7 +1503,7 @@ __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec
         atomicOr(err, 16u);
         return;
     }
-    double2 rb = coordB[payB[bj].idx];
+    double2 rb = coordB[brows(bj)];
     double s = sep_arcsec_rd(raA[t], decA[t], rb.x, rb.y);
     bsep[t] = s;
     if (off) {
@@ -1499,22 +1536,19 @@ __global__ void k_seg_list(const int64_t *__restrict__ off, int64_t n, uint32_t 
 // kSegLds matches are sorted by idxB in LDS (bitonic network over
 // idxB << 32 | position; idxB is unique in a segment) and written out in
 // final form; longer ones are listed for the host-driven radix sort.
-template <bool RARE>
 __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off,
                                                  const uint32_t *__restrict__ cnt,
                                                  const uint32_t *__restrict__ list, uint32_t cap,
                                                  const PairTmp *__restrict__ tmp, int64_t nB,
                                                  int64_t pcap,
-                                                 const double *__restrict__ raA,
-                                                 const double *__restrict__ decA,
+                                                 const double2 *__restrict__ coordA,
                                                  const double2 *__restrict__ coordB,
-                                                 const Pay64 *__restrict__ payB,
                                                  const RowRec *__restrict__ rec,
                                                  int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                                                  double *__restrict__ os, double *__restrict__ bsep,
                                                  uint32_t *__restrict__ huge_n,
                                                  uint32_t *__restrict__ huge,
-                                                 uint32_t *__restrict__ err)
+                                                 uint32_t *__restrict__ err, int defer)
 {
     __shared__ unsigned long long v[kSegLds];
     const uint32_t nseg = min(*cnt, cap);
@@ -1553,10 +1587,32 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
         }
         const int32_t best = rec[a].best;
         for (int k = threadIdx.x; k < len; k += blockDim.x)
-            final_write<RARE>(o + k, a, tmp[o + (uint32_t)v[k]], nB, raA, decA, coordB, payB, best, oa,
-                              ob, os, bsep, err);
+            final_write(o + k, a, tmp[o + (uint32_t)v[k]], nB, coordA, coordB, best, oa, ob, os,
+                        bsep, err, defer != 0);
         __syncthreads();  // v is reused by the next segment
     }
+}
+
+// The separations the final pass left to the coordinates (the mixed path's
+// matches: it keeps no FP64 payload to take a chord from), one thread per
+// output pair, and the best match's separation with them. Outputs whose
+// rows are out of range are skipped (the slots of rows ordered later by
+// finish_huge may still hold anything: they are written after this pass).
+__global__ void k_sep_coords(int64_t P, int64_t nA, int64_t nB, const int32_t *__restrict__ oa,
+                             const int32_t *__restrict__ ob, double *__restrict__ os,
+                             const double2 *__restrict__ coordA,
+                             const double2 *__restrict__ coordB,
+                             const int32_t *__restrict__ best_idx, double *__restrict__ bsep)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const double c = os[q];
+    if (!(c != c)) return;  // not NaN: already final
+    const int32_t a = oa[q], b = ob[q];
+    if (a < 0 || a >= nA || b < 0 || b >= nB) return;
+    const double s = sep_from_coords(coordA[a], coordB[b]);
+    os[q] = s;
+    if (best_idx[a] == b) bsep[a] = s;
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -1567,11 +1623,11 @@ struct FinishArgs {
     int64_t pcap;          // pairs the outputs hold
     const int64_t *off;
     const RowRec *rec;
-    int use_rec, rare;
+    int use_rec;
+    int defer;              // separations from coordinates by k_sep_coords (mixed path)
     PairTmp *tmp;
-    const double *raA, *decA;
-    const double2 *coordB;  // B coordinates in input order
-    const Pay64 *payB;      // sorted B payloads: payB[j].idx is B's input row
+    const double2 *coordA;  // A coordinates by output row
+    const double2 *coordB;  // B coordinates by output idxB
     int32_t *best_idx;
     int32_t *oa, *ob;
     double *os, *bsep;
@@ -1589,21 +1645,17 @@ constexpr unsigned kSegGrid = 1024;
 static void finish_segments(const FinishArgs &f, hipStream_t s)
 {
     if (f.nA == 0) return;
-#define C3X_FIN(R)                                                                                \
-    do {                                                                                          \
-        hipLaunchKernelGGL(k_finalize<R>, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB,      \
-                           f.pcap, f.off, f.rec, f.use_rec, f.tmp, f.raA, f.decA, f.coordB,       \
-                           f.payB,                                                                \
-                           f.best_idx, f.oa, f.ob, f.os, f.bsep, f.err);                          \
-        hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA,        \
-                           f.seg_n, f.list, f.cap);                                               \
-        hipLaunchKernelGGL(k_seg_lds<R>, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list,  \
-                           f.cap, f.tmp, f.nB, f.pcap, f.raA, f.decA, f.coordB, f.payB, f.rec, f.oa,\
-                           f.ob, f.os, f.bsep, f.seg_n + 1, f.huge, f.err);                       \
-    } while (0)
-    if (f.rare) C3X_FIN(true);
-    else C3X_FIN(false);
-#undef C3X_FIN
+    hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.pcap,
+                       f.off, f.rec, f.use_rec, f.tmp, f.coordA, f.coordB, f.best_idx, f.oa, f.ob,
+                       f.os, f.bsep, f.err, f.defer);
+    hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA, f.seg_n,
+                       f.list, f.cap);
+    hipLaunchKernelGGL(k_seg_lds, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list, f.cap,
+                       f.tmp, f.nB, f.pcap, f.coordA, f.coordB, f.rec, f.oa, f.ob, f.os, f.bsep,
+                       f.seg_n + 1, f.huge, f.err, f.defer);
+    if (f.defer && f.pcap > 0)
+        hipLaunchKernelGGL(k_sep_coords, dim3(nblk(f.pcap, 256)), dim3(256), 0, s, f.pcap, f.nA,
+                           f.nB, f.oa, f.ob, f.os, f.coordA, f.coordB, f.best_idx, f.bsep);
 }
 
 // Segments longer than kSegLds (their count already on the host), all at
@@ -1649,8 +1701,8 @@ __global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
                              const uint32_t *__restrict__ seg, const uint32_t *__restrict__ base,
                              const uint32_t *__restrict__ huge, const int64_t *__restrict__ off,
                              const PairTmp *__restrict__ tmp, int64_t nB,
-                             const double *__restrict__ raA, const double *__restrict__ decA,
-                             const double2 *__restrict__ coordB, const Pay64 *__restrict__ payB,
+                             const double2 *__restrict__ coordA,
+                             const double2 *__restrict__ coordB,
                              const RowRec *__restrict__ rec,
                              int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                              double *__restrict__ os, double *__restrict__ bsep,
@@ -1673,8 +1725,8 @@ __global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
         atomicOr(err, 16u);
         return;
     }
-    final_write<true>(o + rk, a, tmp[o + src], nB, raA, decA, coordB, payB, rec[a].best, oa, ob,
-                      os, bsep, err);
+    final_write(o + rk, a, tmp[o + src], nB, coordA, coordB, rec[a].best, oa, ob, os, bsep, err,
+                false);
 }
 
 static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStream_t s)
@@ -1714,7 +1766,7 @@ static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStre
     if (e == hipSuccess) {
         const uint32_t *vf = in2 ? vb : va;
         hipLaunchKernelGGL(k_huge_write, dim3(nblk(n, 256)), dim3(256), 0, s, vf, n, seg, base,
-                           f.huge, f.off, f.tmp, f.nB, f.raA, f.decA, f.coordB, f.payB, f.rec, f.oa, f.ob,
+                           f.huge, f.off, f.tmp, f.nB, f.coordA, f.coordB, f.rec, f.oa, f.ob,
                            f.os, f.bsep, f.err);
         e = hipGetLastError();
     }
@@ -1768,19 +1820,28 @@ static CircleThresholds circle_thresholds(double r_arcsec, double L)
     return t;
 }
 
+// Dispatch of a (shape, precision) pair to a launch macro L(SHAPE, PREC).
+#define C3X_SHAPES(L)                                                 \
+    do {                                                              \
+        if (shape == C3X_CIRCLE) {                                    \
+            if (prec == C3X_FP64) L(C3X_CIRCLE, C3X_FP64);            \
+            else L(C3X_CIRCLE, C3X_MIXED);                            \
+        } else if (shape == C3X_ELLIPSE) {                            \
+            if (prec == C3X_FP64) L(C3X_ELLIPSE, C3X_FP64);           \
+            else L(C3X_ELLIPSE, C3X_MIXED);                           \
+        } else {                                                      \
+            if (prec == C3X_FP64) L(C3X_RECT, C3X_FP64);              \
+            else L(C3X_RECT, C3X_MIXED);                              \
+        }                                                             \
+    } while (0)
+
 template <int MODE>
 static void launch_match(const MatchArgs &m, int shape, int prec, unsigned grid, hipStream_t s)
 {
     if (grid == 0) return;
 #define C3X_LAUNCH(SH, PR) \
     hipLaunchKernelGGL((k_match<SH, PR, MODE, false>), dim3(grid), dim3(kMatchBlock), 0, s, m)
-    if (shape == C3X_CIRCLE) {
-        if (prec == C3X_FP64) C3X_LAUNCH(C3X_CIRCLE, C3X_FP64);
-        else C3X_LAUNCH(C3X_CIRCLE, C3X_MIXED);
-    } else {
-        if (prec == C3X_FP64) C3X_LAUNCH(C3X_ELLIPSE, C3X_FP64);
-        else C3X_LAUNCH(C3X_ELLIPSE, C3X_MIXED);
-    }
+    C3X_SHAPES(C3X_LAUNCH);
 #undef C3X_LAUNCH
 }
 
@@ -1793,13 +1854,7 @@ static void launch_wide(const MatchArgs &m, int shape, int prec, hipStream_t s)
     const unsigned grid = (unsigned)std::min<int64_t>((m.nA + 3) / 4, 1024);
 #define C3X_LAUNCH(SH, PR) \
     hipLaunchKernelGGL((k_match_wide<SH, PR, MODE>), dim3(grid), dim3(256), 0, s, m)
-    if (shape == C3X_CIRCLE) {
-        if (prec == C3X_FP64) C3X_LAUNCH(C3X_CIRCLE, C3X_FP64);
-        else C3X_LAUNCH(C3X_CIRCLE, C3X_MIXED);
-    } else {
-        if (prec == C3X_FP64) C3X_LAUNCH(C3X_ELLIPSE, C3X_FP64);
-        else C3X_LAUNCH(C3X_ELLIPSE, C3X_MIXED);
-    }
+    C3X_SHAPES(C3X_LAUNCH);
 #undef C3X_LAUNCH
 }
 
@@ -1810,13 +1865,7 @@ static void launch_rerank(const MatchArgs &m, int shape, int prec, const uint32_
 #define C3X_RR(SH, PR) \
     hipLaunchKernelGGL((k_rerank<SH, PR, false>), dim3(n), dim3(64), 0, s, m, pos, n, nullptr, \
                        unc_n, unc)
-    if (shape == C3X_CIRCLE) {
-        if (prec == C3X_FP64) C3X_RR(C3X_CIRCLE, C3X_FP64);
-        else C3X_RR(C3X_CIRCLE, C3X_MIXED);
-    } else {
-        if (prec == C3X_FP64) C3X_RR(C3X_ELLIPSE, C3X_FP64);
-        else C3X_RR(C3X_ELLIPSE, C3X_MIXED);
-    }
+    C3X_SHAPES(C3X_RR);
 #undef C3X_RR
 }
 
@@ -1824,17 +1873,10 @@ static void launch_collect(const MatchArgs &m, int shape, int prec, hipStream_t 
 {
     unsigned grid = m.n_col;
     if (grid == 0) return;
-    if (shape == C3X_CIRCLE) {
-        if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_FP64, false>), dim3(grid), dim3(64), 0, s, m);
-        else
-            hipLaunchKernelGGL((k_collect<C3X_CIRCLE, C3X_MIXED, false>), dim3(grid), dim3(64), 0, s, m);
-    } else {
-        if (prec == C3X_FP64)
-            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_FP64, false>), dim3(grid), dim3(64), 0, s, m);
-        else
-            hipLaunchKernelGGL((k_collect<C3X_ELLIPSE, C3X_MIXED, false>), dim3(grid), dim3(64), 0, s, m);
-    }
+#define C3X_COL(SH, PR) \
+    hipLaunchKernelGGL((k_collect<SH, PR, false>), dim3(grid), dim3(64), 0, s, m)
+    C3X_SHAPES(C3X_COL);
+#undef C3X_COL
 }
 
 }  // namespace c3x
@@ -1896,7 +1938,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     RowRec *rec = tmp.get_n<RowRec>(nA);
     AEll *aell = nullptr;
     AEllR *aellr = nullptr;
-    if (shape == C3X_ELLIPSE) {
+    if (shape != C3X_CIRCLE) {
         aell = tmp.get_n<AEll>(nA);
         aellr = tmp.get_n<AEllR>(nA);
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
@@ -1934,16 +1976,14 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     if (in_tmp) wide = wide_min ? keys : nullptr;
     if (nA > 0) {
         const double reach = shape == C3X_CIRCLE ? area->radius_arcsec / 3600.0 : 0.0;
-        if (shape == C3X_CIRCLE)
-            hipLaunchKernelGGL(k_gather_a<C3X_CIRCLE>, dim3(nblk(nA, 256)), dim3(256), 0, s, srows,
-                               packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
-                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng,
-                               wide_min, few, wide, ctr + 8);
-        else
-            hipLaunchKernelGGL(k_gather_a<C3X_ELLIPSE>, dim3(nblk(nA, 256)), dim3(256), 0, s,
-                               srows, packed, nA, sa, sb, pa, area->pa_zero_deg, area->pa_sense,
-                               ix->plan.L_rad, ix->grid, reach, arad, aidx, aell, aellr, arng,
-                               wide_min, few, wide, ctr + 8);
+#define C3X_GATHER(SH)                                                                            \
+    hipLaunchKernelGGL(k_gather_a<SH>, dim3(nblk(nA, 256)), dim3(256), 0, s, srows, packed, nA, sa, \
+                       sb, pa, area->pa_zero_deg, area->pa_sense, ix->plan.L_rad, ix->grid, reach,  \
+                       arad, aidx, aell, aellr, arng, wide_min, few, wide, ctr + 8)
+        if (shape == C3X_CIRCLE) C3X_GATHER(C3X_CIRCLE);
+        else if (shape == C3X_ELLIPSE) C3X_GATHER(C3X_ELLIPSE);
+        else C3X_GATHER(C3X_RECT);
+#undef C3X_GATHER
     }
     HIPCHK(hipGetLastError(), "A records");
     tm.mark();  // 1
@@ -2040,8 +2080,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
                                m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
                                ix->pay32, m.h_r, nullptr, nullptr, nullptr, bin, ctr + 9, hl,
                                ctr + 10);
-        else
+        else if (shape == C3X_ELLIPSE)
             hipLaunchKernelGGL(k_recheck<C3X_ELLIPSE>, dim3(nblk(amb_cap, 256)), dim3(256), 0, s,
+                               m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
+                               ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10);
+        else
+            hipLaunchKernelGGL(k_recheck<C3X_RECT>, dim3(nblk(amb_cap, 256)), dim3(256), 0, s,
                                m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
                                ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10);
     };
@@ -2142,10 +2186,14 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         std::vector<std::pair<unsigned long long, uint8_t>> ver(n_host);
         for (uint32_t k = 0; k < n_host; ++k) {
             const AmbInfo &q = info[k];
-            const int in = shape == C3X_CIRCLE
-                               ? c3x_q_circle(q.raA, q.decA, q.raB, q.decB, area->radius_arcsec)
-                               : c3x_q_ellipse(q.raA, q.decA, q.raB, q.decB, q.a, q.b, q.pa,
-                                               area->pa_zero_deg, area->pa_sense);
+            const int in =
+                shape == C3X_CIRCLE
+                    ? c3x_q_circle(q.raA, q.decA, q.raB, q.decB, area->radius_arcsec)
+                : shape == C3X_ELLIPSE
+                    ? c3x_q_ellipse(q.raA, q.decA, q.raB, q.decB, q.a, q.b, q.pa,
+                                    area->pa_zero_deg, area->pa_sense)
+                    : c3x_q_rect(q.raA, q.decA, q.raB, q.decB, q.a, q.b, q.pa, area->pa_zero_deg,
+                                 area->pa_sense);
             ver[k] = {((unsigned long long)q.i << 32) | q.j, (uint8_t)(in ? 1 : 0)};
             if (in) hadd.push_back(make_uint4(q.i, q.idxA, q.idxB, q.j));
         }
@@ -2347,7 +2395,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (n_x > 0)
             hipLaunchKernelGGL(k_place_x, dim3(nblk(n_x, 256)), dim3(256), 0, s, xent, n_x, nullptr,
                                aidx,
-                               arad, ix->radec, ix->pay64, nA, ix->nB, off, P, rec, emitted ? 1 : 0, pt, c64 + 2,
+                               arad, ix->radec, nA, ix->nB, off, P, rec, emitted ? 1 : 0, pt, c64 + 2,
                                ctr + 4);
         HIPCHK(hipGetLastError(), "band matches");
         tm.mark();  // 4
@@ -2358,13 +2406,10 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         fa.off = off;
         fa.rec = rec;
         fa.use_rec = emitted ? 1 : 0;
-        // separations beyond a few degrees need the general decoding
-        fa.rare = shape == C3X_ELLIPSE || area->radius_arcsec >= 5.0 * 3600.0;
+        fa.defer = prec == C3X_MIXED ? 1 : 0;
         fa.tmp = pt;
-        fa.raA = ra;
-        fa.decA = dec;
+        fa.coordA = packed;  // A coordinates in input order (the key pass's copy)
         fa.coordB = ix->radec;
-        fa.payB = ix->pay64;
         fa.best_idx = R->best_idx;
         fa.oa = R->idxA;
         fa.ob = R->idxB;
@@ -2386,7 +2431,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     }
     if (nA > 0 && !all)
         hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB, rec, ra,
-                           dec, ix->radec, ix->pay64, R->best_idx, R->best_sep, off, P, R->idxA,
+                           dec, ix->radec, BRows{ix->pay64, ix->pay32}, R->best_idx, R->best_sep, off, P, R->idxA,
                            R->idxB,
                            R->sep, ctr + 4);
     HIPCHK(hipGetLastError(), "best separations");
@@ -2460,9 +2505,9 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
         double r = area->radius_arcsec;
         if (!(r == 0.0 || (r >= 1e-6 && r <= 324000.0)))
             return fail(C3X_EINVAL, "radius must be 0 or in [1e-6, 324000] arcsec");
-    } else if (area->shape == C3X_ELLIPSE) {
+    } else if (area->shape == C3X_ELLIPSE || area->shape == C3X_RECT) {
         if (nA > 0 && (!area->semi_major_arcsec || !area->semi_minor_arcsec || !area->pa_deg))
-            return fail(C3X_EINVAL, "ellipse parameter arrays are NULL");
+            return fail(C3X_EINVAL, "ellipse or rectangle parameter arrays are NULL");
         if (!isfinite(area->pa_zero_deg)) return fail(C3X_EINVAL, "pa_zero_deg not finite");
         if (area->pa_sense != 1 && area->pa_sense != -1)
             return fail(C3X_EINVAL, "pa_sense must be +1 or -1");

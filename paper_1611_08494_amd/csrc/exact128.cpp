@@ -88,6 +88,30 @@ extern "C" int c3x_q_ellipse(double ra1, double dec1, double ra2, double dec2, d
     return d < 0 ? 1 : 0;
 }
 
+// Rectangle of half-sides a (along T) and b (across): |u| <= a and |v| <= b,
+// u, v the ellipse's axis coordinates; a side within kTie counts as on it.
+extern "C" int c3x_q_rect(double ra1, double dec1, double ra2, double dec2, double a_arcsec,
+                          double b_arcsec, double pa_deg, double pa_zero_deg, int pa_sense)
+{
+    QPts p = pieces(ra1, dec1, ra2, dec2);
+    q128 h = qhav(p);
+    if (h <= 0) return 1;
+    q128 th = 2 * asinq(sqrtq(h));
+    q128 s2 = sinq(p.da / 2);
+    q128 tn = sinq(p.dd) + 2 * sinq(p.d1) * cosq(p.d2) * s2 * s2;
+    q128 te = cosq(p.d2) * sinq(p.da);
+    q128 T = ((q128)pa_zero_deg + (q128)pa_sense * (q128)pa_deg) * qdeg();
+    q128 ct = cosq(T), st = sinq(T);
+    q128 su = tn * ct + te * st;
+    q128 sv = te * ct - tn * st;
+    q128 A = (q128)a_arcsec / 3600 * qdeg();
+    q128 B = (q128)b_arcsec / 3600 * qdeg();
+    q128 f = th / sinq(th);
+    q128 x = fabsq(f * su / A), y = fabsq(f * sv / B);
+    if ((x > 1 && x - 1 > kTie) || (y > 1 && y - 1 > kTie)) return 0;
+    return 1;
+}
+
 // Index (into the candidate list) of the exact argmin of (theta, idx).
 // Haversine sin^2(theta/2) in FP64 with a relative error below 2^-45 (a few
 // dozen roundings of 2^-53 and the host libm's sine/cosine, each within an

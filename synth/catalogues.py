@@ -46,7 +46,7 @@ class Catalogues:
     raB: np.ndarray
     decB: np.ndarray
     frame: int = 0                 # 0 equatorial, 1 galactic
-    shape: int = 0                 # 0 circle, 1 ellipse
+    shape: int = 0                 # 0 circle, 1 ellipse, 2 rectangle
     radius_arcsec: float = 1.0
     a_arcsec: Optional[np.ndarray] = None
     b_arcsec: Optional[np.ndarray] = None
@@ -68,6 +68,8 @@ class Catalogues:
     def reach_arcsec(self) -> float:
         if self.shape == 1:
             return float(self.a_arcsec.max()) if self.nA else 0.0
+        if self.shape == 2:  # rectangle: the half-diagonal
+            return float(np.hypot(self.a_arcsec, self.b_arcsec).max()) if self.nA else 0.0
         if self.jobs is not None and len(self.jobs):
             return float(self.jobs[:, 4].max())
         return float(self.radius_arcsec)

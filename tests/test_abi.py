@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     for f in ("c3x_build_index", "c3x_match", "c3x_result_sizes", "c3x_result_copy",
               "c3x_result_views", "c3x_result_stats", "c3x_result_free", "c3x_index_free", "c3x_last_error",
               "c3x_version", "c3x_abi_version", "c3x_index_stats", "c3x_result_unmatched",
-              "c3x_match_concentric", "c3x_result_levels"):
+              "c3x_match_concentric", "c3x_result_levels", "c3x_result_mutual"):
         assert f in fns
 
 

@@ -47,8 +47,8 @@ def gpu_match(c3x, dev, cat, precision, mode=3, cell_arcsec=0.0, reach=None):
                          reach_hint_arcsec=cat.reach_arcsec() if reach is None else reach,
                          precision=precision, cell_arcsec=cell_arcsec)
     kw = {}
-    if cat.shape == 1:
-        kw = dict(shape=1, a=_t(cat.a_arcsec, dev), b=_t(cat.b_arcsec, dev),
+    if cat.shape in (1, 2):
+        kw = dict(shape=cat.shape, a=_t(cat.a_arcsec, dev), b=_t(cat.b_arcsec, dev),
                   pa=_t(cat.pa_deg, dev), pa_zero_deg=cat.pa_zero_deg, pa_sense=cat.pa_sense)
     else:
         kw = dict(shape=0, radius_arcsec=cat.radius_arcsec)
@@ -61,7 +61,7 @@ def gpu_match(c3x, dev, cat, precision, mode=3, cell_arcsec=0.0, reach=None):
 def oracle_match(cat, **kw):
     import oracle
     a = dict(shape=cat.shape, radius_arcsec=cat.radius_arcsec)
-    if cat.shape == 1:
+    if cat.shape in (1, 2):
         a.update(a=cat.a_arcsec, b=cat.b_arcsec, pa=cat.pa_deg, pa_zero_deg=cat.pa_zero_deg,
                  pa_sense=cat.pa_sense)
     a.update(kw)
