@@ -85,6 +85,8 @@ def lib():
         L.c3o_decide.restype = ctypes.c_int
         ip = ctypes.POINTER(ctypes.c_int32)
         L.c3o_seps.argtypes = [dp, dp, dp, dp, ip, ip, ctypes.c_int64, dp]
+        L.c3o_frame_convert.argtypes = [dp, dp, dp, ctypes.c_int64, dp, dp, dp]
+        L.c3o_frame_convert.restype = None
         _lib = L
     return _lib
 

@@ -713,3 +713,164 @@ void c3o_seps(const double *raA, const double *decA, const double *raB, const do
 }
 
 int c3o_abi_version(void) { return 1; }
+
+/* ------------------------------------------------------------------------ */
+/* frame conversion rule (catalogues in different frames)                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Reading taken for mixed frames (Section 2: equatorial and galactic
+ * coordinates): catalogue A's positions (and area orientations) are first
+ * converted into catalogue B's frame by the fixed FP64 rule below, and the
+ * converted doubles are A's inputs of the cross-match in B's frame. The rule
+ * uses only correctly rounded +, -, *, /, exact floor, frexp and ldexp, in a
+ * fixed order (no fused operations, no library trigonometry), so any IEEE
+ * FP64 machine evaluating it gets the same bits. M is the rotation between
+ * the frames, each entry the double nearest the exact value fixed by the
+ * galactic pole (RA 192.85948 deg, Dec 27.12825 deg) and the galactic
+ * longitude of the north celestial pole (122.93192 deg), taken as exact
+ * decimals; it is passed in by the caller.
+ *
+ * sin, cos: x in degrees = r + 90 q with q = floor((x + 45) / 90); t = r pi/180
+ *   (|t| <= pi/4 + tiny); Taylor series to t^17 (sin) and t^18 (cos), Horner
+ *   in t^2; quadrant by q mod 4.
+ * atan2: t = min(|x|,|y|) / max(|x|,|y|); above tan(pi/12), t' = (t sqrt3 - 1) /
+ *   (t + sqrt3) and pi/6 added; Taylor series of atan to t'^29; quadrant by
+ *   the signs and the swap; degrees.
+ * sqrt: frexp to [0.5, 2) with an even exponent, a linear first guess, five
+ *   Newton steps, ldexp.
+ */
+
+static const double R_KDEG = 0.017453292519943295;  /* pi / 180 */
+static const double R_KRAD = 57.29577951308232;     /* 180 / pi */
+static const double R_PI = 3.141592653589793;
+static const double R_HALF_PI = 1.5707963267948966;
+static const double R_PI_6 = 0.5235987755982988;
+static const double R_SQRT3 = 1.7320508075688772;
+static const double R_TAN_PI_12 = 0.2679491924311227;
+
+static double r_sqrt(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    int e;
+    double m = frexp(x, &e);          /* x = m 2^e, m in [0.5, 1) */
+    if (e & 1) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double y = 0.41731 + 0.59016 * m;
+    for (int k = 0; k < 5; k++) y = 0.5 * (y + m / y);
+    return ldexp(y, e / 2);
+}
+
+static void r_sincos_deg(double x, double *s_out, double *c_out)
+{
+    double qf = floor((x + 45.0) / 90.0);
+    double r = x - 90.0 * qf;
+    double t = r * R_KDEG;
+    double z = t * t;
+    /* sin t = t (1 - z/3! + z^2/5! - ... + z^8/17!), Horner from the top */
+    double s = 1.0 / 355687428096000.0;
+    s = -1.0 / 1307674368000.0 + z * s;
+    s = 1.0 / 6227020800.0 + z * s;
+    s = -1.0 / 39916800.0 + z * s;
+    s = 1.0 / 362880.0 + z * s;
+    s = -1.0 / 5040.0 + z * s;
+    s = 1.0 / 120.0 + z * s;
+    s = -1.0 / 6.0 + z * s;
+    s = 1.0 + z * s;
+    s = t * s;
+    /* cos t = 1 - z/2! + z^2/4! - ... - z^9/18! */
+    double c = -1.0 / 6402373705728000.0;
+    c = 1.0 / 20922789888000.0 + z * c;
+    c = -1.0 / 87178291200.0 + z * c;
+    c = 1.0 / 479001600.0 + z * c;
+    c = -1.0 / 3628800.0 + z * c;
+    c = 1.0 / 40320.0 + z * c;
+    c = -1.0 / 720.0 + z * c;
+    c = 1.0 / 24.0 + z * c;
+    c = -0.5 + z * c;
+    c = 1.0 + z * c;
+    long q = (long)qf;
+    int k = (int)(((q % 4) + 4) % 4);
+    if (k == 0) { *s_out = s; *c_out = c; }
+    else if (k == 1) { *s_out = c; *c_out = -s; }
+    else if (k == 2) { *s_out = -s; *c_out = -c; }
+    else { *s_out = -c; *c_out = s; }
+}
+
+static double r_atan2_deg(double y, double x)
+{
+    double ax = fabs(x), ay = fabs(y);
+    if (ax == 0.0 && ay == 0.0) return 0.0;
+    int swap = ay > ax;
+    double t = swap ? ax / ay : ay / ax;
+    double off = 0.0;
+    if (t > R_TAN_PI_12) {
+        t = (t * R_SQRT3 - 1.0) / (t + R_SQRT3);
+        off = R_PI_6;
+    }
+    double z = t * t;
+    double p = 1.0 / 29.0;
+    p = -1.0 / 27.0 + z * p;
+    p = 1.0 / 25.0 + z * p;
+    p = -1.0 / 23.0 + z * p;
+    p = 1.0 / 21.0 + z * p;
+    p = -1.0 / 19.0 + z * p;
+    p = 1.0 / 17.0 + z * p;
+    p = -1.0 / 15.0 + z * p;
+    p = 1.0 / 13.0 + z * p;
+    p = -1.0 / 11.0 + z * p;
+    p = 1.0 / 9.0 + z * p;
+    p = -1.0 / 7.0 + z * p;
+    p = 1.0 / 5.0 + z * p;
+    p = -1.0 / 3.0 + z * p;
+    p = 1.0 + z * p;
+    double a = off + t * p;
+    if (swap) a = R_HALF_PI - a;
+    if (x < 0.0) a = R_PI - a;
+    if (y < 0.0) a = -a;
+    return a * R_KRAD;
+}
+
+/* rows of M times v: ((m0 v0 + m1 v1) + m2 v2) */
+static void r_rot(const double *M, const double *v, double *o)
+{
+    o[0] = (M[0] * v[0] + M[1] * v[1]) + M[2] * v[2];
+    o[1] = (M[3] * v[0] + M[4] * v[1]) + M[5] * v[2];
+    o[2] = (M[6] * v[0] + M[7] * v[1]) + M[8] * v[2];
+}
+
+/* Converts n positions (degrees) with the rule; gamma_out (may be NULL)
+ * receives, per position, the angle (degrees) from the target frame's local
+ * north to the source frame's local north, measured towards the target's
+ * local east: an orientation T in the source frame is T + gamma in the
+ * target frame. */
+void c3o_frame_convert(const double *M, const double *ra, const double *dec, int64_t n,
+                       double *ra_out, double *dec_out, double *gamma_out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double sa, ca, sd, cd;
+        r_sincos_deg(ra[i], &sa, &ca);
+        r_sincos_deg(dec[i], &sd, &cd);
+        double p[3] = {cd * ca, cd * sa, sd}, q[3];
+        r_rot(M, p, q);
+        double a2 = r_atan2_deg(q[1], q[0]);
+        if (a2 < 0.0) a2 = a2 + 360.0;
+        if (a2 >= 360.0) a2 = 0.0;
+        double d2 = r_atan2_deg(q[2], r_sqrt(q[0] * q[0] + q[1] * q[1]));
+        if (d2 > 90.0) d2 = 90.0;
+        if (d2 < -90.0) d2 = -90.0;
+        ra_out[i] = a2;
+        dec_out[i] = d2;
+        if (gamma_out) {
+            double nA[3] = {-(sd * ca), -(sd * sa), cd}, nq[3];
+            r_rot(M, nA, nq);
+            double sa2, ca2, sd2, cd2;
+            r_sincos_deg(a2, &sa2, &ca2);
+            r_sincos_deg(d2, &sd2, &cd2);
+            double ue = nq[0] * (-sa2) + nq[1] * ca2;
+            double un = (nq[0] * (-(sd2 * ca2)) + nq[1] * (-(sd2 * sa2))) + nq[2] * cd2;
+            gamma_out[i] = r_atan2_deg(ue, un);
+        }
+    }
+}
