@@ -64,12 +64,13 @@ typedef enum {
     C3X_ERANGE = 2,   /* a row count above 2^31 - 1 */
     C3X_ENOMEM = 3,   /* device or host allocation failed */
     C3X_EDEVICE = 4,  /* HIP runtime error (message holds the HIP string) */
-    C3X_EFRAME = 5    /* index and match frames differ */
+    C3X_EFRAME = 5    /* kept for the ABI; frames that differ are converted */
 } c3x_status;
 
-/* Coordinate frame of both catalogues (Section 2: equatorial and galactic).
- * It fixes what "north" means for the position angle; both catalogues of one
- * match must share it. */
+/* Coordinate frame of a catalogue (Section 2: equatorial and galactic). It
+ * fixes what "north" means for the position angle. A catalogue A in the
+ * other frame than the index's is converted into the index's frame (see
+ * c3x_frame_convert). */
 typedef enum { C3X_EQUATORIAL = 0, C3X_GALACTIC = 1 } c3x_frame;
 
 /* Region shape (Section 2.1: an elliptical, circular -- the special ellipse
@@ -122,6 +123,36 @@ typedef struct {
     double radius_arcsec;
 } c3x_job;
 
+/* Catalogues in different frames (Section 2: equatorial and galactic
+ * coordinates). c3x_match (and c3x_match_concentric) accept catalogue A in
+ * the other frame than the index's: A's positions are first converted into
+ * the index's frame by the fixed FP64 rule of c3x_frame_convert, the area
+ * orientations T = pa_zero + pa_sense * PA turned with them, and the
+ * converted doubles are A's inputs of the match (the result's rows are
+ * still A's own).
+ *
+ * c3x_frame_matrix: the rule's rotation from frame src to frame dst (host,
+ * row-major, 9 doubles): fixed by the galactic north pole at RA 192.85948
+ * deg, Dec 27.12825 deg and the galactic longitude 122.93192 deg of the
+ * north celestial pole, taken as exact decimals, each entry the double
+ * nearest its exact value.
+ *
+ * c3x_frame_convert: n positions (device float64 arrays, degrees) from frame
+ * src to frame dst by the rule, which uses only correctly rounded +, -, *,
+ * / and exact floor, frexp, ldexp in a fixed order (series sine, cosine and
+ * arctangent, a Newton square root), so any IEEE FP64 machine following it
+ * gets the same bits; it is within 1e-11 deg of the exact rotation.
+ * gamma_out (may be NULL) receives for every row the angle (degrees) that
+ * turns an orientation measured in frame src (from local north towards local
+ * east) into one measured in frame dst. Output arrays are caller-owned
+ * device memory; the call synchronises `stream`. Errors: C3X_EINVAL (bad
+ * frame, NULL array, an input row outside RA [0, 360), |Dec| <= 90 or not
+ * finite: the message names the first), C3X_ENOMEM, C3X_EDEVICE. */
+void c3x_frame_matrix(int src, int dst, double *M);
+c3x_status c3x_frame_convert(const double *ra, const double *dec, int64_t n, c3x_frame src,
+                             c3x_frame dst, double *ra_out, double *dec_out, double *gamma_out,
+                             void *stream);
+
 /* Counters and phase times of one call (milliseconds from HIP events). */
 typedef struct {
     int64_t n_a, n_b;
@@ -167,7 +198,10 @@ c3x_status c3x_build_index(const double *ra_deg, const double *dec_deg, int64_t 
  * Output (via c3x_result_copy): pairs in canonical (idxA, idxB) ascending
  * order, 0-based rows of the caller's arrays; sep in arcsec (float64, within
  * 1e-6" of exact); best_idxB[nA] (-1 if unmatched), best_sep[nA] (NaN).
- * Errors: C3X_EINVAL, C3X_ERANGE, C3X_EFRAME, C3X_ENOMEM, C3X_EDEVICE. */
+ * frame: catalogue A's frame; when it differs from the index's, A's
+ * positions and area orientations are converted into the index's frame by
+ * the rule of c3x_frame_convert before the match.
+ * Errors: C3X_EINVAL, C3X_ERANGE, C3X_ENOMEM, C3X_EDEVICE. */
 c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const double *dec_deg,
                      int64_t nA, c3x_frame frame, const c3x_area *area, unsigned mode,
                      const c3x_opts *opts, c3x_result **out);
@@ -215,6 +249,27 @@ c3x_status c3x_match_concentric(const c3x_index *ix, const double *ra_deg, const
  * n_pairs entries in the pairs' order, owned by r. EINVAL for other
  * results. */
 c3x_status c3x_result_levels(const c3x_result *r, const int32_t **level);
+
+/* Column type of the Exact Value case. */
+typedef enum { C3X_KEY_I64 = 0, C3X_KEY_F64 = 1 } c3x_keytype;
+
+/* The Exact Value case (Section 2.1): A row i and B row j match when the
+ * chosen columns hold equal values, keyA[i] == keyB[j] (int64: equal
+ * integers; float64: numerically equal, +0 equal to -0, a NaN equal to
+ * nothing). keyA, keyB: device arrays of nA and nB 8-byte values of `type`
+ * (caller-owned, read during the call). mode: C3X_ALL and/or C3X_BEST
+ * (Section 2.2); every match of a row is equally good, so its best match is
+ * its lowest matching B row. The result reads like c3x_match's: pairs in
+ * (idxA, idxB) order with separation 0, best_idxB (-1 if unmatched) and
+ * best_sep (0, NaN if unmatched); BEST alone stores one pair per matched A
+ * row; c3x_result_unmatched gives its join types (Section 2.2). A GPU hash
+ * join: B hashed and ordered by hash (LDS radix sort), a directory over the
+ * hash's top bits as the buckets, one probe per A row, count, scan, write.
+ * Work is ordered on `stream` (NULL: the null stream), synchronised to size
+ * the outputs. Errors: C3X_EINVAL, C3X_ERANGE (a count above 2^31 - 1),
+ * C3X_ENOMEM, C3X_EDEVICE. */
+c3x_status c3x_exact_match(const void *keyA, int64_t nA, const void *keyB, int64_t nB,
+                           c3x_keytype type, unsigned mode, void *stream, c3x_result **out);
 
 /* Rows without a stored match, from which every join type of Section 2.2
  * ("Match selection and join types") is assembled with the stored pairs:

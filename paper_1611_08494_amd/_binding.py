@@ -109,6 +109,13 @@ def lib():
     L.c3x_result_mutual.argtypes = [vp, vp, vp, vp, vp, vp, pvp, pvp, pvp, ctypes.POINTER(i64),
                                     pvp]
     L.c3x_result_mutual.restype = ctypes.c_int
+    L.c3x_frame_convert.argtypes = [vp, vp, i64, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
+    L.c3x_frame_convert.restype = ctypes.c_int
+    L.c3x_frame_matrix.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl)]
+    L.c3x_frame_matrix.restype = None
+    L.c3x_exact_match.argtypes = [vp, i64, vp, i64, ctypes.c_int, ctypes.c_uint, vp,
+                                  ctypes.POINTER(vp)]
+    L.c3x_exact_match.restype = ctypes.c_int
     L.c3x_result_levels.argtypes = [vp, pvp]
     L.c3x_result_levels.restype = ctypes.c_int
     L.c3x_result_unmatched.restype = ctypes.c_int
@@ -300,6 +307,51 @@ def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
     check(lib().c3x_match(index.handle, ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(frame),
                           ctypes.byref(ar), int(mode), ctypes.byref(o), ctypes.byref(h)))
     return _views(h, ra.device)
+
+
+def frame_matrix(src: int, dst: int):
+    """The frame conversion rule's rotation (c3x_frame_matrix), 9 doubles
+    row-major."""
+    out = (ctypes.c_double * 9)()
+    lib().c3x_frame_matrix(int(src), int(dst), out)
+    return list(out)
+
+
+def frame_convert(ra, dec, src: int, dst: int, stream=None):
+    """Positions converted from frame src to frame dst by the library's fixed
+    FP64 rule (c3x_frame_convert): device tensors (ra', dec', gamma), gamma
+    the angle that turns an orientation from frame src into frame dst."""
+    torch = _torch()
+    ra = _dev_f64(ra, "ra")
+    dec = _dev_f64(dec, "dec")
+    if ra.shape != dec.shape:
+        raise ValueError("ra and dec differ in length")
+    out = [torch.empty_like(ra) for _ in range(3)]
+    check(lib().c3x_frame_convert(ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(src),
+                                  int(dst), *[t.data_ptr() for t in out], _stream_ptr(stream)))
+    return tuple(out)
+
+
+KEY_I64, KEY_F64 = 0, 1
+
+
+def exact_match(keyA, keyB, mode: int = ALL | BEST, stream=None) -> MatchResult:
+    """The Exact Value case (c3x_exact_match): rows of A and B match when
+    their key columns (1-D contiguous int64 or float64 CUDA tensors of one
+    dtype) hold equal values. Returns the result like ``match`` (separations
+    0, best_idx the lowest matching B row)."""
+    torch = _torch()
+    for t, nm in ((keyA, "keyA"), (keyB, "keyB")):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dim() != 1 \
+                or not t.is_contiguous() or t.dtype not in (torch.int64, torch.float64):
+            raise TypeError(f"{nm} must be a contiguous 1-D int64 or float64 CUDA tensor")
+    if keyA.dtype != keyB.dtype:
+        raise TypeError("keyA and keyB must have one dtype")
+    kt = KEY_I64 if keyA.dtype == torch.int64 else KEY_F64
+    h = ctypes.c_void_p()
+    check(lib().c3x_exact_match(keyA.data_ptr(), keyA.shape[0], keyB.data_ptr(), keyB.shape[0],
+                                kt, int(mode), _stream_ptr(stream), ctypes.byref(h)))
+    return _views(h, keyA.device)
 
 
 def result_copy(result: MatchResult, idxA=None, idxB=None, sep=None, best_idx=None,

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libc3x.so")
 HIP_SOURCES = ["c3x_common.hip", "c3x_sort.hip", "c3x_index.hip", "c3x_match.hip",
-               "c3x_join.hip", "c3x_concentric.hip", "c3x_mutual.hip"]
+               "c3x_join.hip", "c3x_concentric.hip", "c3x_mutual.hip",
+               "c3x_exact.hip", "c3x_frames.hip"]
 ARCH = os.environ.get("C3X_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

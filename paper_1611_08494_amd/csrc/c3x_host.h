@@ -126,6 +126,15 @@ struct GridPlan {
     uint32_t dsize;
 };
 
+// Catalogue positions converted from frame src to frame dst by the fixed
+// FP64 rule (c3x_frames.hip); with orient given, also the area orientations
+// T = pa_zero + pa_sense * pa[i] turned into the target frame; the first
+// out-of-domain row goes to *bad (atomicMin). Stream-ordered.
+hipError_t frame_convert(int src, int dst, const double *ra, const double *dec, int64_t n,
+                         double *ra_out, double *dec_out, double *gamma_out, const double *pa,
+                         double pa_zero, int pa_sense, double *orient, uint32_t *bad,
+                         hipStream_t s);
+
 // Device copies of a cell size's zone tables on the current device.
 c3x_status device_zone_tables(const ZoneTables *zt, const ZoneInfo **zinfo, const double2 **zref);
 

@@ -589,5 +589,6 @@ extern "C" int c3x_q_rect(double ra1, double dec1, double ra2, double dec2, doub
 extern "C" int c3x_q_best(double ra1, double dec1, int n, const double *ra2, const double *dec2,
                           const int32_t *idx);
 extern "C" void c3x_q_thresholds(double r_arcsec, double *h_r, double *cr2);
+extern "C" void c3x_frame_matrix(int src, int dst, double *M);
 
 }  // namespace c3x

@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     if constexpr (PREC == C3X_FP64) pay = m.pay64;
     else pay = m.pay32;
 
-    const uint32_t i = blockIdx.x * kMatchBlock + threadIdx.x;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;  // blockDim.x <= kMatchBlock
     bool active = i < (uint32_t)m.nA;
     ARec a{};
     AEll e{};
@@ -2498,7 +2498,7 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
     if (nA > 2147483647LL) return fail(C3X_ERANGE, "nA above 2^31 - 1");
     if (nA > 0 && (!ra_deg || !dec_deg)) return fail(C3X_EINVAL, "NULL coordinate array");
     if (frame != C3X_EQUATORIAL && frame != C3X_GALACTIC) return fail(C3X_EINVAL, "bad frame");
-    if (frame != ix->frame) return fail(C3X_EFRAME, "catalogue A frame differs from the index's");
+
     if (mode == 0 || (mode & ~(unsigned)(C3X_ALL | C3X_BEST)))
         return fail(C3X_EINVAL, "mode must be C3X_ALL, C3X_BEST or both");
     if (area->shape == C3X_CIRCLE) {
@@ -2523,6 +2523,47 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
     memset(&R->stats, 0, sizeof(R->stats));
     R->mode = mode;
     R->nB = ix->nB;
+    // catalogue A in the other frame: converted into the index's frame by the
+    // fixed FP64 rule (orientations turned with it); the converted doubles
+    // are A's inputs
+    Arena conv(s);
+    c3x_area ar = *area;
+    if (frame != ix->frame && nA > 0) {
+        const bool oriented = area->shape != C3X_CIRCLE;
+        double *ra2 = conv.get_n<double>(nA), *dec2 = conv.get_n<double>(nA);
+        double *t2 = oriented ? conv.get_n<double>(nA) : nullptr;
+        uint32_t *bad = conv.get_n<uint32_t>(1);
+        if (!ra2 || !dec2 || (oriented && !t2) || !bad) {
+            delete R;
+            return fail(C3X_ENOMEM, "frame conversion");
+        }
+        uint32_t hbad = 0xffffffffu;
+        hipError_t e = hipMemsetAsync(bad, 0xff, sizeof(uint32_t), s);
+        if (e == hipSuccess)
+            e = frame_convert((int)frame, (int)ix->frame, ra_deg, dec_deg, nA, ra2, dec2, nullptr,
+                              oriented ? area->pa_deg : nullptr, area->pa_zero_deg, area->pa_sense,
+                              t2, bad, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            delete R;
+            return fail_hip(e, "frame conversion");
+        }
+        if (hbad != 0xffffffffu) {
+            delete R;
+            return fail(C3X_EINVAL, "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= "
+                                    "90 or not finite", hbad);
+        }
+        ra_deg = ra2;
+        dec_deg = dec2;
+        if (oriented) {
+            ar.pa_deg = t2;
+            ar.pa_zero_deg = 0.0;
+            ar.pa_sense = 1;
+        }
+        area = &ar;
+    }
     c3x_status st = match_impl(ix, ra_deg, dec_deg, nA, area, mode, s, true, R);
     if (st == kSortGaveUp) {
         // a one-sweep sort gave up its look-back: the call again, with the

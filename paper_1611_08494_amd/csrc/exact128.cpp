@@ -180,3 +180,38 @@ extern "C" void c3x_q_thresholds(double r_arcsec, double *h_r, double *cr2)
     *h_r = (double)(s * s);
     *cr2 = (double)(4 * s * s);
 }
+
+// Rotation between the equatorial and galactic frames (Section 2 names both
+// coordinate systems), fixed by the galactic north pole (RA 192.85948 deg,
+// Dec 27.12825 deg) and the galactic longitude of the north celestial pole
+// (122.93192 deg) taken as exact decimals: the galactic basis vectors in
+// equatorial coordinates, computed in binary128 and rounded to doubles.
+// src == dst gives the identity; equatorial -> galactic has the basis
+// vectors as rows, galactic -> equatorial is the transpose. Row-major.
+extern "C" void c3x_frame_matrix(int src, int dst, double *M)
+{
+    for (int k = 0; k < 9; ++k) M[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    if (src == dst) return;
+    const q128 k = qdeg();
+    const q128 a = strtoflt128("192.85948", nullptr) * k;
+    const q128 d = strtoflt128("27.12825", nullptr) * k;
+    const q128 l = strtoflt128("122.93192", nullptr) * k;
+    const q128 zg[3] = {cosq(d) * cosq(a), cosq(d) * sinq(a), sinq(d)};
+    // the north celestial pole: galactic longitude l, latitude d
+    q128 q[3];
+    for (int i = 0; i < 3; ++i) q[i] = ((i == 2 ? (q128)1 : (q128)0) - sinq(d) * zg[i]) / cosq(d);
+    const q128 qp[3] = {zg[1] * q[2] - zg[2] * q[1], zg[2] * q[0] - zg[0] * q[2],
+                        zg[0] * q[1] - zg[1] * q[0]};
+    q128 xg[3], yg[3];
+    for (int i = 0; i < 3; ++i) {
+        xg[i] = cosq(l) * q[i] - sinq(l) * qp[i];
+        yg[i] = sinq(l) * q[i] + cosq(l) * qp[i];
+    }
+    const q128 *rows[3] = {xg, yg, zg};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            const double v = (double)rows[r][c];
+            if (src == 0) M[3 * r + c] = v;  // equatorial -> galactic
+            else M[3 * c + r] = v;           // galactic -> equatorial
+        }
+}

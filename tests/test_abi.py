@@ -199,3 +199,14 @@ def test_bench_reports_traffic_only_for_the_measured_kernel(monkeypatch):
     for cfg in ("cfg2", "cfg5"):
         assert bench.committed_traffic(cfg, "mixed") is None
         assert bench.committed_traffic(cfg, "fp64") is None
+
+
+def test_frame_rotation_matches_the_oracle(L):
+    """The library's rotation of the frame conversion rule (binary128, host)
+    equals the oracle's (200-bit mpmath) entry for entry, bit for bit."""
+    import numpy as np
+    from oracle import frames
+    for src, dst in ((0, 1), (1, 0), (0, 0), (1, 1)):
+        out = (ctypes.c_double * 9)()
+        L.c3x_frame_matrix(src, dst, out)
+        assert np.array_equal(np.array(list(out)), frames.rotation(src, dst)), (src, dst)

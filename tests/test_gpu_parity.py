@@ -220,8 +220,8 @@ def test_errors(c3x, dev):
     with pytest.raises(c3x.C3XError, match="row 1"):
         c3x.build_index(bad, ok)
     ix = c3x.build_index(ok, ok, frame=c3x.GALACTIC)
-    with pytest.raises(c3x.C3XError, match="EFRAME"):
-        c3x.match(ix, ok, ok, frame=c3x.EQUATORIAL)
+    with pytest.raises(c3x.C3XError, match="row 1"):  # checked before the frame conversion
+        c3x.match(ix, bad, ok, frame=c3x.EQUATORIAL)
     with pytest.raises(c3x.C3XError, match="row 2"):
         c3x.match(ix, _t([1.0, 2.0, 3.0], dev), _t([0.0, 0.0, 91.0], dev), frame=c3x.GALACTIC)
     with pytest.raises(c3x.C3XError, match="radius"):
