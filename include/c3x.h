@@ -294,6 +294,28 @@ c3x_status c3x_result_unmatched(c3x_result *r, unsigned selection, void *stream,
                                 const int32_t **rowsA, int64_t *n_rowsA,
                                 const int32_t **rowsB, int64_t *n_rowsB);
 
+/* No-allocation form of c3x_result_unmatched, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The unmatched rows of r (same meaning,
+ * selection and order as c3x_result_unmatched) go to the caller's device
+ * arrays rowsA[capA] and rowsB[capB] (capA >= nA and capB >= nB of r), and
+ * their numbers to counts[0] (A) and counts[1] (B), a caller device array of
+ * two int64 (-1 in both if a stored pair names a row outside its
+ * catalogue). No memory is allocated: the working memory is one fixed
+ * library array of 64 MiB per GPU, held from the library's load to the end
+ * of the process, which takes about nA + nB bytes for a result of nA and nB
+ * rows; larger results fail with C3X_ERANGE and nothing is written. All work
+ * is queued on `stream` (NULL: the null stream) and the call returns
+ * without waiting for it. Every call on one GPU shares that GPU's array and
+ * leaves it holding its data: calls that overlap in time on one GPU
+ * (different streams or host threads) race and must not be made. Errors:
+ * C3X_EINVAL (NULL argument, batch result, selection not C3X_ALL or
+ * C3X_BEST or not in r's mode, capacity below nA or nB), C3X_ERANGE,
+ * C3X_EDEVICE. */
+c3x_status c3x_result_unmatched_noalloc(const c3x_result *r, unsigned selection, void *stream,
+                                        int32_t *rowsA, int64_t capA, int32_t *rowsB,
+                                        int64_t capB, int64_t *counts);
+
 /* Symmetric best pairs (Section 2.2, the "best" match selection, read as
  * the pairs that are each other's nearest match). Seen from catalogue B,
  * each B row's nearest A row is the one at the smallest exact angle among

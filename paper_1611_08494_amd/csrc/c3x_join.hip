@@ -9,6 +9,7 @@
 //   k_tile_compact              the unmatched rows, ascending         (1 B in, 4 B out per row)
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "c3x_host.h"
 #include "c3x_internal.h"
@@ -197,5 +198,157 @@ extern "C" c3x_status c3x_result_unmatched(c3x_result *r, unsigned selection, vo
     *n_rowsA = (int64_t)h[0];
     *rowsB = r->unB;
     *n_rowsB = (int64_t)h[1];
+    return C3X_OK;
+}
+
+// ---------------------------------------------------------------------------- no allocation
+
+namespace c3x {
+
+// Working memory of c3x_result_unmatched_noalloc: one array per GPU, held
+// until the process ends. Host code reaches it only through the address
+// hipGetSymbolAddress gives for the current device (the array's own name is
+// a host stand-in, not a device address).
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch[kMaxDevices];
+
+// The current device's copy of the array (set-up once per device, with that
+// device current); null, with the message set, when it cannot be had.
+static uint8_t *scratch_on_device(int *dev_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        fail(C3X_EDEVICE, "no current HIP device (or more than %d devices)", kMaxDevices);
+        return nullptr;
+    }
+    *dev_out = dev;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(C3X_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch[dev] = (uint8_t *)p;
+    }
+    return g_scratch[dev];
+}
+
+__global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0u;
+}
+
+// Counts of unmatched rows to the caller's device array; -1 for both when a
+// stored pair named a row outside its catalogue.
+__global__ void k_unmatched_counts(const uint32_t *__restrict__ ctr, int64_t *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const bool bad = ctr[2] != 0;
+        out[0] = bad ? -1 : (int64_t)ctr[0];
+        out[1] = bad ? -1 : (int64_t)ctr[1];
+    }
+}
+
+static inline size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Bytes of the array a result of nA and nB rows needs.
+static size_t noalloc_bytes(int64_t nA, int64_t nB)
+{
+    const int64_t tA = (nA + kJoinTile - 1) / kJoinTile, tB = (nB + kJoinTile - 1) / kJoinTile;
+    return up256((size_t)nA) + up256((size_t)nB) + 2 * up256((size_t)(tA + tB) * 4) + 256 +
+           up256(scan_ws_bytes(std::max<int64_t>(std::max(tA, tB), 1)));
+}
+
+// The flags' rows with flag 0, ascending, as compact_unmatched, without the
+// zero-length scan's memset (n == 0 writes its zero total with a kernel).
+static hipError_t compact_noalloc(const uint8_t *f, int64_t n, int32_t *out, uint32_t *cnt,
+                                  uint32_t *off, uint32_t *total, void *ws, hipStream_t s)
+{
+    const int64_t nt = (n + kJoinTile - 1) / kJoinTile;
+    if (nt == 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, total, (int64_t)1);
+        return hipGetLastError();
+    }
+    return compact_unmatched(f, n, out, cnt, off, total, ws, s);
+}
+
+}  // namespace c3x
+
+extern "C" c3x_status c3x_result_unmatched_noalloc(const c3x_result *r, unsigned selection,
+                                                   void *stream, int32_t *rowsA, int64_t capA,
+                                                   int32_t *rowsB, int64_t capB,
+                                                   int64_t *counts)
+{
+    clear_error();
+    if (!r || !counts || (r->nA > 0 && !rowsA) || (r->nB > 0 && !rowsB))
+        return fail(C3X_EINVAL, "NULL argument");
+    if (r->nB < 0)
+        return fail(C3X_EINVAL, "unmatched rows are defined for c3x_match results only (a batch "
+                                "result holds job-local rows)");
+    if (selection != C3X_ALL && selection != C3X_BEST)
+        return fail(C3X_EINVAL, "selection must be C3X_ALL or C3X_BEST");
+    if (selection == C3X_ALL && !(r->mode & C3X_ALL))
+        return fail(C3X_EINVAL, "selection C3X_ALL needs a result made with C3X_ALL");
+    if (selection == C3X_BEST && !(r->mode & C3X_BEST))
+        return fail(C3X_EINVAL, "selection C3X_BEST needs a result made with C3X_BEST");
+    const int64_t nA = r->nA, nB = r->nB;
+    if (capA < nA || capB < nB)
+        return fail(C3X_EINVAL, "output capacities %lld, %lld below the result's %lld A and %lld "
+                                "B rows", (long long)capA, (long long)capB, (long long)nA,
+                    (long long)nB);
+    const size_t need = noalloc_bytes(nA, nB);
+    if (need > kNoAllocBytes)
+        return fail(C3X_ERANGE, "%lld A + %lld B rows need %zu bytes of working memory, above the "
+                                "fixed %zu", (long long)nA, (long long)nB, need, kNoAllocBytes);
+    int dev = 0;
+    uint8_t *base = scratch_on_device(&dev);
+    if (!base) return C3X_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t tA = (nA + kJoinTile - 1) / kJoinTile, tB = (nB + kJoinTile - 1) / kJoinTile;
+    uint8_t *at = base;
+    uint8_t *fa = at;
+    at += up256((size_t)nA);
+    uint8_t *fb = at;
+    at += up256((size_t)nB);
+    uint32_t *cnt = (uint32_t *)at;
+    at += up256((size_t)(tA + tB) * 4);
+    uint32_t *off = (uint32_t *)at;
+    at += up256((size_t)(tA + tB) * 4);
+    uint32_t *ctr = (uint32_t *)at;  // total A, total B, error
+    at += 256;
+    void *ws = at;
+    // the array keeps the last call's contents: clear what must start at zero
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr, (int64_t)4);
+    if (nA > 0) hipLaunchKernelGGL(k_fill_u8, dim3(jblk(nA, 256)), dim3(256), 0, s, fa, nA);
+    if (nB > 0) hipLaunchKernelGGL(k_fill_u8, dim3(jblk(nB, 256)), dim3(256), 0, s, fb, nB);
+    if (selection == C3X_ALL) {
+        if (r->n_pairs > 0)
+            hipLaunchKernelGGL(k_mark_pairs, dim3(jblk(r->n_pairs, 256)), dim3(256), 0, s, r->idxA,
+                               r->idxB, r->n_pairs, nA, nB, fa, fb, ctr + 2);
+    } else if (nA > 0) {
+        hipLaunchKernelGGL(k_mark_best, dim3(jblk(nA, 256)), dim3(256), 0, s, r->best_idx, nA, nB,
+                           fa, fb, ctr + 2);
+    }
+    JCHK(hipGetLastError(), "mark");
+    JCHK(compact_noalloc(fa, nA, rowsA, cnt, off, ctr + 0, ws, s), "compact A");
+    JCHK(compact_noalloc(fb, nB, rowsB, cnt + tA, off + tA, ctr + 1, ws, s), "compact B");
+    hipLaunchKernelGGL(k_unmatched_counts, dim3(1), dim3(64), 0, s, ctr, counts);
+    JCHK(hipGetLastError(), "counts");
+    (void)dev;
     return C3X_OK;
 }
