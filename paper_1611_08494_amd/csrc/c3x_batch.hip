@@ -371,12 +371,15 @@ __global__ void k_brows(const uint2 *__restrict__ tie, const uint32_t *__restric
 
 // Pair and best outputs in job-local rows.
 __global__ void k_blocal_pairs(const BJob *__restrict__ jobs, const uint32_t *__restrict__ ejobA,
-                               const int64_t *__restrict__ P, int64_t cap,
+                               const int64_t *__restrict__ P, int64_t cap, int64_t nA,
                                int32_t *__restrict__ ia, int32_t *__restrict__ ib)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= min(*P, cap)) return;
     const uint32_t a = (uint32_t)ia[p];
+    // the slots of rows above 2048 matches are written after the graph (and
+    // renumbered then): whatever they hold now is skipped
+    if (a >= (uint64_t)nA) return;
     const BJob &jb = jobs[ejobA[a]];
     ia[p] = (int32_t)(a - jb.a_ent);
     ib[p] = (int32_t)((uint32_t)ib[p] - jb.b_ent);
@@ -389,6 +392,24 @@ __global__ void k_blocal_best(const BJob *__restrict__ jobs, const uint32_t *__r
     if (a >= n || best[a] < 0) return;
     const BJob &jb = jobs[ejobA[a]];
     best[a] = (int32_t)((uint32_t)best[a] - jb.b_ent);
+}
+
+// Job-local rows of the pairs of rows listed in `rows` (ordered after the
+// graph, by finish_huge): one workgroup per row, grid-stride.
+__global__ void k_blocal_rows(const uint32_t *__restrict__ rows, uint32_t n,
+                              const int64_t *__restrict__ off, const BJob *__restrict__ jobs,
+                              const uint32_t *__restrict__ ejobA, int64_t nA,
+                              int32_t *__restrict__ ia, int32_t *__restrict__ ib)
+{
+    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const uint32_t a = rows[r];
+        if (a >= (uint64_t)nA) continue;
+        const BJob &jb = jobs[ejobA[a]];
+        for (int64_t q = off[a] + threadIdx.x; q < off[a + 1]; q += blockDim.x) {
+            ia[q] = (int32_t)(a - jb.a_ent);
+            ib[q] = (int32_t)((uint32_t)ib[q] - jb.b_ent);
+        }
+    }
 }
 
 // New best of a row the host ranked: job-local index and separation.
@@ -501,7 +522,11 @@ struct c3x_batch {
     // look-back gave up (the graph is then captured again without it)
     bool onesweep = true;
     c3x_stats stats{};
-    double cell_scale = 1.0;
+    double cell_scale = 1.0;       // the scale the autotuner set for every class first
+    // per density class of job (by its B rows, see job_class): the cell
+    // scale, and the count kernel's tile (A sources per workgroup)
+    double kappa_class[4] = {1.0, 1.0, 1.0, 1.0};
+    int tile = 256;
     std::vector<int64_t> hjoboff;
 
     ~c3x_batch()
@@ -633,15 +658,15 @@ static hipError_t batch_front(c3x_batch *b)
                            b->ejobA, b->packA, NA, b->g, b->arad, b->aidx, b->ajob, b->arng);
     // count + emit
     MatchArgs m = batch_args(b);
-    const unsigned grid = nblk(NA, kMatchBlock);
+    const unsigned grid = nblk(NA, b->tile);
     if (grid) {
         hipLaunchKernelGGL(k_bfill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->cnts, NA, 0u);
         if (b->prec == C3X_FP64)
             hipLaunchKernelGGL((k_match<C3X_CIRCLE, C3X_FP64, 2, true>), dim3(grid),
-                               dim3(kMatchBlock), 0, s, m);
+                               dim3(b->tile), 0, s, m);
         else
             hipLaunchKernelGGL((k_match<C3X_CIRCLE, C3X_MIXED, 2, true>), dim3(grid),
-                               dim3(kMatchBlock), 0, s, m);
+                               dim3(b->tile), 0, s, m);
     }
     // band candidates: FP64 recheck, then the host decides what is left
     hipLaunchKernelGGL(k_brecheck, dim3(nblk(b->amb_cap, 256)), dim3(256), 0, s, b->amb,
@@ -688,21 +713,11 @@ static hipError_t batch_front(c3x_batch *b)
     return hipGetLastError();
 }
 
-// Placement and output half (capacity P_cap).
-static hipError_t batch_back(c3x_batch *b)
+// What the finishing kernels need, for the batch's buffers.
+static FinishArgs batch_fin_args(c3x_batch *b)
 {
-    hipStream_t s = b->s;
-    const int64_t NA = b->NA;
-    if (b->ov_pool)
-        hipLaunchKernelGGL(k_place_ov, dim3(nblk(b->ov_pool, 256), kEmitPools), dim3(256), 0, s,
-                           b->ovl, b->ov_pool, b->octr, NA, b->off, b->P_cap, b->pt, b->c64 + 2,
-                           b->ctr + 4);
-    hipLaunchKernelGGL(k_place_x, dim3(nblk(b->bin_cap, 256)), dim3(256), 0, s, b->xent,
-                       b->bin_cap, b->ctr + 8, b->aidx, b->arad, b->coordB, NA, b->NB,
-                       b->off,
-                       b->P_cap, b->rec, 1, b->pt, b->c64 + 2, b->ctr + 4);
     FinishArgs fa{};
-    fa.nA = NA;
+    fa.nA = b->NA;
     fa.nB = b->NB;
     fa.pcap = b->P_cap;
     fa.off = b->off;
@@ -718,13 +733,31 @@ static hipError_t batch_back(c3x_batch *b)
     fa.os = b->os;
     fa.bsep = b->obsep;
     fa.err = b->ctr + 4;
+    fa.sort_fail = nullptr;  // rows above 2048 matches: table-schedule sorts
     fa.seg_n = b->ctr + 6;
     fa.cap = b->seg_cap;
     fa.list = b->seg_list;
     fa.huge = b->seg_huge;
+    return fa;
+}
+
+// Placement and output half (capacity P_cap).
+static hipError_t batch_back(c3x_batch *b)
+{
+    hipStream_t s = b->s;
+    const int64_t NA = b->NA;
+    if (b->ov_pool)
+        hipLaunchKernelGGL(k_place_ov, dim3(nblk(b->ov_pool, 256), kEmitPools), dim3(256), 0, s,
+                           b->ovl, b->ov_pool, b->octr, NA, b->off, b->P_cap, b->pt, b->c64 + 2,
+                           b->ctr + 4);
+    hipLaunchKernelGGL(k_place_x, dim3(nblk(b->bin_cap, 256)), dim3(256), 0, s, b->xent,
+                       b->bin_cap, b->ctr + 8, b->aidx, b->arad, b->coordB, NA, b->NB,
+                       b->off,
+                       b->P_cap, b->rec, 1, b->pt, b->c64 + 2, b->ctr + 4);
+    const FinishArgs fa = batch_fin_args(b);
     finish_segments(fa, s);
     hipLaunchKernelGGL(k_blocal_pairs, dim3(nblk(std::max<int64_t>(b->P_cap, 1), 256)), dim3(256),
-                       0, s, b->djobs, b->ejobA, b->off + NA, b->P_cap, b->oa, b->ob);
+                       0, s, b->djobs, b->ejobA, b->off + NA, b->P_cap, NA, b->oa, b->ob);
     hipLaunchKernelGGL(k_blocal_best, dim3(nblk(std::max<int64_t>(NA, 1), 256)), dim3(256), 0, s,
                        b->djobs, b->ejobA, NA, b->obest);
     hipLaunchKernelGGL(k_bjob_off, dim3(nblk(b->nj + 1, 256)), dim3(256), 0, s, b->djobs, b->nj,
@@ -732,15 +765,26 @@ static hipError_t batch_back(c3x_batch *b)
     return hipGetLastError();
 }
 
-// Grids of every job for cell scale kappa (tangent-plane units): the cell
-// side is kappa times the mean spacing of the job's B sources, at least the
-// window half-width (so a window spans at most three rows) and at least
-// 1e-4 arcsec; all cells must fit 32-bit keys.
-static c3x_status batch_grids(c3x_batch *b, double kappa)
+// Density class of a job, by its number of B rows: below 4k, 40k, 400k,
+// and above (the autotuner picks a cell scale per class).
+static inline int job_class(uint32_t nB)
 {
+    return nB < 4000u ? 0 : (nB < 40000u ? 1 : (nB < 400000u ? 2 : 3));
+}
+
+// Grids of every job for the cell scale of its class (tangent-plane
+// units): the cell side is kappa times the mean spacing of the job's B
+// sources, at least the window half-width (so a window spans at most three
+// rows) and at least 1e-4 arcsec; all cells must fit 32-bit keys. kappa > 0
+// sets every class to it first.
+static c3x_status batch_grids(c3x_batch *b, double kappa_all)
+{
+    if (kappa_all > 0.0)
+        for (double &k : b->kappa_class) k = kappa_all;
     uint64_t base = 0;
     for (int j = 0; j < b->nj; ++j) {
         BJob &jb = b->hjobs[j];
+        const double kappa = b->kappa_class[job_class(jb.nB)];
         const double T = jb.T;  // box half-side, set by the plan
         const double area = 4.0 * T * T;
         const double spacing = sqrt(area / (double)std::max<uint32_t>(jb.nB, 1u));
@@ -772,7 +816,7 @@ static c3x_status batch_grids(c3x_batch *b, double kappa)
     b->g.dshift = sh;
     b->g.dsize = (uint32_t)((maxkey >> sh) + 2);
     b->g.nB = (int32_t)b->NB;
-    b->cell_scale = kappa;
+    if (kappa_all > 0.0) b->cell_scale = kappa_all;
     hipError_t e = hipMemcpyAsync(b->djobs, b->hjobs.data(), b->nj * sizeof(BJob),
                                   hipMemcpyHostToDevice, b->s);
     if (e != hipSuccess) return fail_hip(e, "batch job table");
@@ -1083,34 +1127,105 @@ static c3x_status batch_plan_impl(c3x_batch *b)
         clear_error();
     }
 
-    // autotuner: time the index + count half at a few cell scales
-    const char *fixed = getenv("C3X_BATCH_CELL_SCALE");
-    std::vector<double> scales = {0.5, 1.0, 2.0, 4.0};
-    if (fixed) scales = {std::max(0.05, atof(fixed))};
-    double best_ms = 1e300, best_k = scales[0];
-    if (scales.size() > 1) {
-        hipEvent_t e0, e1;
-        BCHK(hipEventCreate(&e0), "events");
-        BCHK(hipEventCreate(&e1), "events");
-        for (double k : scales) {
-            c3x_status st = batch_grids(b, k);
-            if (st != C3X_OK) continue;
+    // autotuner: times the index + count half (the best of two runs of each
+    // setting): first one cell scale for every job, then the count kernel's
+    // tile, then each density class's own cell scale in turn. Settings only
+    // change the speed, never the answer. C3X_BATCH_CELL_SCALE fixes one
+    // scale for all classes, C3X_BATCH_CELL_SCALES "k0,k1,k2,k3" one per
+    // class, C3X_BATCH_TILE the tile (64, 128 or 256).
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0), "events");
+    BCHK(hipEventCreate(&e1), "events");
+    auto timed = [&](double &ms) -> c3x_status {
+        ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
             BCHK(hipEventRecord(e0, s), "events");
             BCHK(batch_front(b), "batch pipeline");
             BCHK(hipEventRecord(e1, s), "events");
             BCHK(hipEventSynchronize(e1), "events");
-            float ms = 0.f;
-            BCHK(hipEventElapsedTime(&ms, e0, e1), "events");
+            float t = 0.f;
+            BCHK(hipEventElapsedTime(&t, e0, e1), "events");
+            ms = std::min(ms, (double)t);
+        }
+        return C3X_OK;
+    };
+    const std::vector<double> scales = {0.5, 1.0, 2.0, 4.0};
+    const char *fixed = getenv("C3X_BATCH_CELL_SCALE");
+    const char *fixed_cls = getenv("C3X_BATCH_CELL_SCALES");
+    const char *fixed_tile = getenv("C3X_BATCH_TILE");
+    bool present[4] = {false, false, false, false};
+    for (const BJob &jb : b->hjobs) present[job_class(jb.nB)] = true;
+    double best_ms = 1e300;
+    c3x_status st = C3X_OK;
+    if (fixed_cls) {
+        double k[4] = {1.0, 1.0, 1.0, 1.0};
+        sscanf(fixed_cls, "%lf,%lf,%lf,%lf", &k[0], &k[1], &k[2], &k[3]);
+        for (int c = 0; c < 4; ++c) b->kappa_class[c] = std::max(0.05, k[c]);
+        st = batch_grids(b, 0.0);
+        if (st != C3X_OK) return st;
+    } else if (fixed) {
+        st = batch_grids(b, std::max(0.05, atof(fixed)));
+        if (st != C3X_OK) return st;
+    } else {
+        double best_k = 1.0;
+        for (double k : scales) {
+            if (batch_grids(b, k) != C3X_OK) continue;
+            double ms;
+            st = timed(ms);
+            if (st != C3X_OK) return st;
             if (ms < best_ms) {
                 best_ms = ms;
                 best_k = k;
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        st = batch_grids(b, best_k);
+        if (st != C3X_OK) return st;
     }
-    c3x_status st = batch_grids(b, best_k);
-    if (st != C3X_OK) return st;
+    if (fixed_tile) {
+        const int t = atoi(fixed_tile);
+        b->tile = (t == 64 || t == 128) ? t : 256;
+    } else {
+        int best_t = b->tile;
+        double tms = 1e300;
+        for (int t : {64, 128, 256}) {
+            b->tile = t;
+            double ms;
+            st = timed(ms);
+            if (st != C3X_OK) return st;
+            if (ms < tms) {
+                tms = ms;
+                best_t = t;
+            }
+        }
+        b->tile = best_t;
+        best_ms = tms;
+    }
+    if (!fixed && !fixed_cls) {
+        // each class's own scale, the others held (kept when 2% faster)
+        for (int c = 0; c < 4; ++c) {
+            if (!present[c]) continue;
+            const double keep = b->kappa_class[c];
+            double bk = keep, bms = best_ms;
+            for (double k : scales) {
+                if (k == keep) continue;
+                b->kappa_class[c] = k;
+                if (batch_grids(b, 0.0) != C3X_OK) continue;
+                double ms;
+                st = timed(ms);
+                if (st != C3X_OK) return st;
+                if (ms < bms * 0.98) {
+                    bms = ms;
+                    bk = k;
+                }
+            }
+            b->kappa_class[c] = bk;
+            best_ms = bms;
+        }
+        st = batch_grids(b, 0.0);
+        if (st != C3X_OK) return st;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     clear_error();
 
     // first run: sizes the lists (grown and run again while one overflows)
@@ -1158,8 +1273,24 @@ static c3x_status batch_finish(c3x_batch *b)
                     "%u of %u, tie list %u of %u, overflow %u): plan again",
                     (long long)P, (long long)b->P_cap, hc[1], b->amb_cap, hc[2], b->tie_cap,
                     hc[5]);
-    if (hc[7]) return fail(C3X_EINVAL, "a batch source has more than 2048 matches: use c3x_match");
-    if (hc[4] || h64[2] != (unsigned long long)P)
+    if (h64[2] != (unsigned long long)P)
+        return fail(C3X_EDEVICE, "internal: batch placement flags %u, %llu of %lld placed", hc[4],
+                    h64[2], (long long)P);
+    if (hc[7]) {
+        // rows with more than 2048 matches: ordered by one segmented sort of
+        // all of them after the graph, then renumbered job-locally
+        const FinishArgs fa = batch_fin_args(b);
+        c3x_status st = finish_huge(fa, hc + 6, s);
+        if (st != C3X_OK) return st;
+        const uint32_t nh = std::min(hc[7], b->seg_cap);
+        hipLaunchKernelGGL(k_blocal_rows, dim3(std::min<uint32_t>(nh, 4096)), dim3(256), 0, s,
+                           b->seg_huge, nh, b->off, b->djobs, b->ejobA, b->NA, b->oa, b->ob);
+        BCHK(hipGetLastError(), "long rows");
+        BCHK(hipMemcpyAsync(&hc[4], b->ctr + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+             "copy");
+        BCHK(hipStreamSynchronize(s), "long rows");
+    }
+    if (hc[4])
         return fail(C3X_EDEVICE, "internal: batch placement flags %u, %llu of %lld placed", hc[4],
                     h64[2], (long long)P);
     b->P = P;
@@ -1306,7 +1437,7 @@ extern "C" c3x_status c3x_batch_plan(const c3x_job *jobs, int32_t n_jobs, const 
     b->stats.n_b = SB;
     b->stats.n_pairs = b->P;
     b->stats.precision = o.precision;
-    b->stats.tile = kMatchBlock;
+    b->stats.tile = b->tile;
     b->stats.cell_arcsec = b->cell_scale;
     *out = b;
     return C3X_OK;

@@ -1688,11 +1688,15 @@ __global__ void k_huge_gather(const uint32_t *__restrict__ huge, uint32_t nh,
     }
 }
 
+// val is a permutation of [0, n) unless the sort by idxB gave up (the call
+// is then redone and its slots may hold anything): other values get key 0.
 __global__ void k_huge_segkey(const uint32_t *__restrict__ val, const uint32_t *__restrict__ seg,
                               uint32_t n, uint32_t *__restrict__ key)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) key[t] = seg[val[t]];
+    if (t >= n) return;
+    const uint32_t v = val[t];
+    key[t] = v < n ? seg[v] : 0u;
 }
 
 // Entry i of the final order: gathered entry e = val[i] of segment h, whose

@@ -392,10 +392,10 @@ __global__ void k_sort_iota(uint32_t *__restrict__ p, int64_t n)
     if (t < n) p[t] = (uint32_t)t;
 }
 
-__global__ void k_sort_clear(uint32_t *__restrict__ p, int64_t n)
+__global__ void k_sort_clear(uint32_t *__restrict__ p, int64_t n, uint32_t v)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = 0u;
+    if (t < n) p[t] = v;
 }
 
 // ---------------------------------------------------------------------------- scans
@@ -618,13 +618,22 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
         uint32_t *status = tctr + 64;
         const int64_t words = (int64_t)onesweep_words(nb, npass);
         hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
-                           ghist, words);
+                           ghist, words, 0u);
         const unsigned hb = (unsigned)std::min<int64_t>((n + 4 * kSortBlock - 1) / (4 * kSortBlock),
                                                         2048);
         hipLaunchKernelGGL(k_digit_hist_all, dim3(hb), dim3(kSortBlock), 0, s, keys, n, lo_bit,
                            npass, ghist);
         uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
+        // with a test spin limit, every output slot starts as 0xffffffff, so
+        // that the slots a pass that gave up leaves unwritten always hold an
+        // out-of-range value (what every reader must survive)
+        const bool poison = getenv("C3X_DEBUG_SORT_SPIN") != nullptr;
+        const unsigned fb = (unsigned)((n + 255) / 256);
         for (int p = 0; p < npass; ++p) {
+            if (poison) {
+                hipLaunchKernelGGL(k_sort_clear, dim3(fb), dim3(256), 0, s, kb, n, 0xffffffffu);
+                hipLaunchKernelGGL(k_sort_clear, dim3(fb), dim3(256), 0, s, vb, n, 0xffffffffu);
+            }
             hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka,
                                p == 0 ? vfirst : va, kb, vb, n, lo_bit + 8 * p, ghist + 256 * p,
                                tctr + p,

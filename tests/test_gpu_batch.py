@@ -159,3 +159,71 @@ def test_batch_errors(c3x, dev):
     bad = _t([10.0, float("nan")], dev)
     with pytest.raises(c3x.C3XError):
         c3x.Batch([(0, 2, 0, 2, 1.0)], bad, de, ra, de)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_rows_with_thousands_of_matches(c3x, dev, precision):
+    """A job whose sources hold tens of thousands of matches each (ordered
+    after the graph by one segmented sort, then renumbered job-locally),
+    beside ordinary jobs; every job against the oracle, and a replay."""
+    import oracle
+    g = np.random.default_rng(31)
+    rb, db = synth.cap_uniform(g, 120_000, 40.0, -30.0, 0.3)
+    ra, da = synth.cap_uniform(g, 10, 40.0, -30.0, 0.05)
+    raA2, decA2, raB2, decB2, jobs2 = small_batch(seed=6)
+    raA = np.concatenate([raA2, ra])
+    decA = np.concatenate([decA2, da])
+    raB = np.concatenate([raB2, rb])
+    decB = np.concatenate([decB2, db])
+    jobs = list(jobs2) + [(len(raA2), len(ra), len(raB2), len(rb), 400.0)]
+    ors = [oracle.match(raA[ao:ao + na], decA[ao:ao + na], raB[bo:bo + nb], decB[bo:bo + nb],
+                        radius_arcsec=r) for ao, na, bo, nb, r in jobs]
+    assert np.bincount(ors[-1].ia).max() > 2048
+    print(f"[gpu] batch long rows precision={precision}", flush=True)
+    b = c3x.Batch(jobs, _t(raA, dev), _t(decA, dev), _t(raB, dev), _t(decB, dev),
+                  precision=precision)
+    check_batch(b.result(), b.pair_offsets(), jobs, ors)
+    b.run()
+    check_batch(b.result(), b.pair_offsets(), jobs, ors)
+    b.free()
+
+
+def _result_bytes(b):
+    r = b.result()
+    return [t.cpu().numpy().tobytes() for t in (r.idxA, r.idxB, r.sep, r.best_idx, r.best_sep)]
+
+
+@pytest.mark.parametrize("name,value", [("C3X_BATCH_TILE", "64"), ("C3X_BATCH_TILE", "128"),
+                                        ("C3X_BATCH_TILE", "256"),
+                                        ("C3X_BATCH_CELL_SCALES", "0.5,4,1,2"),
+                                        ("C3X_BATCH_CELL_SCALES", "4,0.5,2,0.5")])
+def test_batch_autotuner_choices_give_identical_bytes(c3x, dev, name, value, monkeypatch):
+    """Every setting the autotuner may pick -- the count kernel's tile, a
+    cell scale per density class of job -- gives byte-identical outputs;
+    the default (autotuned) run reports the tile it chose."""
+    raA, decA, raB, decB, jobs = small_batch(seed=12)
+    # jobs in every density class: add two larger ones
+    g = np.random.default_rng(13)
+    extra = []
+    for n in (6_000, 50_000):
+        ra, de = synth.cap_uniform(g, n, 120.0, -40.0, 0.5)
+        rb, db = synth.cap_uniform(g, 10 * n, 120.0, -40.0, 0.5)
+        extra.append((ra, de, rb, db))
+    for ra, de, rb, db in extra:
+        jobs.append((len(raA), len(ra), len(raB), len(rb), 3.0))
+        raA, decA = np.concatenate([raA, ra]), np.concatenate([decA, de])
+        raB, decB = np.concatenate([raB, rb]), np.concatenate([decB, db])
+    t = [_t(x, dev) for x in (raA, decA, raB, decB)]
+    b0 = c3x.Batch(jobs, *t, precision=1)
+    want = _result_bytes(b0)
+    assert b0.stats()["tile"] in (64, 128, 256)
+    b0.free()
+    monkeypatch.setenv(name, value)
+    print(f"[gpu] batch {name}={value}", flush=True)
+    b = c3x.Batch(jobs, *t, precision=1)
+    assert _result_bytes(b) == want
+    if name == "C3X_BATCH_TILE":
+        assert b.stats()["tile"] == int(value)
+    b.run()
+    assert _result_bytes(b) == want
+    b.free()
