@@ -311,15 +311,23 @@ def single_config(a, c3x, torch, np, name):
     # recheck and the read-back). Algorithmic bytes per launch: those of the
     # whole cross-match (algorithmic_bytes), since the one launch reads every
     # A and every B payload and decides every pair.
+    # When most rows have many candidates (ellipses in a dense band), the
+    # wavefront-per-row kernel does the counting instead: the count phase
+    # (both kernels, the band recheck and one read-back) is then the figure.
     hp = head["phases_ms"]
     alg_bytes = head["algorithmic_bytes"]
-    achieved = alg_bytes / (hp["count_kernel"] / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_match (count + emit pass)",
+    lane_kernel = hp["count_kernel"] >= 0.5 * hp["count"]
+    kms = hp["count_kernel"] if lane_kernel else hp["count"]
+    achieved = alg_bytes / (kms / 1e3) / 1e9
+    roofline = {"bound": "hbm",
+                "kernel": "k_match (count + emit pass)" if lane_kernel else
+                          "count phase (k_match_wide + k_match)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": committed_traffic(name, order[0]) if a.scale == 1.0 else None,
+                "traffic": (committed_traffic(name, order[0])
+                            if a.scale == 1.0 and lane_kernel else None),
                 "algorithmic_bytes_per_launch": int(alg_bytes),
-                "kernel_ms": round(hp["count_kernel"], 4),
+                "kernel_ms": round(kms, 4),
                 "step_frac": head["step_hbm_frac"]}
 
     cpu = None
@@ -415,13 +423,17 @@ def batch_config(a, c3x, torch, np):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000.0 / a.steps
         st = b.stats()
+        alg = algorithmic_bytes(cat, st["n_pairs"], 16 if prec == c3x.MIXED else 32, True)
         paths[pname] = dict(ms_per_step=ms, graph_ms=mean(gms), a_per_s=cat.nA / (ms / 1e3),
+                            algorithmic_bytes=int(alg),
+                            step_hbm_frac=round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                             pair_tests=int(st["n_tests"]),
                             pair_tests_per_s=st["n_tests"] / (ms / 1e3),
                             n_pairs=int(st["n_pairs"]), n_band=int(st["n_band"]),
                             n_ambiguous=int(st["n_ambiguous"]),
                             n_best_ties=int(st["n_best_ties"]), plan_s=round(plan_s, 2),
-                            cell_scale=st["cell_arcsec"])
+                            cell_scale=st["cell_arcsec"], tile=int(st["tile"]),
+                            queue=int(st["queue"]))
         log(f"{pname}: {ms:.3f} ms/step (graph {mean(gms):.3f} ms), plan {plan_s:.1f}s")
         b.free()
         if not a.no_per_job:
@@ -466,7 +478,18 @@ def batch_config(a, c3x, torch, np):
                    "parallelism": "single GPU"},
         "pair_tests_per_s": round(head["pair_tests_per_s"], 1),
         "paths": paths,
-        "roofline": None,
+        # the whole batch is one graph launch: its algorithmic bytes over the
+        # graph's own duration (HIP events around the launch)
+        "roofline": {"bound": "hbm", "kernel": "batch graph (one launch per step)",
+                     "achieved": round(head["algorithmic_bytes"] / (head["graph_ms"] / 1e3) / 1e9,
+                                       1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(head["algorithmic_bytes"] / (head["graph_ms"] / 1e3) / 1e9 /
+                                   HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "algorithmic_bytes_per_launch": head["algorithmic_bytes"],
+                     "kernel_ms": round(head["graph_ms"], 4),
+                     "step_frac": head["step_hbm_frac"]},
         "cpu_baseline": cpu,
     }
     if "fp64" in paths and "mixed" in paths:

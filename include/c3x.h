@@ -175,7 +175,8 @@ typedef struct {
     double ms_count_kernel;   /* the count kernel's own launch (one lane per source) */
     int32_t n_sort_retries;   /* 1: a large radix sort's look-back gave up and the call's
                                  work was redone with the table schedule */
-    int32_t pad;
+    int32_t queue;            /* batch: 1 when its count pass runs as the persistent kernel
+                                 taking tiles costliest first (0: one workgroup per tile) */
 } c3x_stats;
 
 /* Builds the sky index over catalogue B: validates the rows, puts each row

@@ -67,7 +67,7 @@ class Stats(ctypes.Structure):
         ("ms_total", ctypes.c_double), ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("ms_count_kernel", ctypes.c_double),
         ("n_sort_retries", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("queue", ctypes.c_int32),
     ]
 
     def as_dict(self):

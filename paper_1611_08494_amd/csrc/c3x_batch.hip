@@ -527,6 +527,13 @@ struct c3x_batch {
     // scale, and the count kernel's tile (A sources per workgroup)
     double kappa_class[4] = {1.0, 1.0, 1.0, 1.0};
     int tile = 256;
+    // count pass as a persistent kernel taking tiles costliest first (else
+    // one workgroup per tile, in order); its tile cost keys, order, counter
+    bool queue = false;
+    unsigned queue_blocks = 0;     // workgroups of the persistent kernel
+    uint32_t *qk = nullptr, *qv = nullptr, *qk2 = nullptr, *qv2 = nullptr, *qctr = nullptr;
+    float *jcost = nullptr;
+    void *qws = nullptr;
     std::vector<int64_t> hjoboff;
 
     ~c3x_batch()
@@ -659,7 +666,29 @@ static hipError_t batch_front(c3x_batch *b)
     // count + emit
     MatchArgs m = batch_args(b);
     const unsigned grid = nblk(NA, b->tile);
-    if (grid) {
+    if (grid && b->queue) {
+        // tiles of the costliest jobs first (a job's cost: the candidates of
+        // its rows), each job's tiles together and in order, taken from a
+        // counter by a persistent grid
+        hipLaunchKernelGGL(k_bfill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->cnts, NA, 0u);
+        hipLaunchKernelGGL(k_job_cost, dim3(std::min(nj, 4096)), dim3(256), 0, s, b->djobs, nj,
+                           b->arng, b->jcost);
+        hipLaunchKernelGGL(k_tile_cost, dim3(nblk(grid, 256)), dim3(256), 0, s, b->ajob, b->jcost,
+                           NA, (uint32_t)b->tile, grid, b->qk, b->qv);
+        int qin = 0;
+        e = radix_sort_pairs(b->qk, b->qv, b->qk2, b->qv2, grid, 16, b->qws, s, &qin, false,
+                             nullptr);
+        if (e != hipSuccess) return e;
+        const uint32_t *order = qin ? b->qv2 : b->qv;
+        hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, b->qctr, (int64_t)1, 0u);
+        const unsigned pg = std::max(1u, std::min(grid, b->queue_blocks));
+        if (b->prec == C3X_FP64)
+            hipLaunchKernelGGL(k_match_queue<C3X_FP64>, dim3(pg), dim3(b->tile), 0, s, m, order,
+                               grid, b->qctr);
+        else
+            hipLaunchKernelGGL(k_match_queue<C3X_MIXED>, dim3(pg), dim3(b->tile), 0, s, m, order,
+                               grid, b->qctr);
+    } else if (grid) {
         hipLaunchKernelGGL(k_bfill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->cnts, NA, 0u);
         if (b->prec == C3X_FP64)
             hipLaunchKernelGGL((k_match<C3X_CIRCLE, C3X_FP64, 2, true>), dim3(grid),
@@ -824,6 +853,26 @@ static c3x_status batch_grids(c3x_batch *b, double kappa_all)
 }
 
 }  // namespace c3x
+
+// Workgroups of the persistent count kernel: as many as fit on the device
+// at once for the current tile.
+static c3x_status set_queue_blocks(c3x_batch *b)
+{
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) {
+        if (b->prec == C3X_FP64)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_match_queue<C3X_FP64>,
+                                                             b->tile, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_match_queue<C3X_MIXED>,
+                                                             b->tile, 0);
+    }
+    if (e != hipSuccess) return fail_hip(e, "persistent count kernel occupancy");
+    b->queue_blocks = (unsigned)std::max(1, ncu) * (unsigned)std::max(1, per);
+    return C3X_OK;
+}
 
 #define BCHK(expr, what)                                   \
     do {                                                   \
@@ -1098,7 +1147,17 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->obest = M.get_n<int32_t>(NA);
     b->obsep = M.get_n<double>(NA);
     b->joboff = M.get_n<int64_t>(nj + 1);
+    // the persistent count pass: tiles of at least 64 rows
+    const int64_t qmax = (NA + 63) / 64 + 1;
+    b->qk = M.get_n<uint32_t>(qmax);
+    b->qv = M.get_n<uint32_t>(qmax);
+    b->qk2 = M.get_n<uint32_t>(qmax);
+    b->qv2 = M.get_n<uint32_t>(qmax);
+    b->qws = M.get(radix_ws_bytes(qmax));
+    b->qctr = M.get_n<uint32_t>(1);
+    b->jcost = M.get_n<float>(std::max(nj, 1));
     bool ok = b->bk && b->bv && b->bk2 && b->bv2 && b->bws && (b->p64 || b->p32) &&
+              b->qk && b->qv && b->qk2 && b->qv2 && b->qws && b->qctr && b->jcost &&
               b->coordB && b->packA && b->packB &&
               b->dir && b->gaps && b->n_gaps &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
@@ -1199,6 +1258,23 @@ static c3x_status batch_plan_impl(c3x_batch *b)
         }
         b->tile = best_t;
         best_ms = tms;
+    }
+    // the count pass's mapping: one workgroup per tile in order, or the
+    // persistent kernel taking tiles costliest first (C3X_BATCH_QUEUE=0/1)
+    st = set_queue_blocks(b);
+    if (st != C3X_OK) return st;
+    if (const char *q = getenv("C3X_BATCH_QUEUE")) {
+        b->queue = atoi(q) != 0;
+    } else {
+        b->queue = false;
+        double ms_grid, ms_queue;
+        st = timed(ms_grid);
+        if (st != C3X_OK) return st;
+        b->queue = true;
+        st = timed(ms_queue);
+        if (st != C3X_OK) return st;
+        b->queue = ms_queue < ms_grid;
+        best_ms = std::min(ms_grid, ms_queue);
     }
     if (!fixed && !fixed_cls) {
         // each class's own scale, the others held (kept when 2% faster)
@@ -1438,6 +1514,7 @@ extern "C" c3x_status c3x_batch_plan(const c3x_job *jobs, int32_t n_jobs, const 
     b->stats.n_pairs = b->P;
     b->stats.precision = o.precision;
     b->stats.tile = b->tile;
+    b->stats.queue = b->queue ? 1 : 0;
     b->stats.cell_arcsec = b->cell_scale;
     *out = b;
     return C3X_OK;

@@ -535,26 +535,22 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long hm)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
 }
 
+// One sorted A row of the count / write pass (one lane each), its counters
+// added to tests, band and placed.
 // MODE 0: count + best; MODE 1: write every filter match into the
 // offsets from the count; MODE 2: count + best, the row's first kTab filter
 // matches kept for its record, later ones written to the overflow list.
 // BATCH: a batch of jobs (per-source thresholds and centre, local grids).
 template <int SHAPE, int PREC, int MODE, bool BATCH>
-__global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
+__device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
+                                          unsigned long long &tests, unsigned long long &band,
+                                          unsigned long long &placed)
 {
     using PayT = PayOf<PREC>;
-    __shared__ unsigned long long s_tests, s_band, s_placed;
-    if (threadIdx.x == 0) {
-        s_tests = 0;
-        s_band = 0;
-        s_placed = 0;
-    }
-    __syncthreads();
     const PayT *pay;
     if constexpr (PREC == C3X_FP64) pay = m.pay64;
     else pay = m.pay32;
 
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;  // blockDim.x <= kMatchBlock
     bool active = i < (uint32_t)m.nA;
     ARec a{};
     AEll e{};
@@ -589,7 +585,6 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         o = m.off[a.idx];
         oe = m.off[a.idx + 1];
     }
-    unsigned long long tests = 0, band = 0, placed = 0;
     CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
     if (BATCH && active) batch_ref(m, i, a, cc);
 
@@ -773,6 +768,20 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
             if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
         }
     }
+}
+
+// A workgroup's counters: summed in LDS, then one atomic per counter.
+template <int MODE>
+__device__ __forceinline__ void add_counters(const MatchArgs &m, unsigned long long tests,
+                                             unsigned long long band, unsigned long long placed)
+{
+    __shared__ unsigned long long s_tests, s_band, s_placed;
+    if (threadIdx.x == 0) {
+        s_tests = 0;
+        s_band = 0;
+        s_placed = 0;
+    }
+    __syncthreads();
     if (placed) atomicAdd(&s_placed, placed);
     if (tests) atomicAdd(&s_tests, tests);
     if (band) atomicAdd(&s_band, band);
@@ -782,6 +791,84 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
         if (s_band && MODE != 1) atomicAdd(stat_slot(m.n_band), s_band);
         if (s_placed) atomicAdd(stat_slot(m.n_placed), s_placed);
     }
+}
+
+// One lane per sorted A row, rows in order.
+template <int SHAPE, int PREC, int MODE, bool BATCH>
+__global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
+{
+    unsigned long long tests = 0, band = 0, placed = 0;
+    match_row<SHAPE, PREC, MODE, BATCH>(m, blockIdx.x * blockDim.x + threadIdx.x, tests, band,
+                                        placed);  // blockDim.x <= kMatchBlock
+    add_counters<MODE>(m, tests, band, placed);
+}
+
+// The batch's count pass as a persistent kernel: each workgroup takes tiles
+// (blockDim.x consecutive sorted A rows) from a counter, in the order
+// `order` lists them (the costliest first), until none is left; every
+// workgroup reads the same number of items past the end, so each reaches
+// the exit.
+template <int PREC>
+__global__ __launch_bounds__(kMatchBlock) void k_match_queue(MatchArgs m,
+                                                             const uint32_t *__restrict__ order,
+                                                             uint32_t n_items,
+                                                             uint32_t *__restrict__ qctr)
+{
+    __shared__ uint32_t s_item;
+    unsigned long long tests = 0, band = 0, placed = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(qctr, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();  // every lane has read it before the next take
+        if (it >= n_items) break;
+        const uint32_t tile = min(order[it], n_items - 1u);
+        match_row<C3X_CIRCLE, PREC, 2, true>(m, tile * blockDim.x + threadIdx.x, tests, band,
+                                             placed);
+    }
+    add_counters<2>(m, tests, band, placed);
+}
+
+// Cost of each job (the candidates its rows test, plus one per row): one
+// workgroup per job over its sorted rows (a job's sorted rows take its own
+// entries' places: [a_ent, a_ent + nA)).
+__global__ void k_job_cost(const BJob *__restrict__ jobs, int nj, const ARange *__restrict__ arng,
+                           float *__restrict__ cost)
+{
+    __shared__ float part[kMatchBlock / 64];
+    for (int j = blockIdx.x; j < nj; j += gridDim.x) {
+        const uint32_t a0 = jobs[j].a_ent, na = jobs[j].nA;
+        float c = 0.f;
+        for (uint32_t k = threadIdx.x; k < na; k += blockDim.x) {
+            const ARange g = arng[a0 + k];
+            c += 1.0f + (float)((uint32_t)g.n[0] + g.n[1] + g.n[2]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+        if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+            cost[j] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Sort key of each tile of `tile` sorted A rows: its job's cost (the job of
+// its first row) as the top 16 bits of a float (monotone), complemented, so
+// that a stable sort puts the costliest jobs first and keeps each job's
+// tiles together and in order (their B candidates stay close in memory).
+__global__ void k_tile_cost(const uint32_t *__restrict__ ajob, const float *__restrict__ jcost,
+                            int64_t nA, uint32_t tile, uint32_t n_items,
+                            uint32_t *__restrict__ key, uint32_t *__restrict__ val)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_items) return;
+    const int64_t r0 = min<int64_t>((int64_t)t * tile, nA - 1);
+    key[t] = 0xffffu - (__float_as_uint(jcost[ajob[r0]]) >> 16);
+    val[t] = t;
 }
 
 // Sources with many candidates (large areas, dense fields): one wavefront

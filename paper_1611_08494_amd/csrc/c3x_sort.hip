@@ -272,16 +272,20 @@ __device__ __forceinline__ uint32_t st_read(const uint32_t *p)
 // A tile waits only on tiles that took their numbers before it (and so are
 // running or done); a wait that exceeds spin_limit polls gives up, leaving
 // a wrong order but no access out of bounds, and sets *fail. spin_limit 0
-// (a test setting) makes every tile but the first give up at once.
+// (a test setting) makes every tile but the first give up at once. A tile is
+// kSortBlock * ITEMS elements (longer tiles: longer runs per digit in the
+// scatter, fewer look-backs).
+template <int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
     const uint32_t *__restrict__ ghist, uint32_t *__restrict__ tctr, uint32_t *status, int nb,
     uint32_t spin_limit, uint32_t *__restrict__ fail)
 {
-    constexpr int kPerWave = kSortTile / kWaves;  // 1024
-    constexpr int kRounds = kPerWave / 64;        // 16
-    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+    constexpr int kTile = kSortBlock * ITEMS;
+    constexpr int kPerWave = kTile / kWaves;  // 64 * ITEMS
+    constexpr int kRounds = kPerWave / 64;    // ITEMS
+    __shared__ uint32_t sk[kTile], sv[kTile];
     __shared__ uint32_t gbase[256], tstart[256];
     __shared__ uint32_t wc[kWaves][256];
     __shared__ uint32_t wsum[kWaves];
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= (uint32_t)nb) return;  // the counter was not cleared: nothing is touched
-    const int64_t tbase = (int64_t)tile * kSortTile;
+    const int64_t tbase = (int64_t)tile * kTile;
     const int64_t wbase = tbase + (int64_t)wave * kPerWave + __lane_id();
     uint32_t kk[kRounds], vv[kRounds], loc[kRounds];
 #pragma unroll
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
         }
     }
     __syncthreads();
-    const int nt = (int)min<int64_t>(kSortTile, n - tbase);
+    const int nt = (int)min<int64_t>(kTile, n - tbase);
     for (int q = tid; q < nt; q += kSortBlock) {
         const uint32_t k = sk[q];
         const uint32_t d = (k >> shift) & 255u;
@@ -585,6 +589,18 @@ static int64_t onesweep_min_tiles()
     return kRowScanTiles + 1;
 }
 
+// Elements per thread of a one-sweep tile: 32 (8192-element tiles: 0.13 ms
+// less per pass than 4096 over 200M elements, whose digit runs are half as
+// long); C3X_ONESWEEP_ITEMS=16 or 24 overrides it (for timing).
+static int onesweep_items()
+{
+    if (const char *e = getenv("C3X_ONESWEEP_ITEMS")) {
+        const int v = atoi(e);
+        if (v == 16 || v == 24 || v == 32) return v;
+    }
+    return 32;
+}
+
 static uint32_t spin_limit()
 {
     if (const char *e = getenv("C3X_DEBUG_SORT_SPIN")) return (uint32_t)std::max(0LL, atoll(e));
@@ -612,6 +628,9 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
     // observe a give-up)
     if (fail && nb >= onesweep_min_tiles() && n < kOneSweepMax) {
         const uint32_t spins = spin_limit();
+        const int items = onesweep_items();
+        const int64_t tile = (int64_t)kSortBlock * items;
+        nb = (n + tile - 1) / tile;  // <= the 4096-element count the workspace is sized for
         const int npass = (nbits - lo_bit + 7) / 8;  // at most 4
         uint32_t *ghist = (uint32_t *)ws;
         uint32_t *tctr = ghist + 4 * 256;
@@ -634,10 +653,14 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
                 hipLaunchKernelGGL(k_sort_clear, dim3(fb), dim3(256), 0, s, kb, n, 0xffffffffu);
                 hipLaunchKernelGGL(k_sort_clear, dim3(fb), dim3(256), 0, s, vb, n, 0xffffffffu);
             }
-            hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka,
-                               p == 0 ? vfirst : va, kb, vb, n, lo_bit + 8 * p, ghist + 256 * p,
-                               tctr + p,
-                               status + (size_t)p * 256 * (size_t)nb, (int)nb, spins, fail);
+#define C3X_ONESWEEP(IT)                                                                          \
+    hipLaunchKernelGGL(k_onesweep<IT>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ka,             \
+                       p == 0 ? vfirst : va, kb, vb, n, lo_bit + 8 * p, ghist + 256 * p, tctr + p, \
+                       status + (size_t)p * 256 * (size_t)nb, (int)nb, spins, fail)
+            if (items == 32) C3X_ONESWEEP(32);
+            else if (items == 24) C3X_ONESWEEP(24);
+            else C3X_ONESWEEP(16);
+#undef C3X_ONESWEEP
             std::swap(ka, kb);
             std::swap(va, vb);
             *in_tmp ^= 1;

@@ -103,10 +103,16 @@ def check_batch(res, offs, jobs, oracles):
     assert offs[-1] == len(ia)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_matches_oracle_per_job(c3x, dev, batch_data, batch_oracle, precision):
+@pytest.mark.parametrize("precision,queue", [(0, None), (1, None), (0, "1"), (1, "1")])
+def test_batch_matches_oracle_per_job(c3x, dev, batch_data, batch_oracle, precision, queue,
+                                      monkeypatch):
+    """Every job against the oracle, both precisions; queue "1" forces the
+    persistent count kernel (tiles costliest first), None lets the
+    autotuner choose."""
+    if queue is not None:
+        monkeypatch.setenv("C3X_BATCH_QUEUE", queue)
     raA, decA, raB, decB, jobs = batch_data
-    print(f"[gpu] batch jobs={len(jobs)} precision={precision}", flush=True)
+    print(f"[gpu] batch jobs={len(jobs)} precision={precision} queue={queue}", flush=True)
     b = c3x.Batch(jobs, _t(raA, dev), _t(decA, dev), _t(raB, dev), _t(decB, dev),
                   precision=precision)
     r0 = b.result()
@@ -122,6 +128,8 @@ def test_batch_matches_oracle_per_job(c3x, dev, batch_data, batch_oracle, precis
         assert np.array_equal(r1.best_idx.cpu().numpy(), r0.best_idx.cpu().numpy())
     st = b.stats()
     assert st["n_pairs"] == offs[-1] and st["n_tests"] > 0
+    if queue is not None:
+        assert st["queue"] == int(queue)
     b.free()
 
 
@@ -194,7 +202,8 @@ def _result_bytes(b):
 
 
 @pytest.mark.parametrize("name,value", [("C3X_BATCH_TILE", "64"), ("C3X_BATCH_TILE", "128"),
-                                        ("C3X_BATCH_TILE", "256"),
+                                        ("C3X_BATCH_TILE", "256"), ("C3X_BATCH_QUEUE", "0"),
+                                        ("C3X_BATCH_QUEUE", "1"),
                                         ("C3X_BATCH_CELL_SCALES", "0.5,4,1,2"),
                                         ("C3X_BATCH_CELL_SCALES", "4,0.5,2,0.5")])
 def test_batch_autotuner_choices_give_identical_bytes(c3x, dev, name, value, monkeypatch):
@@ -224,6 +233,8 @@ def test_batch_autotuner_choices_give_identical_bytes(c3x, dev, name, value, mon
     assert _result_bytes(b) == want
     if name == "C3X_BATCH_TILE":
         assert b.stats()["tile"] == int(value)
+    if name == "C3X_BATCH_QUEUE":
+        assert b.stats()["queue"] == int(value)
     b.run()
     assert _result_bytes(b) == want
     b.free()

@@ -78,6 +78,17 @@ def test_one_sweep_schedule_small(c3x, dev, cfg2_small, cfg2_small_oracle, preci
     assert ist["n_sort_retries"] == 0 and g["stats"]["n_sort_retries"] == 0
 
 
+@pytest.mark.parametrize("items", ["16", "24"])
+def test_one_sweep_other_tiles(c3x, dev, cfg2_small, cfg2_small_oracle, items, monkeypatch):
+    """One-sweep passes over tiles of 256 x 16 and 256 x 24 elements (the
+    default is 256 x 32)."""
+    monkeypatch.setenv("C3X_DEBUG_ONESWEEP_TILES", "1")
+    monkeypatch.setenv("C3X_ONESWEEP_ITEMS", items)
+    g, ist = _match_with_stats(c3x, dev, cfg2_small, 1)
+    assert_parity(g, cfg2_small_oracle)
+    assert ist["n_sort_retries"] == 0 and g["stats"]["n_sort_retries"] == 0
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_one_sweep_give_up_is_redone(c3x, dev, cfg2_small, cfg2_small_oracle, precision,
                                      monkeypatch):
