@@ -682,12 +682,15 @@ static hipError_t batch_front(c3x_batch *b)
         const uint32_t *order = qin ? b->qv2 : b->qv;
         hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, b->qctr, (int64_t)1, 0u);
         const unsigned pg = std::max(1u, std::min(grid, b->queue_blocks));
+        // about eight takes per workgroup: few atomics on the one counter,
+        // and the last chunks still short
+        const uint32_t chunk = std::max(1u, grid / (8u * pg));
         if (b->prec == C3X_FP64)
             hipLaunchKernelGGL(k_match_queue<C3X_FP64>, dim3(pg), dim3(b->tile), 0, s, m, order,
-                               grid, b->qctr);
+                               grid, chunk, b->qctr);
         else
             hipLaunchKernelGGL(k_match_queue<C3X_MIXED>, dim3(pg), dim3(b->tile), 0, s, m, order,
-                               grid, b->qctr);
+                               grid, chunk, b->qctr);
     } else if (grid) {
         hipLaunchKernelGGL(k_bfill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->cnts, NA, 0u);
         if (b->prec == C3X_FP64)

@@ -152,6 +152,7 @@ struct c3x_index {
     uint32_t *keys = nullptr;
     c3x::Pay64 *pay64 = nullptr;
     c3x::Pay32 *pay32 = nullptr;
+    uint2 *res = nullptr;           // FP64 residuals of pay32 (mixed)
     double2 *radec = nullptr;  // B coordinates in input order (row pay64[j].idx)
     c3x_stats stats;
 };

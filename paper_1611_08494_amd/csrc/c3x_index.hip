@@ -8,7 +8,7 @@
 // needs in one zone are one contiguous key range. Phases (one stream):
 //   k_prep_b    validate rows, key + row index          16 B in, 8 B out
 //   radix sort  (key, row) by key, ceil(bits/8) passes   16 B per pass
-//   k_gather_b  payload in sorted order                   20 B in, 32/16 B out
+//   k_gather_b  payload in sorted order                   20 B in, 32 or 16 + 8 B out
 //   k_dir_fill  dir[q] = number of keys in buckets below q, written straight
 //               from the sorted keys: each position fills the buckets between
 //               its predecessor's and its own (long gaps by k_dir_fill_gaps)
@@ -189,7 +189,8 @@ __global__ void k_prep_b(const double *__restrict__ ra, const double *__restrict
 
 template <int PREC>
 __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__restrict__ packed,
-                           int64_t n, Grid g, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32)
+                           int64_t n, Grid g, Pay64 *__restrict__ p64, Pay32 *__restrict__ p32,
+                           uint2 *__restrict__ res)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -213,12 +214,14 @@ __global__ void k_gather_b(const uint32_t *__restrict__ rows, const double2 *__r
         double rx, ry, rz;
         const uint32_t st = ref_step(g.zinfo[zz], c);
         ref_vec(g.zref[zz], st, rx, ry, rz);
+        const double ox = x - rx, oy = y - ry, oz = z - rz;
         Pay32 q;
-        q.x = (float)(x - rx);
-        q.y = (float)(y - ry);
-        q.z = (float)(z - rz);
+        q.x = (float)ox;
+        q.y = (float)oy;
+        q.z = (float)oz;
         q.idx = row | ((st & 1u) << 31);  // the step's parity: a window spans at most two
         p32[s] = q;
+        res[s] = res_pack(ox, oy, oz, q.x, q.y, q.z);
     }
 }
 
@@ -299,21 +302,26 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     void *ws = tmp.get(radix_ws_bytes(n));
     uint32_t *bad = tmp.get_n<uint32_t>(2);  // first bad row; sort give-up
     // the coordinates in input order: the gathers' source, then kept by the
-    // index (the band recheck and the separations of the mixed path read
-    // them through the payload's row)
+    // index (the band recheck reads them through the payload's row)
     double2 *packed = ix->mem.get_n<double2>(n);
     Pay64 *p64 = nullptr;
     Pay32 *p32 = nullptr;
+    uint2 *res = nullptr;
     // one payload per index: FP64 unit vectors, or FP32 offsets from the
-    // cell references (the mixed filter)
-    if (o.precision == C3X_FP64) p64 = ix->mem.get_n<Pay64>(n);
-    else p32 = ix->mem.get_n<Pay32>(n);
+    // cell references (the mixed filter) with their FP64 residuals (the
+    // chords of its matches)
+    if (o.precision == C3X_FP64) {
+        p64 = ix->mem.get_n<Pay64>(n);
+    } else {
+        p32 = ix->mem.get_n<Pay32>(n);
+        res = ix->mem.get_n<uint2>(n);
+    }
     uint32_t *dir = ix->mem.get_n<uint32_t>(ix->plan.dsize);
     const uint32_t gap_cap = dir_gap_cap(ix->plan.dsize), big_cap = dir_big_cap(ix->plan.dsize);
     uint3 *gaps = tmp.get_n<uint3>((int64_t)gap_cap + big_cap);
     uint32_t *n_gaps = tmp.get_n<uint32_t>(2);
     if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !dir || !gaps || !n_gaps ||
-        (!p64 && !p32)) {
+        (!p64 && !(p32 && res))) {
         (void)hipStreamSynchronize(s);
         delete ix;
         return fail(C3X_ENOMEM, "index buffers");
@@ -337,10 +345,10 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     if (e == hipSuccess && n > 0) {
         if (o.precision == C3X_FP64)
             hipLaunchKernelGGL(k_gather_b<C3X_FP64>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
-                               packed, n, g, p64, p32);
+                               packed, n, g, p64, p32, res);
         else
             hipLaunchKernelGGL(k_gather_b<C3X_MIXED>, dim3(nblk(n, 256)), dim3(256), 0, s, rows,
-                               packed, n, g, p64, p32);
+                               packed, n, g, p64, p32, res);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemsetAsync(n_gaps, 0, 2 * sizeof(uint32_t), s);
@@ -380,6 +388,7 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     ix->keys = keys;
     ix->pay64 = p64;
     ix->pay32 = p32;
+    ix->res = res;
     ix->radec = packed;
     ix->grid.keys = keys;
     ix->grid.dir = dir;

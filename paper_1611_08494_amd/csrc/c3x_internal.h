@@ -67,6 +67,43 @@ struct alignas(16) Pay32 {
 __device__ __forceinline__ uint32_t pay_row(const Pay32 &b) { return b.idx & 0x7fffffffu; }
 __device__ __forceinline__ uint32_t pay_row(const Pay64 &b) { return b.idx; }
 
+// FP64 residual of an FP32 payload (8 bytes per sorted row, read only for
+// filter matches): for each FP64 offset o whose FP32 value is f = fl32(o),
+// the remainder o - f (exact in FP64, at most half an FP32 ulp of o) as a
+// 21-bit signed multiple of 2^(s - 43), s the binary exponent of f (at
+// least -100), the three packed into one 64-bit word. f plus its residual
+// restores o to within 2^(s - 44) <= 2^-44 |o|: the FP64 chord of a match
+// without an FP64 payload.
+__device__ __forceinline__ int res_exp(float f)
+{
+    const int s = (int)((__float_as_uint(f) >> 23) & 0xffu) - 127;  // zero, subnormal: -127
+    return s < -100 ? -100 : s;
+}
+__device__ __forceinline__ double pow2(int k)  // 2^k, -1022 <= k <= 1023
+{
+    return __longlong_as_double((long long)(k + 1023) << 52);
+}
+__device__ __forceinline__ unsigned long long res_part(double o, float f)
+{
+    const double q = rint((o - (double)f) * pow2(43 - res_exp(f)));
+    const int v = (int)fmin(fmax(q, -1048576.0), 1048575.0);
+    return (unsigned long long)((uint32_t)v & 0x1fffffu);
+}
+__device__ __forceinline__ uint2 res_pack(double ox, double oy, double oz, float fx, float fy,
+                                          float fz)
+{
+    const unsigned long long w = res_part(ox, fx) | (res_part(oy, fy) << 21) |
+                                 (res_part(oz, fz) << 42);
+    return make_uint2((uint32_t)w, (uint32_t)(w >> 32));
+}
+// Offset k (0: x, 1: y, 2: z) of payload f with residual word w.
+__device__ __forceinline__ double res_off(float f, uint2 w, int k)
+{
+    const unsigned long long u = ((unsigned long long)w.y << 32) | w.x;
+    const int v = ((int)((uint32_t)(u >> (21 * k)) << 11)) >> 11;  // sign-extended 21 bits
+    return (double)f + (double)v * pow2(res_exp(f) - 43);
+}
+
 // One A source as a match lane sees it: position, unit vector (z = sin Dec),
 // cos Dec with small relative error near the poles, reach of its area.
 // Rebuilt from (ra, dec) inside each kernel, so every pass gets the same bits.
@@ -185,6 +222,7 @@ struct MatchArgs {
     Grid g;
     const Pay64 *pay64;
     const Pay32 *pay32;
+    const uint2 *res;      // FP64 residuals of pay32 (mixed)
     const double2 *coordB;
     const double2 *arad;   // sorted A coordinates
     const uint32_t *aidx;  // sorted A rows
@@ -248,8 +286,9 @@ struct MatchArgs {
 };
 
 // B row of sorted position j: from the FP64 payload when the index has one,
-// else from the FP32 payload (the mixed index keeps no FP64 payload; its
-// matches take FP64 geometry from the coordinates, coordB[row]).
+// else from the FP32 payload (the mixed index keeps no FP64 payload: its
+// matches take FP64 chords from the payload's residual, and the rechecks
+// FP64 geometry from the coordinates, coordB[row]).
 struct BRows {
     const Pay64 *p64;
     const Pay32 *p32;

@@ -45,6 +45,18 @@ constexpr int kMatchBlock = 256;
 constexpr uint32_t kWideMin = 32;  // candidates from which a row gets a wavefront of its own
 constexpr int64_t kFewRows = 1 << 21;  // fewer A rows: one lane each leaves the device idle
 constexpr int kAKeyBits = 24;          // key bits that order catalogue A
+
+// Key bits that order catalogue A in single calls: kAKeyBits, or
+// C3X_A_KEY_BITS (8 to 32, for timing: fewer bits, fewer radix passes,
+// longer unordered runs).
+static int a_key_bits()
+{
+    if (const char *e = getenv("C3X_A_KEY_BITS")) {
+        const int v = atoi(e);
+        if (v >= 8 && v <= 32) return v;
+    }
+    return kAKeyBits;
+}
 constexpr uint32_t kNoKey = 0xffffffffu;  // no cell key: the lane's FP32 offsets are set
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
@@ -368,15 +380,30 @@ __device__ __forceinline__ bool cand_ranges(const MatchArgs &m, uint32_t i, cons
     }
 }
 
+// Residual word of sorted B position j where decide uses it (single calls
+// of the mixed path), else zero.
+template <int PREC, bool BATCH>
+__device__ __forceinline__ uint2 res_word(const MatchArgs &m, uint32_t j)
+{
+    if constexpr (PREC != C3X_FP64 && !BATCH) return m.res[j];
+    else return make_uint2(0u, 0u);
+}
+
 // Fast certified filter of one candidate: IN, OUT, or AMBIG when the pair
 // lies inside the filter's error band (then the FP64 relative-accuracy
-// recheck decides it, in k_recheck). Also returns the filter's squared chord.
-// Radius 0 is decided structurally here (same point), without a band.
+// recheck decides it, in k_recheck). Also returns a squared chord: for a
+// match of a single call its FP64 chord (the mixed filter's from the FP32
+// payload and its residual, see chord_err), which ranks it and codes its
+// separation; otherwise the filter's. Radius 0 is decided structurally here
+// (same point), without a band. rw: the candidate's residual word (single
+// calls of the mixed path; loaded with its payload, so that a match's chord
+// waits on no further load).
 template <int SHAPE, int PREC, bool BATCH>
 __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const AEll &e,
                                       const AEllR &er, const LaneF32 &f, CellCache &cc,
                                       const Thr &th, int z, const ZoneInfo &zi, double2 zr,
-                                      uint32_t key, const PayOf<PREC> &b, uint32_t j, double &c2o)
+                                      uint32_t key, const PayOf<PREC> &b, uint32_t j, uint2 rw,
+                                      double &c2o)
 {
     int d;
     if constexpr (PREC == C3X_FP64) {
@@ -418,6 +445,17 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
         float dx = b.x - cc.ax, dy = b.y - cc.ay, dz = b.z - cc.az;
         float c2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         c2o = (double)c2;
+        // single calls: the FP64 chord of a match, from the B offset restored
+        // from the payload and its residual and A's FP64 offset from the same
+        // reference
+        auto chord64 = [&]() {
+            double rx, ry, rz;
+            ref_vec(zr, cc.ref & ((1u << kRefBits) - 1u), rx, ry, rz);
+            const double ex = res_off(b.x, rw, 0) - (a.x - rx);
+            const double ey = res_off(b.y, rw, 1) - (a.y - ry);
+            const double ez = res_off(b.z, rw, 2) - (a.z - rz);
+            return fma(ex, ex, fma(ey, ey, ez * ez));
+        };
         if constexpr (SHAPE == C3X_CIRCLE) {
             d = c2 <= th.t32_in ? IN : (c2 > th.t32_out ? OUT : AMBIG);
         } else {
@@ -437,9 +475,17 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
                                       : ((qu <= 1.0f - mm && qv <= 1.0f - mm) ? IN : AMBIG));
             }
         }
+        if constexpr (!BATCH) {
+            if (d == IN) c2o = chord64();
+        }
     }
     if constexpr (SHAPE == C3X_CIRCLE) {
-        if (th.r_zero) d = same_point(a, m.coordB[pay_row(b)]) ? IN : OUT;
+        if (th.r_zero) {
+            d = same_point(a, m.coordB[pay_row(b)]) ? IN : OUT;
+            if constexpr (!BATCH) {
+                if (d == IN) c2o = 0.0;  // the same point: no angle
+            }
+        }
     }
     return d;
 }
@@ -492,14 +538,26 @@ __device__ __forceinline__ double c2_err(double c, double L)
     }
 }
 
+// Error bound of a single call's FP64 match chord at chord c (the ranking
+// of its best matches): the FP64 unit vectors carry <= 32 u per component;
+// L > 0: the B point restored from an FP32 offset of size <= L and its
+// residual (within 2^-44 L, plus roundings of size u L), so 2^-43 L more
+// per component; L = 0: the FP64 payload.
+__device__ __forceinline__ double chord_err(double c, double L)
+{
+    const double s3 = 1.7320508075688772;
+    const double eta = s3 * (64.0 * kU + kU * c + 0x1p-43 * L);
+    return 2.0 * c * eta + eta * eta + 3.0 * kU * (c + eta) * (c + eta);
+}
+
 // ---------------------------------------------------------------------------- count / write
 
 // A match's separation as the match passes leave it, without trigonometry:
 // from the FP64 chord c < 1.38 the code -c^2 (the separation is 2 asin(c / 2),
 // error ~1e-14 rad), 0 for c = 0, otherwise a quiet NaN: the separation is
 // then computed from the coordinates of A and of the match's B row (the
-// mixed path codes every match so: it has no FP64 payload to take a chord
-// from). Non-negative values are separations in arcsec.
+// batch's mixed path codes every match so: it has no FP64 chord of its
+// matches). Non-negative values are separations in arcsec.
 __device__ __forceinline__ double sep_code(double c2)
 {
     if (c2 < 1.9) return c2 > 0.0 ? -c2 : 0.0;
@@ -588,14 +646,14 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
     CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
     if (BATCH && active) batch_ref(m, i, a, cc);
 
-    // A filter match as written: the separation coded from the FP64 path's
-    // filter chord; the mixed path leaves it to the coordinates (the final
-    // pass computes it from both rows' positions).
+    // A filter match as written: the separation coded from its FP64 chord;
+    // the batch's mixed path leaves it to the coordinates (a pass after the
+    // canonical order computes it from both rows' positions).
     auto coded = [&](const PayT &b, uint32_t j, double c2) -> PairTmp {
         PairTmp t;
         t.idxB = pay_row(b);
         t.j = j;
-        if constexpr (PREC == C3X_FP64) t.sep = sep_code(c2);
+        if constexpr (PREC == C3X_FP64 || !BATCH) t.sep = sep_code(c2);
         else t.sep = sep_code_coords();
         return t;
     };
@@ -628,10 +686,10 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
     // One candidate: decide it, then count / rank it (MODE 0), write it
     // (MODE 1), or both (MODE 2). Band candidates are only listed.
     auto visit = [&](int z, const ZoneInfo &zi, double2 zr, uint32_t key, const PayT &b,
-                     uint32_t j) {
+                     uint32_t j, uint2 rw) {
         ++tests;
         double c2;
-        int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j, c2);
+        int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j, rw, c2);
         if (d == AMBIG) {
             if (MODE != 1) {
                 ++band;
@@ -676,7 +734,7 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
         if (rg.zlo >= 0) {
             // the ranges found when A was prepared; candidates are loaded
             // kBatch at a time so that their loads overlap
-            constexpr int kBatch = 4;
+            constexpr int kBatch = (PREC != C3X_FP64 && !BATCH) ? 2 : 4;
 #pragma unroll 1
             for (int q = 0; q < kRZ; ++q) {
                 const uint32_t j0 = q == 0 ? rg.j0[0] : (q == 1 ? rg.j0[1] : rg.j0[2]);
@@ -693,7 +751,7 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
                 // each candidate's parity bit picks one -- no cell keys
                 const bool par = PREC != C3X_FP64 && !BATCH && !(rg.wide & 2u);
                 float oax = 0.f, oay = 0.f, oaz = 0.f, oox = 0.f, ooy = 0.f, ooz = 0.f;
-                uint32_t pa = 0;
+                uint32_t pa = 0, rfa = 0, rfo = 0;
                 if (par) {
                     const uint32_t sa = ref_step(zi, cell_in(zi, a.ra));
                     const uint32_t bits = (rg.wide >> (2 * q + 2)) & 3u;
@@ -713,15 +771,19 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
                         ooz = (float)(a.z - rz);
                     }
                     pa = sa & 1u;
+                    rfa = ((uint32_t)z << kRefBits) | sa;
+                    rfo = ((uint32_t)z << kRefBits) | (so & ((1u << kRefBits) - 1u));
                     cc.key = kNoKey;
                 }
                 for (uint32_t t = 0; t < nq; t += kBatch) {
                     PayT bb[kBatch];
                     uint32_t kk[kBatch];
+                    uint2 rr[kBatch];
 #pragma unroll
                     for (int u = 0; u < kBatch; ++u) {
                         const uint32_t jj = j0 + min(t + u, nq - 1);
                         bb[u] = pay[jj];
+                        rr[u] = res_word<PREC, BATCH>(m, jj);
                         kk[u] = (PREC == C3X_FP64 || BATCH || par) ? kNoKey : m.g.keys[jj];
                     }
 #pragma unroll
@@ -732,8 +794,9 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
                                 cc.ax = other ? oox : oax;
                                 cc.ay = other ? ooy : oay;
                                 cc.az = other ? ooz : oaz;
+                                cc.ref = other ? rfo : rfa;
                             }
-                            visit(z, zi, zr, kk[u], bb[u], j0 + t + u);
+                            visit(z, zi, zr, kk[u], bb[u], j0 + t + u, rr[u]);
                         }
                 }
             }
@@ -747,7 +810,7 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
                 cc.key = cc.ref = 0xffffffffu;
                 for (uint32_t j = j0; j < j1; ++j) {
                     const PayT b = pay[j];
-                    visit(z, zi, zr, m.g.keys[j], b, j);
+                    visit(z, zi, zr, m.g.keys[j], b, j, res_word<PREC, BATCH>(m, j));
                 }
             });
         }
@@ -763,7 +826,9 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
         r.c[0] = tc0;
         m.rec[a.idx] = r;
         if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
-        if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), Lr)) {
+        const double terr = PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
+                            : (BATCH ? c2_err<C3X_MIXED>(sqrt(b2), Lr) : chord_err(sqrt(b2), Lr));
+        if (cnt >= 2 && b2 - b1 <= 4.0 * terr) {
             uint32_t slot = atomicAdd(m.tie_n, 1u);
             if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
         }
@@ -803,28 +868,32 @@ __global__ __launch_bounds__(kMatchBlock) void k_match(MatchArgs m)
     add_counters<MODE>(m, tests, band, placed);
 }
 
-// The batch's count pass as a persistent kernel: each workgroup takes tiles
-// (blockDim.x consecutive sorted A rows) from a counter, in the order
-// `order` lists them (the costliest first), until none is left; every
-// workgroup reads the same number of items past the end, so each reaches
-// the exit.
+// The batch's count pass as a persistent kernel: each workgroup takes
+// `chunk` consecutive entries of `order` at a time from a counter (one
+// atomic per chunk, not per tile: a single counter serialises its atomics),
+// each entry a tile of blockDim.x consecutive sorted A rows, the costliest
+// first, until none is left; the take is workgroup-uniform, so every lane
+// of a workgroup leaves the loop together.
 template <int PREC>
 __global__ __launch_bounds__(kMatchBlock) void k_match_queue(MatchArgs m,
                                                              const uint32_t *__restrict__ order,
-                                                             uint32_t n_items,
+                                                             uint32_t n_items, uint32_t chunk,
                                                              uint32_t *__restrict__ qctr)
 {
     __shared__ uint32_t s_item;
     unsigned long long tests = 0, band = 0, placed = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(qctr, 1u);
+        if (threadIdx.x == 0) s_item = atomicAdd(qctr, chunk);
         __syncthreads();
-        const uint32_t it = s_item;
+        const uint32_t it0 = s_item;
         __syncthreads();  // every lane has read it before the next take
-        if (it >= n_items) break;
-        const uint32_t tile = min(order[it], n_items - 1u);
-        match_row<C3X_CIRCLE, PREC, 2, true>(m, tile * blockDim.x + threadIdx.x, tests, band,
-                                             placed);
+        if (it0 >= n_items) break;
+        const uint32_t it1 = min(it0 + chunk, n_items);
+        for (uint32_t it = it0; it < it1; ++it) {
+            const uint32_t tile = min(order[it], n_items - 1u);
+            match_row<C3X_CIRCLE, PREC, 2, true>(m, tile * blockDim.x + threadIdx.x, tests, band,
+                                                 placed);
+        }
     }
     add_counters<2>(m, tests, band, placed);
 }
@@ -936,7 +1005,8 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                     b = pay[j];
                     const uint32_t key = PREC == C3X_FP64 ? 0u : m.g.keys[j];
                     ++tests;
-                    d = decide<SHAPE, PREC, false>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j, c2);
+                    d = decide<SHAPE, PREC, false>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j,
+                                                   res_word<PREC, false>(m, j), c2);
                 }
                 const unsigned long long am = __ballot(d == AMBIG);
                 if (am) {
@@ -968,8 +1038,7 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                     if (d == IN) {
                         pt.idxB = pay_row(b);
                         pt.j = j;
-                        if constexpr (PREC == C3X_FP64) pt.sep = sep_code(c2);
-                        else pt.sep = sep_code_coords();
+                        pt.sep = sep_code(c2);
                     }
                     if (cnt == 0) {  // the record's slot: the group's first lane
                         const int l = __builtin_ffsll((long long)im) - 1;
@@ -1037,7 +1106,9 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
             r.c[0] = tc0;
             m.rec[a.idx] = r;
             if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
-            if (cnt >= 2 && b2 - b1 <= 4.0 * c2_err<PREC>(sqrt(b2), Lr)) {
+            if (cnt >= 2 &&
+                b2 - b1 <= 4.0 * (PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
+                                                   : chord_err(sqrt(b2), Lr))) {
                 const uint32_t slot = atomicAdd(m.tie_n, 1u);
                 if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
             }
@@ -1090,7 +1161,8 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
-            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j, c2);
+            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j,
+                                               res_word<PREC, BATCH>(m, j), c2);
             if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
@@ -1170,7 +1242,8 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
             const PayT b = pay[j];
             double c2;
-            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j, c2);
+            int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j,
+                                               res_word<PREC, BATCH>(m, j), c2);
             if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             // the FP64 unit vector: the FP64 payload's, or made the same way
@@ -2052,7 +2125,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     // A is ordered by its top 24 key bits only (three passes): runs of up to
     // 2^(bits - 24) cells along a zone keep a wavefront's sources together,
     // and no result depends on the order of A
-    const int a_lo = std::max(0, ix->plan.key_bits - kAKeyBits);
+    const int a_lo = std::max(0, ix->plan.key_bits - a_key_bits());
     // ctr[11]: set when a one-sweep sort gave up (read back after the count)
     HIPCHK(radix_sort_pairs_bits(keys, rows, ktmp, rtmp, nA, a_lo, ix->plan.key_bits, ws, s,
                                  &in_tmp, /*vals_are_index=*/true, onesweep ? ctr + 11 : nullptr),
@@ -2085,6 +2158,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.g = ix->grid;
     m.pay64 = ix->pay64;
     m.pay32 = ix->pay32;
+    m.res = ix->res;
     m.coordB = ix->radec;
     m.arad = arad;
     m.aidx = aidx;
@@ -2497,7 +2571,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         fa.off = off;
         fa.rec = rec;
         fa.use_rec = emitted ? 1 : 0;
-        fa.defer = prec == C3X_MIXED ? 1 : 0;
+        fa.defer = 0;  // every match's separation is coded from its FP64 chord
         fa.tmp = pt;
         fa.coordA = packed;  // A coordinates in input order (the key pass's copy)
         fa.coordB = ix->radec;
