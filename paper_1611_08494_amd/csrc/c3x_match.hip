@@ -395,15 +395,16 @@ __device__ __forceinline__ uint2 res_word(const MatchArgs &m, uint32_t j)
 // match of a single call its FP64 chord (the mixed filter's from the FP32
 // payload and its residual, see chord_err), which ranks it and codes its
 // separation; otherwise the filter's. Radius 0 is decided structurally here
-// (same point), without a band. rw: the candidate's residual word (single
-// calls of the mixed path; loaded with its payload, so that a match's chord
-// waits on no further load).
+// (same point), without a band. rw (have_rw): the candidate's residual word
+// where the caller loaded it with the payload (the one-lane count pass: a
+// match's chord then waits on no further load); otherwise it is loaded for
+// matches only.
 template <int SHAPE, int PREC, bool BATCH>
 __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const AEll &e,
                                       const AEllR &er, const LaneF32 &f, CellCache &cc,
                                       const Thr &th, int z, const ZoneInfo &zi, double2 zr,
                                       uint32_t key, const PayOf<PREC> &b, uint32_t j, uint2 rw,
-                                      double &c2o)
+                                      bool have_rw, double &c2o)
 {
     int d;
     if constexpr (PREC == C3X_FP64) {
@@ -451,9 +452,10 @@ __device__ __forceinline__ int decide(const MatchArgs &m, const ARec &a, const A
         auto chord64 = [&]() {
             double rx, ry, rz;
             ref_vec(zr, cc.ref & ((1u << kRefBits) - 1u), rx, ry, rz);
-            const double ex = res_off(b.x, rw, 0) - (a.x - rx);
-            const double ey = res_off(b.y, rw, 1) - (a.y - ry);
-            const double ez = res_off(b.z, rw, 2) - (a.z - rz);
+            const uint2 w = have_rw ? rw : m.res[j];
+            const double ex = res_off(b.x, w, 0) - (a.x - rx);
+            const double ey = res_off(b.y, w, 1) - (a.y - ry);
+            const double ez = res_off(b.z, w, 2) - (a.z - rz);
             return fma(ex, ex, fma(ey, ey, ez * ez));
         };
         if constexpr (SHAPE == C3X_CIRCLE) {
@@ -686,10 +688,11 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
     // One candidate: decide it, then count / rank it (MODE 0), write it
     // (MODE 1), or both (MODE 2). Band candidates are only listed.
     auto visit = [&](int z, const ZoneInfo &zi, double2 zr, uint32_t key, const PayT &b,
-                     uint32_t j, uint2 rw) {
+                     uint32_t j, uint2 rw, bool have_rw) {
         ++tests;
         double c2;
-        int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j, rw, c2);
+        int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j, rw,
+                                           have_rw, c2);
         if (d == AMBIG) {
             if (MODE != 1) {
                 ++band;
@@ -796,7 +799,7 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
                                 cc.az = other ? ooz : oaz;
                                 cc.ref = other ? rfo : rfa;
                             }
-                            visit(z, zi, zr, kk[u], bb[u], j0 + t + u, rr[u]);
+                            visit(z, zi, zr, kk[u], bb[u], j0 + t + u, rr[u], true);
                         }
                 }
             }
@@ -810,7 +813,7 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
                 cc.key = cc.ref = 0xffffffffu;
                 for (uint32_t j = j0; j < j1; ++j) {
                     const PayT b = pay[j];
-                    visit(z, zi, zr, m.g.keys[j], b, j, res_word<PREC, BATCH>(m, j));
+                    visit(z, zi, zr, m.g.keys[j], b, j, make_uint2(0u, 0u), false);
                 }
             });
         }
@@ -1006,7 +1009,7 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                     const uint32_t key = PREC == C3X_FP64 ? 0u : m.g.keys[j];
                     ++tests;
                     d = decide<SHAPE, PREC, false>(m, a, e, er, f, cc, th, z, zi, zr, key, b, j,
-                                                   res_word<PREC, false>(m, j), c2);
+                                                   make_uint2(0u, 0u), false, c2);
                 }
                 const unsigned long long am = __ballot(d == AMBIG);
                 if (am) {
@@ -1162,7 +1165,7 @@ __global__ __launch_bounds__(64) void k_collect(MatchArgs m)
             const PayT b = pay[j];
             double c2;
             int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j,
-                                               res_word<PREC, BATCH>(m, j), c2);
+                                               make_uint2(0u, 0u), false, c2);
             if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             uint32_t slot = atomicAdd(m.col_n, 1u);
@@ -1243,7 +1246,7 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
             const PayT b = pay[j];
             double c2;
             int d = decide<SHAPE, PREC, BATCH>(m, a, e, er, f, cc, th, z, zi, zr, m.g.keys[j], b, j,
-                                               res_word<PREC, BATCH>(m, j), c2);
+                                               make_uint2(0u, 0u), false, c2);
             if (d == AMBIG) d = band_verdict<SHAPE, BATCH>(m, i, j, a);
             if (d != IN) continue;
             // the FP64 unit vector: the FP64 payload's, or made the same way
