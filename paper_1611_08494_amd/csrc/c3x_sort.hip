@@ -448,16 +448,28 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const Ti *__restrict
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// One workgroup over the tiles' totals, kScanTile of them a round (each lane
+// a run of kScanItems consecutive ones).
 template <typename To>
 __global__ __launch_bounds__(kScanBlock) void k_scan_partials(To *part, int64_t np, To *total)
 {
     To carry = 0;
-    for (int64_t b = 0; b < np; b += kScanBlock) {
-        int64_t e = b + threadIdx.x;
-        To x = e < np ? part[e] : (To)0;
+    for (int64_t b = 0; b < np; b += kScanTile) {
+        const int64_t e0 = b + (int64_t)threadIdx.x * kScanItems;
+        To v[kScanItems];
+        To sum = 0;
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) {
+            v[r] = e0 + r < np ? part[e0 + r] : (To)0;
+            sum += v[r];
+        }
         To tot;
-        To ex = block_excl_scan<To>(x, tot);
-        if (e < np) part[e] = carry + ex;
+        To run = carry + block_excl_scan<To>(sum, tot);
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) {
+            if (e0 + r < np) part[e0 + r] = run;
+            run += v[r];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0 && total) *total = carry;
