@@ -253,6 +253,12 @@ struct MatchArgs {
     uint32_t *tie_n;       // near-tie best matches: (sorted A pos, row)
     uint2 *tie;
     uint32_t tie_cap;
+    // forced paths of single calls (zero otherwise): tie_widen is added to
+    // the factor 4 of the near-tie tests (a huge value lists every row with
+    // two or more matches and lets no FP64 ranking stand); force_host makes
+    // every band candidate take the host's binary128 verdict
+    double tie_widen;
+    int32_t force_host;
     // verdicts of the band candidates: sorted keys (i << 32 | j); in a batch
     // only the host-decided ones, their count in n_ver_dev
     const unsigned long long *ver_key;

@@ -57,6 +57,13 @@ static int a_key_bits()
     }
     return kAKeyBits;
 }
+
+// An environment switch: set and not "0".
+static bool env_on(const char *name)
+{
+    const char *e = getenv(name);
+    return e && *e && strcmp(e, "0") != 0;
+}
 constexpr uint32_t kNoKey = 0xffffffffu;  // no cell key: the lane's FP32 offsets are set
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
@@ -521,7 +528,7 @@ __device__ __forceinline__ int band_verdict(const MatchArgs &m, uint32_t i, uint
     if constexpr (SHAPE == C3X_ELLIPSE) d = recheck_ellipse(q, m.aellr[i], rb);
     else if constexpr (SHAPE == C3X_RECT) d = recheck_rect(q, m.aellr[i], rb);
     else d = recheck_circle(q, rb, BATCH ? m.jobs[m.ajob[i]].h_r : m.h_r);
-    if (d != AMBIG) return d;
+    if (d != AMBIG && !m.force_host) return d;
     return verdict(m, i, j);
 }
 
@@ -831,7 +838,7 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
         if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
         const double terr = PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
                             : (BATCH ? c2_err<C3X_MIXED>(sqrt(b2), Lr) : chord_err(sqrt(b2), Lr));
-        if (cnt >= 2 && b2 - b1 <= 4.0 * terr) {
+        if (cnt >= 2 && b2 - b1 <= (4.0 + m.tie_widen) * terr) {
             uint32_t slot = atomicAdd(m.tie_n, 1u);
             if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
         }
@@ -1110,8 +1117,8 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
             m.rec[a.idx] = r;
             if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
             if (cnt >= 2 &&
-                b2 - b1 <= 4.0 * (PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
-                                                   : chord_err(sqrt(b2), Lr))) {
+                b2 - b1 <= (4.0 + m.tie_widen) * (PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
+                                                                   : chord_err(sqrt(b2), Lr))) {
                 const uint32_t slot = atomicAdd(m.tie_n, 1u);
                 if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
             }
@@ -1283,7 +1290,7 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
     if (threadIdx.x == 0 && b1.idxB != 0xffffffffu) {
         const uint32_t row = a.idx;
         const bool sure = b2.idxB == 0xffffffffu ||
-                          b2.c2 - b1.c2 > 4.0 * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
+                          b2.c2 - b1.c2 > (4.0 + m.tie_widen) * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
         if (sure) {
             m.rec[row].best = (int32_t)b1.idxB;
             if (m.best_only) m.rec[row].b[0] = b1.j;
@@ -1314,6 +1321,7 @@ __global__ __launch_bounds__(64) void k_rerank(MatchArgs m, const uint32_t *__re
 // FP64 recheck of the band candidates the count pass listed (their number
 // is on the device): those it finds inside join the matches list `in`, those
 // it cannot decide go to `hl` for binary128 on the host; outside ones drop.
+// force_host (a forced path for tests): every one goes to `hl`.
 template <int SHAPE>
 __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__restrict__ n_band,
                           uint32_t cap, const double2 *__restrict__ arad,
@@ -1322,7 +1330,7 @@ __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__rest
                           const Pay32 *__restrict__ p32, double h_r, const double *__restrict__ sa,
                           const double *__restrict__ sb, const double *__restrict__ pa,
                           uint4 *__restrict__ in, uint32_t *__restrict__ n_in,
-                          AmbInfo *__restrict__ hl, uint32_t *__restrict__ n_hl)
+                          AmbInfo *__restrict__ hl, uint32_t *__restrict__ n_hl, int force_host)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= min(*n_band, cap)) return;
@@ -1343,6 +1351,7 @@ __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__rest
     if (SHAPE == C3X_CIRCLE) d = recheck_circle(a, rb, h_r);
     else if (SHAPE == C3X_RECT) d = recheck_rect(a, aellr[q.x], rb);
     else d = recheck_ellipse(a, aellr[q.x], rb);
+    if (force_host) d = AMBIG;
     if (d == OUT) return;
     if (d == IN) {
         in[atomicAdd(n_in, 1u)] = make_uint4(q.x, row, idxB, q.y);  // at most one per band entry
@@ -1361,6 +1370,20 @@ __global__ void k_recheck(const uint2 *__restrict__ band, const uint32_t *__rest
     r.idxA = row;
     r.idxB = idxB;
     hl[atomicAdd(n_hl, 1u)] = r;
+}
+
+// Forced band (a test path): ellipse and rectangle margins of 3 make the
+// filter decide nothing inside and nothing within twice the axes outside, so
+// every such candidate is listed for the FP64 recheck.
+// A margin was at most 1/4 where the filter may decide (an FP32 margin of 0
+// marks a row the FP32 filter leaves wholly to the recheck, and stays), so a
+// candidate it still finds outside lies truly outside.
+__global__ void k_force_band_margins(AEllR *__restrict__ er, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    er[t].m64 = fmax(er[t].m64, 3.0);
+    if (er[t].m32 != 0.0f) er[t].m32 = fmaxf(er[t].m32, 3.0f);
 }
 
 // Sorted A positions whose best match is re-ranked: the near-ties, then the
@@ -2152,6 +2175,14 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         else C3X_GATHER(C3X_RECT);
 #undef C3X_GATHER
     }
+    // forced paths (tests; the answer must not change): C3X_DEBUG_FORCE_BAND
+    // lists every candidate within twice the area for the FP64 recheck;
+    // C3X_DEBUG_FORCE_AMBIG sends every band candidate, and the best match of
+    // every row with two or more matches, to binary128 on the host
+    const bool force_band = env_on("C3X_DEBUG_FORCE_BAND");
+    const bool force_ambig = env_on("C3X_DEBUG_FORCE_AMBIG");
+    if (force_band && shape != C3X_CIRCLE && nA > 0)
+        hipLaunchKernelGGL(k_force_band_margins, dim3(nblk(nA, 256)), dim3(256), 0, s, aellr, nA);
     HIPCHK(hipGetLastError(), "A records");
     tm.mark();  // 1
 
@@ -2180,6 +2211,16 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         m.t32_in = t.t32_in;
         m.t32_out = t.t32_out;
         m.r_zero = area->radius_arcsec == 0.0;
+        if (force_band && !m.r_zero) {  // nothing inside, nothing within 2 r outside
+            m.t64_in = -1.0;
+            m.t32_in = -1.0f;
+            m.t64_out = std::max(m.t64_out, 4.0 * m.cr2);
+            m.t32_out = std::max(m.t32_out, (float)(4.0 * m.cr2));
+        }
+    }
+    if (force_ambig) {
+        m.force_host = 1;
+        m.tie_widen = 1e300;
     }
     m.n_tests = c64;
     m.n_band = c64 + 1;
@@ -2247,15 +2288,17 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             hipLaunchKernelGGL(k_recheck<C3X_CIRCLE>, dim3(nblk(amb_cap, 256)), dim3(256), 0, s,
                                m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
                                ix->pay32, m.h_r, nullptr, nullptr, nullptr, bin, ctr + 9, hl,
-                               ctr + 10);
+                               ctr + 10, m.force_host);
         else if (shape == C3X_ELLIPSE)
             hipLaunchKernelGGL(k_recheck<C3X_ELLIPSE>, dim3(nblk(amb_cap, 256)), dim3(256), 0, s,
                                m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
-                               ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10);
+                               ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10,
+                               m.force_host);
         else
             hipLaunchKernelGGL(k_recheck<C3X_RECT>, dim3(nblk(amb_cap, 256)), dim3(256), 0, s,
                                m.amb, ctr + 1, amb_cap, arad, aidx, aellr, ix->radec, ix->pay64,
-                               ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10);
+                               ix->pay32, m.h_r, sa, sb, pa, bin, ctr + 9, hl, ctr + 10,
+                               m.force_host);
     };
     std::vector<uint8_t> hvec;
     uint8_t *hb = pinned_stage(kCtrBytes + 64);

@@ -10,6 +10,10 @@ out, each against the CPU oracle:
   RA = 0/360 (paper Section 2.1, the area centred on the A source);
 * the batch's host binary128 decisions and best-match tie ranking, driven
   by near-boundary rows and mirror-image exact ties;
+* the forced decision paths (host settings; the answer must not change):
+  every candidate within twice the area listed for the FP64 recheck, and
+  every band candidate and every best match of a row with two or more
+  matches decided in binary128 on the host;
 * c3x_result_copy into host and device buffers;
 * allocation failure at every allocation of a call: C3X_ENOMEM, no
   result, nothing left allocated.
@@ -245,6 +249,52 @@ def test_batch_binary128_and_tie_paths(c3x, dev, precision):
 
 
 # ---------------------------------------------------------------------------- result copy
+
+# ---------------------------------------------------------------------------- forced decisions
+
+_FORCED = {}
+
+
+def _forced_case(shape):
+    """Circles: the 10k-source patch; ellipses and rectangles: a small draw
+    of the galactic-plane ellipse catalogue (the same axes taken as half
+    sides); each with the oracle's answer, computed once."""
+    if shape not in _FORCED:
+        if shape == 0:
+            cat = synth.cfg1_patch()
+        else:
+            cat = synth.cfg3_galactic_ellipses(scale=0.001)
+            cat.shape = shape
+        _FORCED[shape] = (cat, oracle_match(cat))
+    return _FORCED[shape]
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("knobs", ["C3X_DEBUG_FORCE_BAND", "C3X_DEBUG_FORCE_AMBIG",
+                                   "C3X_DEBUG_FORCE_BAND,C3X_DEBUG_FORCE_AMBIG"])
+def test_forced_decision_paths(c3x, dev, shape, knobs, monkeypatch):
+    """FORCE_BAND: the filter decides nothing inside, so every match comes
+    through the band list, the FP64 recheck and the re-ranking of rows with a
+    band match. FORCE_AMBIG: the recheck and the FP64 ranking let nothing
+    stand, so every band candidate and every best match among two or more
+    goes to binary128 on the host. Both precisions, the oracle's answer."""
+    cat, o = _forced_case(shape)
+    assert len(o.ia) > 1000
+    for k in knobs.split(","):
+        monkeypatch.setenv(k, "1")
+    multi = int((np.bincount(o.ia, minlength=len(cat.raA)) >= 2).sum())
+    assert multi > 0
+    for precision in (0, 1):
+        print(f"[gpu] forced {knobs} shape={shape} precision={precision}", flush=True)
+        g = gpu_match(c3x, dev, cat, precision)
+        assert_parity(g, o)
+        st = g["stats"]
+        if "BAND" in knobs:
+            assert st["n_band"] >= len(o.ia)
+        if "AMBIG" in knobs:  # (alone, the band may be empty: then only ties)
+            assert st["n_ambiguous"] == st["n_band"]
+            assert st["n_best_ties"] >= multi
+
 
 @pytest.mark.parametrize("where", ["cpu", "cuda"])
 def test_result_copy(c3x, dev, cfg2_small, cfg2_small_oracle, where):
