@@ -235,12 +235,15 @@ c3x_status c3x_result_views(const c3x_result *r, const int32_t **idxA, const int
  * The result is c3x_match's for the largest ellipse (mode must include
  * C3X_ALL; C3X_BEST adds the best matches within it), and each of its pairs
  * has a level: the smallest m whose ellipse holds the B source (the
- * ellipses are nested), read with c3x_result_levels. Every ellipse is a
- * certified c3x_match over the same index (one call per scale), so the
- * scaled axes must satisfy c3x_match's ellipse domain. The returned
- * result's stats are those of the largest ellipse's call. Errors: those of
- * c3x_match; C3X_EINVAL also for a circle, a mode without C3X_ALL, or bad
- * scales. */
+ * ellipses are nested), read with c3x_result_levels. The largest ellipse
+ * is one certified c3x_match over the index; each pair's level is then
+ * decided exactly as a certified match at every smaller scale would decide
+ * it (FP64 with a proven margin, else binary128 on the host), so every
+ * scale's axes must satisfy c3x_match's ellipse domain. The returned
+ * result's stats are those of the largest ellipse's call, with the level
+ * decisions taken on the host added to n_ambiguous. Errors: those of
+ * c3x_match (prefixed with the failing scale); C3X_EINVAL also for a
+ * circle, a mode without C3X_ALL, or bad scales. */
 c3x_status c3x_match_concentric(const c3x_index *ix, const double *ra_deg, const double *dec_deg,
                                 int64_t nA, c3x_frame frame, const c3x_area *area,
                                 const double *scales, int32_t n_scales, unsigned mode,

@@ -210,6 +210,37 @@ hipError_t frame_convert(int src, int dst, const double *ra, const double *dec, 
     return hipGetLastError();
 }
 
+c3x_status convert_catalogue_a(int src, int dst, int64_t n, const double **ra, const double **dec,
+                               c3x_area *area, Arena &conv, hipStream_t s)
+{
+    if (src == dst || n <= 0) return C3X_OK;
+    const bool oriented = area->shape != C3X_CIRCLE;
+    double *ra2 = conv.get_n<double>(n), *dec2 = conv.get_n<double>(n);
+    double *t2 = oriented ? conv.get_n<double>(n) : nullptr;
+    uint32_t *bad = conv.get_n<uint32_t>(1);
+    if (!ra2 || !dec2 || (oriented && !t2) || !bad) return fail(C3X_ENOMEM, "frame conversion");
+    uint32_t hbad = 0xffffffffu;
+    hipError_t e = hipMemsetAsync(bad, 0xff, sizeof(uint32_t), s);
+    if (e == hipSuccess)
+        e = frame_convert(src, dst, *ra, *dec, n, ra2, dec2, nullptr,
+                          oriented ? area->pa_deg : nullptr, area->pa_zero_deg, area->pa_sense, t2,
+                          bad, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "frame conversion");
+    if (hbad != 0xffffffffu)
+        return fail(C3X_EINVAL, "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= "
+                                "90 or not finite", hbad);
+    *ra = ra2;
+    *dec = dec2;
+    if (oriented) {
+        area->pa_deg = t2;
+        area->pa_zero_deg = 0.0;
+        area->pa_sense = 1;
+    }
+    return C3X_OK;
+}
+
 }  // namespace c3x
 
 extern "C" c3x_status c3x_frame_convert(const double *ra, const double *dec, int64_t n,

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include <string>
 #include <vector>
@@ -134,6 +136,22 @@ hipError_t frame_convert(int src, int dst, const double *ra, const double *dec, 
                          double *ra_out, double *dec_out, double *gamma_out, const double *pa,
                          double pa_zero, int pa_sense, double *orient, uint32_t *bad,
                          hipStream_t s);
+
+// An environment switch (test settings): set and not "0".
+inline bool env_on(const char *name)
+{
+    const char *e = getenv(name);
+    return e && *e && strcmp(e, "0") != 0;
+}
+
+// Catalogue A (n rows, frame src) made ready for a cross-match in frame dst:
+// nothing when the frames agree; otherwise its positions converted by the
+// fixed rule into arrays of conv, and an oriented area's orientations turned
+// with them (then taken with zero offset and sense +1). *ra, *dec and *area
+// are replaced; C3X_EINVAL names the first row outside the domain.
+// Synchronises the stream.
+c3x_status convert_catalogue_a(int src, int dst, int64_t n, const double **ra, const double **dec,
+                               c3x_area *area, Arena &conv, hipStream_t s);
 
 // Device copies of a cell size's zone tables on the current device.
 c3x_status device_zone_tables(const ZoneTables *zt, const ZoneInfo **zinfo, const double2 **zref);

@@ -440,6 +440,37 @@ __device__ __forceinline__ int recheck_circle(const ARec &a, double2 rb, double 
     return AMBIG;
 }
 
+// What the ellipse recheck computes from the pair alone (not from the
+// axes): theta / sin theta and the sines of the offset along (su) and
+// across (sv) the orientation (cos, sin of the orientation ct, st), for a
+// pair at haversine h > 0 (cd2: cos Dec of B).
+__device__ __forceinline__ void ell_parts(const ARec &a, double ct, double st, double2 rb,
+                                          double cd2, double h, double &f, double &su,
+                                          double &sv)
+{
+    double tn, te;
+    tangent_ne(a.ra, a.dec, a.z, rb.x, rb.y, cd2, tn, te);
+    double th = 2.0 * asin(sqrt(h));
+    double sth = 2.0 * sqrt(h) * sqrt(1.0 - h);
+    f = th / sth;
+    su = tn * ct + te * st;
+    sv = te * ct - tn * st;
+}
+
+// The ellipse of semi-axes a, b (arcsec) against those parts:
+// Q = (theta / sin theta)^2 ((su / a)^2 + (sv / b)^2), within its margin.
+__device__ __forceinline__ int ell_decide(double f, double su, double sv, double a_arcsec,
+                                          double b_arcsec)
+{
+    double x = su / (kDeg * (a_arcsec / 3600.0));
+    double y = sv / (kDeg * (b_arcsec / 3600.0));
+    double q = (f * f) * (x * x + y * y);
+    double m = kE38 * (1.0 + a_arcsec / b_arcsec);
+    if (q <= 1.0 - m) return IN;
+    if (q > 1.0 + m) return OUT;
+    return AMBIG;
+}
+
 __device__ __forceinline__ int recheck_ellipse(const ARec &a, const AEllR &e, double2 rb)
 {
     double cd2 = cos_dec_acc(rb.y);
@@ -447,20 +478,9 @@ __device__ __forceinline__ int recheck_ellipse(const ARec &a, const AEllR &e, do
     if (h == 0.0) return IN;
     double sa = sin(kHalfDeg * (e.a_arcsec / 3600.0));
     if (h > (sa * sa) * (1.0 + kE40)) return OUT;
-    double tn, te;
-    tangent_ne(a.ra, a.dec, a.z, rb.x, rb.y, cd2, tn, te);
-    double th = 2.0 * asin(sqrt(h));
-    double sth = 2.0 * sqrt(h) * sqrt(1.0 - h);
-    double f = th / sth;
-    double su = tn * e.ct + te * e.st;
-    double sv = te * e.ct - tn * e.st;
-    double x = su / (kDeg * (e.a_arcsec / 3600.0));
-    double y = sv / (kDeg * (e.b_arcsec / 3600.0));
-    double q = (f * f) * (x * x + y * y);
-    double m = kE38 * (1.0 + e.a_arcsec / e.b_arcsec);
-    if (q <= 1.0 - m) return IN;
-    if (q > 1.0 + m) return OUT;
-    return AMBIG;
+    double f, su, sv;
+    ell_parts(a, e.ct, e.st, rb, cd2, h, f, su, sv);
+    return ell_decide(f, su, sv, e.a_arcsec, e.b_arcsec);
 }
 
 // Rectangle of half-sides a (along the orientation) and b (across):

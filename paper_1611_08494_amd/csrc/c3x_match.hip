@@ -58,12 +58,6 @@ static int a_key_bits()
     return kAKeyBits;
 }
 
-// An environment switch: set and not "0".
-static bool env_on(const char *name)
-{
-    const char *e = getenv(name);
-    return e && *e && strcmp(e, "0") != 0;
-}
 constexpr uint32_t kNoKey = 0xffffffffu;  // no cell key: the lane's FP32 offsets are set
 constexpr int kWavesPerBlock = kMatchBlock / 64;
 constexpr int kShortSeg = 16;   // segments up to this long are ordered by the finalize kernel
@@ -2739,39 +2733,12 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
     // are A's inputs
     Arena conv(s);
     c3x_area ar = *area;
-    if (frame != ix->frame && nA > 0) {
-        const bool oriented = area->shape != C3X_CIRCLE;
-        double *ra2 = conv.get_n<double>(nA), *dec2 = conv.get_n<double>(nA);
-        double *t2 = oriented ? conv.get_n<double>(nA) : nullptr;
-        uint32_t *bad = conv.get_n<uint32_t>(1);
-        if (!ra2 || !dec2 || (oriented && !t2) || !bad) {
+    {
+        const c3x_status cs = convert_catalogue_a((int)frame, (int)ix->frame, nA, &ra_deg,
+                                                  &dec_deg, &ar, conv, s);
+        if (cs != C3X_OK) {
             delete R;
-            return fail(C3X_ENOMEM, "frame conversion");
-        }
-        uint32_t hbad = 0xffffffffu;
-        hipError_t e = hipMemsetAsync(bad, 0xff, sizeof(uint32_t), s);
-        if (e == hipSuccess)
-            e = frame_convert((int)frame, (int)ix->frame, ra_deg, dec_deg, nA, ra2, dec2, nullptr,
-                              oriented ? area->pa_deg : nullptr, area->pa_zero_deg, area->pa_sense,
-                              t2, bad, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            delete R;
-            return fail_hip(e, "frame conversion");
-        }
-        if (hbad != 0xffffffffu) {
-            delete R;
-            return fail(C3X_EINVAL, "catalogue A row %u: coordinate outside RA [0,360), |Dec| <= "
-                                    "90 or not finite", hbad);
-        }
-        ra_deg = ra2;
-        dec_deg = dec2;
-        if (oriented) {
-            ar.pa_deg = t2;
-            ar.pa_zero_deg = 0.0;
-            ar.pa_sense = 1;
+            return cs;
         }
         area = &ar;
     }

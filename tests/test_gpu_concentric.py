@@ -1,9 +1,10 @@
 """GPU parity of the concentric ellipses (Section 3, ClumpPopulator):
 c3x_match_concentric through the C ABI against the oracle -- identical
 pairs, separations within 1e-6", identical levels and best matches -- on a
-scaled galactic-ellipse workload, both precisions; the closed-form axis
-placements; one scale equal to the plain elliptical match; empty input and
-the error cases."""
+scaled galactic-ellipse workload, both precisions; every level decided in
+binary128 on the host (a test setting); A in the other frame; the
+closed-form axis placements; one scale equal to the plain elliptical match;
+empty input and the error cases."""
 import json
 import os
 
@@ -80,6 +81,48 @@ def test_levels_match_oracle(c3x, dev, ellipses, precision):
     assert len(np.unique(c.level)) == len(SCALES)
 
 
+def test_levels_decided_on_the_host(c3x, dev, ellipses, monkeypatch):
+    """C3X_DEBUG_FORCE_AMBIG: the FP64 level test decides nothing, so every
+    pair with a smaller scale to decide is decided from scale 0 up in
+    binary128 on the host; the levels stay the oracle's."""
+    cat, c, _ = ellipses
+    monkeypatch.setenv("C3X_DEBUG_FORCE_AMBIG", "1")
+    for precision in (0, 1):
+        r = _run(c3x, dev, cat, precision, SCALES)
+        assert np.array_equal(r.idxA.cpu().numpy(), c.ia)
+        assert np.array_equal(r.idxB.cpu().numpy(), c.ib)
+        assert np.array_equal(r.level.cpu().numpy(), c.level)
+        assert r.stats["n_ambiguous"] >= int(np.count_nonzero(c.level > 0))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_levels_across_frames(c3x, dev, precision):
+    """A in the galactic frame against an equatorial index: the oracle's
+    levels of A converted by the frame rule (orientations turned by its
+    gamma) against the index's B."""
+    from oracle import concentric as C
+    from oracle import frames
+    c = synth.cfg3_galactic_ellipses(scale=0.001)
+    gal, eq = 1, 0
+    rB, dB, _ = frames.convert(c.raB, c.decB, gal, eq)
+    ra2, dec2, gam = frames.convert(c.raA, c.decA, gal, eq)
+    T = (c.pa_zero_deg + c.pa_sense * c.pa_deg) + gam
+    o = C.concentric(ra2, dec2, rB, dB, c.a_arcsec, c.b_arcsec, T, SCALES)
+    assert len(o.ia) > 1000
+    print(f"[gpu] concentric across frames precision={precision}", flush=True)
+    ix = c3x.build_index(_t(rB, dev), _t(dB, dev), frame=eq,
+                         reach_hint_arcsec=float(np.max(c.a_arcsec)) * SCALES[-1],
+                         precision=precision)
+    r = c3x.match_concentric(ix, _t(c.raA, dev), _t(c.decA, dev), _t(c.a_arcsec, dev),
+                             _t(c.b_arcsec, dev), _t(c.pa_deg, dev), SCALES, frame=gal,
+                             pa_zero_deg=c.pa_zero_deg, pa_sense=c.pa_sense, mode=c3x.ALL)
+    ix.free()
+    assert np.array_equal(r.idxA.cpu().numpy(), o.ia)
+    assert np.array_equal(r.idxB.cpu().numpy(), o.ib)
+    assert np.abs(r.sep.cpu().numpy() - o.sep).max() <= SEP_TOL
+    assert np.array_equal(r.level.cpu().numpy(), o.level)
+
+
 @pytest.mark.parametrize("ci", range(6))
 def test_axis_placements(c3x, dev, ci):
     from test_oracle_concentric import axis_catalogue
@@ -127,3 +170,5 @@ def test_empty_and_errors(c3x, dev, ellipses):
                            pa_deg=np.zeros(5))
     with pytest.raises(c3x.C3XError, match="scale 3"):
         _run(c3x, dev, big, 0, SCALES)  # a * 2 leaves the ellipse domain
+    with pytest.raises(c3x.C3XError, match="scale 0"):
+        _run(c3x, dev, cat, 0, [1e-7, 1.0])  # b * 1e-7 leaves it too
