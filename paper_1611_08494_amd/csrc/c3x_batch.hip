@@ -344,14 +344,15 @@ __global__ void k_bapply(const BAmb *__restrict__ hl, const uint32_t *__restrict
     else atomicOr(flags, kBFlagCap);
 }
 
-// Band matches: counted, and listed as the k-th match of their row.
+// Band matches: counted in their row's record, and listed as the k-th
+// match of their row.
 __global__ void k_badd(const uint4 *__restrict__ bin, const uint32_t *__restrict__ n_bin,
-                       uint32_t cap, uint32_t *cnts, WEnt *__restrict__ out)
+                       uint32_t cap, RowRec *rec, WEnt *__restrict__ out)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= min(*n_bin, cap)) return;
     const uint4 q = bin[t];
-    const uint32_t k = atomicAdd(&cnts[q.y], 1u);
+    const uint32_t k = atomicAdd(&rec[q.y].n, 1u) & kCountMask;
     out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
@@ -478,8 +479,8 @@ struct c3x_batch {
     double2 *arad = nullptr;
     uint32_t *aidx = nullptr, *ajob = nullptr;
     ARange *arng = nullptr;
-    uint32_t *cnts = nullptr;
     RowRec *rec = nullptr;
+    int32_t *best2 = nullptr;
     // lists
     uint2 *amb = nullptr, *tie = nullptr;
     uint32_t amb_cap = 0, tie_cap = 0;
@@ -589,8 +590,8 @@ static MatchArgs batch_args(c3x_batch *b)
     m.jobs = b->djobs;
     m.ajob = b->ajob;
     m.nA = (int32_t)b->NA;
-    m.cnts = b->cnts;
-    m.cnts_zeroed = 1;  // cleared by a fill kernel before the count pass
+    m.best2 = b->best2;
+    m.rec_zeroed = 1;  // cleared by a fill kernel before the count pass
     m.best_only = 0;
     m.rec = b->rec;
     m.amb_n = b->ctr + 1;
@@ -670,7 +671,8 @@ static hipError_t batch_front(c3x_batch *b)
         // tiles of the costliest jobs first (a job's cost: the candidates of
         // its rows), each job's tiles together and in order, taken from a
         // counter by a persistent grid
-        hipLaunchKernelGGL(k_bfill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->cnts, NA, 0u);
+        hipLaunchKernelGGL(k_bfill, dim3(nblk(NA * kRecWords, 256)), dim3(256), 0, s,
+                           (uint32_t *)b->rec, NA * kRecWords, 0u);
         hipLaunchKernelGGL(k_job_cost, dim3(std::min(nj, 4096)), dim3(256), 0, s, b->djobs, nj,
                            b->arng, b->jcost);
         hipLaunchKernelGGL(k_tile_cost, dim3(nblk(grid, 256)), dim3(256), 0, s, b->ajob, b->jcost,
@@ -692,7 +694,8 @@ static hipError_t batch_front(c3x_batch *b)
             hipLaunchKernelGGL(k_match_queue<C3X_MIXED>, dim3(pg), dim3(b->tile), 0, s, m, order,
                                grid, chunk, b->qctr);
     } else if (grid) {
-        hipLaunchKernelGGL(k_bfill, dim3(nblk(NA, 256)), dim3(256), 0, s, b->cnts, NA, 0u);
+        hipLaunchKernelGGL(k_bfill, dim3(nblk(NA * kRecWords, 256)), dim3(256), 0, s,
+                           (uint32_t *)b->rec, NA * kRecWords, 0u);
         if (b->prec == C3X_FP64)
             hipLaunchKernelGGL((k_match<C3X_CIRCLE, C3X_FP64, 2, true>), dim3(grid),
                                dim3(b->tile), 0, s, m);
@@ -721,7 +724,7 @@ static hipError_t batch_front(c3x_batch *b)
     hipLaunchKernelGGL(k_bapply, dim3(nblk(b->hl_cap, 256)), dim3(256), 0, s, b->hl, b->ctr + 9,
                        b->hl_cap, b->d_hin, b->bin, b->ctr + 8, b->bin_cap, b->ctr);
     hipLaunchKernelGGL(k_badd, dim3(nblk(b->bin_cap, 256)), dim3(256), 0, s, b->bin, b->ctr + 8,
-                       b->bin_cap, b->cnts, b->xent);
+                       b->bin_cap, b->rec, b->xent);
     // best matches the filter cannot rank: FP64 on the GPU; what FP64 cannot
     // separate is listed (c3x_batch_result ranks it in binary128)
     const uint32_t npos = b->tie_cap + b->bin_cap;
@@ -736,7 +739,8 @@ static hipError_t batch_front(c3x_batch *b)
                            b->pos, npos, b->ctr + 10, b->ctr + 3, b->unc);
     // counts -> offsets (off[NA] = P)
     if (NA > 0) {
-        e = scan_u32_to_i64(b->cnts, 1, b->off, NA, b->off + NA, b->sws, s);
+        e = scan_u32_to_i64(&b->rec->n, kRecWords, kCountMask, b->off, NA, b->off + NA, b->sws,
+                            s);
         if (e != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL(k_bfill64, dim3(1), dim3(64), 0, s, (unsigned long long *)b->off,
@@ -754,6 +758,7 @@ static FinishArgs batch_fin_args(c3x_batch *b)
     fa.pcap = b->P_cap;
     fa.off = b->off;
     fa.rec = b->rec;
+    fa.best2 = b->best2;
     fa.use_rec = 1;
     fa.defer = b->prec == C3X_MIXED ? 1 : 0;
     fa.tmp = b->pt;
@@ -1120,8 +1125,8 @@ static c3x_status batch_plan_impl(c3x_batch *b)
     b->aidx = M.get_n<uint32_t>(NA);
     b->ajob = M.get_n<uint32_t>(NA);
     b->arng = M.get_n<ARange>(NA);
-    b->cnts = M.get_n<uint32_t>(NA);
     b->rec = M.get_n<RowRec>(NA);
+    b->best2 = M.get_n<int32_t>(NA);
     b->amb_cap = (uint32_t)std::min<int64_t>(NA / 16 + 4096, 1 << 26);
     b->tie_cap = (uint32_t)std::min<int64_t>(NA / 16 + 4096, 1 << 26);
     b->bin_cap = b->amb_cap;
@@ -1164,7 +1169,7 @@ static c3x_status batch_plan_impl(c3x_batch *b)
               b->coordB && b->packA && b->packB &&
               b->dir && b->gaps && b->n_gaps &&
               b->ak && b->av && b->ak2 && b->av2 && b->aws && b->arad && b->aidx && b->ajob &&
-              b->arng && b->cnts && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
+              b->arng && b->best2 && b->rec && b->amb && b->tie && b->ovl && b->octr && b->bin &&
               b->hl && b->xent && b->pos && b->unc && b->d_hin && b->d_vi && b->d_vk &&
               b->d_nv && b->ctr && b->c64 && b->off && b->sws && b->seg_list && b->seg_huge &&
               b->obest && b->obsep && b->joboff;

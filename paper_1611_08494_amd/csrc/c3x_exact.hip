@@ -212,7 +212,7 @@ static c3x_status exact_impl(const uint64_t *keyA, int64_t nA, const uint64_t *k
                            rs, nB, dir, dshift, dsize, cnt, R->best_idx, nullptr, (int)!all,
                            (int64_t)0, nullptr, nullptr, ctr);
     ECHK(hipGetLastError(), "probe");
-    ECHK(scan_u32_to_i64(cnt, 1, off, nA, off + nA, ws, s), "scan");
+    ECHK(scan_u32_to_i64(cnt, 1, ~0u, off, nA, off + nA, ws, s), "scan");
     int64_t P = 0;
     ECHK(hipMemcpyAsync(&P, off + nA, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     ECHK(hipStreamSynchronize(s), "exact-value count");

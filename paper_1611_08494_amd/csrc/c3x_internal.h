@@ -157,16 +157,34 @@ __device__ __forceinline__ unsigned long long *stat_slot(unsigned long long *fie
 constexpr int kEmitPools = 64;       // overflow-list counters (spread contention)
 constexpr int kEmitPoolStride = 32;  // u32 words between two counters (128 B)
 
-// Per-A record of the count pass (idxA order), one aligned 16-byte store
-// per row (the records are written scattered, in idxA order: a small record
-// keeps that cheap): the best match and the row's first match. Best-only
-// calls keep no match there; b[0] holds the best match's sorted B position.
+// Per-A record of the count pass (idxA order): the row's match count (the
+// scan's input), its first match and, where that settles it, its best. It
+// is one aligned 16-byte store per matched row, and the only one: the
+// records are written scattered, in idxA order, and each scattered store
+// costs a memory transaction of its own. A row whose best is not the
+// record's match (two or more matches when the record keeps the first one,
+// or a best re-ranked after the count) has kBestSide set and its best in a
+// side table (best2), written for those rows only.
 struct alignas(16) RowRec {
-    int32_t best;          // idxB of the best match, -1: none
-    uint32_t b[kTab];      // idxB of the row's first match (best only: the best's j)
-    double c[kTab];        // its coded separation (see sep_code)
+    uint32_t n;            // matches (filter, then band ones added) | kBestSide
+    uint32_t b0;           // idxB of the row's first match (count-only passes:
+                           // of its best)
+    double c0;             // the first match's coded separation (see sep_code)
 };
 static_assert(sizeof(RowRec) == 16, "one 16-byte store per row");
+static_assert(kTab == 1, "one match slot in the record");
+constexpr uint32_t kBestSide = 1u << 31;       // RowRec.n: the best is in best2
+constexpr uint32_t kCountMask = kBestSide - 1u;  // RowRec.n: the count
+constexpr int64_t kRecWords = sizeof(RowRec) / sizeof(uint32_t);
+
+// Best match (idxB) of idxA row a from its record: -1 for a row without
+// matches.
+__device__ __forceinline__ int32_t row_best(const RowRec &r, const int32_t *__restrict__ best2,
+                                            int64_t a)
+{
+    if ((r.n & kCountMask) == 0u) return -1;
+    return (r.n & kBestSide) ? best2[a] : (int32_t)r.b0;
+}
 
 // Candidate B ranges of one sorted A source, found once when A is prepared:
 // zone zlo + q holds the sorted B positions [j0[q], j0[q] + n[q]). zlo < 0:
@@ -241,12 +259,12 @@ struct MatchArgs {
     int32_t r_zero;        // radius exactly 0
     double L_rad;          // bound on |p - cell reference| (FP32 error model)
     // count pass
-    uint32_t *cnts;        // [nA] matches per row (idxA order)
     RowRec *rec;           // [nA] idxA order
-    int32_t best_only;     // no table: rec.b[0] keeps the best's sorted position
-    int32_t cnts_zeroed;   // cnts cleared beforehand: rows without a filter
-                           // match store neither count nor record (every
-                           // reader of a record checks the row's count first)
+    int32_t *best2;        // [nA] idxA order: bests of rows flagged kBestSide
+    int32_t best_only;     // no pairs kept: only the best of each row
+    int32_t rec_zeroed;    // records cleared beforehand: rows without a filter
+                           // match store no record (every reader of a record
+                           // checks the row's count first)
     uint32_t *amb_n;       // band candidates: (sorted A pos, sorted B pos)
     uint2 *amb;
     uint32_t amb_cap;

@@ -5,25 +5,28 @@
 // central object with the limits of the area; Section 2.2: the matches are
 // kept as rows, all of them or only the best; Section 2.3: each source is
 // tested only against the cells around it. Phases on one stream:
-//   A prep     validate, key, sort A by cell (LDS radix sort), sorted
-//              coordinates (+ ellipse frames)
-//   count      wavefront tiles of 64 consecutive sorted A sources: per zone,
-//              the union of the lanes' cell windows is one key range of B,
-//              found with two directory lookups and staged through LDS; each
-//              lane binary-searches its own cells in LDS and decides its
-//              candidates with the certified filter; candidates inside the
-//              filter's error band are listed. Counts and the best match go
-//              to idxA order.
+//   A prep     validate, key, sort A by cell (LDS radix sort); in sorted
+//              order the coordinates, each source's candidate ranges of
+//              sorted B positions (up to three zones, from the cell
+//              directory) and ellipse frames; sources with many candidates
+//              are listed for a wavefront each
+//   count      one lane per sorted source (a wavefront per listed one): its
+//              candidates decided by the certified filter, those inside the
+//              filter's error band listed; the row's record (count, first
+//              match, best) stored once in idxA order, later matches
+//              appended to the overflow list
 //   recheck    one thread per listed candidate: FP64 relative-accuracy form;
 //              what it cannot certify is decided on the host in binary128
-//   [host]     verdict table; near-tie best matches re-ranked in binary128
-//              from a collect pass
-//   scan       counts -> int64 offsets (idxA order)
-//   write      same tiles and decisions; each lane writes (idxB, B position)
-//              into its own idxA segment
-//   finalize   one thread per pair: rank inside its segment by idxB
-//              (canonical order), separation in FP64, final write
-//   best       one thread per A: separation of the best match
+//   [host]     verdict table; near-tie best matches re-ranked in FP64, and
+//              in binary128 from a collect pass where FP64 cannot rank them
+//   scan       record counts -> int64 offsets (idxA order)
+//   place      overflow-list and band matches to their segments (a write
+//              pass repeats the count's decisions into the segments when an
+//              overflow region ran out)
+//   finalize   one thread per A row: best, the record's match, ranks by idxB
+//              (canonical order) and separations; long segments sorted in
+//              LDS or by the radix sort
+//   best       best-only calls: one thread per A, the best's separation
 // Decisions of the count, write and collect passes come from one device
 // function compiled with -ffp-contract=off, so they agree bit for bit.
 #include <math.h>
@@ -637,7 +640,7 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
 
     uint32_t cnt = 0;
     double b1 = INFINITY, b2 = INFINITY;
-    uint32_t bidx = 0xffffffffu, bj = 0;
+    uint32_t bidx = 0xffffffffu;
     uint32_t tb0 = 0;  // MODE 2: the row's first match
     double tc0 = 0.0;
     static_assert(kTab == 1, "one record slot");
@@ -718,7 +721,6 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
                 b2 = b1;
                 b1 = c2;
                 bidx = pay_row(b);
-                bj = j;
             } else if (c2 < b2) {
                 b2 = c2;
             }
@@ -819,16 +821,18 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
             });
         }
     }
-    // a row's count and record are scattered stores (idxA order), the
-    // costliest of the pass: rows without a match skip them when the counts
-    // start at zero
-    if (active && MODE != 1 && (cnt || !m.cnts_zeroed)) {
-        m.cnts[a.idx] = cnt;
+    // a row's record is a scattered store (idxA order), the costliest of
+    // the pass: rows without a match skip it when the records start at zero
+    if (active && MODE != 1 && (cnt || !m.rec_zeroed)) {
+        // the record keeps the first match (MODE 2): a second one puts the
+        // best in the side table
+        const bool side = MODE == 2 && cnt >= 2;
         RowRec r;
-        r.best = cnt ? (int32_t)bidx : -1;
-        r.b[0] = MODE == 0 ? bj : tb0;
-        r.c[0] = tc0;
+        r.n = cnt | (side ? kBestSide : 0u);
+        r.b0 = MODE == 0 ? bidx : tb0;
+        r.c0 = tc0;
         m.rec[a.idx] = r;
+        if (side) m.best2[a.idx] = (int32_t)bidx;
         if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
         const double terr = PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
                             : (BATCH ? c2_err<C3X_MIXED>(sqrt(b2), Lr) : chord_err(sqrt(b2), Lr));
@@ -992,7 +996,7 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
         CellCache cc{0xffffffffu, 0xffffffffu, 0.f, 0.f, 0.f};
         uint32_t cnt = 0;  // wave-uniform
         double b1 = INFINITY, b2 = INFINITY;
-        uint32_t bidx = 0xffffffffu, bj = 0;
+        uint32_t bidx = 0xffffffffu;
         uint32_t tb0 = 0;
         double tc0 = 0.0;
 
@@ -1031,7 +1035,6 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
                         b2 = b1;
                         b1 = c2;
                         bidx = pay_row(b);
-                        bj = j;
                     } else if (c2 < b2) {
                         b2 = c2;
                     }
@@ -1092,23 +1095,23 @@ __global__ __launch_bounds__(256) void k_match_wide(MatchArgs m)
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const double ob1 = __shfl_xor(b1, o), ob2 = __shfl_xor(b2, o);
-            const uint32_t oidx = __shfl_xor(bidx, o), oj = __shfl_xor(bj, o);
+            const uint32_t oidx = __shfl_xor(bidx, o);
             if (ob1 < b1 || (ob1 == b1 && oidx < bidx)) {
                 b2 = fmin(b1, fmin(b2, ob2));
                 b1 = ob1;
                 bidx = oidx;
-                bj = oj;
             } else {
                 b2 = fmin(ob1, fmin(b2, ob2));
             }
         }
         if (lane == 0) {
-            m.cnts[a.idx] = cnt;
+            const bool side = MODE == 2 && cnt >= 2;
             RowRec r;
-            r.best = cnt ? (int32_t)bidx : -1;
-            r.b[0] = MODE == 0 ? bj : tb0;
-            r.c[0] = tc0;
+            r.n = cnt | (side ? kBestSide : 0u);
+            r.b0 = MODE == 0 ? bidx : tb0;
+            r.c0 = tc0;
             m.rec[a.idx] = r;
+            if (side) m.best2[a.idx] = (int32_t)bidx;
             if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
             if (cnt >= 2 &&
                 b2 - b1 <= (4.0 + m.tie_widen) * (PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
@@ -1210,8 +1213,9 @@ __device__ __forceinline__ Cand cand_shfl_xor(const Cand &x, int o)
 // matches found inside): one wavefront per row. Every match is re-decided
 // (filter, then the band verdicts) and ranked by its FP64 squared chord
 // from the FP64 unit vectors (error c2_err<FP64>); when the runner-up is
-// further than 4 such errors the best is certain and written to the row's
-// record, otherwise the row is listed for the host's binary128 ranking.
+// further than 4 such errors the best is certain and written to the side
+// table (the row's record flagged kBestSide), otherwise the row is listed
+// for the host's binary128 ranking.
 template <int SHAPE, int PREC, bool BATCH>
 __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
                                            uint32_t *__restrict__ unc_n,
@@ -1286,8 +1290,8 @@ __device__ __forceinline__ void rerank_one(const MatchArgs &m, uint32_t i,
         const bool sure = b2.idxB == 0xffffffffu ||
                           b2.c2 - b1.c2 > (4.0 + m.tie_widen) * c2_err<C3X_FP64>(sqrt(b2.c2), 0.0);
         if (sure) {
-            m.rec[row].best = (int32_t)b1.idxB;
-            if (m.best_only) m.rec[row].b[0] = b1.j;
+            m.best2[row] = (int32_t)b1.idxB;
+            atomicOr(&m.rec[row].n, kBestSide);
         } else {
             unc[atomicAdd(unc_n, 1u)] = i;
         }
@@ -1402,14 +1406,15 @@ __global__ void k_gather_pos(const uint32_t *__restrict__ pos, uint32_t n,
 }
 
 // Band candidates found inside (sorted A position, idxA, idxB, sorted B
-// position): each is counted, and listed as the k-th match of its source.
-__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, uint32_t *cnts,
+// position): each is counted in its row's record, and listed as the k-th
+// match of its source.
+__global__ void k_add_pairs(const uint4 *__restrict__ in, uint32_t n, RowRec *rec,
                             WEnt *__restrict__ out)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     uint4 q = in[t];
-    uint32_t k = atomicAdd(&cnts[q.y], 1u);
+    const uint32_t k = atomicAdd(&rec[q.y].n, 1u) & kCountMask;
     if (out) out[t] = WEnt{q.x, k, q.z, q.w};
 }
 
@@ -1487,8 +1492,8 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
     x.j = e.j;
     x.sep = sep_rare(ra.x, ra.y, rb.x, rb.y);
     if (use_rec && e.k < (uint32_t)kTab) {
-        rec[a].b[e.k] = x.idxB;
-        rec[a].c[e.k] = x.sep;
+        rec[a].b0 = x.idxB;
+        rec[a].c0 = x.sep;
     } else {
         tmp[p] = x;
     }
@@ -1496,13 +1501,12 @@ __global__ void k_place_x(const WEnt *__restrict__ xent, uint32_t nx,
 }
 
 __global__ void k_patch_best(const uint32_t *__restrict__ rows, const int32_t *__restrict__ bi,
-                             const uint32_t *__restrict__ bj, uint32_t n, RowRec *rec,
-                             int best_only)
+                             uint32_t n, RowRec *rec, int32_t *__restrict__ best2)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    rec[rows[t]].best = bi[t];
-    if (best_only) rec[rows[t]].b[0] = bj[t];
+    best2[rows[t]] = bi[t];
+    atomicOr(&rec[rows[t]].n, kBestSide);
 }
 
 // Best matches decided on the host after the outputs exist: the row's best
@@ -1531,10 +1535,10 @@ __global__ void k_patch_out(const uint32_t *__restrict__ rows, const int32_t *__
 }
 
 // BEST-only output: one record per row that has a match.
-__global__ void k_nonzero(const uint32_t *__restrict__ cnts, int64_t n, uint32_t *__restrict__ out)
+__global__ void k_nonzero(const RowRec *__restrict__ rec, int64_t n, uint32_t *__restrict__ out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) out[t] = cnts[t] ? 1u : 0u;
+    if (t < n) out[t] = (rec[t].n & kCountMask) ? 1u : 0u;
 }
 
 // Separation (arcsec) of a coded match (see sep_code). A chord below 0.1
@@ -1614,7 +1618,8 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
 // segment). A longer one has its record's matches copied into the segment,
 // which k_seg_lds then finishes.
 __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *__restrict__ off,
-                           const RowRec *__restrict__ rec, int use_rec, PairTmp *__restrict__ tmp,
+                           const RowRec *__restrict__ rec, const int32_t *__restrict__ best2,
+                           int use_rec, PairTmp *__restrict__ tmp,
                            const double2 *__restrict__ coordA, const double2 *__restrict__ coordB,
                            int32_t *__restrict__ best_idx,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
@@ -1634,13 +1639,13 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
         return;
     }
     const RowRec r = rec[a];
-    best_idx[a] = r.best;
+    const int32_t best = row_best(r, best2, a);
+    best_idx[a] = best;
     const int nt = use_rec ? (int)min<int64_t>(len, kTab) : 0;
-    static_assert(kTab == 1, "one record slot");
     PairTmp x0;  // the record's slot
-    x0.idxB = r.b[0];
+    x0.idxB = r.b0;
     x0.j = 0;
-    x0.sep = r.c[0];
+    x0.sep = r.c0;
     if (len > kShortSeg) {
         if (nt > 0) tmp[o] = x0;
         return;
@@ -1653,7 +1658,7 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
         return rk;
     };
     auto put = [&](const PairTmp &x) {
-        final_write(o + rank_of(x.idxB), a, x, nB, coordA, coordB, r.best, oa, ob, os, bsep, err,
+        final_write(o + rank_of(x.idxB), a, x, nB, coordA, coordB, best, oa, ob, os, bsep, err,
                     defer != 0);
     };
     if (nt > 0) put(x0);
@@ -1663,8 +1668,9 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
 // BEST-only mode, one thread per A row: the best match, its separation and
 // the compacted (idxA, idxB, sep) pair.
 __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec,
+                           const int32_t *__restrict__ best2,
                            const double *__restrict__ raA, const double *__restrict__ decA,
-                           const double2 *__restrict__ coordB, BRows brows,
+                           const double2 *__restrict__ coordB,
                            int32_t *__restrict__ bidx,
                            double *__restrict__ bsep, const int64_t *__restrict__ off, int64_t P,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
@@ -1672,18 +1678,17 @@ __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int32_t b = off[t + 1] > off[t] ? rec[t].best : -1;
+    const int32_t b = off[t + 1] > off[t] ? row_best(rec[t], best2, t) : -1;
     bidx[t] = b;
     if (b < 0) {
         bsep[t] = NAN;
         return;
     }
-    uint32_t bj = rec[t].b[0];
-    if (bj >= (uint64_t)nB) {
+    if (b >= nB) {
         atomicOr(err, 16u);
         return;
     }
-    double2 rb = coordB[brows(bj)];
+    const double2 rb = coordB[b];
     double s = sep_arcsec_rd(raA[t], decA[t], rb.x, rb.y);
     bsep[t] = s;
     if (off) {
@@ -1724,6 +1729,7 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                                                  const double2 *__restrict__ coordA,
                                                  const double2 *__restrict__ coordB,
                                                  const RowRec *__restrict__ rec,
+                                                 const int32_t *__restrict__ best2,
                                                  int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                                                  double *__restrict__ os, double *__restrict__ bsep,
                                                  uint32_t *__restrict__ huge_n,
@@ -1765,7 +1771,7 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                 __syncthreads();
             }
         }
-        const int32_t best = rec[a].best;
+        const int32_t best = row_best(rec[a], best2, a);
         for (int k = threadIdx.x; k < len; k += blockDim.x)
             final_write(o + k, a, tmp[o + (uint32_t)v[k]], nB, coordA, coordB, best, oa, ob, os,
                         bsep, err, defer != 0);
@@ -1803,6 +1809,7 @@ struct FinishArgs {
     int64_t pcap;          // pairs the outputs hold
     const int64_t *off;
     const RowRec *rec;
+    const int32_t *best2;   // bests of the rows flagged kBestSide
     int use_rec;
     int defer;              // separations from coordinates by k_sep_coords (mixed path)
     PairTmp *tmp;
@@ -1826,13 +1833,13 @@ static void finish_segments(const FinishArgs &f, hipStream_t s)
 {
     if (f.nA == 0) return;
     hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.pcap,
-                       f.off, f.rec, f.use_rec, f.tmp, f.coordA, f.coordB, f.best_idx, f.oa, f.ob,
-                       f.os, f.bsep, f.err, f.defer);
+                       f.off, f.rec, f.best2, f.use_rec, f.tmp, f.coordA, f.coordB, f.best_idx,
+                       f.oa, f.ob, f.os, f.bsep, f.err, f.defer);
     hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA, f.seg_n,
                        f.list, f.cap);
     hipLaunchKernelGGL(k_seg_lds, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list, f.cap,
-                       f.tmp, f.nB, f.pcap, f.coordA, f.coordB, f.rec, f.oa, f.ob, f.os, f.bsep,
-                       f.seg_n + 1, f.huge, f.err, f.defer);
+                       f.tmp, f.nB, f.pcap, f.coordA, f.coordB, f.rec, f.best2, f.oa, f.ob, f.os,
+                       f.bsep, f.seg_n + 1, f.huge, f.err, f.defer);
     if (f.defer && f.pcap > 0)
         hipLaunchKernelGGL(k_sep_coords, dim3(nblk(f.pcap, 256)), dim3(256), 0, s, f.pcap, f.nA,
                            f.nB, f.oa, f.ob, f.os, f.coordA, f.coordB, f.best_idx, f.bsep);
@@ -1888,6 +1895,7 @@ __global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
                              const double2 *__restrict__ coordA,
                              const double2 *__restrict__ coordB,
                              const RowRec *__restrict__ rec,
+                             const int32_t *__restrict__ best2,
                              int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                              double *__restrict__ os, double *__restrict__ bsep,
                              uint32_t *__restrict__ err)
@@ -1909,8 +1917,8 @@ __global__ void k_huge_write(const uint32_t *__restrict__ val, uint32_t n,
         atomicOr(err, 16u);
         return;
     }
-    final_write(o + rk, a, tmp[o + src], nB, coordA, coordB, rec[a].best, oa, ob, os, bsep, err,
-                false);
+    final_write(o + rk, a, tmp[o + src], nB, coordA, coordB, row_best(rec[a], best2, a), oa, ob,
+                os, bsep, err, false);
 }
 
 static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStream_t s)
@@ -1950,8 +1958,8 @@ static c3x_status finish_huge(const FinishArgs &f, const uint32_t *hseg, hipStre
     if (e == hipSuccess) {
         const uint32_t *vf = in2 ? vb : va;
         hipLaunchKernelGGL(k_huge_write, dim3(nblk(n, 256)), dim3(256), 0, s, vf, n, seg, base,
-                           f.huge, f.off, f.tmp, f.nB, f.coordA, f.coordB, f.rec, f.oa, f.ob,
-                           f.os, f.bsep, f.err);
+                           f.huge, f.off, f.tmp, f.nB, f.coordA, f.coordB, f.rec, f.best2, f.oa,
+                           f.ob, f.os, f.bsep, f.err);
         e = hipGetLastError();
     }
     uint32_t gave_up = 0;
@@ -2118,7 +2126,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     double2 *packed = tmp.get_n<double2>(nA);
     ARange *arng = tmp.get_n<ARange>(nA);
     uint32_t *aidx = tmp.get_n<uint32_t>(nA);
-    uint32_t *cnts = tmp.get_n<uint32_t>(nA);
+    int32_t *best2 = tmp.get_n<int32_t>(nA);
     RowRec *rec = tmp.get_n<RowRec>(nA);
     AEll *aell = nullptr;
     AEllR *aellr = nullptr;
@@ -2128,7 +2136,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
     }
     if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !packed || !aidx ||
-        !cnts || !rec || !arng)
+        !best2 || !rec || !arng)
         return fail(C3X_ENOMEM, "A buffers");
     R->nA = nA;
     R->best_idx = R->mem.get_n<int32_t>(nA);
@@ -2219,8 +2227,8 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     m.n_tests = c64;
     m.n_band = c64 + 1;
     m.err_flag = ctr + 4;
-    m.cnts = cnts;
-    m.cnts_zeroed = 1;
+    m.best2 = best2;
+    m.rec_zeroed = 1;
     m.best_only = !all;
     m.rec = rec;
     m.wide = wide;
@@ -2303,7 +2311,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     uint32_t hctr[16];
     unsigned long long h64[3];
     std::vector<uint32_t> hoctr(kPoolWords);
-    if (nA > 0) HIPCHK(hipMemsetAsync(cnts, 0, (size_t)nA * sizeof(uint32_t), s), "memset");
+    if (nA > 0) HIPCHK(hipMemsetAsync(rec, 0, (size_t)nA * sizeof(RowRec), s), "memset");
     Timer tk(s);  // the count kernel alone (the last attempt's launch)
     for (int attempt = 0; attempt < 2; ++attempt) {
         tk.n = 0;
@@ -2432,7 +2440,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             xent = tmp.get_n<WEnt>(n_bin);
             if (!xent) return fail(C3X_ENOMEM, "band matches");
         }
-        hipLaunchKernelGGL(k_add_pairs, dim3(nblk(n_bin, 256)), dim3(256), 0, s, bin, n_bin, cnts,
+        hipLaunchKernelGGL(k_add_pairs, dim3(nblk(n_bin, 256)), dim3(256), 0, s, bin, n_bin, rec,
                            xent);
     }
 
@@ -2500,7 +2508,6 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         }
         std::vector<uint32_t> prow;
         std::vector<int32_t> pbi;
-        std::vector<uint32_t> pbj;
         for (uint32_t k = 0; k < nc; ++k) {
             auto &v = per[k];
             if (v.empty()) continue;
@@ -2514,22 +2521,20 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
             int w = c3x_q_best(ad[k].x, ad[k].y, (int)v.size(), r2.data(), d2.data(), ib.data());
             prow.push_back(arow[k]);
             pbi.push_back(ib[w]);
-            pbj.push_back(v[w]->j);
         }
         if (!prow.empty()) {
             uint32_t np = (uint32_t)prow.size();
-            uint32_t *d1 = tmp.get_n<uint32_t>(np), *d3 = tmp.get_n<uint32_t>(np);
+            uint32_t *d1 = tmp.get_n<uint32_t>(np);
             int32_t *d2 = tmp.get_n<int32_t>(np);
-            if (!d1 || !d2 || !d3) return fail(C3X_ENOMEM, "best patch");
+            if (!d1 || !d2) return fail(C3X_ENOMEM, "best patch");
             HIPCHK(hipMemcpyAsync(d1, prow.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             HIPCHK(hipMemcpyAsync(d2, pbi.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
-            HIPCHK(hipMemcpyAsync(d3, pbj.data(), np * 4, hipMemcpyHostToDevice, s), "copy");
             if (after_outputs)
                 hipLaunchKernelGGL(k_patch_out, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, np,
                                    off, R->idxB, R->sep, R->best_idx, R->best_sep, ctr + 4);
             else
-                hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, d3,
-                                   np, rec, (int)!all);
+                hipLaunchKernelGGL(k_patch_best, dim3(nblk(np, 256)), dim3(256), 0, s, d1, d2, np,
+                                   rec, best2);
             HIPCHK(hipStreamSynchronize(s), "best patch");
         }
         return C3X_OK;
@@ -2540,16 +2545,19 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     // (first matches in the records, the overflow list, the band matches)
     // and the outputs go ahead without waiting for the scan.
     off = tmp.get_n<int64_t>(nA + 1);
-    const uint32_t *scan_in = cnts;
+    // the counts are the records' first words (the flag bit masked off)
+    const uint32_t *scan_in = &rec->n;
+    int64_t scan_stride = kRecWords;
     if (!all) {  // one output row per A row with a match
         uint32_t *nz = tmp.get_n<uint32_t>(nA);
         if (!nz) return fail(C3X_ENOMEM, "offsets");
         if (nA > 0)
-            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, cnts, nA, nz);
+            hipLaunchKernelGGL(k_nonzero, dim3(nblk(nA, 256)), dim3(256), 0, s, rec, nA, nz);
         scan_in = nz;
+        scan_stride = 1;
     }
     if (!off) return fail(C3X_ENOMEM, "offsets");
-    HIPCHK(scan_u32_to_i64(scan_in, 1, off, nA, off + nA, ws, s), "scan");
+    HIPCHK(scan_u32_to_i64(scan_in, scan_stride, kCountMask, off, nA, off + nA, ws, s), "scan");
     const bool early = all && emitted;
     int64_t P = 0;
     int64_t *hP = (int64_t *)(hb + kCtrBytes);
@@ -2610,6 +2618,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         fa.pcap = P;
         fa.off = off;
         fa.rec = rec;
+        fa.best2 = best2;
         fa.use_rec = emitted ? 1 : 0;
         fa.defer = 0;  // every match's separation is coded from its FP64 chord
         fa.tmp = pt;
@@ -2635,10 +2644,9 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         tm.mark();  // 5
     }
     if (nA > 0 && !all)
-        hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB, rec, ra,
-                           dec, ix->radec, BRows{ix->pay64, ix->pay32}, R->best_idx, R->best_sep, off, P, R->idxA,
-                           R->idxB,
-                           R->sep, ctr + 4);
+        hipLaunchKernelGGL(k_best_sep, dim3(nblk(nA, 256)), dim3(256), 0, s, nA, ix->nB, rec,
+                           best2, ra, dec, ix->radec, R->best_idx, R->best_sep, off, P, R->idxA,
+                           R->idxB, R->sep, ctr + 4);
     HIPCHK(hipGetLastError(), "best separations");
     tm.mark();  // 6
     HIPCHK(hipMemcpyAsync(hb, cblk, kOctrAt, hipMemcpyDeviceToHost, s), "copy");

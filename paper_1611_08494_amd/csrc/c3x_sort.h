@@ -30,9 +30,10 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
 
 size_t scan_ws_bytes(int64_t n);
 // Exclusive scans; *total (device, may be NULL) receives the sum. The
-// 64-bit scan reads in[k * stride] (counts inside larger records).
-hipError_t scan_u32_to_i64(const uint32_t *in, int64_t stride, int64_t *out, int64_t n,
-                           int64_t *total, void *ws, hipStream_t s);
+// 64-bit scan reads in[k * stride] & mask (counts inside larger records,
+// flag bits masked off).
+hipError_t scan_u32_to_i64(const uint32_t *in, int64_t stride, uint32_t mask, int64_t *out,
+                           int64_t n, int64_t *total, void *ws, hipStream_t s);
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *ws,
                     hipStream_t s);
 

@@ -432,16 +432,25 @@ __device__ __forceinline__ T block_excl_scan(T x, T &total)
     return pre + inc - x;
 }
 
+// Strided input (compact != null): the tile's values are also kept, packed,
+// at the start of the tile's own output range (compact = the output as Ti,
+// To twice as wide), so that the final pass reads them there instead of
+// the strided records again.
 template <typename Ti, typename To>
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const Ti *__restrict__ in,
-                                                            int64_t stride, int64_t n,
-                                                            To *__restrict__ part)
+                                                            int64_t stride, Ti mask, int64_t n,
+                                                            To *__restrict__ part,
+                                                            Ti *__restrict__ compact)
 {
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     To s = 0;
     for (int r = 0; r < kScanItems; ++r) {
         int64_t e = base + r * kScanBlock + threadIdx.x;
-        if (e < n) s += (To)in[e * stride];
+        if (e < n) {
+            const Ti v = in[e * stride] & mask;
+            s += (To)v;
+            if (compact) compact[2 * base + r * kScanBlock + threadIdx.x] = v;
+        }
     }
     To tot;
     block_excl_scan<To>(s, tot);
@@ -477,18 +486,18 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_partials(To *part, int64_t 
 
 template <typename Ti, typename To>
 __global__ __launch_bounds__(kScanBlock) void k_scan_final(const Ti *__restrict__ in,
-                                                           int64_t stride, int64_t n,
+                                                           int64_t stride, Ti mask, int64_t n,
                                                            const To *__restrict__ part,
-                                                           To *__restrict__ out)
+                                                           To *out, const Ti *compact)
 {
     __shared__ To tile[kScanTile];
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     for (int r = 0; r < kScanItems; ++r) {
         int i = r * kScanBlock + threadIdx.x;
         int64_t e = base + i;
-        tile[i] = e < n ? (To)in[e * stride] : (To)0;
+        tile[i] = e < n ? (To)(compact ? compact[2 * base + i] : (in[e * stride] & mask)) : (To)0;
     }
-    __syncthreads();
+    __syncthreads();  // the tile's packed values are read before its outputs overwrite them
     To v[kScanItems];
     To s = 0;
 #pragma unroll
@@ -539,8 +548,8 @@ size_t scan_ws_bytes(int64_t n)
 }
 
 template <typename Ti, typename To>
-static hipError_t scan_impl(const Ti *in, int64_t stride, To *out, int64_t n, To *total, void *ws,
-                            hipStream_t s)
+static hipError_t scan_impl(const Ti *in, int64_t stride, Ti mask, To *out, int64_t n, To *total,
+                            void *ws, hipStream_t s)
 {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     To *part = (To *)ws;
@@ -548,24 +557,27 @@ static hipError_t scan_impl(const Ti *in, int64_t stride, To *out, int64_t n, To
         if (total) return hipMemsetAsync(total, 0, sizeof(To), s);
         return hipSuccess;
     }
+    // strided input: its values packed into the output's own tiles (To is
+    // twice Ti's width) by the first pass
+    Ti *compact = (stride != 1 && sizeof(To) == 2 * sizeof(Ti)) ? (Ti *)out : nullptr;
     hipLaunchKernelGGL((k_scan_reduce<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in,
-                       stride, n, part);
+                       stride, mask, n, part, compact);
     hipLaunchKernelGGL((k_scan_partials<To>), dim3(1), dim3(kScanBlock), 0, s, part, nb, total);
     hipLaunchKernelGGL((k_scan_final<Ti, To>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in,
-                       stride, n, part, out);
+                       stride, mask, n, part, out, (const Ti *)compact);
     return hipGetLastError();
 }
 
-hipError_t scan_u32_to_i64(const uint32_t *in, int64_t stride, int64_t *out, int64_t n,
-                           int64_t *total, void *ws, hipStream_t s)
+hipError_t scan_u32_to_i64(const uint32_t *in, int64_t stride, uint32_t mask, int64_t *out,
+                           int64_t n, int64_t *total, void *ws, hipStream_t s)
 {
-    return scan_impl<uint32_t, int64_t>(in, stride, out, n, total, ws, s);
+    return scan_impl<uint32_t, int64_t>(in, stride, mask, out, n, total, ws, s);
 }
 
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *ws,
                     hipStream_t s)
 {
-    return scan_impl<uint32_t, uint32_t>(in, 1, out, n, total, ws, s);
+    return scan_impl<uint32_t, uint32_t>(in, 1, ~0u, out, n, total, ws, s);
 }
 
 // One-sweep workspace: ghist[4][256], tile counters[64], status[4][nb][256].
