@@ -181,16 +181,18 @@ __device__ __forceinline__ ARange a_ranges(const Grid &g, double ra, double dec,
     return rg;
 }
 
-// Invalid rows (already reported through k_prep_a's flag) are given the
-// position (0, 0) and, for ellipses, a 1" circle, so every later loop stays
-// bounded even before the host sees the error.
+// Sorted A position i: its coordinates, candidate ranges and ellipse frame.
+// rows (the sort's values) stay the sorted sources' idxA list. Invalid rows
+// (already reported through k_prep_a's flag) are given the position (0, 0)
+// and, for ellipses, a 1" circle, so every later loop stays bounded even
+// before the host sees the error.
 template <int SHAPE>
-__global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__restrict__ packed,
+__global__ void k_gather_a(uint32_t *__restrict__ rows, const double2 *__restrict__ packed,
                            int64_t n,
                            const double *__restrict__ sa, const double *__restrict__ sb,
                            const double *__restrict__ pa, double pa_zero, int pa_sense,
                            double L_rad, Grid g, double reach_deg,
-                           double2 *__restrict__ arad, uint32_t *__restrict__ aidx,
+                           double2 *__restrict__ arad,
                            AEll *__restrict__ aell, AEllR *__restrict__ aellr,
                            ARange *__restrict__ arng, uint32_t wide_min, bool few,
                            uint32_t *__restrict__ wide, uint32_t *__restrict__ wide_n)
@@ -198,7 +200,10 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t row = rows[i];
-    if (row >= (uint64_t)n) row = 0;  // unreachable for a permutation; keeps reads in bounds
+    if (row >= (uint64_t)n) {  // unreachable for a permutation; keeps every later use in bounds
+        row = 0;
+        rows[i] = 0;
+    }
     const double2 rd = packed[row];
     double r = rd.x, d = rd.y;
     bool ok = isfinite(r) && isfinite(d) && r >= 0.0 && r < 360.0 && fabs(d) <= 90.0;
@@ -218,7 +223,6 @@ __global__ void k_gather_a(const uint32_t *__restrict__ rows, const double2 *__r
         P = 0.0;
     }
     arad[i] = make_double2(r, d);
-    aidx[i] = row;
     bool multi;
     ARange rg = a_ranges(g, r, d, SHAPE == C3X_CIRCLE ? reach_deg : area_reach_deg(SHAPE, A, B),
                          multi);
@@ -834,11 +838,14 @@ __device__ __forceinline__ void match_row(const MatchArgs &m, uint32_t i,
         m.rec[a.idx] = r;
         if (side) m.best2[a.idx] = (int32_t)bidx;
         if (MODE == 2) placed += min(cnt, (uint32_t)kTab);
-        const double terr = PREC == C3X_FP64 ? c2_err<C3X_FP64>(sqrt(b2), Lr)
-                            : (BATCH ? c2_err<C3X_MIXED>(sqrt(b2), Lr) : chord_err(sqrt(b2), Lr));
-        if (cnt >= 2 && b2 - b1 <= (4.0 + m.tie_widen) * terr) {
-            uint32_t slot = atomicAdd(m.tie_n, 1u);
-            if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
+        if (cnt >= 2) {  // a near tie: the two best chords within 4 error bounds
+            const double c = sqrt(b2);
+            const double terr = PREC == C3X_FP64 ? c2_err<C3X_FP64>(c, Lr)
+                                : (BATCH ? c2_err<C3X_MIXED>(c, Lr) : chord_err(c, Lr));
+            if (b2 - b1 <= (4.0 + m.tie_widen) * terr) {
+                uint32_t slot = atomicAdd(m.tie_n, 1u);
+                if (slot < m.tie_cap) m.tie[slot] = make_uint2(i, a.idx);
+            }
         }
     }
 }
@@ -2125,7 +2132,6 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     double2 *arad = tmp.get_n<double2>(nA);
     double2 *packed = tmp.get_n<double2>(nA);
     ARange *arng = tmp.get_n<ARange>(nA);
-    uint32_t *aidx = tmp.get_n<uint32_t>(nA);
     int32_t *best2 = tmp.get_n<int32_t>(nA);
     RowRec *rec = tmp.get_n<RowRec>(nA);
     AEll *aell = nullptr;
@@ -2135,7 +2141,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         aellr = tmp.get_n<AEllR>(nA);
         if (!aell || !aellr) return fail(C3X_ENOMEM, "A buffers");
     }
-    if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !packed || !aidx ||
+    if (!keys || !rows || !ktmp || !rtmp || !ws || !ctr || !c64 || !arad || !packed ||
         !best2 || !rec || !arng)
         return fail(C3X_ENOMEM, "A buffers");
     R->nA = nA;
@@ -2158,7 +2164,9 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     HIPCHK(radix_sort_pairs_bits(keys, rows, ktmp, rtmp, nA, a_lo, ix->plan.key_bits, ws, s,
                                  &in_tmp, /*vals_are_index=*/true, onesweep ? ctr + 11 : nullptr),
            "A sort");
+    // the sorted rows are the sorted sources' idxA (the gather clamps them)
     uint32_t *srows = in_tmp ? rtmp : rows;
+    const uint32_t *aidx = srows;
     // rows with at least wide_min candidates (or a window walked cell by
     // cell) are counted by one wavefront each; C3X_WIDE_MIN=0 turns it off
     uint32_t wide_min = kWideMin;
@@ -2171,7 +2179,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
 #define C3X_GATHER(SH)                                                                            \
     hipLaunchKernelGGL(k_gather_a<SH>, dim3(nblk(nA, 256)), dim3(256), 0, s, srows, packed, nA, sa, \
                        sb, pa, area->pa_zero_deg, area->pa_sense, ix->plan.L_rad, ix->grid, reach,  \
-                       arad, aidx, aell, aellr, arng, wide_min, few, wide, ctr + 8)
+                       arad, aell, aellr, arng, wide_min, few, wide, ctr + 8)
         if (shape == C3X_CIRCLE) C3X_GATHER(C3X_CIRCLE);
         else if (shape == C3X_ELLIPSE) C3X_GATHER(C3X_ELLIPSE);
         else C3X_GATHER(C3X_RECT);
