@@ -1622,8 +1622,8 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
 // single pass filled the records) and at offset off + k of its segment
 // otherwise. A short segment (<= kShortSeg) is finished here: the
 // canonical position of each match is its rank by idxB (unique in a
-// segment). A longer one has its record's matches copied into the segment,
-// which k_seg_lds then finishes.
+// segment). A longer one has its record's match copied into the segment
+// and is listed (seg_n, seg_list) for k_seg_lds, which finishes it.
 __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *__restrict__ off,
                            const RowRec *__restrict__ rec, const int32_t *__restrict__ best2,
                            int use_rec, PairTmp *__restrict__ tmp,
@@ -1631,7 +1631,8 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
                            int32_t *__restrict__ best_idx,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                            double *__restrict__ os, double *__restrict__ bsep,
-                           uint32_t *__restrict__ err, int defer)
+                           uint32_t *__restrict__ err, int defer, uint32_t *__restrict__ seg_n,
+                           uint32_t *__restrict__ seg_list, uint32_t seg_cap)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nA) return;
@@ -1653,8 +1654,10 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
     x0.idxB = r.b0;
     x0.j = 0;
     x0.sep = r.c0;
-    if (len > kShortSeg) {
+    if (len > kShortSeg) {  // the record's match joins the segment; listed for k_seg_lds
         if (nt > 0) tmp[o] = x0;
+        const uint32_t slot = atomicAdd(seg_n, 1u);  // (long segments are few)
+        if (slot < seg_cap) seg_list[slot] = (uint32_t)a;
         return;
     }
     // canonical position of a match: its rank by idxB (unique in a row)
@@ -1712,18 +1715,7 @@ __global__ void k_best_sep(int64_t n, int64_t nB, const RowRec *__restrict__ rec
 
 // ---------------------------------------------------------------------------- long segments
 
-__global__ void k_seg_list(const int64_t *__restrict__ off, int64_t n, uint32_t *__restrict__ cnt,
-                           uint32_t *__restrict__ list, uint32_t cap)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    if (off[t + 1] - off[t] > kShortSeg) {
-        uint32_t s = atomicAdd(cnt, 1u);
-        if (s < cap) list[s] = (uint32_t)t;
-    }
-}
-
-// Segments longer than kShortSeg, one workgroup at a time over the list
+// Segments longer than kShortSeg (listed by the finalize kernel), one workgroup at a time over the list
 // (the grid does not depend on the list's length): segments of up to
 // kSegLds matches are sorted by idxB in LDS (bitonic network over
 // idxB << 32 | position; idxB is unique in a segment) and written out in
@@ -1841,9 +1833,7 @@ static void finish_segments(const FinishArgs &f, hipStream_t s)
     if (f.nA == 0) return;
     hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.pcap,
                        f.off, f.rec, f.best2, f.use_rec, f.tmp, f.coordA, f.coordB, f.best_idx,
-                       f.oa, f.ob, f.os, f.bsep, f.err, f.defer);
-    hipLaunchKernelGGL(k_seg_list, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.off, f.nA, f.seg_n,
-                       f.list, f.cap);
+                       f.oa, f.ob, f.os, f.bsep, f.err, f.defer, f.seg_n, f.list, f.cap);
     hipLaunchKernelGGL(k_seg_lds, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list, f.cap,
                        f.tmp, f.nB, f.pcap, f.coordA, f.coordB, f.rec, f.best2, f.oa, f.ob, f.os,
                        f.bsep, f.seg_n + 1, f.huge, f.err, f.defer);
