@@ -91,6 +91,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-threads", type=int, default=0)
     p.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    p.add_argument("--separate-calls", action="store_true",
+                   help="a step as c3x_build_index then c3x_match (default: c3x_cross_match, "
+                        "which keys and sorts A while B's index is built)")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="also run one plain device copy of this size (to scale HBM counters)")
     return p.parse_args()
@@ -104,14 +107,23 @@ def mean(xs):
     return sum(xs) / max(1, len(xs))
 
 
-def run_path(c3x, torch, tens, cat, precision, steps, warmup, area_kw, frame, mode):
+def run_path(c3x, torch, tens, cat, precision, steps, warmup, area_kw, frame, mode,
+             separate=False):
+    """One step: the index over B and the match of A, as one c3x_cross_match
+    call (A keyed and sorted while B's index is built) or, with ``separate``,
+    as c3x_build_index then c3x_match."""
     raA, decA, raB, decB = tens
     last = {}
 
     def step():
-        ix = c3x.build_index(raB, decB, frame=frame, reach_hint_arcsec=cat.reach_arcsec(),
-                             precision=precision)
-        r = c3x.match(ix, raA, decA, frame=frame, mode=mode, **area_kw)
+        if separate:
+            ix = c3x.build_index(raB, decB, frame=frame, reach_hint_arcsec=cat.reach_arcsec(),
+                                 precision=precision)
+            r = c3x.match(ix, raA, decA, frame=frame, mode=mode, **area_kw)
+        else:
+            r, ix = c3x.cross_match(raB, decB, raA, decA, frame=frame,
+                                    reach_hint_arcsec=cat.reach_arcsec(), precision=precision,
+                                    mode=mode, keep_index=True, **area_kw)
         last["index"] = ix.stats()
         ix.free()
         last["r"] = r
@@ -292,7 +304,8 @@ def single_config(a, c3x, torch, np, name):
     order = {"both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"]}[a.precision]
     for pname in order:
         prec = c3x.MIXED if pname == "mixed" else c3x.FP64
-        ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup, area_kw, frame, mode)
+        ms, r, ks = run_path(c3x, torch, tens, cat, prec, a.steps, a.warmup, area_kw, frame, mode,
+                             separate=a.separate_calls)
         paths[pname] = path_summary(cat, ms, r, ks, 16 if pname == "mixed" else 32,
                                     bool(mode & c3x.BEST))
         if mode & c3x.ALL and not a.core_only:
@@ -364,6 +377,7 @@ def single_config(a, c3x, torch, np, name):
         "config": {"workload": workloads[name], "nA": cat.nA, "nB": cat.nB,
                    "scale": a.scale, "parallelism": "single GPU"},
         "pair_tests_per_s": round(head["pair_tests_per_s"], 1),
+        "step_calls": ("c3x_build_index + c3x_match" if a.separate_calls else "c3x_cross_match"),
         "paths": paths,
         "roofline": roofline,
         "cpu_baseline": cpu,

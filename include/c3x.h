@@ -207,6 +207,23 @@ c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const double *de
                      int64_t nA, c3x_frame frame, const c3x_area *area, unsigned mode,
                      const c3x_opts *opts, c3x_result **out);
 
+/* The whole cross-match of Section 2 in one call: c3x_build_index over
+ * catalogue B (raB/decB, nB, frameB, reach_hint_arcsec) and c3x_match of
+ * catalogue A (raA/decA, nA, frameA, area, mode) against it, with the same
+ * checks, errors and outputs as the two calls in a row. The difference is
+ * only in time: catalogue A is keyed and sorted on a second stream while
+ * B's index is built on opts->stream, and the two meet where A's candidate
+ * ranges are taken from the index. The second stream (default priority,
+ * not synchronising with the null stream) is the library's own, one per
+ * device, kept to the end of the process; calls that overlap on one device
+ * share it and run their A halves one after the other. index_out (may be NULL: the index is freed) receives the index
+ * for later c3x_match calls. Synchronises opts->stream; *out and *index_out
+ * are left NULL on an error. */
+c3x_status c3x_cross_match(const double *raB, const double *decB, int64_t nB, c3x_frame frameB,
+                           double reach_hint_arcsec, const double *raA, const double *decA,
+                           int64_t nA, c3x_frame frameA, const c3x_area *area, unsigned mode,
+                           const c3x_opts *opts, c3x_index **index_out, c3x_result **out);
+
 /* Sizes of a result: number of pairs and of A rows. */
 c3x_status c3x_result_sizes(const c3x_result *r, int64_t *n_pairs, int64_t *nA);
 

@@ -29,6 +29,7 @@ from ._binding import (  # noqa: F401
     MatchResult,
     JOIN_PARTS,
     build_index,
+    cross_match,
     exact_match,
     frame_convert,
     frame_matrix,

@@ -106,6 +106,10 @@ def lib():
                                        ctypes.POINTER(dbl), i32, ctypes.c_uint,
                                        ctypes.POINTER(Opts), ctypes.POINTER(vp)]
     L.c3x_match_concentric.restype = ctypes.c_int
+    L.c3x_cross_match.argtypes = [vp, vp, i64, ctypes.c_int, dbl, vp, vp, i64, ctypes.c_int,
+                                  ctypes.POINTER(Area), ctypes.c_uint, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.c3x_cross_match.restype = ctypes.c_int
     L.c3x_result_mutual.argtypes = [vp, vp, vp, vp, vp, vp, pvp, pvp, pvp, ctypes.POINTER(i64),
                                     pvp]
     L.c3x_result_mutual.restype = ctypes.c_int
@@ -307,6 +311,48 @@ def match(index: Index, ra, dec, frame: int = EQUATORIAL, shape: int = CIRCLE,
     check(lib().c3x_match(index.handle, ra.data_ptr(), dec.data_ptr(), ra.shape[0], int(frame),
                           ctypes.byref(ar), int(mode), ctypes.byref(o), ctypes.byref(h)))
     return _views(h, ra.device)
+
+
+def cross_match(raB, decB, raA, decA, frame: int = EQUATORIAL, frameA: int = None,
+                reach_hint_arcsec: float = 0.0, precision: int = FP64, cell_arcsec: float = 0.0,
+                shape: int = CIRCLE, radius_arcsec: float = 1.0, a=None, b=None, pa=None,
+                pa_zero_deg: float = 0.0, pa_sense: int = 1, mode: int = ALL | BEST,
+                keep_index: bool = False, stream=None):
+    """The index over catalogue B and the match of catalogue A in one call
+    (c3x_cross_match): what ``build_index`` then ``match`` return, with A
+    keyed and sorted while B's index is built. ``frame`` is B's frame
+    (``frameA``: A's, default the same). Returns the MatchResult, or
+    (MatchResult, Index) with ``keep_index``."""
+    raB = _dev_f64(raB, "raB")
+    decB = _dev_f64(decB, "decB")
+    ra = _dev_f64(raA, "raA")
+    dec = _dev_f64(decA, "decA")
+    if raB.shape != decB.shape or ra.shape != dec.shape:
+        raise ValueError("ra and dec differ in length")
+    ar = Area(shape=int(shape), radius_arcsec=float(radius_arcsec), pa_zero_deg=float(pa_zero_deg),
+              pa_sense=int(pa_sense))
+    if shape in (ELLIPSE, RECT):
+        for nm, v in (("a", a), ("b", b), ("pa", pa)):
+            v = _dev_f64(v, nm)
+            if v.shape != ra.shape:
+                raise ValueError(f"{nm} must have one entry per A row")
+        ar.semi_major_arcsec = a.data_ptr()
+        ar.semi_minor_arcsec = b.data_ptr()
+        ar.pa_deg = pa.data_ptr()
+    o = Opts(precision=int(precision), cell_arcsec=float(cell_arcsec), tile=0,
+             stream=_stream_ptr(stream))
+    hi = ctypes.c_void_p()
+    h = ctypes.c_void_p()
+    fa = frame if frameA is None else frameA
+    check(lib().c3x_cross_match(raB.data_ptr(), decB.data_ptr(), raB.shape[0], int(frame),
+                                float(reach_hint_arcsec), ra.data_ptr(), dec.data_ptr(),
+                                ra.shape[0], int(fa), ctypes.byref(ar), int(mode),
+                                ctypes.byref(o), ctypes.byref(hi) if keep_index else None,
+                                ctypes.byref(h)))
+    r = _views(h, ra.device)
+    if keep_index:
+        return r, Index(hi, raB.shape[0], frame, precision)
+    return r
 
 
 def frame_matrix(src: int, dst: int):

@@ -175,6 +175,70 @@ struct c3x_index {
     c3x_stats stats;
 };
 
+namespace c3x {
+
+// An index build enqueued on its stream and not yet checked: index_build_begin
+// validates and plans, allocates and enqueues every kernel;
+// index_build_end waits for them, checks the rows and the sorts and hands
+// the index over (or frees it; kSortGaveUp when a one-sweep sort gave up).
+// c3x_build_index runs the two in a row; c3x_cross_match enqueues the A
+// preparation on a second stream between them.
+struct IndexBuild {
+    c3x_index *ix = nullptr;
+    hipStream_t s;
+    Arena tmp;                // the kernels' working buffers
+    Timer tm;
+    uint32_t *bad = nullptr;  // [2]: first bad row, one-sweep give-up
+    hipEvent_t grid_ready = nullptr;  // recorded on s once the grid is on the device
+    hipError_t e = hipSuccess;
+    explicit IndexBuild(hipStream_t st) : s(st), tmp(st), tm(st) {}
+    ~IndexBuild()
+    {
+        delete ix;  // an index not handed over
+        if (grid_ready) (void)hipEventDestroy(grid_ready);
+    }
+};
+c3x_status index_build_begin(const double *ra_deg, const double *dec_deg, int64_t nB,
+                             c3x_frame frame, double reach_hint_arcsec, const c3x_opts *opts,
+                             bool onesweep, IndexBuild &b);
+c3x_status index_build_end(IndexBuild &b, c3x_index **out);
+
+// Work forked from stream s onto a second stream a: the constructor makes a
+// wait for what s has queued so far (or, given `after`, for that event of
+// s), join() makes s wait for what a has queued since, and the destructor
+// waits for a (an early error return must not free buffers that a's
+// kernels still use). a == s: all of it nothing.
+struct StreamFork {
+    hipStream_t s, a;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    StreamFork(hipStream_t s_, hipStream_t a_, hipEvent_t after = nullptr) : s(s_), a(a_)
+    {
+        if (a == s) return;
+        e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+        if (e == hipSuccess && !after) e = hipEventRecord(ev[0], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(a, after ? after : ev[0], 0);
+    }
+    hipError_t join()
+    {
+        if (a == s || e != hipSuccess) return e;
+        e = hipEventRecord(ev[1], a);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev[1], 0);
+        return e;
+    }
+    ~StreamFork()
+    {
+        if (a != s) (void)hipStreamSynchronize(a);
+        for (auto &x : ev)
+            if (x) (void)hipEventDestroy(x);
+    }
+    StreamFork(const StreamFork &) = delete;
+    StreamFork &operator=(const StreamFork &) = delete;
+};
+
+}  // namespace c3x
+
 struct c3x_result {
     int device;
     int64_t n_pairs;

@@ -254,9 +254,11 @@ using namespace c3x;
 
 // onesweep: large sorts may take the one-sweep schedule (kSortGaveUp if its
 // look-back gave up; the caller then builds again without it).
-static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, int64_t nB,
-                                   c3x_frame frame, double reach_hint_arcsec,
-                                   const c3x_opts *opts, bool onesweep, c3x_index **out)
+namespace c3x {
+
+c3x_status index_build_begin(const double *ra_deg, const double *dec_deg, int64_t nB,
+                             c3x_frame frame, double reach_hint_arcsec, const c3x_opts *opts,
+                             bool onesweep, IndexBuild &b)
 {
     if (nB < 0) return fail(C3X_EINVAL, "nB < 0");
     if (nB > 2147483647LL) return fail(C3X_ERANGE, "nB above 2^31 - 1");
@@ -270,10 +272,11 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
         return fail(C3X_EINVAL, "bad precision");
     if (!(o.cell_arcsec >= 0.0) || !isfinite(o.cell_arcsec))
         return fail(C3X_EINVAL, "cell_arcsec must be finite and >= 0");
-    hipStream_t s = (hipStream_t)o.stream;
+    hipStream_t s = b.s;
 
     c3x_index *ix = new (std::nothrow) c3x_index();
     if (!ix) return fail(C3X_ENOMEM, "host allocation");
+    b.ix = ix;
     (void)hipGetDevice(&ix->device);
     ix->frame = frame;
     ix->precision = o.precision;
@@ -281,19 +284,15 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     ix->reach_hint_arcsec = reach_hint_arcsec;
     memset(&ix->stats, 0, sizeof(ix->stats));
     c3x_status st = plan_grid(ix->plan, nB, reach_hint_arcsec, o.cell_arcsec);
-    if (st != C3X_OK) {
-        delete ix;
-        return st;
-    }
-    Timer tm(s);
-    tm.mark();
+    if (st != C3X_OK) return st;
+    b.tm.mark();
     st = upload_grid(ix, s);
-    if (st != C3X_OK) {
-        (void)hipStreamSynchronize(s);
-        delete ix;
-        return st;
-    }
-    Arena tmp(s);
+    if (st != C3X_OK) return st;
+    // work that needs only the grid may start here on another stream
+    if (hipEventCreateWithFlags(&b.grid_ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(b.grid_ready, s) != hipSuccess)
+        return fail(C3X_EDEVICE, "event");
+    Arena &tmp = b.tmp;
     int64_t n = nB;
     uint32_t *keys = ix->mem.get_n<uint32_t>(n);
     uint32_t *rows = tmp.get_n<uint32_t>(n);
@@ -301,6 +300,7 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     uint32_t *rtmp = tmp.get_n<uint32_t>(n);
     void *ws = tmp.get(radix_ws_bytes(n));
     uint32_t *bad = tmp.get_n<uint32_t>(2);  // first bad row; sort give-up
+    b.bad = bad;
     // the coordinates in input order: the gathers' source, then kept by the
     // index (the band recheck reads them through the payload's row)
     double2 *packed = ix->mem.get_n<double2>(n);
@@ -321,11 +321,8 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     uint3 *gaps = tmp.get_n<uint3>((int64_t)gap_cap + big_cap);
     uint32_t *n_gaps = tmp.get_n<uint32_t>(2);
     if (!keys || !rows || !ktmp || !rtmp || !ws || !bad || !packed || !dir || !gaps || !n_gaps ||
-        (!p64 && !(p32 && res))) {
-        (void)hipStreamSynchronize(s);
-        delete ix;
+        (!p64 && !(p32 && res)))
         return fail(C3X_ENOMEM, "index buffers");
-    }
     hipError_t e = hipMemsetAsync(bad, 0xff, sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(bad + 1, 0, sizeof(uint32_t), s);
     Grid g = ix->grid;
@@ -359,32 +356,7 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
                            big_cap, dir);
         e = hipGetLastError();
     }
-    tm.mark();
-    uint32_t bad_h[2] = {0xffffffffu, 0u};
-    uint32_t *hbad = (uint32_t *)pinned_stage(64);
-    if (!hbad) hbad = bad_h;
-    hbad[0] = 0xffffffffu;
-    hbad[1] = 0u;
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hbad, bad, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    const uint32_t sort_gave_up = hbad[1];
-    bad_h[0] = hbad[0];
-    if (e != hipSuccess) {
-        (void)hipStreamSynchronize(s);
-        delete ix;
-        return fail_hip(e, "c3x_build_index");
-    }
-    if (sort_gave_up) {
-        delete ix;
-        return kSortGaveUp;
-    }
-    if (bad_h[0] != 0xffffffffu) {
-        delete ix;
-        return fail(C3X_EINVAL, "catalogue B row %u: coordinate outside RA [0,360), |Dec| <= 90 "
-                                "or not finite", bad_h[0]);
-    }
+    b.tm.mark();
     ix->keys = keys;
     ix->pay64 = p64;
     ix->pay32 = p32;
@@ -393,15 +365,60 @@ static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, 
     ix->grid.keys = keys;
     ix->grid.dir = dir;
     ix->grid.nB = (int32_t)n;
+    ix->stats.precision = (int32_t)o.precision;
+    b.e = e;
+    if (e != hipSuccess) return fail_hip(e, "c3x_build_index");
+    return C3X_OK;
+}
+
+c3x_status index_build_end(IndexBuild &b, c3x_index **out)
+{
+    hipError_t e = b.e;
+    uint32_t bad_h[2] = {0xffffffffu, 0u};
+    uint32_t *hbad = (uint32_t *)pinned_stage(64);
+    if (!hbad) hbad = bad_h;
+    hbad[0] = 0xffffffffu;
+    hbad[1] = 0u;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hbad, b.bad, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, b.s);
+    if (e == hipSuccess) e = hipStreamSynchronize(b.s);
+    const uint32_t sort_gave_up = hbad[1];
+    bad_h[0] = hbad[0];
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(b.s);
+        return fail_hip(e, "c3x_build_index");
+    }
+    if (sort_gave_up) return kSortGaveUp;
+    if (bad_h[0] != 0xffffffffu)
+        return fail(C3X_EINVAL, "catalogue B row %u: coordinate outside RA [0,360), |Dec| <= 90 "
+                                "or not finite", bad_h[0]);
+    c3x_index *ix = b.ix;
     c3x_stats &S = ix->stats;
-    S.n_b = n;
+    S.n_b = ix->nB;
     S.n_cells = (int64_t)ix->plan.ncells;
     S.cell_arcsec = ix->plan.cell_arcsec;
-    S.ms_index = tm.ms(0, 1);
+    S.ms_index = b.tm.ms(0, 1);
     S.ms_total = S.ms_index;
-    S.precision = (int32_t)o.precision;
+    b.ix = nullptr;
     *out = ix;
     return C3X_OK;
+}
+
+}  // namespace c3x
+
+static c3x_status build_index_impl(const double *ra_deg, const double *dec_deg, int64_t nB,
+                                   c3x_frame frame, double reach_hint_arcsec,
+                                   const c3x_opts *opts, bool onesweep, c3x_index **out)
+{
+    IndexBuild b(opts ? (hipStream_t)opts->stream : nullptr);
+    c3x_status st = index_build_begin(ra_deg, dec_deg, nB, frame, reach_hint_arcsec, opts,
+                                      onesweep, b);
+    if (st != C3X_OK) {
+        (void)hipStreamSynchronize(b.s);
+        return st;
+    }
+    return index_build_end(b, out);
 }
 
 extern "C" c3x_status c3x_build_index(const double *ra_deg, const double *dec_deg, int64_t nB,

@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -2095,9 +2096,13 @@ constexpr uint64_t kOvMaxBytes = 4ull << 30;    // and never more than this
 // onesweep: large sorts may take the one-sweep schedule; kSortGaveUp when
 // one of them gave up its look-back (the caller then redoes the call
 // without it).
+// s_keys (may be s): the stream that keys and sorts catalogue A. ib: an index
+// still being built on s (c3x_cross_match): it is checked, and handed to
+// *ix_built, once A is sorted.
 static c3x_status match_impl(const c3x_index *ix, const double *ra, const double *dec, int64_t nA,
                              const c3x_area *area, unsigned mode, hipStream_t s, bool onesweep,
-                             c3x_result *R)
+                             c3x_result *R, hipStream_t s_keys = nullptr, IndexBuild *ib = nullptr,
+                             c3x_index **ix_built = nullptr)
 {
     const int shape = area->shape;
     const int prec = ix->precision;
@@ -2138,11 +2143,17 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     R->best_idx = R->mem.get_n<int32_t>(nA);
     R->best_sep = R->mem.get_n<double>(nA);
     if (!R->best_idx || !R->best_sep) return fail(C3X_ENOMEM, "best buffers");
-    HIPCHK(hipMemsetAsync(cblk, 0, kCtrBytes, s), "memset");
-    HIPCHK(hipMemsetAsync(ctr, 0xff, sizeof(uint32_t), s), "memset");
+    // catalogue A keyed and sorted on its own stream when the index is still
+    // being built on s (from the moment its grid is on the device; the two
+    // only meet at the gather)
+    StreamFork fork(s, s_keys ? s_keys : s, ib ? ib->grid_ready : nullptr);
+    HIPCHK(fork.e, "stream fork");
+    const hipStream_t s_a = fork.a;
+    HIPCHK(hipMemsetAsync(cblk, 0, kCtrBytes, s_a), "memset");
+    HIPCHK(hipMemsetAsync(ctr, 0xff, sizeof(uint32_t), s_a), "memset");
     const double *sa = area->semi_major_arcsec, *sb = area->semi_minor_arcsec, *pa = area->pa_deg;
     if (nA > 0)
-        hipLaunchKernelGGL(k_prep_a, dim3(nblk(nA, 256)), dim3(256), 0, s, ra, dec, nA, ix->grid,
+        hipLaunchKernelGGL(k_prep_a, dim3(nblk(nA, 256)), dim3(256), 0, s_a, ra, dec, nA, ix->grid,
                            shape, sa, sb, pa, keys, packed, ctr);
     HIPCHK(hipGetLastError(), "A keys");
     int in_tmp = 0;
@@ -2151,9 +2162,14 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     // and no result depends on the order of A
     const int a_lo = std::max(0, ix->plan.key_bits - a_key_bits());
     // ctr[11]: set when a one-sweep sort gave up (read back after the count)
-    HIPCHK(radix_sort_pairs_bits(keys, rows, ktmp, rtmp, nA, a_lo, ix->plan.key_bits, ws, s,
+    HIPCHK(radix_sort_pairs_bits(keys, rows, ktmp, rtmp, nA, a_lo, ix->plan.key_bits, ws, s_a,
                                  &in_tmp, /*vals_are_index=*/true, onesweep ? ctr + 11 : nullptr),
            "A sort");
+    HIPCHK(fork.join(), "stream join");
+    if (ib) {  // the index: its rows and its sort checked before anything reads it
+        const c3x_status st = index_build_end(*ib, ix_built);
+        if (st != C3X_OK) return st;
+    }
     // the sorted rows are the sorted sources' idxA (the gather clamps them)
     uint32_t *srows = in_tmp ? rtmp : rows;
     const uint32_t *aidx = srows;
@@ -2697,14 +2713,12 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
     return C3X_OK;
 }
 
-extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const double *dec_deg,
-                                int64_t nA, c3x_frame frame, const c3x_area *area, unsigned mode,
-                                const c3x_opts *opts, c3x_result **out)
+// Checks of catalogue A, its area and the mode, shared by c3x_match and
+// c3x_cross_match.
+static c3x_status check_match_args(const double *ra_deg, const double *dec_deg, int64_t nA,
+                                   c3x_frame frame, const c3x_area *area, unsigned mode)
 {
-    clear_error();
-    if (!out) return fail(C3X_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!ix || !area) return fail(C3X_EINVAL, "NULL index or area");
+    if (!area) return fail(C3X_EINVAL, "NULL area");
     if (nA < 0) return fail(C3X_EINVAL, "nA < 0");
     if (nA > 2147483647LL) return fail(C3X_ERANGE, "nA above 2^31 - 1");
     if (nA > 0 && (!ra_deg || !dec_deg)) return fail(C3X_EINVAL, "NULL coordinate array");
@@ -2725,15 +2739,37 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
     } else {
         return fail(C3X_EINVAL, "bad shape");
     }
-    if (opts && opts->precision != ix->precision)
-        return fail(C3X_EINVAL, "precision differs from the index's");
-    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    return C3X_OK;
+}
+
+static c3x_result *new_result(unsigned mode, int64_t nB)
+{
     c3x_result *R = new (std::nothrow) c3x_result();
-    if (!R) return fail(C3X_ENOMEM, "host allocation");
+    if (!R) return nullptr;
     (void)hipGetDevice(&R->device);
     memset(&R->stats, 0, sizeof(R->stats));
     R->mode = mode;
-    R->nB = ix->nB;
+    R->nB = nB;
+    return R;
+}
+
+extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const double *dec_deg,
+                                int64_t nA, c3x_frame frame, const c3x_area *area, unsigned mode,
+                                const c3x_opts *opts, c3x_result **out)
+{
+    clear_error();
+    if (!out) return fail(C3X_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ix || !area) return fail(C3X_EINVAL, "NULL index or area");
+    {
+        const c3x_status cs = check_match_args(ra_deg, dec_deg, nA, frame, area, mode);
+        if (cs != C3X_OK) return cs;
+    }
+    if (opts && opts->precision != ix->precision)
+        return fail(C3X_EINVAL, "precision differs from the index's");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    c3x_result *R = new_result(mode, ix->nB);
+    if (!R) return fail(C3X_ENOMEM, "host allocation");
     // catalogue A in the other frame: converted into the index's frame by the
     // fixed FP64 rule (orientations turned with it); the converted doubles
     // are A's inputs
@@ -2754,12 +2790,8 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
         // table schedule (which never waits), into a fresh result
         (void)hipStreamSynchronize(s);
         delete R;
-        R = new (std::nothrow) c3x_result();
+        R = new_result(mode, ix->nB);
         if (!R) return fail(C3X_ENOMEM, "host allocation");
-        (void)hipGetDevice(&R->device);
-        memset(&R->stats, 0, sizeof(R->stats));
-        R->mode = mode;
-        R->nB = ix->nB;
         st = match_impl(ix, ra_deg, dec_deg, nA, area, mode, s, false, R);
         R->stats.n_sort_retries = 1;
     }
@@ -2768,6 +2800,93 @@ extern "C" c3x_status c3x_match(const c3x_index *ix, const double *ra_deg, const
         delete R;
         return st;
     }
+    *out = R;
+    return C3X_OK;
+}
+
+// The stream that keys and sorts catalogue A in c3x_cross_match: one per
+// device, created on first use (default priority, not synchronising with
+// the null stream) and kept to the end of the process. Calls that overlap on
+// one device share it: their work on it runs one call after the other,
+// still ordered by each call's own events. Null when it cannot be created
+// (the call then runs both halves on its own stream).
+static hipStream_t keys_stream()
+{
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static hipStream_t streams[kDevices];
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        streams[dev] = nullptr;
+    }
+    return streams[dev];
+}
+
+extern "C" c3x_status c3x_cross_match(const double *raB, const double *decB, int64_t nB,
+                                      c3x_frame frameB, double reach_hint_arcsec,
+                                      const double *raA, const double *decA, int64_t nA,
+                                      c3x_frame frameA, const c3x_area *area, unsigned mode,
+                                      const c3x_opts *opts, c3x_index **index_out,
+                                      c3x_result **out)
+{
+    clear_error();
+    if (!out) return fail(C3X_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (index_out) *index_out = nullptr;
+    {
+        const c3x_status cs = check_match_args(raA, decA, nA, frameA, area, mode);
+        if (cs != C3X_OK) return cs;
+    }
+    if (frameB != C3X_EQUATORIAL && frameB != C3X_GALACTIC) return fail(C3X_EINVAL, "bad frame");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    // catalogue A in B's frame, as the match converts it
+    Arena conv(s);
+    c3x_area ar = *area;
+    c3x_status st = convert_catalogue_a((int)frameA, (int)frameB, nA, &raA, &decA, &ar, conv, s);
+    if (st != C3X_OK) return st;
+    c3x_index *ix = nullptr;
+    c3x_result *R = nullptr;
+    {
+        IndexBuild b(s);
+        st = index_build_begin(raB, decB, nB, frameB, reach_hint_arcsec, opts, true, b);
+        if (st == C3X_OK) {
+            R = new_result(mode, nB);
+            if (!R) st = fail(C3X_ENOMEM, "host allocation");
+        }
+        // A is keyed and sorted on the device's second stream while the index
+        // is built on s; without one, the two run one after the other
+        if (st == C3X_OK) {
+            hipStream_t s_keys = keys_stream();
+            if (s_keys == s) s_keys = nullptr;
+            st = match_impl(b.ix, raA, decA, nA, &ar, mode, s, true, R, s_keys, &b, &ix);
+        }
+        (void)hipStreamSynchronize(s);
+    }  // (an index not handed over is freed here, its kernels done)
+    if (st == kSortGaveUp) {
+        // a one-sweep sort gave up its look-back: the index build and the
+        // match again, one after the other, each redoing what gave up
+        delete R;
+        R = nullptr;
+        delete ix;
+        ix = nullptr;
+        st = c3x_build_index(raB, decB, nB, frameB, reach_hint_arcsec, opts, &ix);
+        if (st == C3X_OK) st = c3x_match(ix, raA, decA, nA, frameB, &ar, mode, opts, &R);
+        if (st == C3X_OK) R->stats.n_sort_retries = 1;
+    }
+    if (st != C3X_OK) {
+        delete R;
+        delete ix;
+        return st;
+    }
+    R->stats.ms_index = ix->stats.ms_index;
+    if (index_out) *index_out = ix;
+    else delete ix;
     *out = R;
     return C3X_OK;
 }

@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     for f in ("c3x_build_index", "c3x_match", "c3x_result_sizes", "c3x_result_copy",
               "c3x_result_views", "c3x_result_stats", "c3x_result_free", "c3x_index_free", "c3x_last_error",
               "c3x_version", "c3x_abi_version", "c3x_index_stats", "c3x_result_unmatched",
-              "c3x_match_concentric", "c3x_result_levels", "c3x_result_mutual"):
+              "c3x_match_concentric", "c3x_result_levels", "c3x_result_mutual",
+              "c3x_cross_match"):
         assert f in fns
 
 
@@ -67,6 +68,19 @@ def test_argument_errors_need_no_device(L):
                                   ctypes.byref(h2)) == b.EINVAL
     assert h2.value is None
     assert L.c3x_result_levels(None, None) == b.EINVAL
+    h3, h4 = ctypes.c_void_p(), ctypes.c_void_p()
+    assert L.c3x_cross_match(None, None, 0, 0, 1.0, None, None, 0, 0, ctypes.byref(area), 3,
+                             None, ctypes.byref(h3), None) == b.EINVAL  # out NULL
+    assert L.c3x_cross_match(None, None, -1, 0, 1.0, None, None, 0, 0, ctypes.byref(area), 3,
+                             None, ctypes.byref(h3), ctypes.byref(h4)) == b.EINVAL
+    assert b"nB < 0" in L.c3x_last_error()
+    assert L.c3x_cross_match(None, None, 0, 0, 1.0, None, None, 5, 0, ctypes.byref(area), 3,
+                             None, ctypes.byref(h3), ctypes.byref(h4)) == b.EINVAL
+    assert L.c3x_cross_match(None, None, 0, 0, 1.0, None, None, 0, 0, None, 3,
+                             None, ctypes.byref(h3), ctypes.byref(h4)) == b.EINVAL
+    assert L.c3x_cross_match(None, None, 0, 9, 1.0, None, None, 0, 0, ctypes.byref(area), 3,
+                             None, ctypes.byref(h3), ctypes.byref(h4)) == b.EINVAL
+    assert h3.value is None and h4.value is None
     L.c3x_result_free(None)  # a no-op
 
 
