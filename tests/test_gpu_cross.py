@@ -127,6 +127,21 @@ def test_one_sweep_give_up_is_redone(c3x, dev, precision, monkeypatch):
     assert r["stats"]["n_sort_retries"] == 1
 
 
+def test_on_a_caller_stream(c3x, dev):
+    """On a stream of the caller's (the second stream waits for the grid
+    uploaded on it): the same bytes as on the null stream."""
+    import torch
+    cat, _ = _case("cfg1")
+    want = _bytes(_cross(c3x, dev, cat, 1))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        tens = [_t(x, dev) for x in (cat.raB, cat.decB, cat.raA, cat.decA)]
+        r = c3x.cross_match(*tens, reach_hint_arcsec=cat.reach_arcsec(), precision=1,
+                            radius_arcsec=cat.radius_arcsec, stream=st)
+    st.synchronize()
+    assert _bytes(r) == want
+
+
 def test_empty_catalogues(c3x, dev):
     cat, _ = _case("cfg1")
     e = np.zeros(0)
