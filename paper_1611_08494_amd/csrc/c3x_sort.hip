@@ -3,7 +3,7 @@
 //
 // Sort: 8-bit digits, only as many passes as the key range needs. One
 // kernel first counts every pass's digits over the whole input (the keys are
-// read once for all passes). Each pass is then one launch over 4096-element
+// read once for all passes). Each pass is then one launch over 8192-element
 // tiles taken in order from a counter: a tile ranks its elements (each
 // wavefront ranks its quarter with ballots -- eight ballots match the lanes
 // that share a digit, mbcnt ranks them -- against its own digit counters),
@@ -274,7 +274,9 @@ __device__ __forceinline__ uint32_t st_read(const uint32_t *p)
 // a wrong order but no access out of bounds, and sets *fail. spin_limit 0
 // (a test setting) makes every tile but the first give up at once. A tile is
 // kSortBlock * ITEMS elements (longer tiles: longer runs per digit in the
-// scatter, fewer look-backs).
+// scatter, fewer look-backs). The tile passes through LDS twice, keys then
+// values, in one buffer: at 32 items 38 KB a workgroup, so the registers
+// (three wavefronts a SIMD) bound the workgroups a CU holds, not the LDS.
 template <int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
@@ -285,7 +287,9 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     constexpr int kTile = kSortBlock * ITEMS;
     constexpr int kPerWave = kTile / kWaves;  // 64 * ITEMS
     constexpr int kRounds = kPerWave / 64;    // ITEMS
-    __shared__ uint32_t sk[kTile], sv[kTile];
+    // one buffer stages the tile in digit order: its keys, then its values
+    // (38 KB of LDS a workgroup, four workgroups a CU)
+    __shared__ uint32_t sbuf[kTile];
     __shared__ uint32_t gbase[256], tstart[256];
     __shared__ uint32_t wc[kWaves][256];
     __shared__ uint32_t wsum[kWaves];
@@ -302,12 +306,11 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     if (tile >= (uint32_t)nb) return;  // the counter was not cleared: nothing is touched
     const int64_t tbase = (int64_t)tile * kTile;
     const int64_t wbase = tbase + (int64_t)wave * kPerWave + __lane_id();
-    uint32_t kk[kRounds], vv[kRounds], loc[kRounds];
+    uint32_t kk[kRounds], loc[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int64_t e = wbase + r * 64;
         kk[r] = e < n ? kin[e] : 0u;
-        vv[r] = e < n ? (vin ? vin[e] : (uint32_t)e) : 0u;  // no vin: the index
     }
     uint32_t *cnt = wc[wave];
 #pragma unroll
@@ -338,12 +341,36 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
         wc[w][tid] = acc;
         acc += t;
     }
+    // publish the tile's digit counts, stage its keys in digit order, then
+    // look back (the staging overlaps the predecessors' publishing)
     uint32_t *mine = status + (size_t)tile * 256 + tid;
-    uint32_t excl = 0;
-    if (tile == 0) {
-        st_publish(mine, kStInc | acc);
+    st_publish(mine, (tile == 0 ? kStInc : kStAgg) | acc);
+    tstart[tid] = block256_excl_scan(acc, wsum);
+    __syncthreads();
+    // loc becomes each element's place in the tile's digit order
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (wbase + r * 64 < n) {
+            const uint32_t d = (kk[r] >> shift) & 255u;
+            loc[r] += tstart[d] + cnt[d];
+            sbuf[loc[r]] = kk[r];
+        }
+    }
+    // the values (no vin: the element's index), loaded while the tile looks
+    // back; only they and the places stay live
+    uint32_t vv[kRounds];
+    if (vin) {
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const int64_t e = wbase + r * 64;
+            vv[r] = e < n ? vin[e] : 0u;
+        }
     } else {
-        st_publish(mine, kStAgg | acc);
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) vv[r] = (uint32_t)(wbase + r * 64);
+    }
+    uint32_t excl = 0;
+    if (tile != 0) {
         int64_t p = spin_limit ? (int64_t)tile - 1 : -1;
         uint32_t spins = 0;
         bool gave_up = spin_limit == 0;
@@ -366,27 +393,34 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
         st_publish(mine, kStInc | ((excl + acc) & kStVal));
     }
     gbase[tid] = dbase + excl;
-    tstart[tid] = block256_excl_scan(acc, wsum);
+    __syncthreads();
+    // keys out; each lane keeps the digits of its ITEMS places (four to a
+    // register) for the values
+    const int nt = (int)min<int64_t>(kTile, n - tbase);
+    uint32_t dg[kRounds / 4];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int q = tid + r * kSortBlock;
+        uint32_t d = 0;
+        if (q < nt) {
+            const uint32_t k = sbuf[q];
+            d = (k >> shift) & 255u;
+            const uint32_t dst = gbase[d] + (uint32_t)(q - tstart[d]);
+            if (dst < (uint64_t)n) kout[dst] = k;
+        }
+        if (r % 4 == 0) dg[r / 4] = d; else dg[r / 4] |= d << (8 * (r % 4));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+        if (wbase + r * 64 < n) sbuf[loc[r]] = vv[r];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-        if (wbase + r * 64 < n) {
-            const uint32_t d = (kk[r] >> shift) & 255u;
-            const uint32_t slot = tstart[d] + cnt[d] + loc[r];
-            sk[slot] = kk[r];
-            sv[slot] = vv[r];
-        }
-    }
-    __syncthreads();
-    const int nt = (int)min<int64_t>(kTile, n - tbase);
-    for (int q = tid; q < nt; q += kSortBlock) {
-        const uint32_t k = sk[q];
-        const uint32_t d = (k >> shift) & 255u;
+        const int q = tid + r * kSortBlock;
+        const uint32_t d = (dg[r / 4] >> (8 * (r % 4))) & 255u;
         const uint32_t dst = gbase[d] + (uint32_t)(q - tstart[d]);
-        if (dst < (uint64_t)n) {
-            kout[dst] = k;
-            vout[dst] = sv[q];
-        }
+        if (q < nt && dst < (uint64_t)n) vout[dst] = sbuf[q];
     }
 }
 
@@ -613,9 +647,10 @@ static int64_t onesweep_min_tiles()
     return kRowScanTiles + 1;
 }
 
-// Elements per thread of a one-sweep tile: 32 (8192-element tiles: 0.13 ms
-// less per pass than 4096 over 200M elements, whose digit runs are half as
-// long); C3X_ONESWEEP_ITEMS=16 or 24 overrides it (for timing).
+// Elements per thread of a one-sweep tile: 32 (8192-element tiles; over
+// 200M elements 0.16 ms less per pass than 4096, whose digit runs are half
+// as long though six wavefronts a SIMD fit, and level with 6144 at four);
+// C3X_ONESWEEP_ITEMS=16 or 24 overrides it (for timing).
 static int onesweep_items()
 {
     if (const char *e = getenv("C3X_ONESWEEP_ITEMS")) {
