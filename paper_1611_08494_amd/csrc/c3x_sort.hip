@@ -10,10 +10,11 @@
 // publishes its digit counts, and finds how many elements of each digit the
 // earlier tiles hold by looking back over their published counts (a chained
 // scan with decoupled look-back); the tile is staged in LDS in digit order
-// so that the global writes of a digit run are contiguous. Inputs of up to
-// 32M elements (and of 2^30 or more) instead count each pass's digits per
+// so that the global writes of a digit run are contiguous. Inputs below
+// 8M elements (and of 2^30 or more) instead count each pass's digits per
 // tile into a table, scan it, and scatter: there the table is small enough
-// to scan with one workgroup per digit, which costs less than the look-back.
+// to scan with one workgroup per digit, and the three launches a pass cost
+// less than the look-back.
 //
 // A look-back waits only on tiles that took their numbers earlier (so are
 // running or done), but every wait is bounded: a tile that polls an
@@ -37,6 +38,10 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;  // 4096
 constexpr int kWaves = kSortBlock / 64;
 constexpr int64_t kRowScanTiles = 8192;  // 32M elements
+// Sorts of this many 4096-element tiles (8M elements) and more take the
+// one-sweep schedule where the caller can observe a give-up: at 10M
+// elements it measured 7 us a pass faster than the table, at 200M 0.7 ms.
+constexpr int64_t kOneSweepMinTiles = 2048;
 
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
@@ -112,7 +117,8 @@ __device__ __forceinline__ uint32_t block256_excl_scan(uint32_t x, uint32_t *wsu
 // among the wavefront's earlier elements of that digit. One prefix over the
 // four wavefronts' counters then places every element in LDS in (digit,
 // original order); the tile leaves LDS in order, so consecutive threads
-// write consecutive addresses of one digit run.
+// write consecutive addresses of one digit run. Keys and then values pass
+// through one LDS buffer (22 KB a workgroup).
 __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
@@ -121,7 +127,7 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
 {
     constexpr int kPerWave = kSortTile / kWaves;  // 1024
     constexpr int kRounds = kPerWave / 64;        // 16
-    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+    __shared__ uint32_t sbuf[kSortTile];  // the tile in digit order: keys, then values
     __shared__ uint32_t gbase[256], tstart[256];
     __shared__ uint32_t wc[kWaves][256];
     __shared__ uint32_t wsum[kWaves];
@@ -183,21 +189,38 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_scatter(
     for (int r = 0; r < kRounds; ++r) {
         if (wbase + r * 64 < n) {
             const uint32_t d = (kk[r] >> shift) & 255u;
-            const uint32_t slot = tstart[d] + cnt[d] + loc[r];
-            sk[slot] = kk[r];
-            sv[slot] = vv[r];
+            loc[r] += tstart[d] + cnt[d];
+            sbuf[loc[r]] = kk[r];
         }
     }
     __syncthreads();
-    int nt = (int)min<int64_t>(kSortTile, n - tbase);
-    for (int p = tid; p < nt; p += kSortBlock) {
-        uint32_t k = sk[p];
-        uint32_t d = (k >> shift) & 255u;
-        uint32_t dst = gbase[d] + (uint32_t)(p - tstart[d]);
-        if (dst < (uint64_t)n) {
-            kout[dst] = k;
-            vout[dst] = sv[p];
+    // keys out; each lane keeps the digits of its places (four to a
+    // register) for the values
+    const int nt = (int)min<int64_t>(kSortTile, n - tbase);
+    uint32_t dg[kRounds / 4];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int q = tid + r * kSortBlock;
+        uint32_t d = 0;
+        if (q < nt) {
+            const uint32_t k = sbuf[q];
+            d = (k >> shift) & 255u;
+            const uint32_t dst = gbase[d] + (uint32_t)(q - tstart[d]);
+            if (dst < (uint64_t)n) kout[dst] = k;
         }
+        if (r % 4 == 0) dg[r / 4] = d; else dg[r / 4] |= d << (8 * (r % 4));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+        if (wbase + r * 64 < n) sbuf[loc[r]] = vv[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int q = tid + r * kSortBlock;
+        const uint32_t d = (dg[r / 4] >> (8 * (r % 4))) & 255u;
+        const uint32_t dst = gbase[d] + (uint32_t)(q - tstart[d]);
+        if (q < nt && dst < (uint64_t)n) vout[dst] = sbuf[q];
     }
 }
 
@@ -639,12 +662,12 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp, uint
 }
 
 // Test settings: C3X_DEBUG_ONESWEEP_TILES=t takes the one-sweep schedule
-// from t tiles up (default kRowScanTiles + 1); C3X_DEBUG_SORT_SPIN=k sets the
+// from t tiles up (default kOneSweepMinTiles); C3X_DEBUG_SORT_SPIN=k sets the
 // look-back's spin limit (0: every tile but the first gives up).
 static int64_t onesweep_min_tiles()
 {
     if (const char *e = getenv("C3X_DEBUG_ONESWEEP_TILES")) return std::max(1LL, atoll(e));
-    return kRowScanTiles + 1;
+    return kOneSweepMinTiles;
 }
 
 // Elements per thread of a one-sweep tile: 32 (8192-element tiles; over
@@ -681,10 +704,10 @@ hipError_t radix_sort_pairs_bits(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
     // the first pass reads no values when they are the elements' own indices
     const uint32_t *vfirst = vals_are_index ? nullptr : vals;
     int64_t nb = (n + kSortTile - 1) / kSortTile;
-    // up to kRowScanTiles tiles, one workgroup per digit scans its row of the
-    // table cheaply and the look-back's latency does not pay; above, the
-    // table needs a full scan and one sweep is faster (when the caller can
-    // observe a give-up)
+    // below kOneSweepMinTiles tiles the table's launches cost less than the
+    // look-back's latency; above, one sweep is faster (when the caller can
+    // observe a give-up), and from kRowScanTiles on the table would need a
+    // full scan
     if (fail && nb >= onesweep_min_tiles() && n < kOneSweepMax) {
         const uint32_t spins = spin_limit();
         const int items = onesweep_items();
