@@ -770,6 +770,7 @@ static FinishArgs batch_fin_args(c3x_batch *b)
     fa.os = b->os;
     fa.bsep = b->obsep;
     fa.err = b->ctr + 4;
+    fa.open_flag = b->ctr + 14;
     fa.sort_fail = nullptr;  // rows above 2048 matches: table-schedule sorts
     fa.seg_n = b->ctr + 6;
     fa.cap = b->seg_cap;

@@ -1586,7 +1586,8 @@ __device__ __noinline__ double sep_from_coords(double2 pa, double2 pb)
 // best match's separation too. coordA: A coordinates by output row a;
 // coordB: B coordinates by output idxB (before any job-local renumbering).
 // defer: a separation to take from the coordinates is left as the code
-// (NaN) for k_sep_coords, which computes them all in one parallel pass.
+// (NaN) for k_sep_fix, which computes them all in one parallel pass. Used
+// by the segment kernels; k_finalize writes its common cases itself.
 __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp &x, int64_t nB,
                                             const double2 *__restrict__ coordA,
                                             const double2 *__restrict__ coordB, int32_t best,
@@ -1628,11 +1629,11 @@ __device__ __forceinline__ void final_write(int64_t q, int64_t a, const PairTmp 
 __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *__restrict__ off,
                            const RowRec *__restrict__ rec, const int32_t *__restrict__ best2,
                            int use_rec, PairTmp *__restrict__ tmp,
-                           const double2 *__restrict__ coordA, const double2 *__restrict__ coordB,
                            int32_t *__restrict__ best_idx,
                            int32_t *__restrict__ oa, int32_t *__restrict__ ob,
                            double *__restrict__ os, double *__restrict__ bsep,
-                           uint32_t *__restrict__ err, int defer, uint32_t *__restrict__ seg_n,
+                           uint32_t *__restrict__ err, uint32_t *__restrict__ open_flag,
+                           uint32_t *__restrict__ seg_n,
                            uint32_t *__restrict__ seg_list, uint32_t seg_cap)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1668,9 +1669,26 @@ __global__ void k_finalize(int64_t nA, int64_t nB, int64_t pcap, const int64_t *
         for (int y = nt; y < len; ++y) rk += tmp[o + y].idxB < ib;
         return rk;
     };
+    // a separation that needs more than the small-chord series (a chord of
+    // 0.1 or more, or a NaN code: the coordinates') keeps its code for
+    // k_sep_fix; keeping those paths out of this kernel halves its registers
     auto put = [&](const PairTmp &x) {
-        final_write(o + rank_of(x.idxB), a, x, nB, coordA, coordB, best, oa, ob, os, bsep, err,
-                    defer != 0);
+        const int64_t q = o + rank_of(x.idxB);
+        double sp = x.sep;
+        const bool open = !(sp >= 0.0) && !(sp > -0.01);
+        if (!(sp >= 0.0) && !open) sp = theta_small(-sp);
+        oa[q] = (int32_t)a;
+        ob[q] = (int32_t)x.idxB;
+        os[q] = sp;
+        if (!open) {
+            if (best == (int32_t)x.idxB) bsep[a] = sp;
+        } else if (x.idxB >= (uint64_t)nB) {
+            atomicOr(err, 16u);
+        }
+        // one plain store of the flag per wavefront (every writer writes 1)
+        const unsigned long long om = __ballot(open);
+        if (open_flag && om && (int)__lane_id() == __builtin_ffsll((long long)om) - 1)
+            *open_flag = 1u;
     };
     if (nt > 0) put(x0);
     for (int q = nt; q < len; ++q) put(tmp[o + q]);
@@ -1748,6 +1766,9 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
                 uint32_t s = atomicAdd(huge_n, 1u);
                 if (s < cap) huge[s] = a;
             }
+            // until finish_huge writes them, the segment's slots say "no row"
+            // (k_sep_fix skips them)
+            for (int k = threadIdx.x; k < len; k += blockDim.x) oa[o + k] = -1;
             continue;  // uniform over the workgroup
         }
         int p2 = 1;
@@ -1779,26 +1800,36 @@ __global__ __launch_bounds__(256) void k_seg_lds(const int64_t *__restrict__ off
     }
 }
 
-// The separations the final pass left to the coordinates (the mixed path's
-// matches: it keeps no FP64 payload to take a chord from), one thread per
-// output pair, and the best match's separation with them. Outputs whose
-// rows are out of range are skipped (the slots of rows ordered later by
-// finish_huge may still hold anything: they are written after this pass).
-__global__ void k_sep_coords(int64_t P, int64_t nA, int64_t nB, const int32_t *__restrict__ oa,
-                             const int32_t *__restrict__ ob, double *__restrict__ os,
-                             const double2 *__restrict__ coordA,
-                             const double2 *__restrict__ coordB,
-                             const int32_t *__restrict__ best_idx, double *__restrict__ bsep)
+// The separations the final passes left as codes: a chord of 0.1 or more
+// (the arcsine) and NaN codes, taken from both rows' coordinates (the
+// batch's mixed matches, which carry no FP64 chord, and separations near
+// 90 deg or more); the best match's separation with them. Grid-stride over
+// the pairs written (ptot: their count; P: the outputs' capacity); with
+// open_flag given, nothing is done unless the finalize kernel set it. The
+// slots of rows that finish_huge orders later say idxA -1 and are skipped.
+__global__ void k_sep_fix(int64_t P, const int64_t *__restrict__ ptot, int64_t nA, int64_t nB,
+                          const int32_t *__restrict__ oa,
+                          const int32_t *__restrict__ ob, double *__restrict__ os,
+                          const double2 *__restrict__ coordA,
+                          const double2 *__restrict__ coordB,
+                          const int32_t *__restrict__ best_idx, double *__restrict__ bsep,
+                          const uint32_t *__restrict__ open_flag)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= P) return;
-    const double c = os[q];
-    if (!(c != c)) return;  // not NaN: already final
-    const int32_t a = oa[q], b = ob[q];
-    if (a < 0 || a >= nA || b < 0 || b >= nB) return;
-    const double s = sep_from_coords(coordA[a], coordB[b]);
-    os[q] = s;
-    if (best_idx[a] == b) bsep[a] = s;
+    if (open_flag && *open_flag == 0u) return;  // nothing was left open
+    const int64_t n = min(P, max(*ptot, (int64_t)0));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const double c = os[q];
+        if (c >= 0.0) continue;  // final
+        const int32_t a = oa[q], b = ob[q];
+        if (a < 0 || a >= nA || b < 0 || b >= nB) continue;
+        double sp;
+        if (c > -0.01) sp = theta_small(-c);
+        else if (c < 0.0) sp = 2.0 * asin(0.5 * sqrt(-c)) * (180.0 / kPi * 3600.0);
+        else sp = sep_from_coords(coordA[a], coordB[b]);
+        os[q] = sp;
+        if (best_idx[a] == b) bsep[a] = sp;
+    }
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -1811,7 +1842,7 @@ struct FinishArgs {
     const RowRec *rec;
     const int32_t *best2;   // bests of the rows flagged kBestSide
     int use_rec;
-    int defer;              // separations from coordinates by k_sep_coords (mixed path)
+    int defer;              // every separation from the coordinates, by k_sep_fix (a batch's mixed path)
     PairTmp *tmp;
     const double2 *coordA;  // A coordinates by output row
     const double2 *coordB;  // B coordinates by output idxB
@@ -1819,6 +1850,7 @@ struct FinishArgs {
     int32_t *oa, *ob;
     double *os, *bsep;
     uint32_t *err;
+    uint32_t *open_flag;  // cleared device word: separations left to k_sep_fix (unused with defer)
     uint32_t *sort_fail;  // cleared device word for the segment sorts (null: table schedule)
     uint32_t *seg_n;   // [2]: listed long segments, listed huge segments
     uint32_t *list, *huge;
@@ -1832,15 +1864,20 @@ constexpr unsigned kSegGrid = 1024;
 static void finish_segments(const FinishArgs &f, hipStream_t s)
 {
     if (f.nA == 0) return;
+    // with defer every pair is left to k_sep_fix, which then runs over all
+    // of them; otherwise the few left open raise a flag
+    uint32_t *flag = f.defer ? nullptr : f.open_flag;
     hipLaunchKernelGGL(k_finalize, dim3(nblk(f.nA, 256)), dim3(256), 0, s, f.nA, f.nB, f.pcap,
-                       f.off, f.rec, f.best2, f.use_rec, f.tmp, f.coordA, f.coordB, f.best_idx,
-                       f.oa, f.ob, f.os, f.bsep, f.err, f.defer, f.seg_n, f.list, f.cap);
+                       f.off, f.rec, f.best2, f.use_rec, f.tmp, f.best_idx, f.oa, f.ob, f.os,
+                       f.bsep, f.err, flag, f.seg_n, f.list, f.cap);
     hipLaunchKernelGGL(k_seg_lds, dim3(kSegGrid), dim3(256), 0, s, f.off, f.seg_n, f.list, f.cap,
                        f.tmp, f.nB, f.pcap, f.coordA, f.coordB, f.rec, f.best2, f.oa, f.ob, f.os,
                        f.bsep, f.seg_n + 1, f.huge, f.err, f.defer);
-    if (f.defer && f.pcap > 0)
-        hipLaunchKernelGGL(k_sep_coords, dim3(nblk(f.pcap, 256)), dim3(256), 0, s, f.pcap, f.nA,
-                           f.nB, f.oa, f.ob, f.os, f.coordA, f.coordB, f.best_idx, f.bsep);
+    if (f.pcap > 0) {
+        const unsigned g = flag ? kSegGrid : nblk(f.pcap, 256);
+        hipLaunchKernelGGL(k_sep_fix, dim3(g), dim3(256), 0, s, f.pcap, f.off + f.nA, f.nA, f.nB,
+                           f.oa, f.ob, f.os, f.coordA, f.coordB, f.best_idx, f.bsep, flag);
+    }
 }
 
 // Segments longer than kSegLds (their count already on the host), all at
@@ -2644,6 +2681,7 @@ static c3x_status match_impl(const c3x_index *ix, const double *ra, const double
         fa.os = R->sep;
         fa.bsep = R->best_sep;
         fa.err = ctr + 4;
+        fa.open_flag = ctr + 14;
         fa.sort_fail = onesweep ? ctr + 11 : nullptr;
         fa.seg_n = ctr + 6;
         fa.cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(nA, 1), 1 << 22);

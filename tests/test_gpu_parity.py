@@ -158,6 +158,25 @@ def test_cfg2_large_radius_crosses_poles_and_wrap(c3x, dev):
         assert_parity(g, o)
 
 
+@pytest.mark.parametrize("radius_deg", [10.0, 88.0, 90.0])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_huge_radii(c3x, dev, radius_deg, precision):
+    """Radii up to the 90 deg limit (Section 2.1's circle): separations above
+    about 5.7 deg are decoded from the chord by the arcsine, above about
+    87 deg from both rows' coordinates; both are rare in the hot workloads."""
+    rng = np.random.default_rng(synth.SEED_BASE + 777)
+    raA, decA = synth.sphere_uniform(rng, 400)
+    raB, decB = synth.sphere_uniform(rng, 500)
+    cat = synth.Catalogues(f"huge_radius_{radius_deg}", raA, decA, raB, decB,
+                           radius_arcsec=radius_deg * 3600.0)
+    o = oracle_match(cat)
+    assert len(o.ia) > 1000 and np.max(o.sep) > 5.8 * 3600.0
+    if radius_deg > 87.5:
+        assert np.max(o.sep) > 87.2 * 3600.0
+    g = gpu_match(c3x, dev, cat, precision)
+    assert_parity(g, o)
+
+
 @pytest.fixture(scope="module")
 def cfg3_small():
     return synth.cfg3_galactic_ellipses(scale=0.003)
