@@ -6,7 +6,7 @@
 // into n_z RA cells of true width >= h at the zone's edge nearest the
 // equator; key = zbase[zone] + cell is zone-major, so the cells an A source
 // needs in one zone are one contiguous key range. Phases (one stream):
-//   k_prep_b    validate rows, key + row index          16 B in, 8 B out
+//   k_prep_b    validate rows, key + packed copy         16 B in, 4 + 16 B out
 //   radix sort  (key, row) by key, ceil(bits/8) passes   16 B per pass
 //   k_gather_b  payload in sorted order                   20 B in, 32 or 16 + 8 B out
 //   k_dir_fill  dir[q] = number of keys in buckets below q, written straight
